@@ -1,0 +1,1122 @@
+/*
+ * airg_oracle.c -- plain CPU reference of AIRG (arXiv 2408.08262).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg to check the HIP library; never part of the
+ * product path.  Shares no code with the HIP library.
+ *
+ * Plain double-precision loops in natural index order, single threaded,
+ * compiled with -O2 -ffp-contract=off.  Where the paper is silent or garbled
+ * the reading taken is stated at the function (and listed in the design doc).
+ */
+#include "airg_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_LEVELS 128
+
+static void *xmalloc(size_t n)
+{
+    void *p = malloc(n ? n : 1);
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return p;
+}
+
+static void *xcalloc(size_t n, size_t s)
+{
+    void *p = calloc(n ? n : 1, s ? s : 1);
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return p;
+}
+
+static void csr_alloc(orc_csr *A, int64_t nr, int64_t nc, int64_t nnz, int values)
+{
+    A->nr = nr;
+    A->nc = nc;
+    A->rp = (int64_t *)xcalloc((size_t)nr + 1, sizeof(int64_t));
+    A->ci = (int32_t *)xmalloc((size_t)nnz * sizeof(int32_t));
+    A->v = values ? (double *)xmalloc((size_t)nnz * sizeof(double)) : NULL;
+}
+
+void orc_csr_free(orc_csr *A)
+{
+    if (!A) return;
+    free(A->rp);
+    free(A->ci);
+    free(A->v);
+    memset(A, 0, sizeof *A);
+}
+
+void orc_default_params(orc_params *p)
+{
+    /* Parallel-results defaults of the paper (strength 0.5, n_loops^max = 3,
+     * drop 0.001 on coarse A and 0.01 on Z, order-6 polynomial with first-order
+     * fixed sparsity, coarse solve of 3 iterations of an order-12 polynomial),
+     * with alpha_diag = 0.9 chosen directly (Results: choosing alpha_diag
+     * directly avoids decomposition dependence). */
+    p->strong_threshold = 0.5;
+    p->ddc_threshold = 0.9;
+    p->ddc_fraction = 0.1;
+    p->pmisr_max_rounds = 3;
+    p->poly_order = 6;
+    p->drop_R = 0.01;
+    p->drop_A = 0.001;
+    p->coarse_poly_order = 12;
+    p->coarse_iters = 3;
+    p->truncate_n = 0;
+    p->max_levels = 64;
+    p->up_smooths = 2;
+    p->onepoint_weight = 0;
+    p->seed = 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based random numbers: the output function of SplitMix64 (Steele, */
+/* Lea & Flood, OOPSLA 2014) applied to a keyed counter.                    */
+/* ------------------------------------------------------------------------ */
+uint64_t orc_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_counter(uint64_t seed, uint32_t stream, uint32_t level, uint64_t i)
+{
+    return seed ^ ((uint64_t)(stream & 0xffu) << 56) ^ ((uint64_t)(level & 0xffffu) << 40) ^ i;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Strength of connection (CF splitting section, strength equation, with    */
+/* absolute values as in the serial results).                                */
+/*   S_i = { j != i : |a_ij| >= alpha * max_{k != i} |a_ik| }                */
+/* Reading: only stored nonzero entries qualify, so a row whose off-diagonal */
+/* entries are all zero has S_i empty.                                       */
+/* ------------------------------------------------------------------------ */
+void orc_strength(const orc_csr *A, double alpha, uint8_t *strong)
+{
+    for (int64_t i = 0; i < A->nr; ++i) {
+        double M = 0.0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            if (A->ci[k] != i && fabs(A->v[k]) > M) M = fabs(A->v[k]);
+        double thr = alpha * M;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+            double a = fabs(A->v[k]);
+            strong[k] = (uint8_t)(A->ci[k] != i && a > 0.0 && a >= thr);
+        }
+    }
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Symmetrised strength graph G_i = S_i u S_i^T, no self loops (the PMISR
+ * algorithm works on S u S^T).  Rows sorted and duplicate free. */
+int orc_sym_graph(const orc_csr *A, const uint8_t *strong, orc_csr *G)
+{
+    int64_t n = A->nr;
+    int64_t *cnt = (int64_t *)xcalloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            if (strong[k]) { cnt[i]++; cnt[A->ci[k]]++; }
+    int64_t *rp = (int64_t *)xcalloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + cnt[i];
+    int32_t *tmp = (int32_t *)xmalloc((size_t)rp[n] * sizeof(int32_t));
+    int64_t *pos = (int64_t *)xmalloc((size_t)n * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) pos[i] = rp[i];
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            if (strong[k]) {
+                int32_t j = A->ci[k];
+                tmp[pos[i]++] = j;
+                tmp[pos[j]++] = (int32_t)i;
+            }
+    /* sort and remove duplicates row by row */
+    csr_alloc(G, n, n, rp[n], 0);
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t b = rp[i], e = rp[i + 1];
+        qsort(tmp + b, (size_t)(e - b), sizeof(int32_t), cmp_i32);
+        G->rp[i] = w;
+        for (int64_t k = b; k < e; ++k)
+            if (k == b || tmp[k] != tmp[k - 1]) G->ci[w++] = tmp[k];
+    }
+    G->rp[n] = w;
+    free(cnt); free(rp); free(tmp); free(pos);
+    return 0;
+}
+
+/* PMISR measure (PMISR algorithm, first loop): w_i = |S_i u S_i^T| + rand(0,1).
+ * Reading of the garbled "S_i + S_i^T": the number of distinct symmetrised
+ * strong neighbours deg_i.  rand(0,1) is (h_i + 1/2) 2^-32 with h_i the upper
+ * 32 bits of the counter generator (stream 0); comparisons use the exact
+ * integer key (deg_i, h_i, i), which orders identically to the double w_i and
+ * breaks exact ties by index. */
+void orc_pmisr_keys(const orc_csr *G, uint64_t seed, int32_t level, int32_t *deg, uint32_t *h)
+{
+    for (int64_t i = 0; i < G->nr; ++i) {
+        deg[i] = (int32_t)(G->rp[i + 1] - G->rp[i]);
+        h[i] = (uint32_t)(orc_splitmix64(orc_counter(seed, 0, (uint32_t)level, (uint64_t)i)) >> 32);
+    }
+}
+
+static int key_less(const int32_t *deg, const uint32_t *h, int64_t i, int64_t j)
+{
+    if (deg[i] != deg[j]) return deg[i] < deg[j];
+    if (h[i] != h[j]) return h[i] < h[j];
+    return i < j;
+}
+
+/* PMISR (PMISR algorithm).
+ * Initial F = { w_i < 1 } = { deg_i = 0 }.  Each round, from the state at the
+ * start of the round, D = unassigned nodes whose measure is below that of
+ * every unassigned neighbour in G; D joins F and the unassigned neighbours of
+ * D join C.  Readings: the loop condition is "rounds < n_loops^max and some
+ * node is unassigned" (n_loops^max = 0 means no cap), and the comparison in D
+ * is against unassigned neighbours only (standard Luby rounds).  Nodes still
+ * unassigned at the end become C.  Returns the number of rounds run. */
+int32_t orc_pmisr(const orc_csr *G, const int32_t *deg, const uint32_t *h, int32_t max_rounds, int8_t *cf)
+{
+    int64_t n = G->nr;
+    uint8_t *inD = (uint8_t *)xcalloc((size_t)n, 1);
+    for (int64_t i = 0; i < n; ++i) cf[i] = deg[i] == 0 ? ORC_F : ORC_U;
+    int32_t rounds = 0;
+    for (;;) {
+        if (max_rounds > 0 && rounds >= max_rounds) break;
+        int64_t nu = 0;
+        for (int64_t i = 0; i < n; ++i) nu += cf[i] == ORC_U;
+        if (nu == 0) break;
+        for (int64_t i = 0; i < n; ++i) {
+            inD[i] = 0;
+            if (cf[i] != ORC_U) continue;
+            int isMin = 1;
+            for (int64_t k = G->rp[i]; k < G->rp[i + 1]; ++k) {
+                int64_t j = G->ci[k];
+                if (cf[j] == ORC_U && !key_less(deg, h, i, j)) { isMin = 0; break; }
+            }
+            inD[i] = (uint8_t)isMin;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            if (inD[i]) cf[i] = ORC_F;
+        for (int64_t i = 0; i < n; ++i) {
+            if (cf[i] != ORC_U) continue;
+            for (int64_t k = G->rp[i]; k < G->rp[i + 1]; ++k)
+                if (inD[G->ci[k]]) { cf[i] = ORC_C; break; }
+        }
+        rounds++;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (cf[i] == ORC_U) cf[i] = ORC_C;
+    free(inD);
+    return rounds;
+}
+
+/* Row-wise diagonal dominance ratio of A_ff (DDC algorithm):
+ *   theta_i = sum_{j in F, j != i} |a_ij| / |a_ii|,
+ * summed in ascending column order starting from +0.0.  Reading: a zero
+ * (or missing) diagonal gives theta = +inf. */
+static double ddc_theta_row(const orc_csr *A, const int8_t *cf, int64_t i)
+{
+    double s = 0.0, d = 0.0;
+    for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+        int32_t j = A->ci[k];
+        if (j == i) d = A->v[k];
+        else if (cf[j] == ORC_F) s += fabs(A->v[k]);
+    }
+    if (d == 0.0) return INFINITY;
+    return s / fabs(d);
+}
+
+/* Fraction mode of DDC (end of the CF splitting section): alpha_diag is the
+ * boundary of 1000 uniform bins on [0, theta_max] that brings the number of
+ * converted points closest to ceil(fraction * #F).  Reading: bin boundaries
+ * b_k = theta_max * k / 1000, theta_max over finite nonzero theta, count
+ * #{theta > b_k}, ties to the larger k. */
+double orc_ddc_fraction_threshold(const orc_csr *A, const int8_t *cf, double fraction)
+{
+    int64_t n = A->nr, nF = 0;
+    double tmax = 0.0;
+    double *th = (double *)xmalloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        th[i] = -1.0;
+        if (cf[i] != ORC_F) continue;
+        nF++;
+        th[i] = ddc_theta_row(A, cf, i);
+        if (isfinite(th[i]) && th[i] > tmax) tmax = th[i];
+    }
+    int64_t target = (int64_t)ceil(fraction * (double)nF);
+    double best = tmax;
+    int64_t bestd = -1;
+    for (int k = 0; k <= 1000; ++k) {
+        double bk = tmax * (double)k / 1000.0;
+        int64_t c = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (th[i] > bk) c++;
+        int64_t d = c > target ? c - target : target - c;
+        if (bestd < 0 || d <= bestd) { bestd = d; best = bk; }
+    }
+    free(th);
+    return best;
+}
+
+/* DDC (diagonal dominance cleanup algorithm): every F point with
+ * theta_i > alpha_diag and theta_i != 0 becomes C, all at once, with theta
+ * evaluated on the F set output by PMISR.  Reading: a zero diagonal always
+ * converts.  theta (nullable) receives theta_i for F rows (-1 elsewhere).
+ * Returns the number converted. */
+int64_t orc_ddc(const orc_csr *A, double alpha_diag, int8_t *cf, double *theta)
+{
+    int64_t n = A->nr, count = 0;
+    uint8_t *conv = (uint8_t *)xcalloc((size_t)n, 1);
+    for (int64_t i = 0; i < n; ++i) {
+        if (theta) theta[i] = -1.0;
+        if (cf[i] != ORC_F) continue;
+        double t = ddc_theta_row(A, cf, i);
+        if (theta) theta[i] = t;
+        conv[i] = (uint8_t)(isinf(t) || (t > alpha_diag && t != 0.0));
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (conv[i]) { cf[i] = ORC_C; count++; }
+    free(conv);
+    return count;
+}
+
+/* CF splitting: one pass of PMISR then one pass of DDC (end of the CF
+ * splitting section), on every level. */
+int orc_cf_split(const orc_csr *A, const orc_params *p, int32_t level, int8_t *cf)
+{
+    int64_t nnz = A->rp[A->nr];
+    uint8_t *strong = (uint8_t *)xmalloc((size_t)nnz);
+    orc_strength(A, p->strong_threshold, strong);
+    orc_csr G;
+    orc_sym_graph(A, strong, &G);
+    int32_t *deg = (int32_t *)xmalloc((size_t)A->nr * sizeof(int32_t));
+    uint32_t *h = (uint32_t *)xmalloc((size_t)A->nr * sizeof(uint32_t));
+    orc_pmisr_keys(&G, p->seed, level, deg, h);
+    orc_pmisr(&G, deg, h, p->pmisr_max_rounds, cf);
+    double ad = p->ddc_threshold;
+    if (ad < 0.0) ad = orc_ddc_fraction_threshold(A, cf, p->ddc_fraction);
+    orc_ddc(A, ad, cf, NULL);
+    free(strong); free(deg); free(h);
+    orc_csr_free(&G);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Extraction and sparse products                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Block of the CF splitting (reduction multigrid section, 2x2 block form):
+ * rows with marker rowsel, columns with marker colsel, both ranked by
+ * ascending original index, entry order preserved. */
+int orc_submatrix(const orc_csr *A, const int8_t *cf, int8_t rowsel, int8_t colsel, orc_csr *out)
+{
+    int64_t n = A->nr;
+    int32_t *cmap = (int32_t *)xmalloc((size_t)A->nc * sizeof(int32_t));
+    int64_t nc = 0, nr = 0;
+    for (int64_t j = 0; j < A->nc; ++j) cmap[j] = cf[j] == colsel ? (int32_t)nc++ : -1;
+    for (int64_t i = 0; i < n; ++i) nr += cf[i] == rowsel;
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (cf[i] == rowsel)
+            for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) nnz += cmap[A->ci[k]] >= 0;
+    csr_alloc(out, nr, nc, nnz, 1);
+    int64_t r = 0, w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i] != rowsel) continue;
+        out->rp[r] = w;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+            int32_t c = cmap[A->ci[k]];
+            if (c >= 0) { out->ci[w] = c; out->v[w] = A->v[k]; w++; }
+        }
+        r++;
+    }
+    out->rp[nr] = w;
+    free(cmap);
+    return 0;
+}
+
+/* y = A x, each row summed in stored order from 0. */
+void orc_spmv(const orc_csr *A, const double *x, double *y)
+{
+    for (int64_t i = 0; i < A->nr; ++i) {
+        double s = 0.0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s += A->v[k] * x[A->ci[k]];
+        y[i] = s;
+    }
+}
+
+/* C = A B, row-wise Gustavson: for each entry a_rk of row r in ascending k,
+ * for each entry b_kj of row k in ascending j, accumulate a_rk b_kj into c_rj.
+ * Output columns ascending. */
+int orc_spgemm(const orc_csr *A, const orc_csr *B, orc_csr *C)
+{
+    int64_t m = A->nr, n = B->nc;
+    int64_t *mark = (int64_t *)xmalloc((size_t)n * sizeof(int64_t));
+    double *acc = (double *)xmalloc((size_t)n * sizeof(double));
+    int32_t *cols = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
+    for (int64_t j = 0; j < n; ++j) mark[j] = -1;
+    /* symbolic */
+    int64_t *rp = (int64_t *)xcalloc((size_t)m + 1, sizeof(int64_t));
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t cnt = 0;
+        for (int64_t ka = A->rp[r]; ka < A->rp[r + 1]; ++ka) {
+            int32_t k = A->ci[ka];
+            for (int64_t kb = B->rp[k]; kb < B->rp[k + 1]; ++kb) {
+                int32_t j = B->ci[kb];
+                if (mark[j] != r) { mark[j] = r; cnt++; }
+            }
+        }
+        rp[r + 1] = rp[r] + cnt;
+    }
+    csr_alloc(C, m, n, rp[m], 1);
+    memcpy(C->rp, rp, ((size_t)m + 1) * sizeof(int64_t));
+    for (int64_t j = 0; j < n; ++j) mark[j] = -1;
+    /* numeric */
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t cnt = 0;
+        for (int64_t ka = A->rp[r]; ka < A->rp[r + 1]; ++ka) {
+            int32_t k = A->ci[ka];
+            double a = A->v[ka];
+            for (int64_t kb = B->rp[k]; kb < B->rp[k + 1]; ++kb) {
+                int32_t j = B->ci[kb];
+                double prod = a * B->v[kb];
+                if (mark[j] != r) { mark[j] = r; acc[j] = prod; cols[cnt++] = j; }
+                else acc[j] += prod;
+            }
+        }
+        qsort(cols, (size_t)cnt, sizeof(int32_t), cmp_i32);
+        for (int64_t t = 0; t < cnt; ++t) {
+            C->ci[rp[r] + t] = cols[t];
+            C->v[rp[r] + t] = acc[cols[t]];
+        }
+    }
+    free(mark); free(acc); free(cols); free(rp);
+    return 0;
+}
+
+/* Drop small entries by the relative row-wise infinity norm (serial and
+ * parallel results sections): keep x_rj iff |x_rj| >= tau * max_j |x_rj|;
+ * keep_diag keeps the diagonal of a square operator regardless. */
+int orc_drop(const orc_csr *A, double tau, int keep_diag, orc_csr *out)
+{
+    int64_t n = A->nr, nnz = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double mx = 0.0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            if (fabs(A->v[k]) > mx) mx = fabs(A->v[k]);
+        double thr = tau * mx;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            nnz += (keep_diag && A->ci[k] == i) || fabs(A->v[k]) >= thr;
+    }
+    csr_alloc(out, n, A->nc, nnz, 1);
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double mx = 0.0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            if (fabs(A->v[k]) > mx) mx = fabs(A->v[k]);
+        double thr = tau * mx;
+        out->rp[i] = w;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            if ((keep_diag && A->ci[k] == i) || fabs(A->v[k]) >= thr) {
+                out->ci[w] = A->ci[k];
+                out->v[w] = A->v[k];
+                w++;
+            }
+    }
+    out->rp[n] = w;
+    return 0;
+}
+
+int orc_transpose(const orc_csr *A, orc_csr *T)
+{
+    int64_t nnz = A->rp[A->nr];
+    csr_alloc(T, A->nc, A->nr, nnz, A->v != NULL);
+    for (int64_t k = 0; k < nnz; ++k) T->rp[A->ci[k] + 1]++;
+    for (int64_t j = 0; j < A->nc; ++j) T->rp[j + 1] += T->rp[j];
+    int64_t *pos = (int64_t *)xmalloc(((size_t)A->nc + 1) * sizeof(int64_t));
+    memcpy(pos, T->rp, ((size_t)A->nc + 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < A->nr; ++i)
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+            int64_t p = pos[A->ci[k]]++;
+            T->ci[p] = (int32_t)i;
+            if (A->v) T->v[p] = A->v[k];
+        }
+    free(pos);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* GMRES polynomial (AIRG subsection, setup steps 3 to 8)                    */
+/* ------------------------------------------------------------------------ */
+
+/* Step 3: normally distributed rhs by the Box-Muller transform,
+ * b_k = sqrt(-2 ln u1) cos(2 pi u2) with u1 in (0,1] (stream 1) and u2 in
+ * [0,1) (stream 2), 53-bit uniforms from the counter generator. */
+void orc_gauss_rhs(int64_t n, uint64_t seed, int32_t level, double *b)
+{
+    const double two53 = 1.0 / 9007199254740992.0;
+    for (int64_t k = 0; k < n; ++k) {
+        uint64_t r1 = orc_splitmix64(orc_counter(seed, 1, (uint32_t)level, (uint64_t)k));
+        uint64_t r2 = orc_splitmix64(orc_counter(seed, 2, (uint32_t)level, (uint64_t)k));
+        double u1 = ((double)(r1 >> 11) + 1.0) * two53;
+        double u2 = (double)(r2 >> 11) * two53;
+        b[k] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+/* Step 4: power basis K = [b, A b, ..., A^m b], column-major n x (m+1). */
+void orc_power_basis(const orc_csr *A, const double *b, int32_t m, double *K)
+{
+    int64_t n = A->nr;
+    memcpy(K, b, (size_t)n * sizeof(double));
+    for (int32_t c = 1; c <= m; ++c) orc_spmv(A, K + (size_t)(c - 1) * n, K + (size_t)c * n);
+}
+
+/* Step 5: R factor of the Householder QR of K D, D = diag(1/||K_c||)
+ * (column scaling for conditioning; the least-squares minimiser is recovered
+ * exactly after unscaling).  R is cols x cols row-major (R[r*cols+c]),
+ * colnorm[c] = ||K_c||_2. */
+void orc_householder_r(int64_t rows, int32_t cols, const double *K, double *R, double *colnorm)
+{
+    double *W = (double *)xmalloc((size_t)rows * (size_t)cols * sizeof(double));
+    for (int32_t c = 0; c < cols; ++c) {
+        const double *k = K + (size_t)c * rows;
+        double s = 0.0;
+        for (int64_t i = 0; i < rows; ++i) s += k[i] * k[i];
+        colnorm[c] = sqrt(s);
+        double sc = colnorm[c] > 0.0 ? 1.0 / colnorm[c] : 1.0;
+        for (int64_t i = 0; i < rows; ++i) W[(size_t)c * rows + i] = k[i] * sc;
+    }
+    for (int32_t r = 0; r < cols * cols; ++r) R[r] = 0.0;
+    int64_t steps = rows < cols ? rows : cols;
+    double *v = (double *)xmalloc((size_t)rows * sizeof(double));
+    for (int64_t c = 0; c < steps; ++c) {
+        double *x = W + (size_t)c * rows;
+        double nx = 0.0;
+        for (int64_t i = c; i < rows; ++i) nx += x[i] * x[i];
+        nx = sqrt(nx);
+        double alpha = x[c] >= 0.0 ? -nx : nx;
+        double vv = 0.0;
+        for (int64_t i = c; i < rows; ++i) v[i] = x[i];
+        v[c] -= alpha;
+        for (int64_t i = c; i < rows; ++i) vv += v[i] * v[i];
+        if (vv > 0.0) {
+            for (int32_t c2 = (int32_t)c + 1; c2 < cols; ++c2) {
+                double *y = W + (size_t)c2 * rows;
+                double s = 0.0;
+                for (int64_t i = c; i < rows; ++i) s += v[i] * y[i];
+                double f = 2.0 * s / vv;
+                for (int64_t i = c; i < rows; ++i) y[i] -= f * v[i];
+            }
+            x[c] = alpha;
+        }
+        for (int32_t c2 = (int32_t)c; c2 < cols; ++c2) R[c * cols + c2] = W[(size_t)c2 * rows + c];
+    }
+    free(v);
+    free(W);
+}
+
+/* Step 6: least squares for the coefficients,
+ *   alpha = argmin_y || beta e_1 - R~ y ||_2,  R~ = R(:, 2:end), beta = R(1,1),
+ * solved with Givens rotations on the Hessenberg R~ of the scaled basis, then
+ * unscaled.  Reading for breakdown (not described in the paper): if
+ * |R(j,j)| <= 1e-14 ||R(:, 0..j)||_F for some j >= 1, the Krylov space is
+ * invariant and the degree drops to j-1 (exact for A = cI or n < m).
+ * Returns the number of coefficients used (the rest are zero). */
+int orc_poly_coeffs_from_r(const double *R, const double *colnorm, int32_t m, double *alpha)
+{
+    int32_t cols = m + 1;
+    int32_t meff = m;
+    double fro2 = 0.0;
+    for (int32_t j = 0; j <= m; ++j) {
+        for (int32_t r = 0; r <= j; ++r) fro2 += R[r * cols + j] * R[r * cols + j];
+        if (j >= 1 && (fabs(R[j * cols + j]) <= 1e-14 * sqrt(fro2) || colnorm[j] == 0.0)) {
+            meff = colnorm[j] == 0.0 ? j - 1 : j;
+            break;
+        }
+    }
+    for (int32_t k = 0; k < m; ++k) alpha[k] = 0.0;
+    if (meff <= 0 || colnorm[0] == 0.0) return 0;
+    int32_t rows = meff + 1;
+    double *H = (double *)xmalloc((size_t)rows * (size_t)meff * sizeof(double));
+    double *g = (double *)xmalloc((size_t)rows * sizeof(double));
+    for (int32_t r = 0; r < rows; ++r) {
+        g[r] = 0.0;
+        for (int32_t c = 0; c < meff; ++c) H[r * meff + c] = R[r * cols + (c + 1)];
+    }
+    g[0] = R[0];
+    for (int32_t k = 0; k < meff; ++k) {
+        double a = H[k * meff + k], b = H[(k + 1) * meff + k];
+        double rr = hypot(a, b);
+        if (rr == 0.0) continue;
+        double c = a / rr, s = b / rr;
+        for (int32_t j = k; j < meff; ++j) {
+            double t1 = H[k * meff + j], t2 = H[(k + 1) * meff + j];
+            H[k * meff + j] = c * t1 + s * t2;
+            H[(k + 1) * meff + j] = -s * t1 + c * t2;
+        }
+        double t1 = g[k], t2 = g[k + 1];
+        g[k] = c * t1 + s * t2;
+        g[k + 1] = -s * t1 + c * t2;
+    }
+    double *w = (double *)xmalloc((size_t)meff * sizeof(double));
+    for (int32_t k = meff - 1; k >= 0; --k) {
+        double s = g[k];
+        for (int32_t j = k + 1; j < meff; ++j) s -= H[k * meff + j] * w[j];
+        w[k] = H[k * meff + k] != 0.0 ? s / H[k * meff + k] : 0.0;
+    }
+    for (int32_t k = 0; k < meff; ++k) alpha[k] = w[k] * colnorm[0] / colnorm[k + 1];
+    free(H); free(g); free(w);
+    return meff;
+}
+
+/* Steps 3-6 together: coefficients of the stationary GMRES polynomial
+ * q_{m-1} (m coefficients alpha_0..alpha_{m-1}) from a random rhs. */
+int orc_gmres_poly(const orc_csr *A, uint64_t seed, int32_t level, int32_t m, double *alpha)
+{
+    int64_t n = A->nr;
+    double *K = (double *)xmalloc((size_t)n * (size_t)(m + 1) * sizeof(double));
+    double *R = (double *)xmalloc((size_t)(m + 1) * (size_t)(m + 1) * sizeof(double));
+    double *nrm = (double *)xmalloc((size_t)(m + 1) * sizeof(double));
+    orc_gauss_rhs(n, seed, level, K);
+    orc_power_basis(A, K, m, K);
+    orc_householder_r(n, m + 1, K, R, nrm);
+    int used = orc_poly_coeffs_from_r(R, nrm, m, alpha);
+    free(K); free(R); free(nrm);
+    return used;
+}
+
+/* Steps 7-8: assembled fixed-sparsity polynomial (fixed-sparsity equation)
+ *   Ainv = alpha_0 I + alpha_1 A + sum_{k>=2} alpha_k A~^k,
+ * first-order sparsity.  Reading of "powers with entries outside the
+ * sparsity of A_ff dropped" that fits the row-independent fast method: for
+ * row i with J_i = pattern(A row i) u {i} and M_i = A(J_i, J_i), row i of
+ * A~^k is e_i^T M_i^k restricted to J_i (v_k = v_{k-1} M_i, each entry summed
+ * over J_i in ascending order), and the row of Ainv is sum_k alpha_k v_k
+ * accumulated in ascending k.  Pattern of Ainv: pattern(A) u diag. */
+int orc_poly_fixed_sparsity(const orc_csr *A, const double *alpha, int32_t nalpha, orc_csr *out)
+{
+    int64_t n = A->nr;
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int has = 0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) has |= A->ci[k] == i;
+        nnz += A->rp[i + 1] - A->rp[i] + !has;
+    }
+    csr_alloc(out, n, n, nnz, 1);
+    int32_t *pos = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
+    for (int64_t j = 0; j < n; ++j) pos[j] = -1;
+    int64_t maxlen = 1;
+    for (int64_t i = 0; i < n; ++i)
+        if (A->rp[i + 1] - A->rp[i] + 1 > maxlen) maxlen = A->rp[i + 1] - A->rp[i] + 1;
+    int32_t *J = (int32_t *)xmalloc((size_t)maxlen * sizeof(int32_t));
+    double *v = (double *)xmalloc((size_t)maxlen * sizeof(double));
+    double *vn = (double *)xmalloc((size_t)maxlen * sizeof(double));
+    double *acc = (double *)xmalloc((size_t)maxlen * sizeof(double));
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t L = 0;
+        int inserted = 0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+            if (!inserted && A->ci[k] > i) { J[L++] = (int32_t)i; inserted = 1; }
+            if (A->ci[k] == i) inserted = 1;
+            J[L++] = A->ci[k];
+        }
+        if (!inserted) J[L++] = (int32_t)i;
+        for (int64_t a = 0; a < L; ++a) pos[J[a]] = (int32_t)a;
+        for (int64_t a = 0; a < L; ++a) v[a] = J[a] == i ? 1.0 : 0.0;
+        for (int64_t a = 0; a < L; ++a) acc[a] = alpha[0] * v[a];
+        for (int32_t k = 1; k < nalpha; ++k) {
+            for (int64_t b = 0; b < L; ++b) vn[b] = 0.0;
+            for (int64_t a = 0; a < L; ++a) {
+                int32_t p = J[a];
+                for (int64_t kk = A->rp[p]; kk < A->rp[p + 1]; ++kk) {
+                    int32_t b = pos[A->ci[kk]];
+                    if (b >= 0) vn[b] += v[a] * A->v[kk];
+                }
+            }
+            for (int64_t b = 0; b < L; ++b) {
+                v[b] = vn[b];
+                acc[b] += alpha[k] * v[b];
+            }
+        }
+        out->rp[i] = w;
+        for (int64_t a = 0; a < L; ++a) {
+            out->ci[w] = J[a];
+            out->v[w] = acc[a];
+            w++;
+            pos[J[a]] = -1;
+        }
+    }
+    out->rp[n] = w;
+    free(pos); free(J); free(v); free(vn); free(acc);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid transfer and coarse operator                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Classical one-point prolongator (setup step 10; Results: "classical
+ * one-point operator").  Row f(i) of W (n_F x n_C) has a single entry at
+ * c(j*), j* = argmax_{j != i} |a_ij| (ties to the smallest j), weight 1
+ * (weight_mode 0) or -a_ij* / a_ii (weight_mode 1); rows with no nonzero
+ * off-diagonal, or whose strongest neighbour is not a C point, are empty. */
+int orc_onepoint_w(const orc_csr *A, const int8_t *cf, int32_t weight_mode, orc_csr *W)
+{
+    int64_t n = A->nr, nF = 0, nC = 0;
+    int32_t *cmap = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) {
+        cmap[i] = cf[i] == ORC_C ? (int32_t)nC++ : -1;
+        nF += cf[i] == ORC_F;
+    }
+    csr_alloc(W, nF, nC, nF, 1);
+    int64_t r = 0, w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i] != ORC_F) continue;
+        W->rp[r] = w;
+        double best = 0.0, diag = 0.0;
+        int64_t bk = -1;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+            if (A->ci[k] == i) { diag = A->v[k]; continue; }
+            if (fabs(A->v[k]) > best) { best = fabs(A->v[k]); bk = k; }
+        }
+        if (bk >= 0 && cmap[A->ci[bk]] >= 0) {
+            W->ci[w] = cmap[A->ci[bk]];
+            W->v[w] = weight_mode == 1 ? -A->v[bk] / diag : 1.0;
+            w++;
+        }
+        r++;
+    }
+    W->rp[nF] = w;
+    free(cmap);
+    return 0;
+}
+
+/* Approximate ideal restrictor (setup step 9, prolongation equation):
+ * Z = -A_cf Ainv, then dropped by tau_R relative to each row's max. */
+int orc_restrictor(const orc_csr *Acf, const orc_csr *Ainv, double drop_R, orc_csr *Z)
+{
+    orc_csr P;
+    orc_spgemm(Acf, Ainv, &P);
+    for (int64_t k = 0; k < P.rp[P.nr]; ++k) P.v[k] = -P.v[k];
+    orc_drop(&P, drop_R, 0, Z);
+    orc_csr_free(&P);
+    return 0;
+}
+
+/* Galerkin coarse operator (setup step 11): A_c = R (A P) by two sparse
+ * products in the full index space, P = [W; I] (n x n_C), R = [Z I]
+ * (n_C x n), coarse index = C rank; then dropped by tau_A with the diagonal
+ * kept. */
+int orc_coarse_operator(const orc_csr *A, const int8_t *cf, const orc_csr *Z, const orc_csr *W,
+                        double drop_A, orc_csr *Ac)
+{
+    int64_t n = A->nr, nC = Z->nr, nF = W->nr;
+    int32_t *fidx = (int32_t *)xmalloc((size_t)(nF > 0 ? nF : 1) * sizeof(int32_t));
+    int32_t *cidx = (int32_t *)xmalloc((size_t)(nC > 0 ? nC : 1) * sizeof(int32_t));
+    int32_t *frank = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
+    int32_t *crank = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
+    int64_t f = 0, c = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        frank[i] = crank[i] = -1;
+        if (cf[i] == ORC_F) { fidx[f] = (int32_t)i; frank[i] = (int32_t)f++; }
+        else { cidx[c] = (int32_t)i; crank[i] = (int32_t)c++; }
+    }
+    /* P = [W; I] */
+    orc_csr P;
+    csr_alloc(&P, n, nC, W->rp[nF] + nC, 1);
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        P.rp[i] = w;
+        if (cf[i] == ORC_F) {
+            int64_t r = frank[i];
+            for (int64_t k = W->rp[r]; k < W->rp[r + 1]; ++k) { P.ci[w] = W->ci[k]; P.v[w] = W->v[k]; w++; }
+        } else {
+            P.ci[w] = crank[i];
+            P.v[w] = 1.0;
+            w++;
+        }
+    }
+    P.rp[n] = w;
+    /* R = [Z I] with Z's columns mapped back to original F indices */
+    orc_csr R;
+    csr_alloc(&R, nC, n, Z->rp[nC] + nC, 1);
+    w = 0;
+    for (int64_t r = 0; r < nC; ++r) {
+        R.rp[r] = w;
+        int placed = 0;
+        for (int64_t k = Z->rp[r]; k < Z->rp[r + 1]; ++k) {
+            int32_t g = fidx[Z->ci[k]];
+            if (!placed && g > cidx[r]) { R.ci[w] = cidx[r]; R.v[w] = 1.0; w++; placed = 1; }
+            R.ci[w] = g;
+            R.v[w] = Z->v[k];
+            w++;
+        }
+        if (!placed) { R.ci[w] = cidx[r]; R.v[w] = 1.0; w++; }
+    }
+    R.rp[nC] = w;
+    orc_csr AP, RAP;
+    orc_spgemm(A, &P, &AP);
+    orc_spgemm(&R, &AP, &RAP);
+    orc_drop(&RAP, drop_A, 1, Ac);
+    orc_csr_free(&P); orc_csr_free(&R); orc_csr_free(&AP); orc_csr_free(&RAP);
+    free(fidx); free(cidx); free(frank); free(crank);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchy                                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct orc_level {
+    orc_csr A, Ainv, Z, W, Aff, Afc;
+    int8_t *cf;
+    int64_t nF, nC;
+    int32_t *fidx, *cidx;
+    double *alpha;
+    int32_t nalpha;
+} orc_level;
+
+struct orc_hier {
+    int32_t nlev;
+    orc_params p;
+    orc_level lev[ORC_MAX_LEVELS];
+};
+
+int orc_level_build(const orc_csr *A, const orc_params *p, int32_t level, const double *alpha_in,
+                    int8_t *cf, double *alpha_out, orc_csr *Ainv, orc_csr *Z, orc_csr *W, orc_csr *Ac)
+{
+    int32_t m = p->poly_order + 1;
+    orc_cf_split(A, p, level, cf);
+    orc_csr Aff, Acf;
+    orc_submatrix(A, cf, ORC_F, ORC_F, &Aff);
+    orc_submatrix(A, cf, ORC_C, ORC_F, &Acf);
+    if (alpha_in) memcpy(alpha_out, alpha_in, (size_t)m * sizeof(double));
+    else orc_gmres_poly(&Aff, p->seed, level, m, alpha_out);
+    orc_poly_fixed_sparsity(&Aff, alpha_out, m, Ainv);
+    orc_restrictor(&Acf, Ainv, p->drop_R, Z);
+    orc_onepoint_w(A, cf, p->onepoint_weight, W);
+    orc_coarse_operator(A, cf, Z, W, p->drop_A, Ac);
+    orc_csr_free(&Aff);
+    orc_csr_free(&Acf);
+    return 0;
+}
+
+/* Input canonicalisation: columns must be sorted and unique with the
+ * diagonal present; exact-zero off-diagonal entries are removed. */
+static int canonical_copy(const orc_csr *A, orc_csr *B)
+{
+    int64_t n = A->nr, nnz = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int has = 0;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
+            if (k > A->rp[i] && A->ci[k] <= A->ci[k - 1]) return -2;
+            if (A->ci[k] < 0 || A->ci[k] >= n) return -2;
+            if (!isfinite(A->v[k])) return -4;
+            if (A->ci[k] == i) { has = 1; if (A->v[k] == 0.0) return -3; }
+            nnz += A->ci[k] == i || A->v[k] != 0.0;
+        }
+        if (!has) return -3;
+    }
+    csr_alloc(B, n, n, nnz, 1);
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        B->rp[i] = w;
+        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
+            if (A->ci[k] == i || A->v[k] != 0.0) { B->ci[w] = A->ci[k]; B->v[w] = A->v[k]; w++; }
+    }
+    B->rp[n] = w;
+    return 0;
+}
+
+/* Setup recipe of the AIRG subsection applied level by level.
+ * Termination (reading): level l is the coarsest if n_l <= truncate_n (when
+ * set), l = max_levels-1, or its CF splitting gives n_F = 0 or a coarse grid
+ * with fewer points than the polynomial order.  The coarsest level carries a
+ * fixed-sparsity polynomial of order coarse_poly_order built on its whole
+ * matrix (truncation with a GMRES-polynomial coarse solve). */
+orc_hier *orc_setup(const orc_csr *A0, const orc_params *p)
+{
+    orc_hier *h = (orc_hier *)xcalloc(1, sizeof(orc_hier));
+    h->p = *p;
+    if (canonical_copy(A0, &h->lev[0].A) != 0) { free(h); return NULL; }
+    int32_t maxl = p->max_levels < ORC_MAX_LEVELS ? p->max_levels : ORC_MAX_LEVELS;
+    for (int32_t l = 0;; ++l) {
+        orc_level *L = &h->lev[l];
+        int64_t n = L->A.nr;
+        int coarsest = (p->truncate_n > 0 && n <= p->truncate_n) || l == maxl - 1;
+        if (!coarsest) {
+            L->cf = (int8_t *)xmalloc((size_t)n);
+            orc_cf_split(&L->A, p, l, L->cf);
+            L->nF = L->nC = 0;
+            for (int64_t i = 0; i < n; ++i) { L->nF += L->cf[i] == ORC_F; L->nC += L->cf[i] == ORC_C; }
+            if (L->nF == 0 || L->nC < p->poly_order) {
+                coarsest = 1;
+                free(L->cf);
+                L->cf = NULL;
+            }
+        }
+        if (coarsest) {
+            int32_t m = p->coarse_poly_order + 1;
+            L->alpha = (double *)xcalloc((size_t)m, sizeof(double));
+            L->nalpha = m;
+            orc_gmres_poly(&L->A, p->seed, l, m, L->alpha);
+            orc_poly_fixed_sparsity(&L->A, L->alpha, m, &L->Ainv);
+            L->nF = n;
+            L->nC = 0;
+            h->nlev = l + 1;
+            break;
+        }
+        int32_t m = p->poly_order + 1;
+        L->fidx = (int32_t *)xmalloc((size_t)(L->nF > 0 ? L->nF : 1) * sizeof(int32_t));
+        L->cidx = (int32_t *)xmalloc((size_t)(L->nC > 0 ? L->nC : 1) * sizeof(int32_t));
+        int64_t f = 0, c = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (L->cf[i] == ORC_F) L->fidx[f++] = (int32_t)i;
+            else L->cidx[c++] = (int32_t)i;
+        }
+        orc_csr Acf;
+        orc_submatrix(&L->A, L->cf, ORC_F, ORC_F, &L->Aff);
+        orc_submatrix(&L->A, L->cf, ORC_F, ORC_C, &L->Afc);
+        orc_submatrix(&L->A, L->cf, ORC_C, ORC_F, &Acf);
+        L->alpha = (double *)xcalloc((size_t)m, sizeof(double));
+        L->nalpha = m;
+        orc_gmres_poly(&L->Aff, p->seed, l, m, L->alpha);
+        orc_poly_fixed_sparsity(&L->Aff, L->alpha, m, &L->Ainv);
+        orc_restrictor(&Acf, &L->Ainv, p->drop_R, &L->Z);
+        orc_onepoint_w(&L->A, L->cf, p->onepoint_weight, &L->W);
+        orc_coarse_operator(&L->A, L->cf, &L->Z, &L->W, p->drop_A, &h->lev[l + 1].A);
+        orc_csr_free(&Acf);
+    }
+    return h;
+}
+
+void orc_hier_free(orc_hier *h)
+{
+    if (!h) return;
+    for (int32_t l = 0; l < h->nlev; ++l) {
+        orc_level *L = &h->lev[l];
+        orc_csr_free(&L->A); orc_csr_free(&L->Ainv); orc_csr_free(&L->Z);
+        orc_csr_free(&L->W); orc_csr_free(&L->Aff); orc_csr_free(&L->Afc);
+        free(L->cf); free(L->fidx); free(L->cidx); free(L->alpha);
+    }
+    free(h);
+}
+
+int32_t orc_hier_levels(const orc_hier *h) { return h->nlev; }
+
+const orc_csr *orc_hier_matrix(const orc_hier *h, int32_t level, int32_t which)
+{
+    if (level < 0 || level >= h->nlev) return NULL;
+    const orc_level *L = &h->lev[level];
+    const orc_csr *M[6] = {&L->A, &L->Ainv, &L->Z, &L->W, &L->Aff, &L->Afc};
+    if (which < 0 || which > 5 || M[which]->rp == NULL) return NULL;
+    return M[which];
+}
+
+const int8_t *orc_hier_cf(const orc_hier *h, int32_t level)
+{
+    if (level < 0 || level >= h->nlev) return NULL;
+    return h->lev[level].cf;
+}
+
+const double *orc_hier_alpha(const orc_hier *h, int32_t level, int32_t *nalpha)
+{
+    if (level < 0 || level >= h->nlev) return NULL;
+    *nalpha = h->lev[level].nalpha;
+    return h->lev[level].alpha;
+}
+
+/* V-cycle with up F-point smoothing only (Results: two up F-point smooths,
+ * no down smooths, approximate ideal restrictor, one-point prolongator):
+ *   g_c = Z g_F + g_C;  e_C = V(g_c);  e_F = W e_C;
+ *   repeat nu times: e_F += Ainv (g_F - A_ff e_F - A_fc e_C).
+ * Coarsest level: e = Ainv g, then (v_c - 1) times e += Ainv (g - A e). */
+void orc_vcycle(const orc_hier *h, int32_t level, const double *g, double *e)
+{
+    const orc_level *L = &h->lev[level];
+    int64_t n = L->A.nr;
+    if (level == h->nlev - 1) {
+        orc_spmv(&L->Ainv, g, e);
+        double *r = (double *)xmalloc((size_t)n * sizeof(double));
+        double *t = (double *)xmalloc((size_t)n * sizeof(double));
+        for (int32_t it = 1; it < h->p.coarse_iters; ++it) {
+            orc_spmv(&L->A, e, t);
+            for (int64_t i = 0; i < n; ++i) r[i] = g[i] - t[i];
+            orc_spmv(&L->Ainv, r, t);
+            for (int64_t i = 0; i < n; ++i) e[i] += t[i];
+        }
+        free(r); free(t);
+        return;
+    }
+    int64_t nF = L->nF, nC = L->nC;
+    double *gF = (double *)xmalloc((size_t)(nF + 1) * sizeof(double));
+    double *gc = (double *)xmalloc((size_t)(nC + 1) * sizeof(double));
+    double *ec = (double *)xmalloc((size_t)(nC + 1) * sizeof(double));
+    double *tF = (double *)xmalloc((size_t)(nF + 1) * sizeof(double));
+    double *dF = (double *)xmalloc((size_t)(nF + 1) * sizeof(double));
+    double *t = (double *)xmalloc((size_t)n * sizeof(double));
+    for (int64_t f = 0; f < nF; ++f) gF[f] = g[L->fidx[f]];
+    orc_spmv(&L->Z, gF, gc);
+    for (int64_t c = 0; c < nC; ++c) gc[c] += g[L->cidx[c]];
+    orc_vcycle(h, level + 1, gc, ec);
+    orc_spmv(&L->W, ec, tF);
+    for (int64_t c = 0; c < nC; ++c) e[L->cidx[c]] = ec[c];
+    for (int64_t f = 0; f < nF; ++f) e[L->fidx[f]] = tF[f];
+    for (int32_t s = 0; s < h->p.up_smooths; ++s) {
+        orc_spmv(&L->A, e, t);
+        for (int64_t f = 0; f < nF; ++f) tF[f] = g[L->fidx[f]] - t[L->fidx[f]];
+        orc_spmv(&L->Ainv, tF, dF);
+        for (int64_t f = 0; f < nF; ++f) e[L->fidx[f]] += dF[f];
+    }
+    free(gF); free(gc); free(ec); free(tF); free(dF); free(t);
+}
+
+static double nrm2(int64_t n, const double *x)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += x[i] * x[i];
+    return sqrt(s);
+}
+
+/* Undamped Richardson with a zero initial guess (Results):
+ * x += V(b - A x) until ||b - A x||_2 <= rtol ||b||_2.  Returns the number of
+ * V-cycles. */
+int orc_richardson(const orc_hier *h, const double *b, double *x, double rtol, int32_t maxit, double *relres)
+{
+    const orc_csr *A = &h->lev[0].A;
+    int64_t n = A->nr;
+    double *r = (double *)xmalloc((size_t)n * sizeof(double));
+    double *e = (double *)xmalloc((size_t)n * sizeof(double));
+    double nb = nrm2(n, b);
+    for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    int it = 0;
+    double rr = nb;
+    while (rr > rtol * nb && it < maxit) {
+        orc_vcycle(h, 0, r, e);
+        for (int64_t i = 0; i < n; ++i) x[i] += e[i];
+        orc_spmv(A, x, r);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+        rr = nrm2(n, r);
+        it++;
+    }
+    if (relres) *relres = nb > 0.0 ? rr / nb : 0.0;
+    free(r); free(e);
+    return it;
+}
+
+/* Flexible GMRES(restart), right preconditioned by one V-cycle, classical
+ * Gram-Schmidt applied twice, true residual recomputed at each restart.
+ * Returns the number of V-cycles. */
+int orc_fgmres(const orc_hier *h, const double *b, double *x, double rtol, int32_t maxit, int32_t restart,
+               double *relres)
+{
+    const orc_csr *A = &h->lev[0].A;
+    int64_t n = A->nr;
+    int32_t k = restart;
+    double *V = (double *)xmalloc((size_t)n * (size_t)(k + 1) * sizeof(double));
+    double *Zb = (double *)xmalloc((size_t)n * (size_t)k * sizeof(double));
+    double *H = (double *)xcalloc((size_t)(k + 1) * (size_t)k, sizeof(double));
+    double *cs = (double *)xmalloc((size_t)k * sizeof(double));
+    double *sn = (double *)xmalloc((size_t)k * sizeof(double));
+    double *s = (double *)xmalloc((size_t)(k + 1) * sizeof(double));
+    double *y = (double *)xmalloc((size_t)k * sizeof(double));
+    double *hc = (double *)xmalloc((size_t)(k + 1) * sizeof(double));
+    double *r = (double *)xmalloc((size_t)n * sizeof(double));
+    double nb = nrm2(n, b);
+    for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
+    double beta = nb;
+    int it = 0;
+    while (beta > rtol * nb && it < maxit) {
+        for (int64_t i = 0; i < n; ++i) V[i] = r[i] / beta;
+        for (int32_t i = 0; i <= k; ++i) s[i] = 0.0;
+        s[0] = beta;
+        int32_t j = 0;
+        for (; j < k && it < maxit; ++j) {
+            double *vj = V + (size_t)j * n, *zj = Zb + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
+            orc_vcycle(h, 0, vj, zj);
+            it++;
+            orc_spmv(A, zj, w);
+            for (int32_t i = 0; i <= j; ++i) H[i * k + j] = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int32_t i = 0; i <= j; ++i) {
+                    const double *vi = V + (size_t)i * n;
+                    double d = 0.0;
+                    for (int64_t q = 0; q < n; ++q) d += vi[q] * w[q];
+                    hc[i] = d;
+                }
+                for (int32_t i = 0; i <= j; ++i) {
+                    const double *vi = V + (size_t)i * n;
+                    for (int64_t q = 0; q < n; ++q) w[q] -= hc[i] * vi[q];
+                    H[i * k + j] += hc[i];
+                }
+            }
+            double hn = nrm2(n, w);
+            H[(j + 1) * k + j] = hn;
+            if (hn > 0.0)
+                for (int64_t q = 0; q < n; ++q) w[q] /= hn;
+            for (int32_t i = 0; i < j; ++i) {
+                double t1 = H[i * k + j], t2 = H[(i + 1) * k + j];
+                H[i * k + j] = cs[i] * t1 + sn[i] * t2;
+                H[(i + 1) * k + j] = -sn[i] * t1 + cs[i] * t2;
+            }
+            double a = H[j * k + j], bb = H[(j + 1) * k + j];
+            double rr = hypot(a, bb);
+            cs[j] = rr > 0.0 ? a / rr : 1.0;
+            sn[j] = rr > 0.0 ? bb / rr : 0.0;
+            H[j * k + j] = rr;
+            H[(j + 1) * k + j] = 0.0;
+            s[j + 1] = -sn[j] * s[j];
+            s[j] = cs[j] * s[j];
+            if (fabs(s[j + 1]) <= rtol * nb || hn == 0.0) { ++j; break; }
+        }
+        for (int32_t i = j - 1; i >= 0; --i) {
+            double t = s[i];
+            for (int32_t q = i + 1; q < j; ++q) t -= H[i * k + q] * y[q];
+            y[i] = H[i * k + i] != 0.0 ? t / H[i * k + i] : 0.0;
+        }
+        for (int32_t i = 0; i < j; ++i) {
+            const double *zi = Zb + (size_t)i * n;
+            for (int64_t q = 0; q < n; ++q) x[q] += y[i] * zi[q];
+        }
+        orc_spmv(A, x, r);
+        for (int64_t q = 0; q < n; ++q) r[q] = b[q] - r[q];
+        beta = nrm2(n, r);
+    }
+    if (relres) *relres = nb > 0.0 ? beta / nb : 0.0;
+    free(V); free(Zb); free(H); free(cs); free(sn); free(s); free(y); free(hc); free(r);
+    return it;
+}
+
+/* Grid and operator complexity (Results, strong-tolerance subsection) and
+ * storage complexity (storage equation): per level below the coarsest
+ * Ainv, A_ff, A_fc, R = [Z I] and P = [W; I]; on the coarsest level Ainv,
+ * plus A when more than one coarse iteration is run. */
+void orc_hier_complexity(const orc_hier *h, double *grid, double *op, double *storage)
+{
+    double n0 = (double)h->lev[0].A.nr, z0 = (double)h->lev[0].A.rp[h->lev[0].A.nr];
+    double gs = 0.0, os = 0.0, ss = 0.0;
+    for (int32_t l = 0; l < h->nlev; ++l) {
+        const orc_level *L = &h->lev[l];
+        gs += (double)L->A.nr;
+        os += (double)L->A.rp[L->A.nr];
+        if (l == h->nlev - 1) {
+            ss += (double)L->Ainv.rp[L->Ainv.nr];
+            if (h->p.coarse_iters > 1) ss += (double)L->A.rp[L->A.nr];
+        } else {
+            ss += (double)L->Ainv.rp[L->Ainv.nr] + (double)L->Aff.rp[L->Aff.nr] + (double)L->Afc.rp[L->Afc.nr] +
+                  (double)L->Z.rp[L->Z.nr] + (double)L->nC + (double)L->W.rp[L->W.nr] + (double)L->nC;
+        }
+    }
+    *grid = gs / n0;
+    *op = os / z0;
+    *storage = ss / z0;
+}
