@@ -1,0 +1,416 @@
+// CF splitting kernels for gfx950: strength of connection, the transposed
+// strength lists, PMISR rounds decided with wavefront ballots, and the DDC
+// diagonal-dominance scan with a fixed summation order.
+#include <cmath>
+
+#include "cfsplit.hpp"
+#include "csr.hpp"
+#include "group.hpp"
+
+namespace airg {
+
+// ------------------------------------------------------------- strength ---
+template <int G>
+__global__ void __launch_bounds__(256) k_strength(int32_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  double alpha, uint8_t *__restrict__ strong,
+                                                  int32_t *__restrict__ cntS) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    int32_t b = rp[row], e = rp[row + 1];
+    double M = 0.0;
+    for (int32_t k = b + lane; k < e; k += G)
+        if (ci[k] != row) M = fmax(M, fabs(v[k]));
+    M = group_max<G>(M);          // order-free, exact
+    double thr = alpha * M;       // one correctly rounded product
+    int32_t c = 0;
+    for (int32_t k = b + lane; k < e; k += G) {
+        double a = fabs(v[k]);
+        bool st = ci[k] != row && a > 0.0 && a >= thr;
+        strong[k] = st;
+        c += st;
+    }
+    c = group_sum<G>(c);
+    if (lane == 0) cntS[row] = c;
+}
+
+// Per strong entry (i, j): count it for S^T_j, and find whether i in S_j
+// (binary search of column i in row j) to count mutual pairs.
+template <int G>
+__global__ void __launch_bounds__(256) k_strength_mutual(int32_t n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const uint8_t *__restrict__ strong,
+                                                         int32_t *__restrict__ cntT, int32_t *__restrict__ mutual) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    int32_t mu = 0;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
+        if (!strong[k]) continue;
+        int32_t j = ci[k];
+        atomicAdd(&cntT[j], 1);
+        int32_t lo = rp[j], hi = rp[j + 1];
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (ci[mid] < row) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < rp[j + 1] && ci[lo] == row && strong[lo]) ++mu;
+    }
+    mu = group_sum<G>(mu);
+    if (lane == 0) mutual[row] = mu;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_strength_scatter(int32_t n, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ ci,
+                                                          const uint8_t *__restrict__ strong,
+                                                          const int32_t *__restrict__ trp,
+                                                          int32_t *__restrict__ cursor, int32_t *__restrict__ tci) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
+        if (!strong[k]) continue;
+        int32_t j = ci[k];
+        tci[trp[j] + atomicAdd(&cursor[j], 1)] = row;
+    }
+}
+
+__global__ void k_degree(int32_t n, const int32_t *__restrict__ cntS, const int32_t *__restrict__ cntT,
+                         const int32_t *__restrict__ mutual, int32_t *__restrict__ deg) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) deg[i] = cntS[i] + cntT[i] - mutual[i];
+}
+
+StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
+    StrengthGraph G;
+    int32_t n = A.nr;
+    G.n = n;
+    G.strong.alloc((size_t)A.nnz, s);
+    G.deg.alloc((size_t)n, s);
+    G.trp.alloc((size_t)n + 1, s);
+    DBuf<int32_t> cntS((size_t)n, s), cntT((size_t)n + 1, s), mutual((size_t)n, s);
+    fill_zero(cntT.p, ((size_t)n + 1) * 4, s);
+    int g = lanes_for(A.nnz, n);
+    dispatch_group(g, [&]<int W>() {
+        unsigned grid = grid_for((int64_t)n * W, 256);
+        k_strength<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, A.v, alpha, G.strong.p, cntS.p);
+        k_strength_mutual<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, cntT.p, mutual.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    k_degree<<<grid_for(n, 256), 256, 0, s>>>(n, cntS.p, cntT.p, mutual.p, G.deg.p);
+    AIRG_LAUNCH_CHECK();
+    int64_t nt = exclusive_scan(cntT.p, G.trp.p, n, s);
+    G.tci.alloc((size_t)nt, s);
+    DBuf<int32_t> cursor((size_t)n, s);
+    fill_zero(cursor.p, (size_t)n * 4, s);
+    dispatch_group(g, [&]<int W>() {
+        k_strength_scatter<W><<<grid_for((int64_t)n * W, 256), 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p,
+                                                                            cursor.p, G.tci.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    return G;
+}
+
+// ---------------------------------------------------------------- PMISR ---
+__global__ void k_pmisr_hash(int32_t n, uint64_t seed, int32_t level, uint32_t *__restrict__ h) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) h[i] = (uint32_t)(splitmix64(rng_counter(seed, 0, (uint32_t)level, (uint64_t)i)) >> 32);
+}
+
+void pmisr_hash(int32_t n, uint64_t seed, int32_t level, uint32_t *h, hipStream_t s) {
+    k_pmisr_hash<<<grid_for(n, 256), 256, 0, s>>>(n, seed, level, h);
+    AIRG_LAUNCH_CHECK();
+}
+
+// Measure order: (deg, h, index) lexicographic -- the integer form of
+// w = deg + rand(0,1) with the index breaking exact ties.
+__device__ inline bool key_less(int32_t dj, uint32_t hj, int32_t j, int32_t di, uint32_t hi, int32_t i) {
+    if (dj != di) return dj < di;
+    if (hj != hi) return hj < hi;
+    return j < i;
+}
+
+__global__ void k_pmisr_init(int32_t n, const int32_t *__restrict__ deg, int8_t *__restrict__ cf) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) cf[i] = deg[i] == 0 ? CF_F : CF_U;
+}
+
+// D = unassigned nodes whose key is below every unassigned neighbour's key
+// in S_i u S_i^T, taken from the state at the start of the round.  The group
+// walks both neighbour lists and a wavefront ballot decides.
+template <int G>
+__global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      const uint8_t *__restrict__ strong,
+                                                      const int32_t *__restrict__ trp,
+                                                      const int32_t *__restrict__ tci,
+                                                      const int32_t *__restrict__ deg,
+                                                      const uint32_t *__restrict__ h,
+                                                      const int8_t *__restrict__ cf, uint8_t *__restrict__ inD) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    if (cf[row] != CF_U) {
+        if (lane == 0) inD[row] = 0;
+        return;
+    }
+    int32_t di = deg[row];
+    uint32_t hi = h[row];
+    bool beaten = false;
+    int32_t e = rp[row + 1];
+    for (int32_t base = rp[row]; base < e; base += G) {
+        int32_t k = base + lane;
+        bool lose = false;
+        if (k < e && strong[k]) {
+            int32_t j = ci[k];
+            lose = cf[j] == CF_U && key_less(deg[j], h[j], j, di, hi, row);
+        }
+        if (group_any<G>(lose)) { beaten = true; break; }
+    }
+    if (!beaten) {
+        int32_t te = trp[row + 1];
+        for (int32_t base = trp[row]; base < te; base += G) {
+            int32_t k = base + lane;
+            bool lose = false;
+            if (k < te) {
+                int32_t j = tci[k];
+                lose = cf[j] == CF_U && key_less(deg[j], h[j], j, di, hi, row);
+            }
+            if (group_any<G>(lose)) { beaten = true; break; }
+        }
+    }
+    if (lane == 0) inD[row] = !beaten;
+}
+
+// D joins F; unassigned nodes with a neighbour in D join C.
+template <int G>
+__global__ void __launch_bounds__(256) k_pmisr_apply(int32_t n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci,
+                                                     const uint8_t *__restrict__ strong,
+                                                     const int32_t *__restrict__ trp,
+                                                     const int32_t *__restrict__ tci,
+                                                     const uint8_t *__restrict__ inD, int8_t *__restrict__ cf) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    if (cf[row] != CF_U) return;
+    if (inD[row]) {
+        if (lane == 0) cf[row] = CF_F;
+        return;
+    }
+    bool hit = false;
+    int32_t e = rp[row + 1];
+    for (int32_t base = rp[row]; base < e && !hit; base += G) {
+        int32_t k = base + lane;
+        bool p = k < e && strong[k] && inD[ci[k]];
+        hit = group_any<G>(p);
+    }
+    int32_t te = trp[row + 1];
+    for (int32_t base = trp[row]; base < te && !hit; base += G) {
+        int32_t k = base + lane;
+        bool p = k < te && inD[tci[k]];
+        hit = group_any<G>(p);
+    }
+    if (hit && lane == 0) cf[row] = CF_C;
+}
+
+__global__ void k_pmisr_finish(int32_t n, int8_t *__restrict__ cf, int32_t *__restrict__ nu) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == CF_U) {
+        if (nu) atomicAdd(nu, 1);
+        else cf[i] = CF_C;
+    }
+}
+
+int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_rounds, int8_t *cf, hipStream_t s) {
+    int32_t n = A.nr;
+    DBuf<uint8_t> inD((size_t)n, s);
+    DBuf<int32_t> nu(1, s);
+    k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, cf);
+    AIRG_LAUNCH_CHECK();
+    int g = lanes_for(A.nnz, n);
+    int rounds = 0;
+    for (;;) {
+        if (max_rounds > 0 && rounds >= max_rounds) break;
+        if (max_rounds <= 0) {
+            fill_zero(nu.p, 4, s);
+            k_pmisr_finish<<<grid_for(n, 256), 256, 0, s>>>(n, cf, nu.p);
+            AIRG_LAUNCH_CHECK();
+            if (d2h_one(nu.p, s) == 0) break;
+        }
+        dispatch_group(g, [&]<int W>() {
+            unsigned grid = grid_for((int64_t)n * W, 256);
+            k_pmisr_decide<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, G.deg.p, h, cf,
+                                                   inD.p);
+            k_pmisr_apply<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, inD.p, cf);
+        });
+        AIRG_LAUNCH_CHECK();
+        ++rounds;
+    }
+    k_pmisr_finish<<<grid_for(n, 256), 256, 0, s>>>(n, cf, nullptr);
+    AIRG_LAUNCH_CHECK();
+    return rounds;
+}
+
+// ------------------------------------------------------------------ DDC ---
+// theta_i = (sum over F columns j != i of |a_ij|, in ascending column order
+// from +0.0) / |a_ii|.  The group loads a chunk of the row coalesced and every
+// lane folds the chunk in order from the broadcast terms, so the sum is the
+// sequential one.
+template <int G>
+__device__ inline void ddc_row_theta(const int32_t *rp, const int32_t *ci, const double *v, const int8_t *cf,
+                                     int32_t row, int lane, double *s_out, double *d_out) {
+    double s = 0.0, d = 0.0;
+    int32_t e = rp[row + 1];
+    for (int32_t base = rp[row]; base < e; base += G) {
+        int32_t k = base + lane;
+        double term = 0.0, dd = 0.0;
+        if (k < e) {
+            int32_t j = ci[k];
+            if (j == row) dd = v[k];
+            else if (cf[j] == CF_F) term = fabs(v[k]);
+        }
+        int cnt = e - base < G ? e - base : G;
+        for (int q = 0; q < cnt; ++q) {
+            s += group_bcast<G>(term, q);
+        }
+        d += group_sum<G>(dd);   // exactly one lane holds the diagonal
+    }
+    *s_out = s;
+    *d_out = d;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_ddc(int32_t n, const int32_t *__restrict__ rp,
+                                             const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                             double alpha_diag, const int8_t *__restrict__ cf_in,
+                                             int8_t *__restrict__ cf_out, double *__restrict__ theta) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    int8_t c = cf_in[row];
+    if (c != CF_F) {
+        if (lane == 0) {
+            cf_out[row] = c;
+            if (theta) theta[row] = -1.0;
+        }
+        return;
+    }
+    double sum, d;
+    ddc_row_theta<G>(rp, ci, v, cf_in, row, lane, &sum, &d);
+    double th = d == 0.0 ? INFINITY : sum / fabs(d);
+    bool conv = d == 0.0 || isinf(th) || (th > alpha_diag && th != 0.0);
+    if (lane == 0) {
+        cf_out[row] = conv ? CF_C : CF_F;
+        if (theta) theta[row] = th;
+    }
+}
+
+void ddc(const CsrView &A, double alpha_diag, const int8_t *cf_in, int8_t *cf_out, double *theta, hipStream_t s) {
+    int g = lanes_for(A.nnz, A.nr);
+    dispatch_group(g, [&]<int W>() {
+        k_ddc<W><<<grid_for((int64_t)A.nr * W, 256), 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, alpha_diag, cf_in, cf_out,
+                                                                   theta);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------- DDC fraction mode ---
+__global__ void k_theta_max(int32_t n, const double *__restrict__ theta, unsigned long long *__restrict__ mx,
+                            int32_t *__restrict__ nF) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double t = theta[i];
+    if (t >= 0.0) atomicAdd(nF, 1);
+    if (t >= 0.0 && isfinite(t)) atomicMax(mx, (unsigned long long)__double_as_longlong(t));
+}
+
+// hist[q] counts F rows whose theta exceeds exactly the boundaries b_0..b_{q-1}
+// (b_k = theta_max * k / 1000), so #{theta > b_k} = sum_{q > k} hist[q].
+__global__ void k_theta_hist(int32_t n, const double *__restrict__ theta, double tmax,
+                             int32_t *__restrict__ hist) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double t = theta[i];
+    if (!(t >= 0.0)) return;
+    int q;
+    if (!isfinite(t)) {
+        q = 1001;
+    } else {
+        int lo = 0, hi = 1001;   // first k with b_k >= t, in [0, 1001]
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            double bk = tmax * (double)mid / 1000.0;
+            if (bk >= t) hi = mid;
+            else lo = mid + 1;
+        }
+        q = lo;
+    }
+    atomicAdd(&hist[q], 1);
+}
+
+double ddc_fraction_threshold(const CsrView &A, const int8_t *cf, double fraction, hipStream_t s) {
+    int32_t n = A.nr;
+    DBuf<int8_t> tmp((size_t)n, s);
+    DBuf<double> theta((size_t)n, s);
+    ddc(A, 0.0, cf, tmp.p, theta.p, s);
+    DBuf<unsigned long long> mx(1, s);
+    DBuf<int32_t> nF(1, s), hist(1002, s);
+    fill_zero(mx.p, 8, s);
+    fill_zero(nF.p, 4, s);
+    fill_zero(hist.p, 1002 * 4, s);
+    k_theta_max<<<grid_for(n, 256), 256, 0, s>>>(n, theta.p, mx.p, nF.p);
+    AIRG_LAUNCH_CHECK();
+    unsigned long long mbits = d2h_one(mx.p, s);
+    double tmax;
+    std::memcpy(&tmax, &mbits, 8);
+    int32_t nf = d2h_one(nF.p, s);
+    k_theta_hist<<<grid_for(n, 256), 256, 0, s>>>(n, theta.p, tmax, hist.p);
+    AIRG_LAUNCH_CHECK();
+    std::vector<int32_t> hh(1002);
+    d2h(hh.data(), hist.p, 1002, s);
+    int64_t target = (int64_t)std::ceil(fraction * (double)nf);
+    double best = tmax;
+    int64_t bestd = -1;
+    int64_t above = 0;   // #{theta > b_k} for k = 1000 down to 0
+    std::vector<int64_t> cnt(1001);
+    for (int q = 1001; q >= 1; --q) {
+        above += hh[q];
+        cnt[q - 1] = above;
+    }
+    for (int k = 0; k <= 1000; ++k) {
+        int64_t d = cnt[k] > target ? cnt[k] - target : target - cnt[k];
+        if (bestd < 0 || d <= bestd) {
+            bestd = d;
+            best = tmax * (double)k / 1000.0;
+        }
+    }
+    return best;
+}
+
+// ---------------------------------------------------------- full split ---
+std::pair<int32_t, int32_t> cf_split(const CsrView &A, const CfParams &p, int32_t level, int8_t *cf, hipStream_t s) {
+    int32_t n = A.nr;
+    StrengthGraph G = strength_graph(A, p.strong_threshold, s);
+    DBuf<uint32_t> h((size_t)n, s);
+    pmisr_hash(n, p.seed, level, h.p, s);
+    DBuf<int8_t> cf0((size_t)n, s);
+    pmisr(A, G, h.p, p.max_rounds, cf0.p, s);
+    double ad = p.ddc_threshold;
+    if (ad < 0.0) ad = ddc_fraction_threshold(A, cf0.p, p.ddc_fraction, s);
+    ddc(A, ad, cf0.p, cf, nullptr, s);
+    DBuf<int32_t> rank((size_t)n, s);
+    return cf_ranks(cf, n, rank.p, s);
+}
+
+}  // namespace airg

@@ -1,0 +1,41 @@
+// Two-pass CF splitting of the CF splitting section: PMISR (a Luby maximal
+// independent set on the symmetrised strong connections, F points taking the
+// smallest measure) followed by the DDC diagonal-dominance cleanup.
+#pragma once
+#include "common.hpp"
+
+namespace airg {
+
+struct StrengthGraph {
+    int32_t n = 0;
+    DBuf<uint8_t> strong;       // per nonzero of A: 1 if j in S_i
+    DBuf<int32_t> trp, tci;     // S^T as neighbour lists (order within a row unspecified)
+    DBuf<int32_t> deg;          // |S_i u S_i^T|
+};
+
+// Strength of connection, strength equation with absolute values:
+// j in S_i iff j != i, a_ij != 0 and |a_ij| >= alpha * max_{k != i} |a_ik|.
+StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s);
+
+// PMISR measure keys h_i (upper 32 bits of the counter generator, stream 0)
+// and rounds on the graph; writes cf (1 = F, 2 = C).  max_rounds = 0 runs
+// until no node is unassigned.  Returns the rounds run.
+void pmisr_hash(int32_t n, uint64_t seed, int32_t level, uint32_t *h, hipStream_t s);
+int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_rounds, int8_t *cf, hipStream_t s);
+
+// DDC: F rows with theta_i > alpha_diag (theta != 0), or a zero diagonal,
+// become C, all from the F set given in cf_in.  theta (nullable) receives
+// theta_i for F rows and -1 elsewhere.
+void ddc(const CsrView &A, double alpha_diag, const int8_t *cf_in, int8_t *cf_out, double *theta, hipStream_t s);
+// alpha_diag from the fraction rule (1000 uniform bins on [0, theta_max]).
+double ddc_fraction_threshold(const CsrView &A, const int8_t *cf, double fraction, hipStream_t s);
+
+struct CfParams {
+    double strong_threshold, ddc_threshold, ddc_fraction;
+    int max_rounds;
+    uint64_t seed;
+};
+// Full splitting; returns (nF, nC).
+std::pair<int32_t, int32_t> cf_split(const CsrView &A, const CfParams &p, int32_t level, int8_t *cf, hipStream_t s);
+
+}  // namespace airg

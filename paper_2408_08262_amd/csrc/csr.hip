@@ -1,0 +1,724 @@
+// Sparse building blocks on gfx950: validation, CSR SpMV/SpMM with G lanes
+// per row, CF block extraction, row drop filter, transpose, reductions.
+#include <cmath>
+#include <mutex>
+#include <tuple>
+
+#include "csr.hpp"
+#include "group.hpp"
+
+namespace airg {
+
+// ------------------------------------------------------------ validation --
+enum : uint32_t { BAD_COL = 1, NO_DIAG = 2, ZERO_DIAG = 4, NONFINITE = 8, BAD_RP = 16 };
+
+__global__ void k_validate(int32_t n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ v, int32_t *__restrict__ keep, uint32_t *__restrict__ flags) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t f = 0;
+    int32_t b = rp[i], e = rp[i + 1];
+    int32_t cnt = 0;
+    bool diag = false;
+    if (e < b || b < 0 || (int64_t)e > nnz) {
+        f |= BAD_RP;
+    } else {
+        for (int32_t k = b; k < e; ++k) {
+            int32_t j = ci[k];
+            double a = v[k];
+            if (j < 0 || j >= n || (k > b && j <= ci[k - 1])) f |= BAD_COL;
+            if (!isfinite(a)) f |= NONFINITE;
+            if (j == i) {
+                diag = true;
+                if (a == 0.0) f |= ZERO_DIAG;
+            }
+            cnt += (j == i || a != 0.0);
+        }
+        if (!diag) f |= NO_DIAG;
+    }
+    keep[i] = cnt;
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_canonical_fill(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                 const double *__restrict__ v, const int32_t *__restrict__ orp,
+                                 int32_t *__restrict__ oci, double *__restrict__ ov) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t w = orp[i];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        if (ci[k] == i || v[k] != 0.0) {
+            oci[w] = ci[k];
+            ov[w] = v[k];
+            ++w;
+        }
+    }
+}
+
+Csr canonical_copy(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, hipStream_t s) {
+    AIRG_REQUIRE(n > 0, ST_INVALID_ARG, "matrix must have at least one row");
+    AIRG_REQUIRE(nnz >= n && nnz < ((int64_t)1 << 31), ST_INVALID_ARG, "nnz out of range");
+    int32_t ends[2] = {-1, -1};
+    d2h(&ends[0], rp, 1, s);
+    d2h(&ends[1], rp + n, 1, s);
+    AIRG_REQUIRE(ends[0] == 0 && (int64_t)ends[1] == nnz, ST_BAD_CSR, "row pointers must start at 0 and end at nnz");
+    DBuf<int32_t> keep((size_t)n, s);
+    DBuf<uint32_t> flags(1, s);
+    fill_zero(flags.p, 4, s);
+    k_validate<<<grid_for(n, 256), 256, 0, s>>>(n, nnz, rp, ci, v, keep.p, flags.p);
+    AIRG_LAUNCH_CHECK();
+    uint32_t f = d2h_one(flags.p, s);
+    AIRG_REQUIRE(!(f & (BAD_RP | BAD_COL)), ST_BAD_CSR, "columns must be in range and strictly ascending per row");
+    AIRG_REQUIRE(!(f & NONFINITE), ST_NONFINITE, "matrix has a non-finite value");
+    AIRG_REQUIRE(!(f & NO_DIAG), ST_BAD_CSR, "every row must store its diagonal");
+    AIRG_REQUIRE(!(f & ZERO_DIAG), ST_ZERO_DIAG, "matrix has a zero diagonal entry");
+    Csr A;
+    A.nr = A.nc = n;
+    A.rp.alloc((size_t)n + 1, s);
+    int64_t kept = exclusive_scan(keep.p, A.rp.p, n, s);
+    A.nnz = kept;
+    A.ci.alloc((size_t)kept, s);
+    A.v.alloc((size_t)kept, s);
+    if (kept == nnz) {
+        d2d(A.ci.p, ci, (size_t)nnz, s);
+        d2d(A.v.p, v, (size_t)nnz, s);
+    } else {
+        k_canonical_fill<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, v, A.rp.p, A.ci.p, A.v.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    return A;
+}
+
+Csr copy_csr(const CsrView &A, hipStream_t s) {
+    Csr B;
+    B.alloc(A.nr, A.nc, A.nnz, s);
+    d2d(B.rp.p, A.rp, (size_t)A.nr + 1, s);
+    d2d(B.ci.p, A.ci, (size_t)A.nnz, s);
+    d2d(B.v.p, A.v, (size_t)A.nnz, s);
+    return B;
+}
+
+// ------------------------------------------------------------------ SpMV ---
+// G lanes per row; a wavefront covers 64/G consecutive rows so its loads of
+// columns and values stay within a contiguous stretch of the arrays.
+template <int G, class VT, class XT, int MODE, int TAG = 0>
+__global__ void __launch_bounds__(256) k_spmv(int32_t nr, const int32_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci, const VT *__restrict__ v,
+                                              const XT *__restrict__ x, XT *y, const XT *z) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= nr) return;  // uniform across the group
+    int32_t b = rp[row], e = rp[row + 1];
+    XT acc = 0;
+    for (int32_t k = b + lane; k < e; k += G) acc += (XT)v[k] * x[ci[k]];
+    acc = group_sum<G>(acc);
+    if (lane == 0) {
+        if (MODE == SPMV_SET) y[row] = acc;
+        else if (MODE == SPMV_ZMINUS) y[row] = z[row] - acc;
+        else y[row] = y[row] + acc;
+    }
+}
+
+template <int TAG, class VT, class XT>
+static void spmv_t(int32_t nr, int64_t nnz, const int32_t *rp, const int32_t *ci, const VT *v, const XT *x, XT *y,
+                   const XT *z, int mode, hipStream_t s, int lanes) {
+    if (nr == 0) return;
+    int g = lanes > 0 ? lanes : lanes_for(nnz, nr);
+    dispatch_group(g, [&]<int G>() {
+        unsigned grid = grid_for((int64_t)nr * G, 256);
+        if (mode == SPMV_SET) k_spmv<G, VT, XT, SPMV_SET, TAG><<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
+        else if (mode == SPMV_ZMINUS)
+            k_spmv<G, VT, XT, SPMV_ZMINUS, TAG><<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
+        else k_spmv<G, VT, XT, SPMV_ADD, TAG><<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
+void spmv(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s, int lanes) {
+    spmv_t<0, double, double>(A.nr, A.nnz, A.rp, A.ci, A.v, x, y, z, mode, s, lanes);
+}
+void spmv32(const CsrView &A, const float *x, float *y, const float *z, int mode, hipStream_t s, int lanes) {
+    AIRG_REQUIRE(A.vf != nullptr, ST_INVALID_ARG, "matrix has no single-precision copy");
+    spmv_t<0, float, float>(A.nr, A.nnz, A.rp, A.ci, A.vf, x, y, z, mode, s, lanes);
+}
+
+// ------------------------------------------------------ top-operator SpMV ---
+// The outer iterations' products with the finest operator run as their own
+// kernel instantiation (TAG 1) so that they can be timed and profiled apart
+// from the V-cycle's SpMVs; while timing is on, each plain product launch
+// (y = A x, the FGMRES Arnoldi product) is bracketed by events on its stream
+// and its algorithmic bytes are accounted.
+namespace {
+struct TopClock {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::tuple<hipEvent_t, hipEvent_t, double>> spans;
+} g_top;
+}  // namespace
+
+void top_timing(bool enable) {
+    std::lock_guard<std::mutex> lk(g_top.mu);
+    for (auto &t : g_top.spans) {
+        (void)hipEventDestroy(std::get<0>(t));
+        (void)hipEventDestroy(std::get<1>(t));
+    }
+    g_top.spans.clear();
+    g_top.on = enable;
+}
+
+void top_timing_read(int64_t *launches, double *bytes, double *seconds) {
+    std::lock_guard<std::mutex> lk(g_top.mu);
+    double b = 0.0, t = 0.0;
+    for (auto &sp : g_top.spans) {
+        AIRG_HIP(hipEventSynchronize(std::get<1>(sp)));
+        float ms = 0.f;
+        AIRG_HIP(hipEventElapsedTime(&ms, std::get<0>(sp), std::get<1>(sp)));
+        t += ms * 1e-3;
+        b += std::get<2>(sp);
+    }
+    *launches = (int64_t)g_top.spans.size();
+    *bytes = b;
+    *seconds = t;
+}
+
+void spmv_top(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_top.mu);
+        on = g_top.on;
+    }
+    on = on && mode == SPMV_SET;   // the Arnoldi product; residual launches are a different kernel
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (on) {
+        AIRG_HIP(hipEventCreate(&e0));
+        AIRG_HIP(hipEventCreate(&e1));
+        AIRG_HIP(hipEventRecord(e0, s));
+    }
+    spmv_t<1, double, double>(A.nr, A.nnz, A.rp, A.ci, A.v, x, y, z, mode, s, 0);
+    if (on) {
+        AIRG_HIP(hipEventRecord(e1, s));
+        double bytes = (double)A.nnz * 12.0 + 4.0 * (A.nr + 1) + 8.0 * (A.nc + A.nr + (mode != SPMV_SET ? A.nr : 0));
+        std::lock_guard<std::mutex> lk(g_top.mu);
+        g_top.spans.emplace_back(e0, e1, bytes);
+    }
+}
+
+// k right-hand sides, row-major: one group per row, each lane keeps K sums.
+template <int G, int K, class VT, class XT, int MODE>
+__global__ void __launch_bounds__(256) k_spmm(int32_t nr, const int32_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci, const VT *__restrict__ v,
+                                              const XT *__restrict__ x, XT *y, const XT *z) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= nr) return;
+    XT acc[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[c] = 0;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
+        XT a = (XT)v[k];
+        const XT *xr = x + (int64_t)ci[k] * K;
+#pragma unroll
+        for (int c = 0; c < K; ++c) acc[c] += a * xr[c];
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[c] = group_sum<G>(acc[c]);
+    if (lane == 0) {
+        XT *yr = y + (int64_t)row * K;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            if (MODE == SPMV_SET) yr[c] = acc[c];
+            else if (MODE == SPMV_ZMINUS) yr[c] = z[(int64_t)row * K + c] - acc[c];
+            else yr[c] = yr[c] + acc[c];
+        }
+    }
+}
+
+template <int K, class VT, class XT>
+static void spmm_k(const CsrView &A, const VT *v, const XT *x, XT *y, const XT *z, int mode, hipStream_t s) {
+    int g = lanes_for(A.nnz, A.nr);
+    dispatch_group(g, [&]<int G>() {
+        unsigned grid = grid_for((int64_t)A.nr * G, 256);
+        if (mode == SPMV_SET) k_spmm<G, K, VT, XT, SPMV_SET><<<grid, 256, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+        else if (mode == SPMV_ZMINUS)
+            k_spmm<G, K, VT, XT, SPMV_ZMINUS><<<grid, 256, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+        else k_spmm<G, K, VT, XT, SPMV_ADD><<<grid, 256, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
+template <class VT, class XT>
+static void spmm_t(const CsrView &A, const VT *v, int k, const XT *x, XT *y, const XT *z, int mode, hipStream_t s) {
+    if (A.nr == 0) return;
+    switch (k) {
+    case 1: spmm_k<1>(A, v, x, y, z, mode, s); break;
+    case 2: spmm_k<2>(A, v, x, y, z, mode, s); break;
+    case 3: spmm_k<3>(A, v, x, y, z, mode, s); break;
+    case 4: spmm_k<4>(A, v, x, y, z, mode, s); break;
+    case 8: spmm_k<8>(A, v, x, y, z, mode, s); break;
+    default: throw Error(ST_INVALID_ARG, "number of right-hand sides must be 1, 2, 3, 4 or 8");
+    }
+}
+
+void spmm(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s) {
+    spmm_t<double, double>(A, A.v, k, x, y, z, mode, s);
+}
+void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, int mode, hipStream_t s) {
+    AIRG_REQUIRE(A.vf != nullptr, ST_INVALID_ARG, "matrix has no single-precision copy");
+    spmm_t<float, float>(A, A.vf, k, x, y, z, mode, s);
+}
+
+// ------------------------------------------------------------- CF ranks ---
+__global__ void k_cf_flags(const int8_t *__restrict__ cf, int32_t n, int32_t *__restrict__ fF,
+                           int32_t *__restrict__ fC) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    fF[i] = cf[i] == CF_F;
+    fC[i] = cf[i] == CF_C;
+}
+__global__ void k_cf_rank(const int8_t *__restrict__ cf, int32_t n, const int32_t *__restrict__ sF,
+                          const int32_t *__restrict__ sC, int32_t *__restrict__ rank) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    rank[i] = cf[i] == CF_F ? sF[i] : sC[i];
+}
+
+std::pair<int32_t, int32_t> cf_ranks(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s) {
+    DBuf<int32_t> fF((size_t)n, s), fC((size_t)n, s), sF((size_t)n + 1, s), sC((size_t)n + 1, s);
+    k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p);
+    AIRG_LAUNCH_CHECK();
+    int64_t nF = exclusive_scan(fF.p, sF.p, n, s);
+    int64_t nC = exclusive_scan(fC.p, sC.p, n, s);
+    k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, rank);
+    AIRG_LAUNCH_CHECK();
+    return {(int32_t)nF, (int32_t)nC};
+}
+
+__global__ void k_cf_lists(const int8_t *__restrict__ cf, const int32_t *__restrict__ rank, int32_t n,
+                           int32_t *__restrict__ fidx, int32_t *__restrict__ cidx) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == CF_F) {
+        if (fidx) fidx[rank[i]] = i;
+    } else if (cidx) {
+        cidx[rank[i]] = i;
+    }
+}
+
+void cf_index_lists(const int8_t *cf, const int32_t *rank, int32_t n, int32_t *fidx, int32_t *cidx, hipStream_t s) {
+    k_cf_lists<<<grid_for(n, 256), 256, 0, s>>>(cf, rank, n, fidx, cidx);
+    AIRG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------ extraction ---
+template <int G>
+__global__ void __launch_bounds__(256) k_extract_count(int32_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, const int8_t *__restrict__ cf,
+                                                       const int32_t *__restrict__ rank, int8_t rowsel,
+                                                       int8_t colsel, int32_t *__restrict__ cnt) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n || cf[row] != rowsel) return;
+    int32_t c = 0;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) c += cf[ci[k]] == colsel;
+    c = group_sum<G>(c);
+    if (lane == 0) cnt[rank[row]] = c;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_extract_fill(int32_t n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                      const int8_t *__restrict__ cf,
+                                                      const int32_t *__restrict__ rank, int8_t rowsel, int8_t colsel,
+                                                      const int32_t *__restrict__ orp, int32_t *__restrict__ oci,
+                                                      double *__restrict__ ov) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n || cf[row] != rowsel) return;
+    int32_t w = orp[rank[row]];
+    int32_t e = rp[row + 1];
+    for (int32_t base = rp[row]; base < e; base += G) {
+        int32_t k = base + lane;
+        bool keep = false;
+        int32_t j = 0;
+        if (k < e) {
+            j = ci[k];
+            keep = cf[j] == colsel;
+        }
+        int tot;
+        int pre = group_prefix<G>(keep, &tot);
+        if (keep) {
+            oci[w + pre] = rank[j];
+            ov[w + pre] = v[k];
+        }
+        w += tot;
+    }
+}
+
+Csr extract_block(const CsrView &A, const int8_t *cf, const int32_t *rank, int8_t rowsel, int8_t colsel,
+                  int32_t nrows_out, int32_t ncols_out, hipStream_t s) {
+    Csr B;
+    B.nr = nrows_out;
+    B.nc = ncols_out;
+    B.rp.alloc((size_t)nrows_out + 1, s);
+    DBuf<int32_t> cnt((size_t)nrows_out + 1, s);
+    int g = lanes_for(A.nnz, A.nr);
+    dispatch_group(g, [&]<int G>() {
+        k_extract_count<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(A.nr, A.rp, A.ci, cf, rank, rowsel,
+                                                                            colsel, cnt.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    B.nnz = exclusive_scan(cnt.p, B.rp.p, nrows_out, s);
+    B.ci.alloc((size_t)B.nnz, s);
+    B.v.alloc((size_t)B.nnz, s);
+    dispatch_group(g, [&]<int G>() {
+        k_extract_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(
+            A.nr, A.rp, A.ci, A.v, cf, rank, rowsel, colsel, B.rp.p, B.ci.p, B.v.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    return B;
+}
+
+// ------------------------------------------------------------------ drop ---
+template <int G>
+__device__ inline double row_absmax(const int32_t *rp, const double *v, int32_t row, int lane) {
+    double m = 0.0;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) m = fmax(m, fabs(v[k]));
+    return group_max<G>(m);
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_drop_count(int32_t n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                    double tau, int keep_diag, int32_t *__restrict__ cnt) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    double thr = tau * row_absmax<G>(rp, v, row, lane);
+    int32_t c = 0;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G)
+        c += (keep_diag && ci[k] == row) || fabs(v[k]) >= thr;
+    c = group_sum<G>(c);
+    if (lane == 0) cnt[row] = c;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_drop_fill(int32_t n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                   double tau, int keep_diag, double sign,
+                                                   const int32_t *__restrict__ orp, int32_t *__restrict__ oci,
+                                                   double *__restrict__ ov) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    double thr = tau * row_absmax<G>(rp, v, row, lane);
+    int32_t w = orp[row];
+    int32_t e = rp[row + 1];
+    for (int32_t base = rp[row]; base < e; base += G) {
+        int32_t k = base + lane;
+        bool keep = false;
+        if (k < e) keep = (keep_diag && ci[k] == row) || fabs(v[k]) >= thr;
+        int tot;
+        int pre = group_prefix<G>(keep, &tot);
+        if (keep) {
+            oci[w + pre] = ci[k];
+            ov[w + pre] = sign * v[k];
+        }
+        w += tot;
+    }
+}
+
+Csr drop_rows(const CsrView &A, double tau, bool keep_diag, bool negate, hipStream_t s) {
+    Csr B;
+    B.nr = A.nr;
+    B.nc = A.nc;
+    B.rp.alloc((size_t)A.nr + 1, s);
+    DBuf<int32_t> cnt((size_t)A.nr + 1, s);
+    int g = lanes_for(A.nnz, A.nr);
+    dispatch_group(g, [&]<int G>() {
+        k_drop_count<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, tau, keep_diag,
+                                                                         cnt.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    B.nnz = exclusive_scan(cnt.p, B.rp.p, A.nr, s);
+    B.ci.alloc((size_t)B.nnz, s);
+    B.v.alloc((size_t)B.nnz, s);
+    dispatch_group(g, [&]<int G>() {
+        k_drop_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(
+            A.nr, A.rp, A.ci, A.v, tau, keep_diag, negate ? -1.0 : 1.0, B.rp.p, B.ci.p, B.v.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    return B;
+}
+
+// ------------------------------------------------------------- transpose ---
+__global__ void k_col_count(int64_t nnz, const int32_t *__restrict__ ci, int32_t *__restrict__ cnt) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) atomicAdd(&cnt[ci[k]], 1);
+}
+__global__ void k_transpose_fill(int32_t nr, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                 const double *__restrict__ v, const int32_t *__restrict__ trp,
+                                 int32_t *__restrict__ cursor, int32_t *__restrict__ tci, double *__restrict__ tv) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        int32_t j = ci[k];
+        int32_t p = trp[j] + atomicAdd(&cursor[j], 1);
+        tci[p] = i;
+        tv[p] = v[k];
+    }
+}
+// Insertion sort of each row by column: makes the scatter order irrelevant.
+__global__ void k_row_sort(int32_t nr, const int32_t *__restrict__ rp, int32_t *__restrict__ ci,
+                           double *__restrict__ v) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int32_t b = rp[i], e = rp[i + 1];
+    for (int32_t k = b + 1; k < e; ++k) {
+        int32_t c = ci[k];
+        double x = v ? v[k] : 0.0;
+        int32_t q = k - 1;
+        while (q >= b && ci[q] > c) {
+            ci[q + 1] = ci[q];
+            if (v) v[q + 1] = v[q];
+            --q;
+        }
+        ci[q + 1] = c;
+        if (v) v[q + 1] = x;
+    }
+}
+
+Csr transpose(const CsrView &A, hipStream_t s) {
+    Csr T;
+    T.alloc(A.nc, A.nr, A.nnz, s);
+    DBuf<int32_t> cnt((size_t)A.nc + 1, s), cursor((size_t)A.nc, s);
+    fill_zero(cnt.p, ((size_t)A.nc + 1) * 4, s);
+    fill_zero(cursor.p, (size_t)A.nc * 4, s);
+    k_col_count<<<grid_for(A.nnz, 256), 256, 0, s>>>(A.nnz, A.ci, cnt.p);
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(cnt.p, T.rp.p, A.nc, s, false);
+    k_transpose_fill<<<grid_for(A.nr, 256), 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, T.rp.p, cursor.p, T.ci.p, T.v.p);
+    AIRG_LAUNCH_CHECK();
+    k_row_sort<<<grid_for(A.nc, 256), 256, 0, s>>>(A.nc, T.rp.p, T.ci.p, T.v.p);
+    AIRG_LAUNCH_CHECK();
+    return T;
+}
+
+// ------------------------------------------------------------ elementwise ---
+__global__ void k_d2f(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+__global__ void k_f2d(const float *__restrict__ x, double *__restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (double)x[i];
+}
+void cast_d2f(const double *x, float *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_d2f<<<grid_for(n, 256), 256, 0, s>>>(x, y, n);
+    AIRG_LAUNCH_CHECK();
+}
+void cast_f2d(const float *x, double *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_f2d<<<grid_for(n, 256), 256, 0, s>>>(x, y, n);
+    AIRG_LAUNCH_CHECK();
+}
+void make_f32(Csr &A, hipStream_t s) {
+    A.vf.alloc((size_t)A.nnz, s);
+    cast_d2f(A.v.p, A.vf.p, A.nnz, s);
+}
+
+__global__ void k_axpy(double a, const double *__restrict__ x, double *__restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+__global__ void k_scal_copy(double a, const double *__restrict__ x, double *__restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+void axpy(double a, const double *x, double *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_axpy<<<grid_for(n, 256), 256, 0, s>>>(a, x, y, n);
+    AIRG_LAUNCH_CHECK();
+}
+void scal_copy(double a, const double *x, double *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_scal_copy<<<grid_for(n, 256), 256, 0, s>>>(a, x, y, n);
+    AIRG_LAUNCH_CHECK();
+}
+
+__global__ void k_gather(const double *__restrict__ x, const int32_t *__restrict__ idx, double *__restrict__ y,
+                         int64_t n, int k, int64_t ldx, int64_t ldy) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t src = idx[i];
+    for (int c = 0; c < k; ++c) y[i * ldy + c] = x[src * ldx + c];
+}
+__global__ void k_scatter(const double *__restrict__ x, const int32_t *__restrict__ idx, double *__restrict__ y,
+                          int64_t n, int k, int64_t ldx, int64_t ldy) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t dst = idx[i];
+    for (int c = 0; c < k; ++c) y[dst * ldy + c] = x[i * ldx + c];
+}
+void gather(const double *x, const int32_t *idx, double *y, int64_t n, hipStream_t s) {
+    gather_k(x, idx, y, n, 1, 1, 1, s);
+}
+void scatter(const double *x, const int32_t *idx, double *y, int64_t n, hipStream_t s) {
+    scatter_k(x, idx, y, n, 1, 1, 1, s);
+}
+void gather_k(const double *x, const int32_t *idx, double *y, int64_t n, int k, int64_t ldx, int64_t ldy,
+              hipStream_t s) {
+    if (n <= 0) return;
+    k_gather<<<grid_for(n, 256), 256, 0, s>>>(x, idx, y, n, k, ldx, ldy);
+    AIRG_LAUNCH_CHECK();
+}
+void scatter_k(const double *x, const int32_t *idx, double *y, int64_t n, int k, int64_t ldx, int64_t ldy,
+               hipStream_t s) {
+    if (n <= 0) return;
+    k_scatter<<<grid_for(n, 256), 256, 0, s>>>(x, idx, y, n, k, ldx, ldy);
+    AIRG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------ reductions ---
+// Fixed grid (depends only on n) and fixed in-block tree: bitwise
+// reproducible for a given n.
+constexpr int kRedThreads = 256;
+constexpr int kRedMaxBlocks = 1024;
+
+__device__ inline double block_sum(double v) {
+    __shared__ double part[kRedThreads / kWave];
+    v = group_sum<kWave>(v);
+    int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kRedThreads / kWave; ++w) t += part[w];
+    __syncthreads();
+    return t;
+}
+
+static int red_blocks(int64_t n) {
+    int64_t b = (n + kRedThreads * 4 - 1) / (kRedThreads * 4);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, kRedMaxBlocks));
+}
+
+// partial[j * nb + b] = block b's share of dot(V_j, w) for j < nvec.
+__global__ void __launch_bounds__(kRedThreads) k_multi_dot(const double *__restrict__ V, int64_t ldv, int nvec,
+                                                           const double *__restrict__ w, int64_t n,
+                                                           double *__restrict__ partial) {
+    int nb = gridDim.x;
+    for (int j = 0; j < nvec; ++j) {
+        const double *vj = V + (int64_t)j * ldv;
+        double s = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)nb * kRedThreads)
+            s += vj[i] * w[i];
+        s = block_sum(s);
+        if (threadIdx.x == 0) partial[(int64_t)j * nb + blockIdx.x] = s;
+    }
+}
+__global__ void k_finish_dots(const double *__restrict__ partial, int nb, int nvec, double *__restrict__ out) {
+    int j = blockIdx.x;
+    if (j >= nvec) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) s += partial[(int64_t)j * nb + b];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[j] = s;
+}
+
+static void multi_dot_dev(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *d_out,
+                          hipStream_t s) {
+    int nb = red_blocks(n);
+    DBuf<double> part((size_t)nb * nvec, s);
+    k_multi_dot<<<nb, kRedThreads, 0, s>>>(V, ldv, nvec, w, n, part.p);
+    AIRG_LAUNCH_CHECK();
+    k_finish_dots<<<nvec, kRedThreads, 0, s>>>(part.p, nb, nvec, d_out);
+    AIRG_LAUNCH_CHECK();
+}
+
+void multi_dot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *h_out, hipStream_t s) {
+    DBuf<double> out((size_t)nvec, s);
+    multi_dot_dev(V, ldv, nvec, w, n, out.p, s);
+    d2h(h_out, out.p, (size_t)nvec, s);
+}
+
+double dot(const double *x, const double *y, int64_t n, hipStream_t s) {
+    double r;
+    multi_dot(x, n, 1, y, n, &r, s);
+    return r;
+}
+
+double nrm2(const double *x, int64_t n, hipStream_t s) { return std::sqrt(dot(x, x, n, s)); }
+
+__global__ void k_gemv(const double *__restrict__ V, int64_t ldv, int nvec, const double *__restrict__ h,
+                       double *__restrict__ w, int64_t n, double sign) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < nvec; ++j) s += V[(int64_t)j * ldv + i] * h[j];
+    w[i] += sign * s;
+}
+void gemv_sub(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, hipStream_t s) {
+    if (n <= 0 || nvec <= 0) return;
+    k_gemv<<<grid_for(n, 256), 256, 0, s>>>(V, ldv, nvec, h_dev, w, n, -1.0);
+    AIRG_LAUNCH_CHECK();
+}
+void gemv_add(const double *V, int64_t ldv, int nvec, const double *h_dev, double *x, int64_t n, hipStream_t s) {
+    if (n <= 0 || nvec <= 0) return;
+    k_gemv<<<grid_for(n, 256), 256, 0, s>>>(V, ldv, nvec, h_dev, x, n, 1.0);
+    AIRG_LAUNCH_CHECK();
+}
+
+// -------------------------------------------------------------- binning ---
+constexpr int kMaxBins = 16;
+__global__ void k_bin_count(const int8_t *__restrict__ bin, int32_t n, int nbins, int32_t *__restrict__ cnt) {
+    __shared__ int32_t loc[kMaxBins];
+    if (threadIdx.x < kMaxBins) loc[threadIdx.x] = 0;
+    __syncthreads();
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        int b = bin[i];
+        if (b >= 0 && b < nbins) atomicAdd(&loc[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < nbins && loc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], loc[threadIdx.x]);
+}
+__global__ void k_bin_scatter(const int8_t *__restrict__ bin, int32_t n, int nbins, const int32_t *__restrict__ off,
+                              int32_t *__restrict__ cursor, int32_t *__restrict__ rows) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = bin[i];
+    if (b < 0 || b >= nbins) return;
+    rows[off[b] + atomicAdd(&cursor[b], 1)] = i;
+}
+
+Bins bin_rows(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
+    AIRG_REQUIRE(nbins <= kMaxBins, ST_INVALID_ARG, "too many bins");
+    Bins B;
+    DBuf<int32_t> cnt(kMaxBins, s), cursor(kMaxBins, s), off(kMaxBins + 1, s);
+    fill_zero(cnt.p, kMaxBins * 4, s);
+    fill_zero(cursor.p, kMaxBins * 4, s);
+    k_bin_count<<<grid_for(n, 256), 256, 0, s>>>(bin, n, nbins, cnt.p);
+    AIRG_LAUNCH_CHECK();
+    std::vector<int32_t> hc(kMaxBins);
+    d2h(hc.data(), cnt.p, kMaxBins, s);
+    B.off.assign(nbins + 1, 0);
+    std::vector<int32_t> ho(kMaxBins + 1, 0);
+    for (int b = 0; b < nbins; ++b) {
+        B.off[b + 1] = B.off[b] + hc[b];
+        ho[b + 1] = (int32_t)B.off[b + 1];
+    }
+    h2d(off.p, ho.data(), kMaxBins + 1, s);
+    B.rows.alloc((size_t)std::max<int64_t>(B.off[nbins], 1), s);
+    k_bin_scatter<<<grid_for(n, 256), 256, 0, s>>>(bin, n, nbins, off.p, cursor.p, B.rows.p);
+    AIRG_LAUNCH_CHECK();
+    return B;
+}
+
+}  // namespace airg

@@ -1,0 +1,87 @@
+// Sparse-matrix building blocks on the device: validation, SpMV, block
+// extraction under a CF splitting, row drop filter, transpose, casts.
+#pragma once
+#include "common.hpp"
+
+namespace airg {
+
+// Checks the input CSR (columns in range, strictly ascending, diagonal present
+// and nonzero, values finite) and returns a canonical copy with exact-zero
+// off-diagonal entries removed.  Throws Error with ST_BAD_CSR / ST_ZERO_DIAG /
+// ST_NONFINITE.
+Csr canonical_copy(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v, hipStream_t s);
+
+// Copy of a view into an owned matrix.
+Csr copy_csr(const CsrView &A, hipStream_t s);
+
+// y = A x (mode 0), y = z - A x (mode 1), y = y + A x (mode 2).
+enum SpmvMode { SPMV_SET = 0, SPMV_ZMINUS = 1, SPMV_ADD = 2 };
+void spmv(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s, int lanes = 0);
+void spmv32(const CsrView &A, const float *x, float *y, const float *z, int mode, hipStream_t s, int lanes = 0);
+// The outer iterations' products with the finest operator (a separate kernel
+// instantiation), optionally timed with events; see top_timing.
+void spmv_top(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s);
+void top_timing(bool enable);
+void top_timing_read(int64_t *launches, double *bytes, double *seconds);
+// Same with k right-hand sides stored row-major (n x k).
+void spmm(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s);
+void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, int mode, hipStream_t s);
+
+// rank[i] = position of i among the points carrying its own marker
+// (F rank for F points, C rank for C points); returns (nF, nC).
+std::pair<int32_t, int32_t> cf_ranks(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s);
+// fidx[f] = original index of the f-th F point (and likewise cidx for C).
+void cf_index_lists(const int8_t *cf, const int32_t *rank, int32_t n, int32_t *fidx, int32_t *cidx, hipStream_t s);
+
+// Block of A with rows marked rowsel and columns marked colsel, ranked by
+// original index, entry order preserved.
+Csr extract_block(const CsrView &A, const int8_t *cf, const int32_t *rank, int8_t rowsel, int8_t colsel,
+                  int32_t nrows_out, int32_t ncols_out, hipStream_t s);
+
+// Keep entries with |x| >= tau * max_j |x_rj| (and the diagonal when
+// keep_diag); negate scales every kept value by -1 when set.
+Csr drop_rows(const CsrView &A, double tau, bool keep_diag, bool negate, hipStream_t s);
+
+// A^T with rows sorted (deterministic).
+Csr transpose(const CsrView &A, hipStream_t s);
+
+// v -> vf (single precision copy).
+void make_f32(Csr &A, hipStream_t s);
+
+// Dot products / norms with a fixed reduction order (deterministic).
+double dot(const double *x, const double *y, int64_t n, hipStream_t s);
+void multi_dot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *h_out, hipStream_t s);
+double nrm2(const double *x, int64_t n, hipStream_t s);
+
+// Elementwise helpers.
+void axpy(double a, const double *x, double *y, int64_t n, hipStream_t s);            // y += a x
+void scal_copy(double a, const double *x, double *y, int64_t n, hipStream_t s);       // y = a x
+void gemv_sub(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, hipStream_t s);
+void gemv_add(const double *V, int64_t ldv, int nvec, const double *h_dev, double *x, int64_t n, hipStream_t s);
+void cast_d2f(const double *x, float *y, int64_t n, hipStream_t s);
+void cast_f2d(const float *x, double *y, int64_t n, hipStream_t s);
+void gather(const double *x, const int32_t *idx, double *y, int64_t n, hipStream_t s);   // y[i] = x[idx[i]]
+void scatter(const double *x, const int32_t *idx, double *y, int64_t n, hipStream_t s);  // y[idx[i]] = x[i]
+void gather_k(const double *x, const int32_t *idx, double *y, int64_t n, int k, int64_t ldx, int64_t ldy,
+              hipStream_t s);
+void scatter_k(const double *x, const int32_t *idx, double *y, int64_t n, int k, int64_t ldx, int64_t ldy,
+               hipStream_t s);
+
+// Groups row indices by a small bin id (0..nbins-1): rows[off[b] .. off[b+1])
+// hold the rows of bin b (order inside a bin unspecified).  Rows with a bin
+// id outside the range are skipped.
+struct Bins {
+    DBuf<int32_t> rows;
+    std::vector<int64_t> off;
+    int64_t count(int b) const { return off[b + 1] - off[b]; }
+    const int32_t *list(int b) const { return rows.p + off[b]; }
+};
+Bins bin_rows(const int8_t *bin, int32_t n, int nbins, hipStream_t s);
+
+// Wavefront-scope ordering of LDS traffic among the lanes of one wave.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+}  // namespace airg

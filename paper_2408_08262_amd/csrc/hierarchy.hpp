@@ -1,0 +1,80 @@
+// AIRG hierarchy: setup driver (level loop of the AIRG subsection) and the
+// permuted solve-phase operators, V-cycle and outer iterations.
+#pragma once
+#include <memory>
+
+#include "airg.h"
+#include "common.hpp"
+#include "poly.hpp"
+
+namespace airg {
+
+struct Level {
+    int32_t n = 0, nF = 0, nC = 0;
+    bool coarsest = false;
+    // setup objects, natural order (F/C ranks by ascending index)
+    Csr A;                        // operator of this level
+    DBuf<int8_t> cf;
+    DBuf<int32_t> rank, fidx, cidx;
+    Csr Aff, Afc, Ainv, Z, W;
+    PolyInfo poly;
+    // solve objects, level order = F points first (by rank), then C points
+    DBuf<int32_t> perm;           // natural index -> position in level order
+    DBuf<int32_t> iperm;          // position -> natural index
+    Csr AF;                       // [A_ff A_fc]: F rows, all columns in level order
+    Csr Rp;                       // [Z I]: rows in the next level's order
+    Csr Pp;                       // [W; I]: rows in level order, columns in the next level's order
+    // V-cycle work vectors
+    DBuf<double> g64, e64, t64;
+    DBuf<float> g32, e32, t32;
+};
+
+struct Hier {
+    airg_opts opt{};
+    uint64_t seed = 0;
+    hipStream_t s = nullptr;
+    std::vector<std::unique_ptr<Level>> lv;
+    Csr A0p;                      // top operator in level-0 order (residuals)
+    bool top_permuted = false;
+    double setup_seconds = 0.0;
+    double phase[AIRG_PHASE_COUNT] = {};
+    DBuf<double> x, r, e, bp;     // top-level work vectors
+    DBuf<float> r32, e32;
+
+    int nlev() const { return (int)lv.size(); }
+    Level &L(int l) { return *lv[l]; }
+
+    template <class T>
+    void vcycle(int l, const T *g, T *e);
+    void precondition(const double *r, double *e, int precision);
+};
+
+// Builds the full hierarchy of the canonical operator A0 (takes ownership).
+std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t seed, hipStream_t s);
+
+// Single-level build for replay/inspection: CF split, A_ff, polynomial
+// (alpha_in nullable), Ainv, Z, W and the coarse operator.
+struct LevelOut {
+    DBuf<int8_t> cf;
+    int32_t nF = 0, nC = 0;
+    PolyInfo poly;
+    Csr Ainv, Z, W, Ac;
+};
+LevelOut build_one_level(const CsrView &A, const airg_opts &o, uint64_t seed, int level, const double *alpha_in,
+                         hipStream_t s);
+
+// Outer iterations on one right-hand side (contiguous vectors, natural order).
+struct SolveResult {
+    int iterations = 0;
+    double rel_residual = 0.0;
+    bool converged = false;
+};
+SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, int maxit);
+SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit);
+
+// Algorithmic bytes of one V-cycle with vbytes-byte values.
+int64_t vcycle_bytes(const Hier &H, int vbytes);
+void complexities(const Hier &H, double *grid, double *op, double *storage);
+int64_t spmv_bytes(int64_t rows, int64_t cols, int64_t nnz, int vbytes, bool reads_y);
+
+}  // namespace airg

@@ -1,0 +1,39 @@
+// Stationary GMRES polynomial of the AIRG subsection: random rhs by
+// Box-Muller, power basis, tall-skinny Householder QR, least squares for the
+// coefficients, and the assembled fixed-sparsity approximate inverse.
+#pragma once
+#include "common.hpp"
+
+namespace airg {
+
+constexpr int kMaxPolyCols = 16;   // m + 1 <= 16
+
+struct PolyInfo {
+    int m = 0;                     // coefficients requested
+    int used = 0;                  // coefficients kept after the breakdown test
+    double alpha[kMaxPolyCols] = {};
+    double R[kMaxPolyCols * kMaxPolyCols] = {};   // scaled R factor, row-major (m+1)^2
+    double colnorm[kMaxPolyCols] = {};
+};
+
+// b_k = sqrt(-2 ln u1) cos(2 pi u2), u1 in (0,1] from stream 1, u2 in [0,1)
+// from stream 2 of the counter generator.
+void gauss_rhs(int64_t n, uint64_t seed, int32_t level, double *b, hipStream_t s);
+
+// R factor (row-major, cols x cols) of the column-scaled K (n x cols,
+// column-major) by a tall-skinny Householder QR tree, and the column norms.
+void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s);
+
+// alpha = argmin || beta e1 - R~ y || from the scaled R and the column norms,
+// with the Krylov breakdown rule; returns the number of coefficients kept.
+int poly_coeffs_from_r(const double *R, const double *colnorm, int m, double *alpha);
+
+// Steps 3-6 of the setup on a square A (alpha has m entries).
+PolyInfo gmres_poly(const CsrView &A, uint64_t seed, int32_t level, int m, hipStream_t s);
+
+// Assembled fixed-sparsity polynomial on the pattern of A (which must store
+// its diagonal): row i of A~^k is e_i^T M_i^k restricted to J_i, with
+// M_i = A(J_i, J_i).  out_v has A.nnz entries (pattern of A).
+void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, double *out_v, hipStream_t s);
+
+}  // namespace airg

@@ -1,0 +1,241 @@
+// Runtime pieces of the AIRG library: the caching device allocator, fills,
+// and the device-wide exclusive scan used to build every CSR row pointer.
+#include <mutex>
+#include <unordered_map>
+
+#include "common.hpp"
+
+namespace airg {
+
+// ------------------------------------------------------------- allocator --
+namespace {
+struct Block {
+    size_t bytes;
+    hipStream_t s;
+};
+struct Key {
+    uintptr_t s;
+    size_t bytes;
+    bool operator==(const Key &o) const { return s == o.s && bytes == o.bytes; }
+};
+struct KeyHash {
+    size_t operator()(const Key &k) const { return std::hash<uintptr_t>()(k.s) * 31u ^ std::hash<size_t>()(k.bytes); }
+};
+std::mutex g_mu;
+std::unordered_map<Key, std::vector<void *>, KeyHash> g_free;
+std::unordered_map<void *, Block> g_live;
+size_t g_in_use = 0, g_cached = 0;
+int64_t g_cap = 0;
+
+size_t size_class(size_t b) {
+    if (b <= 256) return 256;
+    size_t p = 256;
+    while (p < b && p < ((size_t)1 << 20)) p <<= 1;
+    if (p >= b) return p;
+    // above 1 MiB: multiples of 1/8 of the power of two below
+    size_t q = (size_t)1 << 20;
+    while ((q << 1) <= b) q <<= 1;
+    size_t step = q >> 3;
+    return (b + step - 1) / step * step;
+}
+
+void trim_locked() {
+    for (auto &kv : g_free)
+        for (void *p : kv.second) (void)hipFree(p);
+    g_free.clear();
+    g_cached = 0;
+}
+}  // namespace
+
+void set_device_cap(int64_t bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cap = bytes;
+}
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+    size_t b = size_class(bytes);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Key k{(uintptr_t)s, b};
+    auto it = g_free.find(k);
+    void *p = nullptr;
+    if (g_cap > 0 && (int64_t)(g_in_use + b) > g_cap)
+        throw Error(ST_OOM, "device byte cap exceeded (" + std::to_string(g_in_use + b) + " > " +
+                                std::to_string(g_cap) + ")");
+    if (it != g_free.end() && !it->second.empty()) {
+        p = it->second.back();
+        it->second.pop_back();
+        g_cached -= b;
+    } else {
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim_locked();
+            e = hipMalloc(&p, b);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(ST_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+            }
+        }
+    }
+    g_live[p] = Block{b, s};
+    g_in_use += b;
+    return p;
+}
+
+void dev_release(void *p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    size_t b = it->second.bytes;
+    g_live.erase(it);
+    g_in_use -= b;
+    g_free[Key{(uintptr_t)s, b}].push_back(p);
+    g_cached += b;
+}
+
+void dev_trim() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    (void)hipDeviceSynchronize();
+    trim_locked();
+}
+
+size_t dev_bytes_in_use() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_in_use;
+}
+
+// ------------------------------------------------------------------ fills --
+__global__ void k_fill_u32(uint32_t *d, uint32_t v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) d[i] = v;
+}
+__global__ void k_fill_u8(uint8_t *d, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) d[i] = 0;
+}
+
+// Zero fill by a kernel (rather than a memset node) so that the same code is
+// safe inside captured graphs.
+void fill_zero(void *d, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    if (bytes % 4 == 0 && ((uintptr_t)d % 4) == 0) {
+        size_t n = bytes / 4;
+        unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+        k_fill_u32<<<g, 256, 0, s>>>((uint32_t *)d, 0u, n);
+    } else {
+        unsigned g = (unsigned)std::min<size_t>((bytes + 255) / 256, 8192);
+        k_fill_u8<<<g, 256, 0, s>>>((uint8_t *)d, bytes);
+    }
+    AIRG_LAUNCH_CHECK();
+}
+
+void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s) {
+    if (!count) return;
+    unsigned g = (unsigned)std::min<size_t>((count + 255) / 256, 8192);
+    k_fill_u32<<<g, 256, 0, s>>>((uint32_t *)d, (uint32_t)value, count);
+    AIRG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ scan ---
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Exclusive scan of one value per thread across the block; returns the
+// block total through *total.
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t *total) {
+    __shared__ int64_t wsum[kScanThreads / kWave];
+    int lane = threadIdx.x & (kWave - 1);
+    int wid = threadIdx.x / kWave;
+    int64_t x = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int64_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[wid] = x;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+__global__ void k_scan_reduce(const int32_t *__restrict__ in, int64_t n, int64_t *__restrict__ bsum) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int64_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of the nb block sums in place, total at bsum[nb].
+__global__ void k_scan_bsums(int64_t *bsum, int64_t nb) {
+    int64_t per = (nb + kScanThreads - 1) / kScanThreads;
+    int64_t lo = (int64_t)threadIdx.x * per;
+    int64_t hi = lo + per < nb ? lo + per : nb;
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += bsum[i];
+    int64_t tot;
+    int64_t off = block_exclusive_scan(s, &tot);
+    for (int64_t i = lo; i < hi; ++i) {
+        int64_t v = bsum[i];
+        bsum[i] = off;
+        off += v;
+    }
+    if (threadIdx.x == 0) bsum[nb] = tot;
+}
+
+__global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
+                             const int64_t *__restrict__ bsum, int64_t nb) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int64_t tot;
+    int64_t off = block_exclusive_scan(s, &tot) + bsum[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = (int32_t)off;
+        off += v[k];
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = (int32_t)bsum[nb];
+}
+
+// Blocked layout: thread t of block b owns items [b*tile + t*items, +items).
+// The reduce kernel above strides differently, but only block totals are
+// taken from it, and those do not depend on the layout inside the tile.
+int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, bool want_total) {
+    if (n == 0) {
+        fill_zero(out, sizeof(int32_t), s);
+        return 0;
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    DBuf<int64_t> bsum((size_t)nb + 1, s);
+    k_scan_reduce<<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, n, bsum.p);
+    AIRG_LAUNCH_CHECK();
+    k_scan_bsums<<<1, kScanThreads, 0, s>>>(bsum.p, nb);
+    AIRG_LAUNCH_CHECK();
+    k_scan_final<<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, out, n, bsum.p, nb);
+    AIRG_LAUNCH_CHECK();
+    if (!want_total) return -1;
+    int64_t tot = d2h_one(bsum.p + nb, s);
+    AIRG_REQUIRE(tot < ((int64_t)1 << 31), ST_LIMIT, "prefix sum exceeds the int32 index range");
+    return tot;
+}
+
+}  // namespace airg

@@ -1,0 +1,466 @@
+// AIRG setup driver: the per-level recipe of the AIRG subsection on the
+// device, termination/truncation, and the permuted solve-phase operators.
+#include <chrono>
+#include <cmath>
+
+#include "cfsplit.hpp"
+#include "csr.hpp"
+#include "group.hpp"
+#include "hierarchy.hpp"
+#include "spgemm.hpp"
+#include "transfer.hpp"
+
+namespace airg {
+
+namespace {
+
+// Per-phase device time from events recorded around each phase.
+struct PhaseTimer {
+    hipStream_t s;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> spans;
+    int cur = -1;
+    hipEvent_t start = nullptr;
+    explicit PhaseTimer(hipStream_t st) : s(st) {}
+    ~PhaseTimer() {
+        for (auto &t : spans) {
+            (void)hipEventDestroy(std::get<1>(t));
+            (void)hipEventDestroy(std::get<2>(t));
+        }
+        if (start) (void)hipEventDestroy(start);
+    }
+    void begin(int phase) {
+        end();
+        AIRG_HIP(hipEventCreate(&start));
+        AIRG_HIP(hipEventRecord(start, s));
+        cur = phase;
+    }
+    void end() {
+        if (cur < 0) return;
+        hipEvent_t stop;
+        AIRG_HIP(hipEventCreate(&stop));
+        AIRG_HIP(hipEventRecord(stop, s));
+        spans.emplace_back(cur, start, stop);
+        start = nullptr;
+        cur = -1;
+    }
+    void collect(double *out) {
+        end();
+        AIRG_HIP(hipStreamSynchronize(s));
+        for (auto &t : spans) {
+            float ms = 0.f;
+            AIRG_HIP(hipEventElapsedTime(&ms, std::get<1>(t), std::get<2>(t)));
+            out[std::get<0>(t)] += ms * 1e-3;
+        }
+    }
+};
+
+struct NullTimer {
+    void begin(int) {}
+    void end() {}
+};
+
+CfParams cf_params(const airg_opts &o, uint64_t seed) {
+    return CfParams{o.strong_threshold, o.ddc_threshold, o.ddc_fraction, o.pmisr_max_rounds, seed};
+}
+
+// CF splitting of one level; fills cf and rank, returns (nF, nC).
+std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl, DBuf<int8_t> &cf,
+                                  DBuf<int32_t> &rank, hipStream_t s) {
+    int32_t n = A.nr;
+    cf.alloc((size_t)n, s);
+    rank.alloc((size_t)n, s);
+    StrengthGraph G = strength_graph(A, o.strong_threshold, s);
+    DBuf<uint32_t> h((size_t)n, s);
+    pmisr_hash(n, seed, lvl, h.p, s);
+    DBuf<int8_t> cf0((size_t)n, s);
+    pmisr(A, G, h.p, o.pmisr_max_rounds, cf0.p, s);
+    double ad = o.ddc_threshold;
+    if (ad < 0.0) ad = ddc_fraction_threshold(A, cf0.p, o.ddc_fraction, s);
+    ddc(A, ad, cf0.p, cf.p, nullptr, s);
+    return cf_ranks(cf.p, n, rank.p, s);
+}
+
+// Copy of A's pattern with values from the fixed-sparsity polynomial.
+Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, hipStream_t s) {
+    Csr X;
+    X.alloc(A.nr, A.nc, A.nnz, s);
+    d2d(X.rp.p, A.rp, (size_t)A.nr + 1, s);
+    d2d(X.ci.p, A.ci, (size_t)A.nnz, s);
+    poly_fixed_sparsity(A, P.alpha, m, X.v.p, s);
+    return X;
+}
+
+// Steps 2 and 7-11 of the recipe once the splitting is known.
+template <class Timer>
+void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl, const double *alpha_in,
+                    const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, DBuf<int32_t> &fidx,
+                    DBuf<int32_t> &cidx, Csr &Aff, Csr *Afc, PolyInfo &poly, Csr &Ainv, Csr &Z, Csr &W, Csr &Ac,
+                    Timer &tm, hipStream_t s) {
+    int32_t n = A.nr;
+    int m = o.poly_order + 1;
+    tm.begin(AIRG_PHASE_EXTRACT);
+    fidx.alloc((size_t)nF + 1, s);
+    cidx.alloc((size_t)nC + 1, s);
+    cf_index_lists(cf, rank, n, fidx.p, cidx.p, s);
+    Aff = extract_block(A, cf, rank, CF_F, CF_F, nF, nF, s);
+    if (Afc) *Afc = extract_block(A, cf, rank, CF_F, CF_C, nF, nC, s);
+    Csr Acf = extract_block(A, cf, rank, CF_C, CF_F, nC, nF, s);
+    tm.begin(AIRG_PHASE_POLY);
+    if (alpha_in) {
+        poly = PolyInfo{};
+        poly.m = m;
+        poly.used = m;
+        for (int k = 0; k < m; ++k) poly.alpha[k] = alpha_in[k];
+    } else {
+        poly = gmres_poly(view(Aff), seed, lvl, m, s);
+    }
+    Ainv = assemble_inverse(view(Aff), poly, m, s);
+    tm.begin(AIRG_PHASE_RESTRICTOR);
+    {
+        Csr prod = spgemm(view(Acf), view(Ainv), s);
+        Z = drop_rows(view(prod), o.drop_R, false, true, s);   // Z = -A_cf Ainv, dropped
+    }
+    tm.begin(AIRG_PHASE_PROLONG);
+    Csr P;
+    onepoint_prolongator(A, cf, rank, nF, nC, o.onepoint_weight, &P, &W, s);
+    tm.begin(AIRG_PHASE_COARSE);
+    {
+        Csr R = restriction_full(view(Z), fidx.p, cidx.p, n, s);
+        Csr AP = spgemm(A, view(P), s);
+        Csr RAP = spgemm(view(R), view(AP), s);
+        Ac = drop_rows(view(RAP), o.drop_A, true, false, s);
+    }
+    tm.end();
+}
+
+// ----------------------------------------------------------- permutation ---
+__global__ void k_make_perm(int32_t n, int32_t nF, const int8_t *__restrict__ cf, const int32_t *__restrict__ rank,
+                            int32_t *__restrict__ perm, int32_t *__restrict__ iperm) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t p = cf[i] == CF_F ? rank[i] : nF + rank[i];
+    perm[i] = p;
+    iperm[p] = i;
+}
+
+__global__ void k_perm_count(int32_t nout, const int32_t *__restrict__ src, const int32_t *__restrict__ rp,
+                             int32_t *__restrict__ cnt) {
+    int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nout) return;
+    int32_t i = src[p];
+    cnt[p] = rp[i + 1] - rp[i];
+}
+
+// Output row p is input row src[p]; F columns first (as their ranks), then C
+// columns (as nF + rank): both subsequences keep their ascending order.
+template <int G>
+__global__ void __launch_bounds__(256) k_perm_fill(int32_t nout, const int32_t *__restrict__ src,
+                                                   const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                   const double *__restrict__ v, const int8_t *__restrict__ cf,
+                                                   const int32_t *__restrict__ rank, int32_t nF,
+                                                   const int32_t *__restrict__ orp, int32_t *__restrict__ oci,
+                                                   double *__restrict__ ov) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t p = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (p >= nout) return;
+    int32_t i = src[p];
+    int32_t w = orp[p];
+    int32_t e = rp[i + 1];
+    for (int pass = 0; pass < 2; ++pass) {
+        int8_t want = pass == 0 ? CF_F : CF_C;
+        for (int32_t base = rp[i]; base < e; base += G) {
+            int32_t k = base + lane;
+            bool keep = false;
+            int32_t j = 0;
+            if (k < e) {
+                j = ci[k];
+                keep = cf[j] == want;
+            }
+            int tot;
+            int pre = group_prefix<G>(keep, &tot);
+            if (keep) {
+                oci[w + pre] = pass == 0 ? rank[j] : nF + rank[j];
+                ov[w + pre] = v[k];
+            }
+            w += tot;
+        }
+    }
+}
+
+Csr permute_fc(const CsrView &A, const int32_t *src, int32_t nout, const int8_t *cf, const int32_t *rank, int32_t nF,
+               hipStream_t s) {
+    Csr B;
+    B.nr = nout;
+    B.nc = A.nc;
+    B.rp.alloc((size_t)nout + 1, s);
+    DBuf<int32_t> cnt((size_t)nout + 1, s);
+    if (nout > 0) {
+        k_perm_count<<<grid_for(nout, 256), 256, 0, s>>>(nout, src, A.rp, cnt.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    B.nnz = exclusive_scan(cnt.p, B.rp.p, nout, s);
+    B.ci.alloc((size_t)B.nnz, s);
+    B.v.alloc((size_t)B.nnz, s);
+    if (nout > 0) {
+        int g = lanes_for(A.nnz, A.nr);
+        dispatch_group(g, [&]<int G>() {
+            k_perm_fill<G><<<grid_for((int64_t)nout * G, 256), 256, 0, s>>>(nout, src, A.rp, A.ci, A.v, cf, rank,
+                                                                            nF, B.rp.p, B.ci.p, B.v.p);
+        });
+        AIRG_LAUNCH_CHECK();
+    }
+    return B;
+}
+
+// [Z I] with rows in the next level's order: row q is Z's row r = niperm[q]
+// (identity when niperm is null) followed by the entry (nF + r, 1).
+__global__ void k_rp_count(int32_t nC, const int32_t *__restrict__ niperm, const int32_t *__restrict__ zrp,
+                           int32_t *__restrict__ cnt) {
+    int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nC) return;
+    int32_t r = niperm ? niperm[q] : q;
+    cnt[q] = zrp[r + 1] - zrp[r] + 1;
+}
+__global__ void k_rp_fill(int32_t nC, int32_t nF, const int32_t *__restrict__ niperm, const int32_t *__restrict__ zrp,
+                          const int32_t *__restrict__ zci, const double *__restrict__ zv,
+                          const int32_t *__restrict__ orp, int32_t *__restrict__ oci, double *__restrict__ ov) {
+    int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nC) return;
+    int32_t r = niperm ? niperm[q] : q;
+    int32_t w = orp[q];
+    for (int32_t k = zrp[r]; k < zrp[r + 1]; ++k, ++w) {
+        oci[w] = zci[k];
+        ov[w] = zv[k];
+    }
+    oci[w] = nF + r;
+    ov[w] = 1.0;
+}
+
+// [W; I] in level order: row p < nF is W's row p, row nF + r is e_r; coarse
+// columns mapped through the next level's permutation nperm.
+__global__ void k_pp_count(int32_t n, int32_t nF, const int32_t *__restrict__ wrp, int32_t *__restrict__ cnt) {
+    int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    cnt[p] = p < nF ? wrp[p + 1] - wrp[p] : 1;
+}
+__global__ void k_pp_fill(int32_t n, int32_t nF, const int32_t *__restrict__ nperm, const int32_t *__restrict__ wrp,
+                          const int32_t *__restrict__ wci, const double *__restrict__ wv,
+                          const int32_t *__restrict__ orp, int32_t *__restrict__ oci, double *__restrict__ ov) {
+    int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t w = orp[p];
+    if (p < nF) {
+        for (int32_t k = wrp[p]; k < wrp[p + 1]; ++k, ++w) {
+            int32_t c = wci[k];
+            oci[w] = nperm ? nperm[c] : c;
+            ov[w] = wv[k];
+        }
+    } else {
+        int32_t r = p - nF;
+        oci[w] = nperm ? nperm[r] : r;
+        ov[w] = 1.0;
+    }
+}
+
+void finalize(Hier &H) {
+    hipStream_t s = H.s;
+    int nl = H.nlev();
+    for (int l = 0; l < nl; ++l) {
+        Level &L = H.L(l);
+        if (L.coarsest) continue;
+        L.perm.alloc((size_t)L.n, s);
+        L.iperm.alloc((size_t)L.n, s);
+        k_make_perm<<<grid_for(L.n, 256), 256, 0, s>>>(L.n, L.nF, L.cf.p, L.rank.p, L.perm.p, L.iperm.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    for (int l = 0; l < nl; ++l) {
+        Level &L = H.L(l);
+        if (L.coarsest) {
+            make_f32(L.A, s);
+            make_f32(L.Ainv, s);
+            continue;
+        }
+        Level &N = H.L(l + 1);
+        const int32_t *nperm = N.coarsest ? nullptr : N.perm.p;
+        const int32_t *niperm = N.coarsest ? nullptr : N.iperm.p;
+        L.AF = permute_fc(view(L.A), L.fidx.p, L.nF, L.cf.p, L.rank.p, L.nF, s);
+        // [Z I]
+        {
+            Csr &R = L.Rp;
+            R.nr = L.nC;
+            R.nc = L.n;
+            R.rp.alloc((size_t)L.nC + 1, s);
+            DBuf<int32_t> cnt((size_t)L.nC + 1, s);
+            if (L.nC > 0) {
+                k_rp_count<<<grid_for(L.nC, 256), 256, 0, s>>>(L.nC, niperm, L.Z.rp.p, cnt.p);
+                AIRG_LAUNCH_CHECK();
+            }
+            R.nnz = exclusive_scan(cnt.p, R.rp.p, L.nC, s);
+            R.ci.alloc((size_t)R.nnz, s);
+            R.v.alloc((size_t)R.nnz, s);
+            if (L.nC > 0) {
+                k_rp_fill<<<grid_for(L.nC, 256), 256, 0, s>>>(L.nC, L.nF, niperm, L.Z.rp.p, L.Z.ci.p, L.Z.v.p, R.rp.p,
+                                                             R.ci.p, R.v.p);
+                AIRG_LAUNCH_CHECK();
+            }
+        }
+        // [W; I]
+        {
+            Csr &P = L.Pp;
+            P.nr = L.n;
+            P.nc = L.nC;
+            P.rp.alloc((size_t)L.n + 1, s);
+            DBuf<int32_t> cnt((size_t)L.n + 1, s);
+            k_pp_count<<<grid_for(L.n, 256), 256, 0, s>>>(L.n, L.nF, L.W.rp.p, cnt.p);
+            AIRG_LAUNCH_CHECK();
+            P.nnz = exclusive_scan(cnt.p, P.rp.p, L.n, s);
+            P.ci.alloc((size_t)P.nnz, s);
+            P.v.alloc((size_t)P.nnz, s);
+            k_pp_fill<<<grid_for(L.n, 256), 256, 0, s>>>(L.n, L.nF, nperm, L.W.rp.p, L.W.ci.p, L.W.v.p, P.rp.p,
+                                                        P.ci.p, P.v.p);
+            AIRG_LAUNCH_CHECK();
+        }
+        make_f32(L.AF, s);
+        make_f32(L.Rp, s);
+        make_f32(L.Pp, s);
+        make_f32(L.Ainv, s);
+    }
+    Level &T = H.L(0);
+    if (T.coarsest) {
+        H.top_permuted = false;
+    } else {
+        H.A0p = permute_fc(view(T.A), T.iperm.p, T.n, T.cf.p, T.rank.p, T.nF, s);
+        H.top_permuted = true;
+    }
+    // work vectors
+    for (int l = 0; l < nl; ++l) {
+        Level &L = H.L(l);
+        L.g64.alloc((size_t)L.n, s);
+        L.e64.alloc((size_t)L.n, s);
+        L.t64.alloc((size_t)L.n, s);
+        L.g32.alloc((size_t)L.n, s);
+        L.e32.alloc((size_t)L.n, s);
+        L.t32.alloc((size_t)L.n, s);
+    }
+    int32_t n0 = T.n;
+    H.x.alloc((size_t)n0, s);
+    H.r.alloc((size_t)n0, s);
+    H.e.alloc((size_t)n0, s);
+    H.bp.alloc((size_t)n0, s);
+    H.r32.alloc((size_t)n0, s);
+    H.e32.alloc((size_t)n0, s);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ build --
+std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t seed, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    auto H = std::make_unique<Hier>();
+    H->opt = o;
+    H->seed = seed;
+    H->s = s;
+    PhaseTimer tm(s);
+    auto first = std::make_unique<Level>();
+    first->n = A0.nr;
+    first->A = std::move(A0);
+    H->lv.push_back(std::move(first));
+    int maxl = o.max_levels > 0 ? o.max_levels : 64;
+    for (int l = 0;; ++l) {
+        Level &L = H->L(l);
+        int32_t n = L.n;
+        bool coarsest = (o.truncate_n > 0 && n <= o.truncate_n) || l == maxl - 1;
+        if (!coarsest) {
+            tm.begin(AIRG_PHASE_CF);
+            auto [nF, nC] = split(view(L.A), o, seed, l, L.cf, L.rank, s);
+            L.nF = nF;
+            L.nC = nC;
+            tm.end();
+            if (nF == 0 || nC < o.poly_order) coarsest = true;
+        }
+        if (coarsest) {
+            tm.begin(AIRG_PHASE_POLY);
+            L.coarsest = true;
+            L.cf.reset();
+            L.rank.reset();
+            L.nF = n;
+            L.nC = 0;
+            int m = o.coarse_poly_order + 1;
+            L.poly = gmres_poly(view(L.A), seed, l, m, s);
+            L.Ainv = assemble_inverse(view(L.A), L.poly, m, s);
+            tm.end();
+            break;
+        }
+        auto next = std::make_unique<Level>();
+        complete_level(view(L.A), o, seed, l, nullptr, L.cf.p, L.rank.p, L.nF, L.nC, L.fidx, L.cidx, L.Aff, &L.Afc,
+                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s);
+        next->n = next->A.nr;
+        H->lv.push_back(std::move(next));
+    }
+    tm.begin(AIRG_PHASE_FINALIZE);
+    finalize(*H);
+    tm.collect(H->phase);
+    H->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return H;
+}
+
+LevelOut build_one_level(const CsrView &A, const airg_opts &o, uint64_t seed, int level, const double *alpha_in,
+                         hipStream_t s) {
+    LevelOut out;
+    DBuf<int32_t> rank;
+    auto [nF, nC] = split(A, o, seed, level, out.cf, rank, s);
+    out.nF = nF;
+    out.nC = nC;
+    DBuf<int32_t> fidx, cidx;
+    Csr Aff;
+    NullTimer tm;
+    complete_level(A, o, seed, level, alpha_in, out.cf.p, rank.p, nF, nC, fidx, cidx, Aff, nullptr, out.poly,
+                   out.Ainv, out.Z, out.W, out.Ac, tm, s);
+    return out;
+}
+
+// ------------------------------------------------------------- metrics ---
+int64_t spmv_bytes(int64_t rows, int64_t cols, int64_t nnz, int vbytes, bool reads_y) {
+    return nnz * (vbytes + 4) + 4 * (rows + 1) + (int64_t)vbytes * (cols + rows + (reads_y ? rows : 0));
+}
+
+int64_t vcycle_bytes(const Hier &H, int vb) {
+    int64_t b = 0;
+    for (int l = 0; l < (int)H.lv.size(); ++l) {
+        const Level &L = *H.lv[l];
+        if (L.coarsest) {
+            int vc = H.opt.coarse_iters;
+            // e = Ainv g, then (vc - 1) times: t = g - A e; e += Ainv t
+            b += spmv_bytes(L.n, L.n, L.Ainv.nnz, vb, false);
+            b += (int64_t)(vc - 1) * (spmv_bytes(L.n, L.n, L.A.nnz, vb, true) + spmv_bytes(L.n, L.n, L.Ainv.nnz, vb, true));
+            continue;
+        }
+        b += spmv_bytes(L.Rp.nr, L.Rp.nc, L.Rp.nnz, vb, false);
+        b += spmv_bytes(L.Pp.nr, L.Pp.nc, L.Pp.nnz, vb, false);
+        b += H.opt.up_smooths *
+             (spmv_bytes(L.AF.nr, L.AF.nc, L.AF.nnz, vb, true) + spmv_bytes(L.Ainv.nr, L.Ainv.nc, L.Ainv.nnz, vb, true));
+    }
+    return b;
+}
+
+void complexities(const Hier &H, double *grid, double *op, double *storage) {
+    const Level &T = *H.lv[0];
+    double n0 = T.n, z0 = (double)T.A.nnz, g = 0, o = 0, st = 0;
+    for (auto &lp : H.lv) {
+        const Level &L = *lp;
+        g += L.n;
+        o += (double)L.A.nnz;
+        if (L.coarsest) {
+            st += (double)L.Ainv.nnz + (H.opt.coarse_iters > 1 ? (double)L.A.nnz : 0.0);
+        } else {
+            st += (double)L.Ainv.nnz + (double)L.Aff.nnz + (double)L.Afc.nnz + (double)(L.Z.nnz + L.nC) +
+                  (double)(L.W.nnz + L.nC);
+        }
+    }
+    *grid = g / n0;
+    *op = o / z0;
+    *storage = st / z0;
+}
+
+}  // namespace airg

@@ -1,0 +1,196 @@
+// Solve phase: the V-cycle with up F-point smoothing only (Results), the
+// undamped Richardson outer iteration, and flexible GMRES in FP64 around an
+// FP32 or FP64 V-cycle.
+#include <cmath>
+
+#include "csr.hpp"
+#include "hierarchy.hpp"
+
+namespace airg {
+
+namespace {
+inline void spmvT(const Csr &A, const double *x, double *y, const double *z, int mode, hipStream_t s) {
+    spmv(view(A), x, y, z, mode, s);
+}
+inline void spmvT(const Csr &A, const float *x, float *y, const float *z, int mode, hipStream_t s) {
+    spmv32(view(A), x, y, z, mode, s);
+}
+template <class T> struct Bufs;
+template <> struct Bufs<double> {
+    static double *g(Level &L) { return L.g64.p; }
+    static double *e(Level &L) { return L.e64.p; }
+    static double *t(Level &L) { return L.t64.p; }
+};
+template <> struct Bufs<float> {
+    static float *g(Level &L) { return L.g32.p; }
+    static float *e(Level &L) { return L.e32.p; }
+    static float *t(Level &L) { return L.t32.p; }
+};
+}  // namespace
+
+// e = V(g) on level l, vectors in level order (F points first):
+//   g_c = [Z I] g;  e_c = V(g_c);  e = [W; I] e_c;
+//   up_smooths times: e_F += Ainv (g_F - [A_ff A_fc] e).
+// Coarsest level: e = Ainv g, then (coarse_iters - 1) times e += Ainv (g - A e).
+template <class T>
+void Hier::vcycle(int l, const T *g, T *e) {
+    Level &Lv = L(l);
+    T *t = Bufs<T>::t(Lv);
+    if (Lv.coarsest) {
+        spmvT(Lv.Ainv, g, e, (const T *)nullptr, SPMV_SET, s);
+        for (int it = 1; it < opt.coarse_iters; ++it) {
+            spmvT(Lv.A, e, t, g, SPMV_ZMINUS, s);
+            spmvT(Lv.Ainv, t, e, (const T *)nullptr, SPMV_ADD, s);
+        }
+        return;
+    }
+    Level &N = L(l + 1);
+    T *gc = Bufs<T>::g(N);
+    T *ec = Bufs<T>::e(N);
+    spmvT(Lv.Rp, g, gc, (const T *)nullptr, SPMV_SET, s);
+    vcycle<T>(l + 1, gc, ec);
+    spmvT(Lv.Pp, ec, e, (const T *)nullptr, SPMV_SET, s);
+    for (int k = 0; k < opt.up_smooths; ++k) {
+        spmvT(Lv.AF, e, t, g, SPMV_ZMINUS, s);
+        spmvT(Lv.Ainv, t, e, (const T *)nullptr, SPMV_ADD, s);
+    }
+}
+
+template void Hier::vcycle<double>(int, const double *, double *);
+template void Hier::vcycle<float>(int, const float *, float *);
+
+void Hier::precondition(const double *rv, double *ev, int precision) {
+    int64_t n0 = L(0).n;
+    if (precision == 32) {
+        cast_d2f(rv, r32.p, n0, s);
+        vcycle<float>(0, r32.p, e32.p);
+        cast_f2d(e32.p, ev, n0, s);
+    } else {
+        vcycle<double>(0, rv, ev);
+    }
+}
+
+namespace {
+CsrView top_view(Hier &H) { return H.top_permuted ? view(H.A0p) : view(H.L(0).A); }
+
+void to_level_order(Hier &H, const double *b, double *bp) {
+    int64_t n = H.L(0).n;
+    if (H.top_permuted) scatter(b, H.L(0).perm.p, bp, n, H.s);
+    else d2d(bp, b, (size_t)n, H.s);
+}
+void to_natural_order(Hier &H, const double *xp, double *x) {
+    int64_t n = H.L(0).n;
+    if (H.top_permuted) gather(xp, H.L(0).perm.p, x, n, H.s);
+    else d2d(x, xp, (size_t)n, H.s);
+}
+}  // namespace
+
+// Undamped Richardson from a zero guess: x += V(b - A x) until
+// ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual every iteration).
+SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, int maxit) {
+    hipStream_t s = H.s;
+    int64_t n = H.L(0).n;
+    SolveResult res;
+    CsrView A = top_view(H);
+    to_level_order(H, b, H.bp.p);
+    fill_zero(H.x.p, (size_t)n * 8, s);
+    double nb = nrm2(H.bp.p, n, s);
+    if (nb == 0.0) {
+        to_natural_order(H, H.x.p, x);
+        res.converged = true;
+        return res;
+    }
+    d2d(H.r.p, H.bp.p, (size_t)n, s);
+    double rr = nb;
+    int prec = H.opt.precond_precision == 32 ? 32 : 64;
+    while (rr > rtol * nb && res.iterations < maxit) {
+        H.precondition(H.r.p, H.e.p, prec);
+        axpy(1.0, H.e.p, H.x.p, n, s);
+        spmv_top(A, H.x.p, H.r.p, H.bp.p, SPMV_ZMINUS, s);
+        rr = nrm2(H.r.p, n, s);
+        res.iterations++;
+        AIRG_REQUIRE(std::isfinite(rr), ST_STALL, "residual became non-finite in the Richardson iteration");
+    }
+    to_natural_order(H, H.x.p, x);
+    res.rel_residual = rr / nb;
+    res.converged = rr <= rtol * nb;
+    return res;
+}
+
+// Flexible GMRES(restart), right preconditioned by one V-cycle per Arnoldi
+// step (FP32 or FP64), classical Gram-Schmidt applied twice in FP64, Givens
+// rotations on the host, true FP64 residual at every restart.
+SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit) {
+    hipStream_t s = H.s;
+    int64_t n = H.L(0).n;
+    int m = H.opt.fgmres_restart > 0 ? H.opt.fgmres_restart : 30;
+    SolveResult res;
+    CsrView A = top_view(H);
+    DBuf<double> V((size_t)n * (m + 1), s), Zb((size_t)n * m, s), hd((size_t)m + 1, s);
+    to_level_order(H, b, H.bp.p);
+    fill_zero(H.x.p, (size_t)n * 8, s);
+    double nb = nrm2(H.bp.p, n, s);
+    if (nb == 0.0) {
+        to_natural_order(H, H.x.p, x);
+        res.converged = true;
+        return res;
+    }
+    d2d(H.r.p, H.bp.p, (size_t)n, s);
+    double beta = nb;
+    int prec = H.opt.precond_precision == 32 ? 32 : 64;
+    std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h1(m + 1), h2(m + 1);
+    while (beta > rtol * nb && res.iterations < maxit) {
+        scal_copy(1.0 / beta, H.r.p, V.p, n, s);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        for (; j < m && res.iterations < maxit;) {
+            double *vj = V.p + (int64_t)j * n, *zj = Zb.p + (int64_t)j * n, *w = V.p + (int64_t)(j + 1) * n;
+            H.precondition(vj, zj, prec);
+            res.iterations++;
+            spmv_top(A, zj, w, nullptr, SPMV_SET, s);
+            multi_dot(V.p, n, j + 1, w, n, h1.data(), s);
+            h2d(hd.p, h1.data(), (size_t)j + 1, s);
+            gemv_sub(V.p, n, j + 1, hd.p, w, n, s);
+            multi_dot(V.p, n, j + 1, w, n, h2.data(), s);
+            h2d(hd.p, h2.data(), (size_t)j + 1, s);
+            gemv_sub(V.p, n, j + 1, hd.p, w, n, s);
+            for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h1[i] + h2[i];
+            double hn = nrm2(w, n, s);
+            AIRG_REQUIRE(std::isfinite(hn), ST_STALL, "Arnoldi vector became non-finite");
+            Hm[(size_t)(j + 1) * m + j] = hn;
+            if (hn > 0.0) scal_copy(1.0 / hn, w, w, n, s);
+            for (int i = 0; i < j; ++i) {
+                double a = Hm[(size_t)i * m + j], c = Hm[(size_t)(i + 1) * m + j];
+                Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                Hm[(size_t)(i + 1) * m + j] = cs[i] * c - sn[i] * a;
+            }
+            double a = Hm[(size_t)j * m + j], c = Hm[(size_t)(j + 1) * m + j];
+            double rr = std::hypot(a, c);
+            cs[j] = rr > 0.0 ? a / rr : 1.0;
+            sn[j] = rr > 0.0 ? c / rr : 0.0;
+            Hm[(size_t)j * m + j] = rr;
+            Hm[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++j;
+            if (std::fabs(g[j]) <= rtol * nb || hn == 0.0) break;
+        }
+        for (int i = j - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int q = i + 1; q < j; ++q) t -= Hm[(size_t)i * m + q] * y[q];
+            y[i] = Hm[(size_t)i * m + i] != 0.0 ? t / Hm[(size_t)i * m + i] : 0.0;
+        }
+        h2d(hd.p, y.data(), (size_t)j, s);
+        gemv_add(Zb.p, n, j, hd.p, H.x.p, n, s);
+        spmv_top(A, H.x.p, H.r.p, H.bp.p, SPMV_ZMINUS, s);
+        beta = nrm2(H.r.p, n, s);
+        AIRG_REQUIRE(std::isfinite(beta), ST_STALL, "residual became non-finite in FGMRES");
+    }
+    to_natural_order(H, H.x.p, x);
+    res.rel_residual = beta / nb;
+    res.converged = beta <= rtol * nb;
+    return res;
+}
+
+}  // namespace airg

@@ -1,0 +1,148 @@
+"""End-to-end parity of the HIP hierarchy and solves with the oracle.
+
+* Hierarchy replay: the oracle rebuilds every level from the device's level
+  operator and polynomial coefficients; the splitting, patterns and values
+  must match bit for bit, which pins every device level to the oracle.
+* Solves: the residual of the returned x is recomputed by the oracle in
+  FP64 and must be <= 1e-10 relative; x is compared with the exact sweep
+  solution within the error that residual allows.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle.sweep import sweep_solve
+from tests.helpers import csr_of
+from workloads import p0_square, dg_square, p0_cube
+
+pytestmark = pytest.mark.gpu
+
+airg = pytest.importorskip("paper_2408_08262_amd.airg")
+
+CASES = {
+    "p0_square_64": (lambda: p0_square(64), 1),
+    "dg_square_32": (lambda: dg_square(32), 3),
+    "dg_square_96": (lambda: dg_square(96), 3),
+    "p0_cube_16": (lambda: p0_cube(16), 1),
+}
+
+
+def setup(P, **kw):
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    opts = airg.default_opts(seed=P.seed, **kw)
+    return airg.airg_setup(*A, opts), opts
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_replay_bit_exact(name):
+    P = CASES[name][0]()
+    h, opts = setup(P)
+    st = airg.airg_get_stats(h)
+    prm = O.default_params(seed=P.seed)
+    for l in range(st["levels"] - 1):
+        info = airg.airg_get_level(h, l)
+        A_l = airg.airg_get_level_matrix(h, l, "A")
+        want = O.level_build(A_l, prm, l, alpha_in=info["alpha"])
+        assert np.array_equal(info["cf"], want["cf"]), "level %d splitting" % l
+        for key in ("Ainv", "Z", "W"):
+            got = airg.airg_get_level_matrix(h, l, key)
+            assert np.array_equal(got[0], want[key][0]) and np.array_equal(got[1], want[key][1]), (l, key)
+            assert np.array_equal(got[2], want[key][2]), (l, key)
+        nxt = airg.airg_get_level_matrix(h, l + 1, "A")
+        assert np.array_equal(nxt[0], want["Ac"][0]) and np.array_equal(nxt[1], want["Ac"][1]), l
+        assert np.array_equal(nxt[2], want["Ac"][2]), l
+        # the device's coefficients against the oracle's own on the same A_ff
+        Aff = airg.airg_get_level_matrix(h, l, "Aff")
+        alpha, used = O.gmres_poly(Aff, P.seed, l, opts.poly_order + 1)
+        assert used == info["poly_terms"]
+        assert np.allclose(info["alpha"], alpha, rtol=1e-6, atol=1e-8 * np.abs(alpha).max()), l
+    # level 0 splitting straight from the input operator
+    assert np.array_equal(airg.airg_get_level(h, 0)["cf"], O.cf_split(csr_of(P), prm, 0))
+
+
+@pytest.mark.parametrize("name", ["p0_square_64", "dg_square_32", "p0_cube_16"])
+@pytest.mark.parametrize("outer,prec", [(0, 64), (1, 64), (1, 32), (0, 32)])
+def test_solve_reaches_tolerance(name, outer, prec):
+    make, bs = CASES[name]
+    P = make()
+    h, _ = setup(P, outer=outer, precond_precision=prec)
+    b = torch.as_tensor(P.b, device="cuda")
+    x, info = airg.airg_solve(h, b, rtol=1e-10, max_it=100)
+    x = x.cpu().numpy()
+    r = P.b - O.spmv(csr_of(P), x)
+    rel = np.linalg.norm(r) / np.linalg.norm(P.b)
+    assert info["converged"] and rel <= 1e-10 * 1.0001, rel
+    assert abs(rel - info["rel_residual"]) <= 1e-12
+    xs = sweep_solve(P.rowptr, P.col, P.val, P.b, bs)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
+    assert info["iterations"] <= 40
+
+
+def test_richardson_iterates_match_oracle_cycle_count():
+    """Same hierarchy (bit-exact up to the coefficients) gives the same count."""
+    P = p0_square(64)
+    h, _ = setup(P)
+    _, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10)
+    H = O.Hierarchy(csr_of(P), O.default_params(seed=P.seed))
+    _, its, _ = H.richardson(P.b, 1e-10, 100)
+    assert abs(info["iterations"] - its) <= 1
+
+
+def test_multiple_rhs_and_not_converged_status():
+    P = dg_square(24)
+    h, _ = setup(P)
+    B = np.stack([P.b, 2.0 * P.b + 1.0], axis=1)
+    X, info = airg.airg_solve(h, torch.as_tensor(B, device="cuda"), rtol=1e-10)
+    X = X.cpu().numpy()
+    for c in range(2):
+        r = B[:, c] - O.spmv(csr_of(P), X[:, c])
+        assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(B[:, c])
+    x1, info1 = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=1,
+                                allow_not_converged=True)
+    assert not info1["converged"] and info1["iterations"] == 1
+    with pytest.raises(airg.AirgError) as e:
+        airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=1)
+    assert e.value.status == 1
+
+
+def test_setup_error_statuses():
+    P = p0_square(8)
+    rp, ci, v = P.rowptr.copy(), P.col.copy(), P.val.copy()
+    opts = airg.default_opts()
+    bad = ci.copy()
+    bad[rp[5]], bad[rp[5] + 1] = bad[rp[5] + 1], bad[rp[5]]      # unsorted row (rows have >= 2 entries here)
+    for arrays, status in [((rp, bad, v), -2)]:
+        if np.all(np.diff(rp)[5:6] >= 2):
+            with pytest.raises(airg.AirgError) as e:
+                airg.airg_setup(*airg.to_device(*arrays), opts)
+            assert e.value.status == status
+    vz = v.copy()
+    vz[rp[3] + np.nonzero(ci[rp[3]:rp[4]] == 3)[0][0]] = 0.0
+    with pytest.raises(airg.AirgError) as e:
+        airg.airg_setup(*airg.to_device(rp, ci, vz), opts)
+    assert e.value.status == -3
+    vn = v.copy()
+    vn[0] = np.nan
+    with pytest.raises(airg.AirgError) as e:
+        airg.airg_setup(*airg.to_device(rp, ci, vn), opts)
+    assert e.value.status == -4
+    with pytest.raises(airg.AirgError) as e:
+        airg.airg_setup(*airg.to_device(rp, ci, v), airg.default_opts(poly_order=20))
+    assert e.value.status == -1
+    with pytest.raises(airg.AirgError) as e:
+        airg.airg_setup(*airg.to_device(rp, ci, v), airg.default_opts(device_bytes_cap=1024))
+    assert e.value.status == -5
+
+
+def test_truncated_hierarchy_and_stats():
+    P = dg_square(96)
+    h, _ = setup(P, truncate_n=3000)
+    st = airg.airg_get_stats(h)
+    last = airg.airg_get_level(h, st["levels"] - 1, with_cf=False)
+    assert last["coarsest"] and last["n"] <= 3000
+    prev = airg.airg_get_level(h, st["levels"] - 2, with_cf=False)
+    assert prev["n"] > 3000
+    assert 1.0 < st["grid_complexity"] < 4 and st["vcycle_bytes_fp64"] > st["vcycle_bytes_fp32"] > 0
+    x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
+    assert info["converged"]
