@@ -689,13 +689,24 @@ __global__ void k_bin_count(const int8_t *__restrict__ bin, int32_t n, int nbins
     __syncthreads();
     if (threadIdx.x < nbins && loc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], loc[threadIdx.x]);
 }
+// Each block reserves its bin ranges with one global atomic per bin, then
+// places its rows at block-local offsets taken from LDS counters.
 __global__ void k_bin_scatter(const int8_t *__restrict__ bin, int32_t n, int nbins, const int32_t *__restrict__ off,
                               int32_t *__restrict__ cursor, int32_t *__restrict__ rows) {
+    __shared__ int32_t loc[kMaxBins], base[kMaxBins];
+    if (threadIdx.x < kMaxBins) loc[threadIdx.x] = 0;
+    __syncthreads();
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b = bin[i];
-    if (b < 0 || b >= nbins) return;
-    rows[off[b] + atomicAdd(&cursor[b], 1)] = i;
+    int b = -1, r = 0;
+    if (i < n) {
+        b = bin[i];
+        if (b >= 0 && b < nbins) r = atomicAdd(&loc[b], 1);
+        else b = -1;
+    }
+    __syncthreads();
+    if (threadIdx.x < nbins && loc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], loc[threadIdx.x]);
+    __syncthreads();
+    if (b >= 0) rows[off[b] + base[b] + r] = i;
 }
 
 Bins bin_rows(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {

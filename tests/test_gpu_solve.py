@@ -52,11 +52,20 @@ def test_hierarchy_replay_bit_exact(name):
         nxt = airg.airg_get_level_matrix(h, l + 1, "A")
         assert np.array_equal(nxt[0], want["Ac"][0]) and np.array_equal(nxt[1], want["Ac"][1]), l
         assert np.array_equal(nxt[2], want["Ac"][2]), l
-        # the device's coefficients against the oracle's own on the same A_ff
+        # the device's polynomial against the oracle's own on the same A_ff:
+        # individual power-basis coefficients are ill-conditioned, so compare
+        # the action q(A_ff) v on a random vector
         Aff = airg.airg_get_level_matrix(h, l, "Aff")
         alpha, used = O.gmres_poly(Aff, P.seed, l, opts.poly_order + 1)
         assert used == info["poly_terms"]
-        assert np.allclose(info["alpha"], alpha, rtol=1e-6, atol=1e-8 * np.abs(alpha).max()), l
+        v = np.random.default_rng(l).standard_normal(Aff[0].shape[0] - 1)
+        qd, qo = np.zeros_like(v), np.zeros_like(v)
+        pk = v.copy()
+        for k in range(len(alpha)):
+            qd += info["alpha"][k] * pk
+            qo += alpha[k] * pk
+            pk = O.spmv(Aff, pk)
+        assert np.linalg.norm(qd - qo) <= 1e-7 * np.linalg.norm(qo), l
     # level 0 splitting straight from the input operator
     assert np.array_equal(airg.airg_get_level(h, 0)["cf"], O.cf_split(csr_of(P), prm, 0))
 
