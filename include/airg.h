@@ -175,6 +175,23 @@ airg_status airg_get_level(const airg_handle *h, int32_t segment, int32_t level,
 airg_status airg_get_level_matrix(const airg_handle *h, int32_t segment, int32_t level, int32_t which,
                                   int32_t *h_rowptr, int32_t *h_col, double *h_val);
 
+/* Cell-block helpers of the differentiable solve (the adjoint form).  The
+ * operator is A(sigma) = A_0 + sum_K sigma_K M_K with a dense bs x bs block
+ * M_K per cell K (row-major, ncell*bs*bs doubles in d_mass, bs <= 8), placed
+ * at the CSR value positions d_pos (ncell*bs*bs int32).
+ *   airg_blockdiag_axpy:     d_val[pos] = d_base[pos] + sigma_K M_K[a][b]
+ *                            (other entries of d_val are left untouched);
+ *   airg_blockdiag_apply:    y_K = M_K x_K (vectors of ncell*bs entries);
+ *   airg_blockdiag_bilinear: out_K = scale * lam_K^T M_K u_K (ncell entries).
+ * With these, b = M s, and for a loss L(u) with A^T lambda = dL/du:
+ * dL/ds = M^T lambda and dL/dsigma_K = -lambda_K^T M_K u_K. */
+airg_status airg_blockdiag_axpy(int64_t ncell, int32_t bs, const double *d_mass, const double *d_sigma,
+                                const int32_t *d_pos, const double *d_base, double *d_val, void *hip_stream);
+airg_status airg_blockdiag_apply(int64_t ncell, int32_t bs, const double *d_mass, const double *d_x, double *d_y,
+                                 void *hip_stream);
+airg_status airg_blockdiag_bilinear(int64_t ncell, int32_t bs, const double *d_mass, const double *d_u,
+                                    const double *d_lam, double scale, double *d_out, void *hip_stream);
+
 /* Measurement aid.  While enabled, every plain product y = A x of the outer
  * iteration with the finest operator (the FGMRES Arnoldi product, a kernel
  * instantiation of its own) is bracketed by HIP events on its stream and its

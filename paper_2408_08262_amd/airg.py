@@ -91,6 +91,9 @@ _SIGS = {
                          C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP), _VP],
 }
 _SIGS["airg_kernel_timing"] = [_I32]
+_SIGS["airg_blockdiag_axpy"] = [_I64, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
+_SIGS["airg_blockdiag_apply"] = [_I64, _I32, _VP, _VP, _VP, _VP]
+_SIGS["airg_blockdiag_bilinear"] = [_I64, _I32, _VP, _VP, _VP, _D, _VP, _VP]
 _SIGS["airg_kernel_timing_read"] = [C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D)]
 EXPORTS = tuple(_SIGS) + ("airg_destroy", "airg_status_string", "airg_last_error", "airg_csr_free")
 
@@ -301,6 +304,31 @@ def airg_kernel_timing_read():
     n, b, t = _I64(), _D(), _D()
     _check(lib().airg_kernel_timing_read(C.byref(n), C.byref(b), C.byref(t)))
     return n.value, b.value, t.value
+
+
+def airg_blockdiag_axpy(mass, sigma, pos, base, val, stream=None):
+    """val[pos] = base[pos] + sigma_K M_K (mass: (ncell, bs, bs))."""
+    ncell, bs = mass.shape[0], mass.shape[1]
+    _check(lib().airg_blockdiag_axpy(ncell, bs, _dev(mass, torch.float64), _dev(sigma, torch.float64),
+                                     _dev(pos, torch.int32), _dev(base, torch.float64), _dev(val, torch.float64),
+                                     _stream(stream)))
+
+
+def airg_blockdiag_apply(mass, x, stream=None):
+    ncell, bs = mass.shape[0], mass.shape[1]
+    y = torch.empty_like(x)
+    _check(lib().airg_blockdiag_apply(ncell, bs, _dev(mass, torch.float64), _dev(x, torch.float64),
+                                      _dev(y, torch.float64), _stream(stream)))
+    return y
+
+
+def airg_blockdiag_bilinear(mass, u, lam, scale=1.0, stream=None):
+    ncell, bs = mass.shape[0], mass.shape[1]
+    out = torch.empty(ncell, dtype=torch.float64, device=u.device)
+    _check(lib().airg_blockdiag_bilinear(ncell, bs, _dev(mass, torch.float64), _dev(u, torch.float64),
+                                         _dev(lam, torch.float64), scale, _dev(out, torch.float64),
+                                         _stream(stream)))
+    return out
 
 
 # ----------------------------------------------------------------- steps --

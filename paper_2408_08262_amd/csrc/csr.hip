@@ -120,10 +120,58 @@ __global__ void __launch_bounds__(256) k_spmv(int32_t nr, const int32_t *__restr
     }
 }
 
+// Rows of up to ~16 entries: CSR-stream.  A workgroup owns 256 consecutive
+// rows; its threads stream the rows' nonzeros (values, columns) coalesced in
+// chunks of kStreamChunk, park the products in LDS, and then each thread sums
+// its own row from LDS in ascending order.
+constexpr int kStreamRows = 256;
+constexpr int kStreamChunk = 2048;
+constexpr int32_t kStreamMinRows = 32768;   // below this the lane-group kernel has less latency
+
+template <class VT, class XT, int MODE, int TAG>
+__global__ void __launch_bounds__(kStreamRows) k_spmv_stream(int32_t nr, const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const VT *__restrict__ v, const XT *__restrict__ x,
+                                                            XT *y, const XT *z) {
+    __shared__ XT prod[kStreamChunk];
+    int32_t r0 = blockIdx.x * kStreamRows;
+    int32_t r1 = r0 + kStreamRows < nr ? r0 + kStreamRows : nr;
+    int32_t row = r0 + threadIdx.x;
+    int32_t base = rp[r0], end = rp[r1];
+    int32_t mb = 0, me = 0;
+    if (row < r1) {
+        mb = rp[row];
+        me = rp[row + 1];
+    }
+    XT acc = 0;
+    for (int32_t c0 = base; c0 < end; c0 += kStreamChunk) {
+        int32_t c1 = c0 + kStreamChunk < end ? c0 + kStreamChunk : end;
+        for (int32_t k = c0 + threadIdx.x; k < c1; k += kStreamRows) prod[k - c0] = (XT)v[k] * x[ci[k]];
+        __syncthreads();
+        int32_t lo = mb > c0 ? mb : c0, hi = me < c1 ? me : c1;
+        for (int32_t k = lo; k < hi; ++k) acc += prod[k - c0];
+        __syncthreads();
+    }
+    if (row < r1) {
+        if (MODE == SPMV_SET) y[row] = acc;
+        else if (MODE == SPMV_ZMINUS) y[row] = z[row] - acc;
+        else y[row] = y[row] + acc;
+    }
+}
+
 template <int TAG, class VT, class XT>
 static void spmv_t(int32_t nr, int64_t nnz, const int32_t *rp, const int32_t *ci, const VT *v, const XT *x, XT *y,
                    const XT *z, int mode, hipStream_t s, int lanes) {
     if (nr == 0) return;
+    if (lanes == 0 && nr >= kStreamMinRows && (double)nnz <= 16.0 * (double)nr) {
+        unsigned grid = grid_for(nr, kStreamRows);
+        if (mode == SPMV_SET) k_spmv_stream<VT, XT, SPMV_SET, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
+        else if (mode == SPMV_ZMINUS)
+            k_spmv_stream<VT, XT, SPMV_ZMINUS, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
+        else k_spmv_stream<VT, XT, SPMV_ADD, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
+        AIRG_LAUNCH_CHECK();
+        return;
+    }
     int g = lanes > 0 ? lanes : lanes_for(nnz, nr);
     dispatch_group(g, [&]<int G>() {
         unsigned grid = grid_for((int64_t)nr * G, 256);

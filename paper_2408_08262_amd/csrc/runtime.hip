@@ -216,6 +216,44 @@ __global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = (int32_t)bsum[nb];
 }
 
+// Small inputs: one workgroup scans everything (one launch instead of three).
+constexpr int kSmallScanThreads = 1024;
+constexpr int64_t kSmallScan = 65536;
+
+__global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(const int32_t *__restrict__ in,
+                                                                  int32_t *__restrict__ out, int64_t n,
+                                                                  int64_t *__restrict__ total) {
+    __shared__ int64_t wsum[kSmallScanThreads / kWave];
+    int64_t per = (n + kSmallScanThreads - 1) / kSmallScanThreads;
+    int64_t lo = (int64_t)threadIdx.x * per;
+    int64_t hi = lo + per < n ? lo + per : n;
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += in[i];
+    int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int64_t x = s;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int64_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[wid] = x;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+    for (int w = 0; w < kSmallScanThreads / kWave; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    off += x - s;
+    for (int64_t i = lo; i < hi; ++i) {
+        int32_t v = in[i];
+        out[i] = (int32_t)off;
+        off += v;
+    }
+    if (threadIdx.x == 0) {
+        out[n] = (int32_t)tot;
+        *total = tot;
+    }
+}
+
 // Blocked layout: thread t of block b owns items [b*tile + t*items, +items).
 // The reduce kernel above strides differently, but only block totals are
 // taken from it, and those do not depend on the layout inside the tile.
@@ -223,6 +261,15 @@ int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s
     if (n == 0) {
         fill_zero(out, sizeof(int32_t), s);
         return 0;
+    }
+    if (n <= kSmallScan) {
+        DBuf<int64_t> tot(1, s);
+        k_scan_small<<<1, kSmallScanThreads, 0, s>>>(in, out, n, tot.p);
+        AIRG_LAUNCH_CHECK();
+        if (!want_total) return -1;
+        int64_t t = d2h_one(tot.p, s);
+        AIRG_REQUIRE(t < ((int64_t)1 << 31), ST_LIMIT, "prefix sum exceeds the int32 index range");
+        return t;
     }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     DBuf<int64_t> bsum((size_t)nb + 1, s);

@@ -1,7 +1,9 @@
 // Two-phase sparse matrix product C = A B for gfx950 with LDS hash rows.
 //
 // Rows are binned by their product-count upper bound ub_i = sum_k |B_k|.
-// Small rows: one G-lane group per row with a private hash table in LDS.
+// Short A rows with few products: one thread per row merging the sorted B
+// rows.  Other small rows: one G-lane group per row with a private hash table
+// in LDS.
 // Larger rows: one workgroup per row (table in LDS up to 8192 slots, in
 // global scratch beyond).  The symbolic pass counts distinct columns, the
 // numeric pass accumulates.  Accumulation is deterministic: the entries of
@@ -16,6 +18,7 @@
 namespace airg {
 
 constexpr int32_t kEmpty = -1;
+constexpr int kMergeLists = 16;
 
 __device__ inline uint32_t hash_slot(int32_t c, uint32_t mask) { return ((uint32_t)c * 2654435761u) & mask; }
 
@@ -46,7 +49,80 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
     }
     int32_t uc = u > 0x7fffffff ? 0x7fffffff : (int32_t)u;
     ub[i] = uc;
-    bin[i] = uc == 0 ? 0 : uc <= 8 ? 1 : uc <= 32 ? 2 : uc <= 128 ? 3 : uc <= 1024 ? 4 : uc <= 4096 ? 5 : 6;
+    int32_t L = arp[i + 1] - arp[i];
+    bin[i] = uc == 0                            ? 0
+             : (L <= kMergeLists && uc <= 256) ? 7
+             : uc <= 8                         ? 1
+             : uc <= 32                        ? 2
+             : uc <= 128                       ? 3
+             : uc <= 1024                      ? 4
+             : uc <= 4096                      ? 5
+                                               : 6;
+}
+
+// ---------------------------------------------------------- merged rows ---
+// Short A rows: one thread per row merges the (sorted) B rows of its
+// entries; the smallest head column is emitted with the products of every
+// list holding it summed in list (= ascending k) order.
+template <bool NUMERIC>
+__global__ void __launch_bounds__(256) k_spgemm_merge(const int32_t *__restrict__ list, int64_t count,
+                                                      const int32_t *__restrict__ arp,
+                                                      const int32_t *__restrict__ aci,
+                                                      const double *__restrict__ av,
+                                                      const int32_t *__restrict__ brp,
+                                                      const int32_t *__restrict__ bci,
+                                                      const double *__restrict__ bv, int32_t *__restrict__ cnt,
+                                                      const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
+                                                      double *__restrict__ cv) {
+#pragma clang fp contract(off)
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    int32_t row = list[idx];
+    int32_t a0 = arp[row], L = arp[row + 1] - a0;
+    int32_t pos[kMergeLists], end[kMergeLists], head[kMergeLists];
+    double aval[kMergeLists];
+#pragma unroll
+    for (int q = 0; q < kMergeLists; ++q) {
+        pos[q] = end[q] = 0;
+        head[q] = 0x7fffffff;
+        aval[q] = 0.0;
+        if (q < L) {
+            int32_t k = aci[a0 + q];
+            pos[q] = brp[k];
+            end[q] = brp[k + 1];
+            if (NUMERIC) aval[q] = av[a0 + q];
+            if (pos[q] < end[q]) head[q] = bci[pos[q]];
+        }
+    }
+    int32_t w = NUMERIC ? crp[row] : 0;
+    int32_t emitted = 0;
+    for (;;) {
+        int32_t c = 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < kMergeLists; ++q) c = head[q] < c ? head[q] : c;
+        if (c == 0x7fffffff) break;
+        double acc = 0.0;
+        bool first = true;
+#pragma unroll
+        for (int q = 0; q < kMergeLists; ++q) {
+            if (head[q] == c) {
+                if (NUMERIC) {
+                    double p = aval[q] * bv[pos[q]];
+                    acc = first ? p : acc + p;
+                }
+                first = false;
+                ++pos[q];
+                head[q] = pos[q] < end[q] ? bci[pos[q]] : 0x7fffffff;
+            }
+        }
+        if (NUMERIC) {
+            cci[w] = c;
+            cv[w] = acc;
+            ++w;
+        }
+        ++emitted;
+    }
+    if (!NUMERIC) cnt[row] = emitted;
 }
 
 // ---------------------------------------------------------- group rows ----
@@ -276,6 +352,7 @@ static void run_bins(const Bins &B, const CsrView &A, const CsrView &Bm, int32_t
     auto args = [&](auto kern, unsigned grid, unsigned tpb, int b) {
         kern<<<grid, tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
     };
+    if (B.count(7)) args(k_spgemm_merge<NUMERIC>, grid_for(B.count(7), 256), 256, 7);
     if (B.count(1)) args(k_spgemm_group<4, 16, 256, NUMERIC>, grid_for(B.count(1), 64), 256, 1);
     if (B.count(2)) args(k_spgemm_group<8, 64, 256, NUMERIC>, grid_for(B.count(2), 32), 256, 2);
     if (B.count(3)) args(k_spgemm_group<16, 256, 256, NUMERIC>, grid_for(B.count(3), 16), 256, 3);
@@ -310,7 +387,7 @@ Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
         k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, A.rp, A.ci, Bm.rp, ub.p, bin.p);
         AIRG_LAUNCH_CHECK();
     }
-    Bins B = bin_rows(bin.p, m, 7, s);
+    Bins B = bin_rows(bin.p, m, 8, s);
     std::vector<int32_t> ub6;
     if (B.count(6)) {
         std::vector<int32_t> rows((size_t)B.count(6)), ubh((size_t)m);

@@ -275,3 +275,36 @@ def test_level_build_bit_exact_given_coefficients(k):
     assert np.array_equal(got["cf"].cpu().numpy(), want["cf"])
     for key in ("Ainv", "Z", "W", "Ac"):
         csr_equal(got[key].to_host(), want[key])
+
+
+def test_spgemm_every_bin_bit_exact():
+    """Rows built to land in each product-count bin, with short and long A rows."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(21)
+    k, n = 3000, 5000
+    blen = np.concatenate([np.zeros(100, int), 1 + (np.arange(k - 100) % 60)])
+    rows, cols, vals = [], [], []
+    for r in range(k):
+        c = np.sort(rng.choice(n, size=blen[r], replace=False))
+        rows += [r] * len(c)
+        cols += c.tolist()
+        vals += rng.standard_normal(len(c)).tolist()
+    B = sp.csr_matrix((vals, (rows, cols)), shape=(k, n))
+    by_len = {L: np.nonzero(blen == L)[0] for L in np.unique(blen)}
+    plans = [(17, [0] * 16 + [1]),          # ub 1, long A row
+             (20, [1] * 20), (20, [5] * 20), (20, [40] * 20), (60, [50] * 60), (100, [60] * 100),
+             (5, [2] * 5), (12, [20] * 12), (16, [16] * 16)]
+    arow, acol, aval = [], [], []
+    for i in range(200):
+        L, lens = plans[i % len(plans)]
+        picks = np.unique([rng.choice(by_len[l]) for l in lens])
+        arow += [i] * len(picks)
+        acol += picks.tolist()
+        aval += rng.standard_normal(len(picks)).tolist()
+    Am = sp.csr_matrix((aval, (arow, acol)), shape=(200, k))
+    Am.sort_indices()
+    B.sort_indices()
+    A = (Am.indptr, Am.indices, Am.data, k)
+    Bt = (B.indptr, B.indices, B.data, n)
+    got = airg.airg_spgemm(airg.to_device(*A[:3]), airg.to_device(*Bt[:3]), k, n).to_host()
+    csr_equal(got, O.spgemm(A, Bt))

@@ -131,6 +131,7 @@ def adjoint(N=256, theta=1.1, patch=32):
     (rpa, cia, va), _, _ = dgp1_upwind(xy, tri, om, 0.0, None, edges=edges)
     assert np.array_equal(rp, rpa) and np.array_equal(ci, cia)
     # patch: squares [i0, i0+patch) x [j0, j0+patch); square of a cell from its centroid
+    patch = min(patch, max(1, N // 2))          # reduced-size variants keep a proportionate patch
     p0 = np.random.default_rng(s["patch"]).integers(0, N - patch + 1, size=2)
     cen = xy[tri].mean(axis=1)
     sq = np.floor(cen * N).astype(np.int64)
