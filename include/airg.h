@@ -87,7 +87,7 @@ typedef struct airg_opts {
     int32_t build_adjoint;        /* 1: build the A^T hierarchy during setup            */
     int32_t onepoint_weight;      /* 0: weight 1; 1: -a_ij / a_ii                        */
     int32_t use_graph;            /* 1: replay the V-cycle as a captured HIP graph      */
-    int32_t reserved;
+    int32_t autotune;             /* 1: time candidate SpMM kernels per batch operator  */
     int64_t device_bytes_cap;     /* 0 = no cap; else a cap on the library's device     */
                                   /* memory in use while this setup runs                */
 } airg_opts;
@@ -147,7 +147,12 @@ airg_status airg_setup(const airg_opts *opts, int64_t n, int64_t nnz, const int3
  * zero initial guess until ||b - A x||_2 <= rtol ||b||_2 for every rhs (and
  * segment), or max_it V-cycles.  d_x is overwritten.  Returns
  * AIRG_NOT_CONVERGED (x = last iterate) when max_it is reached.  info may be
- * NULL. */
+ * NULL.  A batched handle (nseg > 1) with outer = FGMRES and
+ * precond_precision = 32 solves every (segment, rhs) pair at once: one FGMRES
+ * per pair in FP64, all preconditioned together by the batched FP32 V-cycle
+ * whose every stage is one SpMM launch over all segments (a captured HIP
+ * graph when use_graph = 1); nrhs must then be 1, 2, 4 or 8.  Other options
+ * solve the segments one after another. */
 airg_status airg_solve(airg_handle *h, int32_t nrhs, const double *d_b, double *d_x, double rtol, int32_t max_it,
                        void *hip_stream, airg_solve_info *info);
 

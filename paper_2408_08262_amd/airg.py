@@ -37,7 +37,7 @@ class Opts(C.Structure):
                 ("up_smooths", C.c_int32), ("down_smooths", C.c_int32), ("precond_precision", C.c_int32),
                 ("outer", C.c_int32), ("fgmres_restart", C.c_int32), ("seed", C.c_uint64),
                 ("build_adjoint", C.c_int32), ("onepoint_weight", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32), ("device_bytes_cap", C.c_int64)]
+                ("autotune", C.c_int32), ("device_bytes_cap", C.c_int64)]
 
 
 class SolveInfo(C.Structure):

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "airg.h"
+#include "batch.hpp"
 #include "csr.hpp"
 #include "hierarchy.hpp"
 
@@ -19,6 +20,8 @@ struct airg_handle {
     std::vector<uint64_t> seeds;
     std::vector<std::unique_ptr<Hier>> fwd;   // one hierarchy per segment
     std::vector<std::unique_ptr<Hier>> adj;   // A^T hierarchies (built on demand)
+    Csr top;                                  // whole canonical operator (batched handles)
+    std::unique_ptr<Batch> batch;             // batched solve operators (built on first solve)
     double setup_seconds = 0.0;
     double adjoint_setup_seconds = 0.0;
 };
@@ -200,6 +203,7 @@ airg_status airg_default_opts(airg_opts *o) {
     o->build_adjoint = 0;
     o->onepoint_weight = 0;
     o->use_graph = 0;
+    o->autotune = 0;
     o->device_bytes_cap = 0;
     return AIRG_OK;
 }
@@ -243,6 +247,7 @@ airg_status airg_setup(const airg_opts *opts, int64_t n, int64_t nnz, const int3
                 Csr S = slice_segment(A, (int32_t)h->seg[p], (int32_t)h->seg[p + 1], s);
                 h->fwd.push_back(build_hierarchy(std::move(S), *opts, h->seeds[p], s));
             }
+            h->top = std::move(A);
         }
         AIRG_HIP(hipStreamSynchronize(s));
         h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -257,7 +262,30 @@ airg_status airg_solve(airg_handle *h, int32_t nrhs, const double *d_b, double *
                        void *hip_stream, airg_solve_info *info) {
     return guarded([&] {
         AIRG_REQUIRE(h, ST_INVALID_ARG, "null handle");
-        run_solve(h, h->fwd, nrhs, d_b, d_x, rtol, max_it, (hipStream_t)hip_stream, info);
+        hipStream_t s = (hipStream_t)hip_stream;
+        bool batched = h->fwd.size() > 1 && h->opt.outer == AIRG_OUTER_FGMRES && h->opt.precond_precision == 32;
+        if (!batched) {
+            run_solve(h, h->fwd, nrhs, d_b, d_x, rtol, max_it, s, info);
+            return;
+        }
+        AIRG_REQUIRE(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8, ST_INVALID_ARG,
+                     "batched solve needs 1, 2, 4 or 8 right-hand sides");
+        AIRG_REQUIRE(d_b && d_x && rtol > 0.0 && max_it >= 0, ST_INVALID_ARG, "bad argument");
+        auto t0 = std::chrono::steady_clock::now();
+        if (!h->batch || h->batch->k != nrhs) {
+            h->batch.reset();
+            h->batch = build_batch(h->fwd, nrhs, h->opt.autotune != 0, s);
+        }
+        BatchResult r = solve_batch(*h->batch, h->top, h->seg, d_b, d_x, rtol, max_it, h->opt.fgmres_restart,
+                                    h->opt.use_graph != 0, s);
+        AIRG_HIP(hipStreamSynchronize(s));
+        if (info) {
+            info->iterations = r.iterations;
+            info->converged = r.converged;
+            info->rel_residual = r.worst;
+            info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (!r.converged) throw Error(ST_NOT_CONVERGED, "not converged within max_it");
     });
 }
 

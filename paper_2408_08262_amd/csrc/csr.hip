@@ -1,5 +1,6 @@
 // Sparse building blocks on gfx950: validation, CSR SpMV/SpMM with G lanes
 // per row, CF block extraction, row drop filter, transpose, reductions.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <tuple>
@@ -283,9 +284,83 @@ __global__ void __launch_bounds__(256) k_spmm(int32_t nr, const int32_t *__restr
     }
 }
 
+// CSR-stream for K right-hand sides (row-major n x K): the workgroup parks
+// the K products of each nonzero in LDS; persistent grid over row blocks.
+template <int K, class VT, class XT, int MODE>
+__global__ void __launch_bounds__(kStreamRows) k_spmm_stream(int32_t nr, const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const VT *__restrict__ v, const XT *__restrict__ x,
+                                                            XT *y, const XT *z) {
+    constexpr int CH = kStreamChunk / K;
+    __shared__ XT prod[CH * K];
+    int32_t nblk = (nr + kStreamRows - 1) / kStreamRows;
+    for (int32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        int32_t r0 = blk * kStreamRows;
+        int32_t r1 = r0 + kStreamRows < nr ? r0 + kStreamRows : nr;
+        int32_t row = r0 + threadIdx.x;
+        int32_t base = rp[r0], end = rp[r1];
+        int32_t mb = 0, me = 0;
+        if (row < r1) {
+            mb = rp[row];
+            me = rp[row + 1];
+        }
+        XT acc[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) acc[c] = 0;
+        for (int32_t c0 = base; c0 < end; c0 += CH) {
+            int32_t c1 = c0 + CH < end ? c0 + CH : end;
+            for (int32_t k = c0 + threadIdx.x; k < c1; k += kStreamRows) {
+                XT a = (XT)v[k];
+                const XT *xr = x + (int64_t)ci[k] * K;
+#pragma unroll
+                for (int c = 0; c < K; ++c) prod[(k - c0) * K + c] = a * xr[c];
+            }
+            __syncthreads();
+            int32_t lo = mb > c0 ? mb : c0, hi = me < c1 ? me : c1;
+            for (int32_t k = lo; k < hi; ++k) {
+#pragma unroll
+                for (int c = 0; c < K; ++c) acc[c] += prod[(k - c0) * K + c];
+            }
+            __syncthreads();
+        }
+        if (row < r1) {
+            XT *yr = y + (int64_t)row * K;
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                if (MODE == SPMV_SET) yr[c] = acc[c];
+                else if (MODE == SPMV_ZMINUS) yr[c] = z[(int64_t)row * K + c] - acc[c];
+                else yr[c] = yr[c] + acc[c];
+            }
+        }
+    }
+}
+
+// Persistent grid size: enough workgroups to fill the chip a few times over.
+static unsigned persistent_grid(int32_t nr) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    }
+    int64_t blocks = ((int64_t)nr + kStreamRows - 1) / kStreamRows;
+    int64_t cap = (int64_t)cus * 8;
+    return (unsigned)std::max<int64_t>(1, std::min(blocks, cap));
+}
+
 template <int K, class VT, class XT>
-static void spmm_k(const CsrView &A, const VT *v, const XT *x, XT *y, const XT *z, int mode, hipStream_t s) {
-    int g = lanes_for(A.nnz, A.nr);
+static void spmm_k(const CsrView &A, const VT *v, const XT *x, XT *y, const XT *z, int mode, hipStream_t s,
+                   int lanes = -1) {
+    if (lanes == 0 || (lanes < 0 && A.nr >= kStreamMinRows && (double)A.nnz <= 16.0 * (double)A.nr)) {
+        unsigned grid = persistent_grid(A.nr);
+        if (mode == SPMV_SET) k_spmm_stream<K, VT, XT, SPMV_SET><<<grid, kStreamRows, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+        else if (mode == SPMV_ZMINUS)
+            k_spmm_stream<K, VT, XT, SPMV_ZMINUS><<<grid, kStreamRows, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+        else k_spmm_stream<K, VT, XT, SPMV_ADD><<<grid, kStreamRows, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+        AIRG_LAUNCH_CHECK();
+        return;
+    }
+    int g = lanes > 0 ? lanes : lanes_for(A.nnz, A.nr);
     dispatch_group(g, [&]<int G>() {
         unsigned grid = grid_for((int64_t)A.nr * G, 256);
         if (mode == SPMV_SET) k_spmm<G, K, VT, XT, SPMV_SET><<<grid, 256, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
@@ -297,24 +372,25 @@ static void spmm_k(const CsrView &A, const VT *v, const XT *x, XT *y, const XT *
 }
 
 template <class VT, class XT>
-static void spmm_t(const CsrView &A, const VT *v, int k, const XT *x, XT *y, const XT *z, int mode, hipStream_t s) {
+static void spmm_t(const CsrView &A, const VT *v, int k, const XT *x, XT *y, const XT *z, int mode, hipStream_t s,
+                   int lanes) {
     if (A.nr == 0) return;
     switch (k) {
-    case 1: spmm_k<1>(A, v, x, y, z, mode, s); break;
-    case 2: spmm_k<2>(A, v, x, y, z, mode, s); break;
-    case 3: spmm_k<3>(A, v, x, y, z, mode, s); break;
-    case 4: spmm_k<4>(A, v, x, y, z, mode, s); break;
-    case 8: spmm_k<8>(A, v, x, y, z, mode, s); break;
+    case 1: spmm_k<1>(A, v, x, y, z, mode, s, lanes); break;
+    case 2: spmm_k<2>(A, v, x, y, z, mode, s, lanes); break;
+    case 3: spmm_k<3>(A, v, x, y, z, mode, s, lanes); break;
+    case 4: spmm_k<4>(A, v, x, y, z, mode, s, lanes); break;
+    case 8: spmm_k<8>(A, v, x, y, z, mode, s, lanes); break;
     default: throw Error(ST_INVALID_ARG, "number of right-hand sides must be 1, 2, 3, 4 or 8");
     }
 }
 
-void spmm(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s) {
-    spmm_t<double, double>(A, A.v, k, x, y, z, mode, s);
+void spmm(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s, int lanes) {
+    spmm_t<double, double>(A, A.v, k, x, y, z, mode, s, lanes);
 }
-void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, int mode, hipStream_t s) {
+void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, int mode, hipStream_t s, int lanes) {
     AIRG_REQUIRE(A.vf != nullptr, ST_INVALID_ARG, "matrix has no single-precision copy");
-    spmm_t<float, float>(A, A.vf, k, x, y, z, mode, s);
+    spmm_t<float, float>(A, A.vf, k, x, y, z, mode, s, lanes);
 }
 
 // ------------------------------------------------------------- CF ranks ---

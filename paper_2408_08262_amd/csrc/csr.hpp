@@ -23,9 +23,13 @@ void spmv32(const CsrView &A, const float *x, float *y, const float *z, int mode
 void spmv_top(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s);
 void top_timing(bool enable);
 void top_timing_read(int64_t *launches, double *bytes, double *seconds);
-// Same with k right-hand sides stored row-major (n x k).
-void spmm(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s);
-void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, int mode, hipStream_t s);
+// Same with k right-hand sides stored row-major (n x k).  lanes: -1 picks
+// the kernel from the row statistics, 0 forces the persistent CSR-stream
+// kernel, G > 0 forces G lanes per row.
+void spmm(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s,
+          int lanes = -1);
+void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, int mode, hipStream_t s,
+            int lanes = -1);
 
 // rank[i] = position of i among the points carrying its own marker
 // (F rank for F points, C rank for C points); returns (nF, nC).

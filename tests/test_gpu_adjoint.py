@@ -2,7 +2,7 @@
 the per-cell removal coefficient, through the hand-written AIRG adjoint.
 
 Checked against (1) the exact gradient from dense solves on a 16 x 16
-instance (1,536 unknowns) and (2) central finite differences of the loss
+instance (1,536 unknowns) and (2) central finite differences (relative steps 1e-4 in sigma, 1e-3 in s) of the loss
 computed with the exact sweep solution, plus the adjoint solve itself against
 the reverse sweep.
 """
@@ -59,7 +59,7 @@ def gpu_grad(prob, m, sigma, src):
     mask = torch.as_tensor(m["patch_mask"], device="cuda")
     L = (u[mask] ** 2).sum()
     L.backward()
-    return float(L), s.grad.cpu().numpy(), g.grad.cpu().numpy(), u.detach().cpu().numpy()
+    return float(L.detach()), s.grad.cpu().numpy(), g.grad.cpu().numpy(), u.detach().cpu().numpy()
 
 
 def test_forward_matches_sweep_and_assembly():
@@ -103,7 +103,7 @@ def test_gradient_matches_central_differences(N):
     pick_s = np.concatenate([rng.choice(bigs, kk // 2, replace=False), rng.choice(len(src), kk - kk // 2)])
     scale_sig = np.abs(gsig).max()
     for K in pick_sig:
-        h = 1e-6 * sigma[K]
+        h = 1e-4 * sigma[K]     # large enough that the loss difference clears its rounding
         sp_, sm_ = sigma.copy(), sigma.copy()
         sp_[K] += h
         sm_[K] -= h
@@ -112,7 +112,7 @@ def test_gradient_matches_central_differences(N):
         assert abs(fd - gsig[K]) <= 5e-5 * max(abs(fd), 1e-3 * scale_sig), (K, fd, gsig[K])
     scale_s = np.abs(gs).max()
     for i in pick_s:
-        h = 1e-6 * max(abs(src[i]), 1e-3)
+        h = 1e-3 * max(abs(src[i]), 1e-3)
         sp_, sm_ = src.copy(), src.copy()
         sp_[i] += h
         sm_[i] -= h

@@ -143,6 +143,29 @@ def adjoint(N=256, theta=1.1, patch=32):
                     "mass": M, "patch_mask": mask, "patch_origin": p0, "theta": theta})
 
 
+def concat(problems):
+    """Block-diagonal concatenation of independent problems.
+
+    Returns (rowptr, col, val, b, offsets, seeds): one CSR with the problems'
+    rows stacked in order, b stacked the same way ((n,) or (n, k)), segment row
+    offsets (len(problems) + 1) and the per-problem AIRG seeds.
+    """
+    offs = np.zeros(len(problems) + 1, dtype=np.int64)
+    for i, P in enumerate(problems):
+        offs[i + 1] = offs[i] + P.n
+    nz = np.zeros(len(problems) + 1, dtype=np.int64)
+    for i, P in enumerate(problems):
+        nz[i + 1] = nz[i] + P.nnz
+    rp = np.concatenate([[0]] + [P.rowptr[1:].astype(np.int64) + nz[i] for i, P in enumerate(problems)])
+    ci = np.concatenate([P.col.astype(np.int64) + offs[i] for i, P in enumerate(problems)])
+    val = np.concatenate([P.val for P in problems])
+    b = np.concatenate([P.b for P in problems], axis=0)
+    if rp[-1] >= 2 ** 31 or offs[-1] >= 2 ** 31:
+        raise ValueError("batch too large for int32 indices")
+    return (rp.astype(np.int32), ci.astype(np.int32), val, b, offs,
+            np.array([P.seed for P in problems], dtype=np.uint64))
+
+
 def by_name(name, **kw):
     return {"p0_square": p0_square, "dg_square": dg_square, "p0_cube": p0_cube,
             "batch": batch, "adjoint": adjoint}[name](**kw)
