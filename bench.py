@@ -30,30 +30,52 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "AIRG solve time to 1e-10 rel resid + setup s, FP32-precond/batched vs FP64"
 
 
+WORKLOADS = ("dg_square_512", "p0_cube_128", "batch48")
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--size", type=int, default=512, help="squares per side of the DG-P1 workload")
+    p.add_argument("--workload", default="dg_square_512", choices=WORKLOADS)
+    p.add_argument("--size", type=int, default=None, help="override the side of the square/cube workload")
+    p.add_argument("--truncate", type=int, default=None, help="truncate_n (p0_cube default 65536)")
     p.add_argument("--rtol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison form")
     return p.parse_args()
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no sharding, no collectives); "
-              "--gpus %d is not supported" % a.gpus, file=sys.stderr)
-        return 2
-    import numpy as np
-    import torch
-    from paper_2408_08262_amd import airg
-    from workloads import dg_square
+def roofline_from_timing(airg):
+    launches, tbytes, tsec = airg.airg_kernel_timing_read()
+    airg.airg_kernel_timing(False)
+    if launches == 0:
+        return None
+    avg = tsec / launches
+    bpl = tbytes / launches
+    ach = bpl / avg / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_spmv*<double, double, 0, 1> (finest-operator y = A x, FGMRES Arnoldi product)",
+            "launches": launches, "bytes_per_launch": int(bpl), "avg_launch_us": round(avg * 1e6, 2)}
 
-    P = dg_square(a.size)
+
+def single(a, airg, torch):
+    """One problem: setup + solve per step."""
+    from workloads import dg_square, p0_cube
+    if a.workload == "dg_square_512":
+        N = a.size or 512
+        P = dg_square(N)
+        desc = ("dg_square_%d: DG-P1 upwind advection, %dx%d jittered triangulation, n=%d, nnz=%d, theta=1.1, "
+                "sigma {1e-4,1} 16x16 block checkerboard" % (N, N, N, P.n, P.nnz))
+        trunc = a.truncate or 0
+    else:
+        N = a.size or 128
+        P = p0_cube(N)
+        trunc = a.truncate if a.truncate is not None else 65536
+        desc = ("p0_cube_%d: P0 upwind advection, %d^3 cubes x 6 Kuhn tetrahedra, n=%d, nnz=%d, "
+                "Omega=(0.5,0.3,0.81)/|.|, sigma=1e-4, truncate_n=%d" % (N, N, P.n, P.nnz, trunc))
     A = airg.to_device(P.rowptr, P.col, P.val)
     b = torch.as_tensor(P.b, device="cuda")
     torch.cuda.synchronize()
@@ -65,9 +87,8 @@ def main():
         del h
         return info, st
 
-    opts32 = airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32)
-    opts64 = airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64)
-
+    opts32 = airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, truncate_n=trunc)
+    opts64 = airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64, truncate_n=trunc)
     for _ in range(a.warmup):
         step(opts32)
     torch.cuda.synchronize()
@@ -77,11 +98,9 @@ def main():
     runs = [step(opts32) for _ in range(a.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    launches, tbytes, tsec = airg.airg_kernel_timing_read()
-    airg.airg_kernel_timing(False)
-    sec_per_step = (t1 - t0) / a.steps
+    roof = roofline_from_timing(airg)
+    sec = (t1 - t0) / a.steps
     info32, st32 = runs[-1]
-
     fp64 = None
     if not a.no_fp64:
         step(opts64)
@@ -91,63 +110,101 @@ def main():
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         i64, s64 = r64[-1]
-        fp64 = {"seconds_per_step": (t3 - t2) / a.steps, "setup_s": s64["setup_seconds"],
-                "solve_s": i64["seconds"], "iterations": i64["iterations"], "rel_residual": i64["rel_residual"],
-                "levels": s64["levels"], "form": "Richardson, FP64 V-cycle"}
-
-    roof = None
-    if launches > 0:
-        avg = tsec / launches
-        bpl = tbytes / launches
-        ach = bpl / avg / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_spmv<*, double, double, 0, 1> (finest-operator y = A x, FGMRES Arnoldi product)",
-                "launches": launches, "bytes_per_launch": int(bpl), "avg_launch_us": round(avg * 1e6, 2)}
-
+        fp64 = {"seconds_per_step": round((t3 - t2) / a.steps, 4), "setup_s": round(s64["setup_seconds"], 4),
+                "solve_s": round(i64["seconds"], 4), "iterations": i64["iterations"],
+                "rel_residual": i64["rel_residual"], "levels": s64["levels"], "form": "Richardson, FP64 V-cycle"}
     cpu = None
     if not a.no_cpu_baseline:
         import oracle as O
         c0 = time.perf_counter()
-        H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed))
+        H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, truncate_n=trunc))
         c1 = time.perf_counter()
         _, its, rr = H.richardson(P.b, a.rtol, 300)
         c2 = time.perf_counter()
         cpu = {"value": round(c2 - c0, 3), "unit": "s", "cores": 1, "kind": "oracle",
                "sample": "whole workload: oracle setup (%.2f s) + FP64 Richardson to %.0e (%.2f s, %d its), "
                          "single thread" % (c1 - c0, a.rtol, c2 - c1, its)}
+    extra = {"setup_s": round(st32["setup_seconds"], 4), "solve_s": round(info32["seconds"], 4),
+             "iterations": info32["iterations"], "rel_residual": info32["rel_residual"], "levels": st32["levels"],
+             "complexity": {"grid": round(st32["grid_complexity"], 3),
+                            "operator": round(st32["operator_complexity"], 3),
+                            "storage": round(st32["storage_complexity"], 3)},
+             "phase_seconds": {k: round(v, 4) for k, v in st32["phase_seconds"].items()},
+             "vcycle_bytes_fp32": st32["vcycle_bytes_fp32"], "fp64_comparison": fp64}
+    cfg = {"workload": desc, "form": "FGMRES(30) FP64 outer + FP32 AIRG V-cycle", "rtol": a.rtol,
+           "parallelism": "single GPU"}
+    return sec, cfg, "f64 (f32 V-cycle)", roof, cpu, extra
 
-    out = {
-        "metric": METRIC,
-        "value": round(sec_per_step, 4),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(sec_per_step * 1e3, 2),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64 (f32 V-cycle)",
-        "data": "synthetic",
-        "config": {"workload": "dg_square_%d: DG-P1 upwind advection, %dx%d jittered triangulation, n=%d, nnz=%d, "
-                               "theta=1.1, sigma {1e-4,1} 16x16 block checkerboard" % (a.size, a.size, a.size,
-                                                                                       P.n, P.nnz),
-                   "form": "FGMRES(30) FP64 outer + FP32 AIRG V-cycle", "rtol": a.rtol,
-                   "parallelism": "single GPU"},
-        "setup_s": round(st32["setup_seconds"], 4),
-        "solve_s": round(info32["seconds"], 4),
-        "iterations": info32["iterations"],
-        "rel_residual": info32["rel_residual"],
-        "levels": st32["levels"],
-        "complexity": {"grid": round(st32["grid_complexity"], 3), "operator": round(st32["operator_complexity"], 3),
-                       "storage": round(st32["storage_complexity"], 3)},
-        "phase_seconds": {k: round(v, 4) for k, v in st32["phase_seconds"].items()},
-        "vcycle_bytes_fp32": st32["vcycle_bytes_fp32"],
-        "fp64_comparison": fp64,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
+
+def batched(a, airg, torch):
+    """48 independent DG-P1 problems x 4 rhs: batched FP32 form vs sequential FP64."""
+    from workloads import batch as batch_problems, concat
+    probs = batch_problems()
+    rp, ci, val, b, offs, seeds = concat(probs)
+    A = airg.to_device(rp, ci, val)
+    B = torch.as_tensor(b, device="cuda")
+    optsb = airg.default_opts(outer=airg.OUTER_FGMRES, precond_precision=32, use_graph=1, autotune=1)
+    opts64 = airg.default_opts(outer=airg.OUTER_RICHARDSON, precond_precision=64)
+
+    def step(opts):
+        h = airg.airg_setup(*A, opts, seg_offsets=offs, seg_seeds=seeds)
+        x, info = airg.airg_solve(h, B, rtol=a.rtol, max_it=300)
+        st = airg.airg_get_stats(h)
+        del h
+        return info, st
+
+    for _ in range(a.warmup):
+        step(optsb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(optsb) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / a.steps
+    infob, stb = runs[-1]
+    fp64 = None
+    if not a.no_fp64:
+        step(opts64)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r64 = [step(opts64) for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        i64, s64 = r64[-1]
+        fp64 = {"seconds_per_step": round((t3 - t2) / a.steps, 4), "setup_s": round(s64["setup_seconds"], 4),
+                "solve_s": round(i64["seconds"], 4), "iterations": i64["iterations"],
+                "rel_residual": i64["rel_residual"],
+                "form": "48 segments solved one after another, 4 rhs one after another, FP64 Richardson"}
+    n = int(offs[-1])
+    desc = ("batch48: 48 DG-P1 upwind problems, sides U{64..384}, theta ~ U(0, 2 pi), sigma=1e-3, 4 rhs each; "
+            "n=%d, nnz=%d" % (n, int(rp[-1])))
+    extra = {"setup_s": round(stb["setup_seconds"], 4), "solve_s": round(infob["seconds"], 4),
+             "iterations": infob["iterations"], "rel_residual": infob["rel_residual"], "levels": stb["levels"],
+             "fp64_comparison": fp64}
+    cfg = {"workload": desc, "form": "batched FGMRES(30) FP64 per (segment, rhs) + batched FP32 V-cycle, "
+                                     "one SpMM launch per stage, HIP graph, autotuned kernels",
+           "rtol": a.rtol, "parallelism": "single GPU"}
+    return sec, cfg, "f64 (f32 V-cycle)", None, None, extra
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no sharding, no collectives); "
+              "--gpus %d is not supported" % a.gpus, file=sys.stderr)
+        return 2
+    import torch
+    from paper_2408_08262_amd import airg
+    if a.workload == "batch48":
+        sec, cfg, dtype, roof, cpu, extra = batched(a, airg, torch)
+    else:
+        sec, cfg, dtype, roof, cpu, extra = single(a, airg, torch)
+    out = {"metric": METRIC, "value": round(sec, 4), "unit": "s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": round(sec * 1e3, 2), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg}
+    out.update(extra)
+    out["roofline"] = roof
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 
