@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--rtol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison form")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device copy of MIB MiB (x5), the reference for HBM byte counters")
     return p.parse_args()
 
 
@@ -187,6 +189,25 @@ def batched(a, airg, torch):
     return sec, cfg, "f64 (f32 V-cycle)", None, None, extra
 
 
+def copy_calibration(mib, torch):
+    """y = 1.0 * x over mib MiB of float32, five times: reads and writes mib MiB per launch."""
+    n = mib * (1 << 20) // 4
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)
+    ev[1].record()
+    torch.cuda.synchronize()
+    sec = ev[0].elapsed_time(ev[1]) / 5e3
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4, "launches": 5,
+                                           "avg_launch_us": round(sec * 1e6, 2),
+                                           "GBps": round(2 * n * 4 / sec / 1e9, 1)}}), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -194,6 +215,8 @@ def main():
               "--gpus %d is not supported" % a.gpus, file=sys.stderr)
         return 2
     import torch
+    if a.copy_calibration:
+        return copy_calibration(a.copy_calibration, torch)
     from paper_2408_08262_amd import airg
     if a.workload == "batch48":
         sec, cfg, dtype, roof, cpu, extra = batched(a, airg, torch)

@@ -127,6 +127,22 @@ inline unsigned grid_for(int64_t work, int per_block) {
     return (unsigned)g;
 }
 
+// Workgroups are handed to the chip's 8 XCDs round-robin by id, and each XCD
+// has its own L2.  xcd_tile renumbers launch ids so that every XCD receives
+// runs of kXcdRun consecutive tiles: neighbouring tiles, whose gathers touch
+// the same lines of x, then share one L2.  The launch must cover
+// xcd_grid(tiles) ids; ids mapped past the last tile do nothing.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 16;
+__device__ inline int32_t xcd_tile(int32_t id) {
+    int32_t x = id % kXcds, r = id / kXcds;
+    return (r / kXcdRun) * (kXcds * kXcdRun) + x * kXcdRun + r % kXcdRun;
+}
+__host__ __device__ inline int64_t xcd_grid(int64_t tiles) {
+    const int64_t g = (int64_t)kXcds * kXcdRun;
+    return (tiles + g - 1) / g * g;
+}
+
 // Group width (lanes per row) for row-parallel kernels: the power of two
 // covering the mean row length, between 1 and 64.
 inline int lanes_for(int64_t nnz, int64_t rows) {

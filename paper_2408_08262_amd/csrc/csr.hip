@@ -121,12 +121,15 @@ __global__ void __launch_bounds__(256) k_spmv(int32_t nr, const int32_t *__restr
     }
 }
 
-// Rows of up to ~16 entries: CSR-stream.  A workgroup owns 256 consecutive
-// rows; its threads stream the rows' nonzeros (values, columns) coalesced in
-// chunks of kStreamChunk, park the products in LDS, and then each thread sums
-// its own row from LDS in ascending order.
+// Rows of up to ~16 entries: CSR-stream.  A workgroup owns kStreamRows
+// consecutive rows; its threads stream the rows' nonzeros (values, columns)
+// coalesced in chunks of kStreamChunk, park the products in LDS, and then each
+// thread sums its own row from LDS in ascending order.  Each thread issues
+// all of its column and value loads of a chunk before any gather of x, so a
+// chunk costs two dependent trips to memory rather than two per entry.
 constexpr int kStreamRows = 256;
-constexpr int kStreamChunk = 2048;
+constexpr int kStreamChunk = 1536;
+constexpr int kStreamUnroll = kStreamChunk / kStreamRows;
 constexpr int32_t kStreamMinRows = 32768;   // below this the lane-group kernel has less latency
 
 template <class VT, class XT, int MODE, int TAG>
@@ -135,7 +138,9 @@ __global__ void __launch_bounds__(kStreamRows) k_spmv_stream(int32_t nr, const i
                                                             const VT *__restrict__ v, const XT *__restrict__ x,
                                                             XT *y, const XT *z) {
     __shared__ XT prod[kStreamChunk];
-    int32_t r0 = blockIdx.x * kStreamRows;
+    int32_t tile = xcd_tile(blockIdx.x);
+    int32_t r0 = tile * kStreamRows;
+    if (r0 >= nr) return;
     int32_t r1 = r0 + kStreamRows < nr ? r0 + kStreamRows : nr;
     int32_t row = r0 + threadIdx.x;
     int32_t base = rp[r0], end = rp[r1];
@@ -147,7 +152,25 @@ __global__ void __launch_bounds__(kStreamRows) k_spmv_stream(int32_t nr, const i
     XT acc = 0;
     for (int32_t c0 = base; c0 < end; c0 += kStreamChunk) {
         int32_t c1 = c0 + kStreamChunk < end ? c0 + kStreamChunk : end;
-        for (int32_t k = c0 + threadIdx.x; k < c1; k += kStreamRows) prod[k - c0] = (XT)v[k] * x[ci[k]];
+        int32_t cc[kStreamUnroll];
+        XT vv[kStreamUnroll], xx[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            int32_t k = c0 + u * kStreamRows + threadIdx.x;
+            cc[u] = 0;
+            vv[u] = 0;
+            if (k < c1) {
+                cc[u] = ci[k];
+                vv[u] = (XT)v[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) xx[u] = c0 + u * kStreamRows + (int32_t)threadIdx.x < c1 ? x[cc[u]] : 0;
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            int32_t k = c0 + u * kStreamRows + threadIdx.x;
+            if (k < c1) prod[k - c0] = vv[u] * xx[u];
+        }
         __syncthreads();
         int32_t lo = mb > c0 ? mb : c0, hi = me < c1 ? me : c1;
         for (int32_t k = lo; k < hi; ++k) acc += prod[k - c0];
@@ -165,7 +188,7 @@ static void spmv_t(int32_t nr, int64_t nnz, const int32_t *rp, const int32_t *ci
                    const XT *z, int mode, hipStream_t s, int lanes) {
     if (nr == 0) return;
     if (lanes == 0 && nr >= kStreamMinRows && (double)nnz <= 16.0 * (double)nr) {
-        unsigned grid = grid_for(nr, kStreamRows);
+        unsigned grid = grid_for(xcd_grid((nr + kStreamRows - 1) / kStreamRows), 1);
         if (mode == SPMV_SET) k_spmv_stream<VT, XT, SPMV_SET, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
         else if (mode == SPMV_ZMINUS)
             k_spmv_stream<VT, XT, SPMV_ZMINUS, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
@@ -285,17 +308,22 @@ __global__ void __launch_bounds__(256) k_spmm(int32_t nr, const int32_t *__restr
 }
 
 // CSR-stream for K right-hand sides (row-major n x K): the workgroup parks
-// the K products of each nonzero in LDS; persistent grid over row blocks.
+// the K products of each nonzero in LDS.  Persistent: the launch walks the
+// tiles in xcd_tile order, gridDim.x (a multiple of the XCD count) apart, so
+// each workgroup stays on the tiles of its own XCD.
 template <int K, class VT, class XT, int MODE>
 __global__ void __launch_bounds__(kStreamRows) k_spmm_stream(int32_t nr, const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ ci,
                                                             const VT *__restrict__ v, const XT *__restrict__ x,
                                                             XT *y, const XT *z) {
-    constexpr int CH = kStreamChunk / K;
+    constexpr int CH = 2048 / K;
+    constexpr int U = (CH + kStreamRows - 1) / kStreamRows;
     __shared__ XT prod[CH * K];
-    int32_t nblk = (nr + kStreamRows - 1) / kStreamRows;
-    for (int32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        int32_t r0 = blk * kStreamRows;
+    int32_t ntiles = (nr + kStreamRows - 1) / kStreamRows;
+    int32_t nid = (int32_t)xcd_grid(ntiles);
+    for (int32_t id = blockIdx.x; id < nid; id += gridDim.x) {
+        int32_t r0 = xcd_tile(id) * kStreamRows;
+        if (r0 >= nr) continue;   // uniform across the workgroup
         int32_t r1 = r0 + kStreamRows < nr ? r0 + kStreamRows : nr;
         int32_t row = r0 + threadIdx.x;
         int32_t base = rp[r0], end = rp[r1];
@@ -309,11 +337,26 @@ __global__ void __launch_bounds__(kStreamRows) k_spmm_stream(int32_t nr, const i
         for (int c = 0; c < K; ++c) acc[c] = 0;
         for (int32_t c0 = base; c0 < end; c0 += CH) {
             int32_t c1 = c0 + CH < end ? c0 + CH : end;
-            for (int32_t k = c0 + threadIdx.x; k < c1; k += kStreamRows) {
-                XT a = (XT)v[k];
-                const XT *xr = x + (int64_t)ci[k] * K;
+            int32_t cc[U];
+            XT vv[U];
 #pragma unroll
-                for (int c = 0; c < K; ++c) prod[(k - c0) * K + c] = a * xr[c];
+            for (int u = 0; u < U; ++u) {
+                int32_t k = c0 + u * kStreamRows + threadIdx.x;
+                cc[u] = 0;
+                vv[u] = 0;
+                if (k < c1 && u * kStreamRows + (int)threadIdx.x < CH) {
+                    cc[u] = ci[k];
+                    vv[u] = (XT)v[k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int32_t k = c0 + u * kStreamRows + threadIdx.x;
+                if (k < c1 && u * kStreamRows + (int)threadIdx.x < CH) {
+                    const XT *xr = x + (int64_t)cc[u] * K;
+#pragma unroll
+                    for (int c = 0; c < K; ++c) prod[(k - c0) * K + c] = vv[u] * xr[c];
+                }
             }
             __syncthreads();
             int32_t lo = mb > c0 ? mb : c0, hi = me < c1 ? me : c1;
@@ -335,7 +378,8 @@ __global__ void __launch_bounds__(kStreamRows) k_spmm_stream(int32_t nr, const i
     }
 }
 
-// Persistent grid size: enough workgroups to fill the chip a few times over.
+// Persistent grid size: enough workgroups to fill the chip a few times over,
+// a multiple of the XCD count, never more than there are tile ids.
 static unsigned persistent_grid(int32_t nr) {
     static int cus = 0;
     if (cus == 0) {
@@ -343,9 +387,9 @@ static unsigned persistent_grid(int32_t nr) {
         if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 256;
     }
-    int64_t blocks = ((int64_t)nr + kStreamRows - 1) / kStreamRows;
-    int64_t cap = (int64_t)cus * 8;
-    return (unsigned)std::max<int64_t>(1, std::min(blocks, cap));
+    int64_t ids = xcd_grid(((int64_t)nr + kStreamRows - 1) / kStreamRows);
+    int64_t cap = std::max<int64_t>(kXcds, (int64_t)cus * 8 / kXcds * kXcds);
+    return (unsigned)std::min(ids, cap);
 }
 
 template <int K, class VT, class XT>

@@ -216,41 +216,67 @@ __global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict
     if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = (int32_t)bsum[nb];
 }
 
-// Small inputs: one workgroup scans everything (one launch instead of three).
+// Small inputs: one workgroup scans everything (one launch instead of three),
+// a tile of kSmallScanTile entries at a time: coalesced loads into LDS, each
+// thread scans kSmallScanItems consecutive entries there, a workgroup scan of
+// the per-thread sums, coalesced stores, and a carry into the next tile.
 constexpr int kSmallScanThreads = 1024;
+constexpr int kSmallScanItems = 8;
+constexpr int kSmallScanTile = kSmallScanThreads * kSmallScanItems;
 constexpr int64_t kSmallScan = 65536;
+
+__device__ inline int small_scan_slot(int p) { return p + (p >> 5); }   // pads out LDS bank conflicts
 
 __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(const int32_t *__restrict__ in,
                                                                   int32_t *__restrict__ out, int64_t n,
                                                                   int64_t *__restrict__ total) {
+    __shared__ int32_t buf[kSmallScanTile + kSmallScanTile / 32];
     __shared__ int64_t wsum[kSmallScanThreads / kWave];
-    int64_t per = (n + kSmallScanThreads - 1) / kSmallScanThreads;
-    int64_t lo = (int64_t)threadIdx.x * per;
-    int64_t hi = lo + per < n ? lo + per : n;
-    int64_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += in[i];
-    int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    int64_t x = s;
-    for (int o = 1; o < kWave; o <<= 1) {
-        int64_t y = __shfl_up(x, o, kWave);
-        if (lane >= o) x += y;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    int64_t carry = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += kSmallScanTile) {
+#pragma unroll
+        for (int j = 0; j < kSmallScanItems; ++j) {
+            int p = j * kSmallScanThreads + tid;
+            buf[small_scan_slot(p)] = t0 + p < n ? in[t0 + p] : 0;
+        }
+        __syncthreads();
+        int32_t v[kSmallScanItems];
+        int64_t s = 0;
+#pragma unroll
+        for (int u = 0; u < kSmallScanItems; ++u) {
+            v[u] = buf[small_scan_slot(tid * kSmallScanItems + u)];
+            s += v[u];
+        }
+        int64_t x = s;
+        for (int o = 1; o < kWave; o <<= 1) {
+            int64_t y = __shfl_up(x, o, kWave);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) wsum[wid] = x;
+        __syncthreads();
+        int64_t off = carry + x - s, tot = 0;
+        for (int w = 0; w < kSmallScanThreads / kWave; ++w) {
+            if (w < wid) off += wsum[w];
+            tot += wsum[w];
+        }
+#pragma unroll
+        for (int u = 0; u < kSmallScanItems; ++u) {
+            buf[small_scan_slot(tid * kSmallScanItems + u)] = (int32_t)off;
+            off += v[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSmallScanItems; ++j) {
+            int p = j * kSmallScanThreads + tid;
+            if (t0 + p < n) out[t0 + p] = buf[small_scan_slot(p)];
+        }
+        carry += tot;
+        __syncthreads();
     }
-    if (lane == kWave - 1) wsum[wid] = x;
-    __syncthreads();
-    int64_t off = 0, tot = 0;
-    for (int w = 0; w < kSmallScanThreads / kWave; ++w) {
-        if (w < wid) off += wsum[w];
-        tot += wsum[w];
-    }
-    off += x - s;
-    for (int64_t i = lo; i < hi; ++i) {
-        int32_t v = in[i];
-        out[i] = (int32_t)off;
-        off += v;
-    }
-    if (threadIdx.x == 0) {
-        out[n] = (int32_t)tot;
-        *total = tot;
+    if (tid == 0) {
+        out[n] = (int32_t)carry;
+        *total = carry;
     }
 }
 
