@@ -282,12 +282,6 @@ std::unique_ptr<Batch> build_batch(std::vector<std::unique_ptr<Hier>> &segs, int
             BL.AT = place(dAT, BL.nT, BL.nT, s);
             BL.AinvT = place(dAinvT, BL.nT, BL.nT, s);
         }
-        BL.g.alloc((size_t)nl * k, s);
-        BL.e.alloc((size_t)nl * k, s);
-        BL.t.alloc((size_t)nl * k, s);
-        fill_zero(BL.g.p, BL.g.bytes(), s);
-        fill_zero(BL.e.p, BL.e.bytes(), s);
-        fill_zero(BL.t.p, BL.t.bytes(), s);
     }
     // natural rows -> level-0 positions
     int64_t n = 0;
@@ -301,8 +295,25 @@ std::unique_ptr<Batch> build_batch(std::vector<std::unique_ptr<Hier>> &segs, int
         AIRG_LAUNCH_CHECK();
         off += L.n;
     }
-    B->g0.alloc((size_t)n * k, s);
-    B->e0.alloc((size_t)n * k, s);
+    finish_batch(*B, tune, s);
+    return B;
+}
+
+void finish_batch(Batch &Bt, bool tune, hipStream_t s) {
+    Batch *B = &Bt;
+    const int k = B->k;
+    for (auto &lp : B->lv) {
+        BatchLevel &BL = *lp;
+        int32_t nl = BL.n();
+        BL.g.alloc((size_t)nl * k, s);
+        BL.e.alloc((size_t)nl * k, s);
+        BL.t.alloc((size_t)nl * k, s);
+        fill_zero(BL.g.p, BL.g.bytes(), s);
+        fill_zero(BL.e.p, BL.e.bytes(), s);
+        fill_zero(BL.t.p, BL.t.bytes(), s);
+    }
+    B->g0.alloc((size_t)B->n * k, s);
+    B->e0.alloc((size_t)B->n * k, s);
     fill_zero(B->g0.p, B->g0.bytes(), s);
     fill_zero(B->e0.p, B->e0.bytes(), s);
     if (tune) {
@@ -326,7 +337,6 @@ std::unique_ptr<Batch> build_batch(std::vector<std::unique_ptr<Hier>> &segs, int
         }
     }
     AIRG_HIP(hipStreamSynchronize(s));
-    return B;
 }
 
 // --------------------------------------------------------------- V-cycle --

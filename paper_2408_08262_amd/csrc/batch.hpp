@@ -41,6 +41,9 @@ struct Batch {
 // Builds the batch operators from per-segment hierarchies for k right-hand
 // sides; tune runs the autotuner on every batch operator.
 std::unique_ptr<Batch> build_batch(std::vector<std::unique_ptr<Hier>> &segs, int k, bool tune, hipStream_t s);
+// Work vectors (zeroed) and, when tune is set, the autotuner over every batch
+// operator; lv, k, n and perm0 must be in place.
+void finish_batch(Batch &B, bool tune, hipStream_t s);
 
 struct BatchResult {
     int iterations = 0;

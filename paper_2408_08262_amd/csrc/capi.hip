@@ -10,6 +10,7 @@
 #include "batch.hpp"
 #include "csr.hpp"
 #include "hierarchy.hpp"
+#include "segmented.hpp"
 
 using namespace airg;
 
@@ -18,9 +19,10 @@ struct airg_handle {
     int64_t n = 0;
     std::vector<int64_t> seg;                 // nseg + 1 row offsets
     std::vector<uint64_t> seeds;
-    std::vector<std::unique_ptr<Hier>> fwd;   // one hierarchy per segment
+    std::vector<std::unique_ptr<Hier>> fwd;   // one hierarchy per segment (single and sequential forms)
+    std::unique_ptr<SegHier> segh;            // all segments in one batch hierarchy (batched form)
     std::vector<std::unique_ptr<Hier>> adj;   // A^T hierarchies (built on demand)
-    Csr top;                                  // whole canonical operator (batched handles)
+    Csr top;                                  // whole canonical operator (per-segment batched handles)
     std::unique_ptr<Batch> batch;             // batched solve operators (built on first solve)
     double setup_seconds = 0.0;
     double adjoint_setup_seconds = 0.0;
@@ -122,8 +124,14 @@ void strided_copy(const double *src, int64_t ss, double *dst, int64_t ds, int64_
 void build_adjoint(airg_handle *h, hipStream_t s) {
     if (!h->adj.empty()) return;
     auto t0 = std::chrono::steady_clock::now();
-    for (size_t p = 0; p < h->fwd.size(); ++p) {
-        Csr T = transpose(view(h->fwd[p]->L(0).A), s);
+    for (size_t p = 0; p + 1 < h->seg.size(); ++p) {
+        Csr T;
+        if (h->segh) {
+            Csr S = slice_segment(h->segh->lv[0]->A, (int32_t)h->seg[p], (int32_t)h->seg[p + 1], s);
+            T = transpose(view(S), s);
+        } else {
+            T = transpose(view(h->fwd[p]->L(0).A), s);
+        }
         h->adj.push_back(build_hierarchy(std::move(T), h->opt, h->seeds[p], s));
     }
     AIRG_HIP(hipStreamSynchronize(s));
@@ -240,8 +248,13 @@ airg_status airg_setup(const airg_opts *opts, int64_t n, int64_t nnz, const int3
         h->seeds.resize(ns);
         for (int p = 0; p < ns; ++p) h->seeds[p] = h_seg_seeds ? h_seg_seeds[p] : opts->seed + (uint64_t)p;
         Csr A = canonical_copy((int32_t)n, nnz, d_rowptr, d_col, d_val, s);
+        bool batched = ns > 1 && opts->outer == AIRG_OUTER_FGMRES && opts->precond_precision == 32 &&
+                       segmented_supported(*opts);
         if (ns == 1) {
             h->fwd.push_back(build_hierarchy(std::move(A), *opts, h->seeds[0], s));
+        } else if (batched) {
+            check_segments(A, h->seg, s);
+            h->segh = build_segmented(std::move(A), h->seg, h->seeds, *opts, s);
         } else {
             for (int p = 0; p < ns; ++p) {
                 Csr S = slice_segment(A, (int32_t)h->seg[p], (int32_t)h->seg[p + 1], s);
@@ -263,7 +276,8 @@ airg_status airg_solve(airg_handle *h, int32_t nrhs, const double *d_b, double *
     return guarded([&] {
         AIRG_REQUIRE(h, ST_INVALID_ARG, "null handle");
         hipStream_t s = (hipStream_t)hip_stream;
-        bool batched = h->fwd.size() > 1 && h->opt.outer == AIRG_OUTER_FGMRES && h->opt.precond_precision == 32;
+        bool batched = h->segh ||
+                       (h->fwd.size() > 1 && h->opt.outer == AIRG_OUTER_FGMRES && h->opt.precond_precision == 32);
         if (!batched) {
             run_solve(h, h->fwd, nrhs, d_b, d_x, rtol, max_it, s, info);
             return;
@@ -274,9 +288,11 @@ airg_status airg_solve(airg_handle *h, int32_t nrhs, const double *d_b, double *
         auto t0 = std::chrono::steady_clock::now();
         if (!h->batch || h->batch->k != nrhs) {
             h->batch.reset();
-            h->batch = build_batch(h->fwd, nrhs, h->opt.autotune != 0, s);
+            h->batch = h->segh ? batch_from_segmented(*h->segh, nrhs, h->opt.autotune != 0, s)
+                               : build_batch(h->fwd, nrhs, h->opt.autotune != 0, s);
         }
-        BatchResult r = solve_batch(*h->batch, h->top, h->seg, d_b, d_x, rtol, max_it, h->opt.fgmres_restart,
+        const Csr &top = h->segh ? h->segh->lv[0]->A : h->top;
+        BatchResult r = solve_batch(*h->batch, top, h->seg, d_b, d_x, rtol, max_it, h->opt.fgmres_restart,
                                     h->opt.use_graph != 0, s);
         AIRG_HIP(hipStreamSynchronize(s));
         if (info) {
@@ -302,6 +318,12 @@ airg_status airg_get_stats(const airg_handle *h, airg_stats *st) {
     return guarded([&] {
         AIRG_REQUIRE(h && st, ST_INVALID_ARG, "null argument");
         std::memset(st, 0, sizeof *st);
+        if (h->segh) {
+            segmented_stats(*h->segh, st);
+            st->setup_seconds = h->setup_seconds;
+            st->device_bytes = (int64_t)dev_bytes_in_use();
+            return;
+        }
         double n0 = 0, z0 = 0, gsum = 0, osum = 0, ssum = 0;
         for (auto &hp : h->fwd) {
             const Hier &H = *hp;
@@ -332,6 +354,10 @@ airg_status airg_get_level(const airg_handle *h, int32_t segment, int32_t level,
                            int8_t *h_cf) {
     return guarded([&] {
         AIRG_REQUIRE(h && info, ST_INVALID_ARG, "null argument");
+        if (h->segh && segment >= 0) {
+            segmented_level_info(*h->segh, segment, level, info, h_cf, h->segh->s);
+            return;
+        }
         Hier *H = pick(h, segment);
         AIRG_REQUIRE(level >= 0 && level < H->nlev(), ST_INVALID_ARG, "level out of range");
         const Level &L = H->L(level);
@@ -361,6 +387,10 @@ airg_status airg_get_level_matrix(const airg_handle *h, int32_t segment, int32_t
                                   int32_t *h_rowptr, int32_t *h_col, double *h_val) {
     return guarded([&] {
         AIRG_REQUIRE(h, ST_INVALID_ARG, "null handle");
+        if (h->segh && segment >= 0) {
+            segmented_level_matrix(*h->segh, segment, level, which, h_rowptr, h_col, h_val, h->segh->s);
+            return;
+        }
         Hier *H = pick(h, segment);
         AIRG_REQUIRE(level >= 0 && level < H->nlev(), ST_INVALID_ARG, "level out of range");
         const Level &L = H->L(level);
@@ -390,6 +420,7 @@ void airg_destroy(airg_handle *h) {
     try {
         for (auto &H : h->fwd)
             if (H) (void)hipStreamSynchronize(H->s);
+        if (h->segh) (void)hipStreamSynchronize(h->segh->s);
         delete h;
     } catch (...) {
     }

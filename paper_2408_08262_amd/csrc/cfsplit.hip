@@ -128,6 +128,23 @@ void pmisr_hash(int32_t n, uint64_t seed, int32_t level, uint32_t *h, hipStream_
     AIRG_LAUNCH_CHECK();
 }
 
+// Batch segments: row i of segment p draws with p's seed at its index within
+// the segment, exactly as in a setup of that segment alone.
+__global__ void k_pmisr_hash_seg(int32_t n, const int32_t *__restrict__ off, int nseg,
+                                 const uint64_t *__restrict__ seeds, int32_t level, uint32_t *__restrict__ h) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int p = seg_of(off, nseg, i);
+    h[i] = (uint32_t)(splitmix64(rng_counter(seeds[p], 0, (uint32_t)level, (uint64_t)(i - off[p]))) >> 32);
+}
+
+void pmisr_hash_seg(int32_t n, const int32_t *off, int nseg, const uint64_t *seeds, int32_t level, uint32_t *h,
+                    hipStream_t s) {
+    if (n <= 0) return;
+    k_pmisr_hash_seg<<<grid_for(n, 256), 256, 0, s>>>(n, off, nseg, seeds, level, h);
+    AIRG_LAUNCH_CHECK();
+}
+
 // Measure order: (deg, h, index) lexicographic -- the integer form of
 // w = deg + rand(0,1) with the index breaking exact ties.
 __device__ inline bool key_less(int32_t dj, uint32_t hj, int32_t j, int32_t di, uint32_t hi, int32_t i) {

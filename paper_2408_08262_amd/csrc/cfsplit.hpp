@@ -21,6 +21,10 @@ StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s);
 // and rounds on the graph; writes cf (1 = F, 2 = C).  max_rounds = 0 runs
 // until no node is unassigned.  Returns the rounds run.
 void pmisr_hash(int32_t n, uint64_t seed, int32_t level, uint32_t *h, hipStream_t s);
+// Keys of a block-diagonal batch: segment p (rows off[p] .. off[p+1]-1, device
+// offsets) uses seeds[p] and indices local to the segment.
+void pmisr_hash_seg(int32_t n, const int32_t *off, int nseg, const uint64_t *seeds, int32_t level, uint32_t *h,
+                    hipStream_t s);
 int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_rounds, int8_t *cf, hipStream_t s);
 
 // DDC: F rows with theta_i > alpha_diag (theta != 0), or a zero diagonal,

@@ -195,7 +195,20 @@ __host__ __device__ inline uint64_t rng_counter(uint64_t seed, uint32_t stream, 
     return seed ^ ((uint64_t)(stream & 0xffu) << 56) ^ ((uint64_t)(level & 0xffffu) << 40) ^ i;
 }
 
-// CF markers.
-constexpr int8_t CF_U = 0, CF_F = 1, CF_C = 2;
+// Segment of row i given the ascending segment row offsets off[0..nseg]
+// (the last p with off[p] <= i).
+__host__ __device__ inline int seg_of(const int32_t *off, int nseg, int32_t i) {
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// CF markers; CF_T marks the rows of a batch segment whose hierarchy ends at
+// this level (they take neither an F nor a C role).
+constexpr int8_t CF_U = 0, CF_F = 1, CF_C = 2, CF_T = 3;
 
 }  // namespace airg

@@ -439,28 +439,76 @@ void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, i
 
 // ------------------------------------------------------------- CF ranks ---
 __global__ void k_cf_flags(const int8_t *__restrict__ cf, int32_t n, int32_t *__restrict__ fF,
-                           int32_t *__restrict__ fC) {
+                           int32_t *__restrict__ fC, int32_t *__restrict__ fT) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    fF[i] = cf[i] == CF_F;
-    fC[i] = cf[i] == CF_C;
+    int8_t c = cf[i];
+    fF[i] = c == CF_F;
+    fC[i] = c == CF_C;
+    fT[i] = c == CF_T;
 }
 __global__ void k_cf_rank(const int8_t *__restrict__ cf, int32_t n, const int32_t *__restrict__ sF,
-                          const int32_t *__restrict__ sC, int32_t *__restrict__ rank) {
+                          const int32_t *__restrict__ sC, const int32_t *__restrict__ sT, int32_t *__restrict__ rank,
+                          int32_t *__restrict__ tot) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        tot[0] = sF[n];
+        tot[1] = sC[n];
+        tot[2] = sT[n];
+    }
     if (i >= n) return;
-    rank[i] = cf[i] == CF_F ? sF[i] : sC[i];
+    int8_t c = cf[i];
+    rank[i] = c == CF_F ? sF[i] : c == CF_C ? sC[i] : sT[i];
+}
+
+CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s) {
+    DBuf<int32_t> fF((size_t)n, s), fC((size_t)n, s), fT((size_t)n, s);
+    DBuf<int32_t> sF((size_t)n + 1, s), sC((size_t)n + 1, s), sT((size_t)n + 1, s), tot(3, s);
+    k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p, fT.p);
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(fF.p, sF.p, n, s, false);
+    exclusive_scan(fC.p, sC.p, n, s, false);
+    exclusive_scan(fT.p, sT.p, n, s, false);
+    k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, sT.p, rank, tot.p);
+    AIRG_LAUNCH_CHECK();
+    int32_t h[3];
+    d2h(h, tot.p, 3, s);
+    return CfCounts{h[0], h[1], h[2]};
+}
+
+// out[3 p + {0, 1, 2}] = F, C and terminal rows before row off[p], p = 0..na
+__global__ void k_cf_bounds(const int32_t *__restrict__ sF, const int32_t *__restrict__ sC,
+                            const int32_t *__restrict__ sT, const int32_t *__restrict__ off, int na,
+                            int32_t *__restrict__ out) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > na) return;
+    int32_t i = off[p];
+    out[3 * p] = sF[i];
+    out[3 * p + 1] = sC[i];
+    out[3 * p + 2] = sT[i];
+}
+
+CfCounts cf_ranks_seg(const int8_t *cf, int32_t n, int32_t *rank, const int32_t *d_off, int na, int32_t *h_bounds,
+                      hipStream_t s) {
+    DBuf<int32_t> fF((size_t)n, s), fC((size_t)n, s), fT((size_t)n, s);
+    DBuf<int32_t> sF((size_t)n + 1, s), sC((size_t)n + 1, s), sT((size_t)n + 1, s), tot(3, s);
+    DBuf<int32_t> bnd((size_t)3 * (na + 1), s);
+    k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p, fT.p);
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(fF.p, sF.p, n, s, false);
+    exclusive_scan(fC.p, sC.p, n, s, false);
+    exclusive_scan(fT.p, sT.p, n, s, false);
+    k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, sT.p, rank, tot.p);
+    AIRG_LAUNCH_CHECK();
+    k_cf_bounds<<<grid_for(na + 1, 256), 256, 0, s>>>(sF.p, sC.p, sT.p, d_off, na, bnd.p);
+    AIRG_LAUNCH_CHECK();
+    d2h(h_bounds, bnd.p, (size_t)3 * (na + 1), s);
+    return CfCounts{h_bounds[3 * na], h_bounds[3 * na + 1], h_bounds[3 * na + 2]};
 }
 
 std::pair<int32_t, int32_t> cf_ranks(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s) {
-    DBuf<int32_t> fF((size_t)n, s), fC((size_t)n, s), sF((size_t)n + 1, s), sC((size_t)n + 1, s);
-    k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p);
-    AIRG_LAUNCH_CHECK();
-    int64_t nF = exclusive_scan(fF.p, sF.p, n, s);
-    int64_t nC = exclusive_scan(fC.p, sC.p, n, s);
-    k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, rank);
-    AIRG_LAUNCH_CHECK();
-    return {(int32_t)nF, (int32_t)nC};
+    CfCounts c = cf_ranks3(cf, n, rank, s);
+    return {c.nF, c.nC};
 }
 
 __global__ void k_cf_lists(const int8_t *__restrict__ cf, const int32_t *__restrict__ rank, int32_t n,
@@ -469,7 +517,7 @@ __global__ void k_cf_lists(const int8_t *__restrict__ cf, const int32_t *__restr
     if (i >= n) return;
     if (cf[i] == CF_F) {
         if (fidx) fidx[rank[i]] = i;
-    } else if (cidx) {
+    } else if (cf[i] == CF_C && cidx) {
         cidx[rank[i]] = i;
     }
 }
@@ -844,59 +892,92 @@ void gemv_add(const double *V, int64_t ldv, int nvec, const double *h_dev, doubl
 }
 
 // -------------------------------------------------------------- binning ---
-constexpr int kMaxBins = 16;
-__global__ void k_bin_count(const int8_t *__restrict__ bin, int32_t n, int nbins, int32_t *__restrict__ cnt) {
-    __shared__ int32_t loc[kMaxBins];
-    if (threadIdx.x < kMaxBins) loc[threadIdx.x] = 0;
-    __syncthreads();
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        int b = bin[i];
-        if (b >= 0 && b < nbins) atomicAdd(&loc[b], 1);
+// Row binning.  Rows are listed bin by bin, in ascending row order within a
+// bin.  One wavefront takes kBinSpan consecutive rows: pass 1 counts its rows
+// per bin, an exclusive scan over the (bin, wavefront) counts gives every
+// wavefront its write offset in each bin, and pass 2 places the rows at those
+// offsets plus their ballot ranks.
+constexpr int32_t kBinSpan = 4096;
+
+template <int NB>
+__global__ void __launch_bounds__(64) k_bin_count(const int8_t *__restrict__ bin, int32_t n, int32_t nw,
+                                                  int32_t *__restrict__ bc) {
+    const int32_t w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t r0 = w * kBinSpan, r1 = r0 + kBinSpan < n ? r0 + kBinSpan : n;
+    int32_t c[NB];
+#pragma unroll
+    for (int v = 0; v < NB; ++v) c[v] = 0;
+    for (int32_t i0 = r0; i0 < r1; i0 += 64) {
+        int32_t i = i0 + lane;
+        int b = i < r1 ? bin[i] : -1;
+#pragma unroll
+        for (int v = 0; v < NB; ++v) c[v] += __popcll(__ballot(b == v));
     }
-    __syncthreads();
-    if (threadIdx.x < nbins && loc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], loc[threadIdx.x]);
+#pragma unroll
+    for (int v = 0; v < NB; ++v)
+        if (lane == v) bc[(int64_t)v * nw + w] = c[v];
 }
-// Each block reserves its bin ranges with one global atomic per bin, then
-// places its rows at block-local offsets taken from LDS counters.
-__global__ void k_bin_scatter(const int8_t *__restrict__ bin, int32_t n, int nbins, const int32_t *__restrict__ off,
-                              int32_t *__restrict__ cursor, int32_t *__restrict__ rows) {
-    __shared__ int32_t loc[kMaxBins], base[kMaxBins];
-    if (threadIdx.x < kMaxBins) loc[threadIdx.x] = 0;
-    __syncthreads();
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = -1, r = 0;
-    if (i < n) {
-        b = bin[i];
-        if (b >= 0 && b < nbins) r = atomicAdd(&loc[b], 1);
-        else b = -1;
+
+template <int NB>
+__global__ void __launch_bounds__(64) k_bin_scatter(const int8_t *__restrict__ bin, int32_t n, int32_t nw,
+                                                    const int32_t *__restrict__ boff, int32_t *__restrict__ rows) {
+    const int32_t w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t r0 = w * kBinSpan, r1 = r0 + kBinSpan < n ? r0 + kBinSpan : n;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int32_t base[NB];
+#pragma unroll
+    for (int v = 0; v < NB; ++v) base[v] = boff[(int64_t)v * nw + w];
+    for (int32_t i0 = r0; i0 < r1; i0 += 64) {
+        int32_t i = i0 + lane;
+        int b = i < r1 ? bin[i] : -1;
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            uint64_t m = __ballot(b == v);
+            if (b == v) rows[base[v] + __popcll(m & below)] = i;
+            base[v] += __popcll(m);
+        }
     }
-    __syncthreads();
-    if (threadIdx.x < nbins && loc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], loc[threadIdx.x]);
-    __syncthreads();
-    if (b >= 0) rows[off[b] + base[b] + r] = i;
+}
+
+// tot[b] = first offset of bin b, tot[nb] = number of binned rows
+__global__ void k_bin_starts(const int32_t *__restrict__ boff, int nb, int32_t nw, int32_t *__restrict__ tot) {
+    int b = threadIdx.x;
+    if (b <= nb) tot[b] = boff[(int64_t)b * nw];
+}
+
+template <int NB>
+static void bin_rows_t(Bins &B, const int8_t *bin, int32_t n, hipStream_t s) {
+    const int32_t nw = (n + kBinSpan - 1) / kBinSpan;
+    const int64_t m = (int64_t)NB * nw;
+    DBuf<int32_t> bc((size_t)m + 1, s), boff((size_t)m + 1, s), tot(NB + 1, s);
+    k_bin_count<NB><<<nw, 64, 0, s>>>(bin, n, nw, bc.p);
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(bc.p, boff.p, m, s, false);
+    k_bin_starts<<<1, 64, 0, s>>>(boff.p, NB, nw, tot.p);
+    AIRG_LAUNCH_CHECK();
+    std::vector<int32_t> h(NB + 1);
+    d2h(h.data(), tot.p, NB + 1, s);
+    for (int b = 0; b <= NB; ++b) B.off[b] = h[b];
+    B.rows.alloc((size_t)std::max<int32_t>(h[NB], 1), s);
+    k_bin_scatter<NB><<<nw, 64, 0, s>>>(bin, n, nw, boff.p, B.rows.p);
+    AIRG_LAUNCH_CHECK();
 }
 
 Bins bin_rows(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
-    AIRG_REQUIRE(nbins <= kMaxBins, ST_INVALID_ARG, "too many bins");
     Bins B;
-    DBuf<int32_t> cnt(kMaxBins, s), cursor(kMaxBins, s), off(kMaxBins + 1, s);
-    fill_zero(cnt.p, kMaxBins * 4, s);
-    fill_zero(cursor.p, kMaxBins * 4, s);
-    k_bin_count<<<grid_for(n, 256), 256, 0, s>>>(bin, n, nbins, cnt.p);
-    AIRG_LAUNCH_CHECK();
-    std::vector<int32_t> hc(kMaxBins);
-    d2h(hc.data(), cnt.p, kMaxBins, s);
     B.off.assign(nbins + 1, 0);
-    std::vector<int32_t> ho(kMaxBins + 1, 0);
-    for (int b = 0; b < nbins; ++b) {
-        B.off[b + 1] = B.off[b] + hc[b];
-        ho[b + 1] = (int32_t)B.off[b + 1];
+    if (n <= 0) {
+        B.rows.alloc(1, s);
+        return B;
     }
-    h2d(off.p, ho.data(), kMaxBins + 1, s);
-    B.rows.alloc((size_t)std::max<int64_t>(B.off[nbins], 1), s);
-    k_bin_scatter<<<grid_for(n, 256), 256, 0, s>>>(bin, n, nbins, off.p, cursor.p, B.rows.p);
-    AIRG_LAUNCH_CHECK();
+    switch (nbins) {
+    case 6: bin_rows_t<6>(B, bin, n, s); break;
+    case 8: bin_rows_t<8>(B, bin, n, s); break;
+    case 9: bin_rows_t<9>(B, bin, n, s); break;
+    default: throw Error(ST_INVALID_ARG, "unsupported number of bins");
+    }
     return B;
 }
 

@@ -34,6 +34,16 @@ void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, i
 // rank[i] = position of i among the points carrying its own marker
 // (F rank for F points, C rank for C points); returns (nF, nC).
 std::pair<int32_t, int32_t> cf_ranks(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s);
+// The same with a third class, terminal rows (CF_T), ranked among themselves.
+struct CfCounts {
+    int32_t nF, nC, nT;
+};
+CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s);
+// cf_ranks3 plus, at the segment boundaries d_off[0..na] (device, ascending,
+// d_off[na] = n), the numbers of F, C and terminal rows before each boundary:
+// h_bounds[3 p + {0, 1, 2}] (host, 3 (na + 1) entries).
+CfCounts cf_ranks_seg(const int8_t *cf, int32_t n, int32_t *rank, const int32_t *d_off, int na, int32_t *h_bounds,
+                      hipStream_t s);
 // fidx[f] = original index of the f-th F point (and likewise cidx for C).
 void cf_index_lists(const int8_t *cf, const int32_t *rank, int32_t n, int32_t *fidx, int32_t *cidx, hipStream_t s);
 

@@ -2,6 +2,8 @@
 // permuted solve-phase operators, V-cycle and outer iterations.
 #pragma once
 #include <memory>
+#include <tuple>
+#include <vector>
 
 #include "airg.h"
 #include "common.hpp"
@@ -48,6 +50,67 @@ struct Hier {
     void vcycle(int l, const T *g, T *e);
     void precondition(const double *r, double *e, int precision);
 };
+
+// Per-phase device time from events recorded around each phase.
+struct PhaseTimer {
+    hipStream_t s;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> spans;
+    int cur = -1;
+    hipEvent_t start = nullptr;
+    explicit PhaseTimer(hipStream_t st) : s(st) {}
+    ~PhaseTimer() {
+        for (auto &t : spans) {
+            (void)hipEventDestroy(std::get<1>(t));
+            (void)hipEventDestroy(std::get<2>(t));
+        }
+        if (start) (void)hipEventDestroy(start);
+    }
+    void begin(int phase) {
+        end();
+        AIRG_HIP(hipEventCreate(&start));
+        AIRG_HIP(hipEventRecord(start, s));
+        cur = phase;
+    }
+    void end() {
+        if (cur < 0) return;
+        hipEvent_t stop;
+        AIRG_HIP(hipEventCreate(&stop));
+        AIRG_HIP(hipEventRecord(stop, s));
+        spans.emplace_back(cur, start, stop);
+        start = nullptr;
+        cur = -1;
+    }
+    void collect(double *out) {
+        end();
+        AIRG_HIP(hipStreamSynchronize(s));
+        for (auto &t : spans) {
+            float ms = 0.f;
+            AIRG_HIP(hipEventElapsedTime(&ms, std::get<1>(t), std::get<2>(t)));
+            out[std::get<0>(t)] += ms * 1e-3;
+        }
+    }
+};
+
+struct NullTimer {
+    void begin(int) {}
+    void end() {}
+};
+
+// Pieces of the setup shared by the single and batch drivers.
+Csr pattern_copy(const CsrView &A, hipStream_t s);
+Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, hipStream_t s);
+// perm: natural index -> level order (F by rank, then C, then terminal rows);
+// iperm its inverse.
+void make_level_perm(int32_t n, int32_t nF, int32_t nC, const int8_t *cf, const int32_t *rank, int32_t *perm,
+                     int32_t *iperm, hipStream_t s);
+// Rows src[0..nout) of A with F columns renumbered by rank and C columns as
+// nF + rank.
+Csr permute_fc(const CsrView &A, const int32_t *src, int32_t nout, const int8_t *cf, const int32_t *rank, int32_t nF,
+               hipStream_t s);
+// [Z I] (nC x ncols) with rows in the next level's order (niperm, nullable).
+Csr build_rp(const Csr &Z, int32_t nF, int32_t nC, int32_t ncols, const int32_t *niperm, hipStream_t s);
+// [W; I] ((nF + nC) x ncols) in level order, columns through nperm (nullable).
+Csr build_pp(const Csr &W, int32_t nF, int32_t nC, int32_t ncols, const int32_t *nperm, hipStream_t s);
 
 // Builds the full hierarchy of the canonical operator A0 (takes ownership).
 std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t seed, hipStream_t s);

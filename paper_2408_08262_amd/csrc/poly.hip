@@ -27,6 +27,22 @@ void gauss_rhs(int64_t n, uint64_t seed, int32_t level, double *b, hipStream_t s
     AIRG_LAUNCH_CHECK();
 }
 
+// Batch segments: entry k of segment p draws with p's seed at the index k
+// takes within the segment.
+__global__ void k_gauss_seg(int32_t n, const int32_t *__restrict__ off, int nseg, const uint64_t *__restrict__ seeds,
+                            int32_t level, double *__restrict__ b) {
+    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int p = seg_of(off, nseg, k);
+    const double two53 = 1.0 / 9007199254740992.0;
+    uint64_t local = (uint64_t)(k - off[p]);
+    uint64_t r1 = splitmix64(rng_counter(seeds[p], 1, (uint32_t)level, local));
+    uint64_t r2 = splitmix64(rng_counter(seeds[p], 2, (uint32_t)level, local));
+    double u1 = ((double)(r1 >> 11) + 1.0) * two53;
+    double u2 = (double)(r2 >> 11) * two53;
+    b[k] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
 // ------------------------------------------------------------ reductions ---
 constexpr int kQrThreads = 256;
 constexpr int kQrRows = 384;          // rows per leaf: cols*384*8 <= 48 KiB of LDS
@@ -92,21 +108,16 @@ __global__ void __launch_bounds__(kQrThreads) k_colsq_finish(const double *__res
 }
 
 // -------------------------------------------------------------- TSQR leaf ---
-// Householder QR of a kQrRows x cols panel staged in LDS (column-major); the
-// R factor of block b is written as rows b*cols .. b*cols+cols-1 of the next
-// (column-major) stacked matrix.
-__global__ void __launch_bounds__(kQrThreads) k_tsqr_leaf(const double *__restrict__ K, int64_t n, int64_t ldk,
-                                                          int cols, const double *__restrict__ scale,
-                                                          double *__restrict__ Rs, int64_t ldr) {
-    extern __shared__ double W[];               // cols * kQrRows
-    __shared__ double sh[4 * kMaxPolyCols];
-    int64_t r0 = (int64_t)blockIdx.x * kQrRows;
+// Householder QR of a panel of `rows` (<= kQrRows) rows x cols staged in LDS
+// (column-major, zero-padded to kQrRows); the upper triangle of the result is
+// the panel's R factor, written column-major at out with leading dimension ldo.
+__device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, int rows, int cols,
+                         const double *__restrict__ scale, double *__restrict__ out, int64_t ldo, double *W,
+                         double *sh) {
     for (int c = 0; c < cols; ++c) {
         double sc = scale ? scale[c] : 1.0;
-        for (int r = threadIdx.x; r < kQrRows; r += kQrThreads) {
-            int64_t row = r0 + r;
-            W[c * kQrRows + r] = row < n ? K[(int64_t)c * ldk + row] * sc : 0.0;
-        }
+        for (int r = threadIdx.x; r < kQrRows; r += kQrThreads)
+            W[c * kQrRows + r] = r < rows ? K[(int64_t)c * ldk + r0 + r] * sc : 0.0;
     }
     __syncthreads();
     int steps = cols < kQrRows ? cols : kQrRows;
@@ -145,8 +156,79 @@ __global__ void __launch_bounds__(kQrThreads) k_tsqr_leaf(const double *__restri
     for (int idx = threadIdx.x; idx < cols * cols; idx += kQrThreads) {
         int r = idx / cols, c = idx % cols;
         double val = (r <= c && r < steps) ? W[c * kQrRows + r] : 0.0;
-        Rs[(int64_t)c * ldr + (int64_t)blockIdx.x * cols + r] = val;
+        out[(int64_t)c * ldo + r] = val;
     }
+}
+
+// Leaf b takes rows b*kQrRows.. of K; its R is rows b*cols.. of the next
+// (column-major) stacked matrix.
+__global__ void __launch_bounds__(kQrThreads) k_tsqr_leaf(const double *__restrict__ K, int64_t n, int64_t ldk,
+                                                          int cols, const double *__restrict__ scale,
+                                                          double *__restrict__ Rs, int64_t ldr) {
+    extern __shared__ double W[];               // cols * kQrRows
+    __shared__ double sh[4 * kMaxPolyCols];
+    int64_t r0 = (int64_t)blockIdx.x * kQrRows;
+    int rows = (int)(n - r0 < kQrRows ? n - r0 : kQrRows);
+    qr_panel(K, ldk, r0, rows, cols, scale, Rs + (int64_t)blockIdx.x * cols, ldr, W, sh);
+}
+
+// Batch form: one leaf per table entry; a leaf with fin >= 0 is the last of
+// segment fin and writes that segment's final R (cols x cols, column-major).
+struct QrLeaf {
+    int64_t r0;      // first row in the source
+    int32_t rows;
+    int32_t seg;     // scale row (round 0), else unused
+    int64_t out;     // first row in the stacked output
+    int32_t fin;
+    int32_t pad;
+};
+
+__global__ void __launch_bounds__(kQrThreads) k_tsqr_leaf_tab(const double *__restrict__ K, int64_t ldk, int cols,
+                                                              const QrLeaf *__restrict__ leaves,
+                                                              const double *__restrict__ scale,
+                                                              double *__restrict__ Rs, int64_t ldr,
+                                                              double *__restrict__ Rf) {
+    extern __shared__ double W[];
+    __shared__ double sh[4 * kMaxPolyCols];
+    QrLeaf L = leaves[blockIdx.x];
+    const double *sc = scale ? scale + (int64_t)L.seg * cols : nullptr;
+    if (L.fin >= 0) qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rf + (int64_t)L.fin * cols * cols, cols, W, sh);
+    else qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rs + L.out, ldr, W, sh);
+}
+
+// partial[leaf * cols + c] = sum over the leaf's rows of K[:, c]^2
+__global__ void __launch_bounds__(kQrThreads) k_colsq_tab(const double *__restrict__ K, int64_t ldk, int cols,
+                                                          const QrLeaf *__restrict__ leaves,
+                                                          double *__restrict__ partial) {
+    __shared__ double sh[4 * kMaxPolyCols];
+    QrLeaf L = leaves[blockIdx.x];
+    double v[kMaxPolyCols];
+#pragma unroll
+    for (int c = 0; c < kMaxPolyCols; ++c) v[c] = 0.0;
+    for (int r = threadIdx.x; r < L.rows; r += kQrThreads) {
+#pragma unroll
+        for (int c = 0; c < kMaxPolyCols; ++c)
+            if (c < cols) {
+                double x = K[(int64_t)c * ldk + L.r0 + r];
+                v[c] += x * x;
+            }
+    }
+    block_sum_vec<kMaxPolyCols>(v, cols, sh);
+    if (threadIdx.x < cols) partial[(int64_t)blockIdx.x * cols + threadIdx.x] = v[threadIdx.x];
+}
+
+// Per segment p (leaves first[p] .. first[p+1]-1, summed in order): column
+// norms into out[p * cols + c] and their inverses into inv.
+__global__ void k_colsq_seg_finish(const double *__restrict__ partial, const int32_t *__restrict__ first, int nseg,
+                                   int cols, double *__restrict__ norm, double *__restrict__ inv) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nseg * cols) return;
+    int p = (int)(t / cols), c = (int)(t % cols);
+    double acc = 0.0;
+    for (int q = first[p]; q < first[p + 1]; ++q) acc += partial[(int64_t)q * cols + c];
+    double nr = sqrt(acc);
+    norm[t] = nr;
+    inv[t] = nr > 0.0 ? 1.0 / nr : 1.0;
 }
 
 void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s) {
@@ -245,11 +327,117 @@ PolyInfo gmres_poly(const CsrView &A, uint64_t seed, int32_t level, int m, hipSt
     return P;
 }
 
-// --------------------------------------------- fixed-sparsity assembly ----
-struct Coeffs {
-    double a[kMaxPolyCols];
-};
+void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, double *h_R, double *h_colnorm,
+                hipStream_t s) {
+    AIRG_REQUIRE(cols >= 1 && cols <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order too large");
+    const int nseg = (int)off.size() - 1;
+    const int64_t n = off[nseg];
+    size_t lds = (size_t)cols * kQrRows * sizeof(double);
+    // round 0 leaves: the segments' own row blocks
+    std::vector<QrLeaf> leaves;
+    std::vector<int32_t> first(nseg + 1, 0);
+    std::vector<int64_t> rows0(nseg), start0(nseg);
+    for (int p = 0; p < nseg; ++p) {
+        first[p] = (int32_t)leaves.size();
+        int64_t m = off[p + 1] - off[p];
+        for (int64_t r = 0; r < m || r == 0; r += kQrRows)
+            leaves.push_back(QrLeaf{off[p] + r, (int32_t)std::min<int64_t>(kQrRows, m - r), p, 0, -1, 0});
+        rows0[p] = m;
+        start0[p] = off[p];
+    }
+    first[nseg] = (int32_t)leaves.size();
+    // column norms per segment
+    DBuf<QrLeaf> dl(leaves.size(), s);
+    DBuf<int32_t> dfirst(first.size(), s);
+    DBuf<double> part(leaves.size() * cols, s), normout((size_t)nseg * cols * (cols + 1), s), inv((size_t)nseg * cols, s);
+    h2d(dl.p, leaves.data(), leaves.size(), s);
+    h2d(dfirst.p, first.data(), first.size(), s);
+    k_colsq_tab<<<(unsigned)leaves.size(), kQrThreads, 0, s>>>(K, n, cols, dl.p, part.p);
+    AIRG_LAUNCH_CHECK();
+    double *Rf = normout.p;                               // nseg * cols * cols, then the norms
+    double *norm = normout.p + (size_t)nseg * cols * cols;
+    k_colsq_seg_finish<<<grid_for((int64_t)nseg * cols, 256), 256, 0, s>>>(part.p, dfirst.p, nseg, cols, norm, inv.p);
+    AIRG_LAUNCH_CHECK();
+    // rounds: every unfinished segment's rows -> one R per leaf, stacked
+    std::vector<int64_t> rows = rows0, start = start0;
+    std::vector<char> done(nseg, 0);
+    const double *src = K;
+    int64_t ld = n;
+    bool scaled = true;
+    DBuf<double> bufs[2];
+    std::vector<DBuf<QrLeaf>> tables;
+    std::vector<std::vector<QrLeaf>> host_tabs;   // sources of the async copies, kept until the final sync
+    int which = 0;
+    for (;;) {
+        host_tabs.emplace_back();
+        std::vector<QrLeaf> &tab = host_tabs.back();
+        int64_t out_rows = 0;
+        std::vector<int64_t> nrows(nseg, 0), nstart(nseg, 0);
+        for (int p = 0; p < nseg; ++p) {
+            if (done[p]) continue;
+            int64_t nb = std::max<int64_t>(1, (rows[p] + kQrRows - 1) / kQrRows);
+            if (nb == 1) {
+                tab.push_back(QrLeaf{start[p], (int32_t)rows[p], p, 0, p, 0});
+                done[p] = 1;
+                continue;
+            }
+            nstart[p] = out_rows;
+            for (int64_t b = 0; b < nb; ++b)
+                tab.push_back(QrLeaf{start[p] + b * kQrRows, (int32_t)std::min<int64_t>(kQrRows, rows[p] - b * kQrRows),
+                                     p, out_rows + b * cols, -1, 0});
+            nrows[p] = nb * cols;
+            out_rows += nb * cols;
+        }
+        if (tab.empty()) break;
+        tables.emplace_back(tab.size(), s);
+        h2d(tables.back().p, tab.data(), tab.size(), s);
+        bufs[which].alloc((size_t)std::max<int64_t>(out_rows, 1) * cols, s);
+        k_tsqr_leaf_tab<<<(unsigned)tab.size(), kQrThreads, lds, s>>>(src, ld, cols, tables.back().p,
+                                                                     scaled ? inv.p : nullptr, bufs[which].p,
+                                                                     std::max<int64_t>(out_rows, 1), Rf);
+        AIRG_LAUNCH_CHECK();
+        src = bufs[which].p;
+        ld = std::max<int64_t>(out_rows, 1);
+        scaled = false;
+        rows = nrows;
+        start = nstart;
+        which ^= 1;
+        if (out_rows == 0) break;
+    }
+    std::vector<double> h((size_t)nseg * cols * (cols + 1));
+    d2h(h.data(), normout.p, h.size(), s);
+    for (int p = 0; p < nseg; ++p) {
+        const double *R = h.data() + (size_t)p * cols * cols;
+        for (int r = 0; r < cols; ++r)
+            for (int c = 0; c < cols; ++c) h_R[(size_t)p * cols * cols + r * cols + c] = R[(size_t)c * cols + r];
+        for (int c = 0; c < cols; ++c) h_colnorm[(size_t)p * cols + c] = h[(size_t)nseg * cols * cols + p * cols + c];
+    }
+}
 
+std::vector<PolyInfo> gmres_poly_seg(const CsrView &A, const std::vector<int32_t> &off, const int32_t *d_off,
+                                     const uint64_t *d_seeds, int32_t level, int m, hipStream_t s) {
+    AIRG_REQUIRE(m >= 1 && m + 1 <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order out of range");
+    const int nseg = (int)off.size() - 1;
+    std::vector<PolyInfo> P(nseg);
+    for (auto &q : P) q.m = m;
+    int32_t n = A.nr;
+    if (n == 0) return P;
+    DBuf<double> K((size_t)n * (m + 1), s);
+    k_gauss_seg<<<grid_for(n, 256), 256, 0, s>>>(n, d_off, nseg, d_seeds, level, K.p);
+    AIRG_LAUNCH_CHECK();
+    for (int k = 1; k <= m; ++k) spmv(A, K.p + (int64_t)(k - 1) * n, K.p + (int64_t)k * n, nullptr, SPMV_SET, s);
+    int cols = m + 1;
+    std::vector<double> R((size_t)nseg * cols * cols), cn((size_t)nseg * cols);
+    tsqr_r_seg(K.p, off, cols, R.data(), cn.data(), s);
+    for (int p = 0; p < nseg; ++p) {
+        std::copy(R.begin() + (size_t)p * cols * cols, R.begin() + (size_t)(p + 1) * cols * cols, P[p].R);
+        std::copy(cn.begin() + (size_t)p * cols, cn.begin() + (size_t)(p + 1) * cols, P[p].colnorm);
+        P[p].used = poly_coeffs_from_r(P[p].R, P[p].colnorm, m, P[p].alpha);
+    }
+    return P;
+}
+
+// --------------------------------------------- fixed-sparsity assembly ----
 __global__ void k_rowlen_bin(int32_t n, const int32_t *__restrict__ rp, int8_t *__restrict__ bin) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -263,7 +451,8 @@ __global__ void k_rowlen_bin(int32_t n, const int32_t *__restrict__ rp, int8_t *
 template <int G, int TPB>
 __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ list, int64_t count,
                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                   const double *__restrict__ v, Coeffs al, int nalpha,
+                                                   const double *__restrict__ v, const double *__restrict__ alt,
+                                                   const int32_t *__restrict__ soff, int nseg, int nalpha,
                                                    double *__restrict__ out) {
 #pragma clang fp contract(off)
     constexpr int NG = TPB / G;
@@ -292,13 +481,14 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
         }
     }
     wave_sync();
+    const double *al = alt + (nseg > 1 ? seg_of(soff, nseg, row) : 0) * kMaxPolyCols;
     double x = (lane < L && J[lane] == row) ? 1.0 : 0.0;
-    double acc = al.a[0] * x;
+    double acc = al[0] * x;
     for (int k = 1; k < nalpha; ++k) {
         double xn = 0.0;
         for (int p = 0; p < L; ++p) xn += group_bcast<G>(x, p) * M[p * G + lane];
         x = xn;
-        acc += al.a[k] * x;
+        acc += al[k] * x;
     }
     if (lane < L) out[b + lane] = acc;
 }
@@ -309,7 +499,8 @@ constexpr int kLongRowMax = 2048;
 // gathered rows streamed once per power in ascending p.
 __global__ void __launch_bounds__(256) k_poly_long(const int32_t *__restrict__ list, int64_t count,
                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                   const double *__restrict__ v, Coeffs al, int nalpha,
+                                                   const double *__restrict__ v, const double *__restrict__ alt,
+                                                   const int32_t *__restrict__ soff, int nseg, int nalpha,
                                                    double *__restrict__ out) {
 #pragma clang fp contract(off)
     __shared__ int32_t J[kLongRowMax];
@@ -319,10 +510,11 @@ __global__ void __launch_bounds__(256) k_poly_long(const int32_t *__restrict__ l
     int32_t row = list[idx];
     int32_t b = rp[row];
     int32_t L = rp[row + 1] - b;
+    const double *al = alt + (nseg > 1 ? seg_of(soff, nseg, row) : 0) * kMaxPolyCols;
     for (int a = threadIdx.x; a < L; a += blockDim.x) {
         J[a] = ci[b + a];
         x[a] = J[a] == row ? 1.0 : 0.0;
-        acc[a] = al.a[0] * x[a];
+        acc[a] = al[0] * x[a];
     }
     __syncthreads();
     for (int k = 1; k < nalpha; ++k) {
@@ -345,43 +537,77 @@ __global__ void __launch_bounds__(256) k_poly_long(const int32_t *__restrict__ l
         }
         for (int a = threadIdx.x; a < L; a += blockDim.x) {
             x[a] = xn[a];
-            acc[a] += al.a[k] * x[a];
+            acc[a] += al[k] * x[a];
         }
         __syncthreads();
     }
     for (int a = threadIdx.x; a < L; a += blockDim.x) out[b + a] = acc[a];
 }
 
-void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, double *out_v, hipStream_t s) {
-    AIRG_REQUIRE(nalpha >= 1 && nalpha <= kMaxPolyCols, ST_INVALID_ARG, "bad number of coefficients");
+// Coefficient table (kMaxPolyCols per segment) and segment offsets on the
+// device; nseg = 1 needs no offsets.
+static void fixed_sparsity_tab(const CsrView &A, const double *alt, const int32_t *soff, int nseg, int nalpha,
+                               double *out_v, hipStream_t s) {
     int32_t n = A.nr;
-    if (n == 0) return;
-    Coeffs c{};
-    for (int k = 0; k < nalpha; ++k) c.a[k] = alpha[k];
     DBuf<int8_t> bin((size_t)n, s);
     k_rowlen_bin<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp, bin.p);
     AIRG_LAUNCH_CHECK();
     Bins B = bin_rows(bin.p, n, 6, s);
-    if (B.count(0)) k_poly_rows<4, 256><<<grid_for(B.count(0), 64), 256, 0, s>>>(B.list(0), B.count(0), A.rp, A.ci, A.v, c, nalpha, out_v);
-    if (B.count(1)) k_poly_rows<8, 256><<<grid_for(B.count(1), 32), 256, 0, s>>>(B.list(1), B.count(1), A.rp, A.ci, A.v, c, nalpha, out_v);
-    if (B.count(2)) k_poly_rows<16, 256><<<grid_for(B.count(2), 16), 256, 0, s>>>(B.list(2), B.count(2), A.rp, A.ci, A.v, c, nalpha, out_v);
-    if (B.count(3)) k_poly_rows<32, 128><<<grid_for(B.count(3), 4), 128, 0, s>>>(B.list(3), B.count(3), A.rp, A.ci, A.v, c, nalpha, out_v);
-    if (B.count(4)) k_poly_rows<64, 64><<<grid_for(B.count(4), 1), 64, 0, s>>>(B.list(4), B.count(4), A.rp, A.ci, A.v, c, nalpha, out_v);
+    auto rows = [&](auto kern, int b, int per_block, unsigned tpb) {
+        if (B.count(b))
+            kern<<<grid_for(B.count(b), per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, alt, soff,
+                                                                nseg, nalpha, out_v);
+    };
+    rows(k_poly_rows<4, 256>, 0, 64, 256);
+    rows(k_poly_rows<8, 256>, 1, 32, 256);
+    rows(k_poly_rows<16, 256>, 2, 16, 256);
+    rows(k_poly_rows<32, 128>, 3, 4, 128);
+    rows(k_poly_rows<64, 64>, 4, 1, 64);
     AIRG_LAUNCH_CHECK();
     if (B.count(5)) {
         int32_t maxlen = 0;
         {
             // longest row among the long ones, checked against the LDS capacity
-            std::vector<int32_t> rows((size_t)B.count(5)), rpl((size_t)n + 1);
-            d2h(rows.data(), B.list(5), rows.size(), s);
+            std::vector<int32_t> lr((size_t)B.count(5)), rpl((size_t)n + 1);
+            d2h(lr.data(), B.list(5), lr.size(), s);
             d2h(rpl.data(), A.rp, rpl.size(), s);
-            for (int32_t r : rows) maxlen = std::max(maxlen, rpl[r + 1] - rpl[r]);
+            for (int32_t r : lr) maxlen = std::max(maxlen, rpl[r + 1] - rpl[r]);
         }
         AIRG_REQUIRE(maxlen <= kLongRowMax, ST_LIMIT,
                      "row of " + std::to_string(maxlen) + " entries exceeds the fixed-sparsity row limit");
-        k_poly_long<<<(unsigned)B.count(5), 256, 0, s>>>(B.list(5), B.count(5), A.rp, A.ci, A.v, c, nalpha, out_v);
+        k_poly_long<<<(unsigned)B.count(5), 256, 0, s>>>(B.list(5), B.count(5), A.rp, A.ci, A.v, alt, soff, nseg,
+                                                         nalpha, out_v);
         AIRG_LAUNCH_CHECK();
     }
+}
+
+void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, double *out_v, hipStream_t s) {
+    AIRG_REQUIRE(nalpha >= 1 && nalpha <= kMaxPolyCols, ST_INVALID_ARG, "bad number of coefficients");
+    if (A.nr == 0) return;
+    double tab[kMaxPolyCols] = {};
+    for (int k = 0; k < nalpha; ++k) tab[k] = alpha[k];
+    DBuf<double> alt(kMaxPolyCols, s);
+    h2d(alt.p, tab, kMaxPolyCols, s);
+    fixed_sparsity_tab(A, alt.p, nullptr, 1, nalpha, out_v, s);   // synchronises (row binning) before tab dies
+}
+
+void poly_fixed_sparsity_seg(const CsrView &A, const std::vector<int32_t> &off, const std::vector<PolyInfo> &P,
+                             double *out_v, hipStream_t s) {
+    const int nseg = (int)P.size();
+    AIRG_REQUIRE(nseg >= 1 && (int)off.size() == nseg + 1, ST_INVALID_ARG, "bad segment table");
+    if (A.nr == 0) return;
+    int nalpha = P[0].m;
+    AIRG_REQUIRE(nalpha >= 1 && nalpha <= kMaxPolyCols, ST_INVALID_ARG, "bad number of coefficients");
+    std::vector<double> tab((size_t)nseg * kMaxPolyCols, 0.0);
+    for (int p = 0; p < nseg; ++p) {
+        AIRG_REQUIRE(P[p].m == nalpha, ST_INVALID_ARG, "segments differ in polynomial order");
+        for (int k = 0; k < nalpha; ++k) tab[(size_t)p * kMaxPolyCols + k] = P[p].alpha[k];
+    }
+    DBuf<double> alt(tab.size(), s);
+    DBuf<int32_t> soff(off.size(), s);
+    h2d(alt.p, tab.data(), tab.size(), s);
+    h2d(soff.p, off.data(), off.size(), s);
+    fixed_sparsity_tab(A, alt.p, soff.p, nseg, nalpha, out_v, s);   // synchronises before the tables die
 }
 
 }  // namespace airg

@@ -2,6 +2,8 @@
 // Box-Muller, power basis, tall-skinny Householder QR, least squares for the
 // coefficients, and the assembled fixed-sparsity approximate inverse.
 #pragma once
+#include <vector>
+
 #include "common.hpp"
 
 namespace airg {
@@ -31,9 +33,22 @@ int poly_coeffs_from_r(const double *R, const double *colnorm, int m, double *al
 // Steps 3-6 of the setup on a square A (alpha has m entries).
 PolyInfo gmres_poly(const CsrView &A, uint64_t seed, int32_t level, int m, hipStream_t s);
 
+// The same for a block-diagonal batch: segment p holds rows off[p] ..
+// off[p+1]-1 (host offsets; d_off the same on the device) and draws its
+// random vector with d_seeds[p] at indices local to the segment.  Each
+// segment gets its own column scaling, R factor and coefficients.
+std::vector<PolyInfo> gmres_poly_seg(const CsrView &A, const std::vector<int32_t> &off, const int32_t *d_off,
+                                     const uint64_t *d_seeds, int32_t level, int m, hipStream_t s);
+void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, double *h_R, double *h_colnorm,
+                hipStream_t s);
+
 // Assembled fixed-sparsity polynomial on the pattern of A (which must store
 // its diagonal): row i of A~^k is e_i^T M_i^k restricted to J_i, with
 // M_i = A(J_i, J_i).  out_v has A.nnz entries (pattern of A).
 void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, double *out_v, hipStream_t s);
+// Batch form: the rows of segment p (host offsets off) use P[p]'s
+// coefficients.
+void poly_fixed_sparsity_seg(const CsrView &A, const std::vector<int32_t> &off, const std::vector<PolyInfo> &P,
+                             double *out_v, hipStream_t s);
 
 }  // namespace airg

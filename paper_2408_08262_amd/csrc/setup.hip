@@ -14,51 +14,6 @@ namespace airg {
 
 namespace {
 
-// Per-phase device time from events recorded around each phase.
-struct PhaseTimer {
-    hipStream_t s;
-    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> spans;
-    int cur = -1;
-    hipEvent_t start = nullptr;
-    explicit PhaseTimer(hipStream_t st) : s(st) {}
-    ~PhaseTimer() {
-        for (auto &t : spans) {
-            (void)hipEventDestroy(std::get<1>(t));
-            (void)hipEventDestroy(std::get<2>(t));
-        }
-        if (start) (void)hipEventDestroy(start);
-    }
-    void begin(int phase) {
-        end();
-        AIRG_HIP(hipEventCreate(&start));
-        AIRG_HIP(hipEventRecord(start, s));
-        cur = phase;
-    }
-    void end() {
-        if (cur < 0) return;
-        hipEvent_t stop;
-        AIRG_HIP(hipEventCreate(&stop));
-        AIRG_HIP(hipEventRecord(stop, s));
-        spans.emplace_back(cur, start, stop);
-        start = nullptr;
-        cur = -1;
-    }
-    void collect(double *out) {
-        end();
-        AIRG_HIP(hipStreamSynchronize(s));
-        for (auto &t : spans) {
-            float ms = 0.f;
-            AIRG_HIP(hipEventElapsedTime(&ms, std::get<1>(t), std::get<2>(t)));
-            out[std::get<0>(t)] += ms * 1e-3;
-        }
-    }
-};
-
-struct NullTimer {
-    void begin(int) {}
-    void end() {}
-};
-
 CfParams cf_params(const airg_opts &o, uint64_t seed) {
     return CfParams{o.strong_threshold, o.ddc_threshold, o.ddc_fraction, o.pmisr_max_rounds, seed};
 }
@@ -80,15 +35,24 @@ std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t
     return cf_ranks(cf.p, n, rank.p, s);
 }
 
-// Copy of A's pattern with values from the fixed-sparsity polynomial.
-Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, hipStream_t s) {
+}  // namespace
+
+Csr pattern_copy(const CsrView &A, hipStream_t s) {
     Csr X;
     X.alloc(A.nr, A.nc, A.nnz, s);
     d2d(X.rp.p, A.rp, (size_t)A.nr + 1, s);
     d2d(X.ci.p, A.ci, (size_t)A.nnz, s);
+    return X;
+}
+
+// Copy of A's pattern with values from the fixed-sparsity polynomial.
+Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, hipStream_t s) {
+    Csr X = pattern_copy(A, s);
     poly_fixed_sparsity(A, P.alpha, m, X.v.p, s);
     return X;
 }
+
+namespace {
 
 // Steps 2 and 7-11 of the recipe once the splitting is known.
 template <class Timer>
@@ -133,14 +97,25 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     tm.end();
 }
 
+}  // namespace
+
 // ----------------------------------------------------------- permutation ---
-__global__ void k_make_perm(int32_t n, int32_t nF, const int8_t *__restrict__ cf, const int32_t *__restrict__ rank,
-                            int32_t *__restrict__ perm, int32_t *__restrict__ iperm) {
+// Level order: F points by rank, then C points, then terminal rows (batch).
+__global__ void k_make_perm(int32_t n, int32_t nF, int32_t nC, const int8_t *__restrict__ cf,
+                            const int32_t *__restrict__ rank, int32_t *__restrict__ perm, int32_t *__restrict__ iperm) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int32_t p = cf[i] == CF_F ? rank[i] : nF + rank[i];
+    int8_t c = cf[i];
+    int32_t p = c == CF_F ? rank[i] : c == CF_C ? nF + rank[i] : nF + nC + rank[i];
     perm[i] = p;
     iperm[p] = i;
+}
+
+void make_level_perm(int32_t n, int32_t nF, int32_t nC, const int8_t *cf, const int32_t *rank, int32_t *perm,
+                     int32_t *iperm, hipStream_t s) {
+    if (n <= 0) return;
+    k_make_perm<<<grid_for(n, 256), 256, 0, s>>>(n, nF, nC, cf, rank, perm, iperm);
+    AIRG_LAUNCH_CHECK();
 }
 
 __global__ void k_perm_count(int32_t nout, const int32_t *__restrict__ src, const int32_t *__restrict__ rp,
@@ -263,6 +238,49 @@ __global__ void k_pp_fill(int32_t n, int32_t nF, const int32_t *__restrict__ npe
     }
 }
 
+Csr build_rp(const Csr &Z, int32_t nF, int32_t nC, int32_t ncols, const int32_t *niperm, hipStream_t s) {
+    Csr R;
+    R.nr = nC;
+    R.nc = ncols;
+    R.rp.alloc((size_t)nC + 1, s);
+    DBuf<int32_t> cnt((size_t)nC + 1, s);
+    if (nC > 0) {
+        k_rp_count<<<grid_for(nC, 256), 256, 0, s>>>(nC, niperm, Z.rp.p, cnt.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    R.nnz = exclusive_scan(cnt.p, R.rp.p, nC, s);
+    R.ci.alloc((size_t)R.nnz, s);
+    R.v.alloc((size_t)R.nnz, s);
+    if (nC > 0) {
+        k_rp_fill<<<grid_for(nC, 256), 256, 0, s>>>(nC, nF, niperm, Z.rp.p, Z.ci.p, Z.v.p, R.rp.p, R.ci.p, R.v.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    return R;
+}
+
+Csr build_pp(const Csr &W, int32_t nF, int32_t nC, int32_t ncols, const int32_t *nperm, hipStream_t s) {
+    Csr P;
+    int32_t rows = nF + nC;
+    P.nr = rows;
+    P.nc = ncols;
+    P.rp.alloc((size_t)rows + 1, s);
+    DBuf<int32_t> cnt((size_t)rows + 1, s);
+    if (rows > 0) {
+        k_pp_count<<<grid_for(rows, 256), 256, 0, s>>>(rows, nF, W.rp.p, cnt.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    P.nnz = exclusive_scan(cnt.p, P.rp.p, rows, s);
+    P.ci.alloc((size_t)P.nnz, s);
+    P.v.alloc((size_t)P.nnz, s);
+    if (rows > 0) {
+        k_pp_fill<<<grid_for(rows, 256), 256, 0, s>>>(rows, nF, nperm, W.rp.p, W.ci.p, W.v.p, P.rp.p, P.ci.p, P.v.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    return P;
+}
+
+namespace {
+
 void finalize(Hier &H) {
     hipStream_t s = H.s;
     int nl = H.nlev();
@@ -271,8 +289,7 @@ void finalize(Hier &H) {
         if (L.coarsest) continue;
         L.perm.alloc((size_t)L.n, s);
         L.iperm.alloc((size_t)L.n, s);
-        k_make_perm<<<grid_for(L.n, 256), 256, 0, s>>>(L.n, L.nF, L.cf.p, L.rank.p, L.perm.p, L.iperm.p);
-        AIRG_LAUNCH_CHECK();
+        make_level_perm(L.n, L.nF, L.nC, L.cf.p, L.rank.p, L.perm.p, L.iperm.p, s);
     }
     for (int l = 0; l < nl; ++l) {
         Level &L = H.L(l);
@@ -285,42 +302,8 @@ void finalize(Hier &H) {
         const int32_t *nperm = N.coarsest ? nullptr : N.perm.p;
         const int32_t *niperm = N.coarsest ? nullptr : N.iperm.p;
         L.AF = permute_fc(view(L.A), L.fidx.p, L.nF, L.cf.p, L.rank.p, L.nF, s);
-        // [Z I]
-        {
-            Csr &R = L.Rp;
-            R.nr = L.nC;
-            R.nc = L.n;
-            R.rp.alloc((size_t)L.nC + 1, s);
-            DBuf<int32_t> cnt((size_t)L.nC + 1, s);
-            if (L.nC > 0) {
-                k_rp_count<<<grid_for(L.nC, 256), 256, 0, s>>>(L.nC, niperm, L.Z.rp.p, cnt.p);
-                AIRG_LAUNCH_CHECK();
-            }
-            R.nnz = exclusive_scan(cnt.p, R.rp.p, L.nC, s);
-            R.ci.alloc((size_t)R.nnz, s);
-            R.v.alloc((size_t)R.nnz, s);
-            if (L.nC > 0) {
-                k_rp_fill<<<grid_for(L.nC, 256), 256, 0, s>>>(L.nC, L.nF, niperm, L.Z.rp.p, L.Z.ci.p, L.Z.v.p, R.rp.p,
-                                                             R.ci.p, R.v.p);
-                AIRG_LAUNCH_CHECK();
-            }
-        }
-        // [W; I]
-        {
-            Csr &P = L.Pp;
-            P.nr = L.n;
-            P.nc = L.nC;
-            P.rp.alloc((size_t)L.n + 1, s);
-            DBuf<int32_t> cnt((size_t)L.n + 1, s);
-            k_pp_count<<<grid_for(L.n, 256), 256, 0, s>>>(L.n, L.nF, L.W.rp.p, cnt.p);
-            AIRG_LAUNCH_CHECK();
-            P.nnz = exclusive_scan(cnt.p, P.rp.p, L.n, s);
-            P.ci.alloc((size_t)P.nnz, s);
-            P.v.alloc((size_t)P.nnz, s);
-            k_pp_fill<<<grid_for(L.n, 256), 256, 0, s>>>(L.n, L.nF, nperm, L.W.rp.p, L.W.ci.p, L.W.v.p, P.rp.p,
-                                                        P.ci.p, P.v.p);
-            AIRG_LAUNCH_CHECK();
-        }
+        L.Rp = build_rp(L.Z, L.nF, L.nC, L.n, niperm, s);
+        L.Pp = build_pp(L.W, L.nF, L.nC, L.nC, nperm, s);
         make_f32(L.AF, s);
         make_f32(L.Rp, s);
         make_f32(L.Pp, s);

@@ -1,12 +1,13 @@
 // Two-phase sparse matrix product C = A B for gfx950 with LDS hash rows.
 //
-// Rows are binned by their product-count upper bound ub_i = sum_k |B_k|.
-// Short A rows with few products: one thread per row merging the sorted B
-// rows.  Other small rows: one G-lane group per row with a private hash table
-// in LDS.
-// Larger rows: one workgroup per row (table in LDS up to 8192 slots, in
-// global scratch beyond).  The symbolic pass counts distinct columns, the
-// numeric pass accumulates.  Accumulation is deterministic: the entries of
+// Symbolic pass: rows are binned by their product-count upper bound
+// ub_i = sum_k |B_k| and their distinct columns counted by a G-lane group (or
+// a whole workgroup) inserting columns into a hash table of at least 2 ub
+// slots in LDS (global scratch beyond 8192 products).
+// Numeric pass: rows are binned again by their exact length cnt_i, so the
+// value table needs only 2 cnt slots however many products collide in it:
+// the group accumulates, compacts the occupied slots in place and
+// bitonic-sorts them by column.  Accumulation is deterministic: the entries of
 // the A row are taken one at a time in ascending order and the lanes spread
 // over the B row, whose columns are distinct, so every output entry receives
 // its products in ascending k order, without contraction -- the same order
@@ -18,7 +19,6 @@
 namespace airg {
 
 constexpr int32_t kEmpty = -1;
-constexpr int kMergeLists = 16;
 
 __device__ inline uint32_t hash_slot(int32_t c, uint32_t mask) { return ((uint32_t)c * 2654435761u) & mask; }
 
@@ -38,6 +38,56 @@ __device__ inline uint32_t hash_insert(int32_t *keys, uint32_t mask, int32_t c, 
     }
 }
 
+// Symbolic bins by ub.
+enum : int8_t { SB_EMPTY = 0, SB_G4, SB_G8, SB_G16, SB_G32, SB_G64, SB_BLOCK, SB_GLOBAL, SB_N };
+// Numeric bins by the exact row length.
+enum : int8_t { NB_EMPTY = 0, NB_G4, NB_G8, NB_G16, NB_G64, NB_BLOCK4K, NB_BLOCK8K, NB_GLOBAL, NB_N };
+
+// Visits the products of row `row` of A with B: for each A entry in
+// ascending order, f(column, a_ik * b_kj) on the lanes holding the entries of
+// B row k.  The A entries are loaded G at a time and broadcast by shuffles,
+// and the first B entries of the next A entry are fetched while the current
+// one is handled.  ORDERED puts a wave-scope barrier between A entries, so
+// that the updates of one table slot happen in ascending k order.
+template <int G, bool ORDERED, bool VALUES, class F>
+__device__ inline void for_products(int32_t row, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
+                                    const double *__restrict__ av, const int32_t *__restrict__ brp,
+                                    const int32_t *__restrict__ bci, const double *__restrict__ bv, F &&f) {
+#pragma clang fp contract(off)
+    const int lane = group_lane<G>();
+    const int32_t a0 = arp[row], a1 = arp[row + 1];
+    for (int32_t kc = a0; kc < a1; kc += G) {
+        const int32_t my = kc + lane;
+        const bool in = my < a1;
+        const int32_t kk = in ? aci[my] : 0;
+        const double aa = VALUES && in ? av[my] : 0.0;
+        const int32_t bb0 = in ? brp[kk] : 0, bb1 = in ? brp[kk + 1] : 0;
+        const int nA = a1 - kc < G ? (int)(a1 - kc) : G;
+        int32_t b1 = __shfl(bb1, 0, G);
+        int32_t kb = __shfl(bb0, 0, G) + lane;
+        double a = VALUES ? __shfl(aa, 0, G) : 0.0;
+        int32_t cc = kb < b1 ? bci[kb] : -1;
+        double vv = VALUES && kb < b1 ? bv[kb] : 0.0;
+        for (int q = 0; q < nA; ++q) {
+            const int qn = q + 1 < nA ? q + 1 : q;
+            const int32_t nb1 = __shfl(bb1, qn, G);
+            const int32_t nkb = __shfl(bb0, qn, G) + lane;
+            const double na = VALUES ? __shfl(aa, qn, G) : 0.0;
+            const bool nin = q + 1 < nA && nkb < nb1;
+            const int32_t ncc = nin ? bci[nkb] : -1;
+            const double nvv = VALUES && nin ? bv[nkb] : 0.0;
+            if (cc >= 0) f(cc, a * vv);
+            for (int32_t k2 = kb + G; k2 < b1; k2 += G) f(bci[k2], VALUES ? a * bv[k2] : 0.0);
+            if (ORDERED) wave_sync();
+            b1 = nb1;
+            kb = nkb;
+            a = na;
+            cc = ncc;
+            vv = nvv;
+        }
+    }
+}
+
 __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
                             const int32_t *__restrict__ brp, int32_t *__restrict__ ub, int8_t *__restrict__ bin) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,99 +99,76 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
     }
     int32_t uc = u > 0x7fffffff ? 0x7fffffff : (int32_t)u;
     ub[i] = uc;
-    int32_t L = arp[i + 1] - arp[i];
-    bin[i] = uc == 0                            ? 0
-             : (L <= kMergeLists && uc <= 256) ? 7
-             : uc <= 8                         ? 1
-             : uc <= 32                        ? 2
-             : uc <= 128                       ? 3
-             : uc <= 1024                      ? 4
-             : uc <= 4096                      ? 5
-                                               : 6;
+    bin[i] = uc == 0                            ? SB_EMPTY
+             : uc <= 8                         ? SB_G4
+             : uc <= 32                        ? SB_G8
+             : uc <= 128                       ? SB_G16
+             : uc <= 512                       ? SB_G32
+             : uc <= 2048                      ? SB_G64
+             : uc <= 8192                      ? SB_BLOCK
+                                               : SB_GLOBAL;
 }
 
-// ---------------------------------------------------------- merged rows ---
-// Short A rows: one thread per row merges the (sorted) B rows of its
-// entries; the smallest head column is emitted with the products of every
-// list holding it summed in list (= ascending k) order.
-template <bool NUMERIC>
-__global__ void __launch_bounds__(256) k_spgemm_merge(const int32_t *__restrict__ list, int64_t count,
-                                                      const int32_t *__restrict__ arp,
-                                                      const int32_t *__restrict__ aci,
-                                                      const double *__restrict__ av,
-                                                      const int32_t *__restrict__ brp,
-                                                      const int32_t *__restrict__ bci,
-                                                      const double *__restrict__ bv, int32_t *__restrict__ cnt,
-                                                      const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
-                                                      double *__restrict__ cv) {
-#pragma clang fp contract(off)
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= count) return;
-    int32_t row = list[idx];
-    int32_t a0 = arp[row], L = arp[row + 1] - a0;
-    int32_t pos[kMergeLists], end[kMergeLists], head[kMergeLists];
-    double aval[kMergeLists];
-#pragma unroll
-    for (int q = 0; q < kMergeLists; ++q) {
-        pos[q] = end[q] = 0;
-        head[q] = 0x7fffffff;
-        aval[q] = 0.0;
-        if (q < L) {
-            int32_t k = aci[a0 + q];
-            pos[q] = brp[k];
-            end[q] = brp[k + 1];
-            if (NUMERIC) aval[q] = av[a0 + q];
-            if (pos[q] < end[q]) head[q] = bci[pos[q]];
-        }
-    }
-    int32_t w = NUMERIC ? crp[row] : 0;
-    int32_t emitted = 0;
-    for (;;) {
-        int32_t c = 0x7fffffff;
-#pragma unroll
-        for (int q = 0; q < kMergeLists; ++q) c = head[q] < c ? head[q] : c;
-        if (c == 0x7fffffff) break;
-        double acc = 0.0;
-        bool first = true;
-#pragma unroll
-        for (int q = 0; q < kMergeLists; ++q) {
-            if (head[q] == c) {
-                if (NUMERIC) {
-                    double p = aval[q] * bv[pos[q]];
-                    acc = first ? p : acc + p;
-                }
-                first = false;
-                ++pos[q];
-                head[q] = pos[q] < end[q] ? bci[pos[q]] : 0x7fffffff;
-            }
-        }
-        if (NUMERIC) {
-            cci[w] = c;
-            cv[w] = acc;
-            ++w;
-        }
-        ++emitted;
-    }
-    if (!NUMERIC) cnt[row] = emitted;
+__global__ void k_spgemm_nbin(int32_t m, const int32_t *__restrict__ cnt, int8_t *__restrict__ nbin) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int32_t c = cnt[i];
+    nbin[i] = c == 0                 ? NB_EMPTY
+              : c <= 8              ? NB_G4
+              : c <= 32             ? NB_G8
+              : c <= 128            ? NB_G16
+              : c <= 512            ? NB_G64
+              : c <= 2048           ? NB_BLOCK4K
+              : c <= 4096           ? NB_BLOCK8K
+                                    : NB_GLOBAL;
 }
 
 // ---------------------------------------------------------- group rows ----
-// One G-lane group per row, T-slot table per group.  NUMERIC = false counts
-// the distinct columns into cnt[row]; NUMERIC = true writes the sorted row.
-template <int G, int T, int TPB, bool NUMERIC>
-__global__ void __launch_bounds__(TPB) k_spgemm_group(const int32_t *__restrict__ list, int64_t count,
+// Symbolic: one G-lane group per row, T-slot key table per group; counts the
+// distinct columns into cnt[row].
+template <int G, int T, int TPB>
+__global__ void __launch_bounds__(TPB) k_spgemm_count(const int32_t *__restrict__ list, int64_t count,
                                                       const int32_t *__restrict__ arp,
                                                       const int32_t *__restrict__ aci,
-                                                      const double *__restrict__ av,
                                                       const int32_t *__restrict__ brp,
-                                                      const int32_t *__restrict__ bci,
-                                                      const double *__restrict__ bv, int32_t *__restrict__ cnt,
-                                                      const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
-                                                      double *__restrict__ cv) {
+                                                      const int32_t *__restrict__ bci, int32_t *__restrict__ cnt) {
+    constexpr int NG = TPB / G;
+    __shared__ int32_t Ks[NG][T];
+    int gid = threadIdx.x / G;
+    int lane = group_lane<G>();
+    int64_t idx = (int64_t)blockIdx.x * NG + gid;
+    if (idx >= count) return;
+    int32_t row = list[idx];
+    int32_t *keys = Ks[gid];
+    for (int t = lane; t < T; t += G) keys[t] = kEmpty;
+    wave_sync();
+    int fresh_cnt = 0;
+    for_products<G, false, false>(row, arp, aci, nullptr, brp, bci, nullptr, [&](int32_t c, double) {
+        bool fresh;
+        hash_insert(keys, T - 1, c, &fresh);
+        fresh_cnt += fresh;
+    });
+    fresh_cnt = group_sum<G>(fresh_cnt);
+    if (lane == 0) cnt[row] = fresh_cnt;
+}
+
+// Numeric: one G-lane group per row of known length w <= T/2.  The products
+// are accumulated in a T-slot table; the occupied slots are then moved to the
+// front of the table (in place, G slots at a time: a slot never moves to a
+// higher index) and bitonic-sorted by column, and the row is written out.
+template <int G, int T, int TPB>
+__global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__ list, int64_t count,
+                                                     const int32_t *__restrict__ arp,
+                                                     const int32_t *__restrict__ aci,
+                                                     const double *__restrict__ av,
+                                                     const int32_t *__restrict__ brp,
+                                                     const int32_t *__restrict__ bci,
+                                                     const double *__restrict__ bv, const int32_t *__restrict__ crp,
+                                                     int32_t *__restrict__ cci, double *__restrict__ cv) {
 #pragma clang fp contract(off)
     constexpr int NG = TPB / G;
     __shared__ int32_t Ks[NG][T];
-    __shared__ double Vs[NG][NUMERIC ? T : 1];
+    __shared__ double Vs[NG][T];
     int gid = threadIdx.x / G;
     int lane = group_lane<G>();
     int64_t idx = (int64_t)blockIdx.x * NG + gid;
@@ -151,39 +178,57 @@ __global__ void __launch_bounds__(TPB) k_spgemm_group(const int32_t *__restrict_
     double *vals = Vs[gid];
     for (int t = lane; t < T; t += G) {
         keys[t] = kEmpty;
-        if (NUMERIC) vals[t] = 0.0;
+        vals[t] = 0.0;
     }
     wave_sync();
-    int fresh_cnt = 0;
-    for (int32_t ka = arp[row]; ka < arp[row + 1]; ++ka) {
-        int32_t k = aci[ka];
-        double a = NUMERIC ? av[ka] : 0.0;
-        for (int32_t kb = brp[k] + lane; kb < brp[k + 1]; kb += G) {
-            bool fresh;
-            uint32_t s = hash_insert(keys, T - 1, bci[kb], &fresh);
-            fresh_cnt += fresh;
-            if (NUMERIC) vals[s] = vals[s] + a * bv[kb];
+    for_products<G, true, true>(row, arp, aci, av, brp, bci, bv, [&](int32_t c, double p) {
+        bool fresh;
+        uint32_t s = hash_insert(keys, T - 1, c, &fresh);
+        vals[s] = vals[s] + p;
+    });
+    wave_sync();
+    int w = 0;
+    for (int t0 = 0; t0 < T; t0 += G) {
+        int32_t key = keys[t0 + lane];
+        double val = vals[t0 + lane];
+        bool occ = key != kEmpty;
+        int tot;
+        int pos = w + group_prefix<G>(occ, &tot);
+        wave_sync();
+        if (occ) {
+            keys[pos] = key;
+            vals[pos] = val;
         }
         wave_sync();
+        w += tot;
     }
-    if (!NUMERIC) {
-        fresh_cnt = group_sum<G>(fresh_cnt);
-        if (lane == 0) cnt[row] = fresh_cnt;
-        return;
-    }
-    // rank each occupied slot among the occupied keys; ranks give the
-    // ascending column order of the output row
-    int32_t base = crp[row];
-    for (int t = lane; t < T; t += G) {
-        int32_t key = keys[t];
-        if (key == kEmpty) continue;
-        int r = 0;
-        for (int u = 0; u < T; ++u) {
-            int32_t o = keys[u];
-            r += (o != kEmpty) & (o < key);
+    int P = 1;
+    while (P < w) P <<= 1;
+    for (int t = w + lane; t < P; t += G) keys[t] = 0x7fffffff;
+    wave_sync();
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < P; t += G) {
+                int q = t ^ j;
+                if (q > t) {
+                    bool up = (t & kk) == 0;
+                    int32_t x = keys[t], y = keys[q];
+                    if ((x > y) == up) {
+                        keys[t] = y;
+                        keys[q] = x;
+                        double vx = vals[t];
+                        vals[t] = vals[q];
+                        vals[q] = vx;
+                    }
+                }
+            }
+            wave_sync();
         }
-        cci[base + r] = key;
-        cv[base + r] = vals[t];
+    }
+    int32_t base = crp[row];
+    for (int t = lane; t < w; t += G) {
+        cci[base + t] = keys[t];
+        cv[base + t] = vals[t];
     }
 }
 
@@ -346,31 +391,73 @@ static uint32_t pow2_at_least(int64_t v) {
     return p;
 }
 
-template <bool NUMERIC>
-static void run_bins(const Bins &B, const CsrView &A, const CsrView &Bm, int32_t *cnt, const int32_t *crp,
-                     int32_t *cci, double *cv, const std::vector<int32_t> &ub6, hipStream_t s) {
-    auto args = [&](auto kern, unsigned grid, unsigned tpb, int b) {
-        kern<<<grid, tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
-    };
-    if (B.count(7)) args(k_spgemm_merge<NUMERIC>, grid_for(B.count(7), 256), 256, 7);
-    if (B.count(1)) args(k_spgemm_group<4, 16, 256, NUMERIC>, grid_for(B.count(1), 64), 256, 1);
-    if (B.count(2)) args(k_spgemm_group<8, 64, 256, NUMERIC>, grid_for(B.count(2), 32), 256, 2);
-    if (B.count(3)) args(k_spgemm_group<16, 256, 256, NUMERIC>, grid_for(B.count(3), 16), 256, 3);
-    if (B.count(4)) args(k_spgemm_block_lds<2048, NUMERIC>, (unsigned)B.count(4), kBlk, 4);
-    if (B.count(5)) args(k_spgemm_block_lds<8192, NUMERIC>, (unsigned)B.count(5), kBlk, 5);
+static void run_global(bool numeric, const Bins &B, int b, const std::vector<int32_t> &per_row, const CsrView &A,
+                       const CsrView &Bm, int32_t *cnt, const int32_t *crp, int32_t *cci, double *cv, hipStream_t s) {
+    // one table of 2 x per_row[r] slots (rounded up to a power of two) per row
+    std::vector<int64_t> off(per_row.size() + 1, 0);
+    for (size_t r = 0; r < per_row.size(); ++r) off[r + 1] = off[r] + pow2_at_least(2 * (int64_t)per_row[r]);
+    DBuf<int64_t> toff(off.size(), s);
+    h2d(toff.p, off.data(), off.size(), s);
+    DBuf<int32_t> gk((size_t)off.back(), s);
+    DBuf<double> gv(numeric ? (size_t)off.back() : 1, s);
+    if (numeric)
+        k_spgemm_block_global<true><<<(unsigned)B.count(b), kBlk, 0, s>>>(
+            B.list(b), B.count(b), toff.p, gk.p, gv.p, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
+    else
+        k_spgemm_block_global<false><<<(unsigned)B.count(b), kBlk, 0, s>>>(
+            B.list(b), B.count(b), toff.p, gk.p, gv.p, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
     AIRG_LAUNCH_CHECK();
-    if (B.count(6)) {
-        // global tables: 2 ub rounded up to a power of two per row
-        std::vector<int64_t> off(ub6.size() + 1, 0);
-        for (size_t r = 0; r < ub6.size(); ++r) off[r + 1] = off[r] + pow2_at_least(2 * (int64_t)ub6[r]);
-        DBuf<int64_t> toff(off.size(), s);
-        h2d(toff.p, off.data(), off.size(), s);
-        DBuf<int32_t> gk((size_t)off.back(), s);
-        DBuf<double> gv(NUMERIC ? (size_t)off.back() : 1, s);
-        k_spgemm_block_global<NUMERIC><<<(unsigned)B.count(6), kBlk, 0, s>>>(
-            B.list(6), B.count(6), toff.p, gk.p, gv.p, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
-        AIRG_LAUNCH_CHECK();
-    }
+}
+
+// per-row values of v at the rows of bin b (host copy)
+static std::vector<int32_t> gather_bin(const Bins &B, int b, const int32_t *v, int32_t m, hipStream_t s) {
+    std::vector<int32_t> rows((size_t)B.count(b)), h((size_t)m), out(rows.size());
+    d2h(rows.data(), B.list(b), rows.size(), s);
+    d2h(h.data(), v, (size_t)m, s);
+    for (size_t r = 0; r < rows.size(); ++r) out[r] = h[rows[r]];
+    return out;
+}
+
+static void run_symbolic(const Bins &B, const CsrView &A, const CsrView &Bm, int32_t *cnt, const int32_t *ub,
+                         int32_t m, hipStream_t s) {
+    auto grp = [&](auto kern, int b, int rows_per_block, unsigned tpb) {
+        if (B.count(b))
+            kern<<<grid_for(B.count(b), rows_per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, Bm.rp,
+                                                                      Bm.ci, cnt);
+    };
+    grp(k_spgemm_count<4, 16, 256>, SB_G4, 64, 256);
+    grp(k_spgemm_count<8, 64, 256>, SB_G8, 32, 256);
+    grp(k_spgemm_count<16, 256, 256>, SB_G16, 16, 256);
+    grp(k_spgemm_count<32, 1024, 256>, SB_G32, 8, 256);
+    grp(k_spgemm_count<64, 4096, 128>, SB_G64, 2, 128);
+    if (B.count(SB_BLOCK))
+        k_spgemm_block_lds<16384, false><<<(unsigned)B.count(SB_BLOCK), kBlk, 0, s>>>(
+            B.list(SB_BLOCK), B.count(SB_BLOCK), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, nullptr, nullptr, nullptr);
+    AIRG_LAUNCH_CHECK();
+    if (B.count(SB_GLOBAL))
+        run_global(false, B, SB_GLOBAL, gather_bin(B, SB_GLOBAL, ub, m, s), A, Bm, cnt, nullptr, nullptr, nullptr, s);
+}
+
+static void run_numeric(const Bins &B, const CsrView &A, const CsrView &Bm, int32_t *cnt, const int32_t *crp,
+                        int32_t *cci, double *cv, int32_t m, hipStream_t s) {
+    auto grp = [&](auto kern, int b, int rows_per_block, unsigned tpb) {
+        if (B.count(b))
+            kern<<<grid_for(B.count(b), rows_per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v,
+                                                                      Bm.rp, Bm.ci, Bm.v, crp, cci, cv);
+    };
+    grp(k_spgemm_fill<4, 16, 256>, NB_G4, 64, 256);
+    grp(k_spgemm_fill<8, 64, 256>, NB_G8, 32, 256);
+    grp(k_spgemm_fill<16, 256, 128>, NB_G16, 8, 128);
+    grp(k_spgemm_fill<64, 1024, 64>, NB_G64, 1, 64);
+    if (B.count(NB_BLOCK4K))
+        k_spgemm_block_lds<4096, true><<<(unsigned)B.count(NB_BLOCK4K), kBlk, 0, s>>>(
+            B.list(NB_BLOCK4K), B.count(NB_BLOCK4K), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
+    if (B.count(NB_BLOCK8K))
+        k_spgemm_block_lds<8192, true><<<(unsigned)B.count(NB_BLOCK8K), kBlk, 0, s>>>(
+            B.list(NB_BLOCK8K), B.count(NB_BLOCK8K), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
+    AIRG_LAUNCH_CHECK();
+    if (B.count(NB_GLOBAL))
+        run_global(true, B, NB_GLOBAL, gather_bin(B, NB_GLOBAL, cnt, m, s), A, Bm, cnt, crp, cci, cv, s);
 }
 
 Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
@@ -381,26 +468,22 @@ Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
     C.rp.alloc((size_t)A.nr + 1, s);
     int32_t m = A.nr;
     DBuf<int32_t> ub((size_t)m + 1, s), cnt((size_t)m + 1, s);
-    DBuf<int8_t> bin((size_t)m + 1, s);
+    DBuf<int8_t> sbin((size_t)m + 1, s), nbin((size_t)m + 1, s);
     fill_zero(cnt.p, ((size_t)m + 1) * 4, s);
     if (m > 0) {
-        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, A.rp, A.ci, Bm.rp, ub.p, bin.p);
+        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, A.rp, A.ci, Bm.rp, ub.p, sbin.p);
         AIRG_LAUNCH_CHECK();
     }
-    Bins B = bin_rows(bin.p, m, 8, s);
-    std::vector<int32_t> ub6;
-    if (B.count(6)) {
-        std::vector<int32_t> rows((size_t)B.count(6)), ubh((size_t)m);
-        d2h(rows.data(), B.list(6), rows.size(), s);
-        d2h(ubh.data(), ub.p, (size_t)m, s);
-        ub6.resize(rows.size());
-        for (size_t r = 0; r < rows.size(); ++r) ub6[r] = ubh[rows[r]];
-    }
-    run_bins<false>(B, A, Bm, cnt.p, nullptr, nullptr, nullptr, ub6, s);
+    Bins SB = bin_rows(sbin.p, m, SB_N, s);
+    run_symbolic(SB, A, Bm, cnt.p, ub.p, m, s);
     C.nnz = exclusive_scan(cnt.p, C.rp.p, m, s);
     C.ci.alloc((size_t)C.nnz, s);
     C.v.alloc((size_t)C.nnz, s);
-    run_bins<true>(B, A, Bm, cnt.p, C.rp.p, C.ci.p, C.v.p, ub6, s);
+    if (C.nnz == 0) return C;
+    k_spgemm_nbin<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.p, nbin.p);
+    AIRG_LAUNCH_CHECK();
+    Bins NB = bin_rows(nbin.p, m, NB_N, s);
+    run_numeric(NB, A, Bm, cnt.p, C.rp.p, C.ci.p, C.v.p, m, s);
     return C;
 }
 

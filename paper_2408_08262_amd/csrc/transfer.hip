@@ -55,7 +55,7 @@ __global__ void k_p_count(int32_t n, const int8_t *__restrict__ cf, const int32_
         cntP[i] = has;
         cntW[rank[i]] = has;
     } else {
-        cntP[i] = 1;
+        cntP[i] = cf[i] == CF_C;   // terminal rows of a batch have no prolongation
     }
 }
 
@@ -74,7 +74,7 @@ __global__ void k_p_fill(int32_t n, const int8_t *__restrict__ cf, const int32_t
             wci[wrp[r]] = c;
             wv[wrp[r]] = wval[r];
         }
-    } else {
+    } else if (cf[i] == CF_C) {
         pci[prp[i]] = r;
         pv[prp[i]] = 1.0;
     }

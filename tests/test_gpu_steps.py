@@ -278,33 +278,47 @@ def test_level_build_bit_exact_given_coefficients(k):
 
 
 def test_spgemm_every_bin_bit_exact():
-    """Rows built to land in each product-count bin, with short and long A rows."""
+    """Rows built to land in every bin of both passes: product counts (ub)
+    from 1 to ~12000 with short and long A rows, and output lengths from 1 to
+    ~4500, including rows whose products collide onto few columns."""
     import scipy.sparse as sp
     rng = np.random.default_rng(21)
-    k, n = 3000, 5000
-    blen = np.concatenate([np.zeros(100, int), 1 + (np.arange(k - 100) % 60)])
+    n = 5000
+    blen = np.concatenate([np.zeros(100, int), 1 + (np.arange(2900) % 60), np.full(100, 40)])
+    k = len(blen)
     rows, cols, vals = [], [], []
     for r in range(k):
-        c = np.sort(rng.choice(n, size=blen[r], replace=False))
+        pool = 64 if r >= 3000 else n            # the last 100 rows share 64 columns
+        c = np.sort(rng.choice(pool, size=blen[r], replace=False))
         rows += [r] * len(c)
         cols += c.tolist()
         vals += rng.standard_normal(len(c)).tolist()
     B = sp.csr_matrix((vals, (rows, cols)), shape=(k, n))
-    by_len = {L: np.nonzero(blen == L)[0] for L in np.unique(blen)}
+    by_len = {L: np.nonzero(blen[:3000] == L)[0] for L in np.unique(blen[:3000])}
+    shared = np.arange(3000, 3100)
     plans = [(17, [0] * 16 + [1]),          # ub 1, long A row
-             (20, [1] * 20), (20, [5] * 20), (20, [40] * 20), (60, [50] * 60), (100, [60] * 100),
-             (5, [2] * 5), (12, [20] * 12), (16, [16] * 16)]
+             (20, [1] * 20), (20, [5] * 20), (20, [20] * 20), (20, [40] * 20), (60, [50] * 60),
+             (100, [60] * 100), (300, list(range(30, 61)) * 10),
+             (5, [2] * 5), (12, [20] * 12), (16, [16] * 16), (50, "shared"), (8, "shared")]
     arow, acol, aval = [], [], []
-    for i in range(200):
+    for i in range(260):
         L, lens = plans[i % len(plans)]
-        picks = np.unique([rng.choice(by_len[l]) for l in lens])
+        if lens == "shared":
+            picks = np.sort(rng.choice(shared, size=L, replace=False))
+        else:
+            picks = np.unique([rng.choice(by_len[l]) for l in lens])
         arow += [i] * len(picks)
         acol += picks.tolist()
         aval += rng.standard_normal(len(picks)).tolist()
-    Am = sp.csr_matrix((aval, (arow, acol)), shape=(200, k))
+    Am = sp.csr_matrix((aval, (arow, acol)), shape=(260, k))
     Am.sort_indices()
     B.sort_indices()
+    ub = np.array([sum(blen[j] for j in Am.indices[Am.indptr[i]:Am.indptr[i + 1]]) for i in range(260)])
+    assert ub.max() > 8192 and (ub == 1).any()
     A = (Am.indptr, Am.indices, Am.data, k)
     Bt = (B.indptr, B.indices, B.data, n)
     got = airg.airg_spgemm(airg.to_device(*A[:3]), airg.to_device(*Bt[:3]), k, n).to_host()
+    want = O.spgemm(A, Bt)
+    lens = np.diff(want[0])
+    assert lens.max() > 4096 and (lens[ub > 1000] < 100).any()
     csr_equal(got, O.spgemm(A, Bt))
