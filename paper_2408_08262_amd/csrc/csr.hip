@@ -5,6 +5,8 @@
 #include <mutex>
 #include <tuple>
 
+#include <hip/hip_ext.h>
+
 #include "csr.hpp"
 #include "group.hpp"
 
@@ -183,26 +185,32 @@ __global__ void __launch_bounds__(kStreamRows) k_spmv_stream(int32_t nr, const i
     }
 }
 
+// e0/e1 (timed launches): events stamped by the kernel dispatch itself at
+// the kernel's start and end, so their interval is the kernel's own duration.
 template <int TAG, class VT, class XT>
 static void spmv_t(int32_t nr, int64_t nnz, const int32_t *rp, const int32_t *ci, const VT *v, const XT *x, XT *y,
-                   const XT *z, int mode, hipStream_t s, int lanes) {
+                   const XT *z, int mode, hipStream_t s, int lanes, hipEvent_t e0 = nullptr,
+                   hipEvent_t e1 = nullptr) {
     if (nr == 0) return;
+    auto launch = [&](auto kern, unsigned grid) {
+        if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, e0, e1, 0, nr, rp, ci, v, x, y, z);
+        else kern<<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
+    };
     if (lanes == 0 && nr >= kStreamMinRows && (double)nnz <= 16.0 * (double)nr) {
+        static_assert(kStreamRows == 256, "stream SpMV launches 256-thread workgroups");
         unsigned grid = grid_for(xcd_grid((nr + kStreamRows - 1) / kStreamRows), 1);
-        if (mode == SPMV_SET) k_spmv_stream<VT, XT, SPMV_SET, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
-        else if (mode == SPMV_ZMINUS)
-            k_spmv_stream<VT, XT, SPMV_ZMINUS, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
-        else k_spmv_stream<VT, XT, SPMV_ADD, TAG><<<grid, kStreamRows, 0, s>>>(nr, rp, ci, v, x, y, z);
+        if (mode == SPMV_SET) launch(k_spmv_stream<VT, XT, SPMV_SET, TAG>, grid);
+        else if (mode == SPMV_ZMINUS) launch(k_spmv_stream<VT, XT, SPMV_ZMINUS, TAG>, grid);
+        else launch(k_spmv_stream<VT, XT, SPMV_ADD, TAG>, grid);
         AIRG_LAUNCH_CHECK();
         return;
     }
     int g = lanes > 0 ? lanes : lanes_for(nnz, nr);
     dispatch_group(g, [&]<int G>() {
         unsigned grid = grid_for((int64_t)nr * G, 256);
-        if (mode == SPMV_SET) k_spmv<G, VT, XT, SPMV_SET, TAG><<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
-        else if (mode == SPMV_ZMINUS)
-            k_spmv<G, VT, XT, SPMV_ZMINUS, TAG><<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
-        else k_spmv<G, VT, XT, SPMV_ADD, TAG><<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
+        if (mode == SPMV_SET) launch(k_spmv<G, VT, XT, SPMV_SET, TAG>, grid);
+        else if (mode == SPMV_ZMINUS) launch(k_spmv<G, VT, XT, SPMV_ZMINUS, TAG>, grid);
+        else launch(k_spmv<G, VT, XT, SPMV_ADD, TAG>, grid);
     });
     AIRG_LAUNCH_CHECK();
 }
@@ -265,11 +273,9 @@ void spmv_top(const CsrView &A, const double *x, double *y, const double *z, int
     if (on) {
         AIRG_HIP(hipEventCreate(&e0));
         AIRG_HIP(hipEventCreate(&e1));
-        AIRG_HIP(hipEventRecord(e0, s));
     }
-    spmv_t<1, double, double>(A.nr, A.nnz, A.rp, A.ci, A.v, x, y, z, mode, s, 0);
+    spmv_t<1, double, double>(A.nr, A.nnz, A.rp, A.ci, A.v, x, y, z, mode, s, 0, e0, e1);
     if (on) {
-        AIRG_HIP(hipEventRecord(e1, s));
         double bytes = (double)A.nnz * 12.0 + 4.0 * (A.nr + 1) + 8.0 * (A.nc + A.nr + (mode != SPMV_SET ? A.nr : 0));
         std::lock_guard<std::mutex> lk(g_top.mu);
         g_top.spans.emplace_back(e0, e1, bytes);
