@@ -118,6 +118,11 @@ struct CsrView {
 };
 inline CsrView view(const Csr &A) { return {A.nr, A.nc, A.nnz, A.rp.p, A.ci.p, A.v.p, A.vf.p}; }
 
+// Two-phase CSR builds: the row pointers are scanned first; resolve_sizes
+// then reads nnz = rp[nr] of every listed matrix with one host
+// synchronisation and allocates their columns and values.
+void resolve_sizes(const std::vector<Csr *> &ms, hipStream_t s);
+
 // ------------------------------------------------------------- launching --
 constexpr int kWave = 64;
 inline unsigned grid_for(int64_t work, int per_block) {
@@ -176,6 +181,11 @@ inline void d2d(T *d, const T *src, size_t count, hipStream_t s) {
 }
 void fill_zero(void *d, size_t bytes, hipStream_t s);
 void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s);
+
+// Several small device int32 ranges (src[i], counts[i] values each) copied to
+// h back to back with one host synchronisation.
+void read_ints(const std::vector<const int32_t *> &src, const std::vector<int32_t> &counts, int32_t *h,
+               hipStream_t s);
 
 // --------------------------------------------------------------- scans ----
 // out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  Returns

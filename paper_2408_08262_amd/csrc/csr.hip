@@ -580,6 +580,107 @@ __global__ void __launch_bounds__(256) k_extract_fill(int32_t n, const int32_t *
     }
 }
 
+// The three blocks of the splitting in one pass: F rows give A_ff and A_fc,
+// C rows give A_cf (terminal rows give nothing).
+template <int G>
+__global__ void __launch_bounds__(256) k_extract3_count(int32_t n, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci, const int8_t *__restrict__ cf,
+                                                        const int32_t *__restrict__ rank, int32_t *__restrict__ cff,
+                                                        int32_t *__restrict__ cfc, int32_t *__restrict__ ccf) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    int8_t me = cf[row];
+    if (me != CF_F && me != CF_C) return;
+    int32_t nf = 0, nc = 0;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
+        int8_t c = cf[ci[k]];
+        nf += c == CF_F;
+        nc += c == CF_C;
+    }
+    nf = group_sum<G>(nf);
+    nc = group_sum<G>(nc);
+    if (lane == 0) {
+        if (me == CF_F) {
+            cff[rank[row]] = nf;
+            cfc[rank[row]] = nc;
+        } else {
+            ccf[rank[row]] = nf;
+        }
+    }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_extract3_fill(int32_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                       const int8_t *__restrict__ cf, const int32_t *__restrict__ rank,
+                                                       const int32_t *__restrict__ ffrp, int32_t *__restrict__ ffci,
+                                                       double *__restrict__ ffv, const int32_t *__restrict__ fcrp,
+                                                       int32_t *__restrict__ fcci, double *__restrict__ fcv,
+                                                       const int32_t *__restrict__ cfrp, int32_t *__restrict__ cfci,
+                                                       double *__restrict__ cfv) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    int8_t me = cf[row];
+    if (me != CF_F && me != CF_C) return;
+    const bool frow = me == CF_F;
+    int32_t r = rank[row];
+    int32_t wf = frow ? ffrp[r] : cfrp[r];
+    int32_t wc = frow ? fcrp[r] : 0;
+    int32_t *oci_f = frow ? ffci : cfci;
+    double *ov_f = frow ? ffv : cfv;
+    int32_t e = rp[row + 1];
+    for (int32_t base = rp[row]; base < e; base += G) {
+        int32_t k = base + lane;
+        int8_t c = CF_U;
+        int32_t j = 0;
+        if (k < e) {
+            j = ci[k];
+            c = cf[j];
+        }
+        int tf, tc;
+        int pf = group_prefix<G>(c == CF_F, &tf);
+        int pc = group_prefix<G>(frow && c == CF_C, &tc);
+        if (c == CF_F) {
+            oci_f[wf + pf] = rank[j];
+            ov_f[wf + pf] = v[k];
+        } else if (frow && c == CF_C) {
+            fcci[wc + pc] = rank[j];
+            fcv[wc + pc] = v[k];
+        }
+        wf += tf;
+        wc += tc;
+    }
+}
+
+void extract_fc_blocks(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, Csr &Aff,
+                       Csr &Afc, Csr &Acf, hipStream_t s) {
+    Aff.nr = nF, Aff.nc = nF;
+    Afc.nr = nF, Afc.nc = nC;
+    Acf.nr = nC, Acf.nc = nF;
+    for (Csr *M : {&Aff, &Afc, &Acf}) M->rp.alloc((size_t)M->nr + 1, s);
+    DBuf<int32_t> cff((size_t)nF + 1, s), cfc((size_t)nF + 1, s), ccf((size_t)nC + 1, s);
+    int g = lanes_for(A.nnz, A.nr);
+    dispatch_group(g, [&]<int G>() {
+        k_extract3_count<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(A.nr, A.rp, A.ci, cf, rank, cff.p,
+                                                                             cfc.p, ccf.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(cff.p, Aff.rp.p, nF, s, false);
+    exclusive_scan(cfc.p, Afc.rp.p, nF, s, false);
+    exclusive_scan(ccf.p, Acf.rp.p, nC, s, false);
+    resolve_sizes({&Aff, &Afc, &Acf}, s);
+    dispatch_group(g, [&]<int G>() {
+        k_extract3_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(
+            A.nr, A.rp, A.ci, A.v, cf, rank, Aff.rp.p, Aff.ci.p, Aff.v.p, Afc.rp.p, Afc.ci.p, Afc.v.p, Acf.rp.p,
+            Acf.ci.p, Acf.v.p);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
 Csr extract_block(const CsrView &A, const int8_t *cf, const int32_t *rank, int8_t rowsel, int8_t colsel,
                   int32_t nrows_out, int32_t ncols_out, hipStream_t s) {
     Csr B;
@@ -903,22 +1004,27 @@ void gemv_add(const double *V, int64_t ldv, int nvec, const double *h_dev, doubl
 // per bin, an exclusive scan over the (bin, wavefront) counts gives every
 // wavefront its write offset in each bin, and pass 2 places the rows at those
 // offsets plus their ballot ranks.
-constexpr int32_t kBinSpan = 4096;
+constexpr int kBinItems = 8;                     // rows per lane
+constexpr int32_t kBinSpan = 64 * kBinItems;
 
 template <int NB>
 __global__ void __launch_bounds__(64) k_bin_count(const int8_t *__restrict__ bin, int32_t n, int32_t nw,
                                                   int32_t *__restrict__ bc) {
     const int32_t w = blockIdx.x;
     const int lane = threadIdx.x;
-    const int32_t r0 = w * kBinSpan, r1 = r0 + kBinSpan < n ? r0 + kBinSpan : n;
+    const int32_t r0 = w * kBinSpan;
+    int b[kBinItems];
+#pragma unroll
+    for (int u = 0; u < kBinItems; ++u) {
+        int32_t i = r0 + u * 64 + lane;
+        b[u] = i < n ? bin[i] : -1;
+    }
     int32_t c[NB];
 #pragma unroll
-    for (int v = 0; v < NB; ++v) c[v] = 0;
-    for (int32_t i0 = r0; i0 < r1; i0 += 64) {
-        int32_t i = i0 + lane;
-        int b = i < r1 ? bin[i] : -1;
+    for (int v = 0; v < NB; ++v) {
+        c[v] = 0;
 #pragma unroll
-        for (int v = 0; v < NB; ++v) c[v] += __popcll(__ballot(b == v));
+        for (int u = 0; u < kBinItems; ++u) c[v] += __popcll(__ballot(b[u] == v));
     }
 #pragma unroll
     for (int v = 0; v < NB; ++v)
@@ -930,18 +1036,24 @@ __global__ void __launch_bounds__(64) k_bin_scatter(const int8_t *__restrict__ b
                                                     const int32_t *__restrict__ boff, int32_t *__restrict__ rows) {
     const int32_t w = blockIdx.x;
     const int lane = threadIdx.x;
-    const int32_t r0 = w * kBinSpan, r1 = r0 + kBinSpan < n ? r0 + kBinSpan : n;
+    const int32_t r0 = w * kBinSpan;
     const uint64_t below = (1ull << lane) - 1ull;
+    int b[kBinItems];
+#pragma unroll
+    for (int u = 0; u < kBinItems; ++u) {
+        int32_t i = r0 + u * 64 + lane;
+        b[u] = i < n ? bin[i] : -1;
+    }
     int32_t base[NB];
 #pragma unroll
     for (int v = 0; v < NB; ++v) base[v] = boff[(int64_t)v * nw + w];
-    for (int32_t i0 = r0; i0 < r1; i0 += 64) {
-        int32_t i = i0 + lane;
-        int b = i < r1 ? bin[i] : -1;
+#pragma unroll
+    for (int u = 0; u < kBinItems; ++u) {
+        int32_t i = r0 + u * 64 + lane;
 #pragma unroll
         for (int v = 0; v < NB; ++v) {
-            uint64_t m = __ballot(b == v);
-            if (b == v) rows[base[v] + __popcll(m & below)] = i;
+            uint64_t m = __ballot(b[u] == v);
+            if (b[u] == v) rows[base[v] + __popcll(m & below)] = i;
             base[v] += __popcll(m);
         }
     }
@@ -954,37 +1066,63 @@ __global__ void k_bin_starts(const int32_t *__restrict__ boff, int nb, int32_t n
 }
 
 template <int NB>
-static void bin_rows_t(Bins &B, const int8_t *bin, int32_t n, hipStream_t s) {
-    const int32_t nw = (n + kBinSpan - 1) / kBinSpan;
-    const int64_t m = (int64_t)NB * nw;
-    DBuf<int32_t> bc((size_t)m + 1, s), boff((size_t)m + 1, s), tot(NB + 1, s);
-    k_bin_count<NB><<<nw, 64, 0, s>>>(bin, n, nw, bc.p);
+static void bin_begin_t(BinPlan &P, hipStream_t s) {
+    const int64_t m = (int64_t)NB * P.nw;
+    DBuf<int32_t> bc((size_t)m + 1, s);
+    P.boff.alloc((size_t)m + 1, s);
+    P.tot.alloc(NB + 1, s);
+    k_bin_count<NB><<<P.nw, 64, 0, s>>>(P.bin, P.n, P.nw, bc.p);
     AIRG_LAUNCH_CHECK();
-    exclusive_scan(bc.p, boff.p, m, s, false);
-    k_bin_starts<<<1, 64, 0, s>>>(boff.p, NB, nw, tot.p);
-    AIRG_LAUNCH_CHECK();
-    std::vector<int32_t> h(NB + 1);
-    d2h(h.data(), tot.p, NB + 1, s);
-    for (int b = 0; b <= NB; ++b) B.off[b] = h[b];
-    B.rows.alloc((size_t)std::max<int32_t>(h[NB], 1), s);
-    k_bin_scatter<NB><<<nw, 64, 0, s>>>(bin, n, nw, boff.p, B.rows.p);
+    exclusive_scan(bc.p, P.boff.p, m, s, false);
+    k_bin_starts<<<1, 64, 0, s>>>(P.boff.p, NB, P.nw, P.tot.p);
     AIRG_LAUNCH_CHECK();
 }
 
-Bins bin_rows(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
-    Bins B;
-    B.off.assign(nbins + 1, 0);
-    if (n <= 0) {
-        B.rows.alloc(1, s);
-        return B;
-    }
+template <int NB>
+static void bin_end_t(BinPlan &P, Bins &B, hipStream_t s) {
+    k_bin_scatter<NB><<<P.nw, 64, 0, s>>>(P.bin, P.n, P.nw, P.boff.p, B.rows.p);
+    AIRG_LAUNCH_CHECK();
+}
+
+template <class F>
+static void with_nbins(int nbins, F &&f) {
     switch (nbins) {
-    case 6: bin_rows_t<6>(B, bin, n, s); break;
-    case 8: bin_rows_t<8>(B, bin, n, s); break;
-    case 9: bin_rows_t<9>(B, bin, n, s); break;
+    case 6: f.template operator()<6>(); break;
+    case 8: f.template operator()<8>(); break;
+    case 9: f.template operator()<9>(); break;
     default: throw Error(ST_INVALID_ARG, "unsupported number of bins");
     }
+}
+
+BinPlan bin_rows_begin(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
+    BinPlan P;
+    P.bin = bin;
+    P.n = n;
+    P.nbins = nbins;
+    P.nw = n > 0 ? (n + kBinSpan - 1) / kBinSpan : 0;
+    if (n <= 0) {
+        P.tot.alloc((size_t)nbins + 1, s);
+        fill_zero(P.tot.p, ((size_t)nbins + 1) * 4, s);
+        return P;
+    }
+    with_nbins(nbins, [&]<int NB>() { bin_begin_t<NB>(P, s); });
+    return P;
+}
+
+Bins bin_rows_end(BinPlan &P, const int32_t *h_tot, hipStream_t s) {
+    Bins B;
+    B.off.assign(P.nbins + 1, 0);
+    for (int b = 0; b <= P.nbins; ++b) B.off[b] = h_tot[b];
+    B.rows.alloc((size_t)std::max<int32_t>(h_tot[P.nbins], 1), s);
+    if (P.n > 0) with_nbins(P.nbins, [&]<int NB>() { bin_end_t<NB>(P, B, s); });
     return B;
+}
+
+Bins bin_rows(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
+    BinPlan P = bin_rows_begin(bin, n, nbins, s);
+    std::vector<int32_t> h(nbins + 1);
+    d2h(h.data(), P.tot.p, h.size(), s);
+    return bin_rows_end(P, h.data(), s);
 }
 
 }  // namespace airg

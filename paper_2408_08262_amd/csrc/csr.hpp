@@ -51,6 +51,9 @@ void cf_index_lists(const int8_t *cf, const int32_t *rank, int32_t n, int32_t *f
 // original index, entry order preserved.
 Csr extract_block(const CsrView &A, const int8_t *cf, const int32_t *rank, int8_t rowsel, int8_t colsel,
                   int32_t nrows_out, int32_t ncols_out, hipStream_t s);
+// A_ff, A_fc and A_cf together (one pass, one host synchronisation).
+void extract_fc_blocks(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, Csr &Aff,
+                       Csr &Afc, Csr &Acf, hipStream_t s);
 
 // Keep entries with |x| >= tau * max_j |x_rj| (and the diagonal when
 // keep_diag); negate scales every kept value by -1 when set.
@@ -91,6 +94,17 @@ struct Bins {
     const int32_t *list(int b) const { return rows.p + off[b]; }
 };
 Bins bin_rows(const int8_t *bin, int32_t n, int nbins, hipStream_t s);
+// The same in two halves around the caller's own readback: begin leaves the
+// bin starts (nbins + 1 values) in tot on the device; end takes them from the
+// host and lists the rows.
+struct BinPlan {
+    const int8_t *bin = nullptr;
+    int32_t n = 0, nw = 0;
+    int nbins = 0;
+    DBuf<int32_t> boff, tot;
+};
+BinPlan bin_rows_begin(const int8_t *bin, int32_t n, int nbins, hipStream_t s);
+Bins bin_rows_end(BinPlan &P, const int32_t *h_tot, hipStream_t s);
 
 // Wavefront-scope ordering of LDS traffic among the lanes of one wave.
 __device__ inline void wave_sync() {

@@ -104,13 +104,19 @@ Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, hipStream_t s);
 void make_level_perm(int32_t n, int32_t nF, int32_t nC, const int8_t *cf, const int32_t *rank, int32_t *perm,
                      int32_t *iperm, hipStream_t s);
 // Rows src[0..nout) of A with F columns renumbered by rank and C columns as
-// nF + rank.
+// nF + rank.  The _begin/_fill halves leave the size readback to the caller
+// (resolve_sizes), so that many matrices share one synchronisation.
 Csr permute_fc(const CsrView &A, const int32_t *src, int32_t nout, const int8_t *cf, const int32_t *rank, int32_t nF,
                hipStream_t s);
+Csr permute_fc_begin(const CsrView &A, const int32_t *src, int32_t nout, hipStream_t s);
+void permute_fc_fill(Csr &B, const CsrView &A, const int32_t *src, const int8_t *cf, const int32_t *rank, int32_t nF,
+                     hipStream_t s);
 // [Z I] (nC x ncols) with rows in the next level's order (niperm, nullable).
-Csr build_rp(const Csr &Z, int32_t nF, int32_t nC, int32_t ncols, const int32_t *niperm, hipStream_t s);
+Csr build_rp_begin(const Csr &Z, int32_t nC, int32_t ncols, const int32_t *niperm, hipStream_t s);
+void build_rp_fill(Csr &R, const Csr &Z, int32_t nF, const int32_t *niperm, hipStream_t s);
 // [W; I] ((nF + nC) x ncols) in level order, columns through nperm (nullable).
-Csr build_pp(const Csr &W, int32_t nF, int32_t nC, int32_t ncols, const int32_t *nperm, hipStream_t s);
+Csr build_pp_begin(const Csr &W, int32_t nF, int32_t nC, int32_t ncols, hipStream_t s);
+void build_pp_fill(Csr &P, const Csr &W, int32_t nF, const int32_t *nperm, hipStream_t s);
 
 // Builds the full hierarchy of the canonical operator A0 (takes ownership).
 std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t seed, hipStream_t s);

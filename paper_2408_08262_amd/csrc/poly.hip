@@ -44,7 +44,8 @@ __global__ void k_gauss_seg(int32_t n, const int32_t *__restrict__ off, int nseg
 }
 
 // ------------------------------------------------------------ reductions ---
-constexpr int kQrThreads = 256;
+constexpr int kQrThreads = 256;       // column-norm reductions
+constexpr int kQrLanes = 64;          // one wavefront per QR panel
 constexpr int kQrRows = 384;          // rows per leaf: cols*384*8 <= 48 KiB of LDS
 
 template <int N>
@@ -109,24 +110,25 @@ __global__ void __launch_bounds__(kQrThreads) k_colsq_finish(const double *__res
 
 // -------------------------------------------------------------- TSQR leaf ---
 // Householder QR of a panel of `rows` (<= kQrRows) rows x cols staged in LDS
-// (column-major, zero-padded to kQrRows); the upper triangle of the result is
-// the panel's R factor, written column-major at out with leading dimension ldo.
+// (column-major, zero-padded to kQrRows) by one wavefront: the reductions are
+// wave shuffles and the LDS traffic needs no workgroup barrier.  The upper
+// triangle of the result is the panel's R factor, written column-major at out
+// with leading dimension ldo.
 __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, int rows, int cols,
-                         const double *__restrict__ scale, double *__restrict__ out, int64_t ldo, double *W,
-                         double *sh) {
+                         const double *__restrict__ scale, double *__restrict__ out, int64_t ldo, double *W) {
+    const int lane = threadIdx.x;
     for (int c = 0; c < cols; ++c) {
         double sc = scale ? scale[c] : 1.0;
-        for (int r = threadIdx.x; r < kQrRows; r += kQrThreads)
+        for (int r = lane; r < kQrRows; r += kQrLanes)
             W[c * kQrRows + r] = r < rows ? K[(int64_t)c * ldk + r0 + r] * sc : 0.0;
     }
-    __syncthreads();
+    wave_sync();
     int steps = cols < kQrRows ? cols : kQrRows;
     for (int col = 0; col < steps; ++col) {
         double *x = W + col * kQrRows;
-        double part[1] = {0.0};
-        for (int r = col + threadIdx.x; r < kQrRows; r += kQrThreads) part[0] += x[r] * x[r];
-        block_sum_vec<1>(part, 1, sh);
-        double nx2 = part[0];
+        double part = 0.0;
+        for (int r = col + lane; r < kQrRows; r += kQrLanes) part += x[r] * x[r];
+        double nx2 = group_sum<64>(part);
         double x0 = x[col];
         double nx = sqrt(nx2);
         double alpha = x0 >= 0.0 ? -nx : nx;
@@ -135,25 +137,27 @@ __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, 
             double d[kMaxPolyCols];
 #pragma unroll
             for (int c = 0; c < kMaxPolyCols; ++c) d[c] = 0.0;
-            for (int r = col + threadIdx.x; r < kQrRows; r += kQrThreads) {
+            for (int r = col + lane; r < kQrRows; r += kQrLanes) {
                 double vr = r == col ? x0 - alpha : x[r];
 #pragma unroll
                 for (int c = 0; c < kMaxPolyCols; ++c)
                     if (c > col && c < cols) d[c] += vr * W[c * kQrRows + r];
             }
-            block_sum_vec<kMaxPolyCols>(d, cols, sh);
-            for (int r = col + threadIdx.x; r < kQrRows; r += kQrThreads) {
+#pragma unroll
+            for (int c = 0; c < kMaxPolyCols; ++c)
+                if (c > col && c < cols) d[c] = group_sum<64>(d[c]);
+            for (int r = col + lane; r < kQrRows; r += kQrLanes) {
                 double vr = r == col ? x0 - alpha : x[r];
 #pragma unroll
                 for (int c = 0; c < kMaxPolyCols; ++c)
                     if (c > col && c < cols) W[c * kQrRows + r] -= (2.0 * d[c] / vv) * vr;
             }
-            __syncthreads();
-            if (threadIdx.x == 0) x[col] = alpha;
+            wave_sync();
+            if (lane == 0) x[col] = alpha;
         }
-        __syncthreads();
+        wave_sync();
     }
-    for (int idx = threadIdx.x; idx < cols * cols; idx += kQrThreads) {
+    for (int idx = lane; idx < cols * cols; idx += kQrLanes) {
         int r = idx / cols, c = idx % cols;
         double val = (r <= c && r < steps) ? W[c * kQrRows + r] : 0.0;
         out[(int64_t)c * ldo + r] = val;
@@ -162,14 +166,13 @@ __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, 
 
 // Leaf b takes rows b*kQrRows.. of K; its R is rows b*cols.. of the next
 // (column-major) stacked matrix.
-__global__ void __launch_bounds__(kQrThreads) k_tsqr_leaf(const double *__restrict__ K, int64_t n, int64_t ldk,
-                                                          int cols, const double *__restrict__ scale,
-                                                          double *__restrict__ Rs, int64_t ldr) {
+__global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf(const double *__restrict__ K, int64_t n, int64_t ldk,
+                                                        int cols, const double *__restrict__ scale,
+                                                        double *__restrict__ Rs, int64_t ldr) {
     extern __shared__ double W[];               // cols * kQrRows
-    __shared__ double sh[4 * kMaxPolyCols];
     int64_t r0 = (int64_t)blockIdx.x * kQrRows;
     int rows = (int)(n - r0 < kQrRows ? n - r0 : kQrRows);
-    qr_panel(K, ldk, r0, rows, cols, scale, Rs + (int64_t)blockIdx.x * cols, ldr, W, sh);
+    qr_panel(K, ldk, r0, rows, cols, scale, Rs + (int64_t)blockIdx.x * cols, ldr, W);
 }
 
 // Batch form: one leaf per table entry; a leaf with fin >= 0 is the last of
@@ -183,17 +186,16 @@ struct QrLeaf {
     int32_t pad;
 };
 
-__global__ void __launch_bounds__(kQrThreads) k_tsqr_leaf_tab(const double *__restrict__ K, int64_t ldk, int cols,
+__global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf_tab(const double *__restrict__ K, int64_t ldk, int cols,
                                                               const QrLeaf *__restrict__ leaves,
                                                               const double *__restrict__ scale,
                                                               double *__restrict__ Rs, int64_t ldr,
                                                               double *__restrict__ Rf) {
     extern __shared__ double W[];
-    __shared__ double sh[4 * kMaxPolyCols];
     QrLeaf L = leaves[blockIdx.x];
     const double *sc = scale ? scale + (int64_t)L.seg * cols : nullptr;
-    if (L.fin >= 0) qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rf + (int64_t)L.fin * cols * cols, cols, W, sh);
-    else qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rs + L.out, ldr, W, sh);
+    if (L.fin >= 0) qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rf + (int64_t)L.fin * cols * cols, cols, W);
+    else qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rs + L.out, ldr, W);
 }
 
 // partial[leaf * cols + c] = sum over the leaf's rows of K[:, c]^2
@@ -250,7 +252,7 @@ void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm
         if (nb < 1) nb = 1;
         int64_t out_rows = nb * cols;
         bufs[which].alloc((size_t)out_rows * cols, s);
-        k_tsqr_leaf<<<(unsigned)nb, kQrThreads, lds, s>>>(src, rows, ld, cols, scale, bufs[which].p, out_rows);
+        k_tsqr_leaf<<<(unsigned)nb, kQrLanes, lds, s>>>(src, rows, ld, cols, scale, bufs[which].p, out_rows);
         AIRG_LAUNCH_CHECK();
         src = bufs[which].p;
         rows = out_rows;
@@ -259,11 +261,15 @@ void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm
         which ^= 1;
         if (nb == 1) break;
     }
-    std::vector<double> R((size_t)cols * cols);
-    d2h(R.data(), src, (size_t)cols * cols, s);      // column-major cols x cols
+    // R (column-major cols x cols) and the norms in one transfer
+    DBuf<double> both((size_t)cols * (cols + 1), s);
+    d2d(both.p, src, (size_t)cols * cols, s);
+    d2d(both.p + (size_t)cols * cols, norm.p, (size_t)cols, s);
+    std::vector<double> R((size_t)cols * (cols + 1));
+    d2h(R.data(), both.p, R.size(), s);
     for (int r = 0; r < cols; ++r)
         for (int c = 0; c < cols; ++c) h_R[r * cols + c] = R[(size_t)c * cols + r];
-    d2h(h_colnorm, norm.p, (size_t)cols, s);
+    for (int c = 0; c < cols; ++c) h_colnorm[c] = R[(size_t)cols * cols + c];
 }
 
 // -------------------------------------------------------- least squares ---
@@ -392,7 +398,7 @@ void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, doub
         tables.emplace_back(tab.size(), s);
         h2d(tables.back().p, tab.data(), tab.size(), s);
         bufs[which].alloc((size_t)std::max<int64_t>(out_rows, 1) * cols, s);
-        k_tsqr_leaf_tab<<<(unsigned)tab.size(), kQrThreads, lds, s>>>(src, ld, cols, tables.back().p,
+        k_tsqr_leaf_tab<<<(unsigned)tab.size(), kQrLanes, lds, s>>>(src, ld, cols, tables.back().p,
                                                                      scaled ? inv.p : nullptr, bufs[which].p,
                                                                      std::max<int64_t>(out_rows, 1), Rf);
         AIRG_LAUNCH_CHECK();

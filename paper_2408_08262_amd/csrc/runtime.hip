@@ -223,7 +223,7 @@ __global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict
 constexpr int kSmallScanThreads = 1024;
 constexpr int kSmallScanItems = 8;
 constexpr int kSmallScanTile = kSmallScanThreads * kSmallScanItems;
-constexpr int64_t kSmallScan = 65536;
+constexpr int64_t kSmallScan = 16384;
 
 __device__ inline int small_scan_slot(int p) { return p + (p >> 5); }   // pads out LDS bank conflicts
 
@@ -277,6 +277,53 @@ __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(const int32_t 
     if (tid == 0) {
         out[n] = (int32_t)carry;
         *total = carry;
+    }
+}
+
+// ------------------------------------------------------ batched readback --
+// Block b copies src[b][0 .. cnt[b]) to out[off[b] ..).
+__global__ void k_gather_ints(const int32_t *const *__restrict__ src, const int32_t *__restrict__ cnt,
+                              const int32_t *__restrict__ off, int32_t *__restrict__ out) {
+    const int32_t *p = src[blockIdx.x];
+    int32_t c = cnt[blockIdx.x], o = off[blockIdx.x];
+    for (int32_t i = threadIdx.x; i < c; i += blockDim.x) out[o + i] = p[i];
+}
+
+void read_ints(const std::vector<const int32_t *> &src, const std::vector<int32_t> &counts, int32_t *h,
+               hipStream_t s) {
+    const size_t m = src.size();
+    if (m == 0) return;
+    std::vector<int32_t> off(m);
+    int32_t total = 0;
+    for (size_t i = 0; i < m; ++i) {
+        off[i] = total;
+        total += counts[i];
+    }
+    DBuf<const int32_t *> dsrc(m, s);
+    DBuf<int32_t> dcnt(m, s), doff(m, s), out((size_t)std::max(total, 1), s);
+    h2d(dsrc.p, src.data(), m, s);
+    h2d(dcnt.p, counts.data(), m, s);
+    h2d(doff.p, off.data(), m, s);
+    k_gather_ints<<<(unsigned)m, 64, 0, s>>>(dsrc.p, dcnt.p, doff.p, out.p);
+    AIRG_LAUNCH_CHECK();
+    d2h(h, out.p, (size_t)total, s);
+}
+
+void resolve_sizes(const std::vector<Csr *> &ms, hipStream_t s) {
+    std::vector<const int32_t *> src;
+    std::vector<int32_t> cnt;
+    for (Csr *M : ms) {
+        src.push_back(M->rp.p + M->nr);
+        cnt.push_back(1);
+    }
+    std::vector<int32_t> nz(ms.size());
+    read_ints(src, cnt, nz.data(), s);
+    for (size_t i = 0; i < ms.size(); ++i) {
+        AIRG_REQUIRE(nz[i] >= 0, ST_LIMIT, "prefix sum exceeds the int32 index range");
+        Csr &M = *ms[i];
+        M.nnz = nz[i];
+        M.ci.alloc((size_t)M.nnz, s);
+        M.v.alloc((size_t)M.nnz, s);
     }
 }
 

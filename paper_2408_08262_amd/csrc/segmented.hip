@@ -67,13 +67,24 @@ void finalize_seg(SegHier &H, hipStream_t s) {
         L.iperm.alloc((size_t)L.n, s);
         make_level_perm(L.n, L.nF, L.nC, L.cf.p, L.rank.p, L.perm.p, L.iperm.p, s);
     }
+    std::vector<Csr *> pending;
+    for (int l = 0; l < nl; ++l) {
+        SegLevel &L = *H.lv[l];
+        if (L.nF + L.nC == 0) continue;
+        SegLevel &N = *H.lv[l + 1];
+        L.AF = permute_fc_begin(view(L.A), L.fidx.p, L.nF, s);
+        L.Rp = build_rp_begin(L.Z, L.nC, L.n, N.iperm.p, s);
+        L.Pp = build_pp_begin(L.W, L.nF, L.nC, N.n, s);
+        pending.insert(pending.end(), {&L.AF, &L.Rp, &L.Pp});
+    }
+    resolve_sizes(pending, s);
     for (int l = 0; l < nl; ++l) {
         SegLevel &L = *H.lv[l];
         if (L.nF + L.nC > 0) {
             SegLevel &N = *H.lv[l + 1];
-            L.AF = permute_fc(view(L.A), L.fidx.p, L.nF, L.cf.p, L.rank.p, L.nF, s);
-            L.Rp = build_rp(L.Z, L.nF, L.nC, L.n, N.iperm.p, s);
-            L.Pp = build_pp(L.W, L.nF, L.nC, N.n, N.perm.p, s);
+            permute_fc_fill(L.AF, view(L.A), L.fidx.p, L.cf.p, L.rank.p, L.nF, s);
+            build_rp_fill(L.Rp, L.Z, L.nF, N.iperm.p, s);
+            build_pp_fill(L.Pp, L.W, L.nF, N.perm.p, s);
             make_f32(L.AF, s);
             make_f32(L.Rp, s);
             make_f32(L.Pp, s);
@@ -234,9 +245,8 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         L.fidx.alloc((size_t)c.nF + 1, s);
         L.cidx.alloc((size_t)c.nC + 1, s);
         cf_index_lists(L.cf.p, L.rank.p, n, L.fidx.p, L.cidx.p, s);
-        L.Aff = extract_block(view(L.A), L.cf.p, L.rank.p, CF_F, CF_F, c.nF, c.nF, s);
-        L.Afc = extract_block(view(L.A), L.cf.p, L.rank.p, CF_F, CF_C, c.nF, c.nC, s);
-        Csr Acf = extract_block(view(L.A), L.cf.p, L.rank.p, CF_C, CF_F, c.nC, c.nF, s);
+        Csr Acf;
+        extract_fc_blocks(view(L.A), L.cf.p, L.rank.p, c.nF, c.nC, L.Aff, L.Afc, Acf, s);
         tm.begin(AIRG_PHASE_POLY);
         foff.push_back(c.nF);
         {

@@ -66,9 +66,9 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     fidx.alloc((size_t)nF + 1, s);
     cidx.alloc((size_t)nC + 1, s);
     cf_index_lists(cf, rank, n, fidx.p, cidx.p, s);
-    Aff = extract_block(A, cf, rank, CF_F, CF_F, nF, nF, s);
-    if (Afc) *Afc = extract_block(A, cf, rank, CF_F, CF_C, nF, nC, s);
-    Csr Acf = extract_block(A, cf, rank, CF_C, CF_F, nC, nF, s);
+    Csr fc, Acf;
+    extract_fc_blocks(A, cf, rank, nF, nC, Aff, fc, Acf, s);
+    if (Afc) *Afc = std::move(fc);
     tm.begin(AIRG_PHASE_POLY);
     if (alpha_in) {
         poly = PolyInfo{};
@@ -163,8 +163,7 @@ __global__ void __launch_bounds__(256) k_perm_fill(int32_t nout, const int32_t *
     }
 }
 
-Csr permute_fc(const CsrView &A, const int32_t *src, int32_t nout, const int8_t *cf, const int32_t *rank, int32_t nF,
-               hipStream_t s) {
+Csr permute_fc_begin(const CsrView &A, const int32_t *src, int32_t nout, hipStream_t s) {
     Csr B;
     B.nr = nout;
     B.nc = A.nc;
@@ -174,17 +173,27 @@ Csr permute_fc(const CsrView &A, const int32_t *src, int32_t nout, const int8_t 
         k_perm_count<<<grid_for(nout, 256), 256, 0, s>>>(nout, src, A.rp, cnt.p);
         AIRG_LAUNCH_CHECK();
     }
-    B.nnz = exclusive_scan(cnt.p, B.rp.p, nout, s);
-    B.ci.alloc((size_t)B.nnz, s);
-    B.v.alloc((size_t)B.nnz, s);
-    if (nout > 0) {
-        int g = lanes_for(A.nnz, A.nr);
-        dispatch_group(g, [&]<int G>() {
-            k_perm_fill<G><<<grid_for((int64_t)nout * G, 256), 256, 0, s>>>(nout, src, A.rp, A.ci, A.v, cf, rank,
-                                                                            nF, B.rp.p, B.ci.p, B.v.p);
-        });
-        AIRG_LAUNCH_CHECK();
-    }
+    exclusive_scan(cnt.p, B.rp.p, nout, s, false);
+    return B;
+}
+
+void permute_fc_fill(Csr &B, const CsrView &A, const int32_t *src, const int8_t *cf, const int32_t *rank, int32_t nF,
+                     hipStream_t s) {
+    int32_t nout = B.nr;
+    if (nout == 0) return;
+    int g = lanes_for(A.nnz, A.nr);
+    dispatch_group(g, [&]<int G>() {
+        k_perm_fill<G><<<grid_for((int64_t)nout * G, 256), 256, 0, s>>>(nout, src, A.rp, A.ci, A.v, cf, rank, nF,
+                                                                        B.rp.p, B.ci.p, B.v.p);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
+Csr permute_fc(const CsrView &A, const int32_t *src, int32_t nout, const int8_t *cf, const int32_t *rank, int32_t nF,
+               hipStream_t s) {
+    Csr B = permute_fc_begin(A, src, nout, s);
+    resolve_sizes({&B}, s);
+    permute_fc_fill(B, A, src, cf, rank, nF, s);
     return B;
 }
 
@@ -238,7 +247,7 @@ __global__ void k_pp_fill(int32_t n, int32_t nF, const int32_t *__restrict__ npe
     }
 }
 
-Csr build_rp(const Csr &Z, int32_t nF, int32_t nC, int32_t ncols, const int32_t *niperm, hipStream_t s) {
+Csr build_rp_begin(const Csr &Z, int32_t nC, int32_t ncols, const int32_t *niperm, hipStream_t s) {
     Csr R;
     R.nr = nC;
     R.nc = ncols;
@@ -248,17 +257,18 @@ Csr build_rp(const Csr &Z, int32_t nF, int32_t nC, int32_t ncols, const int32_t 
         k_rp_count<<<grid_for(nC, 256), 256, 0, s>>>(nC, niperm, Z.rp.p, cnt.p);
         AIRG_LAUNCH_CHECK();
     }
-    R.nnz = exclusive_scan(cnt.p, R.rp.p, nC, s);
-    R.ci.alloc((size_t)R.nnz, s);
-    R.v.alloc((size_t)R.nnz, s);
-    if (nC > 0) {
-        k_rp_fill<<<grid_for(nC, 256), 256, 0, s>>>(nC, nF, niperm, Z.rp.p, Z.ci.p, Z.v.p, R.rp.p, R.ci.p, R.v.p);
-        AIRG_LAUNCH_CHECK();
-    }
+    exclusive_scan(cnt.p, R.rp.p, nC, s, false);
     return R;
 }
 
-Csr build_pp(const Csr &W, int32_t nF, int32_t nC, int32_t ncols, const int32_t *nperm, hipStream_t s) {
+void build_rp_fill(Csr &R, const Csr &Z, int32_t nF, const int32_t *niperm, hipStream_t s) {
+    int32_t nC = R.nr;
+    if (nC == 0) return;
+    k_rp_fill<<<grid_for(nC, 256), 256, 0, s>>>(nC, nF, niperm, Z.rp.p, Z.ci.p, Z.v.p, R.rp.p, R.ci.p, R.v.p);
+    AIRG_LAUNCH_CHECK();
+}
+
+Csr build_pp_begin(const Csr &W, int32_t nF, int32_t nC, int32_t ncols, hipStream_t s) {
     Csr P;
     int32_t rows = nF + nC;
     P.nr = rows;
@@ -269,14 +279,15 @@ Csr build_pp(const Csr &W, int32_t nF, int32_t nC, int32_t ncols, const int32_t 
         k_pp_count<<<grid_for(rows, 256), 256, 0, s>>>(rows, nF, W.rp.p, cnt.p);
         AIRG_LAUNCH_CHECK();
     }
-    P.nnz = exclusive_scan(cnt.p, P.rp.p, rows, s);
-    P.ci.alloc((size_t)P.nnz, s);
-    P.v.alloc((size_t)P.nnz, s);
-    if (rows > 0) {
-        k_pp_fill<<<grid_for(rows, 256), 256, 0, s>>>(rows, nF, nperm, W.rp.p, W.ci.p, W.v.p, P.rp.p, P.ci.p, P.v.p);
-        AIRG_LAUNCH_CHECK();
-    }
+    exclusive_scan(cnt.p, P.rp.p, rows, s, false);
     return P;
+}
+
+void build_pp_fill(Csr &P, const Csr &W, int32_t nF, const int32_t *nperm, hipStream_t s) {
+    int32_t rows = P.nr;
+    if (rows == 0) return;
+    k_pp_fill<<<grid_for(rows, 256), 256, 0, s>>>(rows, nF, nperm, W.rp.p, W.ci.p, W.v.p, P.rp.p, P.ci.p, P.v.p);
+    AIRG_LAUNCH_CHECK();
 }
 
 namespace {
@@ -291,6 +302,23 @@ void finalize(Hier &H) {
         L.iperm.alloc((size_t)L.n, s);
         make_level_perm(L.n, L.nF, L.nC, L.cf.p, L.rank.p, L.perm.p, L.iperm.p, s);
     }
+    // all levels' solve operators: counts and scans, one size readback, fills
+    std::vector<Csr *> pending;
+    for (int l = 0; l < nl; ++l) {
+        Level &L = H.L(l);
+        if (L.coarsest) continue;
+        Level &N = H.L(l + 1);
+        L.AF = permute_fc_begin(view(L.A), L.fidx.p, L.nF, s);
+        L.Rp = build_rp_begin(L.Z, L.nC, L.n, N.coarsest ? nullptr : N.iperm.p, s);
+        L.Pp = build_pp_begin(L.W, L.nF, L.nC, L.nC, s);
+        pending.insert(pending.end(), {&L.AF, &L.Rp, &L.Pp});
+    }
+    Level &T = H.L(0);
+    if (!T.coarsest) {
+        H.A0p = permute_fc_begin(view(T.A), T.iperm.p, T.n, s);
+        pending.push_back(&H.A0p);
+    }
+    resolve_sizes(pending, s);
     for (int l = 0; l < nl; ++l) {
         Level &L = H.L(l);
         if (L.coarsest) {
@@ -299,21 +327,18 @@ void finalize(Hier &H) {
             continue;
         }
         Level &N = H.L(l + 1);
-        const int32_t *nperm = N.coarsest ? nullptr : N.perm.p;
-        const int32_t *niperm = N.coarsest ? nullptr : N.iperm.p;
-        L.AF = permute_fc(view(L.A), L.fidx.p, L.nF, L.cf.p, L.rank.p, L.nF, s);
-        L.Rp = build_rp(L.Z, L.nF, L.nC, L.n, niperm, s);
-        L.Pp = build_pp(L.W, L.nF, L.nC, L.nC, nperm, s);
+        permute_fc_fill(L.AF, view(L.A), L.fidx.p, L.cf.p, L.rank.p, L.nF, s);
+        build_rp_fill(L.Rp, L.Z, L.nF, N.coarsest ? nullptr : N.iperm.p, s);
+        build_pp_fill(L.Pp, L.W, L.nF, N.coarsest ? nullptr : N.perm.p, s);
         make_f32(L.AF, s);
         make_f32(L.Rp, s);
         make_f32(L.Pp, s);
         make_f32(L.Ainv, s);
     }
-    Level &T = H.L(0);
     if (T.coarsest) {
         H.top_permuted = false;
     } else {
-        H.A0p = permute_fc(view(T.A), T.iperm.p, T.n, T.cf.p, T.rank.p, T.nF, s);
+        permute_fc_fill(H.A0p, view(T.A), T.iperm.p, T.cf.p, T.rank.p, T.nF, s);
         H.top_permuted = true;
     }
     // work vectors

@@ -476,13 +476,21 @@ Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
     }
     Bins SB = bin_rows(sbin.p, m, SB_N, s);
     run_symbolic(SB, A, Bm, cnt.p, ub.p, m, s);
-    C.nnz = exclusive_scan(cnt.p, C.rp.p, m, s);
+    exclusive_scan(cnt.p, C.rp.p, m, s, false);
+    if (m > 0) {
+        k_spgemm_nbin<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.p, nbin.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    // nnz and the numeric bin starts come back in one readback
+    BinPlan NP = bin_rows_begin(nbin.p, m, NB_N, s);
+    std::vector<int32_t> h(NB_N + 2);
+    read_ints({C.rp.p + m, NP.tot.p}, {1, NB_N + 1}, h.data(), s);
+    AIRG_REQUIRE(h[0] >= 0, ST_LIMIT, "product exceeds the int32 index range");
+    C.nnz = h[0];
     C.ci.alloc((size_t)C.nnz, s);
     C.v.alloc((size_t)C.nnz, s);
     if (C.nnz == 0) return C;
-    k_spgemm_nbin<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.p, nbin.p);
-    AIRG_LAUNCH_CHECK();
-    Bins NB = bin_rows(nbin.p, m, NB_N, s);
+    Bins NB = bin_rows_end(NP, h.data() + 1, s);
     run_numeric(NB, A, Bm, cnt.p, C.rp.p, C.ci.p, C.v.p, m, s);
     return C;
 }

@@ -96,15 +96,12 @@ void onepoint_prolongator(const CsrView &A, const int8_t *cf, const int32_t *ran
     P->nr = n;
     P->nc = nC;
     P->rp.alloc((size_t)n + 1, s);
-    P->nnz = exclusive_scan(cntP.p, P->rp.p, n, s);
-    P->ci.alloc((size_t)P->nnz, s);
-    P->v.alloc((size_t)P->nnz, s);
+    exclusive_scan(cntP.p, P->rp.p, n, s, false);
     W->nr = nF;
     W->nc = nC;
     W->rp.alloc((size_t)nF + 1, s);
-    W->nnz = exclusive_scan(cntW.p, W->rp.p, nF, s);
-    W->ci.alloc((size_t)W->nnz, s);
-    W->v.alloc((size_t)W->nnz, s);
+    exclusive_scan(cntW.p, W->rp.p, nF, s, false);
+    resolve_sizes({P, W}, s);
     k_p_fill<<<grid_for(n, 256), 256, 0, s>>>(n, cf, rank, wcol.p, wval.p, P->rp.p, P->ci.p, P->v.p, W->rp.p,
                                               W->ci.p, W->v.p);
     AIRG_LAUNCH_CHECK();
