@@ -247,7 +247,11 @@ def batched(a, airg, torch):
             "n=%d, nnz=%d" % (n, int(rp[-1])))
     extra = {"setup_s": round(stb["setup_seconds"], 4), "solve_s": round(infob["seconds"], 4),
              "iterations": infob["iterations"], "rel_residual": infob["rel_residual"], "levels": stb["levels"],
-             "fp64_comparison": fp64}
+             "complexity": {"grid": round(stb["grid_complexity"], 3),
+                            "operator": round(stb["operator_complexity"], 3),
+                            "storage": round(stb["storage_complexity"], 3)},
+             "phase_seconds": {kk: round(v, 4) for kk, v in stb["phase_seconds"].items()},
+             "vcycle_bytes_fp32": stb["vcycle_bytes_fp32"], "fp64_comparison": fp64}
     cfg = {"workload": desc, "form": "batched FGMRES(30) FP64 per (segment, rhs) + batched FP32 V-cycle, "
                                      "one SpMM launch per stage, HIP graph, autotuned kernels",
            "rtol": a.rtol, "parallelism": "single GPU"}

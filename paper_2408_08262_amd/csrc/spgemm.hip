@@ -152,10 +152,78 @@ __global__ void __launch_bounds__(TPB) k_spgemm_count(const int32_t *__restrict_
     if (lane == 0) cnt[row] = fresh_cnt;
 }
 
+// Bitonic sort of a group's w entries (keys distinct) held in registers: lane
+// l owns entries l*E .. l*E+E-1; exchanges within a lane are register
+// compare-swaps, between lanes shuffles.  Pads (keys INT_MAX) sort last.
+template <int E, int J>
+__device__ inline void sort_in_lane(int32_t (&k)[E], double (&v)[E], int lane, int kk) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if ((e ^ J) > e) {
+            const int p = e ^ J;
+            bool up = ((lane * E + e) & kk) == 0;
+            if ((k[e] > k[p]) == up) {
+                int32_t tk = k[e];
+                k[e] = k[p];
+                k[p] = tk;
+                double tv = v[e];
+                v[e] = v[p];
+                v[p] = tv;
+            }
+        }
+    }
+}
+
+template <int G, int E>
+__device__ inline void group_sort_store(const int32_t *keys, const double *vals, int w, int32_t *__restrict__ oci,
+                                        double *__restrict__ ov) {
+    const int lane = group_lane<G>();
+    int32_t k[E];
+    double v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        int i = lane * E + e;
+        k[e] = i < w ? keys[i] : 0x7fffffff;
+        v[e] = i < w ? vals[i] : 0.0;
+    }
+    constexpr int N = G * E;
+    for (int kk = 2; kk <= N; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j < E) {
+                if (j == 1) sort_in_lane<E, 1>(k, v, lane, kk);
+                else if (j == 2) sort_in_lane<E, 2>(k, v, lane, kk);
+                else sort_in_lane<E, 4>(k, v, lane, kk);
+            } else {
+                const int m = j / E;
+                const bool lower = (lane & m) == 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    bool up = ((lane * E + e) & kk) == 0;
+                    int32_t ok = __shfl_xor(k[e], m, G);
+                    double oval = __shfl_xor(v[e], m, G);
+                    bool take = lower == up ? ok < k[e] : ok > k[e];
+                    if (take) {
+                        k[e] = ok;
+                        v[e] = oval;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        int i = lane * E + e;
+        if (i < w) {
+            oci[i] = k[e];
+            ov[i] = v[e];
+        }
+    }
+}
+
 // Numeric: one G-lane group per row of known length w <= T/2.  The products
 // are accumulated in a T-slot table; the occupied slots are then moved to the
 // front of the table (in place, G slots at a time: a slot never moves to a
-// higher index) and bitonic-sorted by column, and the row is written out.
+// higher index), sorted by column in registers, and the row is written out.
 template <int G, int T, int TPB>
 __global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__ list, int64_t count,
                                                      const int32_t *__restrict__ arp,
@@ -202,33 +270,14 @@ __global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__
         wave_sync();
         w += tot;
     }
-    int P = 1;
-    while (P < w) P <<= 1;
-    for (int t = w + lane; t < P; t += G) keys[t] = 0x7fffffff;
-    wave_sync();
-    for (int kk = 2; kk <= P; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int t = lane; t < P; t += G) {
-                int q = t ^ j;
-                if (q > t) {
-                    bool up = (t & kk) == 0;
-                    int32_t x = keys[t], y = keys[q];
-                    if ((x > y) == up) {
-                        keys[t] = y;
-                        keys[q] = x;
-                        double vx = vals[t];
-                        vals[t] = vals[q];
-                        vals[q] = vx;
-                    }
-                }
-            }
-            wave_sync();
-        }
-    }
     int32_t base = crp[row];
-    for (int t = lane; t < w; t += G) {
-        cci[base + t] = keys[t];
-        cv[base + t] = vals[t];
+    int P = G;
+    while (P < w) P <<= 1;
+    switch (P / G) {
+    case 1: group_sort_store<G, 1>(keys, vals, w, cci + base, cv + base); break;
+    case 2: group_sort_store<G, 2>(keys, vals, w, cci + base, cv + base); break;
+    case 4: group_sort_store<G, 4>(keys, vals, w, cci + base, cv + base); break;
+    default: group_sort_store<G, 8>(keys, vals, w, cci + base, cv + base); break;
     }
 }
 
