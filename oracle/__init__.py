@@ -83,6 +83,9 @@ def lib():
             "orc_level_build": (C.c_int, [cs, P(Params), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           cs, cs, cs, cs]),
             "orc_setup": (C.c_void_p, [cs, P(Params)]),
+            "orc_level_renumeric": (C.c_int, [cs, C.c_void_p, P(Params), C.c_int32, C.c_void_p, cs, cs, cs,
+                                              C.c_void_p, cs, cs, cs, cs]),
+            "orc_resetup": (C.c_void_p, [C.c_void_p, C.c_void_p]),
             "orc_hier_free": (None, [C.c_void_p]),
             "orc_hier_levels": (C.c_int32, [C.c_void_p]),
             "orc_hier_matrix": (cs, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -343,6 +346,24 @@ def level_build(A, params, level, alpha_in=None):
     return {"cf": cf, "alpha": alpha, "Ainv": Ainv, "Z": Z, "W": W, "Ac": Ac}
 
 
+def level_renumeric(A, cf, params, level, W, Z, Ac, alpha_in=None):
+    """Numeric re-setup of one level on given patterns (W, Z, Ac: CSR tuples
+    whose values are ignored); returns dict(alpha, Ainv, Z, W, Ac)."""
+    a = _csr_in(A)
+    cf = np.ascontiguousarray(cf, np.int8)
+    w = _csr_in(W, W[3] if len(W) > 3 else None)
+    z = _csr_in(Z, Z[3] if len(Z) > 3 else None)
+    ac = _csr_in(Ac, Ac[3] if len(Ac) > 3 else None)
+    m = params.poly_order + 1
+    alpha = np.zeros(m)
+    ain = None if alpha_in is None else np.ascontiguousarray(alpha_in, np.float64)
+    outs = [_Csr() for _ in range(4)]
+    lib().orc_level_renumeric(a.ref, _ptr(cf), C.byref(params), level, None if ain is None else _ptr(ain),
+                              w.ref, z.ref, ac.ref, _ptr(alpha), *[C.byref(o) for o in outs])
+    Ainv, Zo, Wo, Aco = [_csr_out(o) for o in outs]
+    return {"alpha": alpha, "Ainv": Ainv, "Z": Zo, "W": Wo, "Ac": Aco}
+
+
 class Hierarchy:
     """Oracle AIRG hierarchy (setup) with V-cycle, Richardson and FGMRES."""
 
@@ -360,6 +381,20 @@ class Hierarchy:
         if getattr(self, "h", None):
             lib().orc_hier_free(self.h)
             self.h = None
+
+    def resetup(self, vals):
+        """Numeric re-setup with new values on the canonical level-0 pattern:
+        same CF splittings and patterns, recomputed values (a new Hierarchy)."""
+        vals = np.ascontiguousarray(vals, np.float64)
+        nnz = self.matrix(0, "A")[0][-1]
+        if vals.shape != (nnz,):
+            raise ValueError("values must match the canonical level-0 pattern")
+        out = Hierarchy.__new__(Hierarchy)
+        out._a = self._a
+        out.params = self.params
+        out.n = self.n
+        out.h = lib().orc_resetup(self.h, _ptr(vals))
+        return out
 
     @property
     def nlevels(self):

@@ -716,7 +716,7 @@ int orc_restrictor(const orc_csr *Acf, const orc_csr *Ainv, double drop_R, orc_c
 /* Galerkin coarse operator (setup step 11): A_c = R (A P) by two sparse
  * products in the full index space, P = [W; I] (n x n_C), R = [Z I]
  * (n_C x n), coarse index = C rank; then dropped by tau_A with the diagonal
- * kept. */
+ * kept (drop_A < 0: returned undropped). */
 int orc_coarse_operator(const orc_csr *A, const int8_t *cf, const orc_csr *Z, const orc_csr *W,
                         double drop_A, orc_csr *Ac)
 {
@@ -767,8 +767,13 @@ int orc_coarse_operator(const orc_csr *A, const int8_t *cf, const orc_csr *Z, co
     orc_csr AP, RAP;
     orc_spgemm(A, &P, &AP);
     orc_spgemm(&R, &AP, &RAP);
-    orc_drop(&RAP, drop_A, 1, Ac);
-    orc_csr_free(&P); orc_csr_free(&R); orc_csr_free(&AP); orc_csr_free(&RAP);
+    if (drop_A >= 0.0) {
+        orc_drop(&RAP, drop_A, 1, Ac);
+        orc_csr_free(&RAP);
+    } else {
+        *Ac = RAP;       /* the undropped product (numeric re-setup) */
+    }
+    orc_csr_free(&P); orc_csr_free(&R); orc_csr_free(&AP);
     free(fidx); free(cidx); free(frank); free(crank);
     return 0;
 }
@@ -897,6 +902,122 @@ orc_hier *orc_setup(const orc_csr *A0, const orc_params *p)
         orc_csr_free(&Acf);
     }
     return h;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Numeric re-setup (reuse of the CF splitting and the sparsity patterns)    */
+/* ------------------------------------------------------------------------ */
+/* The Results section notes that the CF splitting and the symbolic products
+ * can be reused across solves whose operators share a pattern, with a padded
+ * sparsity because the drops depend on the values.  Reading: the new
+ * hierarchy keeps every level's CF splitting and the patterns of W, Z and
+ * the coarse operators; values are recomputed on those patterns, with no
+ * drop: an entry kept before is kept (whatever its new size), an entry
+ * dropped before stays absent. */
+
+/* out[k] = X_ij for the k-th stored (i, j) of the pattern Pt, 0.0 where X
+ * stores no (i, j). */
+static void values_on_pattern(const orc_csr *X, const orc_csr *Pt, double *out)
+{
+    for (int64_t i = 0; i < Pt->nr; ++i) {
+        int64_t q = X->rp[i];
+        for (int64_t k = Pt->rp[i]; k < Pt->rp[i + 1]; ++k) {
+            int32_t j = Pt->ci[k];
+            while (q < X->rp[i + 1] && X->ci[q] < j) ++q;
+            out[k] = (q < X->rp[i + 1] && X->ci[q] == j) ? X->v[q] : 0.0;
+        }
+    }
+}
+
+static void copy_pattern(const orc_csr *Pt, orc_csr *out)
+{
+    csr_alloc(out, Pt->nr, Pt->nc, Pt->rp[Pt->nr], 1);
+    memcpy(out->rp, Pt->rp, (size_t)(Pt->nr + 1) * sizeof(int64_t));
+    memcpy(out->ci, Pt->ci, (size_t)Pt->rp[Pt->nr] * sizeof(int32_t));
+}
+
+int orc_level_renumeric(const orc_csr *A, const int8_t *cf, const orc_params *p, int32_t level,
+                        const double *alpha_in, const orc_csr *Wpat, const orc_csr *Zpat, const orc_csr *Acpat,
+                        double *alpha_out, orc_csr *Ainv, orc_csr *Z, orc_csr *W, orc_csr *Ac)
+{
+    int32_t m = p->poly_order + 1;
+    int64_t n = A->nr;
+    orc_csr Aff, Acf, prod;
+    orc_submatrix(A, cf, ORC_F, ORC_F, &Aff);
+    orc_submatrix(A, cf, ORC_C, ORC_F, &Acf);
+    if (alpha_in) memcpy(alpha_out, alpha_in, (size_t)m * sizeof(double));
+    else orc_gmres_poly(&Aff, p->seed, level, m, alpha_out);
+    orc_poly_fixed_sparsity(&Aff, alpha_out, m, Ainv);
+    /* Z = -A_cf Ainv on Z's pattern */
+    orc_spgemm(&Acf, Ainv, &prod);
+    for (int64_t k = 0; k < prod.rp[prod.nr]; ++k) prod.v[k] = -prod.v[k];
+    copy_pattern(Zpat, Z);
+    values_on_pattern(&prod, Zpat, Z->v);
+    orc_csr_free(&prod);
+    /* W: same columns; weight 1, or minus a_ij* over a_ii at the same j* */
+    copy_pattern(Wpat, W);
+    int32_t *fidx = (int32_t *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *cidx = (int32_t *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t nf = 0, nc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i] == ORC_F) fidx[nf++] = (int32_t)i;
+        else if (cf[i] == ORC_C) cidx[nc++] = (int32_t)i;
+    }
+    for (int64_t r = 0; r < Wpat->nr; ++r) {
+        for (int64_t k = Wpat->rp[r]; k < Wpat->rp[r + 1]; ++k) {
+            if (p->onepoint_weight != 1) { W->v[k] = 1.0; continue; }
+            int64_t i = fidx[r], j = cidx[Wpat->ci[k]];
+            double aij = 0.0, aii = 0.0;
+            for (int64_t q = A->rp[i]; q < A->rp[i + 1]; ++q) {
+                if (A->ci[q] == j) aij = A->v[q];
+                if (A->ci[q] == i) aii = A->v[q];
+            }
+            W->v[k] = -aij / aii;
+        }
+    }
+    free(fidx); free(cidx);
+    /* A_c = R (A P) on the coarse pattern */
+    orc_coarse_operator(A, cf, Z, W, -1.0, &prod);
+    copy_pattern(Acpat, Ac);
+    values_on_pattern(&prod, Acpat, Ac->v);
+    orc_csr_free(&prod);
+    orc_csr_free(&Aff);
+    orc_csr_free(&Acf);
+    return 0;
+}
+
+orc_hier *orc_resetup(const orc_hier *h, const double *vals)
+{
+    orc_hier *g = (orc_hier *)xcalloc(1, sizeof(orc_hier));
+    g->p = h->p;
+    g->nlev = h->nlev;
+    copy_pattern(&h->lev[0].A, &g->lev[0].A);
+    memcpy(g->lev[0].A.v, vals, (size_t)h->lev[0].A.rp[h->lev[0].A.nr] * sizeof(double));
+    for (int32_t l = 0; l < h->nlev; ++l) {
+        const orc_level *H = &h->lev[l];
+        orc_level *L = &g->lev[l];
+        int64_t n = L->A.nr;
+        L->nF = H->nF;
+        L->nC = H->nC;
+        L->nalpha = H->nalpha;
+        L->alpha = (double *)xcalloc((size_t)H->nalpha, sizeof(double));
+        if (l == h->nlev - 1) {        /* coarsest: polynomial of the whole matrix */
+            orc_gmres_poly(&L->A, g->p.seed, l, H->nalpha, L->alpha);
+            orc_poly_fixed_sparsity(&L->A, L->alpha, H->nalpha, &L->Ainv);
+            break;
+        }
+        L->cf = (int8_t *)xmalloc((size_t)n);
+        memcpy(L->cf, H->cf, (size_t)n);
+        L->fidx = (int32_t *)xmalloc((size_t)(H->nF > 0 ? H->nF : 1) * sizeof(int32_t));
+        L->cidx = (int32_t *)xmalloc((size_t)(H->nC > 0 ? H->nC : 1) * sizeof(int32_t));
+        memcpy(L->fidx, H->fidx, (size_t)H->nF * sizeof(int32_t));
+        memcpy(L->cidx, H->cidx, (size_t)H->nC * sizeof(int32_t));
+        orc_submatrix(&L->A, L->cf, ORC_F, ORC_F, &L->Aff);
+        orc_submatrix(&L->A, L->cf, ORC_F, ORC_C, &L->Afc);
+        orc_level_renumeric(&L->A, L->cf, &g->p, l, NULL, &H->W, &H->Z, &h->lev[l + 1].A, L->alpha, &L->Ainv,
+                            &L->Z, &L->W, &g->lev[l + 1].A);
+    }
+    return g;
 }
 
 void orc_hier_free(orc_hier *h)

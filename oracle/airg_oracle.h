@@ -94,6 +94,18 @@ int orc_level_build(const orc_csr *A, const orc_params *p, int32_t level, const 
                     int8_t *cf, double *alpha_out, orc_csr *Ainv, orc_csr *Z, orc_csr *W, orc_csr *Ac);
 
 orc_hier *orc_setup(const orc_csr *A, const orc_params *p);
+
+/* Numeric re-setup (Results: reuse of the CF splitting and symbolic products
+ * with a padded sparsity).  One level: given the new values of A on the
+ * level's pattern and its CF splitting, recompute the coefficients (or take
+ * alpha_in), Ainv, and the values of Z, W and the coarse operator on the
+ * given patterns (no drops).  The hierarchy form applies it level by level
+ * to vals (the canonical level-0 pattern of h); the coarsest level takes a
+ * new coarse polynomial. */
+int orc_level_renumeric(const orc_csr *A, const int8_t *cf, const orc_params *p, int32_t level,
+                        const double *alpha_in, const orc_csr *Wpat, const orc_csr *Zpat, const orc_csr *Acpat,
+                        double *alpha_out, orc_csr *Ainv, orc_csr *Z, orc_csr *W, orc_csr *Ac);
+orc_hier *orc_resetup(const orc_hier *h, const double *vals);
 void      orc_hier_free(orc_hier *h);
 int32_t   orc_hier_levels(const orc_hier *h);
 /* which: 0 A, 1 Ainv, 2 Z, 3 W, 4 Aff, 5 Afc ; returns a borrowed pointer or NULL */

@@ -482,3 +482,80 @@ def test_householder_is_stable_for_nearly_aligned_columns():
     Ks = K / np.linalg.norm(K, axis=0)
     Rn = np.linalg.qr(Ks, mode="r")
     assert np.allclose(np.abs(R), np.abs(Rn), rtol=1e-6, atol=1e-15)
+
+
+# ------------------------------------------------------ numeric re-setup ---
+# Reuse of the CF splitting and the symbolic products (Results section,
+# padded-sparsity reading): the re-setup keeps every level's splitting and the
+# patterns of W, Z and the coarse operators, and recomputes the values.
+
+def _levels_equal(H, G):
+    assert H.nlevels == G.nlevels
+    for l in range(H.nlevels):
+        if l < H.nlevels - 1:
+            assert np.array_equal(H.cf(l), G.cf(l)), l
+        assert np.array_equal(H.alpha(l), G.alpha(l)), l
+        for key in ("A", "Ainv", "Z", "W", "Aff", "Afc"):
+            a, b = H.matrix(l, key), G.matrix(l, key)
+            assert (a is None) == (b is None), (l, key)
+            if a is not None:
+                assert all(np.array_equal(x, y) for x, y in zip(a[:3], b[:3])), (l, key)
+
+
+def test_resetup_with_the_same_values_reproduces_the_hierarchy():
+    P = dg_square(24)
+    H = O.Hierarchy(csr_of(P), O.default_params(seed=P.seed))
+    _levels_equal(H, H.resetup(H.matrix(0, "A")[2]))
+
+
+def test_resetup_of_a_doubled_operator_equals_its_setup():
+    """Scaling by 2 is exact in binary floating point: the splitting, every
+    pattern after the drops, Z and the coarse patterns of setup(2A) equal
+    those of setup(A); the coefficients halve per power.  So re-setup with
+    2A must reproduce setup(2A) bit for bit."""
+    P = p0_square(24)
+    prm = O.default_params(seed=P.seed)
+    H = O.Hierarchy(csr_of(P), prm)
+    A2 = (P.rowptr, P.col, 2.0 * P.val)
+    _levels_equal(O.Hierarchy(A2, prm), H.resetup(2.0 * H.matrix(0, "A")[2]))
+    assert H.nlevels > 3
+
+
+def test_resetup_values_are_the_products_on_the_old_patterns():
+    """Level 0 against dense products: Z' = -A'_cf Ainv' on Z's pattern,
+    W' = W (weight 1), A'_1 = R' A' P' on the old coarse pattern; and the
+    re-set-up hierarchy solves the new system."""
+    P = p0_square(12)
+    prm = O.default_params(seed=P.seed)
+    H = O.Hierarchy(csr_of(P), prm)
+    vals = H.matrix(0, "A")[2] * np.random.default_rng(3).uniform(0.5, 1.5, H.matrix(0, "A")[2].shape)
+    G = H.resetup(vals)
+    Ad = dense((P.rowptr, P.col, vals))
+    cf = G.cf(0)
+    F, Cc = np.nonzero(cf == 1)[0], np.nonzero(cf == 2)[0]
+    Ainv = dense(G.matrix(0, "Ainv"))
+    Zd = -Ad[np.ix_(Cc, F)] @ Ainv
+    Z = G.matrix(0, "Z")
+    Zpat = H.matrix(0, "Z")
+    assert np.array_equal(Z[0], Zpat[0]) and np.array_equal(Z[1], Zpat[1])
+    rows = np.repeat(np.arange(len(Z[0]) - 1), np.diff(Z[0]))
+    assert np.allclose(Z[2], Zd[rows, Z[1]], rtol=1e-13, atol=1e-16)
+    W = G.matrix(0, "W")
+    assert np.array_equal(W[2], np.ones_like(W[2]))
+    n, nC = Ad.shape[0], len(Cc)
+    R = np.zeros((nC, n))
+    R[np.ix_(np.arange(nC), F)] = dense(Z)
+    R[np.arange(nC), Cc] = 1.0
+    Pm = np.zeros((n, nC))
+    Pm[np.ix_(F, np.arange(nC))] = dense(W)
+    Pm[Cc, np.arange(nC)] = 1.0
+    Acd = R @ Ad @ Pm
+    A1 = G.matrix(1, "A")
+    assert np.array_equal(A1[1], H.matrix(1, "A")[1])
+    r1 = np.repeat(np.arange(len(A1[0]) - 1), np.diff(A1[0]))
+    scale = np.abs(Acd).max()
+    assert np.allclose(A1[2], Acd[r1, A1[1]], rtol=1e-12, atol=1e-14 * scale)
+    b = P.b
+    x, its, rr = G.richardson(b, 1e-10, 200)
+    xs = sweep_solve(P.rowptr, P.col, vals, b, 1)
+    assert rr <= 1e-10 and np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
