@@ -124,6 +124,7 @@ typedef struct airg_stats {
     int64_t vcycle_bytes_fp32;    /* same with 4-byte values                            */
     int64_t top_spmv_bytes_fp64;  /* bytes of one SpMV with the top operator            */
     int64_t device_bytes;         /* device memory held by the handle                   */
+    double resetup_seconds;       /* last airg_resetup (0 before the first)             */
 } airg_stats;
 
 /* Fills *opts with the defaults above.  Returns AIRG_ERR_INVALID_ARG if
@@ -163,6 +164,21 @@ airg_status airg_adjoint_solve(airg_handle *h, int32_t nrhs, const double *d_g, 
                                int32_t max_it, void *hip_stream, airg_solve_info *info);
 
 airg_status airg_get_stats(const airg_handle *h, airg_stats *stats);
+
+/* Numeric re-setup: the reuse of the CF splittings and symbolic products
+ * across operators that share a pattern, with a padded sparsity (Results
+ * section, CF splitting and strong-tolerance discussions).  d_val (device,
+ * nnz doubles) holds new values for the matrix given to airg_setup: same row
+ * pointers and columns, entries in the same order.  Every level keeps its CF
+ * splitting and the patterns of its operator, Z and W -- an entry dropped at
+ * setup stays absent, a kept one stays whatever its new size -- while the
+ * values, the polynomial coefficients and Ainv are recomputed (the A^T
+ * hierarchies too, when built).  The inputs are borrowed for the call.
+ * Errors: AIRG_ERR_NONFINITE, AIRG_ERR_ZERO_DIAG, AIRG_ERR_INVALID_ARG for a
+ * nonzero where setup found an explicit zero, or for a handle set up in the
+ * batched form (segments with FGMRES and the FP32 V-cycle).  Synchronises
+ * hip_stream. */
+airg_status airg_resetup(airg_handle *h, const double *d_val, void *hip_stream);
 
 /* Describes one level of one segment; h_cf (nullable, n entries) receives
  * the CF markers (1 = F, 2 = C; all 1 on the coarsest level).  segment >= 0

@@ -57,7 +57,8 @@ class Stats(C.Structure):
                 ("operator_complexity", C.c_double), ("storage_complexity", C.c_double),
                 ("setup_seconds", C.c_double), ("phase_seconds", C.c_double * 7),
                 ("vcycle_bytes_fp64", C.c_int64), ("vcycle_bytes_fp32", C.c_int64),
-                ("top_spmv_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64)]
+                ("top_spmv_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64),
+                ("resetup_seconds", C.c_double)]
 
 
 _VP, _I32, _I64, _U64, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
@@ -67,6 +68,7 @@ _SIGS = {
     "airg_solve": [_VP, _I32, _VP, _VP, _D, _I32, _VP, C.POINTER(SolveInfo)],
     "airg_adjoint_solve": [_VP, _I32, _VP, _VP, _D, _I32, _VP, C.POINTER(SolveInfo)],
     "airg_get_stats": [_VP, C.POINTER(Stats)],
+    "airg_resetup": [_VP, _VP, _VP],
     "airg_get_level": [_VP, _I32, _I32, C.POINTER(LevelInfo), _VP],
     "airg_get_level_matrix": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
     "airg_csr_info": [_VP, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)],
@@ -252,6 +254,12 @@ def airg_solve(h, b, rtol=1e-10, max_it=200, stream=None, allow_not_converged=Fa
 def airg_adjoint_solve(h, g, rtol=1e-10, max_it=200, stream=None, allow_not_converged=False):
     """lambda with A^T lambda = g, by an AIRG hierarchy built on A^T."""
     return _solve(lib().airg_adjoint_solve, h, g, rtol, max_it, stream, allow_not_converged)
+
+
+def airg_resetup(h, val, stream=None):
+    """Numeric re-setup with new values (device float64 tensor, nnz entries in
+    the order of the matrix given to airg_setup)."""
+    _check(lib().airg_resetup(h.ptr, _dev(val, torch.float64), _stream(stream)))
 
 
 def airg_get_stats(h):

@@ -26,6 +26,12 @@ struct airg_handle {
     std::unique_ptr<Batch> batch;             // batched solve operators (built on first solve)
     double setup_seconds = 0.0;
     double adjoint_setup_seconds = 0.0;
+    double resetup_seconds = 0.0;
+    // numeric re-setup: input entry k -> canonical entry (or -1 for an
+    // explicit zero removed at setup); empty when nothing was removed
+    int64_t nnz_in = 0;
+    DBuf<int32_t> canon_pos;
+    std::vector<int64_t> seg_nnz;             // canonical row pointer at each segment start
 };
 
 namespace airg {
@@ -118,6 +124,53 @@ __global__ void k_strided(const double *__restrict__ src, int64_t ss, double *__
 void strided_copy(const double *src, int64_t ss, double *dst, int64_t ds, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     k_strided<<<grid_for(n, 256), 256, 0, s>>>(src, ss, dst, ds, n);
+    AIRG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------ numeric re-setup --
+enum : uint32_t { RS_NONFINITE = 1, RS_ZERO_DIAG = 2, RS_OFF_PATTERN = 4 };
+
+__global__ void k_keep_flags(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                             const double *__restrict__ v, int32_t *__restrict__ keep) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) keep[k] = ci[k] == i || v[k] != 0.0;
+}
+__global__ void k_keep_pos(int64_t nnz, const int32_t *__restrict__ keep, int32_t *__restrict__ pos) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz && !keep[k]) pos[k] = -1;
+}
+__global__ void k_resetup_gather(int64_t nnz, const int32_t *__restrict__ pos, const double *__restrict__ vin,
+                                 double *__restrict__ vout, uint32_t *__restrict__ flags) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    int32_t p = pos[k];
+    if (p >= 0) vout[p] = vin[k];
+    else if (vin[k] != 0.0) atomicOr(flags, RS_OFF_PATTERN);
+}
+__global__ void k_resetup_check(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                const double *__restrict__ v, uint32_t *__restrict__ flags) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t f = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        if (!isfinite(v[k])) f |= RS_NONFINITE;
+        if (ci[k] == i && v[k] == 0.0) f |= RS_ZERO_DIAG;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// canonical_pos[k] for every input entry when setup removed explicit zeros
+void record_canonical_map(airg_handle *h, int32_t n, int64_t nnz_in, const int32_t *rp, const int32_t *ci,
+                          const double *v, int64_t nnz_canon, hipStream_t s) {
+    h->nnz_in = nnz_in;
+    if (nnz_canon == nnz_in) return;
+    DBuf<int32_t> keep((size_t)nnz_in, s);
+    h->canon_pos.alloc((size_t)nnz_in + 1, s);
+    k_keep_flags<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, v, keep.p);
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(keep.p, h->canon_pos.p, nnz_in, s, false);
+    k_keep_pos<<<grid_for(nnz_in, 256), 256, 0, s>>>(nnz_in, keep.p, h->canon_pos.p);
     AIRG_LAUNCH_CHECK();
 }
 
@@ -248,6 +301,12 @@ airg_status airg_setup(const airg_opts *opts, int64_t n, int64_t nnz, const int3
         h->seeds.resize(ns);
         for (int p = 0; p < ns; ++p) h->seeds[p] = h_seg_seeds ? h_seg_seeds[p] : opts->seed + (uint64_t)p;
         Csr A = canonical_copy((int32_t)n, nnz, d_rowptr, d_col, d_val, s);
+        record_canonical_map(h.get(), (int32_t)n, nnz, d_rowptr, d_col, d_val, A.nnz, s);
+        {
+            std::vector<int32_t> rph((size_t)n + 1);
+            d2h(rph.data(), A.rp.p, rph.size(), s);
+            for (int p = 0; p <= ns; ++p) h->seg_nnz.push_back(rph[(size_t)h->seg[p]]);
+        }
         bool batched = ns > 1 && opts->outer == AIRG_OUTER_FGMRES && opts->precond_precision == 32 &&
                        segmented_supported(*opts);
         if (ns == 1) {
@@ -347,6 +406,45 @@ airg_status airg_get_stats(const airg_handle *h, airg_stats *st) {
         st->storage_complexity = ssum / z0;
         st->setup_seconds = h->setup_seconds;
         st->device_bytes = (int64_t)dev_bytes_in_use();
+        st->resetup_seconds = h->resetup_seconds;
+    });
+}
+
+airg_status airg_resetup(airg_handle *h, const double *d_val, void *hip_stream) {
+    return guarded([&] {
+        AIRG_REQUIRE(h && d_val, ST_INVALID_ARG, "null argument");
+        AIRG_REQUIRE(!h->segh, ST_INVALID_ARG, "numeric re-setup is not available for the batched form");
+        hipStream_t s = (hipStream_t)hip_stream;
+        auto t0 = std::chrono::steady_clock::now();
+        const int ns = (int)h->seg.size() - 1;
+        const Csr &Acanon = ns == 1 ? h->fwd[0]->L(0).A : h->top;
+        DBuf<double> vals((size_t)Acanon.nnz, s);
+        DBuf<uint32_t> flags(1, s);
+        fill_zero(flags.p, 4, s);
+        if (h->canon_pos.p) {
+            k_resetup_gather<<<grid_for(h->nnz_in, 256), 256, 0, s>>>(h->nnz_in, h->canon_pos.p, d_val, vals.p,
+                                                                     flags.p);
+            AIRG_LAUNCH_CHECK();
+        } else {
+            d2d(vals.p, d_val, (size_t)Acanon.nnz, s);
+        }
+        k_resetup_check<<<grid_for(Acanon.nr, 256), 256, 0, s>>>(Acanon.nr, Acanon.rp.p, Acanon.ci.p, vals.p,
+                                                                 flags.p);
+        AIRG_LAUNCH_CHECK();
+        uint32_t f = d2h_one(flags.p, s);
+        AIRG_REQUIRE(!(f & RS_NONFINITE), ST_NONFINITE, "new values include a non-finite value");
+        AIRG_REQUIRE(!(f & RS_ZERO_DIAG), ST_ZERO_DIAG, "new values have a zero diagonal entry");
+        AIRG_REQUIRE(!(f & RS_OFF_PATTERN), ST_INVALID_ARG,
+                     "a new value is nonzero where setup found an explicit zero (outside the kept pattern)");
+        if (ns > 1) d2d(h->top.v.p, vals.p, (size_t)h->top.nnz, s);
+        for (int p = 0; p < ns; ++p) resetup_hierarchy(*h->fwd[p], vals.p + h->seg_nnz[p], s);
+        for (size_t p = 0; p < h->adj.size(); ++p) {
+            Csr T = transpose(view(h->fwd[p]->L(0).A), s);
+            resetup_hierarchy(*h->adj[p], T.v.p, s);
+        }
+        h->batch.reset();
+        AIRG_HIP(hipStreamSynchronize(s));
+        h->resetup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     });
 }
 

@@ -39,6 +39,7 @@ struct Hier {
     Csr A0p;                      // top operator in level-0 order (residuals)
     bool top_permuted = false;
     double setup_seconds = 0.0;
+    double resetup_seconds = 0.0;
     double phase[AIRG_PHASE_COUNT] = {};
     DBuf<double> x, r, e, bp;     // top-level work vectors
     DBuf<float> r32, e32;
@@ -120,6 +121,10 @@ void build_pp_fill(Csr &P, const Csr &W, int32_t nF, const int32_t *nperm, hipSt
 
 // Builds the full hierarchy of the canonical operator A0 (takes ownership).
 std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t seed, hipStream_t s);
+
+// Numeric re-setup with new top-level values (canonical pattern of level 0,
+// device): same splittings and patterns, recomputed values.
+void resetup_hierarchy(Hier &H, const double *vals, hipStream_t s);
 
 // Single-level build for replay/inspection: CF split, A_ff, polynomial
 // (alpha_in nullable), Ainv, Z, W and the coarse operator.

@@ -413,6 +413,43 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
     return H;
 }
 
+// ----------------------------------------------------- numeric re-setup --
+// The CF splittings, the pattern of every level operator (after its drop)
+// and the patterns of Z and W are kept; the values are recomputed level by
+// level from the new top-level values: extraction, coefficients and Ainv,
+// Z = -A_cf Ainv and A_c = R (A P) on the kept patterns (no drops), then the
+// solve operators.
+void resetup_hierarchy(Hier &H, const double *vals, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    H.s = s;
+    const airg_opts &o = H.opt;
+    const int m = o.poly_order + 1, mc = o.coarse_poly_order + 1;
+    Level &T = H.L(0);
+    d2d(T.A.v.p, vals, (size_t)T.A.nnz, s);
+    for (int l = 0; l < H.nlev(); ++l) {
+        Level &L = H.L(l);
+        if (L.coarsest) {
+            L.poly = gmres_poly(view(L.A), H.seed, l, mc, s);
+            poly_fixed_sparsity(view(L.A), L.poly.alpha, mc, L.Ainv.v.p, s);
+            break;
+        }
+        Level &N = H.L(l + 1);
+        Csr Acf;
+        extract_fc_blocks(view(L.A), L.cf.p, L.rank.p, L.nF, L.nC, L.Aff, L.Afc, Acf, s);
+        L.poly = gmres_poly(view(L.Aff), H.seed, l, m, s);
+        poly_fixed_sparsity(view(L.Aff), L.poly.alpha, m, L.Ainv.v.p, s);
+        spgemm_on_pattern(view(Acf), view(L.Ainv), L.Z, -1.0, L.Z.v.p, s);
+        if (o.onepoint_weight == 1) onepoint_values(view(L.A), L.fidx.p, L.cidx.p, L.W, s);
+        Csr P = prolongator_from_w(L.W, L.cf.p, L.rank.p, L.n, L.nC, s);
+        Csr R = restriction_full(view(L.Z), L.fidx.p, L.cidx.p, L.n, s);
+        Csr AP = spgemm(view(L.A), view(P), s);
+        spgemm_on_pattern(view(R), view(AP), N.A, 1.0, N.A.v.p, s);
+    }
+    finalize(H);
+    AIRG_HIP(hipStreamSynchronize(s));
+    H.resetup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 LevelOut build_one_level(const CsrView &A, const airg_opts &o, uint64_t seed, int level, const double *alpha_in,
                          hipStream_t s) {
     LevelOut out;

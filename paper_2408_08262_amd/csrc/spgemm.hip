@@ -440,6 +440,85 @@ static uint32_t pow2_at_least(int64_t v) {
     return p;
 }
 
+// ------------------------------------------------------- fixed pattern ---
+// Values of sign * (A B) on a given pattern: out[e] for each stored (i, j) of
+// row i of the pattern.  One G-lane group per row stages the pattern row in
+// LDS; every product finds its column there by binary search (products off
+// the pattern are skipped) and is accumulated in ascending k from 0.0 without
+// contraction -- the same order and rounding as the two-pass product, so the
+// values equal those of the full product at the pattern's positions.
+template <int G, int L, int TPB>
+__global__ void __launch_bounds__(TPB) k_spgemm_on_pattern(const int32_t *__restrict__ list, int64_t count,
+                                                           const int32_t *__restrict__ arp,
+                                                           const int32_t *__restrict__ aci,
+                                                           const double *__restrict__ av,
+                                                           const int32_t *__restrict__ brp,
+                                                           const int32_t *__restrict__ bci,
+                                                           const double *__restrict__ bv,
+                                                           const int32_t *__restrict__ prp,
+                                                           const int32_t *__restrict__ pci, double sign,
+                                                           double *__restrict__ out) {
+#pragma clang fp contract(off)
+    constexpr int NG = TPB / G;
+    __shared__ int32_t Cs[NG][L];
+    __shared__ double Vs[NG][L];
+    int gid = threadIdx.x / G;
+    int lane = group_lane<G>();
+    int64_t idx = (int64_t)blockIdx.x * NG + gid;
+    if (idx >= count) return;
+    int32_t row = list[idx];
+    int32_t *cols = Cs[gid];
+    double *vals = Vs[gid];
+    const int32_t p0 = prp[row];
+    const int len = prp[row + 1] - p0;
+    for (int t = lane; t < len; t += G) {
+        cols[t] = pci[p0 + t];
+        vals[t] = 0.0;
+    }
+    wave_sync();
+    for_products<G, true, true>(row, arp, aci, av, brp, bci, bv, [&](int32_t c, double p) {
+        int lo = 0, hi = len;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (cols[mid] < c) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < len && cols[lo] == c) vals[lo] = vals[lo] + p;
+    });
+    wave_sync();
+    for (int t = lane; t < len; t += G) out[p0 + t] = sign * vals[t];
+}
+
+__global__ void k_pattern_bin(int32_t m, const int32_t *__restrict__ prp, int8_t *__restrict__ bin) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int32_t L = prp[i + 1] - prp[i];
+    bin[i] = L == 0 ? 0 : L <= 16 ? 1 : L <= 64 ? 2 : L <= 256 ? 3 : L <= 1024 ? 4 : L <= 4096 ? 5 : 6;
+}
+
+void spgemm_on_pattern(const CsrView &A, const CsrView &Bm, const Csr &Pt, double sign, double *out_v,
+                       hipStream_t s) {
+    AIRG_REQUIRE(A.nc == Bm.nr && Pt.nr == A.nr, ST_INVALID_ARG, "pattern product dimensions differ");
+    int32_t m = A.nr;
+    if (m == 0 || Pt.nnz == 0) return;
+    DBuf<int8_t> bin((size_t)m, s);
+    k_pattern_bin<<<grid_for(m, 256), 256, 0, s>>>(m, Pt.rp.p, bin.p);
+    AIRG_LAUNCH_CHECK();
+    Bins B = bin_rows(bin.p, m, 8, s);
+    AIRG_REQUIRE(B.count(6) == 0, ST_LIMIT, "pattern row longer than 4096 entries");
+    auto grp = [&](auto kern, int b, int rows_per_block, unsigned tpb) {
+        if (B.count(b))
+            kern<<<grid_for(B.count(b), rows_per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Bm.rp,
+                                                                      Bm.ci, Bm.v, Pt.rp.p, Pt.ci.p, sign, out_v);
+    };
+    grp(k_spgemm_on_pattern<4, 16, 256>, 1, 64, 256);
+    grp(k_spgemm_on_pattern<8, 64, 256>, 2, 32, 256);
+    grp(k_spgemm_on_pattern<16, 256, 128>, 3, 8, 128);
+    grp(k_spgemm_on_pattern<64, 1024, 64>, 4, 1, 64);
+    grp(k_spgemm_on_pattern<64, 4096, 64>, 5, 1, 64);
+    AIRG_LAUNCH_CHECK();
+}
+
 static void run_global(bool numeric, const Bins &B, int b, const std::vector<int32_t> &per_row, const CsrView &A,
                        const CsrView &Bm, int32_t *cnt, const int32_t *crp, int32_t *cci, double *cv, hipStream_t s) {
     // one table of 2 x per_row[r] slots (rounded up to a power of two) per row

@@ -107,6 +107,76 @@ void onepoint_prolongator(const CsrView &A, const int8_t *cf, const int32_t *ran
     AIRG_LAUNCH_CHECK();
 }
 
+// [W; I] in natural row order from an existing W (numeric re-setup keeps
+// W's columns): F rows copy W's row, C rows hold the identity entry,
+// terminal rows nothing.
+__global__ void k_pw_count(int32_t n, const int8_t *__restrict__ cf, const int32_t *__restrict__ rank,
+                           const int32_t *__restrict__ wrp, int32_t *__restrict__ cnt) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int8_t c = cf[i];
+    cnt[i] = c == CF_F ? wrp[rank[i] + 1] - wrp[rank[i]] : c == CF_C ? 1 : 0;
+}
+__global__ void k_pw_fill(int32_t n, const int8_t *__restrict__ cf, const int32_t *__restrict__ rank,
+                          const int32_t *__restrict__ wrp, const int32_t *__restrict__ wci,
+                          const double *__restrict__ wv, const int32_t *__restrict__ prp, int32_t *__restrict__ pci,
+                          double *__restrict__ pv) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int8_t c = cf[i];
+    int32_t w = prp[i], r = rank[i];
+    if (c == CF_F) {
+        for (int32_t k = wrp[r]; k < wrp[r + 1]; ++k, ++w) {
+            pci[w] = wci[k];
+            pv[w] = wv[k];
+        }
+    } else if (c == CF_C) {
+        pci[w] = r;
+        pv[w] = 1.0;
+    }
+}
+
+Csr prolongator_from_w(const Csr &W, const int8_t *cf, const int32_t *rank, int32_t n, int32_t nC, hipStream_t s) {
+    Csr P;
+    P.nr = n;
+    P.nc = nC;
+    P.rp.alloc((size_t)n + 1, s);
+    DBuf<int32_t> cnt((size_t)n + 1, s);
+    k_pw_count<<<grid_for(n, 256), 256, 0, s>>>(n, cf, rank, W.rp.p, cnt.p);
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(cnt.p, P.rp.p, n, s, false);
+    resolve_sizes({&P}, s);
+    k_pw_fill<<<grid_for(n, 256), 256, 0, s>>>(n, cf, rank, W.rp.p, W.ci.p, W.v.p, P.rp.p, P.ci.p, P.v.p);
+    AIRG_LAUNCH_CHECK();
+    return P;
+}
+
+// Weight mode 1 at W's existing columns: w = -a_ij / a_ii with j the C point
+// of the column.
+__global__ void k_w_values(int32_t nF, const int32_t *__restrict__ fidx, const int32_t *__restrict__ cidx,
+                           const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ v, const int32_t *__restrict__ wrp,
+                           const int32_t *__restrict__ wci, double *__restrict__ wv) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nF) return;
+    int32_t i = fidx[r];
+    for (int32_t k = wrp[r]; k < wrp[r + 1]; ++k) {
+        int32_t j = cidx[wci[k]];
+        double aij = 0.0, aii = 0.0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            if (ci[q] == j) aij = v[q];
+            if (ci[q] == i) aii = v[q];
+        }
+        wv[k] = -aij / aii;
+    }
+}
+
+void onepoint_values(const CsrView &A, const int32_t *fidx, const int32_t *cidx, Csr &W, hipStream_t s) {
+    if (W.nr == 0) return;
+    k_w_values<<<grid_for(W.nr, 256), 256, 0, s>>>(W.nr, fidx, cidx, A.rp, A.ci, A.v, W.rp.p, W.ci.p, W.v.p);
+    AIRG_LAUNCH_CHECK();
+}
+
 __global__ void k_r_rowptr(int32_t nC, const int32_t *__restrict__ zrp, int32_t *__restrict__ rrp) {
     int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r <= nC) rrp[r] = zrp[r] + r;
