@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--rtol", type=float, default=1e-10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison form")
+    p.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
+                   help="extra AIRG option for every form and the oracle (e.g. strong_threshold=0.0)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB (x5), the reference for HBM byte counters")
     p.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -128,6 +130,14 @@ def roofline_from_timing(airg, workload):
             "launches": launches, "bytes_per_launch": int(bpl), "avg_launch_us": round(avg * 1e6, 2)}
 
 
+def parse_opts(items):
+    out = {}
+    for it in items:
+        k, v = it.split("=", 1)
+        out[k] = float(v) if any(c in v for c in ".eE") or v in ("inf", "-inf") else int(v)
+    return out
+
+
 def single(a, airg, torch):
     """One problem: setup + solve per step."""
     from workloads import dg_square, p0_cube
@@ -154,8 +164,11 @@ def single(a, airg, torch):
         del h
         return info, st
 
-    opts32 = airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, truncate_n=trunc)
-    opts64 = airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64, truncate_n=trunc)
+    extra_opts = parse_opts(a.opt)
+    opts32 = airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, truncate_n=trunc,
+                               **extra_opts)
+    opts64 = airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64, truncate_n=trunc,
+                               **extra_opts)
     for _ in range(a.warmup):
         step(opts32)
     torch.cuda.synchronize()
@@ -180,11 +193,30 @@ def single(a, airg, torch):
         fp64 = {"seconds_per_step": round((t3 - t2) / a.steps, 4), "setup_s": round(s64["setup_seconds"], 4),
                 "solve_s": round(i64["seconds"], 4), "iterations": i64["iterations"],
                 "rel_residual": i64["rel_residual"], "levels": s64["levels"], "form": "Richardson, FP64 V-cycle"}
+    # numeric re-setup (kept splittings and patterns) for an operator with the same pattern and
+    # values perturbed by U(0.9, 1.1), then the solve: timed after the timed region, own handle
+    import numpy as np
+    h = airg.airg_setup(*A, opts32)
+    newval = torch.as_tensor(P.val * np.random.default_rng(77).uniform(0.9, 1.1, P.val.shape), device="cuda")
+    airg.airg_resetup(h, newval)
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    for _ in range(a.steps):
+        airg.airg_resetup(h, newval)
+        xr, ir = airg.airg_solve(h, b, rtol=a.rtol, max_it=300)
+    torch.cuda.synchronize()
+    r1 = time.perf_counter()
+    resetup = {"seconds_per_step": round((r1 - r0) / a.steps, 4),
+               "resetup_s": round(airg.airg_get_stats(h)["resetup_seconds"], 4),
+               "solve_s": round(ir["seconds"], 4), "iterations": ir["iterations"],
+               "rel_residual": ir["rel_residual"],
+               "form": "numeric re-setup (kept CF splittings and patterns) + FGMRES/FP32, values x U(0.9, 1.1)"}
+    del h
     cpu = None
     if not a.no_cpu_baseline:
         import oracle as O
         c0 = time.perf_counter()
-        H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, truncate_n=trunc))
+        H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, truncate_n=trunc, **extra_opts))
         c1 = time.perf_counter()
         _, its, rr = H.richardson(P.b, a.rtol, 300)
         c2 = time.perf_counter()
@@ -197,9 +229,11 @@ def single(a, airg, torch):
                             "operator": round(st32["operator_complexity"], 3),
                             "storage": round(st32["storage_complexity"], 3)},
              "phase_seconds": {k: round(v, 4) for k, v in st32["phase_seconds"].items()},
-             "vcycle_bytes_fp32": st32["vcycle_bytes_fp32"], "fp64_comparison": fp64}
+             "vcycle_bytes_fp32": st32["vcycle_bytes_fp32"], "fp64_comparison": fp64, "resetup": resetup}
     cfg = {"workload": desc, "form": "FGMRES(30) FP64 outer + FP32 AIRG V-cycle", "rtol": a.rtol,
            "parallelism": "single GPU"}
+    if extra_opts:
+        cfg["options"] = extra_opts
     return sec, cfg, "f64 (f32 V-cycle)", roof, cpu, extra
 
 

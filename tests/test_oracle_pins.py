@@ -559,3 +559,23 @@ def test_resetup_values_are_the_products_on_the_old_patterns():
     x, its, rr = G.richardson(b, 1e-10, 200)
     xs = sweep_solve(P.rowptr, P.col, vals, b, 1)
     assert rr <= 1e-10 and np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_tolerance_zero_hierarchy_has_diagonal_ff_and_direction_free_top_split():
+    """Strong tolerance 0.0: A_ff diagonal on every level (an independent set
+    in the adjacency graph), and the top splitting the same for every
+    direction on one mesh (its symmetrised adjacency does not depend on it)."""
+    prm = O.default_params(strong_threshold=0.0, up_smooths=1, max_levels=128)
+    tops = []
+    for theta in (0.3, 1.1, 2.5):
+        P = dg_square(16, theta=theta)
+        prm.seed = P.seed
+        H = O.Hierarchy(csr_of(P), prm)
+        for l in range(H.nlevels - 1):
+            Aff = H.matrix(l, "Aff")
+            assert np.array_equal(np.diff(Aff[0]), np.ones(len(Aff[0]) - 1, int)), l
+            assert np.array_equal(Aff[1], np.arange(len(Aff[0]) - 1)), l
+        tops.append(H.cf(0))
+        x, its, rr = H.fgmres(P.b, 1e-10, 200)
+        assert rr <= 1e-10
+    assert all(np.array_equal(tops[0], t) for t in tops[1:])
