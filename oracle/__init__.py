@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("poly_order", C.c_int32), ("drop_R", C.c_double), ("drop_A", C.c_double),
                 ("coarse_poly_order", C.c_int32), ("coarse_iters", C.c_int32),
                 ("truncate_n", C.c_int64), ("max_levels", C.c_int32), ("up_smooths", C.c_int32),
-                ("onepoint_weight", C.c_int32), ("seed", C.c_uint64)]
+                ("onepoint_weight", C.c_int32), ("seed", C.c_uint64),
+                ("poly_sparsity_order", C.c_int32), ("coarse_matrix_free", C.c_int32)]
 
 
 _lib = None
@@ -77,6 +78,8 @@ def lib():
             "orc_poly_coeffs_from_r": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
             "orc_gmres_poly": (C.c_int, [cs, C.c_uint64, C.c_int32, C.c_int32, C.c_void_p]),
             "orc_poly_fixed_sparsity": (C.c_int, [cs, C.c_void_p, C.c_int32, cs]),
+            "orc_poly_fixed_sparsity_pattern": (C.c_int, [cs, cs, C.c_void_p, C.c_int32, cs]),
+            "orc_power_pattern": (C.c_int, [cs, C.c_int32, cs]),
             "orc_onepoint_w": (C.c_int, [cs, C.c_void_p, C.c_int32, cs]),
             "orc_restrictor": (C.c_int, [cs, cs, C.c_double, cs]),
             "orc_coarse_operator": (C.c_int, [cs, C.c_void_p, cs, cs, C.c_double, cs]),
@@ -305,6 +308,22 @@ def poly_fixed_sparsity(A, alpha):
     alpha = np.ascontiguousarray(alpha, np.float64)
     o = _Csr()
     lib().orc_poly_fixed_sparsity(a.ref, _ptr(alpha), len(alpha), C.byref(o))
+    return _csr_out(o)
+
+
+def poly_fixed_sparsity_pattern(A, S, alpha):
+    """Fixed-sparsity polynomial with row patterns from S (plus diagonals)."""
+    a, sp_ = _csr_in(A), _csr_in(S)
+    alpha = np.ascontiguousarray(alpha, np.float64)
+    o = _Csr()
+    lib().orc_poly_fixed_sparsity_pattern(a.ref, sp_.ref, _ptr(alpha), len(alpha), C.byref(o))
+    return _csr_out(o)
+
+
+def power_pattern(A, order):
+    a = _csr_in(A)
+    o = _Csr()
+    lib().orc_power_pattern(a.ref, order, C.byref(o))
     return _csr_out(o)
 
 

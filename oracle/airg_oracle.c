@@ -71,6 +71,8 @@ void orc_default_params(orc_params *p)
     p->up_smooths = 2;
     p->onepoint_weight = 0;
     p->seed = 0;
+    p->poly_sparsity_order = 1;
+    p->coarse_matrix_free = 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -602,21 +604,22 @@ int orc_gmres_poly(const orc_csr *A, uint64_t seed, int32_t level, int32_t m, do
  * A~^k is e_i^T M_i^k restricted to J_i (v_k = v_{k-1} M_i, each entry summed
  * over J_i in ascending order), and the row of Ainv is sum_k alpha_k v_k
  * accumulated in ascending k.  Pattern of Ainv: pattern(A) u diag. */
-int orc_poly_fixed_sparsity(const orc_csr *A, const double *alpha, int32_t nalpha, orc_csr *out)
+int orc_poly_fixed_sparsity_pattern(const orc_csr *A, const orc_csr *S, const double *alpha, int32_t nalpha,
+                                    orc_csr *out)
 {
     int64_t n = A->nr;
     int64_t nnz = 0;
     for (int64_t i = 0; i < n; ++i) {
         int has = 0;
-        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) has |= A->ci[k] == i;
-        nnz += A->rp[i + 1] - A->rp[i] + !has;
+        for (int64_t k = S->rp[i]; k < S->rp[i + 1]; ++k) has |= S->ci[k] == i;
+        nnz += S->rp[i + 1] - S->rp[i] + !has;
     }
     csr_alloc(out, n, n, nnz, 1);
     int32_t *pos = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
     for (int64_t j = 0; j < n; ++j) pos[j] = -1;
     int64_t maxlen = 1;
     for (int64_t i = 0; i < n; ++i)
-        if (A->rp[i + 1] - A->rp[i] + 1 > maxlen) maxlen = A->rp[i + 1] - A->rp[i] + 1;
+        if (S->rp[i + 1] - S->rp[i] + 1 > maxlen) maxlen = S->rp[i + 1] - S->rp[i] + 1;
     int32_t *J = (int32_t *)xmalloc((size_t)maxlen * sizeof(int32_t));
     double *v = (double *)xmalloc((size_t)maxlen * sizeof(double));
     double *vn = (double *)xmalloc((size_t)maxlen * sizeof(double));
@@ -625,10 +628,10 @@ int orc_poly_fixed_sparsity(const orc_csr *A, const double *alpha, int32_t nalph
     for (int64_t i = 0; i < n; ++i) {
         int64_t L = 0;
         int inserted = 0;
-        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) {
-            if (!inserted && A->ci[k] > i) { J[L++] = (int32_t)i; inserted = 1; }
-            if (A->ci[k] == i) inserted = 1;
-            J[L++] = A->ci[k];
+        for (int64_t k = S->rp[i]; k < S->rp[i + 1]; ++k) {
+            if (!inserted && S->ci[k] > i) { J[L++] = (int32_t)i; inserted = 1; }
+            if (S->ci[k] == i) inserted = 1;
+            J[L++] = S->ci[k];
         }
         if (!inserted) J[L++] = (int32_t)i;
         for (int64_t a = 0; a < L; ++a) pos[J[a]] = (int32_t)a;
@@ -659,6 +662,44 @@ int orc_poly_fixed_sparsity(const orc_csr *A, const double *alpha, int32_t nalph
     out->rp[n] = w;
     free(pos); free(J); free(v); free(vn); free(acc);
     return 0;
+}
+
+int orc_poly_fixed_sparsity(const orc_csr *A, const double *alpha, int32_t nalpha, orc_csr *out)
+{
+    return orc_poly_fixed_sparsity_pattern(A, A, alpha, nalpha, out);
+}
+
+/* Pattern of A^order (values of the last product; order 1: A itself).  The
+ * sparsity order of the fixed-sparsity polynomial (GMRES polynomial order
+ * subsection): order s keeps the entries of the s-th power's pattern. */
+int orc_power_pattern(const orc_csr *A, int32_t order, orc_csr *out)
+{
+    orc_csr cur, nxt;
+    csr_alloc(&cur, A->nr, A->nc, A->rp[A->nr], 1);
+    memcpy(cur.rp, A->rp, (size_t)(A->nr + 1) * sizeof(int64_t));
+    memcpy(cur.ci, A->ci, (size_t)A->rp[A->nr] * sizeof(int32_t));
+    memcpy(cur.v, A->v, (size_t)A->rp[A->nr] * sizeof(double));
+    for (int32_t k = 1; k < order; ++k) {
+        orc_spgemm(&cur, A, &nxt);
+        orc_csr_free(&cur);
+        cur = nxt;
+    }
+    *out = cur;
+    return 0;
+}
+
+/* The approximate inverse of the setup: the fixed-sparsity polynomial on
+ * the pattern of A^order. */
+static void assembled_inverse(const orc_csr *A, int32_t order, const double *alpha, int32_t m, orc_csr *out)
+{
+    if (order <= 1) {
+        orc_poly_fixed_sparsity(A, alpha, m, out);
+        return;
+    }
+    orc_csr S;
+    orc_power_pattern(A, order, &S);
+    orc_poly_fixed_sparsity_pattern(A, &S, alpha, m, out);
+    orc_csr_free(&S);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -806,7 +847,7 @@ int orc_level_build(const orc_csr *A, const orc_params *p, int32_t level, const 
     orc_submatrix(A, cf, ORC_C, ORC_F, &Acf);
     if (alpha_in) memcpy(alpha_out, alpha_in, (size_t)m * sizeof(double));
     else orc_gmres_poly(&Aff, p->seed, level, m, alpha_out);
-    orc_poly_fixed_sparsity(&Aff, alpha_out, m, Ainv);
+    assembled_inverse(&Aff, p->poly_sparsity_order, alpha_out, m, Ainv);
     orc_restrictor(&Acf, Ainv, p->drop_R, Z);
     orc_onepoint_w(A, cf, p->onepoint_weight, W);
     orc_coarse_operator(A, cf, Z, W, p->drop_A, Ac);
@@ -874,7 +915,7 @@ orc_hier *orc_setup(const orc_csr *A0, const orc_params *p)
             L->alpha = (double *)xcalloc((size_t)m, sizeof(double));
             L->nalpha = m;
             orc_gmres_poly(&L->A, p->seed, l, m, L->alpha);
-            orc_poly_fixed_sparsity(&L->A, L->alpha, m, &L->Ainv);
+            if (!p->coarse_matrix_free) assembled_inverse(&L->A, p->poly_sparsity_order, L->alpha, m, &L->Ainv);
             L->nF = n;
             L->nC = 0;
             h->nlev = l + 1;
@@ -895,7 +936,7 @@ orc_hier *orc_setup(const orc_csr *A0, const orc_params *p)
         L->alpha = (double *)xcalloc((size_t)m, sizeof(double));
         L->nalpha = m;
         orc_gmres_poly(&L->Aff, p->seed, l, m, L->alpha);
-        orc_poly_fixed_sparsity(&L->Aff, L->alpha, m, &L->Ainv);
+        assembled_inverse(&L->Aff, p->poly_sparsity_order, L->alpha, m, &L->Ainv);
         orc_restrictor(&Acf, &L->Ainv, p->drop_R, &L->Z);
         orc_onepoint_w(&L->A, L->cf, p->onepoint_weight, &L->W);
         orc_coarse_operator(&L->A, L->cf, &L->Z, &L->W, p->drop_A, &h->lev[l + 1].A);
@@ -947,7 +988,7 @@ int orc_level_renumeric(const orc_csr *A, const int8_t *cf, const orc_params *p,
     orc_submatrix(A, cf, ORC_C, ORC_F, &Acf);
     if (alpha_in) memcpy(alpha_out, alpha_in, (size_t)m * sizeof(double));
     else orc_gmres_poly(&Aff, p->seed, level, m, alpha_out);
-    orc_poly_fixed_sparsity(&Aff, alpha_out, m, Ainv);
+    assembled_inverse(&Aff, p->poly_sparsity_order, alpha_out, m, Ainv);
     /* Z = -A_cf Ainv on Z's pattern */
     orc_spgemm(&Acf, Ainv, &prod);
     for (int64_t k = 0; k < prod.rp[prod.nr]; ++k) prod.v[k] = -prod.v[k];
@@ -1003,7 +1044,8 @@ orc_hier *orc_resetup(const orc_hier *h, const double *vals)
         L->alpha = (double *)xcalloc((size_t)H->nalpha, sizeof(double));
         if (l == h->nlev - 1) {        /* coarsest: polynomial of the whole matrix */
             orc_gmres_poly(&L->A, g->p.seed, l, H->nalpha, L->alpha);
-            orc_poly_fixed_sparsity(&L->A, L->alpha, H->nalpha, &L->Ainv);
+            if (!g->p.coarse_matrix_free)
+                assembled_inverse(&L->A, g->p.poly_sparsity_order, L->alpha, H->nalpha, &L->Ainv);
             break;
         }
         L->cf = (int8_t *)xmalloc((size_t)n);
@@ -1061,18 +1103,41 @@ const double *orc_hier_alpha(const orc_hier *h, int32_t level, int32_t *nalpha)
  *   g_c = Z g_F + g_C;  e_C = V(g_c);  e_F = W e_C;
  *   repeat nu times: e_F += Ainv (g_F - A_ff e_F - A_fc e_C).
  * Coarsest level: e = Ainv g, then (v_c - 1) times e += Ainv (g - A e). */
+/* Coarse polynomial applied to x: the assembled fixed-sparsity matrix, or
+ * (coarse_matrix_free) q(A) x = sum_k alpha_k A^k x by matrix-vector products,
+ * the powers taken in ascending order (Truncation subsection: the order-12
+ * polynomial applied matrix-free). */
+static void coarse_apply(const orc_hier *h, const orc_level *L, const double *x, double *y)
+{
+    if (!h->p.coarse_matrix_free) {
+        orc_spmv(&L->Ainv, x, y);
+        return;
+    }
+    int64_t n = L->A.nr;
+    double *pk = (double *)xmalloc((size_t)n * sizeof(double));
+    double *pn = (double *)xmalloc((size_t)n * sizeof(double));
+    memcpy(pk, x, (size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) y[i] = L->alpha[0] * pk[i];
+    for (int32_t k = 1; k < L->nalpha; ++k) {
+        orc_spmv(&L->A, pk, pn);
+        double *tmp = pk; pk = pn; pn = tmp;
+        for (int64_t i = 0; i < n; ++i) y[i] += L->alpha[k] * pk[i];
+    }
+    free(pk); free(pn);
+}
+
 void orc_vcycle(const orc_hier *h, int32_t level, const double *g, double *e)
 {
     const orc_level *L = &h->lev[level];
     int64_t n = L->A.nr;
     if (level == h->nlev - 1) {
-        orc_spmv(&L->Ainv, g, e);
         double *r = (double *)xmalloc((size_t)n * sizeof(double));
         double *t = (double *)xmalloc((size_t)n * sizeof(double));
+        coarse_apply(h, L, g, e);
         for (int32_t it = 1; it < h->p.coarse_iters; ++it) {
             orc_spmv(&L->A, e, t);
             for (int64_t i = 0; i < n; ++i) r[i] = g[i] - t[i];
-            orc_spmv(&L->Ainv, r, t);
+            coarse_apply(h, L, r, t);
             for (int64_t i = 0; i < n; ++i) e[i] += t[i];
         }
         free(r); free(t);

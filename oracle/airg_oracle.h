@@ -45,6 +45,8 @@ typedef struct orc_params {
     int32_t  up_smooths;         /* F-point smooths after the coarse correction  */
     int32_t  onepoint_weight;    /* 0: weight 1, 1: weight -a_ij / a_ii          */
     uint64_t seed;
+    int32_t  poly_sparsity_order;   /* fixed sparsity of the powers: pattern of A^s */
+    int32_t  coarse_matrix_free;    /* 1: coarse polynomial applied by matvecs      */
 } orc_params;
 
 void orc_default_params(orc_params *p);
@@ -77,6 +79,11 @@ void orc_householder_r(int64_t rows, int32_t cols, const double *K, double *R, d
 int  orc_poly_coeffs_from_r(const double *R, const double *colnorm, int32_t m, double *alpha);
 int  orc_gmres_poly(const orc_csr *A, uint64_t seed, int32_t level, int32_t m, double *alpha);
 int  orc_poly_fixed_sparsity(const orc_csr *A, const double *alpha, int32_t nalpha, orc_csr *out);
+/* The same with the row patterns J_i taken from S (plus the diagonal);
+ * M_i = A(J_i, J_i).  orc_power_pattern gives the pattern of A^order. */
+int  orc_poly_fixed_sparsity_pattern(const orc_csr *A, const orc_csr *S, const double *alpha, int32_t nalpha,
+                                     orc_csr *out);
+int  orc_power_pattern(const orc_csr *A, int32_t order, orc_csr *out);
 
 /* --- grid transfer and coarse operator ---------------------------------- */
 int orc_onepoint_w(const orc_csr *A, const int8_t *cf, int32_t weight_mode, orc_csr *W);

@@ -579,3 +579,76 @@ def test_tolerance_zero_hierarchy_has_diagonal_ff_and_direction_free_top_split()
         x, its, rr = H.fgmres(P.b, 1e-10, 200)
         assert rr <= 1e-10
     assert all(np.array_equal(tops[0], t) for t in tops[1:])
+
+
+# ------------------------------------------------ polynomial variants ---
+# Sparsity order s (GMRES polynomial order subsection): the powers keep the
+# pattern of A^s; the coarse polynomial may be applied matrix-free.
+
+def test_power_pattern_brute_force():
+    D, A = small_operator(6, 40)
+    for order in (1, 2, 3):
+        S = O.power_pattern(A, order)
+        want = np.linalg.matrix_power((D != 0).astype(float), order) != 0
+        assert np.array_equal(dense((S[0], S[1], np.ones(len(S[1])))) != 0, want), order
+
+
+def test_sparsity_order_polynomial():
+    D, A = small_operator(6, 40)
+    rng = np.random.default_rng(4)
+    n = D.shape[0]
+    for s in (2, 3):
+        S = O.power_pattern(A, s)
+        # degree <= s: the row-local reading is the exact polynomial
+        for d in range(1, s + 2):
+            al = rng.standard_normal(d)
+            Q = sum(a * np.linalg.matrix_power(D, k) for k, a in enumerate(al))
+            got = dense(O.poly_fixed_sparsity_pattern(A, S, al))
+            assert np.allclose(got, Q, rtol=1e-12, atol=1e-13), (s, d)
+        # degree > s: e_i^T M_i^k on J_i = pattern(A^s)_i, brute force
+        al = rng.standard_normal(s + 3)
+        got = dense(O.poly_fixed_sparsity_pattern(A, S, al))
+        Sd = dense((S[0], S[1], np.ones(len(S[1])))) != 0
+        want = np.zeros((n, n))
+        for i in range(n):
+            J = np.nonzero(Sd[i] | (np.arange(n) == i))[0]
+            M = D[np.ix_(J, J)]
+            e = (J == i).astype(float)
+            want[i, J] = sum(a * (e @ np.linalg.matrix_power(M, k)) for k, a in enumerate(al))
+        assert np.allclose(got, want, rtol=1e-11, atol=1e-12), s
+
+
+def test_matrix_free_coarse_polynomial_cycle():
+    """One-level hierarchy (truncated at the top): the cycle is
+    e = q(A) g, then e += q(A)(g - A e) twice, with q applied exactly."""
+    P = p0_square(8)
+    prm = O.default_params(seed=P.seed, truncate_n=10 ** 6, coarse_matrix_free=1)
+    H = O.Hierarchy(csr_of(P), prm)
+    assert H.nlevels == 1 and H.matrix(0, "Ainv") is None
+    D = dense(csr_of(P))
+    al = H.alpha(0)
+    Q = sum(a * np.linalg.matrix_power(D, k) for k, a in enumerate(al))
+    g = np.random.default_rng(6).standard_normal(D.shape[0])
+    e = Q @ g
+    for _ in range(prm.coarse_iters - 1):
+        e = e + Q @ (g - D @ e)
+    assert np.allclose(H.vcycle(g), e, rtol=1e-11, atol=1e-13 * np.abs(e).max())
+    # and the assembled form differs from it (first-order fixed sparsity)
+    prm.coarse_matrix_free = 0
+    H1 = O.Hierarchy(csr_of(P), prm)
+    assert not np.allclose(H1.vcycle(g), e, rtol=1e-6)
+
+
+def test_sparsity_order_two_hierarchy_solves():
+    P = dg_square(24)
+    its = {}
+    for s in (1, 2):
+        H = O.Hierarchy(csr_of(P), O.default_params(seed=P.seed, poly_sparsity_order=s))
+        x, its[s], rr = H.richardson(P.b, 1e-10, 200)
+        assert rr <= 1e-10
+        xs = sweep_solve(P.rowptr, P.col, P.val, P.b, 3)
+        assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+        Ainv, Aff = H.matrix(0, "Ainv"), H.matrix(0, "Aff")
+        S = O.power_pattern(Aff, s)
+        assert np.array_equal(Ainv[0], S[0]) and np.array_equal(Ainv[1], S[1])
+    assert its[2] <= its[1]
