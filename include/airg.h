@@ -73,7 +73,7 @@ typedef struct airg_opts {
     double drop_R;                /* relative row drop tolerance on Z                   */
     double drop_A;                /* relative row drop tolerance on coarse operators    */
     int32_t poly_order;           /* order of q (m - 1), at most 14                      */
-    int32_t poly_sparsity_order;  /* must be 1 (first-order fixed sparsity)             */
+    int32_t poly_sparsity_order;  /* 1, 2 or 3: the powers keep the pattern of A^s      */
     int32_t coarse_poly_order;    /* polynomial order on the coarsest level, <= 14      */
     int32_t coarse_iters;         /* iterations of the coarse polynomial solve          */
     int64_t truncate_n;           /* a level with n <= truncate_n is coarsest; 0 = off  */
@@ -90,6 +90,10 @@ typedef struct airg_opts {
     int32_t autotune;             /* 1: time candidate SpMM kernels per batch operator  */
     int64_t device_bytes_cap;     /* 0 = no cap; else a cap on the library's device     */
                                   /* memory in use while this setup runs                */
+    int32_t coarse_matrix_free;   /* 1: the coarse polynomial is applied as q(A) x by   */
+                                  /* products with A instead of an assembled matrix     */
+                                  /* (truncation subsection); not in the batched form   */
+    int32_t reserved_opts;
 } airg_opts;
 
 typedef struct airg_solve_info {
@@ -179,6 +183,14 @@ airg_status airg_get_stats(const airg_handle *h, airg_stats *stats);
  * batched form (segments with FGMRES and the FP32 V-cycle).  Synchronises
  * hip_stream. */
 airg_status airg_resetup(airg_handle *h, const double *d_val, void *hip_stream);
+
+/* One V-cycle of the hierarchy (V-cycle of the AIRG subsection: restrict,
+ * recurse, prolong, up F-point smooths; coarse polynomial iterations on the
+ * coarsest level): d_e = V(d_g), device vectors of the segment's size in
+ * natural order, computed in precision 64 or 32 (FP32 operators, FP64 in and
+ * out).  segment as for airg_get_level; not for the batched form. */
+airg_status airg_vcycle(const airg_handle *h, int32_t segment, const double *d_g, double *d_e, int32_t precision,
+                        void *hip_stream);
 
 /* Describes one level of one segment; h_cf (nullable, n entries) receives
  * the CF markers (1 = F, 2 = C; all 1 on the coarsest level).  segment >= 0

@@ -37,7 +37,8 @@ class Opts(C.Structure):
                 ("up_smooths", C.c_int32), ("down_smooths", C.c_int32), ("precond_precision", C.c_int32),
                 ("outer", C.c_int32), ("fgmres_restart", C.c_int32), ("seed", C.c_uint64),
                 ("build_adjoint", C.c_int32), ("onepoint_weight", C.c_int32), ("use_graph", C.c_int32),
-                ("autotune", C.c_int32), ("device_bytes_cap", C.c_int64)]
+                ("autotune", C.c_int32), ("device_bytes_cap", C.c_int64),
+                ("coarse_matrix_free", C.c_int32), ("reserved_opts", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -69,6 +70,7 @@ _SIGS = {
     "airg_adjoint_solve": [_VP, _I32, _VP, _VP, _D, _I32, _VP, C.POINTER(SolveInfo)],
     "airg_get_stats": [_VP, C.POINTER(Stats)],
     "airg_resetup": [_VP, _VP, _VP],
+    "airg_vcycle": [_VP, _I32, _VP, _VP, _I32, _VP],
     "airg_get_level": [_VP, _I32, _I32, C.POINTER(LevelInfo), _VP],
     "airg_get_level_matrix": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
     "airg_csr_info": [_VP, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)],
@@ -260,6 +262,14 @@ def airg_resetup(h, val, stream=None):
     """Numeric re-setup with new values (device float64 tensor, nnz entries in
     the order of the matrix given to airg_setup)."""
     _check(lib().airg_resetup(h.ptr, _dev(val, torch.float64), _stream(stream)))
+
+
+def airg_vcycle(h, g, precision=64, segment=0, stream=None):
+    """e = V(g): one V-cycle of the hierarchy, natural order."""
+    e = torch.empty_like(g)
+    _check(lib().airg_vcycle(h.ptr, segment, _dev(g, torch.float64), _dev(e, torch.float64), precision,
+                             _stream(stream)))
+    return e
 
 
 def airg_get_stats(h):

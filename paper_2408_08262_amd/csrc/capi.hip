@@ -65,7 +65,10 @@ void check_opts(const airg_opts &o) {
     AIRG_REQUIRE(o.poly_order >= 0 && o.poly_order + 2 <= kMaxPolyCols, ST_INVALID_ARG, "poly_order out of range");
     AIRG_REQUIRE(o.coarse_poly_order >= 0 && o.coarse_poly_order + 2 <= kMaxPolyCols, ST_INVALID_ARG,
                  "coarse_poly_order out of range");
-    AIRG_REQUIRE(o.poly_sparsity_order == 1, ST_INVALID_ARG, "only first-order fixed sparsity is implemented");
+    AIRG_REQUIRE(o.poly_sparsity_order >= 1 && o.poly_sparsity_order <= 3, ST_INVALID_ARG,
+                 "poly_sparsity_order must be 1, 2 or 3");
+    AIRG_REQUIRE(o.coarse_matrix_free == 0 || o.coarse_matrix_free == 1, ST_INVALID_ARG,
+                 "coarse_matrix_free must be 0 or 1");
     AIRG_REQUIRE(o.down_smooths == 0, ST_INVALID_ARG, "only up F-point smoothing is implemented");
     AIRG_REQUIRE(o.up_smooths >= 0 && o.coarse_iters >= 1, ST_INVALID_ARG, "bad smoothing counts");
     AIRG_REQUIRE(o.precond_precision == 32 || o.precond_precision == 64, ST_INVALID_ARG,
@@ -266,6 +269,7 @@ airg_status airg_default_opts(airg_opts *o) {
     o->use_graph = 0;
     o->autotune = 0;
     o->device_bytes_cap = 0;
+    o->coarse_matrix_free = 0;
     return AIRG_OK;
 }
 
@@ -307,8 +311,10 @@ airg_status airg_setup(const airg_opts *opts, int64_t n, int64_t nnz, const int3
             d2h(rph.data(), A.rp.p, rph.size(), s);
             for (int p = 0; p <= ns; ++p) h->seg_nnz.push_back(rph[(size_t)h->seg[p]]);
         }
-        bool batched = ns > 1 && opts->outer == AIRG_OUTER_FGMRES && opts->precond_precision == 32 &&
-                       segmented_supported(*opts);
+        const bool batch_solve = ns > 1 && opts->outer == AIRG_OUTER_FGMRES && opts->precond_precision == 32;
+        AIRG_REQUIRE(!(batch_solve && opts->coarse_matrix_free), ST_INVALID_ARG,
+                     "the batched form applies assembled coarse polynomials only");
+        bool batched = batch_solve && segmented_supported(*opts);
         if (ns == 1) {
             h->fwd.push_back(build_hierarchy(std::move(A), *opts, h->seeds[0], s));
         } else if (batched) {
@@ -445,6 +451,19 @@ airg_status airg_resetup(airg_handle *h, const double *d_val, void *hip_stream) 
         h->batch.reset();
         AIRG_HIP(hipStreamSynchronize(s));
         h->resetup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    });
+}
+
+airg_status airg_vcycle(const airg_handle *h, int32_t segment, const double *d_g, double *d_e, int32_t precision,
+                        void *hip_stream) {
+    return guarded([&] {
+        AIRG_REQUIRE(h && d_g && d_e, ST_INVALID_ARG, "null argument");
+        AIRG_REQUIRE(!h->segh, ST_INVALID_ARG, "the batched form has no per-segment V-cycle");
+        AIRG_REQUIRE(precision == 32 || precision == 64, ST_INVALID_ARG, "precision must be 32 or 64");
+        Hier *H = pick(h, segment);
+        H->s = (hipStream_t)hip_stream;
+        apply_vcycle(*H, d_g, d_e, precision);
+        AIRG_HIP(hipStreamSynchronize(H->s));
     });
 }
 

@@ -29,6 +29,8 @@ struct Level {
     // V-cycle work vectors
     DBuf<double> g64, e64, t64;
     DBuf<float> g32, e32, t32;
+    DBuf<double> p64, q64, u64;   // coarsest level, matrix-free polynomial
+    DBuf<float> p32, q32, u32;
 };
 
 struct Hier {
@@ -99,7 +101,9 @@ struct NullTimer {
 
 // Pieces of the setup shared by the single and batch drivers.
 Csr pattern_copy(const CsrView &A, hipStream_t s);
-Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, hipStream_t s);
+// The fixed-sparsity polynomial on the pattern of A^order (order 1: A's).
+Csr inverse_pattern(const CsrView &A, int order, hipStream_t s);
+Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, int order, hipStream_t s);
 // perm: natural index -> level order (F by rank, then C, then terminal rows);
 // iperm its inverse.
 void make_level_perm(int32_t n, int32_t nF, int32_t nC, const int8_t *cf, const int32_t *rank, int32_t *perm,
@@ -144,6 +148,8 @@ struct SolveResult {
     bool converged = false;
 };
 SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, int maxit);
+// One V-cycle e = V(g) in natural order (precision 64 or 32).
+void apply_vcycle(Hier &H, const double *g, double *e, int precision);
 SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit);
 
 // Algorithmic bytes of one V-cycle with vbytes-byte values.

@@ -6,6 +6,7 @@
 #include "csr.hpp"
 #include "group.hpp"
 #include "poly.hpp"
+#include "spgemm.hpp"
 
 namespace airg {
 
@@ -457,7 +458,8 @@ __global__ void k_rowlen_bin(int32_t n, const int32_t *__restrict__ rp, int8_t *
 template <int G, int TPB>
 __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ list, int64_t count,
                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                   const double *__restrict__ v, const double *__restrict__ alt,
+                                                   const double *__restrict__ v, const int32_t *__restrict__ prp,
+                                                   const int32_t *__restrict__ pci, const double *__restrict__ alt,
                                                    const int32_t *__restrict__ soff, int nseg, int nalpha,
                                                    double *__restrict__ out) {
 #pragma clang fp contract(off)
@@ -469,11 +471,11 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     int64_t idx = (int64_t)blockIdx.x * NG + gid;
     if (idx >= count) return;
     int32_t row = list[idx];
-    int32_t b = rp[row];
-    int32_t L = rp[row + 1] - b;
+    int32_t b = prp[row];
+    int32_t L = prp[row + 1] - b;
     double *M = Ms[gid];
     int32_t *J = Js[gid];
-    if (lane < L) J[lane] = ci[b + lane];
+    if (lane < L) J[lane] = pci[b + lane];
     for (int t = lane; t < G * G; t += G) M[t] = 0.0;
     wave_sync();
     if (lane < L) {
@@ -505,7 +507,8 @@ constexpr int kLongRowMax = 2048;
 // gathered rows streamed once per power in ascending p.
 __global__ void __launch_bounds__(256) k_poly_long(const int32_t *__restrict__ list, int64_t count,
                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                   const double *__restrict__ v, const double *__restrict__ alt,
+                                                   const double *__restrict__ v, const int32_t *__restrict__ prp,
+                                                   const int32_t *__restrict__ pci, const double *__restrict__ alt,
                                                    const int32_t *__restrict__ soff, int nseg, int nalpha,
                                                    double *__restrict__ out) {
 #pragma clang fp contract(off)
@@ -514,11 +517,11 @@ __global__ void __launch_bounds__(256) k_poly_long(const int32_t *__restrict__ l
     int64_t idx = blockIdx.x;
     if (idx >= count) return;
     int32_t row = list[idx];
-    int32_t b = rp[row];
-    int32_t L = rp[row + 1] - b;
+    int32_t b = prp[row];
+    int32_t L = prp[row + 1] - b;
     const double *al = alt + (nseg > 1 ? seg_of(soff, nseg, row) : 0) * kMaxPolyCols;
     for (int a = threadIdx.x; a < L; a += blockDim.x) {
-        J[a] = ci[b + a];
+        J[a] = pci[b + a];
         x[a] = J[a] == row ? 1.0 : 0.0;
         acc[a] = al[0] * x[a];
     }
@@ -552,17 +555,17 @@ __global__ void __launch_bounds__(256) k_poly_long(const int32_t *__restrict__ l
 
 // Coefficient table (kMaxPolyCols per segment) and segment offsets on the
 // device; nseg = 1 needs no offsets.
-static void fixed_sparsity_tab(const CsrView &A, const double *alt, const int32_t *soff, int nseg, int nalpha,
-                               double *out_v, hipStream_t s) {
+static void fixed_sparsity_tab(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff,
+                               int nseg, int nalpha, double *out_v, hipStream_t s) {
     int32_t n = A.nr;
     DBuf<int8_t> bin((size_t)n, s);
-    k_rowlen_bin<<<grid_for(n, 256), 256, 0, s>>>(n, A.rp, bin.p);
+    k_rowlen_bin<<<grid_for(n, 256), 256, 0, s>>>(n, Pt.rp, bin.p);
     AIRG_LAUNCH_CHECK();
     Bins B = bin_rows(bin.p, n, 6, s);
     auto rows = [&](auto kern, int b, int per_block, unsigned tpb) {
         if (B.count(b))
-            kern<<<grid_for(B.count(b), per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, alt, soff,
-                                                                nseg, nalpha, out_v);
+            kern<<<grid_for(B.count(b), per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Pt.rp,
+                                                                Pt.ci, alt, soff, nseg, nalpha, out_v);
     };
     rows(k_poly_rows<4, 256>, 0, 64, 256);
     rows(k_poly_rows<8, 256>, 1, 32, 256);
@@ -576,29 +579,35 @@ static void fixed_sparsity_tab(const CsrView &A, const double *alt, const int32_
             // longest row among the long ones, checked against the LDS capacity
             std::vector<int32_t> lr((size_t)B.count(5)), rpl((size_t)n + 1);
             d2h(lr.data(), B.list(5), lr.size(), s);
-            d2h(rpl.data(), A.rp, rpl.size(), s);
+            d2h(rpl.data(), Pt.rp, rpl.size(), s);
             for (int32_t r : lr) maxlen = std::max(maxlen, rpl[r + 1] - rpl[r]);
         }
         AIRG_REQUIRE(maxlen <= kLongRowMax, ST_LIMIT,
                      "row of " + std::to_string(maxlen) + " entries exceeds the fixed-sparsity row limit");
-        k_poly_long<<<(unsigned)B.count(5), 256, 0, s>>>(B.list(5), B.count(5), A.rp, A.ci, A.v, alt, soff, nseg,
-                                                         nalpha, out_v);
+        k_poly_long<<<(unsigned)B.count(5), 256, 0, s>>>(B.list(5), B.count(5), A.rp, A.ci, A.v, Pt.rp, Pt.ci, alt,
+                                                         soff, nseg, nalpha, out_v);
         AIRG_LAUNCH_CHECK();
     }
 }
 
 void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, double *out_v, hipStream_t s) {
+    poly_fixed_sparsity_pattern(A, A, alpha, nalpha, out_v, s);
+}
+
+void poly_fixed_sparsity_pattern(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha,
+                                 double *out_v, hipStream_t s) {
     AIRG_REQUIRE(nalpha >= 1 && nalpha <= kMaxPolyCols, ST_INVALID_ARG, "bad number of coefficients");
+    AIRG_REQUIRE(Pt.nr == A.nr, ST_INVALID_ARG, "pattern and matrix differ in rows");
     if (A.nr == 0) return;
     double tab[kMaxPolyCols] = {};
     for (int k = 0; k < nalpha; ++k) tab[k] = alpha[k];
     DBuf<double> alt(kMaxPolyCols, s);
     h2d(alt.p, tab, kMaxPolyCols, s);
-    fixed_sparsity_tab(A, alt.p, nullptr, 1, nalpha, out_v, s);   // synchronises (row binning) before tab dies
+    fixed_sparsity_tab(A, Pt, alt.p, nullptr, 1, nalpha, out_v, s);   // synchronises (row binning) before tab dies
 }
 
-void poly_fixed_sparsity_seg(const CsrView &A, const std::vector<int32_t> &off, const std::vector<PolyInfo> &P,
-                             double *out_v, hipStream_t s) {
+void poly_fixed_sparsity_seg(const CsrView &A, const CsrView &Pt, const std::vector<int32_t> &off,
+                             const std::vector<PolyInfo> &P, double *out_v, hipStream_t s) {
     const int nseg = (int)P.size();
     AIRG_REQUIRE(nseg >= 1 && (int)off.size() == nseg + 1, ST_INVALID_ARG, "bad segment table");
     if (A.nr == 0) return;
@@ -613,7 +622,14 @@ void poly_fixed_sparsity_seg(const CsrView &A, const std::vector<int32_t> &off, 
     DBuf<int32_t> soff(off.size(), s);
     h2d(alt.p, tab.data(), tab.size(), s);
     h2d(soff.p, off.data(), off.size(), s);
-    fixed_sparsity_tab(A, alt.p, soff.p, nseg, nalpha, out_v, s);   // synchronises before the tables die
+    fixed_sparsity_tab(A, Pt, alt.p, soff.p, nseg, nalpha, out_v, s);   // synchronises before the tables die
+}
+
+Csr power_pattern(const CsrView &A, int order, hipStream_t s) {
+    AIRG_REQUIRE(order >= 1 && order <= 3, ST_INVALID_ARG, "sparsity order must be 1, 2 or 3");
+    Csr P = spgemm(A, A, s);
+    if (order == 3) P = spgemm(view(P), A, s);
+    return P;
 }
 
 }  // namespace airg

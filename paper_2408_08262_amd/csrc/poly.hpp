@@ -46,9 +46,16 @@ void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, doub
 // its diagonal): row i of A~^k is e_i^T M_i^k restricted to J_i, with
 // M_i = A(J_i, J_i).  out_v has A.nnz entries (pattern of A).
 void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, double *out_v, hipStream_t s);
+// The same with the row patterns J_i taken from Pt (which holds the
+// diagonal; out_v has Pt.nnz entries); M_i = A(J_i, J_i).
+void poly_fixed_sparsity_pattern(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha,
+                                 double *out_v, hipStream_t s);
 // Batch form: the rows of segment p (host offsets off) use P[p]'s
-// coefficients.
-void poly_fixed_sparsity_seg(const CsrView &A, const std::vector<int32_t> &off, const std::vector<PolyInfo> &P,
-                             double *out_v, hipStream_t s);
+// coefficients; patterns from Pt.
+void poly_fixed_sparsity_seg(const CsrView &A, const CsrView &Pt, const std::vector<int32_t> &off,
+                             const std::vector<PolyInfo> &P, double *out_v, hipStream_t s);
+// Pattern (and values) of A^order, order 2 or 3: the sparsity order of the
+// fixed-sparsity powers.
+Csr power_pattern(const CsrView &A, int order, hipStream_t s);
 
 }  // namespace airg

@@ -234,8 +234,8 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             DBuf<uint64_t> dtsd = to_dev(tsd, s);
             std::vector<PolyInfo> P = gmres_poly_seg(view(L.AT), toff, dtoff.p, dtsd.p, l, mc, s);
             for (size_t j = 0; j < tidx.size(); ++j) L.seg[tidx[j]].poly = P[j];
-            L.AinvT = pattern_copy(view(L.AT), s);
-            poly_fixed_sparsity_seg(view(L.AT), toff, P, L.AinvT.v.p, s);
+            L.AinvT = inverse_pattern(view(L.AT), o.poly_sparsity_order, s);
+            poly_fixed_sparsity_seg(view(L.AT), view(L.AinvT), toff, P, L.AinvT.v.p, s);
             tm.end();
         }
         if (c.nF + c.nC == 0) break;
@@ -254,8 +254,8 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             DBuf<uint64_t> dfsd = to_dev(fsd, s);
             std::vector<PolyInfo> P = gmres_poly_seg(view(L.Aff), foff, dfoff.p, dfsd.p, l, m, s);
             for (size_t j = 0; j < aidx.size(); ++j) L.seg[aidx[j]].poly = P[j];
-            L.Ainv = pattern_copy(view(L.Aff), s);
-            poly_fixed_sparsity_seg(view(L.Aff), foff, P, L.Ainv.v.p, s);
+            L.Ainv = inverse_pattern(view(L.Aff), o.poly_sparsity_order, s);
+            poly_fixed_sparsity_seg(view(L.Aff), view(L.Ainv), foff, P, L.Ainv.v.p, s);
         }
         tm.begin(AIRG_PHASE_RESTRICTOR);
         {

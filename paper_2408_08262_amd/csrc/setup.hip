@@ -45,10 +45,15 @@ Csr pattern_copy(const CsrView &A, hipStream_t s) {
     return X;
 }
 
-// Copy of A's pattern with values from the fixed-sparsity polynomial.
-Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, hipStream_t s) {
-    Csr X = pattern_copy(A, s);
-    poly_fixed_sparsity(A, P.alpha, m, X.v.p, s);
+// The fixed-sparsity polynomial on the pattern of A^order (order 1: A's own
+// pattern).
+Csr inverse_pattern(const CsrView &A, int order, hipStream_t s) {
+    return order <= 1 ? pattern_copy(A, s) : power_pattern(A, order, s);
+}
+
+Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, int order, hipStream_t s) {
+    Csr X = inverse_pattern(A, order, s);
+    poly_fixed_sparsity_pattern(A, view(X), P.alpha, m, X.v.p, s);
     return X;
 }
 
@@ -78,7 +83,7 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     } else {
         poly = gmres_poly(view(Aff), seed, lvl, m, s);
     }
-    Ainv = assemble_inverse(view(Aff), poly, m, s);
+    Ainv = assemble_inverse(view(Aff), poly, m, o.poly_sparsity_order, s);
     tm.begin(AIRG_PHASE_RESTRICTOR);
     {
         Csr prod = spgemm(view(Acf), view(Ainv), s);
@@ -323,7 +328,7 @@ void finalize(Hier &H) {
         Level &L = H.L(l);
         if (L.coarsest) {
             make_f32(L.A, s);
-            make_f32(L.Ainv, s);
+            if (L.Ainv.rp.p) make_f32(L.Ainv, s);
             continue;
         }
         Level &N = H.L(l + 1);
@@ -350,6 +355,10 @@ void finalize(Hier &H) {
         L.g32.alloc((size_t)L.n, s);
         L.e32.alloc((size_t)L.n, s);
         L.t32.alloc((size_t)L.n, s);
+        if (L.coarsest && H.opt.coarse_matrix_free) {
+            for (DBuf<double> *b : {&L.p64, &L.q64, &L.u64}) b->alloc((size_t)L.n, s);
+            for (DBuf<float> *b : {&L.p32, &L.q32, &L.u32}) b->alloc((size_t)L.n, s);
+        }
     }
     int32_t n0 = T.n;
     H.x.alloc((size_t)n0, s);
@@ -396,7 +405,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             L.nC = 0;
             int m = o.coarse_poly_order + 1;
             L.poly = gmres_poly(view(L.A), seed, l, m, s);
-            L.Ainv = assemble_inverse(view(L.A), L.poly, m, s);
+            if (!o.coarse_matrix_free) L.Ainv = assemble_inverse(view(L.A), L.poly, m, o.poly_sparsity_order, s);
             tm.end();
             break;
         }
@@ -430,14 +439,15 @@ void resetup_hierarchy(Hier &H, const double *vals, hipStream_t s) {
         Level &L = H.L(l);
         if (L.coarsest) {
             L.poly = gmres_poly(view(L.A), H.seed, l, mc, s);
-            poly_fixed_sparsity(view(L.A), L.poly.alpha, mc, L.Ainv.v.p, s);
+            if (!o.coarse_matrix_free)
+                poly_fixed_sparsity_pattern(view(L.A), view(L.Ainv), L.poly.alpha, mc, L.Ainv.v.p, s);
             break;
         }
         Level &N = H.L(l + 1);
         Csr Acf;
         extract_fc_blocks(view(L.A), L.cf.p, L.rank.p, L.nF, L.nC, L.Aff, L.Afc, Acf, s);
         L.poly = gmres_poly(view(L.Aff), H.seed, l, m, s);
-        poly_fixed_sparsity(view(L.Aff), L.poly.alpha, m, L.Ainv.v.p, s);
+        poly_fixed_sparsity_pattern(view(L.Aff), view(L.Ainv), L.poly.alpha, m, L.Ainv.v.p, s);
         spgemm_on_pattern(view(Acf), view(L.Ainv), L.Z, -1.0, L.Z.v.p, s);
         if (o.onepoint_weight == 1) onepoint_values(view(L.A), L.fidx.p, L.cidx.p, L.W, s);
         Csr P = prolongator_from_w(L.W, L.cf.p, L.rank.p, L.n, L.nC, s);
@@ -476,6 +486,12 @@ int64_t vcycle_bytes(const Hier &H, int vb) {
         const Level &L = *H.lv[l];
         if (L.coarsest) {
             int vc = H.opt.coarse_iters;
+            if (H.opt.coarse_matrix_free) {
+                // vc applications of q(A): m - 1 products each; vc - 1 residuals
+                int64_t per = (int64_t)(L.poly.m - 1) * spmv_bytes(L.n, L.n, L.A.nnz, vb, false);
+                b += (int64_t)vc * per + (int64_t)(vc - 1) * spmv_bytes(L.n, L.n, L.A.nnz, vb, true);
+                continue;
+            }
             // e = Ainv g, then (vc - 1) times: t = g - A e; e += Ainv t
             b += spmv_bytes(L.n, L.n, L.Ainv.nnz, vb, false);
             b += (int64_t)(vc - 1) * (spmv_bytes(L.n, L.n, L.A.nnz, vb, true) + spmv_bytes(L.n, L.n, L.Ainv.nnz, vb, true));
@@ -497,7 +513,7 @@ void complexities(const Hier &H, double *grid, double *op, double *storage) {
         g += L.n;
         o += (double)L.A.nnz;
         if (L.coarsest) {
-            st += (double)L.Ainv.nnz + (H.opt.coarse_iters > 1 ? (double)L.A.nnz : 0.0);
+            st += (double)L.Ainv.nnz + (H.opt.coarse_iters > 1 || H.opt.coarse_matrix_free ? (double)L.A.nnz : 0.0);
         } else {
             st += (double)L.Ainv.nnz + (double)L.Aff.nnz + (double)L.Afc.nnz + (double)(L.Z.nnz + L.nC) +
                   (double)(L.W.nnz + L.nC);

@@ -2,6 +2,7 @@
 // undamped Richardson outer iteration, and flexible GMRES in FP64 around an
 // FP32 or FP64 V-cycle.
 #include <cmath>
+#include <utility>
 
 #include "csr.hpp"
 #include "hierarchy.hpp"
@@ -20,27 +21,69 @@ template <> struct Bufs<double> {
     static double *g(Level &L) { return L.g64.p; }
     static double *e(Level &L) { return L.e64.p; }
     static double *t(Level &L) { return L.t64.p; }
+    static double *p(Level &L) { return L.p64.p; }
+    static double *q(Level &L) { return L.q64.p; }
+    static double *u(Level &L) { return L.u64.p; }
 };
 template <> struct Bufs<float> {
     static float *g(Level &L) { return L.g32.p; }
     static float *e(Level &L) { return L.e32.p; }
     static float *t(Level &L) { return L.t32.p; }
+    static float *p(Level &L) { return L.p32.p; }
+    static float *q(Level &L) { return L.q32.p; }
+    static float *u(Level &L) { return L.u32.p; }
 };
+
+// y = a x (SET) or y += a x (ADD), contraction off as in the power sums
+template <class T>
+__global__ void k_scale_acc(int64_t n, T a, const T *__restrict__ x, T *__restrict__ y, int add) {
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T v = a * x[i];
+    y[i] = add ? y[i] + v : v;
+}
+
+// Coarse polynomial on the coarsest level: the assembled fixed-sparsity
+// matrix, or q(A) x = sum_k alpha_k A^k x by products with A in ascending
+// powers (matrix-free; the truncation subsection's alternative).  mode as in
+// spmv: SET writes y, ADD adds to it.
+template <class T>
+void coarse_apply(Hier &H, Level &Lv, const T *x, T *y, int mode) {
+    hipStream_t s = H.s;
+    if (!H.opt.coarse_matrix_free) {
+        spmvT(Lv.Ainv, x, y, (const T *)nullptr, mode, s);
+        return;
+    }
+    const int64_t n = Lv.n;
+    T *pk = Bufs<T>::p(Lv), *pn = Bufs<T>::q(Lv), *acc = mode == SPMV_SET ? y : Bufs<T>::u(Lv);
+    const unsigned grid = grid_for(n, 256);
+    d2d(pk, x, (size_t)n, s);
+    k_scale_acc<T><<<grid, 256, 0, s>>>(n, (T)Lv.poly.alpha[0], pk, acc, 0);
+    for (int k = 1; k < Lv.poly.m; ++k) {
+        spmvT(Lv.A, pk, pn, (const T *)nullptr, SPMV_SET, s);
+        std::swap(pk, pn);
+        k_scale_acc<T><<<grid, 256, 0, s>>>(n, (T)Lv.poly.alpha[k], pk, acc, 1);
+    }
+    if (mode != SPMV_SET) k_scale_acc<T><<<grid, 256, 0, s>>>(n, (T)1, acc, y, 1);
+    AIRG_LAUNCH_CHECK();
+}
 }  // namespace
 
 // e = V(g) on level l, vectors in level order (F points first):
 //   g_c = [Z I] g;  e_c = V(g_c);  e = [W; I] e_c;
 //   up_smooths times: e_F += Ainv (g_F - [A_ff A_fc] e).
-// Coarsest level: e = Ainv g, then (coarse_iters - 1) times e += Ainv (g - A e).
+// Coarsest level: e = Ainv g, then (coarse_iters - 1) times e += Ainv (g - A e),
+// with Ainv the assembled coarse polynomial or q(A) applied matrix-free.
 template <class T>
 void Hier::vcycle(int l, const T *g, T *e) {
     Level &Lv = L(l);
     T *t = Bufs<T>::t(Lv);
     if (Lv.coarsest) {
-        spmvT(Lv.Ainv, g, e, (const T *)nullptr, SPMV_SET, s);
+        coarse_apply<T>(*this, Lv, g, e, SPMV_SET);
         for (int it = 1; it < opt.coarse_iters; ++it) {
             spmvT(Lv.A, e, t, g, SPMV_ZMINUS, s);
-            spmvT(Lv.Ainv, t, e, (const T *)nullptr, SPMV_ADD, s);
+            coarse_apply<T>(*this, Lv, t, e, SPMV_ADD);
         }
         return;
     }
@@ -84,6 +127,14 @@ void to_natural_order(Hier &H, const double *xp, double *x) {
     else d2d(x, xp, (size_t)n, H.s);
 }
 }  // namespace
+
+void apply_vcycle(Hier &H, const double *g, double *e, int precision) {
+    int64_t n = H.L(0).n;
+    DBuf<double> gp((size_t)n, H.s), ep((size_t)n, H.s);
+    to_level_order(H, g, gp.p);
+    H.precondition(gp.p, ep.p, precision);
+    to_natural_order(H, ep.p, e);
+}
 
 // Undamped Richardson from a zero guess: x += V(b - A x) until
 // ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual every iteration).
