@@ -206,6 +206,7 @@ def single(a, airg, torch):
         return info, st
 
     extra_opts = parse_opts(a.opt)
+    extra_opts.setdefault("use_graph", 1)      # both forms replay a captured V-cycle graph
     opts32 = airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, truncate_n=trunc,
                                **extra_opts)
     opts64 = airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64, truncate_n=trunc,
@@ -257,7 +258,8 @@ def single(a, airg, torch):
     if not a.no_cpu_baseline:
         import oracle as O
         c0 = time.perf_counter()
-        H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, truncate_n=trunc, **extra_opts))
+        oracle_opts = {k: v for k, v in extra_opts.items() if k != "use_graph"}
+        H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, truncate_n=trunc, **oracle_opts))
         c1 = time.perf_counter()
         _, its, rr = H.richardson(P.b, a.rtol, 300)
         c2 = time.perf_counter()
@@ -273,8 +275,7 @@ def single(a, airg, torch):
              "vcycle_bytes_fp32": st32["vcycle_bytes_fp32"], "fp64_comparison": fp64, "resetup": resetup}
     cfg = {"workload": desc, "form": "FGMRES(30) FP64 outer + FP32 AIRG V-cycle", "rtol": a.rtol,
            "parallelism": "single GPU"}
-    if extra_opts:
-        cfg["options"] = extra_opts
+    cfg["options"] = extra_opts
     return sec, cfg, "f64 (f32 V-cycle)", roof, cpu, extra
 
 

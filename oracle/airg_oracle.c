@@ -1295,8 +1295,8 @@ void orc_hier_complexity(const orc_hier *h, double *grid, double *op, double *st
         gs += (double)L->A.nr;
         os += (double)L->A.rp[L->A.nr];
         if (l == h->nlev - 1) {
-            ss += (double)L->Ainv.rp[L->Ainv.nr];
-            if (h->p.coarse_iters > 1) ss += (double)L->A.rp[L->A.nr];
+            if (L->Ainv.rp) ss += (double)L->Ainv.rp[L->Ainv.nr];
+            if (h->p.coarse_iters > 1 || h->p.coarse_matrix_free) ss += (double)L->A.rp[L->A.nr];
         } else {
             ss += (double)L->Ainv.rp[L->Ainv.nr] + (double)L->Aff.rp[L->Aff.nr] + (double)L->Afc.rp[L->Afc.nr] +
                   (double)L->Z.rp[L->Z.nr] + (double)L->nC + (double)L->W.rp[L->W.nr] + (double)L->nC;

@@ -45,13 +45,23 @@ struct Hier {
     double phase[AIRG_PHASE_COUNT] = {};
     DBuf<double> x, r, e, bp;     // top-level work vectors
     DBuf<float> r32, e32;
+    // V-cycle graphs (use_graph): [0] FP64, [1] FP32, captured once on the
+    // private stream cap over fixed buffers and replayed on s
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipStream_t cap = nullptr;
 
+    Hier() = default;
+    Hier(const Hier &) = delete;
+    Hier &operator=(const Hier &) = delete;
+    ~Hier();
     int nlev() const { return (int)lv.size(); }
     Level &L(int l) { return *lv[l]; }
 
     template <class T>
     void vcycle(int l, const T *g, T *e);
     void precondition(const double *r, double *e, int precision);
+    void drop_graphs();
 };
 
 // Per-phase device time from events recorded around each phase.

@@ -299,6 +299,7 @@ namespace {
 
 void finalize(Hier &H) {
     hipStream_t s = H.s;
+    H.drop_graphs();   // the work vectors are reallocated below
     int nl = H.nlev();
     for (int l = 0; l < nl; ++l) {
         Level &L = H.L(l);

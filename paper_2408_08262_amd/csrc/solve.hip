@@ -58,7 +58,7 @@ void coarse_apply(Hier &H, Level &Lv, const T *x, T *y, int mode) {
     const int64_t n = Lv.n;
     T *pk = Bufs<T>::p(Lv), *pn = Bufs<T>::q(Lv), *acc = mode == SPMV_SET ? y : Bufs<T>::u(Lv);
     const unsigned grid = grid_for(n, 256);
-    d2d(pk, x, (size_t)n, s);
+    k_scale_acc<T><<<grid, 256, 0, s>>>(n, (T)1, x, pk, 0);   // pk = x (kernel: the cycle may be captured)
     k_scale_acc<T><<<grid, 256, 0, s>>>(n, (T)Lv.poly.alpha[0], pk, acc, 0);
     for (int k = 1; k < Lv.poly.m; ++k) {
         spmvT(Lv.A, pk, pn, (const T *)nullptr, SPMV_SET, s);
@@ -102,12 +102,62 @@ void Hier::vcycle(int l, const T *g, T *e) {
 template void Hier::vcycle<double>(int, const double *, double *);
 template void Hier::vcycle<float>(int, const float *, float *);
 
+Hier::~Hier() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
+void Hier::drop_graphs() {
+    for (int k = 0; k < 2; ++k) {
+        if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
+        if (graph[k]) (void)hipGraphDestroy(graph[k]);
+        gexec[k] = nullptr;
+        graph[k] = nullptr;
+    }
+}
+
+namespace {
+// Captures f's launches on the private stream once (the legacy default stream
+// cannot be captured), then replays them on the hierarchy's stream.
+template <class F>
+void run_captured(Hier &H, int k, F &&f) {
+    if (!H.gexec[k]) {
+        if (!H.cap) AIRG_HIP(hipStreamCreateWithFlags(&H.cap, hipStreamNonBlocking));
+        hipStream_t user = H.s;
+        AIRG_HIP(hipStreamBeginCapture(H.cap, hipStreamCaptureModeRelaxed));
+        H.s = H.cap;
+        try {
+            f();
+        } catch (...) {
+            H.s = user;
+            hipGraph_t dummy = nullptr;
+            (void)hipStreamEndCapture(H.cap, &dummy);
+            if (dummy) (void)hipGraphDestroy(dummy);
+            throw;
+        }
+        H.s = user;
+        AIRG_HIP(hipStreamEndCapture(H.cap, &H.graph[k]));
+        AIRG_HIP(hipGraphInstantiate(&H.gexec[k], H.graph[k], nullptr, nullptr, 0));
+    }
+    AIRG_HIP(hipGraphLaunch(H.gexec[k], H.s));
+}
+}  // namespace
+
+// With use_graph the cycle runs between fixed buffers (level 0's g and e for
+// FP64, r32/e32 for FP32) so that one captured graph serves every call.
 void Hier::precondition(const double *rv, double *ev, int precision) {
     int64_t n0 = L(0).n;
+    const bool graphed = opt.use_graph != 0;
     if (precision == 32) {
         cast_d2f(rv, r32.p, n0, s);
-        vcycle<float>(0, r32.p, e32.p);
+        if (graphed) run_captured(*this, 1, [&] { vcycle<float>(0, r32.p, e32.p); });
+        else vcycle<float>(0, r32.p, e32.p);
         cast_f2d(e32.p, ev, n0, s);
+    } else if (graphed) {
+        Level &T = L(0);
+        d2d(T.g64.p, rv, (size_t)n0, s);
+        run_captured(*this, 0, [&] { vcycle<double>(0, T.g64.p, T.e64.p); });
+        d2d(ev, T.e64.p, (size_t)n0, s);
     } else {
         vcycle<double>(0, rv, ev);
     }

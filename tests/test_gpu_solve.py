@@ -155,3 +155,27 @@ def test_truncated_hierarchy_and_stats():
     assert 1.0 < st["grid_complexity"] < 4 and st["vcycle_bytes_fp64"] > st["vcycle_bytes_fp32"] > 0
     x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
     assert info["converged"]
+
+
+@pytest.mark.parametrize("outer,prec", [(0, 64), (1, 32), (1, 64)], ids=["richardson64", "fgmres32", "fgmres64"])
+def test_captured_vcycle_graph_replays_the_eager_cycle(outer, prec):
+    """use_graph: the single hierarchy's V-cycle is captured once and replayed;
+    solves must equal the eager ones bit for bit, call after call."""
+    P = dg_square(64)
+    b = torch.as_tensor(P.b, device="cuda")
+    h0, _ = setup(P, outer=outer, precond_precision=prec)
+    h1, _ = setup(P, outer=outer, precond_precision=prec, use_graph=1)
+    x0, i0 = airg.airg_solve(h0, b, rtol=1e-10, max_it=200, allow_not_converged=True)
+    for _ in range(3):
+        x1, i1 = airg.airg_solve(h1, b, rtol=1e-10, max_it=200, allow_not_converged=True)
+        assert i1["iterations"] == i0["iterations"]
+        assert torch.equal(x0, x1)
+    g = torch.as_tensor(np.random.default_rng(1).standard_normal(P.n), device="cuda")
+    assert torch.equal(airg.airg_vcycle(h0, g, precision=prec), airg.airg_vcycle(h1, g, precision=prec))
+    # a re-setup rebuilds the work vectors; the graph is captured again
+    vals = torch.as_tensor(P.val * 1.1, device="cuda")
+    airg.airg_resetup(h0, vals)
+    airg.airg_resetup(h1, vals)
+    x0, i0 = airg.airg_solve(h0, b, rtol=1e-10, max_it=200, allow_not_converged=True)
+    x1, i1 = airg.airg_solve(h1, b, rtol=1e-10, max_it=200, allow_not_converged=True)
+    assert i1["iterations"] == i0["iterations"] and torch.equal(x0, x1)
