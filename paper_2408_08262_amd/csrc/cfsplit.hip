@@ -169,7 +169,8 @@ __global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *
                                                       const int32_t *__restrict__ tci,
                                                       const int32_t *__restrict__ deg,
                                                       const uint32_t *__restrict__ h,
-                                                      const int8_t *__restrict__ cf, uint8_t *__restrict__ inD) {
+                                                      const int8_t *__restrict__ cf, uint8_t *__restrict__ inD,
+                                                      int32_t *__restrict__ nu) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
@@ -178,6 +179,7 @@ __global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *
         if (lane == 0) inD[row] = 0;
         return;
     }
+    if (nu && lane == 0) atomicAdd(nu, 1);   // unassigned at the start of the round
     int32_t di = deg[row];
     uint32_t hi = h[row];
     bool beaten = false;
@@ -248,30 +250,47 @@ __global__ void k_pmisr_finish(int32_t n, int8_t *__restrict__ cf, int32_t *__re
     }
 }
 
+// Until no node is unassigned (max_rounds <= 0), every round's decide pass
+// also counts the unassigned nodes it starts from into nu[round]; the counts
+// are read back every kPmisrCheck rounds.  A round that starts with none
+// changes nothing, so the rounds run past the end are no-ops and the count
+// of rounds is the first round that found none.
+constexpr int kPmisrCheck = 2;
+constexpr int kPmisrSlots = 4096;
+
 int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_rounds, int8_t *cf, hipStream_t s) {
     int32_t n = A.nr;
     DBuf<uint8_t> inD((size_t)n, s);
-    DBuf<int32_t> nu(1, s);
+    const bool until_done = max_rounds <= 0;
+    DBuf<int32_t> nu(until_done ? (size_t)kPmisrSlots : 1, s);
+    if (until_done) fill_zero(nu.p, (size_t)kPmisrSlots * 4, s);
     k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, cf);
     AIRG_LAUNCH_CHECK();
     int g = lanes_for(A.nnz, n);
     int rounds = 0;
     for (;;) {
-        if (max_rounds > 0 && rounds >= max_rounds) break;
-        if (max_rounds <= 0) {
-            fill_zero(nu.p, 4, s);
-            k_pmisr_finish<<<grid_for(n, 256), 256, 0, s>>>(n, cf, nu.p);
-            AIRG_LAUNCH_CHECK();
-            if (d2h_one(nu.p, s) == 0) break;
-        }
+        if (!until_done && rounds >= max_rounds) break;
+        AIRG_REQUIRE(rounds < kPmisrSlots, ST_STALL, "PMISR did not finish");
+        int32_t *cnt = until_done ? nu.p + rounds : nullptr;
         dispatch_group(g, [&]<int W>() {
             unsigned grid = grid_for((int64_t)n * W, 256);
             k_pmisr_decide<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, G.deg.p, h, cf,
-                                                   inD.p);
+                                                   inD.p, cnt);
             k_pmisr_apply<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, inD.p, cf);
         });
         AIRG_LAUNCH_CHECK();
         ++rounds;
+        if (until_done && rounds % kPmisrCheck == 0) {
+            int32_t got[kPmisrCheck];
+            d2h(got, nu.p + rounds - kPmisrCheck, kPmisrCheck, s);
+            int first_zero = -1;
+            for (int q = 0; q < kPmisrCheck && first_zero < 0; ++q)
+                if (got[q] == 0) first_zero = rounds - kPmisrCheck + q;
+            if (first_zero >= 0) {
+                rounds = first_zero;
+                break;
+            }
+        }
     }
     k_pmisr_finish<<<grid_for(n, 256), 256, 0, s>>>(n, cf, nullptr);
     AIRG_LAUNCH_CHECK();

@@ -157,11 +157,14 @@ inline int lanes_for(int64_t nnz, int64_t rows) {
     return g;
 }
 
+// Device-to-host read of `bytes` with one stream synchronisation: small
+// word-aligned reads go through pinned host memory that a kernel writes
+// directly, larger or unaligned ones through a copy.
+void read_bytes(void *h, const void *d, size_t bytes, hipStream_t s);
 template <class T>
 inline void d2h(T *h, const T *d, size_t count, hipStream_t s) {
     if (!count) return;
-    AIRG_HIP(hipMemcpyAsync(h, d, count * sizeof(T), hipMemcpyDeviceToHost, s));
-    AIRG_HIP(hipStreamSynchronize(s));
+    read_bytes(h, d, count * sizeof(T), s);
 }
 template <class T>
 inline T d2h_one(const T *d, hipStream_t s) {
@@ -183,7 +186,8 @@ void fill_zero(void *d, size_t bytes, hipStream_t s);
 void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s);
 
 // Several small device int32 ranges (src[i], counts[i] values each) copied to
-// h back to back with one host synchronisation.
+// h back to back with one host synchronisation (one gather launch per 16
+// ranges, its table in the kernel arguments, writing pinned host memory).
 void read_ints(const std::vector<const int32_t *> &src, const std::vector<int32_t> &counts, int32_t *h,
                hipStream_t s);
 

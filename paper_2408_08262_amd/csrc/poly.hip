@@ -262,12 +262,10 @@ void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm
         which ^= 1;
         if (nb == 1) break;
     }
-    // R (column-major cols x cols) and the norms in one transfer
-    DBuf<double> both((size_t)cols * (cols + 1), s);
-    d2d(both.p, src, (size_t)cols * cols, s);
-    d2d(both.p + (size_t)cols * cols, norm.p, (size_t)cols, s);
+    // R (column-major cols x cols) and the norms in one readback
     std::vector<double> R((size_t)cols * (cols + 1));
-    d2h(R.data(), both.p, R.size(), s);
+    read_ints({reinterpret_cast<const int32_t *>(src), reinterpret_cast<const int32_t *>(norm.p)},
+              {2 * cols * cols, 2 * cols}, reinterpret_cast<int32_t *>(R.data()), s);
     for (int r = 0; r < cols; ++r)
         for (int c = 0; c < cols; ++c) h_R[r * cols + c] = R[(size_t)c * cols + r];
     for (int c = 0; c < cols; ++c) h_colnorm[c] = R[(size_t)cols * cols + c];

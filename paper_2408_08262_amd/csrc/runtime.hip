@@ -1,5 +1,6 @@
 // Runtime pieces of the AIRG library: the caching device allocator, fills,
 // and the device-wide exclusive scan used to build every CSR row pointer.
+#include <algorithm>
 #include <mutex>
 #include <unordered_map>
 
@@ -281,32 +282,107 @@ __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(const int32_t 
 }
 
 // ------------------------------------------------------ batched readback --
-// Block b copies src[b][0 .. cnt[b]) to out[off[b] ..).
-__global__ void k_gather_ints(const int32_t *const *__restrict__ src, const int32_t *__restrict__ cnt,
-                              const int32_t *__restrict__ off, int32_t *__restrict__ out) {
-    const int32_t *p = src[blockIdx.x];
-    int32_t c = cnt[blockIdx.x], o = off[blockIdx.x];
-    for (int32_t i = threadIdx.x; i < c; i += blockDim.x) out[o + i] = p[i];
+// Readbacks land in one pinned host buffer mapped into the device address
+// space: the gather kernel stores into it directly, so a readback costs one
+// launch and one stream synchronisation, with no staging copy through
+// pageable memory and no upload of the gather table.
+namespace {
+constexpr int kReadRanges = 16;
+constexpr int kReadChunk = 1024;                      // words per block and range
+constexpr size_t kReadStageMax = (size_t)1 << 22;     // bytes read through the pinned buffer
+
+struct ReadArgs {
+    const int32_t *src[kReadRanges];
+    int32_t cnt[kReadRanges];
+    int64_t off[kReadRanges];
+};
+
+// Block (x, r) copies words [x * kReadChunk, (x + 1) * kReadChunk) of range r.
+__global__ void __launch_bounds__(256) k_read_words(ReadArgs a, int32_t *__restrict__ out) {
+    const int r = blockIdx.y;
+    const int64_t end = (int64_t)a.cnt[r] < ((int64_t)blockIdx.x + 1) * kReadChunk ? (int64_t)a.cnt[r]
+                                                                                   : ((int64_t)blockIdx.x + 1) * kReadChunk;
+    const int32_t *p = a.src[r];
+    int32_t *o = out + a.off[r];
+    for (int64_t i = (int64_t)blockIdx.x * kReadChunk + threadIdx.x; i < end; i += 256) o[i] = p[i];
 }
+
+std::mutex g_read_mu;
+int32_t *g_read_host = nullptr;   // host view of the pinned buffer
+int32_t *g_read_dev = nullptr;    // its device address
+size_t g_read_words = 0;
+
+// The pinned buffer with room for `words` (g_read_mu held; every earlier
+// use has been synchronised, so the old buffer can go).
+int32_t *read_buffer(size_t words) {
+    if (words > g_read_words) {
+        if (g_read_host) (void)hipHostFree(g_read_host);
+        g_read_host = g_read_dev = nullptr;
+        g_read_words = 0;
+        size_t w = std::max<size_t>(words, (size_t)1 << 14);
+        AIRG_HIP(hipHostMalloc((void **)&g_read_host, w * sizeof(int32_t),
+                               hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent));
+        AIRG_HIP(hipHostGetDevicePointer((void **)&g_read_dev, g_read_host, 0));
+        g_read_words = w;
+    }
+    return g_read_dev;
+}
+
+// Launches the gathers of ranges [0, m) into dev (offsets in words).
+void launch_reads(const int32_t *const *src, const int32_t *cnt, const int64_t *off, size_t m, int32_t *dev,
+                  hipStream_t s) {
+    for (size_t b = 0; b < m; b += kReadRanges) {
+        ReadArgs a{};
+        const int k = (int)std::min<size_t>(kReadRanges, m - b);
+        int64_t maxc = 0;
+        for (int j = 0; j < k; ++j) {
+            a.src[j] = src[b + j];
+            a.cnt[j] = cnt[b + j];
+            a.off[j] = off[b + j];
+            maxc = std::max<int64_t>(maxc, cnt[b + j]);
+        }
+        if (maxc == 0) continue;
+        dim3 grid((unsigned)((maxc + kReadChunk - 1) / kReadChunk), (unsigned)k);
+        k_read_words<<<grid, 256, 0, s>>>(a, dev);
+        AIRG_LAUNCH_CHECK();
+    }
+}
+}  // namespace
 
 void read_ints(const std::vector<const int32_t *> &src, const std::vector<int32_t> &counts, int32_t *h,
                hipStream_t s) {
     const size_t m = src.size();
     if (m == 0) return;
-    std::vector<int32_t> off(m);
-    int32_t total = 0;
+    std::vector<int64_t> off(m);
+    int64_t total = 0;
     for (size_t i = 0; i < m; ++i) {
+        AIRG_REQUIRE(counts[i] >= 0, ST_INVALID_ARG, "negative readback count");
         off[i] = total;
         total += counts[i];
     }
-    DBuf<const int32_t *> dsrc(m, s);
-    DBuf<int32_t> dcnt(m, s), doff(m, s), out((size_t)std::max(total, 1), s);
-    h2d(dsrc.p, src.data(), m, s);
-    h2d(dcnt.p, counts.data(), m, s);
-    h2d(doff.p, off.data(), m, s);
-    k_gather_ints<<<(unsigned)m, 64, 0, s>>>(dsrc.p, dcnt.p, doff.p, out.p);
-    AIRG_LAUNCH_CHECK();
-    d2h(h, out.p, (size_t)total, s);
+    if (total == 0) return;
+    std::lock_guard<std::mutex> lk(g_read_mu);
+    int32_t *dev = read_buffer((size_t)total);
+    launch_reads(src.data(), counts.data(), off.data(), m, dev, s);
+    AIRG_HIP(hipStreamSynchronize(s));
+    std::memcpy(h, g_read_host, (size_t)total * sizeof(int32_t));
+}
+
+void read_bytes(void *h, const void *d, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    if (bytes % 4 != 0 || (uintptr_t)d % 4 != 0 || bytes > kReadStageMax) {
+        AIRG_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+        AIRG_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    const int32_t *src = static_cast<const int32_t *>(d);
+    const int32_t cnt = (int32_t)(bytes / 4);
+    const int64_t off = 0;
+    std::lock_guard<std::mutex> lk(g_read_mu);
+    int32_t *dev = read_buffer(bytes / 4);
+    launch_reads(&src, &cnt, &off, 1, dev, s);
+    AIRG_HIP(hipStreamSynchronize(s));
+    std::memcpy(h, g_read_host, bytes);
 }
 
 void resolve_sizes(const std::vector<Csr *> &ms, hipStream_t s) {
