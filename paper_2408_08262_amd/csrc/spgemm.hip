@@ -1,4 +1,5 @@
-// Two-phase sparse matrix product C = A B for gfx950 with LDS hash rows.
+// Two-phase sparse matrix product C = A B for gfx950 with LDS hash rows
+// (dense LDS accumulator rows when B has at most 4096 columns).
 //
 // Symbolic pass: rows are binned by their product-count upper bound
 // ub_i = sum_k |B_k| and their distinct columns counted by a G-lane group (or
@@ -433,6 +434,157 @@ __global__ void __launch_bounds__(kBlk) k_spgemm_block_global(const int32_t *__r
                               cnt, crp, cci, cv);
 }
 
+// -------------------------------------------------------- narrow rows ----
+// When B has at most NC <= 4096 columns (the coarse levels), one wavefront
+// builds a row of C in a dense accumulator of NC values and NC marks in LDS:
+// no hashing, no sort (the marks are read out in ascending column order) and
+// no row binning, so a product costs a count pass, a scan and a fill pass.
+// The products of up to 64 A entries at a time are staged in LDS first, so
+// that all their loads are in flight together; the fill pass then adds them
+// in ascending k (one A entry per step, the lanes over its B row, whose
+// columns are distinct) from 0.0 without contraction -- the same order and
+// rounding as the hash-table kernels.
+constexpr int kNarrowStage = 1024;
+
+template <int NC, bool NUMERIC>
+__global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *__restrict__ arp,
+                                                      const int32_t *__restrict__ aci,
+                                                      const double *__restrict__ av,
+                                                      const int32_t *__restrict__ brp,
+                                                      const int32_t *__restrict__ bci,
+                                                      const double *__restrict__ bv, int32_t *__restrict__ cnt,
+                                                      const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
+                                                      double *__restrict__ cv) {
+#pragma clang fp contract(off)
+    __shared__ double acc[NUMERIC ? NC : 1];
+    __shared__ uint8_t mark[NC];
+    __shared__ int32_t sc[kNarrowStage];
+    __shared__ double sv[NUMERIC ? kNarrowStage : 1];
+    __shared__ int32_t qoff[65], qb0[64];
+    __shared__ double qa[64];
+    const int lane = threadIdx.x;
+    const int32_t row = blockIdx.x;
+    if (row >= m) return;
+    for (int c = lane; c < NC; c += 64) {
+        mark[c] = 0;
+        if (NUMERIC) acc[c] = 0.0;
+    }
+    wave_sync();
+    const int32_t a1 = arp[row + 1];
+    for (int32_t q0 = arp[row]; q0 < a1;) {
+        const int32_t q = q0 + lane;
+        int32_t b0 = 0, len = 0;
+        double a = 0.0;
+        if (q < a1) {
+            const int32_t k = aci[q];
+            b0 = brp[k];
+            len = brp[k + 1] - b0;
+            if (NUMERIC) a = av[q];
+        }
+        int32_t x = len;   // inclusive scan of the B row lengths over the lanes
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        // entries taken now: the prefix whose products fit the stage (x is
+        // nondecreasing, so the ballot is a prefix of the lanes)
+        const int nq = __popcll(__ballot(q < a1 && x <= kNarrowStage));
+        if (nq == 0) {
+            // the first entry's B row alone exceeds the stage: read it directly
+            const int32_t kb0 = __shfl(b0, 0, 64), kl = __shfl(len, 0, 64);
+            const double ka = __shfl(a, 0, 64);
+            for (int32_t t = lane; t < kl; t += 64) {
+                const int32_t c = bci[kb0 + t];
+                if ((uint32_t)c >= (uint32_t)NC) continue;   // columns beyond B's width are not stored
+                mark[c] = 1;
+                if (NUMERIC) acc[c] = acc[c] + ka * bv[kb0 + t];
+            }
+            wave_sync();
+            q0 += 1;
+            continue;
+        }
+        if (lane < nq) {
+            qoff[lane] = x - len;
+            qb0[lane] = b0;
+            if (NUMERIC) qa[lane] = a;
+        }
+        const int32_t tot = __shfl(x, nq - 1, 64);
+        if (lane == 0) qoff[nq] = tot;
+        wave_sync();
+        // product p belongs to the last entry j with qoff[j] <= p
+        for (int32_t p = lane; p < tot; p += 64) {
+            int lo = 0, hi = nq - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (qoff[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t e = qb0[lo] + (p - qoff[lo]);
+            sc[p] = bci[e];
+            if (NUMERIC) sv[p] = qa[lo] * bv[e];
+        }
+        wave_sync();
+        if (NUMERIC) {
+            for (int j = 0; j < nq; ++j) {
+                const int32_t o1 = qoff[j + 1];
+                for (int32_t p = qoff[j] + lane; p < o1; p += 64) {
+                    const int32_t c = sc[p];
+                    if ((uint32_t)c >= (uint32_t)NC) continue;
+                    mark[c] = 1;
+                    acc[c] = acc[c] + sv[p];
+                }
+                wave_sync();
+            }
+        } else {
+            for (int32_t p = lane; p < tot; p += 64)
+                if ((uint32_t)sc[p] < (uint32_t)NC) mark[sc[p]] = 1;
+            wave_sync();
+        }
+        q0 += nq;
+    }
+    const int32_t base = NUMERIC ? crp[row] : 0;
+    int32_t w = 0;
+    for (int c0 = 0; c0 < NC; c0 += 64) {
+        const int c = c0 + lane;
+        const bool occ = mark[c] != 0;
+        const uint64_t bm = __ballot(occ);
+        if (NUMERIC && occ) {
+            const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
+            cci[base + pos] = c;
+            cv[base + pos] = acc[c];
+        }
+        w += __popcll(bm);
+    }
+    if (!NUMERIC && lane == 0) cnt[row] = w;
+}
+
+constexpr int32_t kNarrowMaxCols = 4096;
+constexpr int64_t kNarrowMaxWork = (int64_t)1 << 25;   // rows x NC: the accumulator sweeps per product
+
+template <int NC>
+static Csr spgemm_narrow(const CsrView &A, const CsrView &Bm, hipStream_t s) {
+    Csr C;
+    C.nr = A.nr;
+    C.nc = Bm.nc;
+    const int32_t m = A.nr;
+    C.rp.alloc((size_t)m + 1, s);
+    DBuf<int32_t> cnt((size_t)m + 1, s);
+    if (m > 0) {
+        k_spgemm_narrow<NC, false><<<(unsigned)m, 64, 0, s>>>(m, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt.p,
+                                                                nullptr, nullptr, nullptr);
+        AIRG_LAUNCH_CHECK();
+    }
+    C.nnz = exclusive_scan(cnt.p, C.rp.p, m, s);
+    C.ci.alloc((size_t)C.nnz, s);
+    C.v.alloc((size_t)C.nnz, s);
+    if (C.nnz > 0) {
+        k_spgemm_narrow<NC, true><<<(unsigned)m, 64, 0, s>>>(m, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, nullptr,
+                                                               C.rp.p, C.ci.p, C.v.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    return C;
+}
+
 // ------------------------------------------------------------------ host --
 static uint32_t pow2_at_least(int64_t v) {
     uint32_t p = 1;
@@ -590,6 +742,14 @@ static void run_numeric(const Bins &B, const CsrView &A, const CsrView &Bm, int3
 
 Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
     AIRG_REQUIRE(A.nc == Bm.nr, ST_INVALID_ARG, "inner dimensions differ");
+    if (Bm.nc <= kNarrowMaxCols) {
+        const int nc = Bm.nc <= 1024 ? 1024 : Bm.nc <= 2048 ? 2048 : 4096;
+        if ((int64_t)A.nr * nc <= kNarrowMaxWork) {
+            if (nc == 1024) return spgemm_narrow<1024>(A, Bm, s);
+            if (nc == 2048) return spgemm_narrow<2048>(A, Bm, s);
+            return spgemm_narrow<4096>(A, Bm, s);
+        }
+    }
     Csr C;
     C.nr = A.nr;
     C.nc = Bm.nc;

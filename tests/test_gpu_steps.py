@@ -322,3 +322,46 @@ def test_spgemm_every_bin_bit_exact():
     lens = np.diff(want[0])
     assert lens.max() > 4096 and (lens[ub > 1000] < 100).any()
     csr_equal(got, O.spgemm(A, Bt))
+
+
+@pytest.mark.parametrize("nc", [64, 1024, 2000, 4096])
+def test_spgemm_narrow_rows_bit_exact(nc):
+    """B with at most 4096 columns takes the dense-accumulator kernel: A rows
+    longer than a wavefront, stage overflows in mid-chunk, B rows longer than
+    the stage, empty rows and explicit zeros.  The same operands declared 5000
+    columns wide take the hash-table kernels; both equal the oracle."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(nc)
+    k, m = 700, 400
+    blen = rng.integers(0, min(nc, 40) + 1, size=k)
+    blen[:5] = 0
+    if nc >= 2000:
+        blen[5:8] = [1100, 1500, nc]
+    brows, bcols, bvals = [], [], []
+    for r in range(k):
+        c = np.sort(rng.choice(nc, size=blen[r], replace=False))
+        brows += [r] * len(c)
+        bcols += c.tolist()
+        v = rng.standard_normal(len(c))
+        v[rng.random(len(c)) < 0.05] = 0.0
+        bvals += v.tolist()
+    B = sp.csr_matrix((bvals, (brows, bcols)), shape=(k, nc))
+    alen = np.concatenate([np.zeros(10, int), rng.integers(1, 20, size=m - 60), rng.integers(60, 300, size=50)])
+    arows, acols, avals = [], [], []
+    for r in range(m):
+        c = np.sort(rng.choice(k, size=alen[r], replace=False))
+        if r == 12 and nc >= 2000:
+            c = np.array([0, 5, 6, 7, 9])            # the long B rows, one after another
+        arows += [r] * len(c)
+        acols += c.tolist()
+        avals += rng.standard_normal(len(c)).tolist()
+    Am = sp.csr_matrix((avals, (arows, acols)), shape=(m, k))
+    for M in (Am, B):
+        M.sort_indices()
+    A = (Am.indptr, Am.indices, Am.data, k)
+    Bt = (B.indptr, B.indices, B.data, nc)
+    want = O.spgemm(A, Bt)
+    narrow = airg.airg_spgemm(airg.to_device(*A[:3]), airg.to_device(*Bt[:3]), k, nc).to_host()
+    csr_equal(narrow, want)
+    wide = airg.airg_spgemm(airg.to_device(*A[:3]), airg.to_device(*Bt[:3]), k, 5000).to_host()
+    csr_equal(wide, want)
