@@ -38,6 +38,29 @@ __device__ inline T group_sum(T v) {
     return v;
 }
 
+// Sum over a whole wavefront (all 64 lanes active) returned to every lane:
+// a butterfly inside each row of 16 lanes on the DPP crossbar (lane swaps
+// within quads, then the half-row and row mirrors), then the four row sums
+// read out through scalar registers.  No LDS traffic, unlike the shuffle
+// tree of group_sum.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xF, 0xF, true);
+}
+__device__ inline double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 template <int G, class T>
 __device__ inline T group_max(T v) {
 #pragma unroll

@@ -111,25 +111,27 @@ __global__ void __launch_bounds__(kQrThreads) k_colsq_finish(const double *__res
 
 // -------------------------------------------------------------- TSQR leaf ---
 // Householder QR of a panel of `rows` (<= kQrRows) rows x cols staged in LDS
-// (column-major, zero-padded to kQrRows) by one wavefront: the reductions are
-// wave shuffles and the LDS traffic needs no workgroup barrier.  The upper
-// triangle of the result is the panel's R factor, written column-major at out
-// with leading dimension ldo.
+// (column-major) by one wavefront: the reductions are DPP wave sums and the
+// LDS traffic needs no workgroup barrier.  Only the first nr = rows rounded
+// up to 64 rows are touched (the rest would be zeros).  The upper triangle of
+// the result is the panel's R factor, written column-major at out with
+// leading dimension ldo.
 __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, int rows, int cols,
                          const double *__restrict__ scale, double *__restrict__ out, int64_t ldo, double *W) {
     const int lane = threadIdx.x;
+    const int nr = (rows + kQrLanes - 1) / kQrLanes * kQrLanes;
     for (int c = 0; c < cols; ++c) {
         double sc = scale ? scale[c] : 1.0;
-        for (int r = lane; r < kQrRows; r += kQrLanes)
+        for (int r = lane; r < nr; r += kQrLanes)
             W[c * kQrRows + r] = r < rows ? K[(int64_t)c * ldk + r0 + r] * sc : 0.0;
     }
     wave_sync();
-    int steps = cols < kQrRows ? cols : kQrRows;
+    int steps = cols < nr ? cols : nr;
     for (int col = 0; col < steps; ++col) {
         double *x = W + col * kQrRows;
         double part = 0.0;
-        for (int r = col + lane; r < kQrRows; r += kQrLanes) part += x[r] * x[r];
-        double nx2 = group_sum<64>(part);
+        for (int r = col + lane; r < nr; r += kQrLanes) part += x[r] * x[r];
+        double nx2 = wave_sum_f64(part);
         double x0 = x[col];
         double nx = sqrt(nx2);
         double alpha = x0 >= 0.0 ? -nx : nx;
@@ -138,7 +140,7 @@ __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, 
             double d[kMaxPolyCols];
 #pragma unroll
             for (int c = 0; c < kMaxPolyCols; ++c) d[c] = 0.0;
-            for (int r = col + lane; r < kQrRows; r += kQrLanes) {
+            for (int r = col + lane; r < nr; r += kQrLanes) {
                 double vr = r == col ? x0 - alpha : x[r];
 #pragma unroll
                 for (int c = 0; c < kMaxPolyCols; ++c)
@@ -146,8 +148,8 @@ __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, 
             }
 #pragma unroll
             for (int c = 0; c < kMaxPolyCols; ++c)
-                if (c > col && c < cols) d[c] = group_sum<64>(d[c]);
-            for (int r = col + lane; r < kQrRows; r += kQrLanes) {
+                if (c > col && c < cols) d[c] = wave_sum_f64(d[c]);
+            for (int r = col + lane; r < nr; r += kQrLanes) {
                 double vr = r == col ? x0 - alpha : x[r];
 #pragma unroll
                 for (int c = 0; c < kMaxPolyCols; ++c)
