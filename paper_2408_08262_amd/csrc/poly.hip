@@ -71,44 +71,6 @@ __device__ inline void block_sum_vec(double (&v)[N], int cnt, double *sh /* [4][
     __syncthreads();
 }
 
-// partial[c * nb + b] = sum over block b's rows of K[:, c]^2.
-__global__ void __launch_bounds__(kQrThreads) k_colsq(const double *__restrict__ K, int64_t n, int cols,
-                                                      double *__restrict__ partial) {
-    __shared__ double sh[4 * kMaxPolyCols];
-    double v[kMaxPolyCols];
-#pragma unroll
-    for (int c = 0; c < kMaxPolyCols; ++c) v[c] = 0.0;
-    int nb = gridDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * kQrThreads + threadIdx.x; i < n; i += (int64_t)nb * kQrThreads) {
-#pragma unroll
-        for (int c = 0; c < kMaxPolyCols; ++c)
-            if (c < cols) {
-                double x = K[(int64_t)c * n + i];
-                v[c] += x * x;
-            }
-    }
-    block_sum_vec<kMaxPolyCols>(v, cols, sh);
-    if (threadIdx.x < cols) partial[(int64_t)threadIdx.x * nb + blockIdx.x] = v[threadIdx.x];
-}
-
-__global__ void __launch_bounds__(kQrThreads) k_colsq_finish(const double *__restrict__ partial, int nb, int cols,
-                                                             double *__restrict__ norm, double *__restrict__ inv) {
-    __shared__ double sh[4 * kMaxPolyCols];
-    double v[kMaxPolyCols];
-#pragma unroll
-    for (int c = 0; c < kMaxPolyCols; ++c) {
-        v[c] = 0.0;
-        if (c < cols)
-            for (int b = threadIdx.x; b < nb; b += kQrThreads) v[c] += partial[(int64_t)c * nb + b];
-    }
-    block_sum_vec<kMaxPolyCols>(v, cols, sh);
-    if (threadIdx.x < cols) {
-        double nr = sqrt(v[threadIdx.x]);
-        norm[threadIdx.x] = nr;
-        inv[threadIdx.x] = nr > 0.0 ? 1.0 / nr : 1.0;
-    }
-}
-
 // -------------------------------------------------------------- TSQR leaf ---
 // Householder QR of a panel of `rows` (<= kQrRows) rows x cols staged in LDS
 // (column-major) by one wavefront: the reductions are DPP wave sums and the
@@ -120,10 +82,19 @@ __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, 
                          const double *__restrict__ scale, double *__restrict__ out, int64_t ldo, double *W) {
     const int lane = threadIdx.x;
     const int nr = (rows + kQrLanes - 1) / kQrLanes * kQrLanes;
-    for (int c = 0; c < cols; ++c) {
-        double sc = scale ? scale[c] : 1.0;
-        for (int r = lane; r < nr; r += kQrLanes)
-            W[c * kQrRows + r] = r < rows ? K[(int64_t)c * ldk + r0 + r] * sc : 0.0;
+    // the column scales (one load per lane), then every column of a row block
+    // loaded before any is stored, so that the loads are in flight together
+    const double scv = scale && lane < cols ? scale[lane] : 1.0;
+    double scl[kMaxPolyCols];
+#pragma unroll
+    for (int c = 0; c < kMaxPolyCols; ++c) scl[c] = readlane_f64(scv, c);
+    for (int r = lane; r < nr; r += kQrLanes) {
+        double t[kMaxPolyCols];
+#pragma unroll
+        for (int c = 0; c < kMaxPolyCols; ++c) t[c] = c < cols && r < rows ? K[(int64_t)c * ldk + r0 + r] : 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxPolyCols; ++c)
+            if (c < cols) W[c * kQrRows + r] = t[c] * scl[c];
     }
     wave_sync();
     int steps = cols < nr ? cols : nr;
@@ -236,18 +207,16 @@ __global__ void k_colsq_seg_finish(const double *__restrict__ partial, const int
     inv[t] = nr > 0.0 ? 1.0 / nr : 1.0;
 }
 
+// R of the column-scaled basis K D (D = diag(1 / ||K e_c||)) by a tree of
+// Householder panels over K itself: Householder QR is columnwise backward
+// stable, so R(K D) = R(K) D up to rounding, and the column norms of K are
+// those of R(K).  The scaling is therefore applied to the final R on the host
+// and the norms need no pass over K.
 void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s) {
     AIRG_REQUIRE(cols >= 1 && cols <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order too large");
-    int nbn = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 1024));
-    DBuf<double> part((size_t)nbn * cols, s), norm((size_t)cols, s), inv((size_t)cols, s);
-    k_colsq<<<nbn, kQrThreads, 0, s>>>(K, n, cols, part.p);
-    AIRG_LAUNCH_CHECK();
-    k_colsq_finish<<<1, kQrThreads, 0, s>>>(part.p, nbn, cols, norm.p, inv.p);
-    AIRG_LAUNCH_CHECK();
     size_t lds = (size_t)cols * kQrRows * sizeof(double);
     const double *src = K;
     int64_t rows = n, ld = n;
-    const double *scale = inv.p;
     DBuf<double> bufs[2];
     int which = 0;
     for (;;) {
@@ -255,22 +224,26 @@ void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm
         if (nb < 1) nb = 1;
         int64_t out_rows = nb * cols;
         bufs[which].alloc((size_t)out_rows * cols, s);
-        k_tsqr_leaf<<<(unsigned)nb, kQrLanes, lds, s>>>(src, rows, ld, cols, scale, bufs[which].p, out_rows);
+        k_tsqr_leaf<<<(unsigned)nb, kQrLanes, lds, s>>>(src, rows, ld, cols, nullptr, bufs[which].p, out_rows);
         AIRG_LAUNCH_CHECK();
         src = bufs[which].p;
         rows = out_rows;
         ld = out_rows;
-        scale = nullptr;
         which ^= 1;
         if (nb == 1) break;
     }
-    // R (column-major cols x cols) and the norms in one readback
-    std::vector<double> R((size_t)cols * (cols + 1));
-    read_ints({reinterpret_cast<const int32_t *>(src), reinterpret_cast<const int32_t *>(norm.p)},
-              {2 * cols * cols, 2 * cols}, reinterpret_cast<int32_t *>(R.data()), s);
+    std::vector<double> R((size_t)cols * cols);   // column-major
+    d2h(R.data(), src, R.size(), s);
+    for (int c = 0; c < cols; ++c) {
+        double ss = 0.0;
+        for (int r = 0; r <= c; ++r) ss += R[(size_t)c * cols + r] * R[(size_t)c * cols + r];
+        h_colnorm[c] = std::sqrt(ss);
+    }
     for (int r = 0; r < cols; ++r)
-        for (int c = 0; c < cols; ++c) h_R[r * cols + c] = R[(size_t)c * cols + r];
-    for (int c = 0; c < cols; ++c) h_colnorm[c] = R[(size_t)cols * cols + c];
+        for (int c = 0; c < cols; ++c) {
+            const double sc = h_colnorm[c] > 0.0 ? 1.0 / h_colnorm[c] : 1.0;
+            h_R[r * cols + c] = r <= c ? R[(size_t)c * cols + r] * sc : 0.0;
+        }
 }
 
 // -------------------------------------------------------- least squares ---

@@ -144,6 +144,7 @@ void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s) {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int64_t kScanFusedBlocks = 1024;   // up to this many tiles the final pass reduces the block sums itself
 
 // Exclusive scan of one value per thread across the block; returns the
 // block total through *total.
@@ -197,8 +198,21 @@ __global__ void k_scan_bsums(int64_t *bsum, int64_t nb) {
     if (threadIdx.x == 0) bsum[nb] = tot;
 }
 
+// Block b scans its tile and adds the sums of the blocks before it: with
+// SUMS_SCANNED bsum[b] already holds them (k_scan_bsums ran); otherwise the
+// block reduces bsum[0..b) itself (few, L2-resident values), which saves the
+// separate pass.  The last block writes out[n] and the total.
+template <bool SUMS_SCANNED>
 __global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
-                             const int64_t *__restrict__ bsum, int64_t nb) {
+                             const int64_t *__restrict__ bsum, int64_t nb, int64_t *__restrict__ total) {
+    int64_t before;
+    if (SUMS_SCANNED) {
+        before = bsum[blockIdx.x];
+    } else {
+        int64_t part = 0;
+        for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) part += bsum[i];
+        block_exclusive_scan(part, &before);
+    }
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t v[kScanItems];
     int64_t s = 0;
@@ -208,13 +222,16 @@ __global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict
         s += v[k];
     }
     int64_t tot;
-    int64_t off = block_exclusive_scan(s, &tot) + bsum[blockIdx.x];
+    int64_t off = block_exclusive_scan(s, &tot) + before;
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + k;
         if (i < n) out[i] = (int32_t)off;
         off += v[k];
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = (int32_t)bsum[nb];
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
+        out[n] = (int32_t)(before + tot);
+        if (!SUMS_SCANNED) *total = before + tot;
+    }
 }
 
 // Small inputs: one workgroup scans everything (one launch instead of three),
@@ -424,9 +441,13 @@ int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s
     DBuf<int64_t> bsum((size_t)nb + 1, s);
     k_scan_reduce<<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, n, bsum.p);
     AIRG_LAUNCH_CHECK();
-    k_scan_bsums<<<1, kScanThreads, 0, s>>>(bsum.p, nb);
-    AIRG_LAUNCH_CHECK();
-    k_scan_final<<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, out, n, bsum.p, nb);
+    if (nb <= kScanFusedBlocks) {
+        k_scan_final<false><<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, out, n, bsum.p, nb, bsum.p + nb);
+    } else {
+        k_scan_bsums<<<1, kScanThreads, 0, s>>>(bsum.p, nb);
+        AIRG_LAUNCH_CHECK();
+        k_scan_final<true><<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, out, n, bsum.p, nb, nullptr);
+    }
     AIRG_LAUNCH_CHECK();
     if (!want_total) return -1;
     int64_t tot = d2h_one(bsum.p + nb, s);
