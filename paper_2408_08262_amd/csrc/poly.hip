@@ -72,69 +72,84 @@ __device__ inline void block_sum_vec(double (&v)[N], int cnt, double *sh /* [4][
 }
 
 // -------------------------------------------------------------- TSQR leaf ---
-// Householder QR of a panel of `rows` (<= kQrRows) rows x cols staged in LDS
-// (column-major) by one wavefront: the reductions are DPP wave sums and the
-// LDS traffic needs no workgroup barrier.  Only the first nr = rows rounded
-// up to 64 rows are touched (the rest would be zeros).  The upper triangle of
-// the result is the panel's R factor, written column-major at out with
-// leading dimension ldo.
-__device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, int rows, int cols,
-                         const double *__restrict__ scale, double *__restrict__ out, int64_t ldo, double *W) {
+// Householder QR of a panel of `rows` (<= kQrRows) rows x cols (columns
+// scaled by `scale` when given) by one wavefront, the panel held in
+// registers: lane l owns rows l, l + 64, ... of every column.  After each
+// step the remaining columns move one register column to the left, so the
+// active column is always register column 0 and every register index is a
+// constant.  The reductions are DPP wave sums.  Row `col` of R is taken after
+// step col (alpha on the diagonal, or x0 when the column below is already
+// zero); R (cols x cols, upper triangular) is written column-major at out with
+// leading dimension ldo, through Rl (cols * cols doubles of LDS).
+__device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, int rows, int cols,
+                         const double *__restrict__ scale, double *__restrict__ out, int64_t ldo,
+                         double *__restrict__ Rl) {
+    constexpr int RPL = kQrRows / kQrLanes;
     const int lane = threadIdx.x;
-    const int nr = (rows + kQrLanes - 1) / kQrLanes * kQrLanes;
-    // the column scales (one load per lane), then every column of a row block
-    // loaded before any is stored, so that the loads are in flight together
     const double scv = scale && lane < cols ? scale[lane] : 1.0;
-    double scl[kMaxPolyCols];
+    double W[RPL][kMaxPolyCols];
 #pragma unroll
-    for (int c = 0; c < kMaxPolyCols; ++c) scl[c] = readlane_f64(scv, c);
-    for (int r = lane; r < nr; r += kQrLanes) {
-        double t[kMaxPolyCols];
+    for (int c = 0; c < kMaxPolyCols; ++c) {
+        const double sc = readlane_f64(scv, c);
 #pragma unroll
-        for (int c = 0; c < kMaxPolyCols; ++c) t[c] = c < cols && r < rows ? K[(int64_t)c * ldk + r0 + r] : 0.0;
+        for (int j = 0; j < RPL; ++j) {
+            const int r = lane + j * kQrLanes;
+            W[j][c] = c < cols && r < rows ? K[(int64_t)c * ldk + r0 + r] * sc : 0.0;
+        }
+    }
+    for (int idx = lane; idx < cols * cols; idx += kQrLanes) Rl[idx] = 0.0;
+    wave_sync();
+    for (int col = 0; col < cols; ++col) {
+        const int left = cols - col;   // active register columns 0 .. left-1
+        double part = 0.0;
 #pragma unroll
-        for (int c = 0; c < kMaxPolyCols; ++c)
-            if (c < cols) W[c * kQrRows + r] = t[c] * scl[c];
+        for (int j = 0; j < RPL; ++j)
+            if (lane + j * kQrLanes >= col) part += W[j][0] * W[j][0];
+        const double nx2 = wave_sum_f64(part);
+        const double x0 = readlane_f64(W[0][0], col);   // row col: lane col (cols <= 64)
+        const double nx = sqrt(nx2);
+        const double alpha = x0 >= 0.0 ? -nx : nx;
+        const double vv = 2.0 * nx * (nx + fabs(x0));
+        double diag = x0;
+        if (vv > 0.0) {
+            double v[RPL];
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) {
+                const int r = lane + j * kQrLanes;
+                v[j] = r == col ? x0 - alpha : (r > col ? W[j][0] : 0.0);
+            }
+#pragma unroll
+            for (int c = 1; c < kMaxPolyCols; ++c) {
+                if (c < left) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int j = 0; j < RPL; ++j) d += v[j] * W[j][c];
+                    const double f = 2.0 * wave_sum_f64(d) / vv;
+#pragma unroll
+                    for (int j = 0; j < RPL; ++j) W[j][c] -= f * v[j];
+                }
+            }
+            diag = alpha;
+        }
+        // row col of R: lane t < left takes entry (col, col + t)
+        double mine = diag;
+#pragma unroll
+        for (int c = 1; c < kMaxPolyCols; ++c) {
+            if (c < left) {
+                const double t = readlane_f64(W[0][c], col);
+                if (lane == c) mine = t;
+            }
+        }
+        if (lane < left) Rl[(col + lane) * cols + col] = mine;
+#pragma unroll
+        for (int c = 0; c + 1 < kMaxPolyCols; ++c)
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) W[j][c] = W[j][c + 1];
     }
     wave_sync();
-    int steps = cols < nr ? cols : nr;
-    for (int col = 0; col < steps; ++col) {
-        double *x = W + col * kQrRows;
-        double part = 0.0;
-        for (int r = col + lane; r < nr; r += kQrLanes) part += x[r] * x[r];
-        double nx2 = wave_sum_f64(part);
-        double x0 = x[col];
-        double nx = sqrt(nx2);
-        double alpha = x0 >= 0.0 ? -nx : nx;
-        double vv = 2.0 * nx * (nx + fabs(x0));
-        if (vv > 0.0) {
-            double d[kMaxPolyCols];
-#pragma unroll
-            for (int c = 0; c < kMaxPolyCols; ++c) d[c] = 0.0;
-            for (int r = col + lane; r < nr; r += kQrLanes) {
-                double vr = r == col ? x0 - alpha : x[r];
-#pragma unroll
-                for (int c = 0; c < kMaxPolyCols; ++c)
-                    if (c > col && c < cols) d[c] += vr * W[c * kQrRows + r];
-            }
-#pragma unroll
-            for (int c = 0; c < kMaxPolyCols; ++c)
-                if (c > col && c < cols) d[c] = wave_sum_f64(d[c]);
-            for (int r = col + lane; r < nr; r += kQrLanes) {
-                double vr = r == col ? x0 - alpha : x[r];
-#pragma unroll
-                for (int c = 0; c < kMaxPolyCols; ++c)
-                    if (c > col && c < cols) W[c * kQrRows + r] -= (2.0 * d[c] / vv) * vr;
-            }
-            wave_sync();
-            if (lane == 0) x[col] = alpha;
-        }
-        wave_sync();
-    }
     for (int idx = lane; idx < cols * cols; idx += kQrLanes) {
-        int r = idx / cols, c = idx % cols;
-        double val = (r <= c && r < steps) ? W[c * kQrRows + r] : 0.0;
-        out[(int64_t)c * ldo + r] = val;
+        const int c = idx / cols, r = idx % cols;
+        out[(int64_t)c * ldo + r] = Rl[idx];
     }
 }
 
@@ -143,10 +158,10 @@ __device__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, 
 __global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf(const double *__restrict__ K, int64_t n, int64_t ldk,
                                                         int cols, const double *__restrict__ scale,
                                                         double *__restrict__ Rs, int64_t ldr) {
-    extern __shared__ double W[];               // cols * kQrRows
+    __shared__ double Rl[kMaxPolyCols * kMaxPolyCols];
     int64_t r0 = (int64_t)blockIdx.x * kQrRows;
     int rows = (int)(n - r0 < kQrRows ? n - r0 : kQrRows);
-    qr_panel(K, ldk, r0, rows, cols, scale, Rs + (int64_t)blockIdx.x * cols, ldr, W);
+    qr_panel(K, ldk, r0, rows, cols, scale, Rs + (int64_t)blockIdx.x * cols, ldr, Rl);
 }
 
 // Batch form: one leaf per table entry; a leaf with fin >= 0 is the last of
@@ -165,11 +180,11 @@ __global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf_tab(const double *__rest
                                                               const double *__restrict__ scale,
                                                               double *__restrict__ Rs, int64_t ldr,
                                                               double *__restrict__ Rf) {
-    extern __shared__ double W[];
+    __shared__ double Rl[kMaxPolyCols * kMaxPolyCols];
     QrLeaf L = leaves[blockIdx.x];
     const double *sc = scale ? scale + (int64_t)L.seg * cols : nullptr;
-    if (L.fin >= 0) qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rf + (int64_t)L.fin * cols * cols, cols, W);
-    else qr_panel(K, ldk, L.r0, L.rows, cols, sc, Rs + L.out, ldr, W);
+    double *out = L.fin >= 0 ? Rf + (int64_t)L.fin * cols * cols : Rs + L.out;
+    qr_panel(K, ldk, L.r0, L.rows, cols, sc, out, L.fin >= 0 ? (int64_t)cols : ldr, Rl);
 }
 
 // partial[leaf * cols + c] = sum over the leaf's rows of K[:, c]^2
@@ -214,7 +229,6 @@ __global__ void k_colsq_seg_finish(const double *__restrict__ partial, const int
 // and the norms need no pass over K.
 void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s) {
     AIRG_REQUIRE(cols >= 1 && cols <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order too large");
-    size_t lds = (size_t)cols * kQrRows * sizeof(double);
     const double *src = K;
     int64_t rows = n, ld = n;
     DBuf<double> bufs[2];
@@ -224,7 +238,7 @@ void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm
         if (nb < 1) nb = 1;
         int64_t out_rows = nb * cols;
         bufs[which].alloc((size_t)out_rows * cols, s);
-        k_tsqr_leaf<<<(unsigned)nb, kQrLanes, lds, s>>>(src, rows, ld, cols, nullptr, bufs[which].p, out_rows);
+        k_tsqr_leaf<<<(unsigned)nb, kQrLanes, 0, s>>>(src, rows, ld, cols, nullptr, bufs[which].p, out_rows);
         AIRG_LAUNCH_CHECK();
         src = bufs[which].p;
         rows = out_rows;
@@ -312,7 +326,6 @@ void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, doub
     AIRG_REQUIRE(cols >= 1 && cols <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order too large");
     const int nseg = (int)off.size() - 1;
     const int64_t n = off[nseg];
-    size_t lds = (size_t)cols * kQrRows * sizeof(double);
     // round 0 leaves: the segments' own row blocks
     std::vector<QrLeaf> leaves;
     std::vector<int32_t> first(nseg + 1, 0);
@@ -372,7 +385,7 @@ void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, doub
         tables.emplace_back(tab.size(), s);
         h2d(tables.back().p, tab.data(), tab.size(), s);
         bufs[which].alloc((size_t)std::max<int64_t>(out_rows, 1) * cols, s);
-        k_tsqr_leaf_tab<<<(unsigned)tab.size(), kQrLanes, lds, s>>>(src, ld, cols, tables.back().p,
+        k_tsqr_leaf_tab<<<(unsigned)tab.size(), kQrLanes, 0, s>>>(src, ld, cols, tables.back().p,
                                                                      scaled ? inv.p : nullptr, bufs[which].p,
                                                                      std::max<int64_t>(out_rows, 1), Rf);
         AIRG_LAUNCH_CHECK();
