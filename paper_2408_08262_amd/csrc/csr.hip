@@ -955,8 +955,8 @@ __global__ void k_finish_dots(const double *__restrict__ partial, int nb, int nv
     if (threadIdx.x == 0) out[j] = s;
 }
 
-static void multi_dot_dev(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *d_out,
-                          hipStream_t s) {
+void multi_dot_dev(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *d_out,
+                   hipStream_t s) {
     int nb = red_blocks(n);
     DBuf<double> part((size_t)nb * nvec, s);
     k_multi_dot<<<nb, kRedThreads, 0, s>>>(V, ldv, nvec, w, n, part.p);
@@ -987,6 +987,19 @@ __global__ void k_gemv(const double *__restrict__ V, int64_t ldv, int nvec, cons
     for (int j = 0; j < nvec; ++j) s += V[(int64_t)j * ldv + i] * h[j];
     w[i] += sign * s;
 }
+// w *= 1 / sqrt(nn[0]) when nn[0] > 0 (the norm squared stays on the device)
+__global__ void k_normalize(double *__restrict__ w, const double *__restrict__ nn, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double q = nn[0];
+    if (i >= n || !(q > 0.0)) return;
+    w[i] = (1.0 / sqrt(q)) * w[i];
+}
+void normalize_dev(double *w, const double *nn_dev, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_normalize<<<grid_for(n, 256), 256, 0, s>>>(w, nn_dev, n);
+    AIRG_LAUNCH_CHECK();
+}
+
 void gemv_sub(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, hipStream_t s) {
     if (n <= 0 || nvec <= 0) return;
     k_gemv<<<grid_for(n, 256), 256, 0, s>>>(V, ldv, nvec, h_dev, w, n, -1.0);

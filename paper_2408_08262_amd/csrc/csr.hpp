@@ -68,6 +68,11 @@ void make_f32(Csr &A, hipStream_t s);
 // Dot products / norms with a fixed reduction order (deterministic).
 double dot(const double *x, const double *y, int64_t n, hipStream_t s);
 void multi_dot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *h_out, hipStream_t s);
+// The same dot products left on the device (d_out[0..nvec)), no synchronisation.
+void multi_dot_dev(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *d_out,
+                   hipStream_t s);
+// w *= 1 / sqrt(nn_dev[0]) when that is positive.
+void normalize_dev(double *w, const double *nn_dev, int64_t n, hipStream_t s);
 double nrm2(const double *x, int64_t n, hipStream_t s);
 
 // Elementwise helpers.

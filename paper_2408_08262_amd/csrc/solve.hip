@@ -1,8 +1,10 @@
 // Solve phase: the V-cycle with up F-point smoothing only (Results), the
 // undamped Richardson outer iteration, and flexible GMRES in FP64 around an
 // FP32 or FP64 V-cycle.
+#include <algorithm>
 #include <cmath>
 #include <utility>
+#include <vector>
 
 #include "csr.hpp"
 #include "hierarchy.hpp"
@@ -220,7 +222,9 @@ SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, i
 
 // Flexible GMRES(restart), right preconditioned by one V-cycle per Arnoldi
 // step (FP32 or FP64), classical Gram-Schmidt applied twice in FP64, Givens
-// rotations on the host, true FP64 residual at every restart.
+// rotations on the host, true FP64 residual at every restart.  The
+// Gram-Schmidt coefficients and the new vector's norm stay on the device
+// until one readback per Arnoldi step brings all of them to the host.
 SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit) {
     hipStream_t s = H.s;
     int64_t n = H.L(0).n;
@@ -228,6 +232,7 @@ SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int m
     SolveResult res;
     CsrView A = top_view(H);
     DBuf<double> V((size_t)n * (m + 1), s), Zb((size_t)n * m, s), hd((size_t)m + 1, s);
+    DBuf<double> hdev((size_t)2 * (m + 1) + 1, s);   // [h1 (m+1) | h2 (m+1) | ||w||^2]
     to_level_order(H, b, H.bp.p);
     fill_zero(H.x.p, (size_t)n * 8, s);
     double nb = nrm2(H.bp.p, n, s);
@@ -240,6 +245,7 @@ SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int m
     double beta = nb;
     int prec = H.opt.precond_precision == 32 ? 32 : 64;
     std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h1(m + 1), h2(m + 1);
+    std::vector<double> rb((size_t)2 * (m + 1) + 1);
     while (beta > rtol * nb && res.iterations < maxit) {
         scal_copy(1.0 / beta, H.r.p, V.p, n, s);
         std::fill(g.begin(), g.end(), 0.0);
@@ -250,17 +256,24 @@ SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int m
             H.precondition(vj, zj, prec);
             res.iterations++;
             spmv_top(A, zj, w, nullptr, SPMV_SET, s);
-            multi_dot(V.p, n, j + 1, w, n, h1.data(), s);
-            h2d(hd.p, h1.data(), (size_t)j + 1, s);
-            gemv_sub(V.p, n, j + 1, hd.p, w, n, s);
-            multi_dot(V.p, n, j + 1, w, n, h2.data(), s);
-            h2d(hd.p, h2.data(), (size_t)j + 1, s);
-            gemv_sub(V.p, n, j + 1, hd.p, w, n, s);
+            double *d1 = hdev.p, *d2 = hdev.p + (m + 1), *dn = hdev.p + 2 * (m + 1);
+            multi_dot_dev(V.p, n, j + 1, w, n, d1, s);
+            gemv_sub(V.p, n, j + 1, d1, w, n, s);
+            multi_dot_dev(V.p, n, j + 1, w, n, d2, s);
+            gemv_sub(V.p, n, j + 1, d2, w, n, s);
+            multi_dot_dev(w, n, 1, w, n, dn, s);
+            normalize_dev(w, dn, n, s);
+            read_ints({reinterpret_cast<const int32_t *>(d1), reinterpret_cast<const int32_t *>(d2),
+                       reinterpret_cast<const int32_t *>(dn)},
+                      {2 * (j + 1), 2 * (j + 1), 2},
+                      reinterpret_cast<int32_t *>(rb.data()), s);
+            std::copy(rb.begin(), rb.begin() + j + 1, h1.begin());
+            std::copy(rb.begin() + j + 1, rb.begin() + 2 * (j + 1), h2.begin());
+            const double nn = rb[2 * (j + 1)];
             for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = h1[i] + h2[i];
-            double hn = nrm2(w, n, s);
+            double hn = std::sqrt(nn);
             AIRG_REQUIRE(std::isfinite(hn), ST_STALL, "Arnoldi vector became non-finite");
             Hm[(size_t)(j + 1) * m + j] = hn;
-            if (hn > 0.0) scal_copy(1.0 / hn, w, w, n, s);
             for (int i = 0; i < j; ++i) {
                 double a = Hm[(size_t)i * m + j], c = Hm[(size_t)(i + 1) * m + j];
                 Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
