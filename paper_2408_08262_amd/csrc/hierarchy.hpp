@@ -1,6 +1,11 @@
 // AIRG hierarchy: setup driver (level loop of the AIRG subsection) and the
 // permuted solve-phase operators, V-cycle and outer iterations.
 #pragma once
+#include <condition_variable>
+#include <exception>
+#include <functional>
+#include <mutex>
+#include <thread>
 #include <memory>
 #include <tuple>
 #include <vector>
@@ -64,9 +69,12 @@ struct Hier {
     void drop_graphs();
 };
 
-// Per-phase device time from events recorded around each phase.
+// Per-phase device time from events recorded around each phase on the setup
+// stream; span_on times work enqueued by another thread on another stream
+// (its phase then overlaps the others).
 struct PhaseTimer {
     hipStream_t s;
+    std::mutex mu;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> spans;
     int cur = -1;
     hipEvent_t start = nullptr;
@@ -89,14 +97,29 @@ struct PhaseTimer {
         hipEvent_t stop;
         AIRG_HIP(hipEventCreate(&stop));
         AIRG_HIP(hipEventRecord(stop, s));
+        std::lock_guard<std::mutex> lk(mu);
         spans.emplace_back(cur, start, stop);
         start = nullptr;
         cur = -1;
+    }
+    template <class F>
+    void span_on(int phase, hipStream_t st, F &&f) {
+        hipEvent_t a, b;
+        AIRG_HIP(hipEventCreate(&a));
+        AIRG_HIP(hipEventCreate(&b));
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            spans.emplace_back(phase, a, b);
+        }
+        AIRG_HIP(hipEventRecord(a, st));
+        f();
+        AIRG_HIP(hipEventRecord(b, st));
     }
     void collect(double *out) {
         end();
         AIRG_HIP(hipStreamSynchronize(s));
         for (auto &t : spans) {
+            AIRG_HIP(hipEventSynchronize(std::get<2>(t)));
             float ms = 0.f;
             AIRG_HIP(hipEventElapsedTime(&ms, std::get<1>(t), std::get<2>(t)));
             out[std::get<0>(t)] += ms * 1e-3;
@@ -107,6 +130,38 @@ struct PhaseTimer {
 struct NullTimer {
     void begin(int) {}
     void end() {}
+    template <class F>
+    void span_on(int, hipStream_t, F &&f) {
+        f();
+    }
+};
+
+// A second host thread with its own stream.  start() runs a job there after
+// everything enqueued so far on the main stream; finish() waits for the job
+// and makes later work on the main stream wait for the job's work.  The two
+// threads enqueue and synchronise independently, so latency-bound work of one
+// overlaps that of the other.
+class Branch {
+public:
+    explicit Branch(hipStream_t main);
+    ~Branch();
+    Branch(const Branch &) = delete;
+    Branch &operator=(const Branch &) = delete;
+    hipStream_t stream() const { return s_; }
+    void start(std::function<void()> job);
+    void finish();        // rethrows the job's exception
+    void wait_idle();     // waits for a running job, ignoring its outcome
+private:
+    void loop();
+    hipStream_t main_, s_ = nullptr;
+    hipEvent_t fork_ = nullptr, join_ = nullptr;
+    int dev_ = 0;
+    std::thread th_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::function<void()> job_;
+    std::exception_ptr err_;
+    bool has_ = false, busy_ = false, quit_ = false;
 };
 
 // Pieces of the setup shared by the single and batch drivers.

@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(const int32_t 
 }
 
 // ------------------------------------------------------ batched readback --
-// Readbacks land in one pinned host buffer mapped into the device address
+// Readbacks land in pinned host memory mapped into the device address
 // space: the gather kernel stores into it directly, so a readback costs one
 // launch and one stream synchronisation, with no staging copy through
 // pageable memory and no upload of the gather table.
@@ -324,25 +324,44 @@ __global__ void __launch_bounds__(256) k_read_words(ReadArgs a, int32_t *__restr
     for (int64_t i = (int64_t)blockIdx.x * kReadChunk + threadIdx.x; i < end; i += 256) o[i] = p[i];
 }
 
-std::mutex g_read_mu;
-int32_t *g_read_host = nullptr;   // host view of the pinned buffer
-int32_t *g_read_dev = nullptr;    // its device address
-size_t g_read_words = 0;
+// A few pinned buffers, so that host threads driving different streams do
+// not wait on each other's synchronisations; a readback takes the first free
+// one (or waits for the first).
+struct ReadStage {
+    std::mutex mu;
+    int32_t *host = nullptr;   // host view of the pinned buffer
+    int32_t *dev = nullptr;    // its device address
+    size_t words = 0;
 
-// The pinned buffer with room for `words` (g_read_mu held; every earlier
-// use has been synchronised, so the old buffer can go).
-int32_t *read_buffer(size_t words) {
-    if (words > g_read_words) {
-        if (g_read_host) (void)hipHostFree(g_read_host);
-        g_read_host = g_read_dev = nullptr;
-        g_read_words = 0;
-        size_t w = std::max<size_t>(words, (size_t)1 << 14);
-        AIRG_HIP(hipHostMalloc((void **)&g_read_host, w * sizeof(int32_t),
-                               hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent));
-        AIRG_HIP(hipHostGetDevicePointer((void **)&g_read_dev, g_read_host, 0));
-        g_read_words = w;
+    // Room for `words` (mu held; every earlier use has been synchronised, so
+    // the old buffer can go).
+    int32_t *reserve(size_t w) {
+        if (w > words) {
+            if (host) (void)hipHostFree(host);
+            host = dev = nullptr;
+            words = 0;
+            size_t n = std::max<size_t>(w, (size_t)1 << 14);
+            AIRG_HIP(hipHostMalloc((void **)&host, n * sizeof(int32_t),
+                                   hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent));
+            AIRG_HIP(hipHostGetDevicePointer((void **)&dev, host, 0));
+            words = n;
+        }
+        return dev;
     }
-    return g_read_dev;
+};
+constexpr int kReadStages = 4;
+ReadStage g_stage[kReadStages];
+
+std::unique_lock<std::mutex> take_stage(ReadStage **out) {
+    for (auto &st : g_stage) {
+        std::unique_lock<std::mutex> lk(st.mu, std::try_to_lock);
+        if (lk.owns_lock()) {
+            *out = &st;
+            return lk;
+        }
+    }
+    *out = &g_stage[0];
+    return std::unique_lock<std::mutex>(g_stage[0].mu);
 }
 
 // Launches the gathers of ranges [0, m) into dev (offsets in words).
@@ -378,11 +397,12 @@ void read_ints(const std::vector<const int32_t *> &src, const std::vector<int32_
         total += counts[i];
     }
     if (total == 0) return;
-    std::lock_guard<std::mutex> lk(g_read_mu);
-    int32_t *dev = read_buffer((size_t)total);
+    ReadStage *st;
+    auto lk = take_stage(&st);
+    int32_t *dev = st->reserve((size_t)total);
     launch_reads(src.data(), counts.data(), off.data(), m, dev, s);
     AIRG_HIP(hipStreamSynchronize(s));
-    std::memcpy(h, g_read_host, (size_t)total * sizeof(int32_t));
+    std::memcpy(h, st->host, (size_t)total * sizeof(int32_t));
 }
 
 void read_bytes(void *h, const void *d, size_t bytes, hipStream_t s) {
@@ -395,11 +415,12 @@ void read_bytes(void *h, const void *d, size_t bytes, hipStream_t s) {
     const int32_t *src = static_cast<const int32_t *>(d);
     const int32_t cnt = (int32_t)(bytes / 4);
     const int64_t off = 0;
-    std::lock_guard<std::mutex> lk(g_read_mu);
-    int32_t *dev = read_buffer(bytes / 4);
+    ReadStage *st;
+    auto lk = take_stage(&st);
+    int32_t *dev = st->reserve(bytes / 4);
     launch_reads(&src, &cnt, &off, 1, dev, s);
     AIRG_HIP(hipStreamSynchronize(s));
-    std::memcpy(h, g_read_host, bytes);
+    std::memcpy(h, st->host, bytes);
 }
 
 void resolve_sizes(const std::vector<Csr *> &ms, hipStream_t s) {

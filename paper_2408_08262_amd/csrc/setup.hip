@@ -12,7 +12,102 @@
 
 namespace airg {
 
+// ----------------------------------------------------------------- branch --
+// One branch stream per device for the life of the process, so that device
+// blocks released on it return to the allocator's cache under a stream that
+// later setups use again.  Work of concurrent setups on it stays ordered by
+// their own fork and join events.
+static hipStream_t branch_stream(int dev) {
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize((size_t)dev + 1, nullptr);
+    if (!streams[dev]) AIRG_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    return streams[dev];
+}
+
+Branch::Branch(hipStream_t main) : main_(main) {
+    AIRG_HIP(hipGetDevice(&dev_));
+    s_ = branch_stream(dev_);
+    AIRG_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+    AIRG_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
+    th_ = std::thread([this] { loop(); });
+}
+
+Branch::~Branch() {
+    wait_idle();
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        quit_ = true;
+    }
+    cv_.notify_all();
+    th_.join();
+    (void)hipStreamSynchronize(s_);
+    (void)hipEventDestroy(fork_);
+    (void)hipEventDestroy(join_);
+}
+
+void Branch::loop() {
+    (void)hipSetDevice(dev_);
+    for (;;) {
+        std::function<void()> job;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_.wait(lk, [&] { return has_ || quit_; });
+            if (!has_) return;
+            job = std::move(job_);
+            has_ = false;
+        }
+        std::exception_ptr e;
+        try {
+            job();
+        } catch (...) {
+            e = std::current_exception();
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            err_ = e;
+            busy_ = false;
+        }
+        cv_.notify_all();
+    }
+}
+
+void Branch::start(std::function<void()> job) {
+    AIRG_HIP(hipEventRecord(fork_, main_));
+    AIRG_HIP(hipStreamWaitEvent(s_, fork_, 0));
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        job_ = std::move(job);
+        err_ = nullptr;
+        has_ = true;
+        busy_ = true;
+    }
+    cv_.notify_all();
+}
+
+void Branch::wait_idle() {
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_.wait(lk, [&] { return !busy_; });
+}
+
+void Branch::finish() {
+    wait_idle();
+    if (err_) std::rethrow_exception(err_);
+    AIRG_HIP(hipEventRecord(join_, s_));
+    AIRG_HIP(hipStreamWaitEvent(main_, join_, 0));
+}
+
 namespace {
+
+// Waits for a started branch job when the main thread leaves the scope
+// early (an exception), before the objects the job writes are destroyed.
+struct BranchGuard {
+    Branch *b = nullptr;
+    ~BranchGuard() {
+        if (b) b->wait_idle();
+    }
+};
 
 CfParams cf_params(const airg_opts &o, uint64_t seed) {
     return CfParams{o.strong_threshold, o.ddc_threshold, o.ddc_fraction, o.pmisr_max_rounds, seed};
@@ -59,14 +154,29 @@ Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, int order, hipS
 
 namespace {
 
-// Steps 2 and 7-11 of the recipe once the splitting is known.
+// Steps 2 and 7-11 of the recipe once the splitting is known.  The
+// prolongator and A P depend on the splitting only: with a Branch they are
+// built by its thread on its stream while this thread builds the F-block
+// polynomial, Ainv and Z.
 template <class Timer>
 void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl, const double *alpha_in,
                     const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, DBuf<int32_t> &fidx,
                     DBuf<int32_t> &cidx, Csr &Aff, Csr *Afc, PolyInfo &poly, Csr &Ainv, Csr &Z, Csr &W, Csr &Ac,
-                    Timer &tm, hipStream_t s) {
+                    Timer &tm, hipStream_t s, Branch *br = nullptr) {
     int32_t n = A.nr;
     int m = o.poly_order + 1;
+    Csr P, AP;
+    auto prolong = [&](hipStream_t st) {
+        tm.span_on(AIRG_PHASE_PROLONG, st, [&] {
+            onepoint_prolongator(A, cf, rank, nF, nC, o.onepoint_weight, &P, &W, st);
+            AP = spgemm(A, view(P), st);
+        });
+    };
+    BranchGuard guard;
+    if (br) {
+        guard.b = br;
+        br->start([&] { prolong(br->stream()); });
+    }
     tm.begin(AIRG_PHASE_EXTRACT);
     fidx.alloc((size_t)nF + 1, s);
     cidx.alloc((size_t)nC + 1, s);
@@ -89,13 +199,17 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
         Csr prod = spgemm(view(Acf), view(Ainv), s);
         Z = drop_rows(view(prod), o.drop_R, false, true, s);   // Z = -A_cf Ainv, dropped
     }
-    tm.begin(AIRG_PHASE_PROLONG);
-    Csr P;
-    onepoint_prolongator(A, cf, rank, nF, nC, o.onepoint_weight, &P, &W, s);
+    if (br) {
+        tm.end();
+        guard.b = nullptr;
+        br->finish();
+    } else {
+        tm.end();
+        prolong(s);
+    }
     tm.begin(AIRG_PHASE_COARSE);
     {
         Csr R = restriction_full(view(Z), fidx.p, cidx.p, n, s);
-        Csr AP = spgemm(A, view(P), s);
         Csr RAP = spgemm(view(R), view(AP), s);
         Ac = drop_rows(view(RAP), o.drop_A, true, false, s);
     }
@@ -385,6 +499,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
     first->A = std::move(A0);
     H->lv.push_back(std::move(first));
     int maxl = o.max_levels > 0 ? o.max_levels : 64;
+    Branch br(s);
     for (int l = 0;; ++l) {
         Level &L = H->L(l);
         int32_t n = L.n;
@@ -412,7 +527,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
         }
         auto next = std::make_unique<Level>();
         complete_level(view(L.A), o, seed, l, nullptr, L.cf.p, L.rank.p, L.nF, L.nC, L.fidx, L.cidx, L.Aff, &L.Afc,
-                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s);
+                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br);
         next->n = next->A.nr;
         H->lv.push_back(std::move(next));
     }
