@@ -162,7 +162,8 @@ template <class Timer>
 void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl, const double *alpha_in,
                     const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, DBuf<int32_t> &fidx,
                     DBuf<int32_t> &cidx, Csr &Aff, Csr *Afc, PolyInfo &poly, Csr &Ainv, Csr &Z, Csr &W, Csr &Ac,
-                    Timer &tm, hipStream_t s, Branch *br = nullptr) {
+                    Timer &tm, hipStream_t s, Branch *br = nullptr,
+                    const std::function<void(hipStream_t)> &pre = nullptr) {
     int32_t n = A.nr;
     int m = o.poly_order + 1;
     Csr P, AP;
@@ -175,7 +176,12 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     BranchGuard guard;
     if (br) {
         guard.b = br;
-        br->start([&] { prolong(br->stream()); });
+        br->start([&] {
+            if (pre) pre(br->stream());
+            prolong(br->stream());
+        });
+    } else if (pre) {
+        pre(s);
     }
     tm.begin(AIRG_PHASE_EXTRACT);
     fidx.alloc((size_t)nF + 1, s);
@@ -411,49 +417,67 @@ void build_pp_fill(Csr &P, const Csr &W, int32_t nF, const int32_t *nperm, hipSt
 
 namespace {
 
-void finalize(Hier &H) {
+// Level l's permutation to level order (F by rank, then C).
+void level_perm(Level &L, hipStream_t s) {
+    if (L.coarsest) return;
+    L.perm.alloc((size_t)L.n, s);
+    L.iperm.alloc((size_t)L.n, s);
+    make_level_perm(L.n, L.nF, L.nC, L.cf.p, L.rank.p, L.perm.p, L.iperm.p, s);
+}
+
+// Level l's solve operators [A_ff A_fc], [Z I] and [W; I] in level order
+// (the next level's permutation must exist): row counts and scans first, the
+// sizes of many matrices then come back in one readback, then the fills.
+void solve_ops_begin(Hier &H, int l, std::vector<Csr *> &pending, hipStream_t s) {
+    Level &L = H.L(l), &N = H.L(l + 1);
+    L.AF = permute_fc_begin(view(L.A), L.fidx.p, L.nF, s);
+    L.Rp = build_rp_begin(L.Z, L.nC, L.n, N.coarsest ? nullptr : N.iperm.p, s);
+    L.Pp = build_pp_begin(L.W, L.nF, L.nC, L.nC, s);
+    pending.insert(pending.end(), {&L.AF, &L.Rp, &L.Pp});
+}
+void solve_ops_fill(Hier &H, int l, hipStream_t s) {
+    Level &L = H.L(l), &N = H.L(l + 1);
+    permute_fc_fill(L.AF, view(L.A), L.fidx.p, L.cf.p, L.rank.p, L.nF, s);
+    build_rp_fill(L.Rp, L.Z, L.nF, N.coarsest ? nullptr : N.iperm.p, s);
+    build_pp_fill(L.Pp, L.W, L.nF, N.coarsest ? nullptr : N.perm.p, s);
+    make_f32(L.AF, s);
+    make_f32(L.Rp, s);
+    make_f32(L.Pp, s);
+    make_f32(L.Ainv, s);
+}
+void solve_ops(Hier &H, int l, hipStream_t s) {
+    std::vector<Csr *> pending;
+    solve_ops_begin(H, l, pending, s);
+    resolve_sizes(pending, s);
+    solve_ops_fill(H, l, s);
+}
+
+// Solve-phase objects of levels [built, coarsest) (permutations of every
+// level made where missing), the coarsest level's FP32 copies, the top
+// operator in level order and the work vectors.
+void finalize(Hier &H, int built = 0) {
     hipStream_t s = H.s;
     H.drop_graphs();   // the work vectors are reallocated below
     int nl = H.nlev();
-    for (int l = 0; l < nl; ++l) {
-        Level &L = H.L(l);
-        if (L.coarsest) continue;
-        L.perm.alloc((size_t)L.n, s);
-        L.iperm.alloc((size_t)L.n, s);
-        make_level_perm(L.n, L.nF, L.nC, L.cf.p, L.rank.p, L.perm.p, L.iperm.p, s);
-    }
-    // all levels' solve operators: counts and scans, one size readback, fills
+    for (int l = 0; l < nl; ++l)
+        if (!H.L(l).perm.p) level_perm(H.L(l), s);
     std::vector<Csr *> pending;
-    for (int l = 0; l < nl; ++l) {
-        Level &L = H.L(l);
-        if (L.coarsest) continue;
-        Level &N = H.L(l + 1);
-        L.AF = permute_fc_begin(view(L.A), L.fidx.p, L.nF, s);
-        L.Rp = build_rp_begin(L.Z, L.nC, L.n, N.coarsest ? nullptr : N.iperm.p, s);
-        L.Pp = build_pp_begin(L.W, L.nF, L.nC, L.nC, s);
-        pending.insert(pending.end(), {&L.AF, &L.Rp, &L.Pp});
-    }
+    for (int l = built; l < nl; ++l)
+        if (!H.L(l).coarsest) solve_ops_begin(H, l, pending, s);
     Level &T = H.L(0);
     if (!T.coarsest) {
         H.A0p = permute_fc_begin(view(T.A), T.iperm.p, T.n, s);
         pending.push_back(&H.A0p);
     }
     resolve_sizes(pending, s);
-    for (int l = 0; l < nl; ++l) {
+    for (int l = built; l < nl; ++l) {
         Level &L = H.L(l);
         if (L.coarsest) {
             make_f32(L.A, s);
             if (L.Ainv.rp.p) make_f32(L.Ainv, s);
             continue;
         }
-        Level &N = H.L(l + 1);
-        permute_fc_fill(L.AF, view(L.A), L.fidx.p, L.cf.p, L.rank.p, L.nF, s);
-        build_rp_fill(L.Rp, L.Z, L.nF, N.coarsest ? nullptr : N.iperm.p, s);
-        build_pp_fill(L.Pp, L.W, L.nF, N.coarsest ? nullptr : N.perm.p, s);
-        make_f32(L.AF, s);
-        make_f32(L.Rp, s);
-        make_f32(L.Pp, s);
-        make_f32(L.Ainv, s);
+        solve_ops_fill(H, l, s);
     }
     if (T.coarsest) {
         H.top_permuted = false;
@@ -526,13 +550,20 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             break;
         }
         auto next = std::make_unique<Level>();
+        // the branch also makes this level's permutation and the previous
+        // level's solve operators, which need it
+        Hier &HH = *H;
+        auto pre = [&HH, l](hipStream_t st) {
+            level_perm(HH.L(l), st);
+            if (l > 0) solve_ops(HH, l - 1, st);
+        };
         complete_level(view(L.A), o, seed, l, nullptr, L.cf.p, L.rank.p, L.nF, L.nC, L.fidx, L.cidx, L.Aff, &L.Afc,
-                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br);
+                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br, pre);
         next->n = next->A.nr;
         H->lv.push_back(std::move(next));
     }
     tm.begin(AIRG_PHASE_FINALIZE);
-    finalize(*H);
+    finalize(*H, std::max(0, H->nlev() - 2));
     tm.collect(H->phase);
     H->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return H;
