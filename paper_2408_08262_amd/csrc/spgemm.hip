@@ -89,6 +89,87 @@ __device__ inline void for_products(int32_t row, const int32_t *__restrict__ arp
     }
 }
 
+// Staged visit for one wavefront per row (G = 64): the products of up to 64
+// A entries at a time (at most kStage of them) are loaded into LDS first, all
+// their loads in flight together, and then visited from LDS -- A entry by A
+// entry, with a wave barrier between entries, when ORDERED.  An A entry whose
+// B row alone exceeds the stage is visited straight from global memory.  The
+// products and their order per table slot are those of for_products.
+constexpr int kStage = 1024;
+template <bool VALUES>
+struct ProdStage {
+    int32_t c[kStage];
+    double v[VALUES ? kStage : 1];
+    int32_t off[65], b0[64];
+    double a[64];
+};
+
+template <bool ORDERED, bool VALUES, class F>
+__device__ inline void for_products_staged(int32_t row, const int32_t *__restrict__ arp,
+                                           const int32_t *__restrict__ aci, const double *__restrict__ av,
+                                           const int32_t *__restrict__ brp, const int32_t *__restrict__ bci,
+                                           const double *__restrict__ bv, ProdStage<VALUES> &S, F &&f) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const int32_t a1 = arp[row + 1];
+    for (int32_t q0 = arp[row]; q0 < a1;) {
+        const int32_t q = q0 + lane;
+        int32_t b0 = 0, len = 0;
+        double a = 0.0;
+        if (q < a1) {
+            const int32_t k = aci[q];
+            b0 = brp[k];
+            len = brp[k + 1] - b0;
+            if (VALUES) a = av[q];
+        }
+        int32_t x = len;   // inclusive scan of the B row lengths
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const int nq = __popcll(__ballot(q < a1 && x <= kStage));   // a prefix of the lanes
+        if (nq == 0) {
+            const int32_t kb0 = __shfl(b0, 0, 64), kl = __shfl(len, 0, 64);
+            const double ka = VALUES ? __shfl(a, 0, 64) : 0.0;
+            for (int32_t t = lane; t < kl; t += 64) f(bci[kb0 + t], VALUES ? ka * bv[kb0 + t] : 0.0);
+            wave_sync();
+            q0 += 1;
+            continue;
+        }
+        if (lane < nq) {
+            S.off[lane] = x - len;
+            S.b0[lane] = b0;
+            if (VALUES) S.a[lane] = a;
+        }
+        const int32_t tot = __shfl(x, nq - 1, 64);
+        if (lane == 0) S.off[nq] = tot;
+        wave_sync();
+        for (int32_t p = lane; p < tot; p += 64) {
+            int lo = 0, hi = nq - 1;   // the last entry j with off[j] <= p
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (S.off[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t e = S.b0[lo] + (p - S.off[lo]);
+            S.c[p] = bci[e];
+            if (VALUES) S.v[p] = S.a[lo] * bv[e];
+        }
+        wave_sync();
+        if (ORDERED) {
+            for (int j = 0; j < nq; ++j) {
+                const int32_t o1 = S.off[j + 1];
+                for (int32_t p = S.off[j] + lane; p < o1; p += 64) f(S.c[p], VALUES ? S.v[p] : 0.0);
+                wave_sync();
+            }
+        } else {
+            for (int32_t p = lane; p < tot; p += 64) f(S.c[p], VALUES ? S.v[p] : 0.0);
+            wave_sync();
+        }
+        q0 += nq;
+    }
+}
+
 __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
                             const int32_t *__restrict__ brp, int32_t *__restrict__ ub, int8_t *__restrict__ bin) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,11 +225,17 @@ __global__ void __launch_bounds__(TPB) k_spgemm_count(const int32_t *__restrict_
     for (int t = lane; t < T; t += G) keys[t] = kEmpty;
     wave_sync();
     int fresh_cnt = 0;
-    for_products<G, false, false>(row, arp, aci, nullptr, brp, bci, nullptr, [&](int32_t c, double) {
+    auto ins = [&](int32_t c, double) {
         bool fresh;
         hash_insert(keys, T - 1, c, &fresh);
         fresh_cnt += fresh;
-    });
+    };
+    if constexpr (G == 64) {
+        __shared__ ProdStage<false> St[NG];
+        for_products_staged<false, false>(row, arp, aci, nullptr, brp, bci, nullptr, St[gid], ins);
+    } else {
+        for_products<G, false, false>(row, arp, aci, nullptr, brp, bci, nullptr, ins);
+    }
     fresh_cnt = group_sum<G>(fresh_cnt);
     if (lane == 0) cnt[row] = fresh_cnt;
 }
@@ -250,11 +337,17 @@ __global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__
         vals[t] = 0.0;
     }
     wave_sync();
-    for_products<G, true, true>(row, arp, aci, av, brp, bci, bv, [&](int32_t c, double p) {
+    auto acc = [&](int32_t c, double p) {
         bool fresh;
         uint32_t s = hash_insert(keys, T - 1, c, &fresh);
         vals[s] = vals[s] + p;
-    });
+    };
+    if constexpr (G == 64) {
+        __shared__ ProdStage<true> St[NG];
+        for_products_staged<true, true>(row, arp, aci, av, brp, bci, bv, St[gid], acc);
+    } else {
+        for_products<G, true, true>(row, arp, aci, av, brp, bci, bv, acc);
+    }
     wave_sync();
     int w = 0;
     for (int t0 = 0; t0 < T; t0 += G) {
@@ -628,7 +721,7 @@ __global__ void __launch_bounds__(TPB) k_spgemm_on_pattern(const int32_t *__rest
         vals[t] = 0.0;
     }
     wave_sync();
-    for_products<G, true, true>(row, arp, aci, av, brp, bci, bv, [&](int32_t c, double p) {
+    auto acc = [&](int32_t c, double p) {
         int lo = 0, hi = len;
         while (lo < hi) {
             int mid = (lo + hi) >> 1;
@@ -636,7 +729,13 @@ __global__ void __launch_bounds__(TPB) k_spgemm_on_pattern(const int32_t *__rest
             else hi = mid;
         }
         if (lo < len && cols[lo] == c) vals[lo] = vals[lo] + p;
-    });
+    };
+    if constexpr (G == 64) {
+        __shared__ ProdStage<true> St[NG];
+        for_products_staged<true, true>(row, arp, aci, av, brp, bci, bv, St[gid], acc);
+    } else {
+        for_products<G, true, true>(row, arp, aci, av, brp, bci, bv, acc);
+    }
     wave_sync();
     for (int t = lane; t < len; t += G) out[p0 + t] = sign * vals[t];
 }

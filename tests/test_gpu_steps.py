@@ -365,3 +365,38 @@ def test_spgemm_narrow_rows_bit_exact(nc):
     csr_equal(narrow, want)
     wide = airg.airg_spgemm(airg.to_device(*A[:3]), airg.to_device(*Bt[:3]), k, 5000).to_host()
     csr_equal(wide, want)
+
+
+def test_spgemm_staged_rows_with_long_b_rows():
+    """Rows in the whole-wavefront bins (ub up to 2048) whose products are
+    staged in LDS: B rows longer than the stage (1024 entries) are read
+    directly, shorter ones staged several A entries at a time; columns
+    collide across A entries.  Equal to the oracle bit for bit."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(17)
+    n, k = 6000, 40
+    blen = np.concatenate([rng.integers(1030, 1900, size=8), rng.integers(20, 200, size=k - 8)])
+    brows, bcols, bvals = [], [], []
+    for r in range(k):
+        pool = 2500 if r % 2 else n                  # half the rows share a narrower column range
+        c = np.sort(rng.choice(pool, size=blen[r], replace=False))
+        brows += [r] * len(c)
+        bcols += c.tolist()
+        bvals += rng.standard_normal(len(c)).tolist()
+    B = sp.csr_matrix((bvals, (brows, bcols)), shape=(k, n))
+    arows, acols, avals = [], [], []
+    for r in range(60):
+        if r < 8:
+            c = [r]                                  # one long B row: ub 1030..1900
+        else:
+            c = np.sort(rng.choice(np.arange(8, k), size=int(rng.integers(3, 12)), replace=False)).tolist()
+        arows += [r] * len(c)
+        acols += list(c)
+        avals += rng.standard_normal(len(c)).tolist()
+    Am = sp.csr_matrix((avals, (arows, acols)), shape=(60, k))
+    for M in (Am, B):
+        M.sort_indices()
+    A = (Am.indptr, Am.indices, Am.data, k)
+    Bt = (B.indptr, B.indices, B.data, n)
+    got = airg.airg_spgemm(airg.to_device(*A[:3]), airg.to_device(*Bt[:3]), k, n).to_host()
+    csr_equal(got, O.spgemm(A, Bt))
