@@ -105,8 +105,10 @@ StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
     AIRG_LAUNCH_CHECK();
     k_degree<<<grid_for(n, 256), 256, 0, s>>>(n, cntS.p, cntT.p, mutual.p, G.deg.p);
     AIRG_LAUNCH_CHECK();
-    int64_t nt = exclusive_scan(cntT.p, G.trp.p, n, s);
-    G.tci.alloc((size_t)nt, s);
+    // the transposed lists hold the strong entries, at most nnz(A) of them:
+    // allocated at that bound, so that their size needs no readback
+    exclusive_scan(cntT.p, G.trp.p, n, s, false);
+    G.tci.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
     DBuf<int32_t> cursor((size_t)n, s);
     fill_zero(cursor.p, (size_t)n * 4, s);
     dispatch_group(g, [&]<int W>() {

@@ -195,6 +195,10 @@ void read_ints(const std::vector<const int32_t *> &src, const std::vector<int32_
 // out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  Returns
 // the total (synchronising) when want_total is set.
 int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, bool want_total = true);
+// Up to four independent exclusive scans (out[r] of n[r] + 1 entries) in the
+// same launches; no synchronisation.
+void exclusive_scans(const std::vector<const int32_t *> &in, const std::vector<int32_t *> &out,
+                     const std::vector<int64_t> &n, hipStream_t s);
 
 // Counter-based generator shared by the PMISR keys and the Box-Muller rhs:
 // the SplitMix64 output function (Steele, Lea & Flood 2014) of a counter

@@ -472,9 +472,7 @@ CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s) {
     DBuf<int32_t> sF((size_t)n + 1, s), sC((size_t)n + 1, s), sT((size_t)n + 1, s), tot(3, s);
     k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p, fT.p);
     AIRG_LAUNCH_CHECK();
-    exclusive_scan(fF.p, sF.p, n, s, false);
-    exclusive_scan(fC.p, sC.p, n, s, false);
-    exclusive_scan(fT.p, sT.p, n, s, false);
+    exclusive_scans({fF.p, fC.p, fT.p}, {sF.p, sC.p, sT.p}, {n, n, n}, s);
     k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, sT.p, rank, tot.p);
     AIRG_LAUNCH_CHECK();
     int32_t h[3];
@@ -501,9 +499,7 @@ CfCounts cf_ranks_seg(const int8_t *cf, int32_t n, int32_t *rank, const int32_t 
     DBuf<int32_t> bnd((size_t)3 * (na + 1), s);
     k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p, fT.p);
     AIRG_LAUNCH_CHECK();
-    exclusive_scan(fF.p, sF.p, n, s, false);
-    exclusive_scan(fC.p, sC.p, n, s, false);
-    exclusive_scan(fT.p, sT.p, n, s, false);
+    exclusive_scans({fF.p, fC.p, fT.p}, {sF.p, sC.p, sT.p}, {n, n, n}, s);
     k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, sT.p, rank, tot.p);
     AIRG_LAUNCH_CHECK();
     k_cf_bounds<<<grid_for(na + 1, 256), 256, 0, s>>>(sF.p, sC.p, sT.p, d_off, na, bnd.p);
@@ -669,9 +665,7 @@ void extract_fc_blocks(const CsrView &A, const int8_t *cf, const int32_t *rank, 
                                                                              cfc.p, ccf.p);
     });
     AIRG_LAUNCH_CHECK();
-    exclusive_scan(cff.p, Aff.rp.p, nF, s, false);
-    exclusive_scan(cfc.p, Afc.rp.p, nF, s, false);
-    exclusive_scan(ccf.p, Acf.rp.p, nC, s, false);
+    exclusive_scans({cff.p, cfc.p, ccf.p}, {Aff.rp.p, Afc.rp.p, Acf.rp.p}, {nF, nF, nC}, s);
     resolve_sizes({&Aff, &Afc, &Acf}, s);
     dispatch_group(g, [&]<int G>() {
         k_extract3_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(

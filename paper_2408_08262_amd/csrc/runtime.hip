@@ -169,7 +169,25 @@ __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t *total) {
     return off + x - v;
 }
 
-__global__ void k_scan_reduce(const int32_t *__restrict__ in, int64_t n, int64_t *__restrict__ bsum) {
+// Up to kScanArrays independent arrays are scanned by the same launches,
+// blockIdx.y selecting the array.
+constexpr int kScanArrays = 4;
+struct ScanSet {
+    const int32_t *in[kScanArrays];
+    int32_t *out[kScanArrays];
+    int64_t n[kScanArrays];
+    int64_t *bsum[kScanArrays];   // nb + 1 block sums per array (tiled path); [0] the total (small path)
+};
+
+__host__ __device__ inline int64_t scan_tiles(int64_t n) {
+    return n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
+}
+
+__global__ void k_scan_reduce(ScanSet S) {
+    const int r = blockIdx.y;
+    const int32_t *in = S.in[r];
+    const int64_t n = S.n[r];
+    if ((int64_t)blockIdx.x >= scan_tiles(n)) return;
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     int64_t s = 0;
     for (int k = 0; k < kScanItems; ++k) {
@@ -178,11 +196,15 @@ __global__ void k_scan_reduce(const int32_t *__restrict__ in, int64_t n, int64_t
     }
     int64_t tot;
     block_exclusive_scan(s, &tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    if (threadIdx.x == 0) S.bsum[r][blockIdx.x] = tot;
 }
 
-// Single block: exclusive scan of the nb block sums in place, total at bsum[nb].
-__global__ void k_scan_bsums(int64_t *bsum, int64_t nb) {
+// Single block per array: exclusive scan of the nb block sums in place,
+// total at bsum[nb].
+__global__ void k_scan_bsums(ScanSet S) {
+    const int r = blockIdx.y;
+    int64_t *bsum = S.bsum[r];
+    const int64_t nb = scan_tiles(S.n[r]);
     int64_t per = (nb + kScanThreads - 1) / kScanThreads;
     int64_t lo = (int64_t)threadIdx.x * per;
     int64_t hi = lo + per < nb ? lo + per : nb;
@@ -201,10 +223,16 @@ __global__ void k_scan_bsums(int64_t *bsum, int64_t nb) {
 // Block b scans its tile and adds the sums of the blocks before it: with
 // SUMS_SCANNED bsum[b] already holds them (k_scan_bsums ran); otherwise the
 // block reduces bsum[0..b) itself (few, L2-resident values), which saves the
-// separate pass.  The last block writes out[n] and the total.
+// separate pass.  The last block writes out[n] and the total at bsum[nb].
 template <bool SUMS_SCANNED>
-__global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
-                             const int64_t *__restrict__ bsum, int64_t nb, int64_t *__restrict__ total) {
+__global__ void k_scan_final(ScanSet S) {
+    const int r = blockIdx.y;
+    const int32_t *in = S.in[r];
+    int32_t *out = S.out[r];
+    const int64_t n = S.n[r];
+    int64_t *bsum = S.bsum[r];
+    const int64_t nb = scan_tiles(n);
+    if ((int64_t)blockIdx.x >= nb) return;
     int64_t before;
     if (SUMS_SCANNED) {
         before = bsum[blockIdx.x];
@@ -228,16 +256,16 @@ __global__ void k_scan_final(const int32_t *__restrict__ in, int32_t *__restrict
         if (i < n) out[i] = (int32_t)off;
         off += v[k];
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
+    if ((int64_t)blockIdx.x == nb - 1 && threadIdx.x == 0) {
         out[n] = (int32_t)(before + tot);
-        if (!SUMS_SCANNED) *total = before + tot;
+        if (!SUMS_SCANNED) bsum[nb] = before + tot;
     }
 }
 
-// Small inputs: one workgroup scans everything (one launch instead of three),
-// a tile of kSmallScanTile entries at a time: coalesced loads into LDS, each
-// thread scans kSmallScanItems consecutive entries there, a workgroup scan of
-// the per-thread sums, coalesced stores, and a carry into the next tile.
+// Small inputs: one workgroup per array scans everything, a tile of
+// kSmallScanTile entries at a time: coalesced loads into LDS, each thread
+// scans kSmallScanItems consecutive entries there, a workgroup scan of the
+// per-thread sums, coalesced stores, and a carry into the next tile.
 constexpr int kSmallScanThreads = 1024;
 constexpr int kSmallScanItems = 8;
 constexpr int kSmallScanTile = kSmallScanThreads * kSmallScanItems;
@@ -245,11 +273,13 @@ constexpr int64_t kSmallScan = 16384;
 
 __device__ inline int small_scan_slot(int p) { return p + (p >> 5); }   // pads out LDS bank conflicts
 
-__global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(const int32_t *__restrict__ in,
-                                                                  int32_t *__restrict__ out, int64_t n,
-                                                                  int64_t *__restrict__ total) {
+__global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(ScanSet S) {
     __shared__ int32_t buf[kSmallScanTile + kSmallScanTile / 32];
     __shared__ int64_t wsum[kSmallScanThreads / kWave];
+    const int r = blockIdx.y;
+    const int32_t *in = S.in[r];
+    int32_t *out = S.out[r];
+    const int64_t n = S.n[r];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     int64_t carry = 0;
     for (int64_t t0 = 0; t0 < n; t0 += kSmallScanTile) {
@@ -294,7 +324,7 @@ __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(const int32_t 
     }
     if (tid == 0) {
         out[n] = (int32_t)carry;
-        *total = carry;
+        S.bsum[r][0] = carry;
     }
 }
 
@@ -444,36 +474,59 @@ void resolve_sizes(const std::vector<Csr *> &ms, hipStream_t s) {
 // Blocked layout: thread t of block b owns items [b*tile + t*items, +items).
 // The reduce kernel above strides differently, but only block totals are
 // taken from it, and those do not depend on the layout inside the tile.
-int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, bool want_total) {
-    if (n == 0) {
-        fill_zero(out, sizeof(int32_t), s);
-        return 0;
+// Returns where each array's total lands on the device.
+static std::vector<const int64_t *> scan_set(const int32_t *const *in, int32_t *const *out, const int64_t *n, int k,
+                                             DBuf<int64_t> &sums, hipStream_t s) {
+    AIRG_REQUIRE(k >= 1 && k <= kScanArrays, ST_INVALID_ARG, "bad number of scans");
+    ScanSet S{};
+    bool small = true;
+    int64_t maxnb = 1, slots = 0;
+    for (int r = 0; r < k; ++r) {
+        small = small && n[r] <= kSmallScan;
+        maxnb = std::max(maxnb, scan_tiles(n[r]));
+        slots += scan_tiles(n[r]) + 1;
     }
-    if (n <= kSmallScan) {
-        DBuf<int64_t> tot(1, s);
-        k_scan_small<<<1, kSmallScanThreads, 0, s>>>(in, out, n, tot.p);
-        AIRG_LAUNCH_CHECK();
-        if (!want_total) return -1;
-        int64_t t = d2h_one(tot.p, s);
-        AIRG_REQUIRE(t < ((int64_t)1 << 31), ST_LIMIT, "prefix sum exceeds the int32 index range");
-        return t;
+    sums.alloc((size_t)slots, s);
+    std::vector<const int64_t *> tot((size_t)k);
+    int64_t o = 0;
+    for (int r = 0; r < k; ++r) {
+        S.in[r] = in[r];
+        S.out[r] = out[r];
+        S.n[r] = n[r];
+        S.bsum[r] = sums.p + o;
+        tot[r] = small ? sums.p + o : sums.p + o + scan_tiles(n[r]);
+        o += scan_tiles(n[r]) + 1;
     }
-    int64_t nb = (n + kScanTile - 1) / kScanTile;
-    DBuf<int64_t> bsum((size_t)nb + 1, s);
-    k_scan_reduce<<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, n, bsum.p);
-    AIRG_LAUNCH_CHECK();
-    if (nb <= kScanFusedBlocks) {
-        k_scan_final<false><<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, out, n, bsum.p, nb, bsum.p + nb);
+    if (small) {
+        k_scan_small<<<dim3(1, k), kSmallScanThreads, 0, s>>>(S);
     } else {
-        k_scan_bsums<<<1, kScanThreads, 0, s>>>(bsum.p, nb);
+        k_scan_reduce<<<dim3((unsigned)maxnb, k), kScanThreads, 0, s>>>(S);
         AIRG_LAUNCH_CHECK();
-        k_scan_final<true><<<grid_for(n, kScanTile), kScanThreads, 0, s>>>(in, out, n, bsum.p, nb, nullptr);
+        if (maxnb <= kScanFusedBlocks) {
+            k_scan_final<false><<<dim3((unsigned)maxnb, k), kScanThreads, 0, s>>>(S);
+        } else {
+            k_scan_bsums<<<dim3(1, k), kScanThreads, 0, s>>>(S);
+            AIRG_LAUNCH_CHECK();
+            k_scan_final<true><<<dim3((unsigned)maxnb, k), kScanThreads, 0, s>>>(S);
+        }
     }
     AIRG_LAUNCH_CHECK();
-    if (!want_total) return -1;
-    int64_t tot = d2h_one(bsum.p + nb, s);
-    AIRG_REQUIRE(tot < ((int64_t)1 << 31), ST_LIMIT, "prefix sum exceeds the int32 index range");
     return tot;
+}
+
+void exclusive_scans(const std::vector<const int32_t *> &in, const std::vector<int32_t *> &out,
+                     const std::vector<int64_t> &n, hipStream_t s) {
+    DBuf<int64_t> sums;
+    scan_set(in.data(), out.data(), n.data(), (int)in.size(), sums, s);
+}
+
+int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, bool want_total) {
+    DBuf<int64_t> sums;
+    auto tot = scan_set(&in, &out, &n, 1, sums, s);
+    if (!want_total) return -1;
+    int64_t t = d2h_one(tot[0], s);
+    AIRG_REQUIRE(t < ((int64_t)1 << 31), ST_LIMIT, "prefix sum exceeds the int32 index range");
+    return t;
 }
 
 }  // namespace airg

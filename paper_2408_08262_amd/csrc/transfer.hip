@@ -96,11 +96,10 @@ void onepoint_prolongator(const CsrView &A, const int8_t *cf, const int32_t *ran
     P->nr = n;
     P->nc = nC;
     P->rp.alloc((size_t)n + 1, s);
-    exclusive_scan(cntP.p, P->rp.p, n, s, false);
     W->nr = nF;
     W->nc = nC;
     W->rp.alloc((size_t)nF + 1, s);
-    exclusive_scan(cntW.p, W->rp.p, nF, s, false);
+    exclusive_scans({cntP.p, cntW.p}, {P->rp.p, W->rp.p}, {n, nF}, s);
     resolve_sizes({P, W}, s);
     k_p_fill<<<grid_for(n, 256), 256, 0, s>>>(n, cf, rank, wcol.p, wval.p, P->rp.p, P->ci.p, P->v.p, W->rp.p,
                                               W->ci.p, W->v.p);
