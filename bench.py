@@ -58,17 +58,30 @@ def parse():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 TOP_KERNEL = "k_spmv_stream<double, double, 0, 1>"
+TOP_SPMM = "k_spmm_stream<4, double, double, 0, 1>"
 
 
-def kernel_digest():
-    """Digest of the source text that defines the timed finest-operator SpMV: the stream kernel, its
-    constants and the XCD tile order.  Stored counter readings count only while it is unchanged."""
+def top_kernel(workload):
+    """The roofline kernel: the outer iteration's product with the finest operator(s)."""
+    return TOP_SPMM if workload == "batch48" else TOP_KERNEL
+
+
+def kernel_digest(workload="dg_square_512"):
+    """Digest of the source text that defines the timed roofline kernel: the stream SpMV (or, for the
+    batch, the persistent stream SpMM and its grid), its constants and the XCD tile order.  Stored
+    counter readings count only while it is unchanged."""
     import hashlib
     import re
     csr = open(os.path.join(ROOT, "paper_2408_08262_amd", "csrc", "csr.hip")).read()
     com = open(os.path.join(ROOT, "paper_2408_08262_amd", "csrc", "common.hpp")).read()
-    i = csr.index("__global__ void __launch_bounds__(kStreamRows) k_spmv_stream(")
-    parts = [csr[i:csr.index("\n}\n", i)]] + re.findall(r"constexpr int\w* kStream\w+ = [^;]+;", csr)
+    if workload == "batch48":
+        i = csr.index("__global__ void __launch_bounds__(kStreamRows) k_spmm_stream(")
+        j = csr.index("static unsigned persistent_grid(")
+        parts = [csr[i:csr.index("\n}\n", i)], csr[j:csr.index("\n}\n", j)]]
+    else:
+        i = csr.index("__global__ void __launch_bounds__(kStreamRows) k_spmv_stream(")
+        parts = [csr[i:csr.index("\n}\n", i)]]
+    parts += re.findall(r"constexpr int\w* kStream\w+ = [^;]+;", csr)
     k = com.index("constexpr int kXcds")
     parts.append(com[k:com.index("\n}\n", com.index("xcd_grid", k))])
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
@@ -79,7 +92,7 @@ def stored_traffic(workload):
         rec = json.load(open(TRAFFIC_FILE)).get(workload)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("digest") != kernel_digest():
+    if not rec or rec.get("digest") != kernel_digest(workload):
         return None
     return rec["bytes_per_launch"]
 
@@ -96,8 +109,9 @@ def record_traffic(workload, files):
             raise SystemExit("no %s dispatch in %s" % (name_part, path))
         return statistics.median(vals), len(vals)
 
-    fetch, nf = med(files[0], TOP_KERNEL)
-    write, nw = med(files[1], TOP_KERNEL)
+    kern = top_kernel(workload)
+    fetch, nf = med(files[0], kern)
+    write, nw = med(files[1], kern)
     cfetch, _ = med(files[2], "vectorized_elementwise_kernel")
     cwrite, _ = med(files[3], "vectorized_elementwise_kernel")
     copy_kib = 1024.0 * 1024.0              # the 1024 MiB calibration copy reads and writes 1 GiB
@@ -107,7 +121,7 @@ def record_traffic(workload, files):
         data = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         data = {}
-    data[workload] = {"kernel": TOP_KERNEL, "digest": kernel_digest(), "dispatches": [nf, nw],
+    data[workload] = {"kernel": kern, "digest": kernel_digest(workload), "dispatches": [nf, nw],
                       "fetch_kib_per_launch": round(fetch, 1), "write_kib_per_launch": round(write, 1),
                       "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
                       "bytes_per_launch": int(round(total))}
@@ -126,9 +140,11 @@ def roofline_from_timing(airg, workload):
     avg = tsec / launches
     bpl = tbytes / launches
     ach = bpl / avg / 1e9
+    what = (" (finest operators Y = A X on 4 rhs, the batched FGMRES Arnoldi product)" if workload == "batch48"
+            else " (finest-operator y = A x, the FGMRES Arnoldi product)")
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": stored_traffic(workload),
-            "kernel": TOP_KERNEL + " (finest-operator y = A x, the FGMRES Arnoldi product)",
+            "kernel": top_kernel(workload) + what,
             "launches": launches, "bytes_per_launch": int(bpl), "avg_launch_us": round(avg * 1e6, 2)}
 
 
@@ -299,10 +315,13 @@ def batched(a, airg, torch):
     for _ in range(a.warmup):
         step(optsb)
     torch.cuda.synchronize()
+    airg.airg_kernel_timing(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = [step(optsb) for _ in range(a.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    roof = roofline_from_timing(airg, a.workload)
     sec = (t1 - t0) / a.steps
     infob, stb = runs[-1]
     fp64 = None
@@ -331,7 +350,7 @@ def batched(a, airg, torch):
     cfg = {"workload": desc, "form": "batched FGMRES(30) FP64 per (segment, rhs) + batched FP32 V-cycle, "
                                      "one SpMM launch per stage, HIP graph, autotuned kernels",
            "rtol": a.rtol, "parallelism": "single GPU"}
-    return sec, cfg, "f64 (f32 V-cycle)", None, None, extra
+    return sec, cfg, "f64 (f32 V-cycle)", roof, None, extra
 
 
 def copy_calibration(mib, torch):

@@ -577,7 +577,7 @@ BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg,
             k_scatter_cast<<<grid_for(nk, 256), 256, 0, s>>>(B.e0.p, B.perm0.p, k, zj, n);
             AIRG_LAUNCH_CHECK();
             res.iterations++;
-            spmm(view(A), k, zj, w, nullptr, SPMV_SET, s);
+            spmm_top(view(A), k, zj, w, nullptr, SPMV_SET, s);
             // classical Gram-Schmidt twice, per pair
             dots.run(V.p, nk, j + 1, w, h1.data(), s);
             h2d(hd.p, h1.data(), (size_t)(j + 1) * np, s);
@@ -635,7 +635,7 @@ BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg,
         h2d(hd.p, tmp.data(), (size_t)j * np, s);
         k_seg_update<<<grid_for(nk, 256), 256, 0, s>>>(Zb.p, nk, j, hd.p, segrow.p, nseg, k, 1.0, x, n);
         AIRG_LAUNCH_CHECK();
-        spmm(view(A), k, x, r.p, b, SPMV_ZMINUS, s);
+        spmm_top(view(A), k, x, r.p, b, SPMV_ZMINUS, s);
         dots.run(r.p, 0, 1, r.p, beta.data(), s);
         for (auto &v : beta) {
             v = std::sqrt(v);

@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(256) k_spmm(int32_t nr, const int32_t *__restr
 // the K products of each nonzero in LDS.  Persistent: the launch walks the
 // tiles in xcd_tile order, gridDim.x (a multiple of the XCD count) apart, so
 // each workgroup stays on the tiles of its own XCD.
-template <int K, class VT, class XT, int MODE>
+template <int K, class VT, class XT, int MODE, int TAG = 0>
 __global__ void __launch_bounds__(kStreamRows) k_spmm_stream(int32_t nr, const int32_t *__restrict__ rp,
                                                             const int32_t *__restrict__ ci,
                                                             const VT *__restrict__ v, const XT *__restrict__ x,
@@ -398,18 +398,25 @@ static unsigned persistent_grid(int32_t nr) {
     return (unsigned)std::min(ids, cap);
 }
 
-template <int K, class VT, class XT>
+// TAG 1: the batched outer product with the finest operators (timed apart);
+// e0/e1 as in spmv_t.
+template <int K, class VT, class XT, int TAG = 0>
 static void spmm_k(const CsrView &A, const VT *v, const XT *x, XT *y, const XT *z, int mode, hipStream_t s,
-                   int lanes = -1) {
+                   int lanes = -1, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     if (lanes == 0 || (lanes < 0 && A.nr >= kStreamMinRows && (double)A.nnz <= 16.0 * (double)A.nr)) {
         unsigned grid = persistent_grid(A.nr);
-        if (mode == SPMV_SET) k_spmm_stream<K, VT, XT, SPMV_SET><<<grid, kStreamRows, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
-        else if (mode == SPMV_ZMINUS)
-            k_spmm_stream<K, VT, XT, SPMV_ZMINUS><<<grid, kStreamRows, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
-        else k_spmm_stream<K, VT, XT, SPMV_ADD><<<grid, kStreamRows, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+        auto launch = [&](auto kern) {
+            if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kStreamRows), 0, s, e0, e1, 0, A.nr, A.rp, A.ci, v, x,
+                                          y, z);
+            else kern<<<grid, kStreamRows, 0, s>>>(A.nr, A.rp, A.ci, v, x, y, z);
+        };
+        if (mode == SPMV_SET) launch(k_spmm_stream<K, VT, XT, SPMV_SET, TAG>);
+        else if (mode == SPMV_ZMINUS) launch(k_spmm_stream<K, VT, XT, SPMV_ZMINUS, TAG>);
+        else launch(k_spmm_stream<K, VT, XT, SPMV_ADD, TAG>);
         AIRG_LAUNCH_CHECK();
         return;
     }
+    AIRG_REQUIRE(e0 == nullptr, ST_INVALID_ARG, "timed products take the stream kernel");
     int g = lanes > 0 ? lanes : lanes_for(A.nnz, A.nr);
     dispatch_group(g, [&]<int G>() {
         unsigned grid = grid_for((int64_t)A.nr * G, 256);
@@ -441,6 +448,37 @@ void spmm(const CsrView &A, int k, const double *x, double *y, const double *z, 
 void spmm32(const CsrView &A, int k, const float *x, float *y, const float *z, int mode, hipStream_t s, int lanes) {
     AIRG_REQUIRE(A.vf != nullptr, ST_INVALID_ARG, "matrix has no single-precision copy");
     spmm_t<float, float>(A, A.vf, k, x, y, z, mode, s, lanes);
+}
+
+// The batched outer iterations' products with the finest operators: their
+// own kernel instantiation (TAG 1), timed like spmv_top while timing is on.
+void spmm_top(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s) {
+    if (A.nr == 0) return;
+    const bool stream = A.nr >= kStreamMinRows && (double)A.nnz <= 16.0 * (double)A.nr;
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_top.mu);
+        on = g_top.on;
+    }
+    on = on && mode == SPMV_SET && stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (on) {
+        AIRG_HIP(hipEventCreate(&e0));
+        AIRG_HIP(hipEventCreate(&e1));
+    }
+    switch (k) {
+    case 1: spmm_k<1, double, double, 1>(A, A.v, x, y, z, mode, s, -1, e0, e1); break;
+    case 2: spmm_k<2, double, double, 1>(A, A.v, x, y, z, mode, s, -1, e0, e1); break;
+    case 3: spmm_k<3, double, double, 1>(A, A.v, x, y, z, mode, s, -1, e0, e1); break;
+    case 4: spmm_k<4, double, double, 1>(A, A.v, x, y, z, mode, s, -1, e0, e1); break;
+    case 8: spmm_k<8, double, double, 1>(A, A.v, x, y, z, mode, s, -1, e0, e1); break;
+    default: throw Error(ST_INVALID_ARG, "number of right-hand sides must be 1, 2, 3, 4 or 8");
+    }
+    if (on) {
+        double bytes = (double)A.nnz * 12.0 + 4.0 * (A.nr + 1) + 8.0 * k * (A.nc + A.nr);
+        std::lock_guard<std::mutex> lk(g_top.mu);
+        g_top.spans.emplace_back(e0, e1, bytes);
+    }
 }
 
 // ------------------------------------------------------------- CF ranks ---

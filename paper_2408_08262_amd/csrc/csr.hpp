@@ -21,6 +21,8 @@ void spmv32(const CsrView &A, const float *x, float *y, const float *z, int mode
 // The outer iterations' products with the finest operator (a separate kernel
 // instantiation), optionally timed with events; see top_timing.
 void spmv_top(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s);
+// k right-hand sides (row-major), the batched outer product; timed like spmv_top.
+void spmm_top(const CsrView &A, int k, const double *x, double *y, const double *z, int mode, hipStream_t s);
 void top_timing(bool enable);
 void top_timing_read(int64_t *launches, double *bytes, double *seconds);
 // Same with k right-hand sides stored row-major (n x k).  lanes: -1 picks
