@@ -398,49 +398,117 @@ namespace {
 
 constexpr int kTile = 2048;
 
-// partial[(tile * nvec + i) * k + c] = sum over the tile's rows of V_i[r,c] W[r,c]
+// Block reduction of per-thread sums whose column is c = threadIdx.x % K
+// (256 % K == 0): lanes of equal column combine by shuffles, then the four
+// wavefronts through LDS; returns the total on threads 0..K-1 (their own c).
+template <int K>
+__device__ inline double col_block_sum(double x, double (*sh)[8]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int o = 32; o >= K; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane < K) sh[wid][lane] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < K) t = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+    __syncthreads();
+    return t;
+}
+
+// partial[(tile * nvec + i) * k + c] = sum over the tile's rows of V_i[r,c] W[r,c].
+// Vectors are taken kDotGroup at a time, so W is read once per group.
+constexpr int kDotGroup = 8;
 template <int K>
 __global__ void __launch_bounds__(256) k_segdot(const double *__restrict__ V, int64_t vstride, int nvec,
                                                 const double *__restrict__ W, const int64_t *__restrict__ trow,
                                                 double *__restrict__ partial) {
-    __shared__ double sh[4][K];
-    int64_t r0 = trow[blockIdx.x], r1 = trow[blockIdx.x + 1];
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = 0; i < nvec; ++i) {
-        const double *Vi = V + (int64_t)i * vstride;
-        double acc[K];
+    __shared__ double sh[4][8];
+    const int64_t e0 = trow[blockIdx.x] * K, e1 = trow[blockIdx.x + 1] * K;
+    for (int i0 = 0; i0 < nvec; i0 += kDotGroup) {
+        double acc[kDotGroup];
 #pragma unroll
-        for (int c = 0; c < K; ++c) acc[c] = 0.0;
-        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+        for (int v = 0; v < kDotGroup; ++v) acc[v] = 0.0;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+            const double w = W[e];
 #pragma unroll
-            for (int c = 0; c < K; ++c) acc[c] += Vi[r * K + c] * W[r * K + c];
+            for (int v = 0; v < kDotGroup; ++v)
+                if (i0 + v < nvec) acc[v] += V[(int64_t)(i0 + v) * vstride + e] * w;
         }
 #pragma unroll
-        for (int c = 0; c < K; ++c) {
-            double x = acc[c];
-            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-            if (lane == 0) sh[wid][c] = x;
+        for (int v = 0; v < kDotGroup; ++v) {
+            if (i0 + v < nvec) {
+                const double t = col_block_sum<K>(acc[v], sh);
+                if (threadIdx.x < K) partial[((int64_t)blockIdx.x * nvec + i0 + v) * K + threadIdx.x] = t;
+            }
         }
-        __syncthreads();
-        if (threadIdx.x < K) {
-            double x = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
-            partial[((int64_t)blockIdx.x * nvec + i) * K + threadIdx.x] = x;
-        }
-        __syncthreads();
     }
 }
 
-// out[(i * nseg + p) * k + c] = sum over segment p's tiles (in order)
-__global__ void k_segdot_finish(const double *__restrict__ partial, const int32_t *__restrict__ segtile, int nseg,
-                                int nvec, int k, double *__restrict__ out) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)nvec * nseg * k) return;
-    int c = (int)(t % k);
-    int p = (int)((t / k) % nseg);
-    int i = (int)(t / ((int64_t)k * nseg));
-    double s = 0.0;
-    for (int q = segtile[p]; q < segtile[p + 1]; ++q) s += partial[((int64_t)q * nvec + i) * k + c];
-    out[t] = s;
+// One pass of classical Gram-Schmidt fused with what follows it:
+//   W[r,c] -= sum_i V_i[r,c] H[(i * nseg + p(r)) * K + c]
+// and then, per tile, either the dots of the V_i with the new W (DOTS: the
+// second Gram-Schmidt pass's coefficients) into partial[(tile * nvec + i) *
+// K + c], or the squared norm of the new W into partial[tile * K + c].  Each
+// thread keeps the V_i of its element in registers between the update and
+// the dots, so V is read from memory once (NV >= nvec bounds the registers).
+// Tiles lie in one segment.
+constexpr int kMaxKrylov = 32;
+template <int K, bool DOTS, int NV>
+__global__ void __launch_bounds__(256) k_seg_update_fused(const double *__restrict__ V, int64_t vstride, int nvec,
+                                                          const double *__restrict__ H, int nseg,
+                                                          const int32_t *__restrict__ segrow,
+                                                          double *__restrict__ W, const int64_t *__restrict__ trow,
+                                                          double *__restrict__ partial) {
+    __shared__ double sh[4][8];
+    const int64_t r0 = trow[blockIdx.x];
+    const int64_t e0 = r0 * K, e1 = trow[blockIdx.x + 1] * K;
+    const int c = threadIdx.x % K;
+    const int p = segrow[r0];
+    double h[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) h[i] = i < nvec ? H[((int64_t)i * nseg + p) * K + c] : 0.0;
+    double acc[DOTS ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < (DOTS ? NV : 1); ++i) acc[i] = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        double vv[NV];
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            vv[i] = i < nvec ? V[(int64_t)i * vstride + e] : 0.0;
+            if (i < nvec) sum += vv[i] * h[i];
+        }
+        const double w = W[e] - sum;
+        W[e] = w;
+        if (DOTS) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i < nvec) acc[i] += vv[i] * w;
+        } else {
+            acc[0] += w * w;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < (DOTS ? NV : 1); ++i) {
+        if (i < (DOTS ? nvec : 1)) {
+            const double t = col_block_sum<K>(acc[i], sh);
+            if (threadIdx.x < K) partial[((int64_t)blockIdx.x * (DOTS ? nvec : 1) + i) * K + threadIdx.x] = t;
+        }
+    }
+}
+
+// out[(i * nseg + p) * K + c] = sum over segment p's tiles: one workgroup per
+// (i, p), its threads striding over the tiles, then a workgroup reduction.
+template <int K>
+__global__ void __launch_bounds__(256) k_segdot_finish(const double *__restrict__ partial,
+                                                       const int32_t *__restrict__ segtile, int nseg, int nvec,
+                                                       double *__restrict__ out) {
+    __shared__ double sh[4][8];
+    const int i = blockIdx.x / nseg, p = blockIdx.x % nseg;
+    const int c = threadIdx.x % K;
+    double x = 0.0;
+    for (int q = segtile[p] + threadIdx.x / K; q < segtile[p + 1]; q += 256 / K)
+        x += partial[((int64_t)q * nvec + i) * K + c];
+    const double t = col_block_sum<K>(x, sh);
+    if (threadIdx.x < K) out[((int64_t)i * nseg + p) * K + threadIdx.x] = t;
 }
 
 // W[r,c] += sign * sum_i V_i[r,c] H[(i * nseg + p(r)) * k + c]
@@ -521,10 +589,39 @@ struct SegDots {
         default: throw Error(ST_INVALID_ARG, "batched solve supports 1, 2, 4 or 8 right-hand sides");
         }
         AIRG_LAUNCH_CHECK();
-        int64_t tot = (int64_t)nvec * nseg * k;
-        k_segdot_finish<<<grid_for(tot, 256), 256, 0, s>>>(partial.p, segtile.p, nseg, nvec, k, out.p);
+        finish(nvec, h, s);
+    }
+    // W -= sum_i V_i H_i per pair, then (DOTS) the dots of V_0..V_{nvec-1}
+    // with the new W, or its squared norm, per (segment, column) into host h
+    template <bool DOTS>
+    void update(const double *V, int64_t vstride, int nvec, const double *Hd, const int32_t *segrow, double *W,
+                double *h, hipStream_t s) {
+        AIRG_REQUIRE(nvec <= kMaxKrylov, ST_INVALID_ARG, "Krylov basis too long for the fused update");
+        auto launch = [&]<int K>() {
+            if (nvec <= 8) k_seg_update_fused<K, DOTS, 8><<<ntile, 256, 0, s>>>(V, vstride, nvec, Hd, nseg, segrow, W, trow.p, partial.p);
+            else if (nvec <= 16) k_seg_update_fused<K, DOTS, 16><<<ntile, 256, 0, s>>>(V, vstride, nvec, Hd, nseg, segrow, W, trow.p, partial.p);
+            else k_seg_update_fused<K, DOTS, kMaxKrylov><<<ntile, 256, 0, s>>>(V, vstride, nvec, Hd, nseg, segrow, W, trow.p, partial.p);
+        };
+        switch (k) {
+        case 1: launch.template operator()<1>(); break;
+        case 2: launch.template operator()<2>(); break;
+        case 4: launch.template operator()<4>(); break;
+        case 8: launch.template operator()<8>(); break;
+        default: throw Error(ST_INVALID_ARG, "batched solve supports 1, 2, 4 or 8 right-hand sides");
+        }
         AIRG_LAUNCH_CHECK();
-        d2h(h, out.p, (size_t)tot, s);
+        finish(DOTS ? nvec : 1, h, s);
+    }
+    void finish(int nvec, double *h, hipStream_t s) {
+        const unsigned blocks = (unsigned)(nvec * nseg);
+        switch (k) {
+        case 1: k_segdot_finish<1><<<blocks, 256, 0, s>>>(partial.p, segtile.p, nseg, nvec, out.p); break;
+        case 2: k_segdot_finish<2><<<blocks, 256, 0, s>>>(partial.p, segtile.p, nseg, nvec, out.p); break;
+        case 4: k_segdot_finish<4><<<blocks, 256, 0, s>>>(partial.p, segtile.p, nseg, nvec, out.p); break;
+        default: k_segdot_finish<8><<<blocks, 256, 0, s>>>(partial.p, segtile.p, nseg, nvec, out.p); break;
+        }
+        AIRG_LAUNCH_CHECK();
+        d2h(h, out.p, (size_t)nvec * nseg * k, s);
     }
 };
 
@@ -536,6 +633,7 @@ BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg,
     const int64_t n = B.n;
     const int np = nseg * k;   // (segment, rhs) pairs
     int m = std::max(1, std::min(restart > 0 ? restart : 30, std::max(maxit, 1)));
+    m = std::min(m, kMaxKrylov - 1);   // the fused Gram-Schmidt passes keep the basis in registers
     BatchResult res;
     DBuf<int32_t> segrow((size_t)n, s);
     for (int p = 0; p < nseg; ++p) {
@@ -578,17 +676,15 @@ BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg,
             AIRG_LAUNCH_CHECK();
             res.iterations++;
             spmm_top(view(A), k, zj, w, nullptr, SPMV_SET, s);
-            // classical Gram-Schmidt twice, per pair
+            // classical Gram-Schmidt twice, per pair: the first pass's dots; the
+            // first update fused with the second pass's dots; the second update
+            // fused with the new vector's squared norm (three passes over V)
             dots.run(V.p, nk, j + 1, w, h1.data(), s);
             h2d(hd.p, h1.data(), (size_t)(j + 1) * np, s);
-            k_seg_update<<<grid_for(nk, 256), 256, 0, s>>>(V.p, nk, j + 1, hd.p, segrow.p, nseg, k, -1.0, w, n);
-            AIRG_LAUNCH_CHECK();
-            dots.run(V.p, nk, j + 1, w, h2.data(), s);
+            dots.update<true>(V.p, nk, j + 1, hd.p, segrow.p, w, h2.data(), s);
             h2d(hd.p, h2.data(), (size_t)(j + 1) * np, s);
-            k_seg_update<<<grid_for(nk, 256), 256, 0, s>>>(V.p, nk, j + 1, hd.p, segrow.p, nseg, k, -1.0, w, n);
-            AIRG_LAUNCH_CHECK();
             std::vector<double> hn(np);
-            dots.run(w, 0, 1, w, hn.data(), s);
+            dots.update<false>(V.p, nk, j + 1, hd.p, segrow.p, w, hn.data(), s);
             for (int q = 0; q < np; ++q) {
                 hn[q] = std::sqrt(hn[q]);
                 AIRG_REQUIRE(std::isfinite(hn[q]), ST_STALL, "batched Arnoldi vector became non-finite");
