@@ -227,7 +227,13 @@ __global__ void k_colsq_seg_finish(const double *__restrict__ partial, const int
 // stable, so R(K D) = R(K) D up to rounding, and the column norms of K are
 // those of R(K).  The scaling is therefore applied to the final R on the host
 // and the norms need no pass over K.
+static void tsqr_r_x(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s,
+                     const ExtraReads *extra);
 void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s) {
+    tsqr_r_x(K, n, cols, h_R, h_colnorm, s, nullptr);
+}
+static void tsqr_r_x(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s,
+                     const ExtraReads *extra) {
     AIRG_REQUIRE(cols >= 1 && cols <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order too large");
     const double *src = K;
     int64_t rows = n, ld = n;
@@ -247,7 +253,21 @@ void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm
         if (nb == 1) break;
     }
     std::vector<double> R((size_t)cols * cols);   // column-major
-    d2h(R.data(), src, R.size(), s);
+    if (!extra) {
+        d2h(R.data(), src, R.size(), s);
+    } else {
+        // R and the caller's ranges in one readback
+        std::vector<const int32_t *> srcs{reinterpret_cast<const int32_t *>(src)};
+        std::vector<int32_t> cnts{2 * cols * cols};
+        srcs.insert(srcs.end(), extra->src.begin(), extra->src.end());
+        cnts.insert(cnts.end(), extra->cnt.begin(), extra->cnt.end());
+        int64_t words = 0;
+        for (int32_t c : cnts) words += c;
+        std::vector<int32_t> h((size_t)words);
+        read_ints(srcs, cnts, h.data(), s);
+        std::memcpy(R.data(), h.data(), R.size() * sizeof(double));
+        std::copy(h.begin() + 2 * cols * cols, h.end(), extra->h);
+    }
     for (int c = 0; c < cols; ++c) {
         double ss = 0.0;
         for (int r = 0; r <= c; ++r) ss += R[(size_t)c * cols + r] * R[(size_t)c * cols + r];
@@ -307,16 +327,19 @@ int poly_coeffs_from_r(const double *R, const double *colnorm, int m, double *al
     return keep;
 }
 
-PolyInfo gmres_poly(const CsrView &A, uint64_t seed, int32_t level, int m, hipStream_t s) {
+PolyInfo gmres_poly(const CsrView &A, uint64_t seed, int32_t level, int m, hipStream_t s, const ExtraReads *extra) {
     AIRG_REQUIRE(m >= 1 && m + 1 <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order out of range");
     PolyInfo P;
     P.m = m;
     int64_t n = A.nr;
-    if (n == 0) return P;
+    if (n == 0) {
+        if (extra && !extra->src.empty()) read_ints(extra->src, extra->cnt, extra->h, s);
+        return P;
+    }
     DBuf<double> K((size_t)n * (m + 1), s);
     gauss_rhs(n, seed, level, K.p, s);
     for (int k = 1; k <= m; ++k) spmv(A, K.p + (int64_t)(k - 1) * n, K.p + (int64_t)k * n, nullptr, SPMV_SET, s);
-    tsqr_r(K.p, n, m + 1, P.R, P.colnorm, s);
+    tsqr_r_x(K.p, n, m + 1, P.R, P.colnorm, s, extra && !extra->src.empty() ? extra : nullptr);
     P.used = poly_coeffs_from_r(P.R, P.colnorm, m, P.alpha);
     return P;
 }
@@ -539,15 +562,24 @@ __global__ void __launch_bounds__(256) k_poly_long(const int32_t *__restrict__ l
     for (int a = threadIdx.x; a < L; a += blockDim.x) out[b + a] = acc[a];
 }
 
+FixedPlan fixed_sparsity_begin(const CsrView &Pt, hipStream_t s) {
+    FixedPlan F;
+    const int32_t n = Pt.nr;
+    F.bin.alloc((size_t)n + 1, s);
+    if (n > 0) {
+        k_rowlen_bin<<<grid_for(n, 256), 256, 0, s>>>(n, Pt.rp, F.bin.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    F.bins = bin_rows_begin(F.bin.p, n, kFixedBins, s);
+    return F;
+}
+
 // Coefficient table (kMaxPolyCols per segment) and segment offsets on the
-// device; nseg = 1 needs no offsets.
-static void fixed_sparsity_tab(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff,
-                               int nseg, int nalpha, double *out_v, hipStream_t s) {
+// device; nseg = 1 needs no offsets.  h_tot: the plan's bin totals.
+static void fixed_sparsity_run(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff, int nseg,
+                               int nalpha, double *out_v, FixedPlan &F, const int32_t *h_tot, hipStream_t s) {
     int32_t n = A.nr;
-    DBuf<int8_t> bin((size_t)n, s);
-    k_rowlen_bin<<<grid_for(n, 256), 256, 0, s>>>(n, Pt.rp, bin.p);
-    AIRG_LAUNCH_CHECK();
-    Bins B = bin_rows(bin.p, n, 6, s);
+    Bins B = bin_rows_end(F.bins, h_tot, s);
     auto rows = [&](auto kern, int b, int per_block, unsigned tpb) {
         if (B.count(b))
             kern<<<grid_for(B.count(b), per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Pt.rp,
@@ -574,6 +606,40 @@ static void fixed_sparsity_tab(const CsrView &A, const CsrView &Pt, const double
                                                          soff, nseg, nalpha, out_v);
         AIRG_LAUNCH_CHECK();
     }
+}
+
+
+static void fixed_sparsity_tab(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff,
+                               int nseg, int nalpha, double *out_v, hipStream_t s) {
+    FixedPlan F = fixed_sparsity_begin(Pt, s);
+    int32_t h[kFixedBins + 1];
+    d2h(h, F.bins.tot.p, (size_t)kFixedBins + 1, s);
+    fixed_sparsity_run(A, Pt, alt, soff, nseg, nalpha, out_v, F, h, s);
+}
+
+// The single form's coefficients, written to the device by a kernel that
+// takes them as arguments (no host staging to outlive).
+struct CoefArgs {
+    double a[kMaxPolyCols];
+};
+__global__ void k_set_coefs(CoefArgs c, double *__restrict__ out) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kMaxPolyCols; ++k) out[k] = c.a[k];
+    }
+}
+
+void poly_fixed_sparsity_planned(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha,
+                                 double *out_v, FixedPlan &plan, const int32_t *h_tot, hipStream_t s) {
+    AIRG_REQUIRE(nalpha >= 1 && nalpha <= kMaxPolyCols, ST_INVALID_ARG, "bad number of coefficients");
+    AIRG_REQUIRE(Pt.nr == A.nr, ST_INVALID_ARG, "pattern and matrix differ in rows");
+    if (A.nr == 0) return;
+    CoefArgs c{};
+    for (int k = 0; k < nalpha; ++k) c.a[k] = alpha[k];
+    DBuf<double> alt(kMaxPolyCols, s);
+    k_set_coefs<<<1, 64, 0, s>>>(c, alt.p);
+    AIRG_LAUNCH_CHECK();
+    fixed_sparsity_run(A, Pt, alt.p, nullptr, 1, nalpha, out_v, plan, h_tot, s);
 }
 
 void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, double *out_v, hipStream_t s) {

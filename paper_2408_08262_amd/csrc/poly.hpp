@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "csr.hpp"
 
 namespace airg {
 
@@ -26,12 +27,22 @@ void gauss_rhs(int64_t n, uint64_t seed, int32_t level, double *b, hipStream_t s
 // column-major) by a tall-skinny Householder QR tree, and the column norms.
 void tsqr_r(const double *K, int64_t n, int cols, double *h_R, double *h_colnorm, hipStream_t s);
 
+// Device int32 ranges a caller wants read back with the next host
+// synchronisation of a routine (to h, back to back).
+struct ExtraReads {
+    std::vector<const int32_t *> src;
+    std::vector<int32_t> cnt;
+    int32_t *h = nullptr;
+};
+
 // alpha = argmin || beta e1 - R~ y || from the scaled R and the column norms,
 // with the Krylov breakdown rule; returns the number of coefficients kept.
 int poly_coeffs_from_r(const double *R, const double *colnorm, int m, double *alpha);
 
-// Steps 3-6 of the setup on a square A (alpha has m entries).
-PolyInfo gmres_poly(const CsrView &A, uint64_t seed, int32_t level, int m, hipStream_t s);
+// Steps 3-6 of the setup on a square A (alpha has m entries).  The extra
+// ranges come back in the same readback as the R factor.
+PolyInfo gmres_poly(const CsrView &A, uint64_t seed, int32_t level, int m, hipStream_t s,
+                    const ExtraReads *extra = nullptr);
 
 // The same for a block-diagonal batch: segment p holds rows off[p] ..
 // off[p+1]-1 (host offsets; d_off the same on the device) and draws its
@@ -50,6 +61,17 @@ void poly_fixed_sparsity(const CsrView &A, const double *alpha, int nalpha, doub
 // diagonal; out_v has Pt.nnz entries); M_i = A(J_i, J_i).
 void poly_fixed_sparsity_pattern(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha,
                                  double *out_v, hipStream_t s);
+// The same in two halves: the rows of Pt binned by length (no
+// synchronisation; kFixedBins + 1 totals at plan.bins.tot), then, with those
+// totals on the host, the assembly.
+constexpr int kFixedBins = 6;
+struct FixedPlan {
+    DBuf<int8_t> bin;
+    BinPlan bins;
+};
+FixedPlan fixed_sparsity_begin(const CsrView &Pt, hipStream_t s);
+void poly_fixed_sparsity_planned(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha,
+                                 double *out_v, FixedPlan &plan, const int32_t *h_tot, hipStream_t s);
 // Batch form: the rows of segment p (host offsets off) use P[p]'s
 // coefficients; patterns from Pt.
 void poly_fixed_sparsity_seg(const CsrView &A, const CsrView &Pt, const std::vector<int32_t> &off,

@@ -7,6 +7,7 @@
 #include "csr.hpp"
 #include "group.hpp"
 #include "hierarchy.hpp"
+#include "poly.hpp"
 #include "spgemm.hpp"
 #include "transfer.hpp"
 
@@ -191,18 +192,47 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     extract_fc_blocks(A, cf, rank, nF, nC, Aff, fc, Acf, s);
     if (Afc) *Afc = std::move(fc);
     tm.begin(AIRG_PHASE_POLY);
+    // With the first-order pattern, the row bins of the fixed-sparsity
+    // assembly and of Z's product depend only on A_ff's and A_cf's patterns:
+    // they are started first and their totals come back with the R factor.
+    const bool planned = !alpha_in && o.poly_sparsity_order <= 1;
+    FixedPlan fplan;
+    SpgemmPlan zplan;
+    std::vector<int32_t> htot;
+    int32_t zoff = 0;
     if (alpha_in) {
         poly = PolyInfo{};
         poly.m = m;
         poly.used = m;
         for (int k = 0; k < m; ++k) poly.alpha[k] = alpha_in[k];
+    } else if (planned) {
+        fplan = fixed_sparsity_begin(view(Aff), s);
+        zplan = spgemm_begin(view(Acf), Aff.rp.p, Aff.nc, s);   // Ainv has A_ff's pattern
+        ExtraReads ex;
+        ex.src = {fplan.bins.tot.p};
+        ex.cnt = {kFixedBins + 1};
+        zoff = kFixedBins + 1;
+        auto zt = zplan.totals();
+        if (zt.second > 0) {
+            ex.src.push_back(zt.first);
+            ex.cnt.push_back(zt.second);
+        }
+        htot.resize((size_t)zoff + std::max(zt.second, 1));
+        ex.h = htot.data();
+        poly = gmres_poly(view(Aff), seed, lvl, m, s, &ex);
     } else {
         poly = gmres_poly(view(Aff), seed, lvl, m, s);
     }
-    Ainv = assemble_inverse(view(Aff), poly, m, o.poly_sparsity_order, s);
+    if (planned) {
+        Ainv = pattern_copy(view(Aff), s);
+        poly_fixed_sparsity_planned(view(Aff), view(Ainv), poly.alpha, m, Ainv.v.p, fplan, htot.data(), s);
+    } else {
+        Ainv = assemble_inverse(view(Aff), poly, m, o.poly_sparsity_order, s);
+    }
     tm.begin(AIRG_PHASE_RESTRICTOR);
     {
-        Csr prod = spgemm(view(Acf), view(Ainv), s);
+        Csr prod = planned ? spgemm_finish(view(Acf), view(Ainv), zplan, htot.data() + zoff, s)
+                           : spgemm(view(Acf), view(Ainv), s);
         Z = drop_rows(view(prod), o.drop_R, false, true, s);   // Z = -A_cf Ainv, dropped
     }
     if (br) {

@@ -839,30 +839,54 @@ static void run_numeric(const Bins &B, const CsrView &A, const CsrView &Bm, int3
         run_global(true, B, NB_GLOBAL, gather_bin(B, NB_GLOBAL, cnt, m, s), A, Bm, cnt, crp, cci, cv, s);
 }
 
-Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
-    AIRG_REQUIRE(A.nc == Bm.nr, ST_INVALID_ARG, "inner dimensions differ");
-    if (Bm.nc <= kNarrowMaxCols) {
-        const int nc = Bm.nc <= 1024 ? 1024 : Bm.nc <= 2048 ? 2048 : 4096;
-        if ((int64_t)A.nr * nc <= kNarrowMaxWork) {
-            if (nc == 1024) return spgemm_narrow<1024>(A, Bm, s);
-            if (nc == 2048) return spgemm_narrow<2048>(A, Bm, s);
-            return spgemm_narrow<4096>(A, Bm, s);
-        }
+static bool narrow_shape(int32_t m, int32_t bnc, int *nc) {
+    if (bnc > kNarrowMaxCols) return false;
+    *nc = bnc <= 1024 ? 1024 : bnc <= 2048 ? 2048 : 4096;
+    return (int64_t)m * *nc <= kNarrowMaxWork;
+}
+
+std::pair<const int32_t *, int32_t> SpgemmPlan::totals() const {
+    if (narrow) return {nullptr, 0};
+    return {bins.tot.p, SB_N + 1};
+}
+
+SpgemmPlan spgemm_begin(const CsrView &A, const int32_t *b_rp, int32_t b_nc, hipStream_t s) {
+    SpgemmPlan P;
+    P.m = A.nr;
+    P.bnc = b_nc;
+    int nc;
+    P.narrow = narrow_shape(A.nr, b_nc, &nc);
+    if (P.narrow) return P;
+    const int32_t m = A.nr;
+    P.ub.alloc((size_t)m + 1, s);
+    P.sbin.alloc((size_t)m + 1, s);
+    if (m > 0) {
+        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, A.rp, A.ci, b_rp, P.ub.p, P.sbin.p);
+        AIRG_LAUNCH_CHECK();
+    }
+    P.bins = bin_rows_begin(P.sbin.p, m, SB_N, s);
+    return P;
+}
+
+Csr spgemm_finish(const CsrView &A, const CsrView &Bm, SpgemmPlan &P, const int32_t *h_tot, hipStream_t s) {
+    AIRG_REQUIRE(A.nc == Bm.nr && P.m == A.nr && P.bnc == Bm.nc, ST_INVALID_ARG, "product plan does not match");
+    if (P.narrow) {
+        int nc;
+        narrow_shape(A.nr, Bm.nc, &nc);
+        if (nc == 1024) return spgemm_narrow<1024>(A, Bm, s);
+        if (nc == 2048) return spgemm_narrow<2048>(A, Bm, s);
+        return spgemm_narrow<4096>(A, Bm, s);
     }
     Csr C;
     C.nr = A.nr;
     C.nc = Bm.nc;
     C.rp.alloc((size_t)A.nr + 1, s);
     int32_t m = A.nr;
-    DBuf<int32_t> ub((size_t)m + 1, s), cnt((size_t)m + 1, s);
-    DBuf<int8_t> sbin((size_t)m + 1, s), nbin((size_t)m + 1, s);
+    DBuf<int32_t> cnt((size_t)m + 1, s);
+    DBuf<int8_t> nbin((size_t)m + 1, s);
     fill_zero(cnt.p, ((size_t)m + 1) * 4, s);
-    if (m > 0) {
-        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, A.rp, A.ci, Bm.rp, ub.p, sbin.p);
-        AIRG_LAUNCH_CHECK();
-    }
-    Bins SB = bin_rows(sbin.p, m, SB_N, s);
-    run_symbolic(SB, A, Bm, cnt.p, ub.p, m, s);
+    Bins SB = bin_rows_end(P.bins, h_tot, s);
+    run_symbolic(SB, A, Bm, cnt.p, P.ub.p, m, s);
     exclusive_scan(cnt.p, C.rp.p, m, s, false);
     if (m > 0) {
         k_spgemm_nbin<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.p, nbin.p);
@@ -880,6 +904,15 @@ Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
     Bins NB = bin_rows_end(NP, h.data() + 1, s);
     run_numeric(NB, A, Bm, cnt.p, C.rp.p, C.ci.p, C.v.p, m, s);
     return C;
+}
+
+Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
+    AIRG_REQUIRE(A.nc == Bm.nr, ST_INVALID_ARG, "inner dimensions differ");
+    SpgemmPlan P = spgemm_begin(A, Bm.rp, Bm.nc, s);
+    auto [src, cnt] = P.totals();
+    std::vector<int32_t> h((size_t)std::max(cnt, 1));
+    if (cnt > 0) d2h(h.data(), src, (size_t)cnt, s);
+    return spgemm_finish(A, Bm, P, h.data(), s);
 }
 
 }  // namespace airg
