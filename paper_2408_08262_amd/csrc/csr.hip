@@ -185,6 +185,11 @@ __global__ void __launch_bounds__(kStreamRows) k_spmv_stream(int32_t nr, const i
     }
 }
 
+// Whether spmv_t takes the CSR-stream kernel for this shape.
+bool spmv_streams(int32_t nr, int64_t nnz) {
+    return nr >= kStreamMinRows && (double)nnz <= 16.0 * (double)nr;
+}
+
 // e0/e1 (timed launches): events stamped by the kernel dispatch itself at
 // the kernel's start and end, so their interval is the kernel's own duration.
 template <int TAG, class VT, class XT>
@@ -196,7 +201,7 @@ static void spmv_t(int32_t nr, int64_t nnz, const int32_t *rp, const int32_t *ci
         if (e0) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, e0, e1, 0, nr, rp, ci, v, x, y, z);
         else kern<<<grid, 256, 0, s>>>(nr, rp, ci, v, x, y, z);
     };
-    if (lanes == 0 && nr >= kStreamMinRows && (double)nnz <= 16.0 * (double)nr) {
+    if (lanes == 0 && spmv_streams(nr, nnz)) {
         static_assert(kStreamRows == 256, "stream SpMV launches 256-thread workgroups");
         unsigned grid = grid_for(xcd_grid((nr + kStreamRows - 1) / kStreamRows), 1);
         if (mode == SPMV_SET) launch(k_spmv_stream<VT, XT, SPMV_SET, TAG>, grid);

@@ -18,6 +18,9 @@ Csr copy_csr(const CsrView &A, hipStream_t s);
 enum SpmvMode { SPMV_SET = 0, SPMV_ZMINUS = 1, SPMV_ADD = 2 };
 void spmv(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s, int lanes = 0);
 void spmv32(const CsrView &A, const float *x, float *y, const float *z, int mode, hipStream_t s, int lanes = 0);
+// Whether spmv/spmv32 take the CSR-stream kernel for a matrix of this shape
+// (otherwise one lanes_for(nnz, nr)-lane group per row).
+bool spmv_streams(int32_t nr, int64_t nnz);
 // The outer iterations' products with the finest operator (a separate kernel
 // instantiation), optionally timed with events; see top_timing.
 void spmv_top(const CsrView &A, const double *x, double *y, const double *z, int mode, hipStream_t s);

@@ -36,6 +36,12 @@ struct Level {
     DBuf<float> g32, e32, t32;
     DBuf<double> p64, q64, u64;   // coarsest level, matrix-free polynomial
     DBuf<float> p32, q32, u32;
+    // [W; I] as one (column, value) per row (pcol < 0: empty row), kept on
+    // the small levels, where the prolongation is fused with the first
+    // smoothing residual
+    DBuf<int32_t> pcol;
+    DBuf<double> pval64;
+    DBuf<float> pval32;
 };
 
 struct Hier {

@@ -465,6 +465,18 @@ void solve_ops_begin(Hier &H, int l, std::vector<Csr *> &pending, hipStream_t s)
     L.Pp = build_pp_begin(L.W, L.nF, L.nC, L.nC, s);
     pending.insert(pending.end(), {&L.AF, &L.Rp, &L.Pp});
 }
+// One (column, value) per row of [W; I] (at most one entry per row).
+__global__ void k_pp_dense(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ v, const float *__restrict__ vf, int32_t *__restrict__ pcol,
+                           double *__restrict__ pval, float *__restrict__ pvalf) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const bool has = rp[r + 1] > rp[r];
+    pcol[r] = has ? ci[rp[r]] : -1;
+    pval[r] = has ? v[rp[r]] : 0.0;
+    pvalf[r] = has ? vf[rp[r]] : 0.0f;
+}
+
 void solve_ops_fill(Hier &H, int l, hipStream_t s) {
     Level &L = H.L(l), &N = H.L(l + 1);
     permute_fc_fill(L.AF, view(L.A), L.fidx.p, L.cf.p, L.rank.p, L.nF, s);
@@ -474,6 +486,19 @@ void solve_ops_fill(Hier &H, int l, hipStream_t s) {
     make_f32(L.Rp, s);
     make_f32(L.Pp, s);
     make_f32(L.Ainv, s);
+    // small levels (lane-group SpMVs throughout): prolongation rows for the
+    // fused prolongation + residual kernel
+    L.pcol.reset();
+    L.pval64.reset();
+    L.pval32.reset();
+    if (!spmv_streams(L.Pp.nr, L.Pp.nnz) && !spmv_streams(L.AF.nr, L.AF.nnz) && L.n > 0) {
+        L.pcol.alloc((size_t)L.n, s);
+        L.pval64.alloc((size_t)L.n, s);
+        L.pval32.alloc((size_t)L.n, s);
+        k_pp_dense<<<grid_for(L.n, 256), 256, 0, s>>>(L.n, L.Pp.rp.p, L.Pp.ci.p, L.Pp.v.p, L.Pp.vf.p, L.pcol.p,
+                                                      L.pval64.p, L.pval32.p);
+        AIRG_LAUNCH_CHECK();
+    }
 }
 void solve_ops(Hier &H, int l, hipStream_t s) {
     std::vector<Csr *> pending;

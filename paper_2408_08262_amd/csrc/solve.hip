@@ -3,10 +3,12 @@
 // FP32 or FP64 V-cycle.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
 #include "csr.hpp"
+#include "group.hpp"
 #include "hierarchy.hpp"
 
 namespace airg {
@@ -19,6 +21,56 @@ inline void spmvT(const Csr &A, const float *x, float *y, const float *z, int mo
     spmv32(view(A), x, y, z, mode, s);
 }
 template <class T> struct Bufs;
+template <class T> struct PVal;
+template <> struct PVal<double> {
+    static const double *get(const Level &L) { return L.pval64.p; }
+};
+template <> struct PVal<float> {
+    static const float *get(const Level &L) { return L.pval32.p; }
+};
+
+// The prolongation e = [W; I] e_c (one entry or none per row) fused with the
+// first smoothing residual t_F = g_F - [A_ff A_fc] e: each product forms the
+// e entry it needs from e_c as the prolongation would store it, so the
+// result equals the two separate lane-group products.
+template <int G, class T>
+__global__ void __launch_bounds__(256) k_prolong_resid(int32_t n, int32_t nF, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                                       const int32_t *__restrict__ pcol, const T *__restrict__ pval,
+                                                       const T *__restrict__ ec, const T *__restrict__ g,
+                                                       T *__restrict__ e, T *__restrict__ t) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t row = (int32_t)(tid / G);
+    const int lane = group_lane<G>();
+    if (row >= n) return;
+    if (lane == 0) {
+        const int32_t pc = pcol[row];
+        e[row] = pc >= 0 ? pval[row] * ec[pc] : (T)0;
+    }
+    if (row >= nF) return;
+    T acc = 0;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
+        const int32_t j = ci[k];
+        const int32_t pc = pcol[j];
+        const T ej = pc >= 0 ? pval[j] * ec[pc] : (T)0;
+        acc += v[k] * ej;
+    }
+    acc = group_sum<G>(acc);
+    if (lane == 0) t[row] = g[row] - acc;
+}
+
+template <class T>
+void prolong_resid(Level &Lv, const T *ec, const T *g, T *e, T *t, hipStream_t s) {
+    const T *v;
+    if constexpr (std::is_same_v<T, float>) v = Lv.AF.vf.p;
+    else v = Lv.AF.v.p;
+    dispatch_group(lanes_for(Lv.AF.nnz, Lv.AF.nr), [&]<int G>() {
+        k_prolong_resid<G, T><<<grid_for((int64_t)Lv.n * G, 256), 256, 0, s>>>(
+            Lv.n, Lv.nF, Lv.AF.rp.p, Lv.AF.ci.p, v, Lv.pcol.p, PVal<T>::get(Lv), ec, g, e, t);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
 template <> struct Bufs<double> {
     static double *g(Level &L) { return L.g64.p; }
     static double *e(Level &L) { return L.e64.p; }
@@ -94,8 +146,15 @@ void Hier::vcycle(int l, const T *g, T *e) {
     T *ec = Bufs<T>::e(N);
     spmvT(Lv.Rp, g, gc, (const T *)nullptr, SPMV_SET, s);
     vcycle<T>(l + 1, gc, ec);
-    spmvT(Lv.Pp, ec, e, (const T *)nullptr, SPMV_SET, s);
-    for (int k = 0; k < opt.up_smooths; ++k) {
+    int k0 = 0;
+    if (Lv.pcol.p && opt.up_smooths > 0) {
+        prolong_resid<T>(Lv, ec, g, e, t, s);
+        spmvT(Lv.Ainv, t, e, (const T *)nullptr, SPMV_ADD, s);
+        k0 = 1;
+    } else {
+        spmvT(Lv.Pp, ec, e, (const T *)nullptr, SPMV_SET, s);
+    }
+    for (int k = k0; k < opt.up_smooths; ++k) {
         spmvT(Lv.AF, e, t, g, SPMV_ZMINUS, s);
         spmvT(Lv.Ainv, t, e, (const T *)nullptr, SPMV_ADD, s);
     }
