@@ -162,8 +162,8 @@ __global__ void __launch_bounds__(kStreamRows) k_spmv_stream(int32_t nr, const i
             cc[u] = 0;
             vv[u] = 0;
             if (k < c1) {
-                cc[u] = ci[k];
-                vv[u] = (XT)v[k];
+                cc[u] = __builtin_nontemporal_load(ci + k);   // streamed once: keep L2 for the x gathers
+                vv[u] = (XT)__builtin_nontemporal_load(v + k);
             }
         }
 #pragma unroll
