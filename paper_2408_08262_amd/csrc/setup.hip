@@ -29,6 +29,9 @@ static hipStream_t branch_stream(int dev) {
 
 Branch::Branch(hipStream_t main) : main_(main) {
     AIRG_HIP(hipGetDevice(&dev_));
+    hipDevice_t sdev = 0;
+    AIRG_HIP(hipStreamGetDevice(main, &sdev));
+    AIRG_REQUIRE((int)sdev == dev_, ST_INVALID_ARG, "the stream belongs to another device than the current one");
     s_ = branch_stream(dev_);
     AIRG_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
     AIRG_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));

@@ -179,3 +179,28 @@ def test_captured_vcycle_graph_replays_the_eager_cycle(outer, prec):
     x0, i0 = airg.airg_solve(h0, b, rtol=1e-10, max_it=200, allow_not_converged=True)
     x1, i1 = airg.airg_solve(h1, b, rtol=1e-10, max_it=200, allow_not_converged=True)
     assert i1["iterations"] == i0["iterations"] and torch.equal(x0, x1)
+
+
+def test_setup_under_memory_caps_fails_cleanly():
+    """Device byte caps that run out at different points of the level loop
+    (on the main thread or on the prolongator branch thread) make the setup
+    return AIRG_ERR_OOM and leave the library usable."""
+    P = dg_square(48)
+    b = torch.as_tensor(P.b, device="cuda")
+    outcomes = []
+    for cap in np.geomspace(2 ** 16, 2 ** 28, 9).astype(np.int64):
+        try:
+            h = airg.airg_setup(*airg.to_device(P.rowptr, P.col, P.val),
+                                airg.default_opts(seed=P.seed, device_bytes_cap=int(cap)))
+        except airg.AirgError as e:
+            assert e.status == -5
+            outcomes.append("oom")
+            continue
+        x, info = airg.airg_solve(h, b, rtol=1e-10, max_it=100)
+        assert info["converged"]
+        outcomes.append("ok")
+        del h
+    assert "oom" in outcomes and outcomes[-1] == "ok"
+    h, _ = setup(P)
+    x, info = airg.airg_solve(h, b, rtol=1e-10, max_it=100)
+    assert info["converged"]
