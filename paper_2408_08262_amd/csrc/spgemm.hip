@@ -24,16 +24,15 @@ constexpr int32_t kEmpty = -1;
 __device__ inline uint32_t hash_slot(int32_t c, uint32_t mask) { return ((uint32_t)c * 2654435761u) & mask; }
 
 // Returns the slot holding key c, inserting it if absent; *fresh tells
-// whether this call inserted it.
+// whether this call inserted it.  Each probe is one compare-and-swap, which
+// returns the slot's key: empty (now c, inserted), c (present) or another.
 __device__ inline uint32_t hash_insert(int32_t *keys, uint32_t mask, int32_t c, bool *fresh) {
     uint32_t s = hash_slot(c, mask);
     for (;;) {
-        int32_t k = keys[s];
-        if (k == c) { *fresh = false; return s; }
-        if (k == kEmpty) {
-            int32_t old = atomicCAS(&keys[s], kEmpty, c);
-            if (old == kEmpty) { *fresh = true; return s; }
-            if (old == c) { *fresh = false; return s; }
+        const int32_t old = atomicCAS(&keys[s], kEmpty, c);
+        if (old == kEmpty || old == c) {
+            *fresh = old == kEmpty;
+            return s;
         }
         s = (s + 1) & mask;
     }
@@ -42,19 +41,24 @@ __device__ inline uint32_t hash_insert(int32_t *keys, uint32_t mask, int32_t c, 
 // Symbolic bins by ub.
 enum : int8_t { SB_EMPTY = 0, SB_G4, SB_G8, SB_G16, SB_G32, SB_G64, SB_BLOCK, SB_GLOBAL, SB_N };
 // Numeric bins by the exact row length.
-enum : int8_t { NB_EMPTY = 0, NB_G4, NB_G8, NB_G16, NB_G64, NB_BLOCK4K, NB_BLOCK8K, NB_GLOBAL, NB_N };
+enum : int8_t { NB_EMPTY = 0, NB_G4, NB_G8, NB_G16S, NB_G16, NB_G64, NB_BLOCK4K, NB_BLOCK8K, NB_GLOBAL, NB_N };
 
 // Visits the products of row `row` of A with B: for each A entry in
 // ascending order, f(column, a_ik * b_kj) on the lanes holding the entries of
-// B row k.  The A entries are loaded G at a time and broadcast by shuffles,
-// and the first B entries of the next A entry are fetched while the current
-// one is handled.  ORDERED puts a wave-scope barrier between A entries, so
-// that the updates of one table slot happen in ascending k order.
+// B row k.  The A entries are loaded G at a time and broadcast by shuffles.
+// The first lane-stride of the B rows of QB consecutive A entries is loaded
+// in one batch, all loads in flight together, before any of them is visited,
+// and the rest of a B row kChunks lane-strides at a time, so that a row costs
+// a few memory latencies rather than one per A entry.  ORDERED puts a
+// wave-scope barrier between A entries, so that the updates of one table slot
+// happen in ascending k order.
+constexpr int kChunks = 4;
 template <int G, bool ORDERED, bool VALUES, class F>
 __device__ inline void for_products(int32_t row, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
                                     const double *__restrict__ av, const int32_t *__restrict__ brp,
                                     const int32_t *__restrict__ bci, const double *__restrict__ bv, F &&f) {
 #pragma clang fp contract(off)
+    constexpr int QB = 4;
     const int lane = group_lane<G>();
     const int32_t a0 = arp[row], a1 = arp[row + 1];
     for (int32_t kc = a0; kc < a1; kc += G) {
@@ -64,27 +68,40 @@ __device__ inline void for_products(int32_t row, const int32_t *__restrict__ arp
         const double aa = VALUES && in ? av[my] : 0.0;
         const int32_t bb0 = in ? brp[kk] : 0, bb1 = in ? brp[kk + 1] : 0;
         const int nA = a1 - kc < G ? (int)(a1 - kc) : G;
-        int32_t b1 = __shfl(bb1, 0, G);
-        int32_t kb = __shfl(bb0, 0, G) + lane;
-        double a = VALUES ? __shfl(aa, 0, G) : 0.0;
-        int32_t cc = kb < b1 ? bci[kb] : -1;
-        double vv = VALUES && kb < b1 ? bv[kb] : 0.0;
-        for (int q = 0; q < nA; ++q) {
-            const int qn = q + 1 < nA ? q + 1 : q;
-            const int32_t nb1 = __shfl(bb1, qn, G);
-            const int32_t nkb = __shfl(bb0, qn, G) + lane;
-            const double na = VALUES ? __shfl(aa, qn, G) : 0.0;
-            const bool nin = q + 1 < nA && nkb < nb1;
-            const int32_t ncc = nin ? bci[nkb] : -1;
-            const double nvv = VALUES && nin ? bv[nkb] : 0.0;
-            if (cc >= 0) f(cc, a * vv);
-            for (int32_t k2 = kb + G; k2 < b1; k2 += G) f(bci[k2], VALUES ? a * bv[k2] : 0.0);
-            if (ORDERED) wave_sync();
-            b1 = nb1;
-            kb = nkb;
-            a = na;
-            cc = ncc;
-            vv = nvv;
+        for (int q0 = 0; q0 < nA; q0 += QB) {
+            int32_t kb[QB], b1[QB], cc[QB];
+            double a[QB], vv[QB];
+#pragma unroll
+            for (int j = 0; j < QB; ++j) {
+                const int q = q0 + j < nA ? q0 + j : nA - 1;
+                b1[j] = __shfl(bb1, q, G);
+                kb[j] = __shfl(bb0, q, G) + lane;
+                a[j] = VALUES ? __shfl(aa, q, G) : 0.0;
+                const bool ok = q0 + j < nA && kb[j] < b1[j];
+                cc[j] = ok ? bci[kb[j]] : -1;
+                vv[j] = VALUES && ok ? bv[kb[j]] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < QB; ++j) {
+                if (q0 + j < nA) {
+                    if (cc[j] >= 0) f(cc[j], a[j] * vv[j]);
+                    // the rest of the B row, kChunks lane-strides at a time
+                    for (int32_t k2 = kb[j] + G; k2 < b1[j]; k2 += kChunks * G) {
+                        int32_t c2[kChunks];
+                        double v2[kChunks];
+#pragma unroll
+                        for (int t = 0; t < kChunks; ++t) {
+                            const int32_t e = k2 + t * G;
+                            c2[t] = e < b1[j] ? bci[e] : -1;
+                            v2[t] = VALUES && e < b1[j] ? bv[e] : 0.0;
+                        }
+#pragma unroll
+                        for (int t = 0; t < kChunks; ++t)
+                            if (c2[t] >= 0) f(c2[t], VALUES ? a[j] * v2[t] : 0.0);
+                    }
+                }
+                if (ORDERED) wave_sync();
+            }
         }
     }
 }
@@ -198,6 +215,7 @@ __global__ void k_spgemm_nbin(int32_t m, const int32_t *__restrict__ cnt, int8_t
     nbin[i] = c == 0                 ? NB_EMPTY
               : c <= 8              ? NB_G4
               : c <= 32             ? NB_G8
+              : c <= 64             ? NB_G16S
               : c <= 128            ? NB_G16
               : c <= 512            ? NB_G64
               : c <= 2048           ? NB_BLOCK4K
@@ -308,6 +326,22 @@ __device__ inline void group_sort_store(const int32_t *keys, const double *vals,
     }
 }
 
+// Sorts and stores with the least E (entries per lane) that holds w entries,
+// among the widths up to EMAX.
+template <int G, int EMAX>
+__device__ inline void group_sort_store_upto(const int32_t *keys, const double *vals, int w,
+                                             int32_t *__restrict__ oci, double *__restrict__ ov) {
+    if constexpr (EMAX > 1) {
+        if (w > G * (EMAX / 2)) {
+            group_sort_store<G, EMAX>(keys, vals, w, oci, ov);
+            return;
+        }
+        group_sort_store_upto<G, EMAX / 2>(keys, vals, w, oci, ov);
+    } else {
+        group_sort_store<G, 1>(keys, vals, w, oci, ov);
+    }
+}
+
 // Numeric: one G-lane group per row of known length w <= T/2.  The products
 // are accumulated in a T-slot table; the occupied slots are then moved to the
 // front of the table (in place, G slots at a time: a slot never moves to a
@@ -365,14 +399,8 @@ __global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__
         w += tot;
     }
     int32_t base = crp[row];
-    int P = G;
-    while (P < w) P <<= 1;
-    switch (P / G) {
-    case 1: group_sort_store<G, 1>(keys, vals, w, cci + base, cv + base); break;
-    case 2: group_sort_store<G, 2>(keys, vals, w, cci + base, cv + base); break;
-    case 4: group_sort_store<G, 4>(keys, vals, w, cci + base, cv + base); break;
-    default: group_sort_store<G, 8>(keys, vals, w, cci + base, cv + base); break;
-    }
+    constexpr int EMAX = T / 2 / G < 1 ? 1 : T / 2 / G > 8 ? 8 : T / 2 / G;   // w <= T / 2
+    group_sort_store_upto<G, EMAX>(keys, vals, w, cci + base, cv + base);
 }
 
 // ----------------------------------------------------------- block rows ---
@@ -826,6 +854,7 @@ static void run_numeric(const Bins &B, const CsrView &A, const CsrView &Bm, int3
     };
     grp(k_spgemm_fill<4, 16, 256>, NB_G4, 64, 256);
     grp(k_spgemm_fill<8, 64, 256>, NB_G8, 32, 256);
+    grp(k_spgemm_fill<16, 128, 128>, NB_G16S, 8, 128);
     grp(k_spgemm_fill<16, 256, 128>, NB_G16, 8, 128);
     grp(k_spgemm_fill<64, 1024, 64>, NB_G64, 1, 64);
     if (B.count(NB_BLOCK4K))
