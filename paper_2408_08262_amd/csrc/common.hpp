@@ -177,10 +177,12 @@ inline void h2d(T *d, const T *h, size_t count, hipStream_t s) {
     if (!count) return;
     AIRG_HIP(hipMemcpyAsync(d, h, count * sizeof(T), hipMemcpyHostToDevice, s));
 }
+// Device-to-device copy by a copy kernel (no blit or memset node, so also
+// safe inside captured graphs).
+void copy_bytes(void *d, const void *src, size_t bytes, hipStream_t s);
 template <class T>
 inline void d2d(T *d, const T *src, size_t count, hipStream_t s) {
-    if (!count) return;
-    AIRG_HIP(hipMemcpyAsync(d, src, count * sizeof(T), hipMemcpyDeviceToDevice, s));
+    copy_bytes(d, src, count * sizeof(T), s);
 }
 void fill_zero(void *d, size_t bytes, hipStream_t s);
 void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s);

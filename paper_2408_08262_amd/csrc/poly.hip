@@ -80,16 +80,19 @@ __device__ inline void block_sum_vec(double (&v)[N], int cnt, double *sh /* [4][
 // constant.  The reductions are DPP wave sums.  Row `col` of R is taken after
 // step col (alpha on the diagonal, or x0 when the column below is already
 // zero); R (cols x cols, upper triangular) is written column-major at out with
-// leading dimension ldo, through Rl (cols * cols doubles of LDS).
+// leading dimension ldo, through Rl (cols * cols doubles of LDS).  NC >= cols
+// is the compile-time register width, so that the column loops and the shift
+// cover no more than the panel's columns.
+template <int NC>
 __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, int rows, int cols,
                          const double *__restrict__ scale, double *__restrict__ out, int64_t ldo,
                          double *__restrict__ Rl) {
     constexpr int RPL = kQrRows / kQrLanes;
     const int lane = threadIdx.x;
     const double scv = scale && lane < cols ? scale[lane] : 1.0;
-    double W[RPL][kMaxPolyCols];
+    double W[RPL][NC];
 #pragma unroll
-    for (int c = 0; c < kMaxPolyCols; ++c) {
+    for (int c = 0; c < NC; ++c) {
         const double sc = readlane_f64(scv, c);
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {
@@ -119,7 +122,7 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
                 v[j] = r == col ? x0 - alpha : (r > col ? W[j][0] : 0.0);
             }
 #pragma unroll
-            for (int c = 1; c < kMaxPolyCols; ++c) {
+            for (int c = 1; c < NC; ++c) {
                 if (c < left) {
                     double d = 0.0;
 #pragma unroll
@@ -134,7 +137,7 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
         // row col of R: lane t < left takes entry (col, col + t)
         double mine = diag;
 #pragma unroll
-        for (int c = 1; c < kMaxPolyCols; ++c) {
+        for (int c = 1; c < NC; ++c) {
             if (c < left) {
                 const double t = readlane_f64(W[0][c], col);
                 if (lane == c) mine = t;
@@ -142,7 +145,7 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
         }
         if (lane < left) Rl[(col + lane) * cols + col] = mine;
 #pragma unroll
-        for (int c = 0; c + 1 < kMaxPolyCols; ++c)
+        for (int c = 0; c + 1 < NC; ++c)
 #pragma unroll
             for (int j = 0; j < RPL; ++j) W[j][c] = W[j][c + 1];
     }
@@ -155,13 +158,14 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
 
 // Leaf b takes rows b*kQrRows.. of K; its R is rows b*cols.. of the next
 // (column-major) stacked matrix.
+template <int NC>
 __global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf(const double *__restrict__ K, int64_t n, int64_t ldk,
                                                         int cols, const double *__restrict__ scale,
                                                         double *__restrict__ Rs, int64_t ldr) {
-    __shared__ double Rl[kMaxPolyCols * kMaxPolyCols];
+    __shared__ double Rl[NC * NC];
     int64_t r0 = (int64_t)blockIdx.x * kQrRows;
     int rows = (int)(n - r0 < kQrRows ? n - r0 : kQrRows);
-    qr_panel(K, ldk, r0, rows, cols, scale, Rs + (int64_t)blockIdx.x * cols, ldr, Rl);
+    qr_panel<NC>(K, ldk, r0, rows, cols, scale, Rs + (int64_t)blockIdx.x * cols, ldr, Rl);
 }
 
 // Batch form: one leaf per table entry; a leaf with fin >= 0 is the last of
@@ -175,16 +179,17 @@ struct QrLeaf {
     int32_t pad;
 };
 
+template <int NC>
 __global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf_tab(const double *__restrict__ K, int64_t ldk, int cols,
                                                               const QrLeaf *__restrict__ leaves,
                                                               const double *__restrict__ scale,
                                                               double *__restrict__ Rs, int64_t ldr,
                                                               double *__restrict__ Rf) {
-    __shared__ double Rl[kMaxPolyCols * kMaxPolyCols];
+    __shared__ double Rl[NC * NC];
     QrLeaf L = leaves[blockIdx.x];
     const double *sc = scale ? scale + (int64_t)L.seg * cols : nullptr;
     double *out = L.fin >= 0 ? Rf + (int64_t)L.fin * cols * cols : Rs + L.out;
-    qr_panel(K, ldk, L.r0, L.rows, cols, sc, out, L.fin >= 0 ? (int64_t)cols : ldr, Rl);
+    qr_panel<NC>(K, ldk, L.r0, L.rows, cols, sc, out, L.fin >= 0 ? (int64_t)cols : ldr, Rl);
 }
 
 // partial[leaf * cols + c] = sum over the leaf's rows of K[:, c]^2
@@ -244,7 +249,11 @@ static void tsqr_r_x(const double *K, int64_t n, int cols, double *h_R, double *
         if (nb < 1) nb = 1;
         int64_t out_rows = nb * cols;
         bufs[which].alloc((size_t)out_rows * cols, s);
-        k_tsqr_leaf<<<(unsigned)nb, kQrLanes, 0, s>>>(src, rows, ld, cols, nullptr, bufs[which].p, out_rows);
+        if (cols <= 8)
+            k_tsqr_leaf<8><<<(unsigned)nb, kQrLanes, 0, s>>>(src, rows, ld, cols, nullptr, bufs[which].p, out_rows);
+        else
+            k_tsqr_leaf<kMaxPolyCols><<<(unsigned)nb, kQrLanes, 0, s>>>(src, rows, ld, cols, nullptr, bufs[which].p,
+                                                                       out_rows);
         AIRG_LAUNCH_CHECK();
         src = bufs[which].p;
         rows = out_rows;
@@ -408,9 +417,9 @@ void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, doub
         tables.emplace_back(tab.size(), s);
         h2d(tables.back().p, tab.data(), tab.size(), s);
         bufs[which].alloc((size_t)std::max<int64_t>(out_rows, 1) * cols, s);
-        k_tsqr_leaf_tab<<<(unsigned)tab.size(), kQrLanes, 0, s>>>(src, ld, cols, tables.back().p,
-                                                                     scaled ? inv.p : nullptr, bufs[which].p,
-                                                                     std::max<int64_t>(out_rows, 1), Rf);
+        auto leaf_tab = cols <= 8 ? k_tsqr_leaf_tab<8> : k_tsqr_leaf_tab<kMaxPolyCols>;
+        leaf_tab<<<(unsigned)tab.size(), kQrLanes, 0, s>>>(src, ld, cols, tables.back().p, scaled ? inv.p : nullptr,
+                                                          bufs[which].p, std::max<int64_t>(out_rows, 1), Rf);
         AIRG_LAUNCH_CHECK();
         src = bufs[which].p;
         ld = std::max<int64_t>(out_rows, 1);

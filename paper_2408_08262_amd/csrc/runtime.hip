@@ -140,6 +140,44 @@ void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s) {
     AIRG_LAUNCH_CHECK();
 }
 
+// Device-to-device copy by a kernel: 16-byte vectors when both ends are
+// 16-byte aligned, else 4-byte words (every element type here is 4 or 8
+// bytes).  A grid-stride loop over at most 4096 workgroups.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ void k_copy_u128(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = __builtin_nontemporal_load(src + i);
+}
+__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+void copy_bytes(void *d, const void *src, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    const uintptr_t a = (uintptr_t)d, b = (uintptr_t)src;
+    if (bytes % 4 || a % 4 || b % 4) {
+        AIRG_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    size_t head = 0;
+    if (a % 16 == 0 && b % 16 == 0 && bytes >= 16) {
+        const size_t n = bytes / 16;
+        const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+        k_copy_u128<<<g, 256, 0, s>>>((const u32x4 *)src, (u32x4 *)d, n);
+        AIRG_LAUNCH_CHECK();
+        head = n * 16;
+    }
+    if (head < bytes) {
+        const size_t n = (bytes - head) / 4;
+        const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+        k_copy_u32<<<g, 256, 0, s>>>((const uint32_t *)((const char *)src + head), (uint32_t *)((char *)d + head), n);
+        AIRG_LAUNCH_CHECK();
+    }
+}
+
 // ------------------------------------------------------------------ scan ---
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
@@ -268,14 +306,16 @@ __global__ void k_scan_final(ScanSet S) {
 // per-thread sums, coalesced stores, and a carry into the next tile.
 constexpr int kSmallScanThreads = 1024;
 constexpr int kSmallScanItems = 8;
-constexpr int kSmallScanTile = kSmallScanThreads * kSmallScanItems;
 constexpr int64_t kSmallScan = 16384;
+constexpr int64_t kTinyScan = 2048;   // up to this size a 256-thread workgroup
 
 __device__ inline int small_scan_slot(int p) { return p + (p >> 5); }   // pads out LDS bank conflicts
 
-__global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(ScanSet S) {
+template <int TH>
+__global__ void __launch_bounds__(TH) k_scan_small(ScanSet S) {
+    constexpr int kSmallScanTile = TH * kSmallScanItems;
     __shared__ int32_t buf[kSmallScanTile + kSmallScanTile / 32];
-    __shared__ int64_t wsum[kSmallScanThreads / kWave];
+    __shared__ int64_t wsum[TH / kWave];
     const int r = blockIdx.y;
     const int32_t *in = S.in[r];
     int32_t *out = S.out[r];
@@ -285,7 +325,7 @@ __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(ScanSet S) {
     for (int64_t t0 = 0; t0 < n; t0 += kSmallScanTile) {
 #pragma unroll
         for (int j = 0; j < kSmallScanItems; ++j) {
-            int p = j * kSmallScanThreads + tid;
+            int p = j * TH + tid;
             buf[small_scan_slot(p)] = t0 + p < n ? in[t0 + p] : 0;
         }
         __syncthreads();
@@ -304,7 +344,7 @@ __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(ScanSet S) {
         if (lane == kWave - 1) wsum[wid] = x;
         __syncthreads();
         int64_t off = carry + x - s, tot = 0;
-        for (int w = 0; w < kSmallScanThreads / kWave; ++w) {
+        for (int w = 0; w < TH / kWave; ++w) {
             if (w < wid) off += wsum[w];
             tot += wsum[w];
         }
@@ -316,7 +356,7 @@ __global__ void __launch_bounds__(kSmallScanThreads) k_scan_small(ScanSet S) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kSmallScanItems; ++j) {
-            int p = j * kSmallScanThreads + tid;
+            int p = j * TH + tid;
             if (t0 + p < n) out[t0 + p] = buf[small_scan_slot(p)];
         }
         carry += tot;
@@ -498,7 +538,10 @@ static std::vector<const int64_t *> scan_set(const int32_t *const *in, int32_t *
         o += scan_tiles(n[r]) + 1;
     }
     if (small) {
-        k_scan_small<<<dim3(1, k), kSmallScanThreads, 0, s>>>(S);
+        bool tiny = true;
+        for (int r = 0; r < k; ++r) tiny = tiny && n[r] <= kTinyScan;
+        if (tiny) k_scan_small<256><<<dim3(1, k), 256, 0, s>>>(S);
+        else k_scan_small<kSmallScanThreads><<<dim3(1, k), kSmallScanThreads, 0, s>>>(S);
     } else {
         k_scan_reduce<<<dim3((unsigned)maxnb, k), kScanThreads, 0, s>>>(S);
         AIRG_LAUNCH_CHECK();
