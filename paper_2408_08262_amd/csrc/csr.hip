@@ -510,7 +510,8 @@ __global__ void k_cf_rank(const int8_t *__restrict__ cf, int32_t n, const int32_
     rank[i] = c == CF_F ? sF[i] : c == CF_C ? sC[i] : sT[i];
 }
 
-CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s) {
+CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s, const int32_t *extra_src,
+                   int32_t *extra_out) {
     DBuf<int32_t> fF((size_t)n, s), fC((size_t)n, s), fT((size_t)n, s);
     DBuf<int32_t> sF((size_t)n + 1, s), sC((size_t)n + 1, s), sT((size_t)n + 1, s), tot(3, s);
     k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p, fT.p);
@@ -518,8 +519,13 @@ CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s) {
     exclusive_scans({fF.p, fC.p, fT.p}, {sF.p, sC.p, sT.p}, {n, n, n}, s);
     k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, sT.p, rank, tot.p);
     AIRG_LAUNCH_CHECK();
-    int32_t h[3];
-    d2h(h, tot.p, 3, s);
+    int32_t h[4];
+    if (extra_src) {
+        read_ints({tot.p, extra_src}, {3, 1}, h, s);
+        *extra_out = h[3];
+    } else {
+        d2h(h, tot.p, 3, s);
+    }
     return CfCounts{h[0], h[1], h[2]};
 }
 
@@ -793,7 +799,7 @@ __global__ void __launch_bounds__(256) k_drop_fill(int32_t n, const int32_t *__r
     }
 }
 
-Csr drop_rows(const CsrView &A, double tau, bool keep_diag, bool negate, hipStream_t s) {
+static Csr drop_rows_x(const CsrView &A, double tau, bool keep_diag, bool negate, bool bound, hipStream_t s) {
     Csr B;
     B.nr = A.nr;
     B.nc = A.nc;
@@ -805,7 +811,12 @@ Csr drop_rows(const CsrView &A, double tau, bool keep_diag, bool negate, hipStre
                                                                          cnt.p);
     });
     AIRG_LAUNCH_CHECK();
-    B.nnz = exclusive_scan(cnt.p, B.rp.p, A.nr, s);
+    if (bound) {
+        exclusive_scan(cnt.p, B.rp.p, A.nr, s, false);
+        B.nnz = A.nnz;
+    } else {
+        B.nnz = exclusive_scan(cnt.p, B.rp.p, A.nr, s);
+    }
     B.ci.alloc((size_t)B.nnz, s);
     B.v.alloc((size_t)B.nnz, s);
     dispatch_group(g, [&]<int G>() {
@@ -814,6 +825,14 @@ Csr drop_rows(const CsrView &A, double tau, bool keep_diag, bool negate, hipStre
     });
     AIRG_LAUNCH_CHECK();
     return B;
+}
+
+Csr drop_rows(const CsrView &A, double tau, bool keep_diag, bool negate, hipStream_t s) {
+    return drop_rows_x(A, tau, keep_diag, negate, false, s);
+}
+
+Csr drop_rows_bound(const CsrView &A, double tau, bool keep_diag, bool negate, hipStream_t s) {
+    return drop_rows_x(A, tau, keep_diag, negate, true, s);
 }
 
 // ------------------------------------------------------------- transpose ---

@@ -43,7 +43,10 @@ std::pair<int32_t, int32_t> cf_ranks(const int8_t *cf, int32_t n, int32_t *rank,
 struct CfCounts {
     int32_t nF, nC, nT;
 };
-CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s);
+// extra_src, when given, is one more device int read back with the counts
+// into *extra_out.
+CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s, const int32_t *extra_src = nullptr,
+                   int32_t *extra_out = nullptr);
 // cf_ranks3 plus, at the segment boundaries d_off[0..na] (device, ascending,
 // d_off[na] = n), the numbers of F, C and terminal rows before each boundary:
 // h_bounds[3 p + {0, 1, 2}] (host, 3 (na + 1) entries).
@@ -63,6 +66,10 @@ void extract_fc_blocks(const CsrView &A, const int8_t *cf, const int32_t *rank, 
 // Keep entries with |x| >= tau * max_j |x_rj| (and the diagonal when
 // keep_diag); negate scales every kept value by -1 when set.
 Csr drop_rows(const CsrView &A, double tau, bool keep_diag, bool negate, hipStream_t s);
+// The same without the host synchronisation: B.rp is complete on the device
+// and B.ci / B.v have room for A.nnz entries; B.nnz is left at that upper
+// bound, and the caller replaces it by B.rp[nr] once it has read it.
+Csr drop_rows_bound(const CsrView &A, double tau, bool keep_diag, bool negate, hipStream_t s);
 
 // A^T with rows sorted (deterministic).
 Csr transpose(const CsrView &A, hipStream_t s);

@@ -121,13 +121,22 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
                 const int r = lane + j * kQrLanes;
                 v[j] = r == col ? x0 - alpha : (r > col ? W[j][0] : 0.0);
             }
+            // the dot products of every register column, then their wave
+            // sums side by side (independent reductions overlap); columns
+            // at or past `left` are discarded
+            double d[NC];
+#pragma unroll
+            for (int c = 1; c < NC; ++c) {
+                d[c] = 0.0;
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) d[c] += v[j] * W[j][c];
+            }
+#pragma unroll
+            for (int c = 1; c < NC; ++c) d[c] = wave_sum_f64(d[c]);
 #pragma unroll
             for (int c = 1; c < NC; ++c) {
                 if (c < left) {
-                    double d = 0.0;
-#pragma unroll
-                    for (int j = 0; j < RPL; ++j) d += v[j] * W[j][c];
-                    const double f = 2.0 * wave_sum_f64(d) / vv;
+                    const double f = 2.0 * d[c] / vv;
 #pragma unroll
                     for (int j = 0; j < RPL; ++j) W[j][c] -= f * v[j];
                 }

@@ -117,9 +117,12 @@ CfParams cf_params(const airg_opts &o, uint64_t seed) {
     return CfParams{o.strong_threshold, o.ddc_threshold, o.ddc_fraction, o.pmisr_max_rounds, seed};
 }
 
-// CF splitting of one level; fills cf and rank, returns (nF, nC).
+// CF splitting of one level; fills cf and rank, returns (nF, nC).  When
+// nnz_out is given, A.nnz is only an upper bound (A's rows were kept by a
+// drop whose total was not read) and the exact count A.rp[nr] is read back
+// with the splitting's counts into *nnz_out.
 std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl, DBuf<int8_t> &cf,
-                                  DBuf<int32_t> &rank, hipStream_t s) {
+                                  DBuf<int32_t> &rank, hipStream_t s, int64_t *nnz_out = nullptr) {
     int32_t n = A.nr;
     cf.alloc((size_t)n, s);
     rank.alloc((size_t)n, s);
@@ -131,7 +134,11 @@ std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t
     double ad = o.ddc_threshold;
     if (ad < 0.0) ad = ddc_fraction_threshold(A, cf0.p, o.ddc_fraction, s);
     ddc(A, ad, cf0.p, cf.p, nullptr, s);
-    return cf_ranks(cf.p, n, rank.p, s);
+    if (!nnz_out) return cf_ranks(cf.p, n, rank.p, s);
+    int32_t nz = 0;
+    CfCounts c = cf_ranks3(cf.p, n, rank.p, s, A.rp + n, &nz);
+    *nnz_out = nz;
+    return {c.nF, c.nC};
 }
 
 }  // namespace
@@ -236,7 +243,8 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     {
         Csr prod = planned ? spgemm_finish(view(Acf), view(Ainv), zplan, htot.data() + zoff, s)
                            : spgemm(view(Acf), view(Ainv), s);
-        Z = drop_rows(view(prod), o.drop_R, false, true, s);   // Z = -A_cf Ainv, dropped
+        // Z = -A_cf Ainv, dropped; its entry count is read with R A P's plan
+        Z = drop_rows_bound(view(prod), o.drop_R, false, true, s);
     }
     if (br) {
         tm.end();
@@ -248,9 +256,17 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     }
     tm.begin(AIRG_PHASE_COARSE);
     {
-        Csr R = restriction_full(view(Z), fidx.p, cidx.p, n, s);
-        Csr RAP = spgemm(view(R), view(AP), s);
-        Ac = drop_rows(view(RAP), o.drop_A, true, false, s);
+        Csr R = restriction_full(view(Z), fidx.p, cidx.p, n, s);   // entry count bounded by Z's
+        SpgemmPlan plan = spgemm_begin(view(R), AP.rp.p, AP.nc, s);
+        auto [tsrc, tcnt] = plan.totals();
+        std::vector<int32_t> h((size_t)tcnt + 1);
+        if (tcnt > 0) read_ints({Z.rp.p + Z.nr, tsrc}, {1, tcnt}, h.data(), s);
+        else read_ints({Z.rp.p + Z.nr}, {1}, h.data(), s);
+        Z.nnz = h[0];
+        R.nnz = Z.nnz + Z.nr;
+        Csr RAP = spgemm_finish(view(R), view(AP), plan, h.data() + 1, s);
+        // with a Branch the entry count is read by the next level's splitting
+        Ac = br ? drop_rows_bound(view(RAP), o.drop_A, true, false, s) : drop_rows(view(RAP), o.drop_A, true, false, s);
     }
     tm.end();
 }
@@ -586,13 +602,22 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
         Level &L = H->L(l);
         int32_t n = L.n;
         bool coarsest = (o.truncate_n > 0 && n <= o.truncate_n) || l == maxl - 1;
+        // below the top, A's entry count is an upper bound until read: with
+        // the splitting's counts, or on its own for a coarsest level
+        const bool bound = l > 0;
         if (!coarsest) {
             tm.begin(AIRG_PHASE_CF);
-            auto [nF, nC] = split(view(L.A), o, seed, l, L.cf, L.rank, s);
+            int64_t nz = 0;
+            auto [nF, nC] = split(view(L.A), o, seed, l, L.cf, L.rank, s, bound ? &nz : nullptr);
+            if (bound) L.A.nnz = nz;
             L.nF = nF;
             L.nC = nC;
             tm.end();
             if (nF == 0 || nC < o.poly_order) coarsest = true;
+        } else if (bound) {
+            int32_t nz = 0;
+            d2h(&nz, L.A.rp.p + n, 1, s);
+            L.A.nnz = nz;
         }
         if (coarsest) {
             tm.begin(AIRG_PHASE_POLY);
