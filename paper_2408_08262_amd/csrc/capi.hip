@@ -306,10 +306,15 @@ airg_status airg_setup(const airg_opts *opts, int64_t n, int64_t nnz, const int3
         for (int p = 0; p < ns; ++p) h->seeds[p] = h_seg_seeds ? h_seg_seeds[p] : opts->seed + (uint64_t)p;
         Csr A = canonical_copy((int32_t)n, nnz, d_rowptr, d_col, d_val, s);
         record_canonical_map(h.get(), (int32_t)n, nnz, d_rowptr, d_col, d_val, A.nnz, s);
-        {
-            std::vector<int32_t> rph((size_t)n + 1);
-            d2h(rph.data(), A.rp.p, rph.size(), s);
-            for (int p = 0; p <= ns; ++p) h->seg_nnz.push_back(rph[(size_t)h->seg[p]]);
+        if (ns == 1) {
+            h->seg_nnz = {0, A.nnz};
+        } else {
+            // the entry offsets at the segment boundaries only
+            std::vector<const int32_t *> src((size_t)ns + 1);
+            for (int p = 0; p <= ns; ++p) src[(size_t)p] = A.rp.p + h->seg[p];
+            std::vector<int32_t> cnt((size_t)ns + 1, 1), at((size_t)ns + 1);
+            read_ints(src, cnt, at.data(), s);
+            for (int p = 0; p <= ns; ++p) h->seg_nnz.push_back(at[(size_t)p]);
         }
         const bool batch_solve = ns > 1 && opts->outer == AIRG_OUTER_FGMRES && opts->precond_precision == 32;
         AIRG_REQUIRE(!(batch_solve && opts->coarse_matrix_free), ST_INVALID_ARG,

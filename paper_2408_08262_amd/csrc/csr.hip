@@ -62,23 +62,26 @@ Csr canonical_copy(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
     AIRG_REQUIRE(n > 0, ST_INVALID_ARG, "matrix must have at least one row");
     AIRG_REQUIRE(nnz >= n && nnz < ((int64_t)1 << 31), ST_INVALID_ARG, "nnz out of range");
     int32_t ends[2] = {-1, -1};
-    d2h(&ends[0], rp, 1, s);
-    d2h(&ends[1], rp + n, 1, s);
+    read_ints({rp, rp + n}, {1, 1}, ends, s);
     AIRG_REQUIRE(ends[0] == 0 && (int64_t)ends[1] == nnz, ST_BAD_CSR, "row pointers must start at 0 and end at nnz");
     DBuf<int32_t> keep((size_t)n, s);
     DBuf<uint32_t> flags(1, s);
     fill_zero(flags.p, 4, s);
     k_validate<<<grid_for(n, 256), 256, 0, s>>>(n, nnz, rp, ci, v, keep.p, flags.p);
     AIRG_LAUNCH_CHECK();
-    uint32_t f = d2h_one(flags.p, s);
+    Csr A;
+    A.nr = A.nc = n;
+    A.rp.alloc((size_t)n + 1, s);
+    exclusive_scan(keep.p, A.rp.p, n, s, false);
+    // the flags and the kept count in one readback
+    int32_t fk[2];
+    read_ints({reinterpret_cast<const int32_t *>(flags.p), A.rp.p + n}, {1, 1}, fk, s);
+    const uint32_t f = (uint32_t)fk[0];
     AIRG_REQUIRE(!(f & (BAD_RP | BAD_COL)), ST_BAD_CSR, "columns must be in range and strictly ascending per row");
     AIRG_REQUIRE(!(f & NONFINITE), ST_NONFINITE, "matrix has a non-finite value");
     AIRG_REQUIRE(!(f & NO_DIAG), ST_BAD_CSR, "every row must store its diagonal");
     AIRG_REQUIRE(!(f & ZERO_DIAG), ST_ZERO_DIAG, "matrix has a zero diagonal entry");
-    Csr A;
-    A.nr = A.nc = n;
-    A.rp.alloc((size_t)n + 1, s);
-    int64_t kept = exclusive_scan(keep.p, A.rp.p, n, s);
+    const int64_t kept = fk[1];
     A.nnz = kept;
     A.ci.alloc((size_t)kept, s);
     A.v.alloc((size_t)kept, s);
