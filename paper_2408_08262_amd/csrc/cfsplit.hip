@@ -155,9 +155,25 @@ __device__ inline bool key_less(int32_t dj, uint32_t hj, int32_t j, int32_t di, 
     return j < i;
 }
 
-__global__ void k_pmisr_init(int32_t n, const int32_t *__restrict__ deg, int8_t *__restrict__ cf) {
+// Per-node key for the rounds: (deg << 32) | h while unassigned, so that the
+// unsigned order of keys is the (deg, h) order above, and kAssigned once the
+// node has joined F or C -- a neighbour's state and measure are then one
+// 8-byte load.  kAssigned exceeds every unassigned key (deg < 2^31).
+constexpr uint64_t kAssigned = ~0ull;
+
+__global__ void k_pmisr_init(int32_t n, const int32_t *__restrict__ deg, const uint32_t *__restrict__ h,
+                             int8_t *__restrict__ cf, uint64_t *__restrict__ key) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) cf[i] = deg[i] == 0 ? CF_F : CF_U;
+    if (i >= n) return;
+    const bool isolated = deg[i] == 0;
+    cf[i] = isolated ? CF_F : CF_U;
+    key[i] = isolated ? kAssigned : ((uint64_t)(uint32_t)deg[i] << 32) | h[i];
+}
+
+// Neighbour j (key kj) beats node i (key ki, unassigned): j is unassigned
+// and key_less(j, i).
+__device__ inline bool beats(uint64_t kj, int32_t j, uint64_t ki, int32_t i) {
+    return kj < ki || (kj == ki && j < i);
 }
 
 // D = unassigned nodes whose key is below every unassigned neighbour's key
@@ -169,21 +185,18 @@ __global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *
                                                       const uint8_t *__restrict__ strong,
                                                       const int32_t *__restrict__ trp,
                                                       const int32_t *__restrict__ tci,
-                                                      const int32_t *__restrict__ deg,
-                                                      const uint32_t *__restrict__ h,
-                                                      const int8_t *__restrict__ cf, uint8_t *__restrict__ inD,
-                                                      int32_t *__restrict__ nu) {
+                                                      const uint64_t *__restrict__ key,
+                                                      uint8_t *__restrict__ inD, int32_t *__restrict__ nu) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
     if (row >= n) return;
-    if (cf[row] != CF_U) {
+    const uint64_t ki = key[row];
+    if (ki == kAssigned) {
         if (lane == 0) inD[row] = 0;
         return;
     }
     if (nu && lane == 0) atomicAdd(nu, 1);   // unassigned at the start of the round
-    int32_t di = deg[row];
-    uint32_t hi = h[row];
     bool beaten = false;
     int32_t e = rp[row + 1];
     for (int32_t base = rp[row]; base < e; base += G) {
@@ -191,7 +204,7 @@ __global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *
         bool lose = false;
         if (k < e && strong[k]) {
             int32_t j = ci[k];
-            lose = cf[j] == CF_U && key_less(deg[j], h[j], j, di, hi, row);
+            lose = beats(key[j], j, ki, row);
         }
         if (group_any<G>(lose)) { beaten = true; break; }
     }
@@ -202,7 +215,7 @@ __global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *
             bool lose = false;
             if (k < te) {
                 int32_t j = tci[k];
-                lose = cf[j] == CF_U && key_less(deg[j], h[j], j, di, hi, row);
+                lose = beats(key[j], j, ki, row);
             }
             if (group_any<G>(lose)) { beaten = true; break; }
         }
@@ -217,14 +230,18 @@ __global__ void __launch_bounds__(256) k_pmisr_apply(int32_t n, const int32_t *_
                                                      const uint8_t *__restrict__ strong,
                                                      const int32_t *__restrict__ trp,
                                                      const int32_t *__restrict__ tci,
-                                                     const uint8_t *__restrict__ inD, int8_t *__restrict__ cf) {
+                                                     const uint8_t *__restrict__ inD, int8_t *__restrict__ cf,
+                                                     uint64_t *__restrict__ key) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
     if (row >= n) return;
     if (cf[row] != CF_U) return;
     if (inD[row]) {
-        if (lane == 0) cf[row] = CF_F;
+        if (lane == 0) {
+            cf[row] = CF_F;
+            key[row] = kAssigned;
+        }
         return;
     }
     bool hit = false;
@@ -240,7 +257,10 @@ __global__ void __launch_bounds__(256) k_pmisr_apply(int32_t n, const int32_t *_
         bool p = k < te && inD[tci[k]];
         hit = group_any<G>(p);
     }
-    if (hit && lane == 0) cf[row] = CF_C;
+    if (hit && lane == 0) {
+        cf[row] = CF_C;
+        key[row] = kAssigned;
+    }
 }
 
 __global__ void k_pmisr_finish(int32_t n, int8_t *__restrict__ cf, int32_t *__restrict__ nu) {
@@ -266,7 +286,8 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
     const bool until_done = max_rounds <= 0;
     DBuf<int32_t> nu(until_done ? (size_t)kPmisrSlots : 1, s);
     if (until_done) fill_zero(nu.p, (size_t)kPmisrSlots * 4, s);
-    k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, cf);
+    DBuf<uint64_t> key((size_t)n, s);
+    k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, h, cf, key.p);
     AIRG_LAUNCH_CHECK();
     int g = lanes_for(A.nnz, n);
     int rounds = 0;
@@ -276,9 +297,8 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
         int32_t *cnt = until_done ? nu.p + rounds : nullptr;
         dispatch_group(g, [&]<int W>() {
             unsigned grid = grid_for((int64_t)n * W, 256);
-            k_pmisr_decide<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, G.deg.p, h, cf,
-                                                   inD.p, cnt);
-            k_pmisr_apply<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, inD.p, cf);
+            k_pmisr_decide<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, key.p, inD.p, cnt);
+            k_pmisr_apply<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, inD.p, cf, key.p);
         });
         AIRG_LAUNCH_CHECK();
         ++rounds;
