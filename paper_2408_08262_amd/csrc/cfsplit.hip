@@ -64,23 +64,6 @@ __global__ void __launch_bounds__(256) k_strength_mutual(int32_t n, const int32_
     if (lane == 0) mutual[row] = mu;
 }
 
-template <int G>
-__global__ void __launch_bounds__(256) k_strength_scatter(int32_t n, const int32_t *__restrict__ rp,
-                                                          const int32_t *__restrict__ ci,
-                                                          const uint8_t *__restrict__ strong,
-                                                          const int32_t *__restrict__ trp,
-                                                          int32_t *__restrict__ cursor, int32_t *__restrict__ tci) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t row = (int32_t)(t / G);
-    int lane = group_lane<G>();
-    if (row >= n) return;
-    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
-        if (!strong[k]) continue;
-        int32_t j = ci[k];
-        tci[trp[j] + atomicAdd(&cursor[j], 1)] = row;
-    }
-}
-
 __global__ void k_degree(int32_t n, const int32_t *__restrict__ cntS, const int32_t *__restrict__ cntT,
                          const int32_t *__restrict__ mutual, int32_t *__restrict__ deg) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -93,9 +76,8 @@ StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
     G.n = n;
     G.strong.alloc((size_t)A.nnz, s);
     G.deg.alloc((size_t)n, s);
-    G.trp.alloc((size_t)n + 1, s);
-    DBuf<int32_t> cntS((size_t)n, s), cntT((size_t)n + 1, s), mutual((size_t)n, s);
-    fill_zero(cntT.p, ((size_t)n + 1) * 4, s);
+    DBuf<int32_t> cntS((size_t)n, s), cntT((size_t)n, s), mutual((size_t)n, s);
+    fill_zero(cntT.p, (size_t)n * 4, s);
     int g = lanes_for(A.nnz, n);
     dispatch_group(g, [&]<int W>() {
         unsigned grid = grid_for((int64_t)n * W, 256);
@@ -104,17 +86,6 @@ StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
     });
     AIRG_LAUNCH_CHECK();
     k_degree<<<grid_for(n, 256), 256, 0, s>>>(n, cntS.p, cntT.p, mutual.p, G.deg.p);
-    AIRG_LAUNCH_CHECK();
-    // the transposed lists hold the strong entries, at most nnz(A) of them:
-    // allocated at that bound, so that their size needs no readback
-    exclusive_scan(cntT.p, G.trp.p, n, s, false);
-    G.tci.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);
-    DBuf<int32_t> cursor((size_t)n, s);
-    fill_zero(cursor.p, (size_t)n * 4, s);
-    dispatch_group(g, [&]<int W>() {
-        k_strength_scatter<W><<<grid_for((int64_t)n * W, 256), 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p,
-                                                                            cursor.p, G.tci.p);
-    });
     AIRG_LAUNCH_CHECK();
     return G;
 }
@@ -176,17 +147,44 @@ __device__ inline bool beats(uint64_t kj, int32_t j, uint64_t ki, int32_t i) {
     return kj < ki || (kj == ki && j < i);
 }
 
-// D = unassigned nodes whose key is below every unassigned neighbour's key
-// in S_i u S_i^T, taken from the state at the start of the round.  The group
-// walks both neighbour lists and a wavefront ballot decides.
+// Rounds in push/pull form over the rows of S only (S^T is never formed).
+// A round's independent set D holds the unassigned nodes that no unassigned
+// neighbour in S_i u S_i^T beats, taken from the state at the start of the
+// round; then D joins F and the unassigned nodes with a neighbour in D join C.
+// Neighbours j in S_i are read from row i (pull); a node j with i in S_j
+// reaches i through its own row (push), by setting a flag that i consumes and
+// clears:
+//   beaten[i]: some unassigned j with i in S_j beats i (pushed before the round);
+//   markC[x]:  some y in D has x in S_y (pushed by y during the round).
+// Several pushers store the same 1, so the flags do not depend on the order.
+
+// Pushes for the first round.
 template <int G>
-__global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *__restrict__ rp,
+__global__ void __launch_bounds__(256) k_pmisr_push(int32_t n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci,
+                                                    const uint8_t *__restrict__ strong,
+                                                    const uint64_t *__restrict__ key, uint8_t *__restrict__ beaten) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    const uint64_t kj = key[row];
+    if (kj == kAssigned) return;
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G)
+        if (strong[k]) {
+            const int32_t i = ci[k];
+            if (beats(kj, row, key[i], i)) beaten[i] = 1;
+        }
+}
+
+// Selection: inD[i] for every node; a node of D pushes markC along its row.
+template <int G>
+__global__ void __launch_bounds__(256) k_pmisr_select(int32_t n, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci,
                                                       const uint8_t *__restrict__ strong,
-                                                      const int32_t *__restrict__ trp,
-                                                      const int32_t *__restrict__ tci,
                                                       const uint64_t *__restrict__ key,
-                                                      uint8_t *__restrict__ inD, int32_t *__restrict__ nu) {
+                                                      uint8_t *__restrict__ beaten, uint8_t *__restrict__ inD,
+                                                      uint8_t *__restrict__ markC, int32_t *__restrict__ nu) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
@@ -197,46 +195,41 @@ __global__ void __launch_bounds__(256) k_pmisr_decide(int32_t n, const int32_t *
         return;
     }
     if (nu && lane == 0) atomicAdd(nu, 1);   // unassigned at the start of the round
-    bool beaten = false;
-    int32_t e = rp[row + 1];
-    for (int32_t base = rp[row]; base < e; base += G) {
+    bool lost = beaten[row] != 0;
+    const int32_t b = rp[row], e = rp[row + 1];
+    for (int32_t base = b; base < e && !lost; base += G) {
         int32_t k = base + lane;
         bool lose = false;
         if (k < e && strong[k]) {
             int32_t j = ci[k];
             lose = beats(key[j], j, ki, row);
         }
-        if (group_any<G>(lose)) { beaten = true; break; }
+        lost = group_any<G>(lose);
     }
-    if (!beaten) {
-        int32_t te = trp[row + 1];
-        for (int32_t base = trp[row]; base < te; base += G) {
-            int32_t k = base + lane;
-            bool lose = false;
-            if (k < te) {
-                int32_t j = tci[k];
-                lose = beats(key[j], j, ki, row);
-            }
-            if (group_any<G>(lose)) { beaten = true; break; }
-        }
+    if (lane == 0) {
+        beaten[row] = 0;
+        inD[row] = !lost;
     }
-    if (lane == 0) inD[row] = !beaten;
+    if (!lost)
+        for (int32_t k = b + lane; k < e; k += G)
+            if (strong[k]) markC[ci[k]] = 1;
 }
 
-// D joins F; unassigned nodes with a neighbour in D join C.
+// Update: D joins F; an unassigned node with a neighbour in D joins C; a node
+// still unassigned pushes beaten along its row for the next round.
 template <int G>
-__global__ void __launch_bounds__(256) k_pmisr_apply(int32_t n, const int32_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ ci,
-                                                     const uint8_t *__restrict__ strong,
-                                                     const int32_t *__restrict__ trp,
-                                                     const int32_t *__restrict__ tci,
-                                                     const uint8_t *__restrict__ inD, int8_t *__restrict__ cf,
-                                                     uint64_t *__restrict__ key) {
+__global__ void __launch_bounds__(256) k_pmisr_update(int32_t n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      const uint8_t *__restrict__ strong,
+                                                      const uint8_t *__restrict__ inD, int8_t *__restrict__ cf,
+                                                      uint64_t *__restrict__ key, uint8_t *__restrict__ markC,
+                                                      uint8_t *__restrict__ beaten) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
     if (row >= n) return;
-    if (cf[row] != CF_U) return;
+    const uint64_t kx = key[row];
+    if (kx == kAssigned) return;
     if (inD[row]) {
         if (lane == 0) {
             cf[row] = CF_F;
@@ -244,23 +237,28 @@ __global__ void __launch_bounds__(256) k_pmisr_apply(int32_t n, const int32_t *_
         }
         return;
     }
-    bool hit = false;
-    int32_t e = rp[row + 1];
-    for (int32_t base = rp[row]; base < e && !hit; base += G) {
+    bool hit = markC[row] != 0;
+    const int32_t b = rp[row], e = rp[row + 1];
+    for (int32_t base = b; base < e && !hit; base += G) {
         int32_t k = base + lane;
         bool p = k < e && strong[k] && inD[ci[k]];
         hit = group_any<G>(p);
     }
-    int32_t te = trp[row + 1];
-    for (int32_t base = trp[row]; base < te && !hit; base += G) {
-        int32_t k = base + lane;
-        bool p = k < te && inD[tci[k]];
-        hit = group_any<G>(p);
+    if (hit) {
+        if (lane == 0) {
+            markC[row] = 0;
+            cf[row] = CF_C;
+            key[row] = kAssigned;
+        }
+        return;
     }
-    if (hit && lane == 0) {
-        cf[row] = CF_C;
-        key[row] = kAssigned;
-    }
+    // a neighbour assigned in this same pass may be pushed to: its flag is
+    // never read again
+    for (int32_t k = b + lane; k < e; k += G)
+        if (strong[k]) {
+            const int32_t i = ci[k];
+            if (beats(kx, row, key[i], i)) beaten[i] = 1;
+        }
 }
 
 __global__ void k_pmisr_finish(int32_t n, int8_t *__restrict__ cf, int32_t *__restrict__ nu) {
@@ -287,18 +285,25 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
     DBuf<int32_t> nu(until_done ? (size_t)kPmisrSlots : 1, s);
     if (until_done) fill_zero(nu.p, (size_t)kPmisrSlots * 4, s);
     DBuf<uint64_t> key((size_t)n, s);
+    DBuf<uint8_t> flags((size_t)2 * n, s);
+    uint8_t *beaten = flags.p, *markC = flags.p + n;
+    fill_zero(flags.p, (size_t)2 * n, s);
     k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, h, cf, key.p);
     AIRG_LAUNCH_CHECK();
     int g = lanes_for(A.nnz, n);
+    const unsigned grid = grid_for((int64_t)n * g, 256);
+    dispatch_group(g, [&]<int W>() {
+        k_pmisr_push<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, key.p, beaten);
+    });
+    AIRG_LAUNCH_CHECK();
     int rounds = 0;
     for (;;) {
         if (!until_done && rounds >= max_rounds) break;
         AIRG_REQUIRE(rounds < kPmisrSlots, ST_STALL, "PMISR did not finish");
         int32_t *cnt = until_done ? nu.p + rounds : nullptr;
         dispatch_group(g, [&]<int W>() {
-            unsigned grid = grid_for((int64_t)n * W, 256);
-            k_pmisr_decide<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, key.p, inD.p, cnt);
-            k_pmisr_apply<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.trp.p, G.tci.p, inD.p, cf, key.p);
+            k_pmisr_select<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, key.p, beaten, inD.p, markC, cnt);
+            k_pmisr_update<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, inD.p, cf, key.p, markC, beaten);
         });
         AIRG_LAUNCH_CHECK();
         ++rounds;

@@ -9,7 +9,6 @@ namespace airg {
 struct StrengthGraph {
     int32_t n = 0;
     DBuf<uint8_t> strong;       // per nonzero of A: 1 if j in S_i
-    DBuf<int32_t> trp, tci;     // S^T as neighbour lists (order within a row unspecified)
     DBuf<int32_t> deg;          // |S_i u S_i^T|
 };
 
