@@ -148,12 +148,13 @@ __host__ __device__ inline int64_t xcd_grid(int64_t tiles) {
     return (tiles + g - 1) / g * g;
 }
 
-// Group width (lanes per row) for row-parallel kernels: the power of two
-// covering the mean row length, between 1 and 64.
+// Group width (lanes per row) for row-parallel kernels: the largest power of
+// two not above the mean row length, between 1 and 64 (rows a little longer
+// than the group take a second pass rather than leave most lanes idle).
 inline int lanes_for(int64_t nnz, int64_t rows) {
     double avg = rows > 0 ? (double)nnz / (double)rows : 1.0;
     int g = 1;
-    while (g < 64 && g < avg) g <<= 1;
+    while (g < 64 && 2 * g <= avg) g <<= 1;
     return g;
 }
 
