@@ -481,7 +481,7 @@ __global__ void k_rowlen_bin(int32_t n, const int32_t *__restrict__ rp, int8_t *
 
 // One G-lane group per row (L = row length <= G).  M_i = A(J_i, J_i) is built
 // in LDS by merging each gathered row with J_i; then v_k = v_{k-1} M_i with
-// lane a owning column a, the sum over p ascending.
+// lane a owning column a, the sum over p ascending (v_{k-1} read from LDS).
 template <int G, int TPB>
 __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ list, int64_t count,
                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -492,6 +492,7 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
 #pragma clang fp contract(off)
     constexpr int NG = TPB / G;
     __shared__ double Ms[NG][G * G];
+    __shared__ double Xs[NG][G];
     __shared__ int32_t Js[NG][G];
     int gid = threadIdx.x / G;
     int lane = group_lane<G>();
@@ -501,18 +502,32 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     int32_t b = prp[row];
     int32_t L = prp[row + 1] - b;
     double *M = Ms[gid];
+    double *X = Xs[gid];
     int32_t *J = Js[gid];
     if (lane < L) J[lane] = pci[b + lane];
     for (int t = lane; t < G * G; t += G) M[t] = 0.0;
     wave_sync();
     if (lane < L) {
-        int32_t r = J[lane];
+        // row J[lane] of A merged with J, its entries loaded four at a time
+        // (the loads of a batch in flight together); past the row end the
+        // column INT_MAX moves q to L
+        const int32_t r = J[lane];
+        const int32_t ke = rp[r + 1];
         int q = 0;
-        for (int32_t kk = rp[r]; kk < rp[r + 1]; ++kk) {
-            int32_t c = ci[kk];
-            while (q < L && J[q] < c) ++q;
-            if (q == L) break;
-            if (J[q] == c) M[lane * G + q] = v[kk];
+        for (int32_t kk = rp[r]; kk < ke && q < L; kk += 4) {
+            int32_t c4[4];
+            double v4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = kk + u < ke;
+                c4[u] = ok ? ci[kk + u] : 0x7fffffff;
+                v4[u] = ok ? v[kk + u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                while (q < L && J[q] < c4[u]) ++q;
+                if (q < L && J[q] == c4[u]) M[lane * G + q] = v4[u];
+            }
         }
     }
     wave_sync();
@@ -520,8 +535,13 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     double x = (lane < L && J[lane] == row) ? 1.0 : 0.0;
     double acc = al[0] * x;
     for (int k = 1; k < nalpha; ++k) {
+        // x goes through LDS, so that the L broadcast reads are independent
+        // loads rather than a chain of shuffles
+        X[lane] = x;
+        wave_sync();
         double xn = 0.0;
-        for (int p = 0; p < L; ++p) xn += group_bcast<G>(x, p) * M[p * G + lane];
+        for (int p = 0; p < L; ++p) xn += X[p] * M[p * G + lane];
+        wave_sync();
         x = xn;
         acc += al[k] * x;
     }
