@@ -1,6 +1,7 @@
-// CF splitting kernels for gfx950: strength of connection, the transposed
-// strength lists, PMISR rounds decided with wavefront ballots, and the DDC
-// diagonal-dominance scan with a fixed summation order.
+// CF splitting kernels for gfx950: strength of connection and degrees in
+// S u S^T, PMISR rounds decided with wavefront ballots (push/pull over the
+// rows of S), and the DDC diagonal-dominance scan with a fixed summation
+// order.
 #include <cmath>
 
 #include "cfsplit.hpp"
@@ -270,7 +271,7 @@ __global__ void k_pmisr_finish(int32_t n, int8_t *__restrict__ cf, int32_t *__re
     }
 }
 
-// Until no node is unassigned (max_rounds <= 0), every round's decide pass
+// Until no node is unassigned (max_rounds <= 0), every round's selection pass
 // also counts the unassigned nodes it starts from into nu[round]; the counts
 // are read back every kPmisrCheck rounds.  A round that starts with none
 // changes nothing, so the rounds run past the end are no-ops and the count
