@@ -12,7 +12,10 @@
 // the A row are taken one at a time in ascending order and the lanes spread
 // over the B row, whose columns are distinct, so every output entry receives
 // its products in ascending k order, without contraction -- the same order
-// and rounding as a sequential row-wise (Gustavson) product.
+// and rounding as a sequential row-wise (Gustavson) product.  The additions
+// into LDS tables are the LDS unit's double add (one correctly rounded add,
+// as in registers, with no read back into the wavefront): a wavefront's LDS
+// operations complete in program order, so the order per slot is unchanged.
 #include "csr.hpp"
 #include "group.hpp"
 #include "spgemm.hpp"
@@ -374,7 +377,7 @@ __global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__
     auto acc = [&](int32_t c, double p) {
         bool fresh;
         uint32_t s = hash_insert(keys, T - 1, c, &fresh);
-        vals[s] = vals[s] + p;
+        unsafeAtomicAdd(&vals[s], p);
     };
     if constexpr (G == 64) {
         __shared__ ProdStage<true> St[NG];
@@ -618,7 +621,7 @@ __global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *
                 const int32_t c = bci[kb0 + t];
                 if ((uint32_t)c >= (uint32_t)NC) continue;   // columns beyond B's width are not stored
                 mark[c] = 1;
-                if (NUMERIC) acc[c] = acc[c] + ka * bv[kb0 + t];
+                if (NUMERIC) unsafeAtomicAdd(&acc[c], ka * bv[kb0 + t]);
             }
             wave_sync();
             q0 += 1;
@@ -652,7 +655,7 @@ __global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *
                     const int32_t c = sc[p];
                     if ((uint32_t)c >= (uint32_t)NC) continue;
                     mark[c] = 1;
-                    acc[c] = acc[c] + sv[p];
+                    unsafeAtomicAdd(&acc[c], sv[p]);
                 }
                 wave_sync();
             }
@@ -756,7 +759,7 @@ __global__ void __launch_bounds__(TPB) k_spgemm_on_pattern(const int32_t *__rest
             if (cols[mid] < c) lo = mid + 1;
             else hi = mid;
         }
-        if (lo < len && cols[lo] == c) vals[lo] = vals[lo] + p;
+        if (lo < len && cols[lo] == c) unsafeAtomicAdd(&vals[lo], p);
     };
     if constexpr (G == 64) {
         __shared__ ProdStage<true> St[NG];
