@@ -124,6 +124,45 @@ struct ProdStage {
     double a[64];
 };
 
+// Fills a product stage: product p < tot of the nq staged A entries is
+// entry b0[j] + (p - off[j]) of B, with j the last entry whose off[j] <= p
+// (off ascending from 0), scaled by a[j].  Each lane locates four of its
+// products (a fixed six-step search) before issuing their loads together.
+template <bool VALUES>
+__device__ inline void stage_products(int lane, int nq, int32_t tot, const int32_t *off, const int32_t *b0,
+                                      const double *a, const int32_t *__restrict__ bci,
+                                      const double *__restrict__ bv, int32_t *sc, double *sv) {
+#pragma clang fp contract(off)
+    for (int32_t p0 = lane; p0 < tot; p0 += 4 * 64) {
+        int32_t e[4], j4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t p = p0 + u * 64;
+            int lo = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+                if (lo + step < nq && off[lo + step] <= p) lo += step;
+            j4[u] = lo;
+            e[u] = p < tot ? b0[lo] + (p - off[lo]) : -1;
+        }
+        int32_t c[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = e[u] >= 0 ? bci[e[u]] : 0;
+            v[u] = VALUES && e[u] >= 0 ? bv[e[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t p = p0 + u * 64;
+            if (p < tot) {
+                sc[p] = c[u];
+                if (VALUES) sv[p] = a[j4[u]] * v[u];
+            }
+        }
+    }
+}
+
 template <bool ORDERED, bool VALUES, class F>
 __device__ inline void for_products_staged(int32_t row, const int32_t *__restrict__ arp,
                                            const int32_t *__restrict__ aci, const double *__restrict__ av,
@@ -164,17 +203,7 @@ __device__ inline void for_products_staged(int32_t row, const int32_t *__restric
         const int32_t tot = __shfl(x, nq - 1, 64);
         if (lane == 0) S.off[nq] = tot;
         wave_sync();
-        for (int32_t p = lane; p < tot; p += 64) {
-            int lo = 0, hi = nq - 1;   // the last entry j with off[j] <= p
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (S.off[mid] <= p) lo = mid;
-                else hi = mid - 1;
-            }
-            const int32_t e = S.b0[lo] + (p - S.off[lo]);
-            S.c[p] = bci[e];
-            if (VALUES) S.v[p] = S.a[lo] * bv[e];
-        }
+        stage_products<VALUES>(lane, nq, tot, S.off, S.b0, S.a, bci, bv, S.c, S.v);
         wave_sync();
         if (ORDERED) {
             for (int j = 0; j < nq; ++j) {
@@ -635,18 +664,7 @@ __global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *
         const int32_t tot = __shfl(x, nq - 1, 64);
         if (lane == 0) qoff[nq] = tot;
         wave_sync();
-        // product p belongs to the last entry j with qoff[j] <= p
-        for (int32_t p = lane; p < tot; p += 64) {
-            int lo = 0, hi = nq - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (qoff[mid] <= p) lo = mid;
-                else hi = mid - 1;
-            }
-            const int32_t e = qb0[lo] + (p - qoff[lo]);
-            sc[p] = bci[e];
-            if (NUMERIC) sv[p] = qa[lo] * bv[e];
-        }
+        stage_products<NUMERIC>(lane, nq, tot, qoff, qb0, qa, bci, bv, sc, sv);
         wave_sync();
         if (NUMERIC) {
             for (int j = 0; j < nq; ++j) {
