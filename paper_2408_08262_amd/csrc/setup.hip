@@ -380,19 +380,25 @@ __global__ void k_rp_count(int32_t nC, const int32_t *__restrict__ niperm, const
     int32_t r = niperm ? niperm[q] : q;
     cnt[q] = zrp[r + 1] - zrp[r] + 1;
 }
-__global__ void k_rp_fill(int32_t nC, int32_t nF, const int32_t *__restrict__ niperm, const int32_t *__restrict__ zrp,
-                          const int32_t *__restrict__ zci, const double *__restrict__ zv,
-                          const int32_t *__restrict__ orp, int32_t *__restrict__ oci, double *__restrict__ ov) {
-    int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+template <int G>
+__global__ void __launch_bounds__(256) k_rp_fill(int32_t nC, int32_t nF, const int32_t *__restrict__ niperm,
+                                                 const int32_t *__restrict__ zrp, const int32_t *__restrict__ zci,
+                                                 const double *__restrict__ zv, const int32_t *__restrict__ orp,
+                                                 int32_t *__restrict__ oci, double *__restrict__ ov) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t q = (int32_t)(t / G);
+    const int lane = group_lane<G>();
     if (q >= nC) return;
-    int32_t r = niperm ? niperm[q] : q;
-    int32_t w = orp[q];
-    for (int32_t k = zrp[r]; k < zrp[r + 1]; ++k, ++w) {
-        oci[w] = zci[k];
-        ov[w] = zv[k];
+    const int32_t r = niperm ? niperm[q] : q;
+    const int32_t b = zrp[r], e = zrp[r + 1], w = orp[q];
+    for (int32_t k = b + lane; k < e; k += G) {
+        oci[w + (k - b)] = zci[k];
+        ov[w + (k - b)] = zv[k];
     }
-    oci[w] = nF + r;
-    ov[w] = 1.0;
+    if (lane == 0) {
+        oci[w + (e - b)] = nF + r;
+        ov[w + (e - b)] = 1.0;
+    }
 }
 
 // [W; I] in level order: row p < nF is W's row p, row nF + r is e_r; coarse
@@ -438,7 +444,10 @@ Csr build_rp_begin(const Csr &Z, int32_t nC, int32_t ncols, const int32_t *niper
 void build_rp_fill(Csr &R, const Csr &Z, int32_t nF, const int32_t *niperm, hipStream_t s) {
     int32_t nC = R.nr;
     if (nC == 0) return;
-    k_rp_fill<<<grid_for(nC, 256), 256, 0, s>>>(nC, nF, niperm, Z.rp.p, Z.ci.p, Z.v.p, R.rp.p, R.ci.p, R.v.p);
+    dispatch_group(lanes_for(Z.nnz, nC), [&]<int G>() {
+        k_rp_fill<G><<<grid_for((int64_t)nC * G, 256), 256, 0, s>>>(nC, nF, niperm, Z.rp.p, Z.ci.p, Z.v.p, R.rp.p,
+                                                                     R.ci.p, R.v.p);
+    });
     AIRG_LAUNCH_CHECK();
 }
 

@@ -181,30 +181,38 @@ __global__ void k_r_rowptr(int32_t nC, const int32_t *__restrict__ zrp, int32_t 
     if (r <= nC) rrp[r] = zrp[r] + r;
 }
 
-__global__ void k_r_fill(int32_t nC, const int32_t *__restrict__ zrp, const int32_t *__restrict__ zci,
-                         const double *__restrict__ zv, const int32_t *__restrict__ fidx,
-                         const int32_t *__restrict__ cidx, const int32_t *__restrict__ rrp,
-                         int32_t *__restrict__ rci, double *__restrict__ rv) {
-    int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+// R row r = Z row r with columns mapped to level numbering by fidx (ascending,
+// since fidx is) and the entry (cidx[r], 1) in its sorted place.  A G-lane
+// group per row: an entry goes to its own offset, one further when its
+// column passes cidx[r]; the identity goes after the entries below it.
+template <int G>
+__global__ void __launch_bounds__(256) k_r_fill(int32_t nC, const int32_t *__restrict__ zrp,
+                                                const int32_t *__restrict__ zci, const double *__restrict__ zv,
+                                                const int32_t *__restrict__ fidx, const int32_t *__restrict__ cidx,
+                                                const int32_t *__restrict__ rrp, int32_t *__restrict__ rci,
+                                                double *__restrict__ rv) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t r = (int32_t)(t / G);
+    const int lane = group_lane<G>();
     if (r >= nC) return;
-    int32_t w = rrp[r];
-    int32_t me = cidx[r];
-    bool placed = false;
-    for (int32_t k = zrp[r]; k < zrp[r + 1]; ++k) {
-        int32_t g = fidx[zci[k]];
-        if (!placed && g > me) {
-            rci[w] = me;
-            rv[w] = 1.0;
-            ++w;
-            placed = true;
+    const int32_t me = cidx[r];
+    const int32_t b = zrp[r], e = zrp[r + 1];
+    const int32_t w0 = rrp[r];
+    int32_t below = 0;
+    for (int32_t base = b; base < e; base += G) {
+        const int32_t k = base + lane;
+        const bool in = k < e;
+        const int32_t g = in ? fidx[zci[k]] : 0;
+        below += __popcll(group_ballot<G>(in && g < me));
+        if (in) {
+            const int32_t pos = w0 + (k - b) + (g > me ? 1 : 0);
+            rci[pos] = g;
+            rv[pos] = zv[k];
         }
-        rci[w] = g;
-        rv[w] = zv[k];
-        ++w;
     }
-    if (!placed) {
-        rci[w] = me;
-        rv[w] = 1.0;
+    if (lane == 0) {
+        rci[w0 + below] = me;
+        rv[w0 + below] = 1.0;
     }
 }
 
@@ -219,7 +227,10 @@ Csr restriction_full(const CsrView &Z, const int32_t *fidx, const int32_t *cidx,
     k_r_rowptr<<<grid_for((int64_t)Z.nr + 1, 256), 256, 0, s>>>(Z.nr, Z.rp, R.rp.p);
     AIRG_LAUNCH_CHECK();
     if (Z.nr > 0) {
-        k_r_fill<<<grid_for(Z.nr, 256), 256, 0, s>>>(Z.nr, Z.rp, Z.ci, Z.v, fidx, cidx, R.rp.p, R.ci.p, R.v.p);
+        dispatch_group(lanes_for(Z.nnz, Z.nr), [&]<int G>() {
+            k_r_fill<G><<<grid_for((int64_t)Z.nr * G, 256), 256, 0, s>>>(Z.nr, Z.rp, Z.ci, Z.v, fidx, cidx, R.rp.p,
+                                                                         R.ci.p, R.v.p);
+        });
         AIRG_LAUNCH_CHECK();
     }
     return R;
