@@ -15,18 +15,25 @@ namespace airg {
 // ------------------------------------------------------------ validation --
 enum : uint32_t { BAD_COL = 1, NO_DIAG = 2, ZERO_DIAG = 4, NONFINITE = 8, BAD_RP = 16 };
 
-__global__ void k_validate(int32_t n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                           const double *__restrict__ v, int32_t *__restrict__ keep, uint32_t *__restrict__ flags) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// One G-lane group per row: every lane checks its entries; the kept count
+// and the diagonal's presence are combined over the group.
+template <int G>
+__global__ void __launch_bounds__(256) k_validate(int32_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  int32_t *__restrict__ keep, uint32_t *__restrict__ flags) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(t / G);
+    const int lane = group_lane<G>();
     if (i >= n) return;
     uint32_t f = 0;
-    int32_t b = rp[i], e = rp[i + 1];
+    const int32_t b = rp[i], e = rp[i + 1];
+    const bool bad_rp = e < b || b < 0 || (int64_t)e > nnz;
     int32_t cnt = 0;
     bool diag = false;
-    if (e < b || b < 0 || (int64_t)e > nnz) {
+    if (bad_rp) {
         f |= BAD_RP;
     } else {
-        for (int32_t k = b; k < e; ++k) {
+        for (int32_t k = b + lane; k < e; k += G) {
             int32_t j = ci[k];
             double a = v[k];
             if (j < 0 || j >= n || (k > b && j <= ci[k - 1])) f |= BAD_COL;
@@ -37,9 +44,13 @@ __global__ void k_validate(int32_t n, int64_t nnz, const int32_t *__restrict__ r
             }
             cnt += (j == i || a != 0.0);
         }
-        if (!diag) f |= NO_DIAG;
     }
-    keep[i] = cnt;
+    cnt = group_sum<G>(cnt);
+    diag = group_any<G>(diag);
+    if (lane == 0) {
+        keep[i] = cnt;
+        if (!bad_rp && !diag) f |= NO_DIAG;
+    }
     if (f) atomicOr(flags, f);
 }
 
@@ -67,7 +78,9 @@ Csr canonical_copy(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
     DBuf<int32_t> keep((size_t)n, s);
     DBuf<uint32_t> flags(1, s);
     fill_zero(flags.p, 4, s);
-    k_validate<<<grid_for(n, 256), 256, 0, s>>>(n, nnz, rp, ci, v, keep.p, flags.p);
+    dispatch_group(lanes_for(nnz, n), [&]<int G>() {
+        k_validate<G><<<grid_for((int64_t)n * G, 256), 256, 0, s>>>(n, nnz, rp, ci, v, keep.p, flags.p);
+    });
     AIRG_LAUNCH_CHECK();
     Csr A;
     A.nr = A.nc = n;

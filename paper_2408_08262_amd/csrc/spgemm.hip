@@ -219,15 +219,24 @@ __device__ inline void for_products_staged(int32_t row, const int32_t *__restric
     }
 }
 
-__global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
-                            const int32_t *__restrict__ brp, int32_t *__restrict__ ub, int8_t *__restrict__ bin) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// ub_i = sum over the A row of |B_k| by a G-lane group per row, and the
+// row's symbolic bin.
+template <int G>
+__global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp,
+                                                   const int32_t *__restrict__ aci,
+                                                   const int32_t *__restrict__ brp, int32_t *__restrict__ ub,
+                                                   int8_t *__restrict__ bin) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(t / G);
+    const int lane = group_lane<G>();
     if (i >= m) return;
     int64_t u = 0;
-    for (int32_t k = arp[i]; k < arp[i + 1]; ++k) {
+    for (int32_t k = arp[i] + lane; k < arp[i + 1]; k += G) {
         int32_t j = aci[k];
         u += brp[j + 1] - brp[j];
     }
+    u = group_sum<G>(u);
+    if (lane != 0) return;
     int32_t uc = u > 0x7fffffff ? 0x7fffffff : (int32_t)u;
     ub[i] = uc;
     bin[i] = uc == 0                            ? SB_EMPTY
@@ -911,7 +920,9 @@ SpgemmPlan spgemm_begin(const CsrView &A, const int32_t *b_rp, int32_t b_nc, hip
     P.ub.alloc((size_t)m + 1, s);
     P.sbin.alloc((size_t)m + 1, s);
     if (m > 0) {
-        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, A.rp, A.ci, b_rp, P.ub.p, P.sbin.p);
+        dispatch_group(lanes_for(A.nnz, m), [&]<int G>() {
+            k_spgemm_ub<G><<<grid_for((int64_t)m * G, 256), 256, 0, s>>>(m, A.rp, A.ci, b_rp, P.ub.p, P.sbin.p);
+        });
         AIRG_LAUNCH_CHECK();
     }
     P.bins = bin_rows_begin(P.sbin.p, m, SB_N, s);
