@@ -37,29 +37,39 @@ __global__ void __launch_bounds__(256) k_strength(int32_t n, const int32_t *__re
     if (lane == 0) cntS[row] = c;
 }
 
-// Per strong entry (i, j): count it for S^T_j, and find whether i in S_j
-// (binary search of column i in row j) to count mutual pairs.
+// Per strong entry (i, j): write it to row i of S's own CSR, count it for
+// S^T_j, and find whether i in S_j (binary search of column i in row j) to
+// count mutual pairs.
 template <int G>
 __global__ void __launch_bounds__(256) k_strength_mutual(int32_t n, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
                                                          const uint8_t *__restrict__ strong,
+                                                         const int32_t *__restrict__ srp, int32_t *__restrict__ sci,
                                                          int32_t *__restrict__ cntT, int32_t *__restrict__ mutual) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
     if (row >= n) return;
     int32_t mu = 0;
-    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
-        if (!strong[k]) continue;
-        int32_t j = ci[k];
-        atomicAdd(&cntT[j], 1);
-        int32_t lo = rp[j], hi = rp[j + 1];
-        while (lo < hi) {
-            int32_t mid = (lo + hi) >> 1;
-            if (ci[mid] < row) lo = mid + 1;
-            else hi = mid;
+    const int32_t b = rp[row], e = rp[row + 1];
+    int32_t w = srp[row];
+    for (int32_t base = b; base < e; base += G) {
+        const int32_t k = base + lane;
+        const bool st = k < e && strong[k];
+        const uint64_t m = group_ballot<G>(st);
+        if (st) {
+            const int32_t j = ci[k];
+            sci[w + __popcll(m & ((1ull << lane) - 1ull))] = j;
+            atomicAdd(&cntT[j], 1);
+            int32_t lo = rp[j], hi = rp[j + 1];
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (ci[mid] < row) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < rp[j + 1] && ci[lo] == row && strong[lo]) ++mu;
         }
-        if (lo < rp[j + 1] && ci[lo] == row && strong[lo]) ++mu;
+        w += __popcll(m);
     }
     mu = group_sum<G>(mu);
     if (lane == 0) mutual[row] = mu;
@@ -77,13 +87,19 @@ StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
     G.n = n;
     G.strong.alloc((size_t)A.nnz, s);
     G.deg.alloc((size_t)n, s);
+    G.srp.alloc((size_t)n + 1, s);
+    G.sci.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);   // S's size is not read back: room for all of A
     DBuf<int32_t> cntS((size_t)n, s), cntT((size_t)n, s), mutual((size_t)n, s);
     fill_zero(cntT.p, (size_t)n * 4, s);
     int g = lanes_for(A.nnz, n);
+    const unsigned grid = grid_for((int64_t)n * g, 256);
     dispatch_group(g, [&]<int W>() {
-        unsigned grid = grid_for((int64_t)n * W, 256);
         k_strength<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, A.v, alpha, G.strong.p, cntS.p);
-        k_strength_mutual<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, cntT.p, mutual.p);
+    });
+    AIRG_LAUNCH_CHECK();
+    exclusive_scan(cntS.p, G.srp.p, n, s, false);
+    dispatch_group(g, [&]<int W>() {
+        k_strength_mutual<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.srp.p, G.sci.p, cntT.p, mutual.p);
     });
     AIRG_LAUNCH_CHECK();
     k_degree<<<grid_for(n, 256), 256, 0, s>>>(n, cntS.p, cntT.p, mutual.p, G.deg.p);
@@ -163,7 +179,6 @@ __device__ inline bool beats(uint64_t kj, int32_t j, uint64_t ki, int32_t i) {
 template <int G>
 __global__ void __launch_bounds__(256) k_pmisr_push(int32_t n, const int32_t *__restrict__ rp,
                                                     const int32_t *__restrict__ ci,
-                                                    const uint8_t *__restrict__ strong,
                                                     const uint64_t *__restrict__ key, uint8_t *__restrict__ beaten) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
@@ -171,18 +186,16 @@ __global__ void __launch_bounds__(256) k_pmisr_push(int32_t n, const int32_t *__
     if (row >= n) return;
     const uint64_t kj = key[row];
     if (kj == kAssigned) return;
-    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G)
-        if (strong[k]) {
-            const int32_t i = ci[k];
-            if (beats(kj, row, key[i], i)) beaten[i] = 1;
-        }
+    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
+        const int32_t i = ci[k];
+        if (beats(kj, row, key[i], i)) beaten[i] = 1;
+    }
 }
 
 // Selection: inD[i] for every node; a node of D pushes markC along its row.
 template <int G>
 __global__ void __launch_bounds__(256) k_pmisr_select(int32_t n, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci,
-                                                      const uint8_t *__restrict__ strong,
                                                       const uint64_t *__restrict__ key,
                                                       uint8_t *__restrict__ beaten, uint8_t *__restrict__ inD,
                                                       uint8_t *__restrict__ markC, int32_t *__restrict__ nu) {
@@ -201,7 +214,7 @@ __global__ void __launch_bounds__(256) k_pmisr_select(int32_t n, const int32_t *
     for (int32_t base = b; base < e && !lost; base += G) {
         int32_t k = base + lane;
         bool lose = false;
-        if (k < e && strong[k]) {
+        if (k < e) {
             int32_t j = ci[k];
             lose = beats(key[j], j, ki, row);
         }
@@ -212,8 +225,7 @@ __global__ void __launch_bounds__(256) k_pmisr_select(int32_t n, const int32_t *
         inD[row] = !lost;
     }
     if (!lost)
-        for (int32_t k = b + lane; k < e; k += G)
-            if (strong[k]) markC[ci[k]] = 1;
+        for (int32_t k = b + lane; k < e; k += G) markC[ci[k]] = 1;
 }
 
 // Update: D joins F; an unassigned node with a neighbour in D joins C; a node
@@ -221,7 +233,6 @@ __global__ void __launch_bounds__(256) k_pmisr_select(int32_t n, const int32_t *
 template <int G>
 __global__ void __launch_bounds__(256) k_pmisr_update(int32_t n, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci,
-                                                      const uint8_t *__restrict__ strong,
                                                       const uint8_t *__restrict__ inD, int8_t *__restrict__ cf,
                                                       uint64_t *__restrict__ key, uint8_t *__restrict__ markC,
                                                       uint8_t *__restrict__ beaten) {
@@ -242,7 +253,7 @@ __global__ void __launch_bounds__(256) k_pmisr_update(int32_t n, const int32_t *
     const int32_t b = rp[row], e = rp[row + 1];
     for (int32_t base = b; base < e && !hit; base += G) {
         int32_t k = base + lane;
-        bool p = k < e && strong[k] && inD[ci[k]];
+        bool p = k < e && inD[ci[k]];
         hit = group_any<G>(p);
     }
     if (hit) {
@@ -255,11 +266,10 @@ __global__ void __launch_bounds__(256) k_pmisr_update(int32_t n, const int32_t *
     }
     // a neighbour assigned in this same pass may be pushed to: its flag is
     // never read again
-    for (int32_t k = b + lane; k < e; k += G)
-        if (strong[k]) {
-            const int32_t i = ci[k];
-            if (beats(kx, row, key[i], i)) beaten[i] = 1;
-        }
+    for (int32_t k = b + lane; k < e; k += G) {
+        const int32_t i = ci[k];
+        if (beats(kx, row, key[i], i)) beaten[i] = 1;
+    }
 }
 
 __global__ void k_pmisr_finish(int32_t n, int8_t *__restrict__ cf, int32_t *__restrict__ nu) {
@@ -291,10 +301,10 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
     fill_zero(flags.p, (size_t)2 * n, s);
     k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, h, cf, key.p);
     AIRG_LAUNCH_CHECK();
-    int g = lanes_for(A.nnz, n);
+    int g = lanes_for(A.nnz / 2, n);   // rows of S: about half of A's entries
     const unsigned grid = grid_for((int64_t)n * g, 256);
     dispatch_group(g, [&]<int W>() {
-        k_pmisr_push<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, key.p, beaten);
+        k_pmisr_push<W><<<grid, 256, 0, s>>>(n, G.srp.p, G.sci.p, key.p, beaten);
     });
     AIRG_LAUNCH_CHECK();
     int rounds = 0;
@@ -303,8 +313,8 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
         AIRG_REQUIRE(rounds < kPmisrSlots, ST_STALL, "PMISR did not finish");
         int32_t *cnt = until_done ? nu.p + rounds : nullptr;
         dispatch_group(g, [&]<int W>() {
-            k_pmisr_select<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, key.p, beaten, inD.p, markC, cnt);
-            k_pmisr_update<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, inD.p, cf, key.p, markC, beaten);
+            k_pmisr_select<W><<<grid, 256, 0, s>>>(n, G.srp.p, G.sci.p, key.p, beaten, inD.p, markC, cnt);
+            k_pmisr_update<W><<<grid, 256, 0, s>>>(n, G.srp.p, G.sci.p, inD.p, cf, key.p, markC, beaten);
         });
         AIRG_LAUNCH_CHECK();
         ++rounds;

@@ -9,6 +9,7 @@ namespace airg {
 struct StrengthGraph {
     int32_t n = 0;
     DBuf<uint8_t> strong;       // per nonzero of A: 1 if j in S_i
+    DBuf<int32_t> srp, sci;     // S as its own CSR (columns ascending), room for nnz(A) columns
     DBuf<int32_t> deg;          // |S_i u S_i^T|
 };
 
