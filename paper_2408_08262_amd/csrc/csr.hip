@@ -1175,6 +1175,7 @@ static void with_nbins(int nbins, F &&f) {
     case 6: f.template operator()<6>(); break;
     case 8: f.template operator()<8>(); break;
     case 9: f.template operator()<9>(); break;
+    case 10: f.template operator()<10>(); break;
     default: throw Error(ST_INVALID_ARG, "unsupported number of bins");
     }
 }

@@ -42,9 +42,9 @@ __device__ inline uint32_t hash_insert(int32_t *keys, uint32_t mask, int32_t c, 
 }
 
 // Symbolic bins by ub.
-enum : int8_t { SB_EMPTY = 0, SB_G4, SB_G8, SB_G16, SB_G32, SB_G64, SB_BLOCK, SB_GLOBAL, SB_N };
+enum : int8_t { SB_EMPTY = 0, SB_G4, SB_G8, SB_G16, SB_G32, SB_G64S, SB_G64, SB_BLOCK, SB_GLOBAL, SB_N };
 // Numeric bins by the exact row length.
-enum : int8_t { NB_EMPTY = 0, NB_G4, NB_G8, NB_G16S, NB_G16, NB_G64, NB_BLOCK4K, NB_BLOCK8K, NB_GLOBAL, NB_N };
+enum : int8_t { NB_EMPTY = 0, NB_G4, NB_G8, NB_G16S, NB_G16, NB_G64S, NB_G64, NB_BLOCK4K, NB_BLOCK8K, NB_GLOBAL, NB_N };
 
 // Visits the products of row `row` of A with B: for each A entry in
 // ascending order, f(column, a_ik * b_kj) on the lanes holding the entries of
@@ -244,6 +244,7 @@ __global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__r
              : uc <= 32                        ? SB_G8
              : uc <= 128                       ? SB_G16
              : uc <= 512                       ? SB_G32
+             : uc <= 1024                      ? SB_G64S
              : uc <= 2048                      ? SB_G64
              : uc <= 8192                      ? SB_BLOCK
                                                : SB_GLOBAL;
@@ -258,6 +259,7 @@ __global__ void k_spgemm_nbin(int32_t m, const int32_t *__restrict__ cnt, int8_t
               : c <= 32             ? NB_G8
               : c <= 64             ? NB_G16S
               : c <= 128            ? NB_G16
+              : c <= 256            ? NB_G64S
               : c <= 512            ? NB_G64
               : c <= 2048           ? NB_BLOCK4K
               : c <= 4096           ? NB_BLOCK8K
@@ -866,6 +868,7 @@ static void run_symbolic(const Bins &B, const CsrView &A, const CsrView &Bm, int
     grp(k_spgemm_count<8, 64, 256>, SB_G8, 32, 256);
     grp(k_spgemm_count<16, 256, 256>, SB_G16, 16, 256);
     grp(k_spgemm_count<32, 1024, 256>, SB_G32, 8, 256);
+    grp(k_spgemm_count<64, 2048, 128>, SB_G64S, 2, 128);
     grp(k_spgemm_count<64, 4096, 128>, SB_G64, 2, 128);
     if (B.count(SB_BLOCK))
         k_spgemm_block_lds<16384, false><<<(unsigned)B.count(SB_BLOCK), kBlk, 0, s>>>(
@@ -886,6 +889,7 @@ static void run_numeric(const Bins &B, const CsrView &A, const CsrView &Bm, int3
     grp(k_spgemm_fill<8, 64, 256>, NB_G8, 32, 256);
     grp(k_spgemm_fill<16, 128, 128>, NB_G16S, 8, 128);
     grp(k_spgemm_fill<16, 256, 128>, NB_G16, 8, 128);
+    grp(k_spgemm_fill<64, 512, 64>, NB_G64S, 1, 64);
     grp(k_spgemm_fill<64, 1024, 64>, NB_G64, 1, 64);
     if (B.count(NB_BLOCK4K))
         k_spgemm_block_lds<4096, true><<<(unsigned)B.count(NB_BLOCK4K), kBlk, 0, s>>>(
