@@ -42,7 +42,7 @@ __device__ inline uint32_t hash_insert(int32_t *keys, uint32_t mask, int32_t c, 
 }
 
 // Symbolic bins by ub.
-enum : int8_t { SB_EMPTY = 0, SB_G4, SB_G8, SB_G16, SB_G32, SB_G64S, SB_G64, SB_BLOCK, SB_GLOBAL, SB_N };
+enum : int8_t { SB_EMPTY = 0, SB_G4, SB_G8, SB_G16, SB_G32S, SB_G32, SB_G64S, SB_G64, SB_BLOCK, SB_GLOBAL, SB_N };
 // Numeric bins by the exact row length.
 enum : int8_t { NB_EMPTY = 0, NB_G4, NB_G8, NB_G16S, NB_G16, NB_G64S, NB_G64, NB_BLOCK4K, NB_BLOCK8K, NB_GLOBAL, NB_N };
 
@@ -243,6 +243,7 @@ __global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__r
              : uc <= 8                         ? SB_G4
              : uc <= 32                        ? SB_G8
              : uc <= 128                       ? SB_G16
+             : uc <= 256                       ? SB_G32S
              : uc <= 512                       ? SB_G32
              : uc <= 1024                      ? SB_G64S
              : uc <= 2048                      ? SB_G64
@@ -867,6 +868,7 @@ static void run_symbolic(const Bins &B, const CsrView &A, const CsrView &Bm, int
     grp(k_spgemm_count<4, 16, 256>, SB_G4, 64, 256);
     grp(k_spgemm_count<8, 64, 256>, SB_G8, 32, 256);
     grp(k_spgemm_count<16, 256, 256>, SB_G16, 16, 256);
+    grp(k_spgemm_count<32, 512, 256>, SB_G32S, 8, 256);
     grp(k_spgemm_count<32, 1024, 256>, SB_G32, 8, 256);
     grp(k_spgemm_count<64, 2048, 128>, SB_G64S, 2, 128);
     grp(k_spgemm_count<64, 4096, 128>, SB_G64, 2, 128);
