@@ -923,6 +923,28 @@ void cast_f2d(const float *x, double *y, int64_t n, hipStream_t s) {
     k_f2d<<<grid_for(n, 256), 256, 0, s>>>(x, y, n);
     AIRG_LAUNCH_CHECK();
 }
+// y[i] = (float) x[idx[i]] and y[idx[i]] = (double) x[i]: the casts into and
+// out of a level-ordered FP32 cycle from natural-order FP64 vectors.
+__global__ void k_gather_d2f(const double *__restrict__ x, const int32_t *__restrict__ idx, float *__restrict__ y,
+                             int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[idx[i]];
+}
+__global__ void k_scatter_f2d(const float *__restrict__ x, const int32_t *__restrict__ idx, double *__restrict__ y,
+                              int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[idx[i]] = (double)x[i];
+}
+void gather_d2f(const double *x, const int32_t *idx, float *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather_d2f<<<grid_for(n, 256), 256, 0, s>>>(x, idx, y, n);
+    AIRG_LAUNCH_CHECK();
+}
+void scatter_f2d(const float *x, const int32_t *idx, double *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_scatter_f2d<<<grid_for(n, 256), 256, 0, s>>>(x, idx, y, n);
+    AIRG_LAUNCH_CHECK();
+}
 void make_f32(Csr &A, hipStream_t s) {
     A.vf.alloc((size_t)A.nnz, s);
     cast_d2f(A.v.p, A.vf.p, A.nnz, s);

@@ -94,6 +94,8 @@ void gemv_sub(const double *V, int64_t ldv, int nvec, const double *h_dev, doubl
 void gemv_add(const double *V, int64_t ldv, int nvec, const double *h_dev, double *x, int64_t n, hipStream_t s);
 void cast_d2f(const double *x, float *y, int64_t n, hipStream_t s);
 void cast_f2d(const float *x, double *y, int64_t n, hipStream_t s);
+void gather_d2f(const double *x, const int32_t *idx, float *y, int64_t n, hipStream_t s);   // y[i] = x[idx[i]]
+void scatter_f2d(const float *x, const int32_t *idx, double *y, int64_t n, hipStream_t s);  // y[idx[i]] = x[i]
 void gather(const double *x, const int32_t *idx, double *y, int64_t n, hipStream_t s);   // y[i] = x[idx[i]]
 void scatter(const double *x, const int32_t *idx, double *y, int64_t n, hipStream_t s);  // y[idx[i]] = x[i]
 void gather_k(const double *x, const int32_t *idx, double *y, int64_t n, int k, int64_t ldx, int64_t ldy,

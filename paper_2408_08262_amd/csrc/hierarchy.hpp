@@ -49,8 +49,6 @@ struct Hier {
     uint64_t seed = 0;
     hipStream_t s = nullptr;
     std::vector<std::unique_ptr<Level>> lv;
-    Csr A0p;                      // top operator in level-0 order (residuals)
-    bool top_permuted = false;
     double setup_seconds = 0.0;
     double resetup_seconds = 0.0;
     double phase[AIRG_PHASE_COUNT] = {};

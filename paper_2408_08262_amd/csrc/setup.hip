@@ -547,11 +547,6 @@ void finalize(Hier &H, int built = 0) {
     std::vector<Csr *> pending;
     for (int l = built; l < nl; ++l)
         if (!H.L(l).coarsest) solve_ops_begin(H, l, pending, s);
-    Level &T = H.L(0);
-    if (!T.coarsest) {
-        H.A0p = permute_fc_begin(view(T.A), T.iperm.p, T.n, s);
-        pending.push_back(&H.A0p);
-    }
     resolve_sizes(pending, s);
     for (int l = built; l < nl; ++l) {
         Level &L = H.L(l);
@@ -561,12 +556,6 @@ void finalize(Hier &H, int built = 0) {
             continue;
         }
         solve_ops_fill(H, l, s);
-    }
-    if (T.coarsest) {
-        H.top_permuted = false;
-    } else {
-        permute_fc_fill(H.A0p, view(T.A), T.iperm.p, T.cf.p, T.rank.p, T.nF, s);
-        H.top_permuted = true;
     }
     // work vectors
     for (int l = 0; l < nl; ++l) {
@@ -582,7 +571,7 @@ void finalize(Hier &H, int built = 0) {
             for (DBuf<float> *b : {&L.p32, &L.q32, &L.u32}) b->alloc((size_t)L.n, s);
         }
     }
-    int32_t n0 = T.n;
+    int32_t n0 = H.L(0).n;
     H.x.alloc((size_t)n0, s);
     H.r.alloc((size_t)n0, s);
     H.e.alloc((size_t)n0, s);

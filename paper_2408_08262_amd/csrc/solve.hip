@@ -204,48 +204,39 @@ void run_captured(Hier &H, int k, F &&f) {
 }
 }  // namespace
 
-// With use_graph the cycle runs between fixed buffers (level 0's g and e for
-// FP64, r32/e32 for FP32) so that one captured graph serves every call.
+// The outer iterations keep their vectors in natural order and apply the
+// top operator as stored; the cycle runs in level order (F points first)
+// between fixed buffers (level 0's g and e for FP64, r32/e32 for FP32), which
+// the casts in and out permute.  With use_graph one captured graph serves
+// every call.
 void Hier::precondition(const double *rv, double *ev, int precision) {
-    int64_t n0 = L(0).n;
+    Level &T = L(0);
+    const int64_t n0 = T.n;
+    const int32_t *ip = T.coarsest ? nullptr : T.iperm.p;   // level position -> natural index
     const bool graphed = opt.use_graph != 0;
     if (precision == 32) {
-        cast_d2f(rv, r32.p, n0, s);
+        if (ip) gather_d2f(rv, ip, r32.p, n0, s);
+        else cast_d2f(rv, r32.p, n0, s);
         if (graphed) run_captured(*this, 1, [&] { vcycle<float>(0, r32.p, e32.p); });
         else vcycle<float>(0, r32.p, e32.p);
-        cast_f2d(e32.p, ev, n0, s);
-    } else if (graphed) {
-        Level &T = L(0);
-        d2d(T.g64.p, rv, (size_t)n0, s);
-        run_captured(*this, 0, [&] { vcycle<double>(0, T.g64.p, T.e64.p); });
-        d2d(ev, T.e64.p, (size_t)n0, s);
-    } else {
-        vcycle<double>(0, rv, ev);
+        if (ip) scatter_f2d(e32.p, ip, ev, n0, s);
+        else cast_f2d(e32.p, ev, n0, s);
+        return;
     }
+    if (ip) gather(rv, ip, T.g64.p, n0, s);
+    else d2d(T.g64.p, rv, (size_t)n0, s);
+    if (graphed) run_captured(*this, 0, [&] { vcycle<double>(0, T.g64.p, T.e64.p); });
+    else vcycle<double>(0, T.g64.p, T.e64.p);
+    if (ip) scatter(T.e64.p, ip, ev, n0, s);
+    else d2d(ev, T.e64.p, (size_t)n0, s);
 }
 
 namespace {
-CsrView top_view(Hier &H) { return H.top_permuted ? view(H.A0p) : view(H.L(0).A); }
-
-void to_level_order(Hier &H, const double *b, double *bp) {
-    int64_t n = H.L(0).n;
-    if (H.top_permuted) scatter(b, H.L(0).perm.p, bp, n, H.s);
-    else d2d(bp, b, (size_t)n, H.s);
-}
-void to_natural_order(Hier &H, const double *xp, double *x) {
-    int64_t n = H.L(0).n;
-    if (H.top_permuted) gather(xp, H.L(0).perm.p, x, n, H.s);
-    else d2d(x, xp, (size_t)n, H.s);
-}
+CsrView top_view(Hier &H) { return view(H.L(0).A); }
+void copy_vec(Hier &H, const double *src, double *dst) { d2d(dst, src, (size_t)H.L(0).n, H.s); }
 }  // namespace
 
-void apply_vcycle(Hier &H, const double *g, double *e, int precision) {
-    int64_t n = H.L(0).n;
-    DBuf<double> gp((size_t)n, H.s), ep((size_t)n, H.s);
-    to_level_order(H, g, gp.p);
-    H.precondition(gp.p, ep.p, precision);
-    to_natural_order(H, ep.p, e);
-}
+void apply_vcycle(Hier &H, const double *g, double *e, int precision) { H.precondition(g, e, precision); }
 
 // Undamped Richardson from a zero guess: x += V(b - A x) until
 // ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual every iteration).
@@ -254,11 +245,11 @@ SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, i
     int64_t n = H.L(0).n;
     SolveResult res;
     CsrView A = top_view(H);
-    to_level_order(H, b, H.bp.p);
+    copy_vec(H, b, H.bp.p);
     fill_zero(H.x.p, (size_t)n * 8, s);
     double nb = nrm2(H.bp.p, n, s);
     if (nb == 0.0) {
-        to_natural_order(H, H.x.p, x);
+        copy_vec(H, H.x.p, x);
         res.converged = true;
         return res;
     }
@@ -273,7 +264,7 @@ SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, i
         res.iterations++;
         AIRG_REQUIRE(std::isfinite(rr), ST_STALL, "residual became non-finite in the Richardson iteration");
     }
-    to_natural_order(H, H.x.p, x);
+    copy_vec(H, H.x.p, x);
     res.rel_residual = rr / nb;
     res.converged = rr <= rtol * nb;
     return res;
@@ -292,11 +283,11 @@ SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int m
     CsrView A = top_view(H);
     DBuf<double> V((size_t)n * (m + 1), s), Zb((size_t)n * m, s), hd((size_t)m + 1, s);
     DBuf<double> hdev((size_t)2 * (m + 1) + 1, s);   // [h1 (m+1) | h2 (m+1) | ||w||^2]
-    to_level_order(H, b, H.bp.p);
+    copy_vec(H, b, H.bp.p);
     fill_zero(H.x.p, (size_t)n * 8, s);
     double nb = nrm2(H.bp.p, n, s);
     if (nb == 0.0) {
-        to_natural_order(H, H.x.p, x);
+        copy_vec(H, H.x.p, x);
         res.converged = true;
         return res;
     }
@@ -360,7 +351,7 @@ SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int m
         beta = nrm2(H.r.p, n, s);
         AIRG_REQUIRE(std::isfinite(beta), ST_STALL, "residual became non-finite in FGMRES");
     }
-    to_natural_order(H, H.x.p, x);
+    copy_vec(H, H.x.p, x);
     res.rel_residual = beta / nb;
     res.converged = beta <= rtol * nb;
     return res;
