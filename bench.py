@@ -68,8 +68,8 @@ def top_kernel(workload):
 
 def kernel_digest(workload="dg_square_512"):
     """Digest of the source text that defines the timed roofline kernel: the stream SpMV (or, for the
-    batch, the persistent stream SpMM and its grid), its constants and the XCD tile order.  Stored
-    counter readings count only while it is unchanged."""
+    batch, the persistent stream SpMM and its grid), its constants, the XCD tile order and the choice of
+    the finest operator's ordering.  Stored counter readings count only while it is unchanged."""
     import hashlib
     import re
     csr = open(os.path.join(ROOT, "paper_2408_08262_amd", "csrc", "csr.hip")).read()
@@ -84,6 +84,10 @@ def kernel_digest(workload="dg_square_512"):
     parts += re.findall(r"constexpr int\w* kStream\w+ = [^;]+;", csr)
     k = com.index("constexpr int kXcds")
     parts.append(com[k:com.index("\n}\n", com.index("xcd_grid", k))])
+    if workload != "batch48":
+        # which ordering of the finest operator the Arnoldi product runs on (the traffic depends on it)
+        sol = open(os.path.join(ROOT, "paper_2408_08262_amd", "csrc", "solve.hip")).read()
+        parts.append(sol[sol.index("CsrView top_view("):sol.index("\n", sol.index("CsrView top_view("))])
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
