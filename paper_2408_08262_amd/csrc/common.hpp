@@ -185,6 +185,11 @@ template <class T>
 inline void d2d(T *d, const T *src, size_t count, hipStream_t s) {
     copy_bytes(d, src, count * sizeof(T), s);
 }
+// Timing events of the current device, created once and reused: setups record
+// a few hundred per call, and creating and destroying them cost more host
+// time than the records.
+hipEvent_t pooled_event();
+void release_event(hipEvent_t e);
 void fill_zero(void *d, size_t bytes, hipStream_t s);
 void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s);
 

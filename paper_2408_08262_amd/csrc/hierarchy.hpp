@@ -85,21 +85,20 @@ struct PhaseTimer {
     explicit PhaseTimer(hipStream_t st) : s(st) {}
     ~PhaseTimer() {
         for (auto &t : spans) {
-            (void)hipEventDestroy(std::get<1>(t));
-            (void)hipEventDestroy(std::get<2>(t));
+            release_event(std::get<1>(t));
+            release_event(std::get<2>(t));
         }
-        if (start) (void)hipEventDestroy(start);
+        release_event(start);
     }
     void begin(int phase) {
         end();
-        AIRG_HIP(hipEventCreate(&start));
+        start = pooled_event();
         AIRG_HIP(hipEventRecord(start, s));
         cur = phase;
     }
     void end() {
         if (cur < 0) return;
-        hipEvent_t stop;
-        AIRG_HIP(hipEventCreate(&stop));
+        hipEvent_t stop = pooled_event();
         AIRG_HIP(hipEventRecord(stop, s));
         std::lock_guard<std::mutex> lk(mu);
         spans.emplace_back(cur, start, stop);
@@ -108,9 +107,7 @@ struct PhaseTimer {
     }
     template <class F>
     void span_on(int phase, hipStream_t st, F &&f) {
-        hipEvent_t a, b;
-        AIRG_HIP(hipEventCreate(&a));
-        AIRG_HIP(hipEventCreate(&b));
+        hipEvent_t a = pooled_event(), b = pooled_event();
         {
             std::lock_guard<std::mutex> lk(mu);
             spans.emplace_back(phase, a, b);

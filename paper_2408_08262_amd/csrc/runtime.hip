@@ -1,6 +1,7 @@
 // Runtime pieces of the AIRG library: the caching device allocator, fills,
 // and the device-wide exclusive scan used to build every CSR row pointer.
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <unordered_map>
 
@@ -138,6 +139,36 @@ void fill_i32(int32_t *d, int32_t value, size_t count, hipStream_t s) {
     unsigned g = (unsigned)std::min<size_t>((count + 255) / 256, 8192);
     k_fill_u32<<<g, 256, 0, s>>>((uint32_t *)d, (uint32_t)value, count);
     AIRG_LAUNCH_CHECK();
+}
+
+namespace {
+std::mutex g_event_mu;
+std::map<int, std::vector<hipEvent_t>> g_events;   // per device; never destroyed (the pool lives as long as the process)
+}  // namespace
+
+hipEvent_t pooled_event() {
+    int dev = 0;
+    AIRG_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_event_mu);
+        auto &v = g_events[dev];
+        if (!v.empty()) {
+            hipEvent_t e = v.back();
+            v.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e;
+    AIRG_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void release_event(hipEvent_t e) {
+    if (!e) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    g_events[dev].push_back(e);
 }
 
 // Device-to-device copy by a kernel: 16-byte vectors when both ends are
