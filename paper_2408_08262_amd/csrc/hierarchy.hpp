@@ -152,17 +152,12 @@ public:
     void start(std::function<void()> job);
     void finish();        // rethrows the job's exception
     void wait_idle();     // waits for a running job, ignoring its outcome
+    struct Worker;        // the host thread; kept per device for later setups
 private:
-    void loop();
     hipStream_t main_, s_ = nullptr;
     hipEvent_t fork_ = nullptr, join_ = nullptr;
     int dev_ = 0;
-    std::thread th_;
-    std::mutex mu_;
-    std::condition_variable cv_;
-    std::function<void()> job_;
-    std::exception_ptr err_;
-    bool has_ = false, busy_ = false, quit_ = false;
+    Worker *w_ = nullptr;
 };
 
 // Pieces of the setup shared by the single and batch drivers.

@@ -27,77 +27,111 @@ static hipStream_t branch_stream(int dev) {
     return streams[dev];
 }
 
+// The branch's host thread.  Threads are kept per device after their setup
+// and taken again by later ones (starting a thread and attaching it to the
+// device cost tens of microseconds of host time per setup); they wait on
+// their condition variable for the life of the process.
+struct Branch::Worker {
+    int dev = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::function<void()> job;
+    std::exception_ptr err;
+    bool has = false, busy = false;
+
+    void loop() {
+        (void)hipSetDevice(dev);
+        for (;;) {
+            std::function<void()> j;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return has; });
+                j = std::move(job);
+                has = false;
+            }
+            std::exception_ptr e;
+            try {
+                j();
+            } catch (...) {
+                e = std::current_exception();
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                err = e;
+                busy = false;
+            }
+            cv.notify_all();
+        }
+    }
+};
+
+namespace {
+std::mutex g_worker_mu;
+std::vector<std::vector<Branch::Worker *>> g_idle_workers;   // per device
+
+Branch::Worker *take_worker(int dev) {
+    {
+        std::lock_guard<std::mutex> lk(g_worker_mu);
+        if ((int)g_idle_workers.size() <= dev) g_idle_workers.resize((size_t)dev + 1);
+        auto &v = g_idle_workers[dev];
+        if (!v.empty()) {
+            Branch::Worker *w = v.back();
+            v.pop_back();
+            return w;
+        }
+    }
+    auto *w = new Branch::Worker();
+    w->dev = dev;
+    std::thread([w] { w->loop(); }).detach();
+    return w;
+}
+
+void give_worker(Branch::Worker *w) {
+    std::lock_guard<std::mutex> lk(g_worker_mu);
+    g_idle_workers[w->dev].push_back(w);
+}
+}  // namespace
+
 Branch::Branch(hipStream_t main) : main_(main) {
     AIRG_HIP(hipGetDevice(&dev_));
     hipDevice_t sdev = 0;
     AIRG_HIP(hipStreamGetDevice(main, &sdev));
     AIRG_REQUIRE((int)sdev == dev_, ST_INVALID_ARG, "the stream belongs to another device than the current one");
     s_ = branch_stream(dev_);
-    AIRG_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
-    AIRG_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
-    th_ = std::thread([this] { loop(); });
+    fork_ = pooled_event();
+    join_ = pooled_event();
+    w_ = take_worker(dev_);
 }
 
 Branch::~Branch() {
     wait_idle();
-    {
-        std::lock_guard<std::mutex> lk(mu_);
-        quit_ = true;
-    }
-    cv_.notify_all();
-    th_.join();
     (void)hipStreamSynchronize(s_);
-    (void)hipEventDestroy(fork_);
-    (void)hipEventDestroy(join_);
-}
-
-void Branch::loop() {
-    (void)hipSetDevice(dev_);
-    for (;;) {
-        std::function<void()> job;
-        {
-            std::unique_lock<std::mutex> lk(mu_);
-            cv_.wait(lk, [&] { return has_ || quit_; });
-            if (!has_) return;
-            job = std::move(job_);
-            has_ = false;
-        }
-        std::exception_ptr e;
-        try {
-            job();
-        } catch (...) {
-            e = std::current_exception();
-        }
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            err_ = e;
-            busy_ = false;
-        }
-        cv_.notify_all();
-    }
+    release_event(fork_);
+    release_event(join_);
+    give_worker(w_);
 }
 
 void Branch::start(std::function<void()> job) {
     AIRG_HIP(hipEventRecord(fork_, main_));
     AIRG_HIP(hipStreamWaitEvent(s_, fork_, 0));
     {
-        std::lock_guard<std::mutex> lk(mu_);
-        job_ = std::move(job);
-        err_ = nullptr;
-        has_ = true;
-        busy_ = true;
+        std::lock_guard<std::mutex> lk(w_->mu);
+        w_->job = std::move(job);
+        w_->err = nullptr;
+        w_->has = true;
+        w_->busy = true;
     }
-    cv_.notify_all();
+    w_->cv.notify_all();
 }
 
 void Branch::wait_idle() {
-    std::unique_lock<std::mutex> lk(mu_);
-    cv_.wait(lk, [&] { return !busy_; });
+    std::unique_lock<std::mutex> lk(w_->mu);
+    w_->cv.wait(lk, [&] { return !w_->busy; });
 }
 
 void Branch::finish() {
     wait_idle();
-    if (err_) std::rethrow_exception(err_);
+    if (w_->err) std::rethrow_exception(w_->err);
     AIRG_HIP(hipEventRecord(join_, s_));
     AIRG_HIP(hipStreamWaitEvent(main_, join_, 0));
 }
