@@ -150,12 +150,15 @@ __device__ inline bool key_less(int32_t dj, uint32_t hj, int32_t j, int32_t di, 
 constexpr uint64_t kAssigned = ~0ull;
 
 __global__ void k_pmisr_init(int32_t n, const int32_t *__restrict__ deg, const uint32_t *__restrict__ h,
-                             int8_t *__restrict__ cf, uint64_t *__restrict__ key) {
+                             int8_t *__restrict__ cf, uint64_t *__restrict__ key, uint8_t *__restrict__ beaten,
+                             uint8_t *__restrict__ markC) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const bool isolated = deg[i] == 0;
     cf[i] = isolated ? CF_F : CF_U;
     key[i] = isolated ? kAssigned : ((uint64_t)(uint32_t)deg[i] << 32) | h[i];
+    beaten[i] = 0;
+    markC[i] = 0;
 }
 
 // Neighbour j (key kj) beats node i (key ki, unassigned): j is unassigned
@@ -229,13 +232,14 @@ __global__ void __launch_bounds__(256) k_pmisr_select(int32_t n, const int32_t *
 }
 
 // Update: D joins F; an unassigned node with a neighbour in D joins C; a node
-// still unassigned pushes beaten along its row for the next round.
+// still unassigned pushes beaten along its row for the next round, or, after
+// the last of a fixed number of rounds (LAST), joins C.
 template <int G>
 __global__ void __launch_bounds__(256) k_pmisr_update(int32_t n, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci,
                                                       const uint8_t *__restrict__ inD, int8_t *__restrict__ cf,
                                                       uint64_t *__restrict__ key, uint8_t *__restrict__ markC,
-                                                      uint8_t *__restrict__ beaten) {
+                                                      uint8_t *__restrict__ beaten, int last) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
@@ -259,6 +263,13 @@ __global__ void __launch_bounds__(256) k_pmisr_update(int32_t n, const int32_t *
     if (hit) {
         if (lane == 0) {
             markC[row] = 0;
+            cf[row] = CF_C;
+            key[row] = kAssigned;
+        }
+        return;
+    }
+    if (last) {
+        if (lane == 0) {
             cf[row] = CF_C;
             key[row] = kAssigned;
         }
@@ -298,8 +309,7 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
     DBuf<uint64_t> key((size_t)n, s);
     DBuf<uint8_t> flags((size_t)2 * n, s);
     uint8_t *beaten = flags.p, *markC = flags.p + n;
-    fill_zero(flags.p, (size_t)2 * n, s);
-    k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, h, cf, key.p);
+    k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, h, cf, key.p, beaten, markC);
     AIRG_LAUNCH_CHECK();
     int g = lanes_for(A.nnz / 2, n);   // rows of S: about half of A's entries
     const unsigned grid = grid_for((int64_t)n * g, 256);
@@ -314,7 +324,8 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
         int32_t *cnt = until_done ? nu.p + rounds : nullptr;
         dispatch_group(g, [&]<int W>() {
             k_pmisr_select<W><<<grid, 256, 0, s>>>(n, G.srp.p, G.sci.p, key.p, beaten, inD.p, markC, cnt);
-            k_pmisr_update<W><<<grid, 256, 0, s>>>(n, G.srp.p, G.sci.p, inD.p, cf, key.p, markC, beaten);
+            k_pmisr_update<W><<<grid, 256, 0, s>>>(n, G.srp.p, G.sci.p, inD.p, cf, key.p, markC, beaten,
+                                                   !until_done && rounds + 1 == max_rounds);
         });
         AIRG_LAUNCH_CHECK();
         ++rounds;
@@ -330,8 +341,10 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
             }
         }
     }
-    k_pmisr_finish<<<grid_for(n, 256), 256, 0, s>>>(n, cf, nullptr);
-    AIRG_LAUNCH_CHECK();
+    if (until_done) {   // a fixed number of rounds ended in its last update
+        k_pmisr_finish<<<grid_for(n, 256), 256, 0, s>>>(n, cf, nullptr);
+        AIRG_LAUNCH_CHECK();
+    }
     return rounds;
 }
 
