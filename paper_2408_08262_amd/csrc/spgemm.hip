@@ -713,7 +713,7 @@ __global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *
 }
 
 constexpr int32_t kNarrowMaxCols = 4096;
-constexpr int64_t kNarrowMaxWork = (int64_t)1 << 25;   // rows x NC: the accumulator sweeps per product
+constexpr int64_t kNarrowMaxWork = (int64_t)1 << 24;   // rows x NC: the accumulator sweeps per product
 
 template <int NC>
 static Csr spgemm_narrow(const CsrView &A, const CsrView &Bm, hipStream_t s) {
