@@ -87,6 +87,9 @@ typedef struct airg_opts {
     int32_t build_adjoint;        /* 1: build the A^T hierarchy during setup            */
     int32_t onepoint_weight;      /* 0: weight 1; 1: -a_ij / a_ii                        */
     int32_t use_graph;            /* 1: replay the V-cycle as a captured HIP graph      */
+                                  /* (a single hierarchy captures after its first 16    */
+                                  /* cycles at a precision since the last (re)setup;    */
+                                  /* the batched cycle at its first)                    */
     int32_t autotune;             /* 1: time candidate SpMM kernels per batch operator  */
     int64_t device_bytes_cap;     /* 0 = no cap; else a cap on the library's device     */
                                   /* memory in use while this setup runs                */

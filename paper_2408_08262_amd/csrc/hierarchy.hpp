@@ -55,9 +55,14 @@ struct Hier {
     DBuf<double> x, r, e, bp;     // top-level work vectors
     DBuf<float> r32, e32;
     // V-cycle graphs (use_graph): [0] FP64, [1] FP32, captured once on the
-    // private stream cap over fixed buffers and replayed on s
+    // private stream cap over fixed buffers and replayed on s.  A slot is
+    // captured only after kEagerCycles eager cycles at its precision since the
+    // last (re)setup: capture and instantiation cost about as much as that
+    // many replays save, so a hierarchy used for one short solve never pays it.
+    static constexpr int kEagerCycles = 16;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int eager[2] = {0, 0};
     hipStream_t cap = nullptr;
 
     Hier() = default;

@@ -174,15 +174,22 @@ void Hier::drop_graphs() {
         if (graph[k]) (void)hipGraphDestroy(graph[k]);
         gexec[k] = nullptr;
         graph[k] = nullptr;
+        eager[k] = 0;
     }
 }
 
 namespace {
-// Captures f's launches on the private stream once (the legacy default stream
-// cannot be captured), then replays them on the hierarchy's stream.
+// Runs f eagerly for the slot's first kEagerCycles calls; then captures its
+// launches on the private stream once (the legacy default stream cannot be
+// captured) and replays them on the hierarchy's stream.
 template <class F>
 void run_captured(Hier &H, int k, F &&f) {
     if (!H.gexec[k]) {
+        if (H.eager[k] < Hier::kEagerCycles) {
+            ++H.eager[k];
+            f();
+            return;
+        }
         if (!H.cap) AIRG_HIP(hipStreamCreateWithFlags(&H.cap, hipStreamNonBlocking));
         hipStream_t user = H.s;
         AIRG_HIP(hipStreamBeginCapture(H.cap, hipStreamCaptureModeRelaxed));
@@ -207,8 +214,8 @@ void run_captured(Hier &H, int k, F &&f) {
 // The outer iterations keep their vectors in natural order and apply the
 // top operator as stored; the cycle runs in level order (F points first)
 // between fixed buffers (level 0's g and e for FP64, r32/e32 for FP32), which
-// the casts in and out permute.  With use_graph one captured graph serves
-// every call.
+// the casts in and out permute.  With use_graph one captured graph per
+// precision serves every call after the first Hier::kEagerCycles.
 void Hier::precondition(const double *rv, double *ev, int precision) {
     Level &T = L(0);
     const int64_t n0 = T.n;

@@ -159,8 +159,9 @@ def test_truncated_hierarchy_and_stats():
 
 @pytest.mark.parametrize("outer,prec", [(0, 64), (1, 32), (1, 64)], ids=["richardson64", "fgmres32", "fgmres64"])
 def test_captured_vcycle_graph_replays_the_eager_cycle(outer, prec):
-    """use_graph: the single hierarchy's V-cycle is captured once and replayed;
-    solves must equal the eager ones bit for bit, call after call."""
+    """use_graph: the single hierarchy's V-cycle runs eagerly for its first
+    cycles, is then captured once and replayed; solves must equal the eager
+    ones bit for bit, call after call (three solves span the capture)."""
     P = dg_square(64)
     b = torch.as_tensor(P.b, device="cuda")
     h0, _ = setup(P, outer=outer, precond_precision=prec)
@@ -177,8 +178,9 @@ def test_captured_vcycle_graph_replays_the_eager_cycle(outer, prec):
     airg.airg_resetup(h0, vals)
     airg.airg_resetup(h1, vals)
     x0, i0 = airg.airg_solve(h0, b, rtol=1e-10, max_it=200, allow_not_converged=True)
-    x1, i1 = airg.airg_solve(h1, b, rtol=1e-10, max_it=200, allow_not_converged=True)
-    assert i1["iterations"] == i0["iterations"] and torch.equal(x0, x1)
+    for _ in range(3):
+        x1, i1 = airg.airg_solve(h1, b, rtol=1e-10, max_it=200, allow_not_converged=True)
+        assert i1["iterations"] == i0["iterations"] and torch.equal(x0, x1)
 
 
 def test_setup_under_memory_caps_fails_cleanly():
