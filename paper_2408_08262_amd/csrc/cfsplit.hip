@@ -11,11 +11,13 @@
 namespace airg {
 
 // ------------------------------------------------------------- strength ---
+// Marks the strong entries, counts them per row, and clears the row's S^T
+// count for the pass after it.
 template <int G>
 __global__ void __launch_bounds__(256) k_strength(int32_t n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                   double alpha, uint8_t *__restrict__ strong,
-                                                  int32_t *__restrict__ cntS) {
+                                                  int32_t *__restrict__ cntS, int32_t *__restrict__ cntT) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
@@ -34,7 +36,10 @@ __global__ void __launch_bounds__(256) k_strength(int32_t n, const int32_t *__re
         c += st;
     }
     c = group_sum<G>(c);
-    if (lane == 0) cntS[row] = c;
+    if (lane == 0) {
+        cntS[row] = c;
+        cntT[row] = 0;
+    }
 }
 
 // Per strong entry (i, j): write it to row i of S's own CSR, count it for
@@ -90,11 +95,10 @@ StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
     G.srp.alloc((size_t)n + 1, s);
     G.sci.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);   // S's size is not read back: room for all of A
     DBuf<int32_t> cntS((size_t)n, s), cntT((size_t)n, s), mutual((size_t)n, s);
-    fill_zero(cntT.p, (size_t)n * 4, s);
     int g = lanes_for(A.nnz, n);
     const unsigned grid = grid_for((int64_t)n * g, 256);
     dispatch_group(g, [&]<int W>() {
-        k_strength<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, A.v, alpha, G.strong.p, cntS.p);
+        k_strength<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, A.v, alpha, G.strong.p, cntS.p, cntT.p);
     });
     AIRG_LAUNCH_CHECK();
     exclusive_scan(cntS.p, G.srp.p, n, s, false);

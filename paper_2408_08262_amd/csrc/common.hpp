@@ -181,6 +181,14 @@ inline void h2d(T *d, const T *h, size_t count, hipStream_t s) {
 // Device-to-device copy by a copy kernel (no blit or memset node, so also
 // safe inside captured graphs).
 void copy_bytes(void *d, const void *src, size_t bytes, hipStream_t s);
+// Several device-to-device copies in one launch.
+constexpr int kMaxCopies = 4;
+struct CopyReq {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+void copy_many(const CopyReq *req, int n, hipStream_t s);
 template <class T>
 inline void d2d(T *d, const T *src, size_t count, hipStream_t s) {
     copy_bytes(d, src, count * sizeof(T), s);
@@ -203,6 +211,13 @@ void read_ints(const std::vector<const int32_t *> &src, const std::vector<int32_
 // out[0..n] = exclusive prefix sum of in[0..n-1]; out[n] = total.  Returns
 // the total (synchronising) when want_total is set.
 int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, bool want_total = true);
+// The same scan, also writing smp.out[q] = out[q * smp.stride] for
+// q < smp.count (all sampled positions <= n); no synchronisation.
+struct ScanSample {
+    int32_t *out = nullptr;
+    int64_t stride = 1, count = 0;
+};
+void exclusive_scan_sampled(const int32_t *in, int32_t *out, int64_t n, const ScanSample &smp, hipStream_t s);
 // Up to four independent exclusive scans (out[r] of n[r] + 1 entries) in the
 // same launches; no synchronisation.
 void exclusive_scans(const std::vector<const int32_t *> &in, const std::vector<int32_t *> &out,

@@ -99,8 +99,8 @@ Csr canonical_copy(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
     A.ci.alloc((size_t)kept, s);
     A.v.alloc((size_t)kept, s);
     if (kept == nnz) {
-        d2d(A.ci.p, ci, (size_t)nnz, s);
-        d2d(A.v.p, v, (size_t)nnz, s);
+        const CopyReq req[2] = {{A.ci.p, ci, (size_t)nnz * sizeof(int32_t)}, {A.v.p, v, (size_t)nnz * sizeof(double)}};
+        copy_many(req, 2, s);
     } else {
         k_canonical_fill<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, v, A.rp.p, A.ci.p, A.v.p);
         AIRG_LAUNCH_CHECK();
@@ -111,9 +111,10 @@ Csr canonical_copy(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
 Csr copy_csr(const CsrView &A, hipStream_t s) {
     Csr B;
     B.alloc(A.nr, A.nc, A.nnz, s);
-    d2d(B.rp.p, A.rp, (size_t)A.nr + 1, s);
-    d2d(B.ci.p, A.ci, (size_t)A.nnz, s);
-    d2d(B.v.p, A.v, (size_t)A.nnz, s);
+    const CopyReq req[3] = {{B.rp.p, A.rp, ((size_t)A.nr + 1) * sizeof(int32_t)},
+                            {B.ci.p, A.ci, (size_t)A.nnz * sizeof(int32_t)},
+                            {B.v.p, A.v, (size_t)A.nnz * sizeof(double)}};
+    copy_many(req, 3, s);
     return B;
 }
 
@@ -1114,18 +1115,10 @@ void gemv_add(const double *V, int64_t ldv, int nvec, const double *h_dev, doubl
 constexpr int kBinItems = 8;                     // rows per lane
 constexpr int32_t kBinSpan = 64 * kBinItems;
 
+// The wavefront's rows per bin (b: each lane's bins, -1 past the end).
 template <int NB>
-__global__ void __launch_bounds__(64) k_bin_count(const int8_t *__restrict__ bin, int32_t n, int32_t nw,
-                                                  int32_t *__restrict__ bc) {
-    const int32_t w = blockIdx.x;
+__device__ inline void bin_count_store(const int (&b)[kBinItems], int32_t w, int32_t nw, int32_t *__restrict__ bc) {
     const int lane = threadIdx.x;
-    const int32_t r0 = w * kBinSpan;
-    int b[kBinItems];
-#pragma unroll
-    for (int u = 0; u < kBinItems; ++u) {
-        int32_t i = r0 + u * 64 + lane;
-        b[u] = i < n ? bin[i] : -1;
-    }
     int32_t c[NB];
 #pragma unroll
     for (int v = 0; v < NB; ++v) {
@@ -1136,6 +1129,42 @@ __global__ void __launch_bounds__(64) k_bin_count(const int8_t *__restrict__ bin
 #pragma unroll
     for (int v = 0; v < NB; ++v)
         if (lane == v) bc[(int64_t)v * nw + w] = c[v];
+}
+
+template <int NB>
+__global__ void __launch_bounds__(64) k_bin_count(const int8_t *__restrict__ bin, int32_t n, int32_t nw,
+                                                  int32_t *__restrict__ bc) {
+    const int32_t w = blockIdx.x;
+    const int32_t r0 = w * kBinSpan;
+    int b[kBinItems];
+#pragma unroll
+    for (int u = 0; u < kBinItems; ++u) {
+        int32_t i = r0 + u * 64 + (int)threadIdx.x;
+        b[u] = i < n ? bin[i] : -1;
+    }
+    bin_count_store<NB>(b, w, nw, bc);
+}
+
+template <int NB>
+__global__ void __launch_bounds__(64) k_bin_count_rule(const int32_t *__restrict__ val, int diff, BinRule rule,
+                                                       int32_t n, int32_t nw, int8_t *__restrict__ bin,
+                                                       int32_t *__restrict__ bc) {
+    const int32_t w = blockIdx.x;
+    const int32_t r0 = w * kBinSpan;
+    int b[kBinItems];
+#pragma unroll
+    for (int u = 0; u < kBinItems; ++u) {
+        int32_t i = r0 + u * 64 + (int)threadIdx.x;
+        b[u] = -1;
+        if (i < n) {
+            const int32_t x = diff ? val[i + 1] - val[i] : val[i];
+            int c = 0;
+            for (int t = 0; t < rule.nthr; ++t) c += x > rule.thr[t];
+            b[u] = c;
+            bin[i] = (int8_t)c;
+        }
+    }
+    bin_count_store<NB>(b, w, nw, bc);
 }
 
 template <int NB>
@@ -1166,23 +1195,30 @@ __global__ void __launch_bounds__(64) k_bin_scatter(const int8_t *__restrict__ b
     }
 }
 
-// tot[b] = first offset of bin b, tot[nb] = number of binned rows
-__global__ void k_bin_starts(const int32_t *__restrict__ boff, int nb, int32_t nw, int32_t *__restrict__ tot) {
-    int b = threadIdx.x;
-    if (b <= nb) tot[b] = boff[(int64_t)b * nw];
-}
+struct RuleSrc {
+    const int32_t *val;
+    bool diff;
+    BinRule rule;
+    int8_t *out;
+};
 
 template <int NB>
-static void bin_begin_t(BinPlan &P, hipStream_t s) {
+static void bin_begin_t(BinPlan &P, const RuleSrc *src, hipStream_t s) {
     const int64_t m = (int64_t)NB * P.nw;
     DBuf<int32_t> bc((size_t)m + 1, s);
     P.boff.alloc((size_t)m + 1, s);
     P.tot.alloc(NB + 1, s);
-    k_bin_count<NB><<<P.nw, 64, 0, s>>>(P.bin, P.n, P.nw, bc.p);
+    if (src)
+        k_bin_count_rule<NB><<<P.nw, 64, 0, s>>>(src->val, src->diff ? 1 : 0, src->rule, P.n, P.nw, src->out, bc.p);
+    else
+        k_bin_count<NB><<<P.nw, 64, 0, s>>>(P.bin, P.n, P.nw, bc.p);
     AIRG_LAUNCH_CHECK();
-    exclusive_scan(bc.p, P.boff.p, m, s, false);
-    k_bin_starts<<<1, 64, 0, s>>>(P.boff.p, NB, P.nw, P.tot.p);
-    AIRG_LAUNCH_CHECK();
+    // tot[b] = boff[b * nw]: bin b's first offset; tot[NB] = boff[m], the total
+    ScanSample smp;
+    smp.out = P.tot.p;
+    smp.stride = P.nw;
+    smp.count = NB + 1;
+    exclusive_scan_sampled(bc.p, P.boff.p, m, smp, s);
 }
 
 template <int NB>
@@ -1202,7 +1238,7 @@ static void with_nbins(int nbins, F &&f) {
     }
 }
 
-BinPlan bin_rows_begin(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
+static BinPlan bin_begin(const int8_t *bin, const RuleSrc *src, int32_t n, int nbins, hipStream_t s) {
     BinPlan P;
     P.bin = bin;
     P.n = n;
@@ -1213,8 +1249,20 @@ BinPlan bin_rows_begin(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
         fill_zero(P.tot.p, ((size_t)nbins + 1) * 4, s);
         return P;
     }
-    with_nbins(nbins, [&]<int NB>() { bin_begin_t<NB>(P, s); });
+    with_nbins(nbins, [&]<int NB>() { bin_begin_t<NB>(P, src, s); });
     return P;
+}
+
+BinPlan bin_rows_begin(const int8_t *bin, int32_t n, int nbins, hipStream_t s) {
+    return bin_begin(bin, nullptr, n, nbins, s);
+}
+
+BinPlan bin_rows_begin_rule(const int32_t *val, bool diff, const BinRule &rule, int8_t *bin_out, int32_t n, int nbins,
+                            hipStream_t s) {
+    AIRG_REQUIRE(rule.nthr >= 0 && rule.nthr < nbins && rule.nthr <= BinRule::kMax, ST_INVALID_ARG,
+                 "bin rule does not match the number of bins");
+    const RuleSrc src{val, diff, rule, bin_out};
+    return bin_begin(bin_out, &src, n, nbins, s);
 }
 
 Bins bin_rows_end(BinPlan &P, const int32_t *h_tot, hipStream_t s) {

@@ -123,6 +123,16 @@ struct BinPlan {
     DBuf<int32_t> boff, tot;
 };
 BinPlan bin_rows_begin(const int8_t *bin, int32_t n, int nbins, hipStream_t s);
+// Bins computed in the counting pass: row i's value is val[i] (or
+// val[i + 1] - val[i] with diff, a row length from a row pointer), its bin the
+// number of thresholds below that value, also stored in bin_out[i].
+struct BinRule {
+    static constexpr int kMax = 12;
+    int32_t thr[kMax];
+    int nthr;
+};
+BinPlan bin_rows_begin_rule(const int32_t *val, bool diff, const BinRule &rule, int8_t *bin_out, int32_t n, int nbins,
+                            hipStream_t s);
 Bins bin_rows_end(BinPlan &P, const int32_t *h_tot, hipStream_t s);
 
 // Wavefront-scope ordering of LDS traffic among the lanes of one wave.

@@ -472,13 +472,6 @@ std::vector<PolyInfo> gmres_poly_seg(const CsrView &A, const std::vector<int32_t
 }
 
 // --------------------------------------------- fixed-sparsity assembly ----
-__global__ void k_rowlen_bin(int32_t n, const int32_t *__restrict__ rp, int8_t *__restrict__ bin) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t L = rp[i + 1] - rp[i];
-    bin[i] = L <= 4 ? 0 : L <= 8 ? 1 : L <= 16 ? 2 : L <= 32 ? 3 : L <= 64 ? 4 : 5;
-}
-
 // One G-lane group per row (L = row length <= G).  M_i = A(J_i, J_i) is built
 // in LDS by merging each gathered row with J_i; then v_k = v_{k-1} M_i with
 // lane a owning column a, the sum over p ascending (v_{k-1} read from LDS).
@@ -604,11 +597,9 @@ FixedPlan fixed_sparsity_begin(const CsrView &Pt, hipStream_t s) {
     FixedPlan F;
     const int32_t n = Pt.nr;
     F.bin.alloc((size_t)n + 1, s);
-    if (n > 0) {
-        k_rowlen_bin<<<grid_for(n, 256), 256, 0, s>>>(n, Pt.rp, F.bin.p);
-        AIRG_LAUNCH_CHECK();
-    }
-    F.bins = bin_rows_begin(F.bin.p, n, kFixedBins, s);
+    // bins by row length: <= 4, 8, 16, 32, 64, longer
+    const BinRule rule{{4, 8, 16, 32, 64}, 5};
+    F.bins = bin_rows_begin_rule(Pt.rp, true, rule, F.bin.p, n, kFixedBins, s);
     return F;
 }
 

@@ -171,42 +171,77 @@ void release_event(hipEvent_t e) {
     g_events[dev].push_back(e);
 }
 
-// Device-to-device copy by a kernel: 16-byte vectors when both ends are
-// 16-byte aligned, else 4-byte words (every element type here is 4 or 8
-// bytes).  A grid-stride loop over at most 4096 workgroups.
+// Device-to-device copies by one kernel launch for up to kMaxCopies buffers.
+// Each copy owns a contiguous range of workgroups; where both ends are
+// 16-byte aligned its body moves as 16-byte vectors and the last (< 16) bytes
+// as 4-byte words, else all of it as words (every element type here is 4 or 8
+// bytes).  Grid-stride loops, at most 4096 workgroups in all.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-__global__ void k_copy_u128(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) dst[i] = __builtin_nontemporal_load(src + i);
+struct CopyItem {
+    const char *src;
+    char *dst;
+    size_t vecs;       // 16-byte vectors from the start
+    size_t words;      // 4-byte words after them
+    unsigned block0, blocks;
+};
+struct CopySet {
+    CopyItem it[kMaxCopies];
+    int n;
+};
+__global__ void __launch_bounds__(256) k_copy_set(CopySet c) {
+    int k = 0;
+    while (k + 1 < c.n && blockIdx.x >= c.it[k + 1].block0) ++k;
+    const CopyItem &t = c.it[k];
+    const size_t first = (size_t)(blockIdx.x - t.block0) * 256 + threadIdx.x;
+    const size_t stride = (size_t)t.blocks * 256;
+    const u32x4 *sv = reinterpret_cast<const u32x4 *>(t.src);
+    u32x4 *dv = reinterpret_cast<u32x4 *>(t.dst);
+    for (size_t i = first; i < t.vecs; i += stride) dv[i] = __builtin_nontemporal_load(sv + i);
+    const uint32_t *sw = reinterpret_cast<const uint32_t *>(t.src + t.vecs * 16);
+    uint32_t *dw = reinterpret_cast<uint32_t *>(t.dst + t.vecs * 16);
+    for (size_t i = first; i < t.words; i += stride) dw[i] = sw[i];
 }
-__global__ void k_copy_u32(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) dst[i] = src[i];
+
+void copy_many(const CopyReq *req, int n, hipStream_t s) {
+    AIRG_REQUIRE(n >= 0 && n <= kMaxCopies, ST_INVALID_ARG, "too many copies in one launch");
+    CopySet c{};
+    size_t work[kMaxCopies] = {};
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        const CopyReq &r = req[i];
+        if (!r.bytes) continue;
+        const uintptr_t a = (uintptr_t)r.dst, b = (uintptr_t)r.src;
+        if (r.bytes % 4 || a % 4 || b % 4) {   // not met by any element type here
+            AIRG_HIP(hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToDevice, s));
+            continue;
+        }
+        CopyItem &t = c.it[c.n];
+        t.src = static_cast<const char *>(r.src);
+        t.dst = static_cast<char *>(r.dst);
+        t.vecs = (a % 16 == 0 && b % 16 == 0) ? r.bytes / 16 : 0;
+        t.words = (r.bytes - t.vecs * 16) / 4;
+        work[c.n] = std::max(t.vecs, t.words);
+        total += work[c.n];
+        ++c.n;
+    }
+    if (!c.n) return;
+    // workgroups in proportion to each copy's work, at least one each
+    const size_t budget = std::max<size_t>(std::min<size_t>((total + 255) / 256, 4096), (size_t)c.n);
+    unsigned next = 0;
+    for (int i = 0; i < c.n; ++i) {
+        const size_t want = (work[i] + 255) / 256;
+        const size_t share = std::max<size_t>(1, std::min(want, budget * work[i] / std::max<size_t>(total, 1)));
+        c.it[i].block0 = next;
+        c.it[i].blocks = (unsigned)share;
+        next += (unsigned)share;
+    }
+    k_copy_set<<<next, 256, 0, s>>>(c);
+    AIRG_LAUNCH_CHECK();
 }
 
 void copy_bytes(void *d, const void *src, size_t bytes, hipStream_t s) {
-    if (!bytes) return;
-    const uintptr_t a = (uintptr_t)d, b = (uintptr_t)src;
-    if (bytes % 4 || a % 4 || b % 4) {
-        AIRG_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToDevice, s));
-        return;
-    }
-    size_t head = 0;
-    if (a % 16 == 0 && b % 16 == 0 && bytes >= 16) {
-        const size_t n = bytes / 16;
-        const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-        k_copy_u128<<<g, 256, 0, s>>>((const u32x4 *)src, (u32x4 *)d, n);
-        AIRG_LAUNCH_CHECK();
-        head = n * 16;
-    }
-    if (head < bytes) {
-        const size_t n = (bytes - head) / 4;
-        const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-        k_copy_u32<<<g, 256, 0, s>>>((const uint32_t *)((const char *)src + head), (uint32_t *)((char *)d + head), n);
-        AIRG_LAUNCH_CHECK();
-    }
+    const CopyReq r{d, src, bytes};
+    copy_many(&r, 1, s);
 }
 
 // ------------------------------------------------------------------ scan ---
@@ -246,7 +281,17 @@ struct ScanSet {
     int32_t *out[kScanArrays];
     int64_t n[kScanArrays];
     int64_t *bsum[kScanArrays];   // nb + 1 block sums per array (tiled path); [0] the total (small path)
+    // optional samples: samp[q] = out[q * sstride] for q < nsamp (0: none)
+    int32_t *samp[kScanArrays];
+    int64_t sstride[kScanArrays];
+    int64_t nsamp[kScanArrays];
 };
+
+// The sample taken at the total out[n], if n is a sampled position.
+__device__ inline void sample_total(const ScanSet &S, int r, int64_t n, int64_t total) {
+    const int64_t st = S.sstride[r];
+    if (S.nsamp[r] > 0 && n % st == 0 && n / st < S.nsamp[r]) S.samp[r][n / st] = (int32_t)total;
+}
 
 __host__ __device__ inline int64_t scan_tiles(int64_t n) {
     return n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
@@ -320,13 +365,20 @@ __global__ void k_scan_final(ScanSet S) {
     }
     int64_t tot;
     int64_t off = block_exclusive_scan(s, &tot) + before;
+    // next sampled position at or after base
+    const int64_t st = S.sstride[r], ns = S.nsamp[r];
+    int64_t q = ns > 0 ? (base + st - 1) / st : 0;
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + k;
-        if (i < n) out[i] = (int32_t)off;
+        if (i < n) {
+            out[i] = (int32_t)off;
+            if (q < ns && i == q * st) S.samp[r][q++] = (int32_t)off;
+        }
         off += v[k];
     }
     if ((int64_t)blockIdx.x == nb - 1 && threadIdx.x == 0) {
         out[n] = (int32_t)(before + tot);
+        sample_total(S, r, n, before + tot);
         if (!SUMS_SCANNED) bsum[nb] = before + tot;
     }
 }
@@ -390,11 +442,17 @@ __global__ void __launch_bounds__(TH) k_scan_small(ScanSet S) {
             int p = j * TH + tid;
             if (t0 + p < n) out[t0 + p] = buf[small_scan_slot(p)];
         }
+        if (S.nsamp[r] > 0) {   // sampled positions inside [t0, min(t0 + tile, n))
+            const int64_t st = S.sstride[r], hi = t0 + kSmallScanTile < n ? t0 + kSmallScanTile : n;
+            for (int64_t q = (t0 + st - 1) / st + tid; q < S.nsamp[r] && q * st < hi; q += TH)
+                S.samp[r][q] = buf[small_scan_slot((int)(q * st - t0))];
+        }
         carry += tot;
         __syncthreads();
     }
     if (tid == 0) {
         out[n] = (int32_t)carry;
+        sample_total(S, r, n, carry);
         S.bsum[r][0] = carry;
     }
 }
@@ -547,7 +605,7 @@ void resolve_sizes(const std::vector<Csr *> &ms, hipStream_t s) {
 // taken from it, and those do not depend on the layout inside the tile.
 // Returns where each array's total lands on the device.
 static std::vector<const int64_t *> scan_set(const int32_t *const *in, int32_t *const *out, const int64_t *n, int k,
-                                             DBuf<int64_t> &sums, hipStream_t s) {
+                                             DBuf<int64_t> &sums, hipStream_t s, const ScanSample *smp = nullptr) {
     AIRG_REQUIRE(k >= 1 && k <= kScanArrays, ST_INVALID_ARG, "bad number of scans");
     ScanSet S{};
     bool small = true;
@@ -565,6 +623,13 @@ static std::vector<const int64_t *> scan_set(const int32_t *const *in, int32_t *
         S.out[r] = out[r];
         S.n[r] = n[r];
         S.bsum[r] = sums.p + o;
+        if (smp && smp[r].count > 0) {
+            AIRG_REQUIRE(smp[r].stride >= 1 && (smp[r].count - 1) * smp[r].stride <= n[r], ST_INVALID_ARG,
+                         "scan samples beyond the output");
+            S.samp[r] = smp[r].out;
+            S.sstride[r] = smp[r].stride;
+            S.nsamp[r] = smp[r].count;
+        }
         tot[r] = small ? sums.p + o : sums.p + o + scan_tiles(n[r]);
         o += scan_tiles(n[r]) + 1;
     }
@@ -592,6 +657,11 @@ void exclusive_scans(const std::vector<const int32_t *> &in, const std::vector<i
                      const std::vector<int64_t> &n, hipStream_t s) {
     DBuf<int64_t> sums;
     scan_set(in.data(), out.data(), n.data(), (int)in.size(), sums, s);
+}
+
+void exclusive_scan_sampled(const int32_t *in, int32_t *out, int64_t n, const ScanSample &smp, hipStream_t s) {
+    DBuf<int64_t> sums;
+    scan_set(&in, &out, &n, 1, sums, s, &smp);
 }
 
 int64_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, bool want_total) {

@@ -53,9 +53,10 @@ Csr clone_f32(const Csr &A, hipStream_t s) {
     C.rp.alloc((size_t)A.nr + 1, s);
     C.ci.alloc((size_t)A.nnz, s);
     C.vf.alloc((size_t)A.nnz, s);
-    d2d(C.rp.p, A.rp.p, (size_t)A.nr + 1, s);
-    d2d(C.ci.p, A.ci.p, (size_t)A.nnz, s);
-    d2d(C.vf.p, A.vf.p, (size_t)A.nnz, s);
+    const CopyReq req[3] = {{C.rp.p, A.rp.p, ((size_t)A.nr + 1) * sizeof(int32_t)},
+                            {C.ci.p, A.ci.p, (size_t)A.nnz * sizeof(int32_t)},
+                            {C.vf.p, A.vf.p, (size_t)A.nnz * sizeof(float)}};
+    copy_many(req, 3, s);
     return C;
 }
 

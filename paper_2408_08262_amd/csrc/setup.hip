@@ -180,8 +180,9 @@ std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t
 Csr pattern_copy(const CsrView &A, hipStream_t s) {
     Csr X;
     X.alloc(A.nr, A.nc, A.nnz, s);
-    d2d(X.rp.p, A.rp, (size_t)A.nr + 1, s);
-    d2d(X.ci.p, A.ci, (size_t)A.nnz, s);
+    const CopyReq req[2] = {{X.rp.p, A.rp, ((size_t)A.nr + 1) * sizeof(int32_t)},
+                            {X.ci.p, A.ci, (size_t)A.nnz * sizeof(int32_t)}};
+    copy_many(req, 2, s);
     return X;
 }
 

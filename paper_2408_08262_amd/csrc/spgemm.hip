@@ -225,7 +225,7 @@ template <int G>
 __global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp,
                                                    const int32_t *__restrict__ aci,
                                                    const int32_t *__restrict__ brp, int32_t *__restrict__ ub,
-                                                   int8_t *__restrict__ bin) {
+                                                   int8_t *__restrict__ bin, int32_t *__restrict__ cnt) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t i = (int32_t)(t / G);
     const int lane = group_lane<G>();
@@ -239,6 +239,7 @@ __global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__r
     if (lane != 0) return;
     int32_t uc = u > 0x7fffffff ? 0x7fffffff : (int32_t)u;
     ub[i] = uc;
+    cnt[i] = 0;   // the symbolic pass counts into it
     bin[i] = uc == 0                            ? SB_EMPTY
              : uc <= 8                         ? SB_G4
              : uc <= 32                        ? SB_G8
@@ -251,21 +252,9 @@ __global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__r
                                                : SB_GLOBAL;
 }
 
-__global__ void k_spgemm_nbin(int32_t m, const int32_t *__restrict__ cnt, int8_t *__restrict__ nbin) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    int32_t c = cnt[i];
-    nbin[i] = c == 0                 ? NB_EMPTY
-              : c <= 8              ? NB_G4
-              : c <= 32             ? NB_G8
-              : c <= 64             ? NB_G16S
-              : c <= 128            ? NB_G16
-              : c <= 256            ? NB_G64S
-              : c <= 512            ? NB_G64
-              : c <= 2048           ? NB_BLOCK4K
-              : c <= 4096           ? NB_BLOCK8K
-                                    : NB_GLOBAL;
-}
+// Numeric bins by entry count, bin = number of thresholds below it: 0 (empty),
+// <= 8, 32, 64, 128, 256, 512, 2048, 4096, longer (NB_EMPTY .. NB_GLOBAL).
+static const BinRule kNumericBins{{0, 8, 32, 64, 128, 256, 512, 2048, 4096}, 9};
 
 // ---------------------------------------------------------- group rows ----
 // Symbolic: one G-lane group per row, T-slot key table per group; counts the
@@ -925,9 +914,10 @@ SpgemmPlan spgemm_begin(const CsrView &A, const int32_t *b_rp, int32_t b_nc, hip
     const int32_t m = A.nr;
     P.ub.alloc((size_t)m + 1, s);
     P.sbin.alloc((size_t)m + 1, s);
+    P.cnt.alloc((size_t)m + 1, s);
     if (m > 0) {
         dispatch_group(lanes_for(A.nnz, m), [&]<int G>() {
-            k_spgemm_ub<G><<<grid_for((int64_t)m * G, 256), 256, 0, s>>>(m, A.rp, A.ci, b_rp, P.ub.p, P.sbin.p);
+            k_spgemm_ub<G><<<grid_for((int64_t)m * G, 256), 256, 0, s>>>(m, A.rp, A.ci, b_rp, P.ub.p, P.sbin.p, P.cnt.p);
         });
         AIRG_LAUNCH_CHECK();
     }
@@ -949,18 +939,13 @@ Csr spgemm_finish(const CsrView &A, const CsrView &Bm, SpgemmPlan &P, const int3
     C.nc = Bm.nc;
     C.rp.alloc((size_t)A.nr + 1, s);
     int32_t m = A.nr;
-    DBuf<int32_t> cnt((size_t)m + 1, s);
+    DBuf<int32_t> &cnt = P.cnt;   // zeroed by the plan's bound pass
     DBuf<int8_t> nbin((size_t)m + 1, s);
-    fill_zero(cnt.p, ((size_t)m + 1) * 4, s);
     Bins SB = bin_rows_end(P.bins, h_tot, s);
     run_symbolic(SB, A, Bm, cnt.p, P.ub.p, m, s);
     exclusive_scan(cnt.p, C.rp.p, m, s, false);
-    if (m > 0) {
-        k_spgemm_nbin<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.p, nbin.p);
-        AIRG_LAUNCH_CHECK();
-    }
     // nnz and the numeric bin starts come back in one readback
-    BinPlan NP = bin_rows_begin(nbin.p, m, NB_N, s);
+    BinPlan NP = bin_rows_begin_rule(cnt.p, false, kNumericBins, nbin.p, m, NB_N, s);
     std::vector<int32_t> h(NB_N + 2);
     read_ints({C.rp.p + m, NP.tot.p}, {1, NB_N + 1}, h.data(), s);
     AIRG_REQUIRE(h[0] >= 0, ST_LIMIT, "product exceeds the int32 index range");

@@ -19,7 +19,7 @@ Csr spgemm(const CsrView &A, const CsrView &B, hipStream_t s);
 struct SpgemmPlan {
     int32_t m = 0, bnc = 0;
     bool narrow = false;
-    DBuf<int32_t> ub;
+    DBuf<int32_t> ub, cnt;   // per-row bound on the product's entries; its entry counts
     DBuf<int8_t> sbin;
     BinPlan bins;
     std::pair<const int32_t *, int32_t> totals() const;
