@@ -90,7 +90,7 @@ airg_status airg_strength(int64_t n, int64_t nnz, const int32_t *d_rowptr, const
         AIRG_REQUIRE(d_strong, ST_INVALID_ARG, "null output");
         StrengthGraph G = strength_graph(A, alpha, s);
         d2d(d_strong, G.strong.p, (size_t)nnz, s);
-        if (d_deg) d2d(d_deg, G.deg.p, (size_t)n, s);
+        if (d_deg) strength_degree(G, d_deg, s);
         AIRG_HIP(hipStreamSynchronize(s));
     });
 }
@@ -103,14 +103,7 @@ airg_status airg_pmisr(int64_t n, int64_t nnz, const int32_t *d_rowptr, const in
         CsrView A = mk(n, n, nnz, d_rowptr, d_col, d_val);
         AIRG_REQUIRE(d_cf && max_rounds >= 0, ST_INVALID_ARG, "bad argument");
         StrengthGraph G = strength_graph(A, alpha, s);
-        DBuf<uint32_t> h;
-        const uint32_t *hp = d_h;
-        if (!hp) {
-            h.alloc((size_t)n, s);
-            pmisr_hash((int32_t)n, seed, level, h.p, s);
-            hp = h.p;
-        }
-        int r = pmisr(A, G, hp, max_rounds, d_cf, s);
+        int r = pmisr(A, G, d_h, max_rounds, d_cf, s, seed, level);
         if (rounds) *rounds = r;
         AIRG_HIP(hipStreamSynchronize(s));
     });

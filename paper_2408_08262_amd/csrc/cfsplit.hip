@@ -80,10 +80,22 @@ __global__ void __launch_bounds__(256) k_strength_mutual(int32_t n, const int32_
     if (lane == 0) mutual[row] = mu;
 }
 
-__global__ void k_degree(int32_t n, const int32_t *__restrict__ cntS, const int32_t *__restrict__ cntT,
+// |S_i u S_i^T| = |S_i| + |S_i^T| - |S_i n S_i^T|
+__device__ inline int32_t strength_degree_of(const int32_t *__restrict__ srp, const int32_t *__restrict__ cntT,
+                                             const int32_t *__restrict__ mutual, int32_t i) {
+    return srp[i + 1] - srp[i] + cntT[i] - mutual[i];
+}
+
+__global__ void k_degree(int32_t n, const int32_t *__restrict__ srp, const int32_t *__restrict__ cntT,
                          const int32_t *__restrict__ mutual, int32_t *__restrict__ deg) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) deg[i] = cntS[i] + cntT[i] - mutual[i];
+    if (i < n) deg[i] = strength_degree_of(srp, cntT, mutual, i);
+}
+
+void strength_degree(const StrengthGraph &G, int32_t *deg, hipStream_t s) {
+    if (G.n <= 0) return;
+    k_degree<<<grid_for(G.n, 256), 256, 0, s>>>(G.n, G.srp.p, G.cntT.p, G.mutual.p, deg);
+    AIRG_LAUNCH_CHECK();
 }
 
 StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
@@ -91,35 +103,29 @@ StrengthGraph strength_graph(const CsrView &A, double alpha, hipStream_t s) {
     int32_t n = A.nr;
     G.n = n;
     G.strong.alloc((size_t)A.nnz, s);
-    G.deg.alloc((size_t)n, s);
     G.srp.alloc((size_t)n + 1, s);
     G.sci.alloc((size_t)std::max<int64_t>(A.nnz, 1), s);   // S's size is not read back: room for all of A
-    DBuf<int32_t> cntS((size_t)n, s), cntT((size_t)n, s), mutual((size_t)n, s);
+    G.cntT.alloc((size_t)n, s);
+    G.mutual.alloc((size_t)n, s);
+    DBuf<int32_t> cntS((size_t)n, s);
+    int32_t *cntT = G.cntT.p, *mutual = G.mutual.p;
     int g = lanes_for(A.nnz, n);
     const unsigned grid = grid_for((int64_t)n * g, 256);
     dispatch_group(g, [&]<int W>() {
-        k_strength<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, A.v, alpha, G.strong.p, cntS.p, cntT.p);
+        k_strength<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, A.v, alpha, G.strong.p, cntS.p, cntT);
     });
     AIRG_LAUNCH_CHECK();
     exclusive_scan(cntS.p, G.srp.p, n, s, false);
     dispatch_group(g, [&]<int W>() {
-        k_strength_mutual<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.srp.p, G.sci.p, cntT.p, mutual.p);
+        k_strength_mutual<W><<<grid, 256, 0, s>>>(n, A.rp, A.ci, G.strong.p, G.srp.p, G.sci.p, cntT, mutual);
     });
-    AIRG_LAUNCH_CHECK();
-    k_degree<<<grid_for(n, 256), 256, 0, s>>>(n, cntS.p, cntT.p, mutual.p, G.deg.p);
     AIRG_LAUNCH_CHECK();
     return G;
 }
 
 // ---------------------------------------------------------------- PMISR ---
-__global__ void k_pmisr_hash(int32_t n, uint64_t seed, int32_t level, uint32_t *__restrict__ h) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) h[i] = (uint32_t)(splitmix64(rng_counter(seed, 0, (uint32_t)level, (uint64_t)i)) >> 32);
-}
-
-void pmisr_hash(int32_t n, uint64_t seed, int32_t level, uint32_t *h, hipStream_t s) {
-    k_pmisr_hash<<<grid_for(n, 256), 256, 0, s>>>(n, seed, level, h);
-    AIRG_LAUNCH_CHECK();
+__device__ inline uint32_t pmisr_hash_of(uint64_t seed, int32_t level, int64_t i) {
+    return (uint32_t)(splitmix64(rng_counter(seed, 0, (uint32_t)level, (uint64_t)i)) >> 32);
 }
 
 // Batch segments: row i of segment p draws with p's seed at its index within
@@ -129,7 +135,7 @@ __global__ void k_pmisr_hash_seg(int32_t n, const int32_t *__restrict__ off, int
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int p = seg_of(off, nseg, i);
-    h[i] = (uint32_t)(splitmix64(rng_counter(seeds[p], 0, (uint32_t)level, (uint64_t)(i - off[p]))) >> 32);
+    h[i] = pmisr_hash_of(seeds[p], level, i - off[p]);
 }
 
 void pmisr_hash_seg(int32_t n, const int32_t *off, int nseg, const uint64_t *seeds, int32_t level, uint32_t *h,
@@ -153,14 +159,19 @@ __device__ inline bool key_less(int32_t dj, uint32_t hj, int32_t j, int32_t di, 
 // 8-byte load.  kAssigned exceeds every unassigned key (deg < 2^31).
 constexpr uint64_t kAssigned = ~0ull;
 
-__global__ void k_pmisr_init(int32_t n, const int32_t *__restrict__ deg, const uint32_t *__restrict__ h,
-                             int8_t *__restrict__ cf, uint64_t *__restrict__ key, uint8_t *__restrict__ beaten,
-                             uint8_t *__restrict__ markC) {
+// Keys from the degrees; the measures h come from memory, or with h null
+// from the generator for (seed, level), as pmisr_hash_of draws them.
+__global__ void k_pmisr_init(int32_t n, const int32_t *__restrict__ srp, const int32_t *__restrict__ cntT,
+                             const int32_t *__restrict__ mutual, const uint32_t *__restrict__ h, uint64_t seed,
+                             int32_t level, int8_t *__restrict__ cf, uint64_t *__restrict__ key,
+                             uint8_t *__restrict__ beaten, uint8_t *__restrict__ markC) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const bool isolated = deg[i] == 0;
+    const int32_t deg = strength_degree_of(srp, cntT, mutual, i);
+    const bool isolated = deg == 0;
+    const uint32_t hi = h ? h[i] : pmisr_hash_of(seed, level, i);
     cf[i] = isolated ? CF_F : CF_U;
-    key[i] = isolated ? kAssigned : ((uint64_t)(uint32_t)deg[i] << 32) | h[i];
+    key[i] = isolated ? kAssigned : ((uint64_t)(uint32_t)deg << 32) | hi;
     beaten[i] = 0;
     markC[i] = 0;
 }
@@ -304,7 +315,8 @@ __global__ void k_pmisr_finish(int32_t n, int8_t *__restrict__ cf, int32_t *__re
 constexpr int kPmisrCheck = 2;
 constexpr int kPmisrSlots = 4096;
 
-int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_rounds, int8_t *cf, hipStream_t s) {
+int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_rounds, int8_t *cf, hipStream_t s,
+          uint64_t seed, int32_t level) {
     int32_t n = A.nr;
     DBuf<uint8_t> inD((size_t)n, s);
     const bool until_done = max_rounds <= 0;
@@ -313,7 +325,8 @@ int pmisr(const CsrView &A, const StrengthGraph &G, const uint32_t *h, int max_r
     DBuf<uint64_t> key((size_t)n, s);
     DBuf<uint8_t> flags((size_t)2 * n, s);
     uint8_t *beaten = flags.p, *markC = flags.p + n;
-    k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.deg.p, h, cf, key.p, beaten, markC);
+    k_pmisr_init<<<grid_for(n, 256), 256, 0, s>>>(n, G.srp.p, G.cntT.p, G.mutual.p, h, seed, level, cf, key.p,
+                                                  beaten, markC);
     AIRG_LAUNCH_CHECK();
     int g = lanes_for(A.nnz / 2, n);   // rows of S: about half of A's entries
     const unsigned grid = grid_for((int64_t)n * g, 256);
@@ -384,15 +397,24 @@ template <int G>
 __global__ void __launch_bounds__(256) k_ddc(int32_t n, const int32_t *__restrict__ rp,
                                              const int32_t *__restrict__ ci, const double *__restrict__ v,
                                              double alpha_diag, const int8_t *__restrict__ cf_in,
-                                             int8_t *__restrict__ cf_out, double *__restrict__ theta) {
+                                             int8_t *__restrict__ cf_out, double *__restrict__ theta,
+                                             int32_t *__restrict__ flags3) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
     if (row >= n) return;
+    auto put = [&](int8_t c) {
+        cf_out[row] = c;
+        if (flags3) {
+            flags3[row] = c == CF_F;
+            flags3[(int64_t)n + row] = c == CF_C;
+            flags3[2 * (int64_t)n + row] = c == CF_T;
+        }
+    };
     int8_t c = cf_in[row];
     if (c != CF_F) {
         if (lane == 0) {
-            cf_out[row] = c;
+            put(c);
             if (theta) theta[row] = -1.0;
         }
         return;
@@ -402,16 +424,17 @@ __global__ void __launch_bounds__(256) k_ddc(int32_t n, const int32_t *__restric
     double th = d == 0.0 ? INFINITY : sum / fabs(d);
     bool conv = d == 0.0 || isinf(th) || (th > alpha_diag && th != 0.0);
     if (lane == 0) {
-        cf_out[row] = conv ? CF_C : CF_F;
+        put(conv ? CF_C : CF_F);
         if (theta) theta[row] = th;
     }
 }
 
-void ddc(const CsrView &A, double alpha_diag, const int8_t *cf_in, int8_t *cf_out, double *theta, hipStream_t s) {
+void ddc(const CsrView &A, double alpha_diag, const int8_t *cf_in, int8_t *cf_out, double *theta, hipStream_t s,
+         int32_t *flags3) {
     int g = lanes_for(A.nnz, A.nr);
     dispatch_group(g, [&]<int W>() {
         k_ddc<W><<<grid_for((int64_t)A.nr * W, 256), 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, alpha_diag, cf_in, cf_out,
-                                                                   theta);
+                                                                   theta, flags3);
     });
     AIRG_LAUNCH_CHECK();
 }
@@ -493,10 +516,8 @@ double ddc_fraction_threshold(const CsrView &A, const int8_t *cf, double fractio
 std::pair<int32_t, int32_t> cf_split(const CsrView &A, const CfParams &p, int32_t level, int8_t *cf, hipStream_t s) {
     int32_t n = A.nr;
     StrengthGraph G = strength_graph(A, p.strong_threshold, s);
-    DBuf<uint32_t> h((size_t)n, s);
-    pmisr_hash(n, p.seed, level, h.p, s);
     DBuf<int8_t> cf0((size_t)n, s);
-    pmisr(A, G, h.p, p.max_rounds, cf0.p, s);
+    pmisr(A, G, nullptr, p.max_rounds, cf0.p, s, p.seed, level);
     double ad = p.ddc_threshold;
     if (ad < 0.0) ad = ddc_fraction_threshold(A, cf0.p, p.ddc_fraction, s);
     ddc(A, ad, cf0.p, cf, nullptr, s);

@@ -528,12 +528,16 @@ __global__ void k_cf_rank(const int8_t *__restrict__ cf, int32_t n, const int32_
 }
 
 CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s, const int32_t *extra_src,
-                   int32_t *extra_out) {
-    DBuf<int32_t> fF((size_t)n, s), fC((size_t)n, s), fT((size_t)n, s);
+                   int32_t *extra_out, const int32_t *flags3) {
+    DBuf<int32_t> fl;
+    if (!flags3) {
+        fl.alloc((size_t)3 * n, s);
+        k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fl.p, fl.p + n, fl.p + 2 * (size_t)n);
+        AIRG_LAUNCH_CHECK();
+        flags3 = fl.p;
+    }
     DBuf<int32_t> sF((size_t)n + 1, s), sC((size_t)n + 1, s), sT((size_t)n + 1, s), tot(3, s);
-    k_cf_flags<<<grid_for(n, 256), 256, 0, s>>>(cf, n, fF.p, fC.p, fT.p);
-    AIRG_LAUNCH_CHECK();
-    exclusive_scans({fF.p, fC.p, fT.p}, {sF.p, sC.p, sT.p}, {n, n, n}, s);
+    exclusive_scans({flags3, flags3 + n, flags3 + 2 * (size_t)n}, {sF.p, sC.p, sT.p}, {n, n, n}, s);
     k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, sT.p, rank, tot.p);
     AIRG_LAUNCH_CHECK();
     int32_t h[4];

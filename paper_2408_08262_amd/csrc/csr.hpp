@@ -44,9 +44,10 @@ struct CfCounts {
     int32_t nF, nC, nT;
 };
 // extra_src, when given, is one more device int read back with the counts
-// into *extra_out.
+// into *extra_out.  flags3, when given, holds the class indicators already
+// (3 n ints: cf == F, cf == C, cf == T, as the DDC pass writes them).
 CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s, const int32_t *extra_src = nullptr,
-                   int32_t *extra_out = nullptr);
+                   int32_t *extra_out = nullptr, const int32_t *flags3 = nullptr);
 // cf_ranks3 plus, at the segment boundaries d_off[0..na] (device, ascending,
 // d_off[na] = n), the numbers of F, C and terminal rows before each boundary:
 // h_bounds[3 p + {0, 1, 2}] (host, 3 (na + 1) entries).

@@ -161,17 +161,15 @@ std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t
     cf.alloc((size_t)n, s);
     rank.alloc((size_t)n, s);
     StrengthGraph G = strength_graph(A, o.strong_threshold, s);
-    DBuf<uint32_t> h((size_t)n, s);
-    pmisr_hash(n, seed, lvl, h.p, s);
     DBuf<int8_t> cf0((size_t)n, s);
-    pmisr(A, G, h.p, o.pmisr_max_rounds, cf0.p, s);
+    pmisr(A, G, nullptr, o.pmisr_max_rounds, cf0.p, s, seed, lvl);
     double ad = o.ddc_threshold;
     if (ad < 0.0) ad = ddc_fraction_threshold(A, cf0.p, o.ddc_fraction, s);
-    ddc(A, ad, cf0.p, cf.p, nullptr, s);
-    if (!nnz_out) return cf_ranks(cf.p, n, rank.p, s);
+    DBuf<int32_t> flags((size_t)3 * n, s);   // class indicators for the rank scans
+    ddc(A, ad, cf0.p, cf.p, nullptr, s, flags.p);
     int32_t nz = 0;
-    CfCounts c = cf_ranks3(cf.p, n, rank.p, s, A.rp + n, &nz);
-    *nnz_out = nz;
+    CfCounts c = cf_ranks3(cf.p, n, rank.p, s, nnz_out ? A.rp + n : nullptr, nnz_out ? &nz : nullptr, flags.p);
+    if (nnz_out) *nnz_out = nz;
     return {c.nF, c.nC};
 }
 
