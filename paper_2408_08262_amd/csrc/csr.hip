@@ -527,8 +527,8 @@ __global__ void k_cf_rank(const int8_t *__restrict__ cf, int32_t n, const int32_
     rank[i] = c == CF_F ? sF[i] : c == CF_C ? sC[i] : sT[i];
 }
 
-CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s, const int32_t *extra_src,
-                   int32_t *extra_out, const int32_t *flags3) {
+CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s,
+                   const std::vector<const int32_t *> &extra, int32_t *extra_out, const int32_t *flags3) {
     DBuf<int32_t> fl;
     if (!flags3) {
         fl.alloc((size_t)3 * n, s);
@@ -540,12 +540,18 @@ CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s, co
     exclusive_scans({flags3, flags3 + n, flags3 + 2 * (size_t)n}, {sF.p, sC.p, sT.p}, {n, n, n}, s);
     k_cf_rank<<<grid_for(n, 256), 256, 0, s>>>(cf, n, sF.p, sC.p, sT.p, rank, tot.p);
     AIRG_LAUNCH_CHECK();
-    int32_t h[4];
-    if (extra_src) {
-        read_ints({tot.p, extra_src}, {3, 1}, h, s);
-        *extra_out = h[3];
+    std::vector<int32_t> h(3 + extra.size());
+    if (!extra.empty()) {
+        std::vector<const int32_t *> src{tot.p};
+        std::vector<int32_t> cnt{3};
+        for (const int32_t *e : extra) {
+            src.push_back(e);
+            cnt.push_back(1);
+        }
+        read_ints(src, cnt, h.data(), s);
+        std::copy(h.begin() + 3, h.end(), extra_out);
     } else {
-        d2h(h, tot.p, 3, s);
+        d2h(h.data(), tot.p, 3, s);
     }
     return CfCounts{h[0], h[1], h[2]};
 }
@@ -647,55 +653,73 @@ __global__ void __launch_bounds__(256) k_extract_fill(int32_t n, const int32_t *
 }
 
 // The three blocks of the splitting in one pass: F rows give A_ff and A_fc,
-// C rows give A_cf (terminal rows give nothing).
+// C rows give A_cf (terminal rows give nothing).  The counts are kept per
+// original row (zero where a row gives no entries to a block), so that their
+// scans, and the block sizes, need only cf: ranks order the rows of each
+// class as the original order does, so row i's offset is its rank's.
 template <int G>
 __global__ void __launch_bounds__(256) k_extract3_count(int32_t n, const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ ci, const int8_t *__restrict__ cf,
-                                                        const int32_t *__restrict__ rank, int32_t *__restrict__ cff,
-                                                        int32_t *__restrict__ cfc, int32_t *__restrict__ ccf) {
+                                                        int32_t *__restrict__ cff, int32_t *__restrict__ cfc,
+                                                        int32_t *__restrict__ ccf) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
     if (row >= n) return;
-    int8_t me = cf[row];
-    if (me != CF_F && me != CF_C) return;
+    const int8_t me = cf[row];
     int32_t nf = 0, nc = 0;
-    for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
-        int8_t c = cf[ci[k]];
-        nf += c == CF_F;
-        nc += c == CF_C;
-    }
-    nf = group_sum<G>(nf);
-    nc = group_sum<G>(nc);
-    if (lane == 0) {
-        if (me == CF_F) {
-            cff[rank[row]] = nf;
-            cfc[rank[row]] = nc;
-        } else {
-            ccf[rank[row]] = nf;
+    if (me == CF_F || me == CF_C) {
+        for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += G) {
+            int8_t c = cf[ci[k]];
+            nf += c == CF_F;
+            nc += c == CF_C;
         }
+        nf = group_sum<G>(nf);
+        nc = group_sum<G>(nc);
+    }
+    if (lane == 0) {
+        cff[row] = me == CF_F ? nf : 0;
+        cfc[row] = me == CF_F ? nc : 0;
+        ccf[row] = me == CF_C ? nf : 0;
     }
 }
 
+// off: the three scans of the counts (n + 1 entries each: A_ff, A_fc, A_cf);
+// each row also writes its block row pointers, thread 0 their ends.
 template <int G>
 __global__ void __launch_bounds__(256) k_extract3_fill(int32_t n, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                        const int8_t *__restrict__ cf, const int32_t *__restrict__ rank,
-                                                       const int32_t *__restrict__ ffrp, int32_t *__restrict__ ffci,
-                                                       double *__restrict__ ffv, const int32_t *__restrict__ fcrp,
+                                                       const int32_t *__restrict__ off, int32_t nF, int32_t nC,
+                                                       int32_t *__restrict__ ffrp, int32_t *__restrict__ ffci,
+                                                       double *__restrict__ ffv, int32_t *__restrict__ fcrp,
                                                        int32_t *__restrict__ fcci, double *__restrict__ fcv,
-                                                       const int32_t *__restrict__ cfrp, int32_t *__restrict__ cfci,
+                                                       int32_t *__restrict__ cfrp, int32_t *__restrict__ cfci,
                                                        double *__restrict__ cfv) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
+    const int64_t n1 = (int64_t)n + 1;
+    if (t == 0) {
+        ffrp[nF] = off[n];
+        fcrp[nF] = off[n1 + n];
+        cfrp[nC] = off[2 * n1 + n];
+    }
     if (row >= n) return;
     int8_t me = cf[row];
     if (me != CF_F && me != CF_C) return;
     const bool frow = me == CF_F;
-    int32_t r = rank[row];
-    int32_t wf = frow ? ffrp[r] : cfrp[r];
-    int32_t wc = frow ? fcrp[r] : 0;
+    const int32_t r = rank[row];
+    int32_t wf = frow ? off[row] : off[2 * n1 + row];
+    int32_t wc = frow ? off[n1 + row] : 0;
+    if (lane == 0) {
+        if (frow) {
+            ffrp[r] = wf;
+            fcrp[r] = wc;
+        } else {
+            cfrp[r] = wf;
+        }
+    }
     int32_t *oci_f = frow ? ffci : cfci;
     double *ov_f = frow ? ffv : cfv;
     int32_t e = rp[row + 1];
@@ -722,27 +746,52 @@ __global__ void __launch_bounds__(256) k_extract3_fill(int32_t n, const int32_t 
     }
 }
 
+ExtractPlan extract_begin(const CsrView &A, const int8_t *cf, hipStream_t s) {
+    ExtractPlan P;
+    const int32_t n = A.nr;
+    P.n = n;
+    P.off.alloc((size_t)3 * ((size_t)n + 1), s);
+    DBuf<int32_t> cnt((size_t)3 * std::max<int32_t>(n, 1), s);
+    int32_t *off = P.off.p;
+    if (n > 0) {
+        dispatch_group(lanes_for(A.nnz, n), [&]<int G>() {
+            k_extract3_count<G><<<grid_for((int64_t)n * G, 256), 256, 0, s>>>(n, A.rp, A.ci, cf, cnt.p, cnt.p + n,
+                                                                              cnt.p + 2 * (size_t)n);
+        });
+        AIRG_LAUNCH_CHECK();
+    }
+    exclusive_scans({cnt.p, cnt.p + n, cnt.p + 2 * (size_t)n}, {off, off + (n + 1), off + 2 * ((size_t)n + 1)},
+                    {n, n, n}, s);
+    return P;
+}
+
+std::vector<const int32_t *> ExtractPlan::totals() const {
+    const size_t n1 = (size_t)n + 1;
+    return {off.p + n, off.p + n1 + n, off.p + 2 * n1 + n};
+}
+
+void extract_finish(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC,
+                    const int32_t *tot, ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s) {
+    AIRG_REQUIRE(P.n == A.nr, ST_INVALID_ARG, "extraction plan does not match");
+    for (int k = 0; k < 3; ++k) AIRG_REQUIRE(tot[k] >= 0, ST_LIMIT, "prefix sum exceeds the int32 index range");
+    Aff.alloc(nF, nF, tot[0], s);
+    Afc.alloc(nF, nC, tot[1], s);
+    Acf.alloc(nC, nF, tot[2], s);
+    if (A.nr == 0) return;
+    dispatch_group(lanes_for(A.nnz, A.nr), [&]<int G>() {
+        k_extract3_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(
+            A.nr, A.rp, A.ci, A.v, cf, rank, P.off.p, nF, nC, Aff.rp.p, Aff.ci.p, Aff.v.p, Afc.rp.p, Afc.ci.p,
+            Afc.v.p, Acf.rp.p, Acf.ci.p, Acf.v.p);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
 void extract_fc_blocks(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, Csr &Aff,
                        Csr &Afc, Csr &Acf, hipStream_t s) {
-    Aff.nr = nF, Aff.nc = nF;
-    Afc.nr = nF, Afc.nc = nC;
-    Acf.nr = nC, Acf.nc = nF;
-    for (Csr *M : {&Aff, &Afc, &Acf}) M->rp.alloc((size_t)M->nr + 1, s);
-    DBuf<int32_t> cff((size_t)nF + 1, s), cfc((size_t)nF + 1, s), ccf((size_t)nC + 1, s);
-    int g = lanes_for(A.nnz, A.nr);
-    dispatch_group(g, [&]<int G>() {
-        k_extract3_count<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(A.nr, A.rp, A.ci, cf, rank, cff.p,
-                                                                             cfc.p, ccf.p);
-    });
-    AIRG_LAUNCH_CHECK();
-    exclusive_scans({cff.p, cfc.p, ccf.p}, {Aff.rp.p, Afc.rp.p, Acf.rp.p}, {nF, nF, nC}, s);
-    resolve_sizes({&Aff, &Afc, &Acf}, s);
-    dispatch_group(g, [&]<int G>() {
-        k_extract3_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(
-            A.nr, A.rp, A.ci, A.v, cf, rank, Aff.rp.p, Aff.ci.p, Aff.v.p, Afc.rp.p, Afc.ci.p, Afc.v.p, Acf.rp.p,
-            Acf.ci.p, Acf.v.p);
-    });
-    AIRG_LAUNCH_CHECK();
+    ExtractPlan P = extract_begin(A, cf, s);
+    int32_t tot[3];
+    read_ints(P.totals(), {1, 1, 1}, tot, s);
+    extract_finish(A, cf, rank, nF, nC, tot, P, Aff, Afc, Acf, s);
 }
 
 Csr extract_block(const CsrView &A, const int8_t *cf, const int32_t *rank, int8_t rowsel, int8_t colsel,

@@ -43,11 +43,12 @@ std::pair<int32_t, int32_t> cf_ranks(const int8_t *cf, int32_t n, int32_t *rank,
 struct CfCounts {
     int32_t nF, nC, nT;
 };
-// extra_src, when given, is one more device int read back with the counts
-// into *extra_out.  flags3, when given, holds the class indicators already
-// (3 n ints: cf == F, cf == C, cf == T, as the DDC pass writes them).
-CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s, const int32_t *extra_src = nullptr,
-                   int32_t *extra_out = nullptr, const int32_t *flags3 = nullptr);
+// extra: device ints read back with the counts into extra_out[0..].  flags3,
+// when given, holds the class indicators already (3 n ints: cf == F,
+// cf == C, cf == T, as the DDC pass writes them).
+CfCounts cf_ranks3(const int8_t *cf, int32_t n, int32_t *rank, hipStream_t s,
+                   const std::vector<const int32_t *> &extra = {}, int32_t *extra_out = nullptr,
+                   const int32_t *flags3 = nullptr);
 // cf_ranks3 plus, at the segment boundaries d_off[0..na] (device, ascending,
 // d_off[na] = n), the numbers of F, C and terminal rows before each boundary:
 // h_bounds[3 p + {0, 1, 2}] (host, 3 (na + 1) entries).
@@ -63,6 +64,17 @@ Csr extract_block(const CsrView &A, const int8_t *cf, const int32_t *rank, int8_
 // A_ff, A_fc and A_cf together (one pass, one host synchronisation).
 void extract_fc_blocks(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, Csr &Aff,
                        Csr &Afc, Csr &Acf, hipStream_t s);
+// The same in two halves: the counts and their scans need only cf, so the
+// three block sizes (device ints at totals()) can be read back with other
+// values; extract_finish takes them (tot[0..2]) and fills the blocks.
+struct ExtractPlan {
+    int32_t n = 0;
+    DBuf<int32_t> off;   // 3 (n + 1): exclusive scans of the per-row counts of A_ff, A_fc, A_cf
+    std::vector<const int32_t *> totals() const;
+};
+ExtractPlan extract_begin(const CsrView &A, const int8_t *cf, hipStream_t s);
+void extract_finish(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC,
+                    const int32_t *tot, ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s);
 
 // Keep entries with |x| >= tau * max_j |x_rj| (and the diagonal when
 // keep_diag); negate scales every kept value by -1 when set.

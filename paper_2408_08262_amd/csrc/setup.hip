@@ -154,9 +154,12 @@ CfParams cf_params(const airg_opts &o, uint64_t seed) {
 // CF splitting of one level; fills cf and rank, returns (nF, nC).  When
 // nnz_out is given, A.nnz is only an upper bound (A's rows were kept by a
 // drop whose total was not read) and the exact count A.rp[nr] is read back
-// with the splitting's counts into *nnz_out.
+// with the splitting's counts into *nnz_out.  With xp, the extraction's
+// counting half runs too and the three block sizes come back with the
+// counts into xtot[0..2].
 std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl, DBuf<int8_t> &cf,
-                                  DBuf<int32_t> &rank, hipStream_t s, int64_t *nnz_out = nullptr) {
+                                  DBuf<int32_t> &rank, hipStream_t s, int64_t *nnz_out = nullptr,
+                                  ExtractPlan *xp = nullptr, int32_t *xtot = nullptr) {
     int32_t n = A.nr;
     cf.alloc((size_t)n, s);
     rank.alloc((size_t)n, s);
@@ -167,9 +170,16 @@ std::pair<int32_t, int32_t> split(const CsrView &A, const airg_opts &o, uint64_t
     if (ad < 0.0) ad = ddc_fraction_threshold(A, cf0.p, o.ddc_fraction, s);
     DBuf<int32_t> flags((size_t)3 * n, s);   // class indicators for the rank scans
     ddc(A, ad, cf0.p, cf.p, nullptr, s, flags.p);
-    int32_t nz = 0;
-    CfCounts c = cf_ranks3(cf.p, n, rank.p, s, nnz_out ? A.rp + n : nullptr, nnz_out ? &nz : nullptr, flags.p);
-    if (nnz_out) *nnz_out = nz;
+    std::vector<const int32_t *> extra;
+    if (nnz_out) extra.push_back(A.rp + n);
+    if (xp) {
+        *xp = extract_begin(A, cf.p, s);
+        for (const int32_t *t : xp->totals()) extra.push_back(t);
+    }
+    int32_t got[4] = {0, 0, 0, 0};
+    CfCounts c = cf_ranks3(cf.p, n, rank.p, s, extra, got, flags.p);
+    if (nnz_out) *nnz_out = got[0];
+    if (xp) std::copy(got + (nnz_out ? 1 : 0), got + (nnz_out ? 4 : 3), xtot);
     return {c.nF, c.nC};
 }
 
@@ -207,7 +217,8 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
                     const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, DBuf<int32_t> &fidx,
                     DBuf<int32_t> &cidx, Csr &Aff, Csr *Afc, PolyInfo &poly, Csr &Ainv, Csr &Z, Csr &W, Csr &Ac,
                     Timer &tm, hipStream_t s, Branch *br = nullptr,
-                    const std::function<void(hipStream_t)> &pre = nullptr) {
+                    const std::function<void(hipStream_t)> &pre = nullptr, ExtractPlan *xp = nullptr,
+                    const int32_t *xtot = nullptr) {
     int32_t n = A.nr;
     int m = o.poly_order + 1;
     Csr P, AP;
@@ -232,7 +243,8 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     cidx.alloc((size_t)nC + 1, s);
     cf_index_lists(cf, rank, n, fidx.p, cidx.p, s);
     Csr fc, Acf;
-    extract_fc_blocks(A, cf, rank, nF, nC, Aff, fc, Acf, s);
+    if (xp) extract_finish(A, cf, rank, nF, nC, xtot, *xp, Aff, fc, Acf, s);
+    else extract_fc_blocks(A, cf, rank, nF, nC, Aff, fc, Acf, s);
     if (Afc) *Afc = std::move(fc);
     tm.begin(AIRG_PHASE_POLY);
     // With the first-order pattern, the row bins of the fixed-sparsity
@@ -636,10 +648,12 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
         // below the top, A's entry count is an upper bound until read: with
         // the splitting's counts, or on its own for a coarsest level
         const bool bound = l > 0;
+        ExtractPlan xplan;
+        int32_t xtot[3] = {0, 0, 0};
         if (!coarsest) {
             tm.begin(AIRG_PHASE_CF);
             int64_t nz = 0;
-            auto [nF, nC] = split(view(L.A), o, seed, l, L.cf, L.rank, s, bound ? &nz : nullptr);
+            auto [nF, nC] = split(view(L.A), o, seed, l, L.cf, L.rank, s, bound ? &nz : nullptr, &xplan, xtot);
             if (bound) L.A.nnz = nz;
             L.nF = nF;
             L.nC = nC;
@@ -672,7 +686,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             if (l > 0) solve_ops(HH, l - 1, st);
         };
         complete_level(view(L.A), o, seed, l, nullptr, L.cf.p, L.rank.p, L.nF, L.nC, L.fidx, L.cidx, L.Aff, &L.Afc,
-                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br, pre);
+                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br, pre, &xplan, xtot);
         next->n = next->A.nr;
         H->lv.push_back(std::move(next));
     }
