@@ -685,7 +685,8 @@ __global__ void __launch_bounds__(256) k_extract3_count(int32_t n, const int32_t
 }
 
 // off: the three scans of the counts (n + 1 entries each: A_ff, A_fc, A_cf);
-// each row also writes its block row pointers, thread 0 their ends.
+// each row also writes its block row pointers (thread 0 their ends) and,
+// when fidx / cidx are given, its entry in the F or C index list.
 template <int G>
 __global__ void __launch_bounds__(256) k_extract3_fill(int32_t n, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci, const double *__restrict__ v,
@@ -695,7 +696,8 @@ __global__ void __launch_bounds__(256) k_extract3_fill(int32_t n, const int32_t 
                                                        double *__restrict__ ffv, int32_t *__restrict__ fcrp,
                                                        int32_t *__restrict__ fcci, double *__restrict__ fcv,
                                                        int32_t *__restrict__ cfrp, int32_t *__restrict__ cfci,
-                                                       double *__restrict__ cfv) {
+                                                       double *__restrict__ cfv, int32_t *__restrict__ fidx,
+                                                       int32_t *__restrict__ cidx) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t row = (int32_t)(t / G);
     int lane = group_lane<G>();
@@ -716,8 +718,10 @@ __global__ void __launch_bounds__(256) k_extract3_fill(int32_t n, const int32_t 
         if (frow) {
             ffrp[r] = wf;
             fcrp[r] = wc;
+            if (fidx) fidx[r] = row;
         } else {
             cfrp[r] = wf;
+            if (cidx) cidx[r] = row;
         }
     }
     int32_t *oci_f = frow ? ffci : cfci;
@@ -771,7 +775,8 @@ std::vector<const int32_t *> ExtractPlan::totals() const {
 }
 
 void extract_finish(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC,
-                    const int32_t *tot, ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s) {
+                    const int32_t *tot, ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s, int32_t *fidx,
+                    int32_t *cidx) {
     AIRG_REQUIRE(P.n == A.nr, ST_INVALID_ARG, "extraction plan does not match");
     for (int k = 0; k < 3; ++k) AIRG_REQUIRE(tot[k] >= 0, ST_LIMIT, "prefix sum exceeds the int32 index range");
     Aff.alloc(nF, nF, tot[0], s);
@@ -781,7 +786,7 @@ void extract_finish(const CsrView &A, const int8_t *cf, const int32_t *rank, int
     dispatch_group(lanes_for(A.nnz, A.nr), [&]<int G>() {
         k_extract3_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(
             A.nr, A.rp, A.ci, A.v, cf, rank, P.off.p, nF, nC, Aff.rp.p, Aff.ci.p, Aff.v.p, Afc.rp.p, Afc.ci.p,
-            Afc.v.p, Acf.rp.p, Acf.ci.p, Acf.v.p);
+            Afc.v.p, Acf.rp.p, Acf.ci.p, Acf.v.p, fidx, cidx);
     });
     AIRG_LAUNCH_CHECK();
 }

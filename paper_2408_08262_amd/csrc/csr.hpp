@@ -73,8 +73,10 @@ struct ExtractPlan {
     std::vector<const int32_t *> totals() const;
 };
 ExtractPlan extract_begin(const CsrView &A, const int8_t *cf, hipStream_t s);
+// fidx / cidx (nullable) receive the index lists of cf_index_lists.
 void extract_finish(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC,
-                    const int32_t *tot, ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s);
+                    const int32_t *tot, ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s,
+                    int32_t *fidx = nullptr, int32_t *cidx = nullptr);
 
 // Keep entries with |x| >= tau * max_j |x_rj| (and the diagonal when
 // keep_diag); negate scales every kept value by -1 when set.

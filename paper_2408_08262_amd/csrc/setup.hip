@@ -241,10 +241,13 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     tm.begin(AIRG_PHASE_EXTRACT);
     fidx.alloc((size_t)nF + 1, s);
     cidx.alloc((size_t)nC + 1, s);
-    cf_index_lists(cf, rank, n, fidx.p, cidx.p, s);
     Csr fc, Acf;
-    if (xp) extract_finish(A, cf, rank, nF, nC, xtot, *xp, Aff, fc, Acf, s);
-    else extract_fc_blocks(A, cf, rank, nF, nC, Aff, fc, Acf, s);
+    if (xp) {
+        extract_finish(A, cf, rank, nF, nC, xtot, *xp, Aff, fc, Acf, s, fidx.p, cidx.p);
+    } else {
+        cf_index_lists(cf, rank, n, fidx.p, cidx.p, s);
+        extract_fc_blocks(A, cf, rank, nF, nC, Aff, fc, Acf, s);
+    }
     if (Afc) *Afc = std::move(fc);
     tm.begin(AIRG_PHASE_POLY);
     // With the first-order pattern, the row bins of the fixed-sparsity
