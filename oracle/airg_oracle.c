@@ -7,7 +7,7 @@
  *
  * Plain double-precision loops in natural index order, single threaded,
  * compiled with -O2 -ffp-contract=off.  Where the paper is silent or garbled
- * the reading taken is stated at the function (and listed in the design doc).
+ * the reading taken is stated at the function.
  */
 #include "airg_oracle.h"
 
