@@ -86,6 +86,7 @@ def lib():
             "orc_level_build": (C.c_int, [cs, P(Params), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                           cs, cs, cs, cs]),
             "orc_setup": (C.c_void_p, [cs, P(Params)]),
+            "orc_setup_replay": (C.c_void_p, [cs, P(Params), C.c_int32, C.c_void_p]),
             "orc_level_renumeric": (C.c_int, [cs, C.c_void_p, P(Params), C.c_int32, C.c_void_p, cs, cs, cs,
                                               C.c_void_p, cs, cs, cs, cs]),
             "orc_resetup": (C.c_void_p, [C.c_void_p, C.c_void_p]),
@@ -388,11 +389,22 @@ class Hierarchy:
 
     MATS = {"A": 0, "Ainv": 1, "Z": 2, "W": 3, "Aff": 4, "Afc": 5}
 
-    def __init__(self, A, params):
+    ALPHA_STRIDE = 16
+
+    def __init__(self, A, params, alphas=None):
+        """alphas (optional): one coefficient vector per level, used instead of
+        the coefficients computed from the random rhs (hierarchy replay)."""
         self._a = _csr_in(A)
         self.params = params
         self.n = len(self._a.rp) - 1
-        self.h = lib().orc_setup(self._a.ref, C.byref(params))
+        if alphas is None:
+            self.h = lib().orc_setup(self._a.ref, C.byref(params))
+        else:
+            tab = np.zeros((max(len(alphas), 1), self.ALPHA_STRIDE))
+            for l, a in enumerate(alphas):
+                a = np.asarray(a, np.float64)
+                tab[l, :len(a)] = a
+            self.h = lib().orc_setup_replay(self._a.ref, C.byref(params), len(alphas), _ptr(tab))
         if not self.h:
             raise ValueError("oracle setup rejected the matrix")
 

@@ -889,7 +889,34 @@ static int canonical_copy(const orc_csr *A, orc_csr *B)
  * with fewer points than the polynomial order.  The coarsest level carries a
  * fixed-sparsity polynomial of order coarse_poly_order built on its whole
  * matrix (truncation with a GMRES-polynomial coarse solve). */
+static orc_hier *setup_levels(const orc_csr *A0, const orc_params *p, int32_t nlev_in, const double *alpha_in);
+
 orc_hier *orc_setup(const orc_csr *A0, const orc_params *p)
+{
+    return setup_levels(A0, p, 0, NULL);
+}
+
+/* The same setup with the polynomial coefficients of levels 0 .. nlev_in-1
+ * given (alpha_in holds ORC_ALPHA_STRIDE values per level, the level's m
+ * coefficients first) instead of computed from the random rhs.  Every other
+ * step -- splittings, extraction, assembly, products, drops and termination --
+ * is taken as in orc_setup.  This is the parity harness's replay: fed the
+ * coefficients that another implementation computed, it rebuilds that
+ * implementation's hierarchy without depending on the rounding of the
+ * transcendental functions and reductions behind the coefficients. */
+orc_hier *orc_setup_replay(const orc_csr *A0, const orc_params *p, int32_t nlev_in, const double *alpha_in)
+{
+    return setup_levels(A0, p, nlev_in, alpha_in);
+}
+
+static void level_coeffs(const orc_csr *A, const orc_params *p, int32_t l, int32_t m, int32_t nlev_in,
+                         const double *alpha_in, double *alpha)
+{
+    if (alpha_in && l < nlev_in) memcpy(alpha, alpha_in + (size_t)l * ORC_ALPHA_STRIDE, (size_t)m * sizeof(double));
+    else orc_gmres_poly(A, p->seed, l, m, alpha);
+}
+
+static orc_hier *setup_levels(const orc_csr *A0, const orc_params *p, int32_t nlev_in, const double *alpha_in)
 {
     orc_hier *h = (orc_hier *)xcalloc(1, sizeof(orc_hier));
     h->p = *p;
@@ -914,7 +941,7 @@ orc_hier *orc_setup(const orc_csr *A0, const orc_params *p)
             int32_t m = p->coarse_poly_order + 1;
             L->alpha = (double *)xcalloc((size_t)m, sizeof(double));
             L->nalpha = m;
-            orc_gmres_poly(&L->A, p->seed, l, m, L->alpha);
+            level_coeffs(&L->A, p, l, m, nlev_in, alpha_in, L->alpha);
             if (!p->coarse_matrix_free) assembled_inverse(&L->A, p->poly_sparsity_order, L->alpha, m, &L->Ainv);
             L->nF = n;
             L->nC = 0;
@@ -935,7 +962,7 @@ orc_hier *orc_setup(const orc_csr *A0, const orc_params *p)
         orc_submatrix(&L->A, L->cf, ORC_C, ORC_F, &Acf);
         L->alpha = (double *)xcalloc((size_t)m, sizeof(double));
         L->nalpha = m;
-        orc_gmres_poly(&L->Aff, p->seed, l, m, L->alpha);
+        level_coeffs(&L->Aff, p, l, m, nlev_in, alpha_in, L->alpha);
         assembled_inverse(&L->Aff, p->poly_sparsity_order, L->alpha, m, &L->Ainv);
         orc_restrictor(&Acf, &L->Ainv, p->drop_R, &L->Z);
         orc_onepoint_w(&L->A, L->cf, p->onepoint_weight, &L->W);

@@ -101,6 +101,11 @@ int orc_level_build(const orc_csr *A, const orc_params *p, int32_t level, const 
                     int8_t *cf, double *alpha_out, orc_csr *Ainv, orc_csr *Z, orc_csr *W, orc_csr *Ac);
 
 orc_hier *orc_setup(const orc_csr *A, const orc_params *p);
+/* orc_setup with the coefficients of levels 0 .. nlev_in-1 given:
+ * alpha_in[l * ORC_ALPHA_STRIDE + k], k < m of that level (poly_order + 1,
+ * or coarse_poly_order + 1 on the coarsest level). */
+#define ORC_ALPHA_STRIDE 16
+orc_hier *orc_setup_replay(const orc_csr *A, const orc_params *p, int32_t nlev_in, const double *alpha_in);
 
 /* Numeric re-setup (Results: reuse of the CF splitting and symbolic products
  * with a padded sparsity).  One level: given the new values of A on the

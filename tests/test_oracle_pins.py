@@ -342,13 +342,59 @@ def test_fixed_sparsity_polynomial():
     assert not np.allclose(got, masked_exact)
 
 
+
+def golden_rows(rows):
+    rp, ci, v = [0], [], []
+    for row in rows:
+        for c, x in row:
+            ci.append(c)
+            v.append(x)
+        rp.append(len(ci))
+    return (np.array(rp), np.array(ci), np.array(v))
+
+
+@pytest.mark.parametrize("case", load("ddc_fraction_hand.json")["cases"], ids=lambda c: c["name"])
+def test_ddc_fraction_threshold_hand_cases(case):
+    """Hand-worked thresholds: the closest count, ties to the larger k, strict
+    comparison with the boundary, the ceiling target over all F rows, and an
+    infinite theta counted but not part of theta_max."""
+    A = golden_rows(case["rows"])
+    cf = np.array(case["cf"], np.int8)
+    assert O.ddc_fraction_threshold(A, cf, case["fraction"]) == case["alpha_diag"]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ddc_fraction_threshold_brute_force(seed):
+    """Brute force over all 1001 boundaries from theta computed densely."""
+    P = dg_square(16)
+    A = csr_of(P)
+    D = dense(A)
+    G = O.sym_graph(A, O.strength(A, 0.5))
+    deg, h = O.pmisr_keys(G, seed, 0)
+    cf, _ = O.pmisr(G, deg, h, 3)
+    F = cf == O.F_POINT
+    off = np.abs(D) * (1 - np.eye(D.shape[0]))
+    theta = off[:, F].sum(1)[F] / np.abs(np.diag(D))[F]
+    for frac in (0.05, 0.1, 0.3):
+        target = int(np.ceil(frac * F.sum()))
+        tmax = theta[np.isfinite(theta)].max()
+        best, bestd = None, None
+        for k in range(1001):
+            bk = tmax * k / 1000.0
+            d = abs(int((theta > bk).sum()) - target)
+            if bestd is None or d <= bestd:
+                best, bestd = bk, d
+        assert O.ddc_fraction_threshold(A, cf, frac) == pytest.approx(best, rel=1e-12)
+
 # -------------------------------------------- grid transfer, RAP, cycle ---
-def test_onepoint_w_brute_force():
+@pytest.mark.parametrize("mode", [0, 1])
+def test_onepoint_w_brute_force(mode):
+    """Weight 1 (mode 0) or -a_ij*/a_ii (mode 1) at the strongest neighbour."""
     P = dg_square(10)
     A = csr_of(P)
     D = dense(A)
     cf = O.cf_split(A, O.default_params(seed=4), 0)
-    W = dense(O.onepoint_w(A, cf, 0))
+    W = dense(O.onepoint_w(A, cf, mode))
     F = np.nonzero(cf == O.F_POINT)[0]
     C = np.nonzero(cf == O.C_POINT)[0]
     crank = {c: k for k, c in enumerate(C)}
@@ -361,7 +407,7 @@ def test_onepoint_w_brute_force():
         j = int(np.argmax(off))                       # first maximum = smallest index
         assert cf[j] == O.C_POINT                     # strongest neighbour of an F point is C
         want = np.zeros(len(C))
-        want[crank[j]] = 1.0
+        want[crank[j]] = 1.0 if mode == 0 else -D[i, j] / D[i, i]
         assert np.array_equal(W[r], want)
 
 
@@ -652,3 +698,89 @@ def test_sparsity_order_two_hierarchy_solves():
         S = O.power_pattern(Aff, s)
         assert np.array_equal(Ainv[0], S[0]) and np.array_equal(Ainv[1], S[1])
     assert its[2] <= its[1]
+
+
+# ------------------------------------------------------------ complexities --
+def test_complexity_hand_worked_two_level_hierarchy():
+    g = load("complexity_hand.json")
+    A = golden_rows(g["rows"])
+    for vc, key in ((3, "storage_vc3"), (1, "storage_vc1")):
+        H = O.Hierarchy(A, O.default_params(coarse_iters=vc, **g["params"]))
+        assert H.nlevels == g["levels"]
+        gr, op, st = H.complexity()
+        assert gr == pytest.approx(g["grid"], rel=1e-15)
+        assert op == pytest.approx(g["operator"], rel=1e-15)
+        assert st == pytest.approx(g[key], rel=1e-15)
+
+
+def test_complexity_single_level_diagonal():
+    """A diagonal matrix is its own coarsest level: grid = operator = 1 and the
+    storage is Ainv (n entries) plus A when more than one coarse iteration runs."""
+    n = 10
+    A = (np.arange(n + 1), np.arange(n), np.linspace(1.0, 2.0, n))
+    for vc, want in ((1, 1.0), (3, 2.0)):
+        H = O.Hierarchy(A, O.default_params(coarse_iters=vc))
+        assert H.nlevels == 1
+        assert H.complexity() == (1.0, 1.0, want)
+
+
+@pytest.mark.parametrize("make,kw", [(lambda: dg_square(24), {}), (lambda: p0_square(32), {"coarse_iters": 1}),
+                                     (lambda: dg_square(16), {"strong_threshold": 0.0, "max_levels": 40})])
+def test_complexity_counted_from_the_assembled_matrices(make, kw):
+    """The storage equation counted from the hierarchy's matrices, with R and P
+    assembled densely as [Z I] and [W; I] in the level's full index space."""
+    P = make()
+    prm = O.default_params(seed=P.seed, **kw)
+    H = O.Hierarchy(csr_of(P), prm)
+    L = H.nlevels
+    assert L >= 3
+    nnz = lambda M: int(np.count_nonzero(pattern(M)))
+    A = [H.matrix(l, "A") for l in range(L)]
+    n = [len(a[0]) - 1 for a in A]
+    store = 0
+    for l in range(L - 1):
+        cf = H.cf(l)
+        F, C = np.nonzero(cf == O.F_POINT)[0], np.nonzero(cf == O.C_POINT)[0]
+        R = np.zeros((len(C), n[l]), bool)
+        R[:, F] = pattern(H.matrix(l, "Z"))
+        R[np.arange(len(C)), C] = True
+        Pm = np.zeros((n[l], len(C)), bool)
+        Pm[F] = pattern(H.matrix(l, "W"))
+        Pm[C, np.arange(len(C))] = True
+        Dl = pattern(A[l])
+        assert np.array_equal(pattern(H.matrix(l, "Aff")), Dl[np.ix_(F, F)])
+        assert np.array_equal(pattern(H.matrix(l, "Afc")), Dl[np.ix_(F, C)])
+        store += nnz(H.matrix(l, "Ainv")) + Dl[np.ix_(F, F)].sum() + Dl[np.ix_(F, C)].sum() + R.sum() + Pm.sum()
+    store += nnz(H.matrix(L - 1, "Ainv")) + min(prm.coarse_iters - 1, 1) * nnz(A[L - 1])
+    gr, op, st = H.complexity()
+    assert gr == pytest.approx(sum(n) / n[0], rel=1e-14)
+    assert op == pytest.approx(sum(nnz(a) for a in A) / nnz(A[0]), rel=1e-14)
+    assert st == pytest.approx(store / nnz(A[0]), rel=1e-14)
+
+
+# ------------------------------------------------------------------ replay --
+def test_setup_replay_with_own_coefficients_is_identical():
+    """Fed its own coefficients, the replay setup rebuilds the same hierarchy
+    bit for bit; fed other coefficients, only the values change."""
+    P = dg_square(24)
+    A = csr_of(P)
+    prm = O.default_params(seed=P.seed)
+    H = O.Hierarchy(A, prm)
+    al = [H.alpha(l) for l in range(H.nlevels)]
+    R = O.Hierarchy(A, prm, alphas=al)
+    assert R.nlevels == H.nlevels
+    for l in range(H.nlevels):
+        assert np.array_equal(R.alpha(l), H.alpha(l))
+        for key in ("A", "Ainv", "Z", "W"):
+            a, b = H.matrix(l, key), R.matrix(l, key)
+            assert (a is None) == (b is None)
+            if a is not None:
+                assert all(np.array_equal(x, y) for x, y in zip(a[:3], b[:3])), (l, key)
+    # level-0 coefficients scaled by 1 + 2^-20: level 0's Ainv changes, its splitting does not
+    al2 = [a.copy() for a in al]
+    al2[0] = al2[0] * (1 + 2.0 ** -20)
+    R2 = O.Hierarchy(A, prm, alphas=al2[:1])
+    assert np.array_equal(R2.cf(0), H.cf(0))
+    assert np.array_equal(R2.alpha(0), al2[0])
+    assert not np.array_equal(R2.matrix(0, "Ainv")[2], H.matrix(0, "Ainv")[2])
+    assert np.array_equal(R2.alpha(1), O.Hierarchy(A, prm, alphas=al2[:1]).alpha(1))
