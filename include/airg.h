@@ -195,6 +195,17 @@ airg_status airg_resetup(airg_handle *h, const double *d_val, void *hip_stream);
 airg_status airg_vcycle(const airg_handle *h, int32_t segment, const double *d_g, double *d_e, int32_t precision,
                         void *hip_stream);
 
+/* One batched FP32 V-cycle (the preconditioner of the batched solve, the
+ * batched form of airg_solve): d_e = V(d_g) for nrhs right-hand sides, n x
+ * nrhs row-major FP64 device vectors in natural row order, every segment's
+ * rows cycled through that segment's own hierarchy, all segments and
+ * right-hand sides in one SpMM launch per stage (replayed from the captured
+ * HIP graph when use_graph = 1).  nrhs must be 1, 2, 4 or 8.  Only for a
+ * handle in the batched form (segments with outer = FGMRES and
+ * precond_precision = 32); builds the batched operators on first use, as
+ * airg_solve does.  Synchronises hip_stream. */
+airg_status airg_batch_vcycle(airg_handle *h, int32_t nrhs, const double *d_g, double *d_e, void *hip_stream);
+
 /* Describes one level of one segment; h_cf (nullable, n entries) receives
  * the CF markers (1 = F, 2 = C; all 1 on the coarsest level).  segment >= 0
  * selects the forward hierarchy of that segment (0 for a single problem);

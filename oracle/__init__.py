@@ -23,7 +23,7 @@ F_POINT, C_POINT = 1, 2
 
 def build():
     """Compile the oracle shared library (always recompiles)."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp", "-fPIC", "-shared",
            "-o", LIB_PATH + ".tmp", SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)
@@ -57,6 +57,8 @@ def lib():
         cs = P(_Csr)
         sig = {
             "orc_default_params": (None, [P(Params)]),
+            "orc_set_threads": (None, [C.c_int32]),
+            "orc_get_threads": (C.c_int32, []),
             "orc_csr_free": (None, [cs]),
             "orc_splitmix64": (C.c_uint64, [C.c_uint64]),
             "orc_counter": (C.c_uint64, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64]),
@@ -108,6 +110,15 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's row-parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
 
 
 def default_params(**kw):

@@ -5,9 +5,15 @@
  * benchmark's CPU-baseline leg to check the HIP library; never part of the
  * product path.  Shares no code with the HIP library.
  *
- * Plain double-precision loops in natural index order, single threaded,
- * compiled with -O2 -ffp-contract=off.  Where the paper is silent or garbled
- * the reading taken is stated at the function.
+ * Plain double-precision loops in natural index order, compiled with -O2
+ * -ffp-contract=off.  Where the paper is silent or garbled the reading taken
+ * is stated at the function.
+ *
+ * Threads: loops whose iterations are independent rows (or entries) may run
+ * in parallel through OpenMP ("#pragma omp parallel for").  Every output
+ * element is still computed by one thread with the same sequence of
+ * operations, and every sum over many rows (norms, dot products) stays a
+ * single sequential loop, so the results do not depend on the thread count.
  */
 #include "airg_oracle.h"
 
@@ -15,8 +21,29 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_MAX_LEVELS 128
+
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int32_t orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static void *xmalloc(size_t n)
 {
@@ -101,6 +128,7 @@ uint64_t orc_counter(uint64_t seed, uint32_t stream, uint32_t level, uint64_t i)
 /* ------------------------------------------------------------------------ */
 void orc_strength(const orc_csr *A, double alpha, uint8_t *strong)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < A->nr; ++i) {
         double M = 0.0;
         for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
@@ -193,8 +221,10 @@ int32_t orc_pmisr(const orc_csr *G, const int32_t *deg, const uint32_t *h, int32
     for (;;) {
         if (max_rounds > 0 && rounds >= max_rounds) break;
         int64_t nu = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nu)
         for (int64_t i = 0; i < n; ++i) nu += cf[i] == ORC_U;
         if (nu == 0) break;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             inD[i] = 0;
             if (cf[i] != ORC_U) continue;
@@ -205,8 +235,10 @@ int32_t orc_pmisr(const orc_csr *G, const int32_t *deg, const uint32_t *h, int32
             }
             inD[i] = (uint8_t)isMin;
         }
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i)
             if (inD[i]) cf[i] = ORC_F;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             if (cf[i] != ORC_U) continue;
             for (int64_t k = G->rp[i]; k < G->rp[i + 1]; ++k)
@@ -246,6 +278,7 @@ double orc_ddc_fraction_threshold(const orc_csr *A, const int8_t *cf, double fra
     int64_t n = A->nr, nF = 0;
     double tmax = 0.0;
     double *th = (double *)xmalloc((size_t)n * sizeof(double));
+#pragma omp parallel for schedule(static) reduction(+ : nF) reduction(max : tmax)
     for (int64_t i = 0; i < n; ++i) {
         th[i] = -1.0;
         if (cf[i] != ORC_F) continue;
@@ -259,6 +292,7 @@ double orc_ddc_fraction_threshold(const orc_csr *A, const int8_t *cf, double fra
     for (int k = 0; k <= 1000; ++k) {
         double bk = tmax * (double)k / 1000.0;
         int64_t c = 0;
+#pragma omp parallel for schedule(static) reduction(+ : c)
         for (int64_t i = 0; i < n; ++i)
             if (th[i] > bk) c++;
         int64_t d = c > target ? c - target : target - c;
@@ -277,6 +311,7 @@ int64_t orc_ddc(const orc_csr *A, double alpha_diag, int8_t *cf, double *theta)
 {
     int64_t n = A->nr, count = 0;
     uint8_t *conv = (uint8_t *)xcalloc((size_t)n, 1);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         if (theta) theta[i] = -1.0;
         if (cf[i] != ORC_F) continue;
@@ -348,6 +383,7 @@ int orc_submatrix(const orc_csr *A, const int8_t *cf, int8_t rowsel, int8_t cols
 /* y = A x, each row summed in stored order from 0. */
 void orc_spmv(const orc_csr *A, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < A->nr; ++i) {
         double s = 0.0;
         for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k) s += A->v[k] * x[A->ci[k]];
@@ -361,46 +397,58 @@ void orc_spmv(const orc_csr *A, const double *x, double *y)
 int orc_spgemm(const orc_csr *A, const orc_csr *B, orc_csr *C)
 {
     int64_t m = A->nr, n = B->nc;
-    int64_t *mark = (int64_t *)xmalloc((size_t)n * sizeof(int64_t));
-    double *acc = (double *)xmalloc((size_t)n * sizeof(double));
-    int32_t *cols = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
-    for (int64_t j = 0; j < n; ++j) mark[j] = -1;
-    /* symbolic */
+    /* symbolic: the number of distinct columns of each row */
     int64_t *rp = (int64_t *)xcalloc((size_t)m + 1, sizeof(int64_t));
-    for (int64_t r = 0; r < m; ++r) {
-        int64_t cnt = 0;
-        for (int64_t ka = A->rp[r]; ka < A->rp[r + 1]; ++ka) {
-            int32_t k = A->ci[ka];
-            for (int64_t kb = B->rp[k]; kb < B->rp[k + 1]; ++kb) {
-                int32_t j = B->ci[kb];
-                if (mark[j] != r) { mark[j] = r; cnt++; }
+#pragma omp parallel
+    {
+        int64_t *mark = (int64_t *)xmalloc((size_t)n * sizeof(int64_t));
+        for (int64_t j = 0; j < n; ++j) mark[j] = -1;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < m; ++r) {
+            int64_t cnt = 0;
+            for (int64_t ka = A->rp[r]; ka < A->rp[r + 1]; ++ka) {
+                int32_t k = A->ci[ka];
+                for (int64_t kb = B->rp[k]; kb < B->rp[k + 1]; ++kb) {
+                    int32_t j = B->ci[kb];
+                    if (mark[j] != r) { mark[j] = r; cnt++; }
+                }
             }
+            rp[r + 1] = cnt;
         }
-        rp[r + 1] = rp[r] + cnt;
+        free(mark);
     }
+    for (int64_t r = 0; r < m; ++r) rp[r + 1] += rp[r];
     csr_alloc(C, m, n, rp[m], 1);
     memcpy(C->rp, rp, ((size_t)m + 1) * sizeof(int64_t));
-    for (int64_t j = 0; j < n; ++j) mark[j] = -1;
     /* numeric */
-    for (int64_t r = 0; r < m; ++r) {
-        int64_t cnt = 0;
-        for (int64_t ka = A->rp[r]; ka < A->rp[r + 1]; ++ka) {
-            int32_t k = A->ci[ka];
-            double a = A->v[ka];
-            for (int64_t kb = B->rp[k]; kb < B->rp[k + 1]; ++kb) {
-                int32_t j = B->ci[kb];
-                double prod = a * B->v[kb];
-                if (mark[j] != r) { mark[j] = r; acc[j] = prod; cols[cnt++] = j; }
-                else acc[j] += prod;
+#pragma omp parallel
+    {
+        int64_t *mark = (int64_t *)xmalloc((size_t)n * sizeof(int64_t));
+        double *acc = (double *)xmalloc((size_t)n * sizeof(double));
+        int32_t *cols = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
+        for (int64_t j = 0; j < n; ++j) mark[j] = -1;
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < m; ++r) {
+            int64_t cnt = 0;
+            for (int64_t ka = A->rp[r]; ka < A->rp[r + 1]; ++ka) {
+                int32_t k = A->ci[ka];
+                double a = A->v[ka];
+                for (int64_t kb = B->rp[k]; kb < B->rp[k + 1]; ++kb) {
+                    int32_t j = B->ci[kb];
+                    double prod = a * B->v[kb];
+                    if (mark[j] != r) { mark[j] = r; acc[j] = prod; cols[cnt++] = j; }
+                    else acc[j] += prod;
+                }
+            }
+            qsort(cols, (size_t)cnt, sizeof(int32_t), cmp_i32);
+            for (int64_t t = 0; t < cnt; ++t) {
+                C->ci[rp[r] + t] = cols[t];
+                C->v[rp[r] + t] = acc[cols[t]];
             }
         }
-        qsort(cols, (size_t)cnt, sizeof(int32_t), cmp_i32);
-        for (int64_t t = 0; t < cnt; ++t) {
-            C->ci[rp[r] + t] = cols[t];
-            C->v[rp[r] + t] = acc[cols[t]];
-        }
+        free(mark); free(acc); free(cols);
     }
-    free(mark); free(acc); free(cols); free(rp);
+    free(rp);
     return 0;
 }
 
@@ -409,31 +457,34 @@ int orc_spgemm(const orc_csr *A, const orc_csr *B, orc_csr *C)
  * keep_diag keeps the diagonal of a square operator regardless. */
 int orc_drop(const orc_csr *A, double tau, int keep_diag, orc_csr *out)
 {
-    int64_t n = A->nr, nnz = 0;
+    int64_t n = A->nr;
+    int64_t *rp = (int64_t *)xcalloc((size_t)n + 1, sizeof(int64_t));
+    double *thr = (double *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double mx = 0.0;
         for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
             if (fabs(A->v[k]) > mx) mx = fabs(A->v[k]);
-        double thr = tau * mx;
+        thr[i] = tau * mx;
+        int64_t c = 0;
         for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
-            nnz += (keep_diag && A->ci[k] == i) || fabs(A->v[k]) >= thr;
+            c += (keep_diag && A->ci[k] == i) || fabs(A->v[k]) >= thr[i];
+        rp[i + 1] = c;
     }
-    csr_alloc(out, n, A->nc, nnz, 1);
-    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    csr_alloc(out, n, A->nc, rp[n], 1);
+    memcpy(out->rp, rp, ((size_t)n + 1) * sizeof(int64_t));
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double mx = 0.0;
+        int64_t w = rp[i];
         for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
-            if (fabs(A->v[k]) > mx) mx = fabs(A->v[k]);
-        double thr = tau * mx;
-        out->rp[i] = w;
-        for (int64_t k = A->rp[i]; k < A->rp[i + 1]; ++k)
-            if ((keep_diag && A->ci[k] == i) || fabs(A->v[k]) >= thr) {
+            if ((keep_diag && A->ci[k] == i) || fabs(A->v[k]) >= thr[i]) {
                 out->ci[w] = A->ci[k];
                 out->v[w] = A->v[k];
                 w++;
             }
     }
-    out->rp[n] = w;
+    free(rp); free(thr);
     return 0;
 }
 
@@ -465,6 +516,7 @@ int orc_transpose(const orc_csr *A, orc_csr *T)
 void orc_gauss_rhs(int64_t n, uint64_t seed, int32_t level, double *b)
 {
     const double two53 = 1.0 / 9007199254740992.0;
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) {
         uint64_t r1 = orc_splitmix64(orc_counter(seed, 1, (uint32_t)level, (uint64_t)k));
         uint64_t r2 = orc_splitmix64(orc_counter(seed, 2, (uint32_t)level, (uint64_t)k));
@@ -608,59 +660,62 @@ int orc_poly_fixed_sparsity_pattern(const orc_csr *A, const orc_csr *S, const do
                                     orc_csr *out)
 {
     int64_t n = A->nr;
-    int64_t nnz = 0;
+    csr_alloc(out, n, n, 0, 0);
+    int64_t maxlen = 1;
     for (int64_t i = 0; i < n; ++i) {
         int has = 0;
         for (int64_t k = S->rp[i]; k < S->rp[i + 1]; ++k) has |= S->ci[k] == i;
-        nnz += S->rp[i + 1] - S->rp[i] + !has;
+        out->rp[i + 1] = out->rp[i] + S->rp[i + 1] - S->rp[i] + !has;
+        if (out->rp[i + 1] - out->rp[i] > maxlen) maxlen = out->rp[i + 1] - out->rp[i];
     }
-    csr_alloc(out, n, n, nnz, 1);
-    int32_t *pos = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
-    for (int64_t j = 0; j < n; ++j) pos[j] = -1;
-    int64_t maxlen = 1;
-    for (int64_t i = 0; i < n; ++i)
-        if (S->rp[i + 1] - S->rp[i] + 1 > maxlen) maxlen = S->rp[i + 1] - S->rp[i] + 1;
-    int32_t *J = (int32_t *)xmalloc((size_t)maxlen * sizeof(int32_t));
-    double *v = (double *)xmalloc((size_t)maxlen * sizeof(double));
-    double *vn = (double *)xmalloc((size_t)maxlen * sizeof(double));
-    double *acc = (double *)xmalloc((size_t)maxlen * sizeof(double));
-    int64_t w = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t L = 0;
-        int inserted = 0;
-        for (int64_t k = S->rp[i]; k < S->rp[i + 1]; ++k) {
-            if (!inserted && S->ci[k] > i) { J[L++] = (int32_t)i; inserted = 1; }
-            if (S->ci[k] == i) inserted = 1;
-            J[L++] = S->ci[k];
-        }
-        if (!inserted) J[L++] = (int32_t)i;
-        for (int64_t a = 0; a < L; ++a) pos[J[a]] = (int32_t)a;
-        for (int64_t a = 0; a < L; ++a) v[a] = J[a] == i ? 1.0 : 0.0;
-        for (int64_t a = 0; a < L; ++a) acc[a] = alpha[0] * v[a];
-        for (int32_t k = 1; k < nalpha; ++k) {
-            for (int64_t b = 0; b < L; ++b) vn[b] = 0.0;
-            for (int64_t a = 0; a < L; ++a) {
-                int32_t p = J[a];
-                for (int64_t kk = A->rp[p]; kk < A->rp[p + 1]; ++kk) {
-                    int32_t b = pos[A->ci[kk]];
-                    if (b >= 0) vn[b] += v[a] * A->v[kk];
+    free(out->ci);
+    out->ci = (int32_t *)xmalloc((size_t)out->rp[n] * sizeof(int32_t));
+    out->v = (double *)xmalloc((size_t)out->rp[n] * sizeof(double));
+#pragma omp parallel
+    {
+        int32_t *pos = (int32_t *)xmalloc((size_t)n * sizeof(int32_t));
+        for (int64_t j = 0; j < n; ++j) pos[j] = -1;
+        int32_t *J = (int32_t *)xmalloc((size_t)maxlen * sizeof(int32_t));
+        double *v = (double *)xmalloc((size_t)maxlen * sizeof(double));
+        double *vn = (double *)xmalloc((size_t)maxlen * sizeof(double));
+        double *acc = (double *)xmalloc((size_t)maxlen * sizeof(double));
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t L = 0;
+            int inserted = 0;
+            for (int64_t k = S->rp[i]; k < S->rp[i + 1]; ++k) {
+                if (!inserted && S->ci[k] > i) { J[L++] = (int32_t)i; inserted = 1; }
+                if (S->ci[k] == i) inserted = 1;
+                J[L++] = S->ci[k];
+            }
+            if (!inserted) J[L++] = (int32_t)i;
+            for (int64_t a = 0; a < L; ++a) pos[J[a]] = (int32_t)a;
+            for (int64_t a = 0; a < L; ++a) v[a] = J[a] == i ? 1.0 : 0.0;
+            for (int64_t a = 0; a < L; ++a) acc[a] = alpha[0] * v[a];
+            for (int32_t k = 1; k < nalpha; ++k) {
+                for (int64_t b = 0; b < L; ++b) vn[b] = 0.0;
+                for (int64_t a = 0; a < L; ++a) {
+                    int32_t p = J[a];
+                    for (int64_t kk = A->rp[p]; kk < A->rp[p + 1]; ++kk) {
+                        int32_t b = pos[A->ci[kk]];
+                        if (b >= 0) vn[b] += v[a] * A->v[kk];
+                    }
+                }
+                for (int64_t b = 0; b < L; ++b) {
+                    v[b] = vn[b];
+                    acc[b] += alpha[k] * v[b];
                 }
             }
-            for (int64_t b = 0; b < L; ++b) {
-                v[b] = vn[b];
-                acc[b] += alpha[k] * v[b];
+            int64_t w = out->rp[i];
+            for (int64_t a = 0; a < L; ++a) {
+                out->ci[w] = J[a];
+                out->v[w] = acc[a];
+                w++;
+                pos[J[a]] = -1;
             }
         }
-        out->rp[i] = w;
-        for (int64_t a = 0; a < L; ++a) {
-            out->ci[w] = J[a];
-            out->v[w] = acc[a];
-            w++;
-            pos[J[a]] = -1;
-        }
+        free(pos); free(J); free(v); free(vn); free(acc);
     }
-    out->rp[n] = w;
-    free(pos); free(J); free(v); free(vn); free(acc);
     return 0;
 }
 
@@ -1144,10 +1199,12 @@ static void coarse_apply(const orc_hier *h, const orc_level *L, const double *x,
     double *pk = (double *)xmalloc((size_t)n * sizeof(double));
     double *pn = (double *)xmalloc((size_t)n * sizeof(double));
     memcpy(pk, x, (size_t)n * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) y[i] = L->alpha[0] * pk[i];
     for (int32_t k = 1; k < L->nalpha; ++k) {
         orc_spmv(&L->A, pk, pn);
         double *tmp = pk; pk = pn; pn = tmp;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) y[i] += L->alpha[k] * pk[i];
     }
     free(pk); free(pn);
@@ -1163,8 +1220,10 @@ void orc_vcycle(const orc_hier *h, int32_t level, const double *g, double *e)
         coarse_apply(h, L, g, e);
         for (int32_t it = 1; it < h->p.coarse_iters; ++it) {
             orc_spmv(&L->A, e, t);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) r[i] = g[i] - t[i];
             coarse_apply(h, L, r, t);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) e[i] += t[i];
         }
         free(r); free(t);
@@ -1177,17 +1236,23 @@ void orc_vcycle(const orc_hier *h, int32_t level, const double *g, double *e)
     double *tF = (double *)xmalloc((size_t)(nF + 1) * sizeof(double));
     double *dF = (double *)xmalloc((size_t)(nF + 1) * sizeof(double));
     double *t = (double *)xmalloc((size_t)n * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nF; ++f) gF[f] = g[L->fidx[f]];
     orc_spmv(&L->Z, gF, gc);
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nC; ++c) gc[c] += g[L->cidx[c]];
     orc_vcycle(h, level + 1, gc, ec);
     orc_spmv(&L->W, ec, tF);
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nC; ++c) e[L->cidx[c]] = ec[c];
+#pragma omp parallel for schedule(static)
     for (int64_t f = 0; f < nF; ++f) e[L->fidx[f]] = tF[f];
     for (int32_t s = 0; s < h->p.up_smooths; ++s) {
         orc_spmv(&L->A, e, t);
+#pragma omp parallel for schedule(static)
         for (int64_t f = 0; f < nF; ++f) tF[f] = g[L->fidx[f]] - t[L->fidx[f]];
         orc_spmv(&L->Ainv, tF, dF);
+#pragma omp parallel for schedule(static)
         for (int64_t f = 0; f < nF; ++f) e[L->fidx[f]] += dF[f];
     }
     free(gF); free(gc); free(ec); free(tF); free(dF); free(t);
@@ -1215,8 +1280,10 @@ int orc_richardson(const orc_hier *h, const double *b, double *x, double rtol, i
     double rr = nb;
     while (rr > rtol * nb && it < maxit) {
         orc_vcycle(h, 0, r, e);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) x[i] += e[i];
         orc_spmv(A, x, r);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
         rr = nrm2(n, r);
         it++;
@@ -1268,6 +1335,7 @@ int orc_fgmres(const orc_hier *h, const double *b, double *x, double rtol, int32
                 }
                 for (int32_t i = 0; i <= j; ++i) {
                     const double *vi = V + (size_t)i * n;
+#pragma omp parallel for schedule(static)
                     for (int64_t q = 0; q < n; ++q) w[q] -= hc[i] * vi[q];
                     H[i * k + j] += hc[i];
                 }
@@ -1298,6 +1366,7 @@ int orc_fgmres(const orc_hier *h, const double *b, double *x, double rtol, int32
         }
         for (int32_t i = 0; i < j; ++i) {
             const double *zi = Zb + (size_t)i * n;
+#pragma omp parallel for schedule(static)
             for (int64_t q = 0; q < n; ++q) x[q] += y[i] * zi[q];
         }
         orc_spmv(A, x, r);

@@ -6,7 +6,9 @@
  * leg, never from the product path.  It shares no code with the HIP library.
  *
  * Everything is double precision, natural (unpermuted) index order, plain
- * loops; compiled with -O2 -ffp-contract=off.  Each function names the
+ * loops; compiled with -O2 -ffp-contract=off.  Loops over independent rows
+ * may run on several threads (OpenMP); the results do not depend on the
+ * thread count.  Each function names the
  * passage of Dargaville et al., "Coarsening and parallelism with reduction
  * multigrids for hyperbolic Boltzmann transport" (arXiv 2408.08262) that it
  * follows.
@@ -50,6 +52,9 @@ typedef struct orc_params {
 } orc_params;
 
 void orc_default_params(orc_params *p);
+/* Threads for the row-parallel loops (OpenMP); results do not depend on it. */
+void    orc_set_threads(int32_t n);
+int32_t orc_get_threads(void);
 void orc_csr_free(orc_csr *A);
 
 /* counter-based generator (SplitMix64 output of a keyed counter) */

@@ -71,6 +71,7 @@ _SIGS = {
     "airg_get_stats": [_VP, C.POINTER(Stats)],
     "airg_resetup": [_VP, _VP, _VP],
     "airg_vcycle": [_VP, _I32, _VP, _VP, _I32, _VP],
+    "airg_batch_vcycle": [_VP, _I32, _VP, _VP, _VP],
     "airg_get_level": [_VP, _I32, _I32, C.POINTER(LevelInfo), _VP],
     "airg_get_level_matrix": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
     "airg_csr_info": [_VP, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)],
@@ -269,6 +270,15 @@ def airg_vcycle(h, g, precision=64, segment=0, stream=None):
     e = torch.empty_like(g)
     _check(lib().airg_vcycle(h.ptr, segment, _dev(g, torch.float64), _dev(e, torch.float64), precision,
                              _stream(stream)))
+    return e
+
+
+def airg_batch_vcycle(h, g, stream=None):
+    """E = V(G): one batched FP32 V-cycle over every segment and right-hand
+    side (G: (n, nrhs) float64 device tensor, natural order)."""
+    nrhs = 1 if g.dim() == 1 else g.shape[1]
+    e = torch.empty_like(g)
+    _check(lib().airg_batch_vcycle(h.ptr, nrhs, _dev(g, torch.float64), _dev(e, torch.float64), _stream(stream)))
     return e
 
 

@@ -743,4 +743,13 @@ BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg,
     return res;
 }
 
+void batch_apply(Batch &B, const double *g, double *e, bool use_graph, hipStream_t s) {
+    const int64_t nk = B.n * B.k;
+    k_gather_cast<<<grid_for(nk, 256), 256, 0, s>>>(g, B.perm0.p, B.k, B.g0.p, B.n);
+    AIRG_LAUNCH_CHECK();
+    B.run(s, use_graph);
+    k_scatter_cast<<<grid_for(nk, 256), 256, 0, s>>>(B.e0.p, B.perm0.p, B.k, e, B.n);
+    AIRG_LAUNCH_CHECK();
+}
+
 }  // namespace airg

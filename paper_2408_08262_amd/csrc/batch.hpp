@@ -56,4 +56,8 @@ struct BatchResult {
 BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg, const double *b, double *x,
                         double rtol, int maxit, int restart, bool use_graph, hipStream_t s);
 
+// One batched FP32 V-cycle on FP64 vectors in natural row order (n x k
+// row-major): e = V(g), the cast into and out of the cycle included.
+void batch_apply(Batch &B, const double *g, double *e, bool use_graph, hipStream_t s);
+
 }  // namespace airg

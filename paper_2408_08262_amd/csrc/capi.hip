@@ -228,6 +228,21 @@ void run_solve(airg_handle *h, std::vector<std::unique_ptr<Hier>> &hs, int32_t n
     if (!conv) throw Error(ST_NOT_CONVERGED, "not converged within max_it");
 }
 
+bool batched_form(const airg_handle *h) {
+    return h->segh || (h->fwd.size() > 1 && h->opt.outer == AIRG_OUTER_FGMRES && h->opt.precond_precision == 32);
+}
+
+// The batched solve operators for nrhs right-hand sides (built on first use).
+void ensure_batch(airg_handle *h, int32_t nrhs, hipStream_t s) {
+    AIRG_REQUIRE(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8, ST_INVALID_ARG,
+                 "batched solve needs 1, 2, 4 or 8 right-hand sides");
+    if (!h->batch || h->batch->k != nrhs) {
+        h->batch.reset();
+        h->batch = h->segh ? batch_from_segmented(*h->segh, nrhs, h->opt.autotune != 0, s)
+                           : build_batch(h->fwd, nrhs, h->opt.autotune != 0, s);
+    }
+}
+
 Hier *pick(const airg_handle *h, int32_t segment) {
     if (segment >= 0) {
         AIRG_REQUIRE((size_t)segment < h->fwd.size(), ST_INVALID_ARG, "segment out of range");
@@ -346,21 +361,13 @@ airg_status airg_solve(airg_handle *h, int32_t nrhs, const double *d_b, double *
     return guarded([&] {
         AIRG_REQUIRE(h, ST_INVALID_ARG, "null handle");
         hipStream_t s = (hipStream_t)hip_stream;
-        bool batched = h->segh ||
-                       (h->fwd.size() > 1 && h->opt.outer == AIRG_OUTER_FGMRES && h->opt.precond_precision == 32);
-        if (!batched) {
+        if (!batched_form(h)) {
             run_solve(h, h->fwd, nrhs, d_b, d_x, rtol, max_it, s, info);
             return;
         }
-        AIRG_REQUIRE(nrhs == 1 || nrhs == 2 || nrhs == 4 || nrhs == 8, ST_INVALID_ARG,
-                     "batched solve needs 1, 2, 4 or 8 right-hand sides");
         AIRG_REQUIRE(d_b && d_x && rtol > 0.0 && max_it >= 0, ST_INVALID_ARG, "bad argument");
         auto t0 = std::chrono::steady_clock::now();
-        if (!h->batch || h->batch->k != nrhs) {
-            h->batch.reset();
-            h->batch = h->segh ? batch_from_segmented(*h->segh, nrhs, h->opt.autotune != 0, s)
-                               : build_batch(h->fwd, nrhs, h->opt.autotune != 0, s);
-        }
+        ensure_batch(h, nrhs, s);
         const Csr &top = h->segh ? h->segh->lv[0]->A : h->top;
         BatchResult r = solve_batch(*h->batch, top, h->seg, d_b, d_x, rtol, max_it, h->opt.fgmres_restart,
                                     h->opt.use_graph != 0, s);
@@ -469,6 +476,17 @@ airg_status airg_vcycle(const airg_handle *h, int32_t segment, const double *d_g
         H->s = (hipStream_t)hip_stream;
         apply_vcycle(*H, d_g, d_e, precision);
         AIRG_HIP(hipStreamSynchronize(H->s));
+    });
+}
+
+airg_status airg_batch_vcycle(airg_handle *h, int32_t nrhs, const double *d_g, double *d_e, void *hip_stream) {
+    return guarded([&] {
+        AIRG_REQUIRE(h && d_g && d_e, ST_INVALID_ARG, "null argument");
+        AIRG_REQUIRE(batched_form(h), ST_INVALID_ARG, "the handle is not in the batched form");
+        hipStream_t s = (hipStream_t)hip_stream;
+        ensure_batch(h, nrhs, s);
+        batch_apply(*h->batch, d_g, d_e, h->opt.use_graph != 0, s);
+        AIRG_HIP(hipStreamSynchronize(s));
     });
 }
 

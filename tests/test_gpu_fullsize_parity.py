@@ -1,0 +1,237 @@
+"""Element-wise parity at the full workload sizes, through the C ABI, in the
+configurations the benchmark times.
+
+The oracle's replay setup is fed the device's per-level polynomial
+coefficients and so rebuilds the device's whole hierarchy without depending on
+the rounding of the random rhs and the TSQR behind them.  Then:
+
+* every level's splitting, operator, approximate inverse, Z and W match bit
+  for bit, and the grid, operator and storage complexities match the oracle's;
+* one V-cycle (AIRG subsection: restrict, recurse, prolong, two up F-point
+  smooths; coarse polynomial iterations on the coarsest level) matches the
+  oracle's cycle element by element: the FP64 cycle within 1e-12 and the FP32
+  cycle within 1e-5 relative (2-norm of the difference over the 2-norm of the
+  oracle's output).  These sizes run the CSR-stream products and the fused
+  prolongation the small cases never reach;
+* the batched FP32 cycle, taken segment by segment from one batched launch
+  sequence, matches each segment's replayed oracle cycle within 1e-5;
+* solutions: FP64 residuals recomputed by the oracle for every (segment, rhs)
+  pair, errors against the exact sweep, and the adjoint gradients element by
+  element against the gradients formed from the forward and reverse sweeps.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle.sweep import sweep_solve
+from workloads import dg_square, p0_cube, batch as batch_problems, concat, adjoint as adjoint_problem
+
+pytestmark = pytest.mark.gpu
+
+airg = pytest.importorskip("paper_2408_08262_amd.airg")
+
+FP64_CYCLE_RTOL = 1e-12
+FP32_CYCLE_RTOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def device_alphas(h, levels, segment=0):
+    return [airg.airg_get_level(h, l, segment=segment, with_cf=False)["alpha"] for l in range(levels)]
+
+
+def check_whole_hierarchy(h, H, levels, segment=0):
+    """Every level of the device hierarchy against the replayed oracle's."""
+    assert H.nlevels == levels
+    for l in range(levels):
+        info = airg.airg_get_level(h, l, segment=segment)
+        coarsest = l == levels - 1
+        assert bool(info["coarsest"]) == coarsest
+        if not coarsest:
+            assert np.array_equal(info["cf"], H.cf(l)), ("cf", l)
+        for key in (("A", "Ainv") if coarsest else ("A", "Ainv", "Z", "W")):
+            got = airg.airg_get_level_matrix(h, l, key, segment=segment)
+            want = H.matrix(l, key)
+            assert all(np.array_equal(x, y) for x, y in zip(got[:3], want[:3])), (l, key)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def bench_opts(P, **kw):
+    return airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, use_graph=1, **kw)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["dg_square_512", "p0_cube_128"])
+def test_whole_hierarchy_replay_complexities_and_vcycle(name):
+    if name == "dg_square_512":
+        P, kw = dg_square(512), {}
+    else:
+        P, kw = p0_cube(128), {"truncate_n": 65536}
+    say("%s: n=%d nnz=%d" % (name, P.n, P.nnz))
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    h = airg.airg_setup(*A, bench_opts(P, **kw))
+    st = airg.airg_get_stats(h)
+    say("device setup done, %d levels" % st["levels"])
+    H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, **kw),
+                    alphas=device_alphas(h, st["levels"]))
+    say("oracle replay done")
+    check_whole_hierarchy(h, H, st["levels"])
+    g, o, s = H.complexity()
+    assert st["grid_complexity"] == pytest.approx(g, rel=1e-14)
+    assert st["operator_complexity"] == pytest.approx(o, rel=1e-14)
+    assert st["storage_complexity"] == pytest.approx(s, rel=1e-14)
+    rng = np.random.default_rng(5)
+    for trial in range(2):
+        gv = rng.standard_normal(P.n) if trial == 0 else P.b.copy()
+        want = H.vcycle(gv)
+        gd = torch.as_tensor(gv, device="cuda")
+        e64 = airg.airg_vcycle(h, gd, precision=64).cpu().numpy()
+        e32 = airg.airg_vcycle(h, gd, precision=32).cpu().numpy()
+        r64, r32 = rel(e64, want), rel(e32, want)
+        say("V-cycle trial %d: fp64 %.3e fp32 %.3e" % (trial, r64, r32))
+        assert r64 <= FP64_CYCLE_RTOL, r64
+        assert r32 <= FP32_CYCLE_RTOL, r32
+
+
+@pytest.mark.timeout(600)
+def test_dg_square_512_fp64_richardson_against_oracle_and_sweep():
+    """The benchmark's comparison form at full size: FP64 V-cycle inside
+    undamped Richardson (Results), residual recomputed by the oracle, error
+    against the exact sweep and against the oracle's own Richardson solution
+    on the replayed hierarchy."""
+    P = dg_square(512)
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64,
+                                              use_graph=1))
+    x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
+    x = x.cpu().numpy()
+    r = np.linalg.norm(P.b - O.spmv((P.rowptr, P.col, P.val), x)) / np.linalg.norm(P.b)
+    say("device Richardson: %d its, residual %.3e" % (info["iterations"], r))
+    assert info["converged"] and r <= 1.0001e-10
+    st = airg.airg_get_stats(h)
+    H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed), alphas=device_alphas(h, st["levels"]))
+    xo, its, rr = H.richardson(P.b, 1e-10, 100)
+    say("oracle Richardson: %d its, residual %.3e" % (its, rr))
+    assert its == info["iterations"]
+    xs = sweep_solve(P.rowptr, P.col, P.val, P.b, 3)
+    assert rel(x, xs) <= 1e-8 and rel(xo, xs) <= 1e-8
+    assert rel(x, xo) <= 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_batch48_every_pair_and_batched_vcycle_per_segment():
+    probs = batch_problems()
+    rp, ci, val, b, offs, seeds = concat(probs)
+    say("batch48: n=%d nnz=%d" % (offs[-1], rp[-1]))
+    A = airg.to_device(rp, ci, val)
+    opts = airg.default_opts(outer=airg.OUTER_FGMRES, precond_precision=32, use_graph=1, autotune=1)
+    h = airg.airg_setup(*A, opts, seg_offsets=offs, seg_seeds=seeds)
+    B = torch.as_tensor(b, device="cuda")
+    X, info = airg.airg_solve(h, B, rtol=1e-10, max_it=100)
+    assert info["converged"]
+    X = X.cpu().numpy()
+    k = b.shape[1]
+    worst = 0.0
+    for p, P in enumerate(probs):                        # every (segment, rhs) pair
+        Ap = (P.rowptr, P.col, P.val)
+        for c in range(k):
+            r = np.linalg.norm(P.b[:, c] - O.spmv(Ap, X[offs[p]:offs[p + 1], c])) / np.linalg.norm(P.b[:, c])
+            worst = max(worst, r)
+            assert r <= 1.0001e-10, (p, c, r)
+    say("all %d pairs converged, worst residual %.3e" % (len(probs) * k, worst))
+    # one batched FP32 cycle on random vectors, compared segment by segment
+    G = np.random.default_rng(9).standard_normal(b.shape)
+    E = airg.airg_batch_vcycle(h, torch.as_tensor(G, device="cuda")).cpu().numpy()
+    E2 = airg.airg_batch_vcycle(h, torch.as_tensor(G, device="cuda")).cpu().numpy()
+    assert np.array_equal(E, E2)                         # graph replays are deterministic
+    worst = 0.0
+    for p, P in enumerate(probs):
+        lv = airg.airg_get_level(h, 0, segment=p)
+        prm = O.default_params(seed=int(seeds[p]))
+        assert np.array_equal(lv["cf"], O.cf_split((P.rowptr, P.col, P.val), prm, 0)), p
+        nl = 0
+        while True:
+            info_l = airg.airg_get_level(h, nl, segment=p, with_cf=False)
+            nl += 1
+            if info_l["coarsest"]:
+                break
+        H = O.Hierarchy((P.rowptr, P.col, P.val), prm, alphas=device_alphas(h, nl, segment=p))
+        assert H.nlevels == nl, p
+        for c in range(k):
+            g = G[offs[p]:offs[p + 1], c]
+            e = E[offs[p]:offs[p + 1], c]
+            r = rel(e, H.vcycle(g))
+            worst = max(worst, r)
+            assert r <= FP32_CYCLE_RTOL, (p, c, r)
+        del H
+    say("batched FP32 cycle: worst segment difference %.3e" % worst)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_256_gradients_element_by_element_against_sweeps():
+    """grad_s = M^T lambda and grad_sigma_K = -lambda_K^T M_K u_K with u from
+    the forward sweep of A and lambda from the reverse sweep of A^T (A is
+    block lower triangular in sweep order, A^T block upper)."""
+    from paper_2408_08262_amd import adjoint as adj
+    import scipy.sparse as sp
+    P = adjoint_problem(256)
+    m = P.meta
+    prob = adj.DiffProblem(P.rowptr, P.col, m["val_adv"], m["mass"], opts=airg.default_opts(seed=P.seed))
+    s = torch.as_tensor(m["src"], device="cuda").requires_grad_(True)
+    sg = torch.as_tensor(m["sigma"], device="cuda").requires_grad_(True)
+    u = adj.solve(s, sg, prob)
+    mask = torch.as_tensor(m["patch_mask"], device="cuda")
+    (u[mask] ** 2).sum().backward()
+    gs, gsig = s.grad.cpu().numpy(), sg.grad.cpu().numpy()
+    nc = m["mass"].shape[0]
+    K = np.repeat(np.arange(nc), 9)
+    r = K * 3 + np.tile(np.repeat(np.arange(3), 3), nc)
+    c = K * 3 + np.tile(np.arange(3), nc * 3)
+    Mb = sp.csr_matrix((m["mass"].ravel(), (r, c)), shape=(P.n, P.n))
+    us = sweep_solve(P.rowptr, P.col, P.val, Mb @ m["src"], 3)
+    assert rel(u.detach().cpu().numpy(), us) <= 1e-8
+    lam = sweep_solve(P.rowptr, P.col, P.val, np.where(m["patch_mask"], 2.0 * us, 0.0), 3, transpose=True)
+    want_s = Mb.T @ lam
+    want_sig = -np.einsum("ka,kab,kb->k", lam.reshape(-1, 3), m["mass"], us.reshape(-1, 3))
+    es = np.abs(gs - want_s).max() / np.abs(want_s).max()
+    esig = np.abs(gsig - want_sig).max() / np.abs(want_sig).max()
+    say("adjoint_256: max |grad_s error| %.3e, max |grad_sigma error| %.3e (relative to the largest entry)"
+        % (es, esig))
+    assert rel(gs, want_s) <= 1e-8 and rel(gsig, want_sig) <= 1e-8
+    assert es <= 1e-8 and esig <= 1e-8
+
+
+@pytest.mark.timeout(300)
+def test_richardson_divergence_case_agrees_with_oracle():
+    """A known property of the method on these operators: on the DG-P1 64^2
+    instance the level-1 stationary polynomial leaves one outlier eigenvalue
+    with |1 - lambda q(lambda)| > 1, so undamped Richardson diverges while
+    FGMRES converges.  The device and the replayed oracle agree on it: the same
+    residual history and the same not-converged outcome at the cap."""
+    P = dg_square(64)
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64))
+    st = airg.airg_get_stats(h)
+    H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed), alphas=device_alphas(h, st["levels"]))
+    check_whole_hierarchy(h, H, st["levels"])
+    b = torch.as_tensor(P.b, device="cuda")
+    hist = []
+    for its in (5, 10, 20, 40):
+        _, info = airg.airg_solve(h, b, rtol=1e-10, max_it=its, allow_not_converged=True)
+        _, oits, orr = H.richardson(P.b, 1e-10, its)
+        say("after %d cycles: device %.6e oracle %.6e" % (its, info["rel_residual"], orr))
+        assert not info["converged"] and oits == its == info["iterations"]
+        assert info["rel_residual"] == pytest.approx(orr, rel=1e-6)
+        hist.append(orr)
+    assert hist[-1] > hist[1]                       # growing: the iteration diverges
+    h2 = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=64))
+    _, info = airg.airg_solve(h2, b, rtol=1e-10, max_it=100)
+    _, oits, orr = H.fgmres(P.b, 1e-10, 100, 30)
+    assert info["converged"] and orr <= 1e-10
+    assert abs(info["iterations"] - oits) <= 1

@@ -784,3 +784,36 @@ def test_setup_replay_with_own_coefficients_is_identical():
     assert np.array_equal(R2.alpha(0), al2[0])
     assert not np.array_equal(R2.matrix(0, "Ainv")[2], H.matrix(0, "Ainv")[2])
     assert np.array_equal(R2.alpha(1), O.Hierarchy(A, prm, alphas=al2[:1]).alpha(1))
+
+
+# ----------------------------------------------------------------- threads --
+@pytest.mark.parametrize("make", [lambda: dg_square(40), lambda: p0_cube(10)], ids=["dg40", "cube10"])
+def test_thread_count_does_not_change_results(make):
+    """The oracle's row-parallel loops leave every result bit for bit equal
+    to the single-threaded run: hierarchy, cycle, Richardson and FGMRES."""
+    P = make()
+    A = csr_of(P)
+    prm = O.default_params(seed=P.seed)
+    nthreads = max(4, O.get_threads())
+    runs = []
+    try:
+        for t in (1, nthreads):
+            O.set_threads(t)
+            H = O.Hierarchy(A, prm)
+            mats = [[H.matrix(l, k) for k in ("A", "Ainv", "Z", "W")] for l in range(H.nlevels)]
+            g = np.random.default_rng(3).standard_normal(P.n)
+            runs.append((H.nlevels, mats, H.vcycle(g), H.richardson(P.b, 1e-10, 50), H.fgmres(P.b, 1e-10, 50, 30),
+                         H.complexity()))
+    finally:
+        O.set_threads(nthreads)
+    a, b = runs
+    assert a[0] == b[0]
+    for la, lb in zip(a[1], b[1]):
+        for x, y in zip(la, lb):
+            assert (x is None) == (y is None)
+            if x is not None:
+                assert all(np.array_equal(p, q) for p, q in zip(x[:3], y[:3]))
+    assert np.array_equal(a[2], b[2])
+    assert np.array_equal(a[3][0], b[3][0]) and a[3][1:] == b[3][1:]
+    assert np.array_equal(a[4][0], b[4][0]) and a[4][1:] == b[4][1:]
+    assert a[5] == b[5]
