@@ -50,3 +50,17 @@ def random_nonsym(n, density, seed, dominance=2.0):
 
 def csr_of(P):
     return (P.rowptr, P.col, P.val)
+
+
+_PROBLEMS = {}
+
+
+def full_problem(name):
+    """The full-size workloads, generated once per test session (the 3D mesh
+    takes tens of seconds to build).  Callers must not modify the arrays."""
+    if name not in _PROBLEMS:
+        from workloads import dg_square, p0_cube, batch
+        make = {"dg_square_512": lambda: dg_square(512), "p0_cube_128": lambda: p0_cube(128),
+                "batch48": lambda: batch()}[name]
+        _PROBLEMS[name] = make()
+    return _PROBLEMS[name]

@@ -13,7 +13,8 @@ import pytest
 import torch
 
 import oracle as O
-from workloads import dg_square, p0_cube, batch as batch_problems, concat
+from workloads import concat
+from tests.helpers import full_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +44,7 @@ def residual_ok(P, x, b):
 
 @pytest.mark.timeout(300)
 def test_dg_square_512_fp32_fgmres():
-    P = dg_square(512)
+    P = full_problem("dg_square_512")
     A = airg.to_device(P.rowptr, P.col, P.val)
     h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32))
     x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
@@ -54,7 +55,7 @@ def test_dg_square_512_fp32_fgmres():
 
 @pytest.mark.timeout(400)
 def test_p0_cube_128_truncated_fp32_fgmres():
-    P = p0_cube(128)
+    P = full_problem("p0_cube_128")
     A = airg.to_device(P.rowptr, P.col, P.val)
     kw = {"truncate_n": 65536}
     h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, **kw))
@@ -69,7 +70,7 @@ def test_p0_cube_128_truncated_fp32_fgmres():
 
 @pytest.mark.timeout(300)
 def test_batch_48_problems_4_rhs():
-    probs = batch_problems()
+    probs = full_problem("batch48")
     rp, ci, val, b, offs, seeds = concat(probs)
     A = airg.to_device(rp, ci, val)
     opts = airg.default_opts(outer=airg.OUTER_FGMRES, precond_precision=32, use_graph=1, autotune=1)

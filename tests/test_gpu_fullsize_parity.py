@@ -25,7 +25,8 @@ import torch
 
 import oracle as O
 from oracle.sweep import sweep_solve
-from workloads import dg_square, p0_cube, batch as batch_problems, concat, adjoint as adjoint_problem
+from workloads import dg_square, concat, adjoint as adjoint_problem
+from tests.helpers import full_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -70,9 +71,9 @@ def bench_opts(P, **kw):
 @pytest.mark.parametrize("name", ["dg_square_512", "p0_cube_128"])
 def test_whole_hierarchy_replay_complexities_and_vcycle(name):
     if name == "dg_square_512":
-        P, kw = dg_square(512), {}
+        P, kw = full_problem("dg_square_512"), {}
     else:
-        P, kw = p0_cube(128), {"truncate_n": 65536}
+        P, kw = full_problem("p0_cube_128"), {"truncate_n": 65536}
     say("%s: n=%d nnz=%d" % (name, P.n, P.nnz))
     A = airg.to_device(P.rowptr, P.col, P.val)
     h = airg.airg_setup(*A, bench_opts(P, **kw))
@@ -105,7 +106,7 @@ def test_dg_square_512_fp64_richardson_against_oracle_and_sweep():
     undamped Richardson (Results), residual recomputed by the oracle, error
     against the exact sweep and against the oracle's own Richardson solution
     on the replayed hierarchy."""
-    P = dg_square(512)
+    P = full_problem("dg_square_512")
     A = airg.to_device(P.rowptr, P.col, P.val)
     h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64,
                                               use_graph=1))
@@ -126,7 +127,7 @@ def test_dg_square_512_fp64_richardson_against_oracle_and_sweep():
 
 @pytest.mark.timeout(900)
 def test_batch48_every_pair_and_batched_vcycle_per_segment():
-    probs = batch_problems()
+    probs = full_problem("batch48")
     rp, ci, val, b, offs, seeds = concat(probs)
     say("batch48: n=%d nnz=%d" % (offs[-1], rp[-1]))
     A = airg.to_device(rp, ci, val)

@@ -130,22 +130,43 @@ def tet_faces(xyz, tet):
     Face k of tetrahedron t is the one opposite vertex k.  Returns a dict with
       nbr[nt,4]   neighbour across face k (-1 on the boundary),
       nrm[nt,4,3] outward unit normal, area[nt,4], vol[nt].
+
+    The normals are formed one face slot and one component at a time (the
+    same products and differences as a vector cross product, in the same
+    order), which keeps the temporaries at a few nt-long columns.
     """
     nt = tet.shape[0]
     nv = xyz.shape[0]
-    fv = np.stack([tet[:, [1, 2, 3]], tet[:, [0, 2, 3]], tet[:, [0, 1, 3]], tet[:, [0, 1, 2]]], axis=1)
-    p = xyz[fv]                                               # nt,4,3,3
-    n = np.cross(p[:, :, 1] - p[:, :, 0], p[:, :, 2] - p[:, :, 0])
-    nlen = np.linalg.norm(n, axis=-1)
-    area = 0.5 * nlen
-    n = n / nlen[..., None]
-    opp = xyz[tet]                                            # nt,4,3 opposite vertex of face k is tet[:,k]
-    s = np.einsum("tkd,tkd->tk", n, p[:, :, 0] - opp)
-    n = n * np.sign(s)[..., None]
-    v = xyz[tet]
-    vol = np.abs(np.einsum("td,td->t", np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]), v[:, 3] - v[:, 0])) / 6.0
+    X = [np.ascontiguousarray(xyz[:, d]) for d in range(3)]
+    FACES = ((1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2))
+    nrm = np.empty((nt, 4, 3))
+    area = np.empty((nt, 4))
+    for k, (a, b, c) in enumerate(FACES):
+        ia, ib, ic, io = tet[:, a], tet[:, b], tet[:, c], tet[:, k]
+        pa = [X[d][ia] for d in range(3)]
+        u = [X[d][ib] - pa[d] for d in range(3)]
+        v = [X[d][ic] - pa[d] for d in range(3)]
+        n = [u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]]
+        del u, v
+        nlen = np.sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2])
+        area[:, k] = 0.5 * nlen
+        n = [n[d] / nlen for d in range(3)]
+        s = n[0] * (pa[0] - X[0][io]) + n[1] * (pa[1] - X[1][io]) + n[2] * (pa[2] - X[2][io])
+        sg = np.sign(s)
+        for d in range(3):
+            nrm[:, k, d] = n[d] * sg
+        del n, pa, s, sg
+    p0 = [X[d][tet[:, 0]] for d in range(3)]
+    u = [X[d][tet[:, 1]] - p0[d] for d in range(3)]
+    v = [X[d][tet[:, 2]] - p0[d] for d in range(3)]
+    w = [X[d][tet[:, 3]] - p0[d] for d in range(3)]
+    c = [u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]]
+    vol = np.abs(c[0] * w[0] + c[1] * w[1] + c[2] * w[2]) / 6.0
+    del p0, u, v, w, c
     # face key: sorted vertex ids, encoded relative to the smallest id
+    fv = np.stack([tet[:, list(f)] for f in FACES], axis=1)
     fs = np.sort(fv.reshape(-1, 3), axis=1)
+    del fv
     d1 = fs[:, 1] - fs[:, 0]
     d2 = fs[:, 2] - fs[:, 0]
     S = int(max(d1.max(), d2.max())) + 1
@@ -161,4 +182,4 @@ def tet_faces(xyz, tet):
     i1 = order[1:][same]
     nbr[i0] = i1 // 4
     nbr[i1] = i0 // 4
-    return {"nbr": nbr.reshape(nt, 4), "nrm": n, "area": area, "vol": vol}
+    return {"nbr": nbr.reshape(nt, 4), "nrm": nrm, "area": area, "vol": vol}
