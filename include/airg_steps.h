@@ -61,6 +61,21 @@ airg_status airg_ddc_fraction_threshold(int64_t n, int64_t nnz, const int32_t *d
                                         const double *d_val, const int8_t *d_cf, double fraction,
                                         double *alpha_diag, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same threshold
+ * as airg_ddc_fraction_threshold, bit for bit, with no device allocation.
+ * theta and the counters live in a fixed array of the library on each device
+ * (4 KiB + 8 B per row for at most
+ * airg_ddc_fraction_threshold_noalloc_max_rows() = 2,097,152 rows, held until
+ * the process ends); larger n returns AIRG_ERR_LIMIT before any device work.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind, so calls that overlap on one device (other threads or streams)
+ * race.  Synchronises hip_stream twice (two small readbacks). */
+airg_status airg_ddc_fraction_threshold_noalloc(int64_t n, int64_t nnz, const int32_t *d_rowptr,
+                                                const int32_t *d_col, const double *d_val, const int8_t *d_cf,
+                                                double fraction, double *alpha_diag, void *hip_stream);
+int64_t airg_ddc_fraction_threshold_noalloc_max_rows(void);
+
 /* PMISR followed by DDC with the options' parameters, measures seeded by
  * opts->seed at the given level.  d_cf (n): 1 = F, 2 = C. */
 airg_status airg_cf_split(int64_t n, int64_t nnz, const int32_t *d_rowptr, const int32_t *d_col,

@@ -80,6 +80,7 @@ _SIGS = {
     "airg_pmisr": [_I64, _I64, _VP, _VP, _VP, _D, _VP, _U64, _I32, _I32, _VP, C.POINTER(_I32), _VP],
     "airg_ddc": [_I64, _I64, _VP, _VP, _VP, _D, _VP, _VP, _VP, _VP],
     "airg_ddc_fraction_threshold": [_I64, _I64, _VP, _VP, _VP, _VP, _D, C.POINTER(_D), _VP],
+    "airg_ddc_fraction_threshold_noalloc": [_I64, _I64, _VP, _VP, _VP, _VP, _D, C.POINTER(_D), _VP],
     "airg_cf_split": [_I64, _I64, _VP, _VP, _VP, C.POINTER(Opts), _I32, _VP, C.POINTER(_I64), C.POINTER(_I64),
                       _VP],
     "airg_extract": [_I64, _I64, _VP, _VP, _VP, _VP, C.c_int8, C.c_int8, C.POINTER(_VP), _VP],
@@ -100,7 +101,8 @@ _SIGS["airg_blockdiag_axpy"] = [_I64, _I32, _VP, _VP, _VP, _VP, _VP, _VP]
 _SIGS["airg_blockdiag_apply"] = [_I64, _I32, _VP, _VP, _VP, _VP]
 _SIGS["airg_blockdiag_bilinear"] = [_I64, _I32, _VP, _VP, _VP, _D, _VP, _VP]
 _SIGS["airg_kernel_timing_read"] = [C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D)]
-EXPORTS = tuple(_SIGS) + ("airg_destroy", "airg_status_string", "airg_last_error", "airg_csr_free")
+EXPORTS = tuple(_SIGS) + ("airg_destroy", "airg_status_string", "airg_last_error", "airg_csr_free",
+                         "airg_ddc_fraction_threshold_noalloc_max_rows")
 
 _lib = None
 
@@ -124,6 +126,8 @@ def lib():
         L.airg_status_string.restype = C.c_char_p
         L.airg_last_error.argtypes = []
         L.airg_last_error.restype = C.c_char_p
+        L.airg_ddc_fraction_threshold_noalloc_max_rows.argtypes = []
+        L.airg_ddc_fraction_threshold_noalloc_max_rows.restype = _I64
         _lib = L
     return _lib
 
@@ -399,6 +403,18 @@ def airg_ddc_fraction_threshold(A, cf, fraction, stream=None):
     _check(lib().airg_ddc_fraction_threshold(n, nnz, rp, ci, v, _dev(cf, torch.int8), fraction, C.byref(out),
                                              _stream(stream)))
     return out.value
+
+
+def airg_ddc_fraction_threshold_noalloc(A, cf, fraction, stream=None):
+    n, nnz, rp, ci, v = _csr_args(A)
+    out = _D()
+    _check(lib().airg_ddc_fraction_threshold_noalloc(n, nnz, rp, ci, v, _dev(cf, torch.int8), fraction,
+                                                     C.byref(out), _stream(stream)))
+    return out.value
+
+
+def ddc_fraction_noalloc_max_rows():
+    return int(lib().airg_ddc_fraction_threshold_noalloc_max_rows())
 
 
 def airg_cf_split(A, opts, level=0, stream=None):

@@ -132,6 +132,19 @@ airg_status airg_ddc_fraction_threshold(int64_t n, int64_t nnz, const int32_t *d
     });
 }
 
+airg_status airg_ddc_fraction_threshold_noalloc(int64_t n, int64_t nnz, const int32_t *d_rowptr,
+                                                const int32_t *d_col, const double *d_val, const int8_t *d_cf,
+                                                double fraction, double *alpha_diag, void *hip_stream) {
+    return guarded([&] {
+        hipStream_t s = (hipStream_t)hip_stream;
+        CsrView A = mk(n, n, nnz, d_rowptr, d_col, d_val);
+        AIRG_REQUIRE(d_cf && alpha_diag, ST_INVALID_ARG, "null argument");
+        *alpha_diag = ddc_fraction_threshold_noalloc(A, d_cf, fraction, s);
+    });
+}
+
+int64_t airg_ddc_fraction_threshold_noalloc_max_rows(void) { return ddc_fraction_noalloc_max_rows(); }
+
 airg_status airg_cf_split(int64_t n, int64_t nnz, const int32_t *d_rowptr, const int32_t *d_col,
                           const double *d_val, const airg_opts *opts, int32_t level, int8_t *d_cf, int64_t *n_f,
                           int64_t *n_c, void *hip_stream) {

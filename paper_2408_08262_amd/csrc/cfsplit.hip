@@ -3,6 +3,7 @@
 // rows of S), and the DDC diagonal-dominance scan with a fixed summation
 // order.
 #include <cmath>
+#include <mutex>
 
 #include "cfsplit.hpp"
 #include "csr.hpp"
@@ -473,6 +474,26 @@ __global__ void k_theta_hist(int32_t n, const double *__restrict__ theta, double
     atomicAdd(&hist[q], 1);
 }
 
+// The boundary b_k = tmax k / 1000 whose count #{theta > b_k} is closest to
+// ceil(fraction #F), ties to the larger k.  hist has 1002 bins as written by
+// k_theta_hist; walking k downwards accumulates the counts, and a strict
+// comparison keeps the larger k on a tie.
+static double fraction_boundary(const int32_t *hist, int32_t nf, double tmax, double fraction) {
+    int64_t target = (int64_t)std::ceil(fraction * (double)nf);
+    int64_t above = hist[1001];   // #{theta > b_1000}
+    int64_t bestd = above > target ? above - target : target - above;
+    int bestk = 1000;
+    for (int k = 999; k >= 0; --k) {
+        above += hist[k + 1];
+        int64_t d = above > target ? above - target : target - above;
+        if (d < bestd) {
+            bestd = d;
+            bestk = k;
+        }
+    }
+    return tmax * (double)bestk / 1000.0;
+}
+
 double ddc_fraction_threshold(const CsrView &A, const int8_t *cf, double fraction, hipStream_t s) {
     int32_t n = A.nr;
     DBuf<int8_t> tmp((size_t)n, s);
@@ -493,23 +514,91 @@ double ddc_fraction_threshold(const CsrView &A, const int8_t *cf, double fractio
     AIRG_LAUNCH_CHECK();
     std::vector<int32_t> hh(1002);
     d2h(hh.data(), hist.p, 1002, s);
-    int64_t target = (int64_t)std::ceil(fraction * (double)nf);
-    double best = tmax;
-    int64_t bestd = -1;
-    int64_t above = 0;   // #{theta > b_k} for k = 1000 down to 0
-    std::vector<int64_t> cnt(1001);
-    for (int q = 1001; q >= 1; --q) {
-        above += hh[q];
-        cnt[q - 1] = above;
+    return fraction_boundary(hh.data(), nf, tmax, fraction);
+}
+
+// ------------------------------------ fraction rule without allocation ---
+// The same threshold for callers that cannot allocate device memory (code
+// under graph capture, serving loops): theta and the counters live in a
+// fixed device array of this file.  Layout: max bits (8 B) at 0, #F (4 B) at
+// 8, the 1002 histogram bins at 16, theta (8 B per row) from kNaThetaOff.
+// Every call on a device shares that device's copy and keeps the previous
+// call's contents; calls that overlap on one device race.
+constexpr size_t kNaThetaOff = 4096;
+constexpr int64_t kNaMaxRows = (int64_t)1 << 21;
+static __device__ __align__(256) unsigned char scratch[kNaThetaOff + (size_t)kNaMaxRows * 8];
+
+constexpr int kNaMaxDevices = 64;
+static std::mutex g_na_mu;
+static unsigned char *g_na_ptr[kNaMaxDevices];
+
+// Device address of this device's scratch, looked up once per device with
+// that device current (the array's name is only a host-side stand-in).
+static unsigned char *noalloc_scratch() {
+    int dev = -1;
+    AIRG_HIP(hipGetDevice(&dev));
+    AIRG_REQUIRE(dev >= 0 && dev < kNaMaxDevices, ST_LIMIT, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        AIRG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        AIRG_REQUIRE(p != nullptr, ST_HIP, "no device address for the scratch array");
+        g_na_ptr[dev] = (unsigned char *)p;
     }
-    for (int k = 0; k <= 1000; ++k) {
-        int64_t d = cnt[k] > target ? cnt[k] - target : target - cnt[k];
-        if (bestd < 0 || d <= bestd) {
-            bestd = d;
-            best = tmax * (double)k / 1000.0;
-        }
+    return g_na_ptr[dev];
+}
+
+int64_t ddc_fraction_noalloc_max_rows() { return kNaMaxRows; }
+
+// theta_i of every row (-1 off F), by the same row sum as k_ddc.
+template <int G>
+__global__ void __launch_bounds__(256) k_ddc_theta(int32_t n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                   const int8_t *__restrict__ cf, double *__restrict__ theta) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t row = (int32_t)(t / G);
+    int lane = group_lane<G>();
+    if (row >= n) return;
+    if (cf[row] != CF_F) {
+        if (lane == 0) theta[row] = -1.0;
+        return;
     }
-    return best;
+    double sum, d;
+    ddc_row_theta<G>(rp, ci, v, cf, row, lane, &sum, &d);
+    if (lane == 0) theta[row] = d == 0.0 ? INFINITY : sum / fabs(d);
+}
+
+double ddc_fraction_threshold_noalloc(const CsrView &A, const int8_t *cf, double fraction, hipStream_t s) {
+    int32_t n = A.nr;
+    AIRG_REQUIRE(n <= kNaMaxRows, ST_LIMIT,
+                 "ddc_fraction_threshold_noalloc: " + std::to_string(n) + " rows exceed the scratch limit of " +
+                     std::to_string(kNaMaxRows));
+    unsigned char *base = noalloc_scratch();
+    auto *mx = (unsigned long long *)base;
+    auto *nF = (int32_t *)(base + 8);
+    auto *hist = (int32_t *)(base + 16);
+    auto *theta = (double *)(base + kNaThetaOff);
+    fill_zero(base, 16 + 1002 * 4, s);
+    int g = lanes_for(A.nnz, A.nr);
+    dispatch_group(g, [&]<int W>() {
+        k_ddc_theta<W><<<grid_for((int64_t)n * W, 256), 256, 0, s>>>(n, A.rp, A.ci, A.v, cf, theta);
+    });
+    AIRG_LAUNCH_CHECK();
+    k_theta_max<<<grid_for(n, 256), 256, 0, s>>>(n, theta, mx, nF);
+    AIRG_LAUNCH_CHECK();
+    unsigned char head[16];
+    AIRG_HIP(hipMemcpyAsync(head, base, 16, hipMemcpyDeviceToHost, s));
+    AIRG_HIP(hipStreamSynchronize(s));
+    double tmax;
+    int32_t nf;
+    std::memcpy(&tmax, head, 8);
+    std::memcpy(&nf, head + 8, 4);
+    k_theta_hist<<<grid_for(n, 256), 256, 0, s>>>(n, theta, tmax, hist);
+    AIRG_LAUNCH_CHECK();
+    int32_t hh[1002];
+    AIRG_HIP(hipMemcpyAsync(hh, hist, sizeof hh, hipMemcpyDeviceToHost, s));
+    AIRG_HIP(hipStreamSynchronize(s));
+    return fraction_boundary(hh, nf, tmax, fraction);
 }
 
 // ---------------------------------------------------------- full split ---

@@ -40,6 +40,11 @@ void ddc(const CsrView &A, double alpha_diag, const int8_t *cf_in, int8_t *cf_ou
          int32_t *flags3 = nullptr);
 // alpha_diag from the fraction rule (1000 uniform bins on [0, theta_max]).
 double ddc_fraction_threshold(const CsrView &A, const int8_t *cf, double fraction, hipStream_t s);
+// The same threshold with theta and the counters in a fixed device array of
+// the library (no device allocation); at most ddc_fraction_noalloc_max_rows()
+// rows, and calls that overlap on one device race.
+double ddc_fraction_threshold_noalloc(const CsrView &A, const int8_t *cf, double fraction, hipStream_t s);
+int64_t ddc_fraction_noalloc_max_rows();
 
 struct CfParams {
     double strong_threshold, ddc_threshold, ddc_fraction;
