@@ -1,21 +1,30 @@
 #!/usr/bin/env python3
 """AIRG benchmark on one MI355X: setup + solve to 1e-10 relative residual.
 
-Workload (default): DG-P1 upwind advection on a 512 x 512 jittered
+Headline workload: DG-P1 upwind advection on a 512 x 512 jittered
 triangulation, 1,572,864 unknowns, 7,860,224 nonzeros, theta = 1.1 rad,
-sigma in {1e-4, 1} on a seeded 16 x 16 block checkerboard (seeded synthetic
-input, resident in device memory before timing starts).
+sigma in {1e-4, 1} on a seeded 16 x 16 block checkerboard, hierarchy truncated
+at 65,536 unknowns with 6 iterations of the order-12 coarse polynomial (seeded
+synthetic input, resident in device memory before timing starts).
 
 A step is one pass of the whole hot path: the full AIRG setup (CF splitting,
 extraction, GMRES polynomials, restrictor, prolongator, Galerkin products,
 finalisation) followed by the solve to ||b - A x|| <= 1e-10 ||b||.  The
 headline form is FP64 flexible GMRES right-preconditioned by an FP32 V-cycle;
-plain FP64 AIRG (Richardson, FP64 V-cycle) is timed on the same GPU for the
-comparison.  value = seconds per step (lower is better).
+on the same GPU and hierarchy options the line also times plain FP64 AIRG
+(undamped Richardson, FP64 V-cycle) and FGMRES around an FP64 V-cycle (which
+separates the precision from the outer solver).  value = seconds per step
+(lower is better).
 
-Also reported: the roofline of the finest-operator SpMV kernel (event-timed
-inside the timed steps) against the 8 TB/s HBM3E peak, and the CPU oracle's
-time on the same workload (setup + Richardson, one host core).
+Also reported for every form: the error against the exact sweep solution and
+against the oracle's own solution, the residual recomputed by the oracle, work
+units and grind time; the roofline of the finest-operator SpMV (event-timed
+inside the timed steps) against the 8 TB/s HBM3E peak; the solve's and the
+setup's algorithmic bytes over their times; two sub-records on workloads whose
+operators do not fit the 256 MB Infinity Cache (the 128^3 tetrahedral P0
+problem, and the 48-problem batch in its batched FP32 form against sequential
+FP64 solves); and the CPU oracle's time on the same workload on all host cores
+and on one.
 """
 import argparse
 import json
@@ -30,7 +39,15 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "AIRG solve time to 1e-10 rel resid + setup s, FP32-precond/batched vs FP64"
 
 
-WORKLOADS = ("dg_square_512", "p0_cube_128", "batch48")
+WORKLOADS = ("dg_square_512", "p0_cube_128", "batch48", "p0_square_64", "adjoint_256")
+# hierarchy options of the timed forms per workload (truncation of the hierarchy and the
+# coarse polynomial's iterations; the sweep that chose them is in the design notes)
+TRUNCATE = {"dg_square_512": (65536, 6), "p0_cube_128": (65536, 3), "batch48": (0, 3),
+            "p0_square_64": (0, 3), "adjoint_256": (0, 3)}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -40,10 +57,15 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="dg_square_512", choices=WORKLOADS)
     p.add_argument("--size", type=int, default=None, help="override the side of the square/cube workload")
-    p.add_argument("--truncate", type=int, default=None, help="truncate_n (p0_cube default 65536)")
+    p.add_argument("--truncate", type=int, default=None, help="truncate_n (default per workload)")
+    p.add_argument("--coarse-iters", type=int, default=None, help="coarse polynomial iterations")
     p.add_argument("--rtol", type=float, default=1e-10)
+    p.add_argument("--sub-steps", type=int, default=3, help="timed steps of each sub-record")
+    p.add_argument("--quick", action="store_true", help="headline only: no sub-records, no oracle legs")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison form")
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison forms")
+    p.add_argument("--levels", action="store_true",
+                   help="only print per-level setup (by phase) and V-cycle times of the workload")
     p.add_argument("--sweep-poly", action="store_true",
                    help="only sweep polynomial order x sparsity order (setup + FP32-FGMRES solve per pair)")
     p.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
@@ -199,162 +221,6 @@ def sweep_poly(a, airg, torch):
     return 0
 
 
-def single(a, airg, torch):
-    """One problem: setup + solve per step."""
-    from workloads import dg_square, p0_cube
-    if a.workload == "dg_square_512":
-        N = a.size or 512
-        P = dg_square(N)
-        desc = ("dg_square_%d: DG-P1 upwind advection, %dx%d jittered triangulation, n=%d, nnz=%d, theta=1.1, "
-                "sigma {1e-4,1} 16x16 block checkerboard" % (N, N, N, P.n, P.nnz))
-        trunc = a.truncate or 0
-    else:
-        N = a.size or 128
-        P = p0_cube(N)
-        trunc = a.truncate if a.truncate is not None else 65536
-        desc = ("p0_cube_%d: P0 upwind advection, %d^3 cubes x 6 Kuhn tetrahedra, n=%d, nnz=%d, "
-                "Omega=(0.5,0.3,0.81)/|.|, sigma=1e-4, truncate_n=%d" % (N, N, P.n, P.nnz, trunc))
-    A = airg.to_device(P.rowptr, P.col, P.val)
-    b = torch.as_tensor(P.b, device="cuda")
-    torch.cuda.synchronize()
-
-    def step(opts):
-        h = airg.airg_setup(*A, opts)
-        x, info = airg.airg_solve(h, b, rtol=a.rtol, max_it=300)
-        st = airg.airg_get_stats(h)
-        del h
-        return info, st
-
-    extra_opts = parse_opts(a.opt)
-    extra_opts.setdefault("use_graph", 1)      # both forms replay a captured V-cycle graph
-    opts32 = airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, truncate_n=trunc,
-                               **extra_opts)
-    opts64 = airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64, truncate_n=trunc,
-                               **extra_opts)
-    for _ in range(a.warmup):
-        step(opts32)
-    torch.cuda.synchronize()
-    airg.airg_kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = [step(opts32) for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    roof = roofline_from_timing(airg, a.workload)
-    sec = (t1 - t0) / a.steps
-    info32, st32 = runs[-1]
-    fp64 = None
-    if not a.no_fp64:
-        step(opts64)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        r64 = [step(opts64) for _ in range(a.steps)]
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        i64, s64 = r64[-1]
-        fp64 = {"seconds_per_step": round((t3 - t2) / a.steps, 4), "setup_s": round(s64["setup_seconds"], 4),
-                "solve_s": round(i64["seconds"], 4), "iterations": i64["iterations"],
-                "rel_residual": i64["rel_residual"], "levels": s64["levels"], "form": "Richardson, FP64 V-cycle"}
-    # numeric re-setup (kept splittings and patterns) for an operator with the same pattern and
-    # values perturbed by U(0.9, 1.1), then the solve: timed after the timed region, own handle
-    import numpy as np
-    h = airg.airg_setup(*A, opts32)
-    newval = torch.as_tensor(P.val * np.random.default_rng(77).uniform(0.9, 1.1, P.val.shape), device="cuda")
-    airg.airg_resetup(h, newval)
-    torch.cuda.synchronize()
-    r0 = time.perf_counter()
-    for _ in range(a.steps):
-        airg.airg_resetup(h, newval)
-        xr, ir = airg.airg_solve(h, b, rtol=a.rtol, max_it=300)
-    torch.cuda.synchronize()
-    r1 = time.perf_counter()
-    resetup = {"seconds_per_step": round((r1 - r0) / a.steps, 4),
-               "resetup_s": round(airg.airg_get_stats(h)["resetup_seconds"], 4),
-               "solve_s": round(ir["seconds"], 4), "iterations": ir["iterations"],
-               "rel_residual": ir["rel_residual"],
-               "form": "numeric re-setup (kept CF splittings and patterns) + FGMRES/FP32, values x U(0.9, 1.1)"}
-    del h
-    cpu = None
-    if not a.no_cpu_baseline:
-        import oracle as O
-        c0 = time.perf_counter()
-        oracle_opts = {k: v for k, v in extra_opts.items() if k != "use_graph"}
-        H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, truncate_n=trunc, **oracle_opts))
-        c1 = time.perf_counter()
-        _, its, rr = H.richardson(P.b, a.rtol, 300)
-        c2 = time.perf_counter()
-        cpu = {"value": round(c2 - c0, 3), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": "whole workload: oracle setup (%.2f s) + FP64 Richardson to %.0e (%.2f s, %d its), "
-                         "single thread" % (c1 - c0, a.rtol, c2 - c1, its)}
-    extra = {"setup_s": round(st32["setup_seconds"], 4), "solve_s": round(info32["seconds"], 4),
-             "iterations": info32["iterations"], "rel_residual": info32["rel_residual"], "levels": st32["levels"],
-             "complexity": {"grid": round(st32["grid_complexity"], 3),
-                            "operator": round(st32["operator_complexity"], 3),
-                            "storage": round(st32["storage_complexity"], 3)},
-             "phase_seconds": {k: round(v, 4) for k, v in st32["phase_seconds"].items()},
-             "vcycle_bytes_fp32": st32["vcycle_bytes_fp32"], "fp64_comparison": fp64, "resetup": resetup}
-    cfg = {"workload": desc, "form": "FGMRES(30) FP64 outer + FP32 AIRG V-cycle", "rtol": a.rtol,
-           "parallelism": "single GPU"}
-    cfg["options"] = extra_opts
-    return sec, cfg, "f64 (f32 V-cycle)", roof, cpu, extra
-
-
-def batched(a, airg, torch):
-    """48 independent DG-P1 problems x 4 rhs: batched FP32 form vs sequential FP64."""
-    from workloads import batch as batch_problems, concat
-    probs = batch_problems()
-    rp, ci, val, b, offs, seeds = concat(probs)
-    A = airg.to_device(rp, ci, val)
-    B = torch.as_tensor(b, device="cuda")
-    optsb = airg.default_opts(outer=airg.OUTER_FGMRES, precond_precision=32, use_graph=1, autotune=1)
-    opts64 = airg.default_opts(outer=airg.OUTER_RICHARDSON, precond_precision=64)
-
-    def step(opts):
-        h = airg.airg_setup(*A, opts, seg_offsets=offs, seg_seeds=seeds)
-        x, info = airg.airg_solve(h, B, rtol=a.rtol, max_it=300)
-        st = airg.airg_get_stats(h)
-        del h
-        return info, st
-
-    for _ in range(a.warmup):
-        step(optsb)
-    torch.cuda.synchronize()
-    airg.airg_kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = [step(optsb) for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    roof = roofline_from_timing(airg, a.workload)
-    sec = (t1 - t0) / a.steps
-    infob, stb = runs[-1]
-    fp64 = None
-    if not a.no_fp64:
-        step(opts64)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        r64 = [step(opts64) for _ in range(a.steps)]
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        i64, s64 = r64[-1]
-        fp64 = {"seconds_per_step": round((t3 - t2) / a.steps, 4), "setup_s": round(s64["setup_seconds"], 4),
-                "solve_s": round(i64["seconds"], 4), "iterations": i64["iterations"],
-                "rel_residual": i64["rel_residual"],
-                "form": "48 segments solved one after another, 4 rhs one after another, FP64 Richardson"}
-    n = int(offs[-1])
-    desc = ("batch48: 48 DG-P1 upwind problems, sides U{64..384}, theta ~ U(0, 2 pi), sigma=1e-3, 4 rhs each; "
-            "n=%d, nnz=%d" % (n, int(rp[-1])))
-    extra = {"setup_s": round(stb["setup_seconds"], 4), "solve_s": round(infob["seconds"], 4),
-             "iterations": infob["iterations"], "rel_residual": infob["rel_residual"], "levels": stb["levels"],
-             "complexity": {"grid": round(stb["grid_complexity"], 3),
-                            "operator": round(stb["operator_complexity"], 3),
-                            "storage": round(stb["storage_complexity"], 3)},
-             "phase_seconds": {kk: round(v, 4) for kk, v in stb["phase_seconds"].items()},
-             "vcycle_bytes_fp32": stb["vcycle_bytes_fp32"], "fp64_comparison": fp64}
-    cfg = {"workload": desc, "form": "batched FGMRES(30) FP64 per (segment, rhs) + batched FP32 V-cycle, "
-                                     "one SpMM launch per stage, HIP graph, autotuned kernels",
-           "rtol": a.rtol, "parallelism": "single GPU"}
-    return sec, cfg, "f64 (f32 V-cycle)", roof, None, extra
 
 
 def copy_calibration(mib, torch):
@@ -378,6 +244,425 @@ def copy_calibration(mib, torch):
     return 0
 
 
+def truncation(a):
+    t, c = TRUNCATE[a.workload]
+    return (a.truncate if a.truncate is not None else t), (a.coarse_iters if a.coarse_iters is not None else c)
+
+
+def make_problem(name, size=None):
+    from workloads import dg_square, p0_cube, p0_square
+    if name == "dg_square_512":
+        N = size or 512
+        P = dg_square(N)
+        desc = ("dg_square_%d: DG-P1 upwind advection, %dx%d jittered triangulation, n=%d, nnz=%d, theta=1.1, "
+                "sigma {1e-4,1} 16x16 block checkerboard" % (N, N, N, P.n, P.nnz))
+        bs = 3
+    elif name == "p0_cube_128":
+        N = size or 128
+        P = p0_cube(N)
+        desc = ("p0_cube_%d: P0 upwind advection, %d^3 cubes x 6 Kuhn tetrahedra, n=%d, nnz=%d, "
+                "Omega=(0.5,0.3,0.81)/|.|, sigma=1e-4" % (N, N, P.n, P.nnz))
+        bs = 1
+    else:
+        N = size or 64
+        P = p0_square(N)
+        desc = ("p0_square_%d: P0 upwind advection, %dx%d squares x 2 triangles, n=%d, nnz=%d, theta=0.3, "
+                "sigma=1e-3" % (N, N, N, P.n, P.nnz))
+        bs = 1
+    return P, desc, bs
+
+
+def forms(airg):
+    return {
+        "fp32_fgmres": (dict(outer=airg.OUTER_FGMRES, precond_precision=32),
+                        "FGMRES(30) FP64 outer + FP32 AIRG V-cycle"),
+        "fp64_richardson": (dict(outer=airg.OUTER_RICHARDSON, precond_precision=64),
+                            "undamped Richardson + FP64 AIRG V-cycle (plain AIRG)"),
+        "fp64_fgmres": (dict(outer=airg.OUTER_FGMRES, precond_precision=64),
+                        "FGMRES(30) FP64 outer + FP64 AIRG V-cycle"),
+    }
+
+
+def time_form(airg, torch, A, b, opts, steps, warmup, rtol, workload=None, seg=None):
+    """warmup untimed and `steps` timed passes of setup + solve on fresh handles; the
+    finest-operator product is event-timed over the timed passes when workload is given."""
+    segkw = {} if seg is None else {"seg_offsets": seg[0], "seg_seeds": seg[1]}
+
+    def step():
+        h = airg.airg_setup(*A, opts, **segkw)
+        x, info = airg.airg_solve(h, b, rtol=rtol, max_it=300)
+        st = airg.airg_get_stats(h)
+        del h
+        return x, info, st
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if workload:
+        airg.airg_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = None
+        last = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    roof = roofline_from_timing(airg, workload) if workload else None
+    x, info, st = last
+    return {"sec": (t1 - t0) / steps, "x": x, "info": info, "st": st, "roof": roof}
+
+
+def outer_bytes(form, its, n, restart=30):
+    """Vector traffic of the outer iterations around the cycles and top products: the casts and
+    permutations into and out of the cycle, FGMRES's classical Gram-Schmidt twice (read the basis
+    twice per pass, update w) and normalisation, or Richardson's update and norm."""
+    if form == "fp64_richardson":
+        return its * (24 + 8 + 40) * n
+    cast = 32 if form == "fp32_fgmres" else 40
+    tot = 0
+    for i in range(its):
+        j = i % restart
+        tot += (4 * (j + 1) + 8) * 8 * n + cast * n
+    return tot
+
+
+def form_record(form, label, r, n, top_us=None):
+    info, st = r["info"], r["st"]
+    its = max(1, info["iterations"])
+    wu_cycle = st["vcycle_nnz"] / st["top_nnz"]
+    wus = info["iterations"] * (wu_cycle + 1.0)
+    vb = st["vcycle_bytes_fp32"] if form == "fp32_fgmres" else st["vcycle_bytes_fp64"]
+    solve_bytes = info["iterations"] * (vb + st["top_spmv_bytes_fp64"]) + outer_bytes(form, info["iterations"], n)
+    solve_gbs = solve_bytes / info["seconds"] / 1e9 if info["seconds"] > 0 else 0.0
+    setup_gbs = st["setup_bytes"] / st["setup_seconds"] / 1e9 if st["setup_seconds"] > 0 else 0.0
+    rec = {"form": label, "seconds_per_step": round(r["sec"], 4), "setup_s": round(st["setup_seconds"], 4),
+           "solve_s": round(info["seconds"], 4), "iterations": info["iterations"],
+           "rel_residual": info["rel_residual"], "levels": st["levels"],
+           "wu_per_cycle": round(wu_cycle, 3), "wus": round(wus, 1),
+           "grind_ns_per_unknown_per_cycle": round(info["seconds"] / n / its * 1e9, 4),
+           "cycles": {"eager": st["cycles_eager"], "graph_replays": st["cycles_graph"]},
+           "solve_roofline": {"bound": "hbm", "achieved": round(solve_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(solve_gbs / HBM_PEAK_GBS, 4), "bytes": int(solve_bytes),
+                              "what": "iterations x (V-cycle + top-product algorithmic bytes) + outer vector "
+                                      "traffic, over the solve time"},
+           "setup_roofline": {"bound": "hbm", "achieved": round(setup_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(setup_gbs / HBM_PEAK_GBS, 4), "bytes": int(st["setup_bytes"]),
+                              "what": "bytes the setup steps must move (each reading its inputs and writing its "
+                                      "outputs once), over the setup time"}}
+    if top_us:
+        rec["wu_ratio"] = round(info["seconds"] / (wus * top_us * 1e-6), 3) if wus > 0 else None
+    return rec
+
+
+def accuracy(P, x, xs, xo=None, A=None):
+    """Errors of a device solution against the exact sweep and the oracle's solution, and its
+    residual recomputed by the oracle's product (FP64)."""
+    import numpy as np
+    import oracle as O
+    A = A or (P.rowptr, P.col, P.val)
+    b = P.b
+    out = {"rel_residual_oracle": float(np.linalg.norm(b - O.spmv(A, x)) / np.linalg.norm(b)),
+           "err_vs_sweep": float(np.linalg.norm(x - xs) / np.linalg.norm(xs))}
+    if xo is not None:
+        out["err_vs_oracle"] = float(np.linalg.norm(x - xo) / np.linalg.norm(xo))
+    return out
+
+
+def oracle_baseline(P, params, rtol):
+    """The oracle on the headline workload: setup + FP64 Richardson, on every host core the process
+    may use and on one."""
+    import oracle as O
+    want = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    res = {}
+    for thr in (want, 1):
+        O.set_threads(thr)
+        used = O.get_threads()
+        c0 = time.perf_counter()
+        H = O.Hierarchy((P.rowptr, P.col, P.val), params)
+        c1 = time.perf_counter()
+        x, its, rr = H.richardson(P.b, rtol, 300)
+        c2 = time.perf_counter()
+        res[thr] = {"cores": used, "setup_s": c1 - c0, "solve_s": c2 - c1, "its": its, "x": x}
+        del H
+        if want == 1:
+            res[1] = res[thr]
+            break
+    O.set_threads(want)
+    return res[want], res[1]
+
+
+def single(a, airg, torch):
+    """The headline workload: three forms of setup + solve, accuracy, work units, rooflines and the
+    oracle baseline."""
+    import numpy as np
+    P, desc, bs = make_problem(a.workload, a.size)
+    trunc, citers = truncation(a)
+    desc += ", truncate_n=%d, coarse_iters=%d" % (trunc, citers)
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    b = torch.as_tensor(P.b, device="cuda")
+    torch.cuda.synchronize()
+    extra_opts = parse_opts(a.opt)
+    extra_opts.setdefault("use_graph", 1)
+    base = dict(seed=P.seed, truncate_n=trunc, coarse_iters=citers, **extra_opts)
+    F = forms(airg)
+    names = ["fp32_fgmres"] + ([] if a.no_fp64 else ["fp64_richardson", "fp64_fgmres"])
+    runs = {}
+    for k in names:
+        kw, _ = F[k]
+        log("timing %s: %s" % (a.workload, k))
+        runs[k] = time_form(airg, torch, A, b, airg.default_opts(**base, **kw), a.steps if k == "fp32_fgmres" else
+                            max(1, min(a.steps, 10)), a.warmup if k == "fp32_fgmres" else 1, a.rtol,
+                            workload=a.workload if k == "fp32_fgmres" else None)
+    roof = runs["fp32_fgmres"]["roof"]
+    top_us = roof["avg_launch_us"] if roof else None
+    recs = {k: form_record(k, F[k][1], runs[k], P.n, top_us) for k in names}
+    # numeric re-setup (kept splittings and patterns) for an operator with the same pattern and
+    # values perturbed by U(0.9, 1.1), then the solve: timed after the timed region, own handle
+    h = airg.airg_setup(*A, airg.default_opts(**base, **F["fp32_fgmres"][0]))
+    newval = torch.as_tensor(P.val * np.random.default_rng(77).uniform(0.9, 1.1, P.val.shape), device="cuda")
+    airg.airg_resetup(h, newval)
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    nre = max(1, min(a.steps, 10))
+    for _ in range(nre):
+        airg.airg_resetup(h, newval)
+        xr, ir = airg.airg_solve(h, b, rtol=a.rtol, max_it=300)
+    torch.cuda.synchronize()
+    r1 = time.perf_counter()
+    resetup = {"seconds_per_step": round((r1 - r0) / nre, 4),
+               "resetup_s": round(airg.airg_get_stats(h)["resetup_seconds"], 4),
+               "solve_s": round(ir["seconds"], 4), "iterations": ir["iterations"],
+               "rel_residual": ir["rel_residual"],
+               "form": "numeric re-setup (kept CF splittings and patterns) + FGMRES/FP32, values x U(0.9, 1.1)"}
+    del h, xr, newval
+    cpu = None
+    if not a.quick:
+        import oracle as O
+        from oracle.sweep import sweep_solve
+        xs = sweep_solve(P.rowptr, P.col, P.val, P.b, bs)
+        xo = None
+        if not a.no_cpu_baseline:
+            log("oracle baseline")
+            oracle_opts = {k: v for k, v in extra_opts.items() if k != "use_graph"}
+            params = O.default_params(seed=P.seed, truncate_n=trunc, coarse_iters=citers, **oracle_opts)
+            allc, one = oracle_baseline(P, params, a.rtol)
+            xo = allc["x"]
+            cpu = {"value": round(allc["setup_s"] + allc["solve_s"], 3), "unit": "s", "cores": allc["cores"],
+                   "kind": "oracle",
+                   "sample": "whole workload: oracle setup (%.2f s) + FP64 Richardson to %.0e (%.2f s, %d its) on "
+                             "%d threads" % (allc["setup_s"], a.rtol, allc["solve_s"], allc["its"], allc["cores"]),
+                   "single_core": {"value": round(one["setup_s"] + one["solve_s"], 3), "cores": 1,
+                                   "setup_s": round(one["setup_s"], 3), "solve_s": round(one["solve_s"], 3)}}
+            oerr = {"oracle_rel_residual": float(np.linalg.norm(P.b - O.spmv((P.rowptr, P.col, P.val), xo)) /
+                                                 np.linalg.norm(P.b)),
+                    "oracle_err_vs_sweep": float(np.linalg.norm(xo - xs) / np.linalg.norm(xs))}
+            cpu["accuracy"] = oerr
+        for k in names:
+            recs[k]["accuracy"] = accuracy(P, runs[k]["x"].cpu().numpy(), xs, xo)
+    head = recs["fp32_fgmres"]
+    st = runs["fp32_fgmres"]["st"]
+    extra = dict(head)
+    del extra["form"]
+    extra["complexity"] = {"grid": round(st["grid_complexity"], 3), "operator": round(st["operator_complexity"], 3),
+                           "storage": round(st["storage_complexity"], 3)}
+    extra["phase_seconds"] = {k: round(v, 4) for k, v in st["phase_seconds"].items()}
+    extra["vcycle_bytes_fp32"] = st["vcycle_bytes_fp32"]
+    extra["comparison"] = {k: recs[k] for k in names if k != "fp32_fgmres"}
+    extra["resetup"] = resetup
+    cfg = {"workload": desc, "form": F["fp32_fgmres"][1], "rtol": a.rtol, "parallelism": "single GPU",
+           "options": extra_opts}
+    del runs, A, b
+    return a.steps, cfg, "f64 (f32 V-cycle)", roof, cpu, extra
+
+
+def hbm_subrecord(a, airg, torch):
+    """The 128^3 tetrahedral P0 problem (operator 703.5 MB in FP64, beyond the Infinity Cache):
+    FP32-preconditioned FGMRES against plain FP64 AIRG, truncated hierarchy."""
+    import numpy as np
+    P, desc, bs = make_problem("p0_cube_128")
+    trunc, citers = TRUNCATE["p0_cube_128"]
+    desc += ", truncate_n=%d, coarse_iters=%d" % (trunc, citers)
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    b = torch.as_tensor(P.b, device="cuda")
+    F = forms(airg)
+    out = {"workload": desc}
+    xs = None
+    if not a.quick:
+        from oracle.sweep import sweep_solve
+        xs = sweep_solve(P.rowptr, P.col, P.val, P.b, bs)
+    for k in ("fp32_fgmres", "fp64_richardson"):
+        log("timing p0_cube_128: %s" % k)
+        r = time_form(airg, torch, A, b, airg.default_opts(seed=P.seed, truncate_n=trunc, coarse_iters=citers,
+                                                           use_graph=1, **F[k][0]),
+                      a.sub_steps, 1, a.rtol, workload="p0_cube_128" if k == "fp32_fgmres" else None)
+        top_us = out["roofline"]["avg_launch_us"] if "roofline" in out else (r["roof"] or {}).get("avg_launch_us")
+        rec = form_record(k, F[k][1], r, P.n, top_us)
+        if xs is not None:
+            rec["accuracy"] = accuracy(P, r["x"].cpu().numpy(), xs)
+        if r["roof"]:
+            out["roofline"] = r["roof"]
+        out[k] = rec
+        del r
+    out["steps"] = a.sub_steps
+    out["value"] = out["fp32_fgmres"]["seconds_per_step"]
+    out["fp64_over_fp32"] = round(out["fp64_richardson"]["seconds_per_step"] / out["value"], 3)
+    del A, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_subrecord(a, airg, torch):
+    """48 independent DG-P1 problems x 4 rhs: the batched FP32 form (one SpMM launch per stage,
+    captured graph, autotuned kernels) against the 48 problems solved one after another in plain FP64
+    AIRG."""
+    import numpy as np
+    from workloads import batch as batch_problems, concat
+    probs = batch_problems()
+    rp, ci, val, bb, offs, seeds = concat(probs)
+    A = airg.to_device(rp, ci, val)
+    B = torch.as_tensor(bb, device="cuda")
+    n = int(offs[-1])
+    out = {"workload": "batch48: 48 DG-P1 upwind problems, sides U{64..384}, theta ~ U(0, 2 pi), sigma=1e-3, "
+                       "4 rhs each; n=%d, nnz=%d" % (n, int(rp[-1]))}
+    log("timing batch48: batched FP32")
+    rb = time_form(airg, torch, A, B, airg.default_opts(outer=airg.OUTER_FGMRES, precond_precision=32, use_graph=1,
+                                                        autotune=1),
+                   a.sub_steps, 1, a.rtol, workload="batch48", seg=(offs, seeds))
+    out["roofline"] = rb["roof"]
+    recb = form_record("fp32_fgmres", "batched FGMRES(30) FP64 per (segment, rhs) + batched FP32 V-cycle, one "
+                                      "SpMM launch per stage, HIP graph, autotuned kernels", rb, n,
+                       rb["roof"]["avg_launch_us"] if rb["roof"] else None)
+    log("timing batch48: sequential FP64")
+    r64 = time_form(airg, torch, A, B, airg.default_opts(outer=airg.OUTER_RICHARDSON, precond_precision=64),
+                    1, 1, a.rtol, seg=(offs, seeds))
+    rec64 = form_record("fp64_richardson", "48 segments solved one after another, 4 rhs one after another, "
+                                           "plain FP64 AIRG (Richardson)", r64, n)
+    if not a.quick:
+        import oracle as O
+        from oracle.sweep import sweep_solve
+        Xb, X64 = rb["x"].cpu().numpy(), r64["x"].cpu().numpy()
+        worst = {"fp32": [0.0, 0.0], "fp64": [0.0, 0.0]}
+        for p, Pp in enumerate(probs):
+            Ap = (Pp.rowptr, Pp.col, Pp.val)
+            xs = sweep_solve(Pp.rowptr, Pp.col, Pp.val, Pp.b, 3)
+            for key, X in (("fp32", Xb), ("fp64", X64)):
+                Xp = X[offs[p]:offs[p + 1]]
+                for c in range(Pp.b.shape[1]):
+                    r = np.linalg.norm(Pp.b[:, c] - O.spmv(Ap, Xp[:, c])) / np.linalg.norm(Pp.b[:, c])
+                    e = np.linalg.norm(Xp[:, c] - xs[:, c]) / np.linalg.norm(xs[:, c])
+                    worst[key][0] = max(worst[key][0], float(r))
+                    worst[key][1] = max(worst[key][1], float(e))
+        recb["accuracy"] = {"max_rel_residual_oracle": worst["fp32"][0], "max_err_vs_sweep": worst["fp32"][1],
+                            "pairs": len(probs) * bb.shape[1]}
+        rec64["accuracy"] = {"max_rel_residual_oracle": worst["fp64"][0], "max_err_vs_sweep": worst["fp64"][1],
+                             "pairs": len(probs) * bb.shape[1]}
+    out["batched_fp32"] = recb
+    out["sequential_fp64"] = rec64
+    out["steps"] = a.sub_steps
+    out["value"] = recb["seconds_per_step"]
+    out["fp64_over_batched"] = round(rec64["seconds_per_step"] / recb["seconds_per_step"], 3)
+    del A, B, rb, r64
+    torch.cuda.empty_cache()
+    return out
+
+
+def levels_report(a, airg, torch):
+    """Per-level setup time by phase and per-level V-cycle time (FP32 and FP64) of one workload."""
+    P, desc, bs = make_problem(a.workload, a.size)
+    trunc, citers = truncation(a)
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    opts = airg.default_opts(seed=P.seed, truncate_n=trunc, coarse_iters=citers, outer=airg.OUTER_FGMRES,
+                             precond_precision=32, use_graph=1)
+    for _ in range(2):
+        h = airg.airg_setup(*A, opts)
+        del h
+    h = airg.airg_setup(*A, opts)
+    st = airg.airg_get_stats(h)
+    t32 = airg.airg_vcycle_profile(h, precision=32, reps=20)
+    t64 = airg.airg_vcycle_profile(h, precision=64, reps=20)
+    rows = []
+    for l in range(st["levels"]):
+        lv = airg.airg_get_level(h, l, with_cf=False)
+        rows.append({"level": l, "n": lv["n"], "nnz_a": lv["nnz_a"], "coarsest": lv["coarsest"],
+                     "setup_ms": {k: round(v * 1e3, 4) for k, v in lv["setup_seconds"].items()},
+                     "setup_bytes": lv["setup_bytes"],
+                     "vcycle_us_fp32": round(t32[l] * 1e6, 2), "vcycle_us_fp64": round(t64[l] * 1e6, 2)})
+    print(json.dumps({"levels_report": desc + ", truncate_n=%d, coarse_iters=%d" % (trunc, citers),
+                      "setup_s": st["setup_seconds"], "phase_seconds": st["phase_seconds"], "rows": rows}),
+          flush=True)
+    return 0
+
+
+def small_workload(a, airg, torch):
+    """C1 (p0_square_64, plain untruncated FP64 AIRG) or C5 (adjoint_256: forward solve and the
+    adjoint A^T solve with the gradients) timed per step."""
+    import numpy as np
+    if a.workload == "p0_square_64":
+        P, desc, bs = make_problem("p0_square_64", a.size)
+        A = airg.to_device(P.rowptr, P.col, P.val)
+        b = torch.as_tensor(P.b, device="cuda")
+        r = time_form(airg, torch, A, b, airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON,
+                                                           precond_precision=64, use_graph=1),
+                      a.steps, a.warmup, a.rtol)
+        rec = form_record("fp64_richardson", "undamped Richardson + FP64 AIRG V-cycle (plain AIRG)", r, P.n)
+        if not a.quick:
+            from oracle.sweep import sweep_solve
+            rec["accuracy"] = accuracy(P, r["x"].cpu().numpy(), sweep_solve(P.rowptr, P.col, P.val, P.b, 1))
+        cfg = {"workload": desc, "form": rec.pop("form"), "rtol": a.rtol, "parallelism": "single GPU"}
+        return r["sec"], cfg, "f64", None, None, rec
+    # adjoint_256: loss = sum of u^2 over the detector patch; one step = forward setup + solve, the
+    # adjoint hierarchy and A^T solve, and both gradients
+    from paper_2408_08262_amd import adjoint as adj
+    from workloads import adjoint as adjoint_problem
+    N = a.size or 256
+    P = adjoint_problem(N)
+    m = P.meta
+    prob = adj.DiffProblem(P.rowptr, P.col, m["val_adv"], m["mass"], opts=airg.default_opts(seed=P.seed))
+    s = torch.as_tensor(m["src"], device="cuda")
+    sg = torch.as_tensor(m["sigma"], device="cuda")
+    mask = torch.as_tensor(m["patch_mask"], device="cuda")
+
+    def step():
+        si = s.clone().requires_grad_(True)
+        gi = sg.clone().requires_grad_(True)
+        u = adj.solve(si, gi, prob)
+        (u[mask] ** 2).sum().backward()
+        return u, si.grad, gi.grad
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        u, gs, gsig = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / a.steps
+    rec = {"seconds_per_step": round(sec, 4)}
+    if not a.quick:
+        import scipy.sparse as sp
+        from oracle.sweep import sweep_solve
+        nc = m["mass"].shape[0]
+        K = np.repeat(np.arange(nc), 9)
+        rr = K * 3 + np.tile(np.repeat(np.arange(3), 3), nc)
+        cc = K * 3 + np.tile(np.arange(3), nc * 3)
+        Mb = sp.csr_matrix((m["mass"].ravel(), (rr, cc)), shape=(P.n, P.n))
+        us = sweep_solve(P.rowptr, P.col, P.val, Mb @ m["src"], 3)
+        lam = sweep_solve(P.rowptr, P.col, P.val, np.where(m["patch_mask"], 2.0 * us, 0.0), 3, transpose=True)
+        want_s = Mb.T @ lam
+        want_sig = -np.einsum("ka,kab,kb->k", lam.reshape(-1, 3), m["mass"], us.reshape(-1, 3))
+        rec["accuracy"] = {
+            "u_err_vs_sweep": float(np.linalg.norm(u.detach().cpu().numpy() - us) / np.linalg.norm(us)),
+            "grad_source_err_vs_sweeps": float(np.linalg.norm(gs.cpu().numpy() - want_s) / np.linalg.norm(want_s)),
+            "grad_sigma_err_vs_sweeps": float(np.linalg.norm(gsig.cpu().numpy() - want_sig) /
+                                              np.linalg.norm(want_sig))}
+    desc = ("adjoint_256: DG-P1 upwind advection, %dx%d jittered triangulation, n=%d, nnz=%d, theta=1.1, "
+            "sigma_K = exp(N(ln 1e-2, 1)), loss = sum of u^2 over a 32x32-square detector patch" % (N, N, P.n, P.nnz))
+    cfg = {"workload": desc, "form": "forward AIRG setup + FP64 Richardson solve, A^T hierarchy + adjoint solve, "
+                                     "gradients wrt source and sigma", "rtol": 1e-10, "parallelism": "single GPU"}
+    return sec, cfg, "f64", None, None, rec
+
+
 def main():
     a = parse()
     if a.record_traffic:
@@ -392,14 +677,30 @@ def main():
     from paper_2408_08262_amd import airg
     if a.sweep_poly:
         return sweep_poly(a, airg, torch)
+    if a.levels:
+        return levels_report(a, airg, torch)
+    sub = {}
     if a.workload == "batch48":
-        sec, cfg, dtype, roof, cpu, extra = batched(a, airg, torch)
+        rec = batched_subrecord(a, airg, torch)
+        sec = rec["value"]
+        cfg = {"workload": rec.pop("workload"), "form": rec["batched_fp32"]["form"], "rtol": a.rtol,
+               "parallelism": "single GPU"}
+        roof, cpu, extra, dtype = rec.pop("roofline"), None, rec, "f64 (f32 V-cycle)"
+        steps = a.sub_steps
+    elif a.workload in ("p0_square_64", "adjoint_256"):
+        sec, cfg, dtype, roof, cpu, extra = small_workload(a, airg, torch)
+        steps = a.steps
     else:
-        sec, cfg, dtype, roof, cpu, extra = single(a, airg, torch)
-    out = {"metric": METRIC, "value": round(sec, 4), "unit": "s", "n_gpus": 1, "steps": a.steps,
+        steps, cfg, dtype, roof, cpu, extra = single(a, airg, torch)
+        sec = extra["seconds_per_step"]
+        if a.workload == "dg_square_512" and not a.quick and a.size is None:
+            sub["hbm"] = hbm_subrecord(a, airg, torch)
+            sub["batched"] = batched_subrecord(a, airg, torch)
+    out = {"metric": METRIC, "value": round(sec, 4), "unit": "s", "n_gpus": 1, "steps": steps,
            "warmup": a.warmup, "ms_per_step": round(sec * 1e3, 2), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg}
     out.update(extra)
+    out.update(sub)
     out["roofline"] = roof
     out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -106,6 +106,8 @@ typedef struct airg_solve_info {
     double seconds;               /* device-synchronised wall time of the call          */
 } airg_solve_info;
 
+enum { AIRG_PHASE_CF = 0, AIRG_PHASE_EXTRACT, AIRG_PHASE_POLY, AIRG_PHASE_RESTRICTOR, AIRG_PHASE_PROLONG,
+       AIRG_PHASE_COARSE, AIRG_PHASE_FINALIZE, AIRG_PHASE_COUNT };
 typedef struct airg_level_info {
     int32_t level;
     int32_t coarsest;
@@ -114,10 +116,13 @@ typedef struct airg_level_info {
     int32_t poly_terms;           /* coefficients kept after the breakdown test         */
     int32_t poly_requested;
     double alpha[16];             /* polynomial coefficients alpha_0 .. alpha_{m-1}     */
+    double setup_seconds[AIRG_PHASE_COUNT]; /* device time of this level's setup by phase */
+                                  /* (batched form: the level over all segments)         */
+    int64_t setup_bytes;          /* bytes the level's setup steps must move, each step */
+                                  /* reading its inputs and writing its outputs once    */
+                                  /* (0 in the batched form)                            */
 } airg_level_info;
 
-enum { AIRG_PHASE_CF = 0, AIRG_PHASE_EXTRACT, AIRG_PHASE_POLY, AIRG_PHASE_RESTRICTOR, AIRG_PHASE_PROLONG,
-       AIRG_PHASE_COARSE, AIRG_PHASE_FINALIZE, AIRG_PHASE_COUNT };
 
 typedef struct airg_stats {
     int32_t levels;
@@ -132,6 +137,14 @@ typedef struct airg_stats {
     int64_t top_spmv_bytes_fp64;  /* bytes of one SpMV with the top operator            */
     int64_t device_bytes;         /* device memory held by the handle                   */
     double resetup_seconds;       /* last airg_resetup (0 before the first)             */
+    int64_t vcycle_nnz;           /* stored entries of the matrices one V-cycle applies;  */
+                                  /* / top_nnz = work units per cycle (WUs: the work     */
+                                  /* over that of one product with the top operator,     */
+                                  /* strong-tolerance subsection of the Results)         */
+    int64_t top_nnz;              /* nnz(A_0)                                           */
+    int64_t cycles_eager;         /* V-cycles applied since setup kernel by kernel      */
+    int64_t cycles_graph;         /* ... and as replays of a captured HIP graph         */
+    int64_t setup_bytes;          /* sum of the levels' setup_bytes                     */
 } airg_stats;
 
 /* Fills *opts with the defaults above.  Returns AIRG_ERR_INVALID_ARG if
@@ -205,6 +218,19 @@ airg_status airg_vcycle(const airg_handle *h, int32_t segment, const double *d_g
  * precond_precision = 32); builds the batched operators on first use, as
  * airg_solve does.  Synchronises hip_stream. */
 airg_status airg_batch_vcycle(airg_handle *h, int32_t nrhs, const double *d_g, double *d_e, void *hip_stream);
+
+/* Per-level cost of the V-cycle (the per-level solve breakdown of the
+ * parallel-results section): runs reps eager cycles (no graph) at precision
+ * 64 or 32 on a zero input with events around each level's own work -- the
+ * restriction to the next level plus the prolongation and smoothing after
+ * the coarse correction; the whole coarse solve on the coarsest level -- and
+ * writes the mean device seconds per cycle of level l to h_level_seconds[l]
+ * for l < min(levels, max_levels).  The events add a few microseconds per
+ * level, so the sum exceeds a graph-replayed cycle's time on small levels.
+ * segment as for airg_get_level; not for the batched form.  Synchronises
+ * hip_stream. */
+airg_status airg_vcycle_profile(const airg_handle *h, int32_t segment, int32_t precision, int32_t reps,
+                                double *h_level_seconds, int32_t max_levels, void *hip_stream);
 
 /* Describes one level of one segment; h_cf (nullable, n entries) receives
  * the CF markers (1 = F, 2 = C; all 1 on the coarsest level).  segment >= 0

@@ -50,7 +50,8 @@ class LevelInfo(C.Structure):
     _fields_ = [("level", C.c_int32), ("coarsest", C.c_int32), ("n", C.c_int64), ("n_f", C.c_int64),
                 ("n_c", C.c_int64), ("nnz_a", C.c_int64), ("nnz_aff", C.c_int64), ("nnz_afc", C.c_int64),
                 ("nnz_ainv", C.c_int64), ("nnz_z", C.c_int64), ("nnz_w", C.c_int64),
-                ("poly_terms", C.c_int32), ("poly_requested", C.c_int32), ("alpha", C.c_double * 16)]
+                ("poly_terms", C.c_int32), ("poly_requested", C.c_int32), ("alpha", C.c_double * 16),
+                ("setup_seconds", C.c_double * 7), ("setup_bytes", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -59,7 +60,8 @@ class Stats(C.Structure):
                 ("setup_seconds", C.c_double), ("phase_seconds", C.c_double * 7),
                 ("vcycle_bytes_fp64", C.c_int64), ("vcycle_bytes_fp32", C.c_int64),
                 ("top_spmv_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64),
-                ("resetup_seconds", C.c_double)]
+                ("resetup_seconds", C.c_double), ("vcycle_nnz", C.c_int64), ("top_nnz", C.c_int64),
+                ("cycles_eager", C.c_int64), ("cycles_graph", C.c_int64), ("setup_bytes", C.c_int64)]
 
 
 _VP, _I32, _I64, _U64, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
@@ -72,6 +74,7 @@ _SIGS = {
     "airg_resetup": [_VP, _VP, _VP],
     "airg_vcycle": [_VP, _I32, _VP, _VP, _I32, _VP],
     "airg_batch_vcycle": [_VP, _I32, _VP, _VP, _VP],
+    "airg_vcycle_profile": [_VP, _I32, _I32, _I32, _VP, _I32, _VP],
     "airg_get_level": [_VP, _I32, _I32, C.POINTER(LevelInfo), _VP],
     "airg_get_level_matrix": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
     "airg_csr_info": [_VP, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)],
@@ -277,6 +280,15 @@ def airg_vcycle(h, g, precision=64, segment=0, stream=None):
     return e
 
 
+def airg_vcycle_profile(h, precision=32, reps=10, segment=0, stream=None):
+    """Mean device seconds per V-cycle of each level's own work (eager cycles
+    with events around every level), as a list indexed by level."""
+    nl = airg_get_stats(h)["levels"]
+    out = (C.c_double * max(nl, 1))()
+    _check(lib().airg_vcycle_profile(h.ptr, segment, precision, reps, out, nl, _stream(stream)))
+    return list(out)[:nl]
+
+
 def airg_batch_vcycle(h, g, stream=None):
     """E = V(G): one batched FP32 V-cycle over every segment and right-hand
     side (G: (n, nrhs) float64 device tensor, natural order)."""
@@ -297,8 +309,9 @@ def airg_get_stats(h):
 def airg_get_level(h, level, segment=0, with_cf=True):
     info = LevelInfo()
     _check(lib().airg_get_level(h.ptr, segment, level, C.byref(info), None))
-    d = {k: getattr(info, k) for k, _ in LevelInfo._fields_ if k != "alpha"}
+    d = {k: getattr(info, k) for k, _ in LevelInfo._fields_ if k not in ("alpha", "setup_seconds")}
     d["alpha"] = np.array(list(info.alpha)[:info.poly_requested])
+    d["setup_seconds"] = dict(zip(PHASES, list(info.setup_seconds)))
     if with_cf:
         cf = np.zeros(info.n, np.int8)
         _check(lib().airg_get_level(h.ptr, segment, level, C.byref(info), cf.ctypes.data_as(_VP)))

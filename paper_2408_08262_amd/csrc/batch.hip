@@ -373,6 +373,7 @@ void Batch::vcycle(int l, const float *g, float *e, hipStream_t s) {
 // stream; it holds only kernel nodes over the batch's own buffers.
 void Batch::run(hipStream_t s, bool use_graph) {
     if (!use_graph) {
+        ++cycles_eager;
         vcycle(0, g0.p, e0.p, s);
         return;
     }
@@ -390,6 +391,7 @@ void Batch::run(hipStream_t s, bool use_graph) {
         AIRG_HIP(hipStreamEndCapture(cap, &graph));
         AIRG_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
+    ++cycles_graph;
     AIRG_HIP(hipGraphLaunch(exec, s));
 }
 

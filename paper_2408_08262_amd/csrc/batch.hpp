@@ -33,6 +33,7 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;         // private stream the graph is captured on
     std::map<std::string, int> tuned;  // autotuner record: "rows:nnz:k" -> kernel choice
+    int64_t cycles_eager = 0, cycles_graph = 0;   // cycles run kernel by kernel / as graph replays
     ~Batch();
     void vcycle(int l, const float *g, float *e, hipStream_t s);
     void run(hipStream_t s, bool use_graph);   // e0 = V(g0)

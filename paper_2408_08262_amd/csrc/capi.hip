@@ -399,6 +399,10 @@ airg_status airg_get_stats(const airg_handle *h, airg_stats *st) {
             segmented_stats(*h->segh, st);
             st->setup_seconds = h->setup_seconds;
             st->device_bytes = (int64_t)dev_bytes_in_use();
+            if (h->batch) {
+                st->cycles_eager = h->batch->cycles_eager;
+                st->cycles_graph = h->batch->cycles_graph;
+            }
             return;
         }
         double n0 = 0, z0 = 0, gsum = 0, osum = 0, ssum = 0;
@@ -418,6 +422,11 @@ airg_status airg_get_stats(const airg_handle *h, airg_stats *st) {
             st->vcycle_bytes_fp32 += vcycle_bytes(H, 4);
             const Level &T = *H.lv[0];
             st->top_spmv_bytes_fp64 += spmv_bytes(T.n, T.n, T.A.nnz, 8, false);
+            st->vcycle_nnz += vcycle_nnz(H);
+            st->top_nnz += T.A.nnz;
+            st->cycles_eager += H.cycles_eager;
+            st->cycles_graph += H.cycles_graph;
+            for (auto &lp : H.lv) st->setup_bytes += lp->setup_bytes;
         }
         st->grid_complexity = gsum / n0;
         st->operator_complexity = osum / z0;
@@ -479,6 +488,20 @@ airg_status airg_vcycle(const airg_handle *h, int32_t segment, const double *d_g
     });
 }
 
+airg_status airg_vcycle_profile(const airg_handle *h, int32_t segment, int32_t precision, int32_t reps,
+                                double *h_level_seconds, int32_t max_levels, void *hip_stream) {
+    return guarded([&] {
+        AIRG_REQUIRE(h && h_level_seconds && reps > 0 && max_levels > 0, ST_INVALID_ARG, "bad argument");
+        AIRG_REQUIRE(!h->segh, ST_INVALID_ARG, "the batched form has no per-segment V-cycle");
+        AIRG_REQUIRE(precision == 32 || precision == 64, ST_INVALID_ARG, "precision must be 32 or 64");
+        Hier *H = pick(h, segment);
+        H->s = (hipStream_t)hip_stream;
+        std::vector<double> t((size_t)H->nlev());
+        profile_vcycle(*H, precision, reps, t.data());
+        for (int l = 0; l < H->nlev() && l < max_levels; ++l) h_level_seconds[l] = t[l];
+    });
+}
+
 airg_status airg_batch_vcycle(airg_handle *h, int32_t nrhs, const double *d_g, double *d_e, void *hip_stream) {
     return guarded([&] {
         AIRG_REQUIRE(h && d_g && d_e, ST_INVALID_ARG, "null argument");
@@ -516,6 +539,8 @@ airg_status airg_get_level(const airg_handle *h, int32_t segment, int32_t level,
         info->poly_terms = L.poly.used;
         info->poly_requested = L.poly.m;
         for (int k = 0; k < L.poly.m && k < 16; ++k) info->alpha[k] = L.poly.alpha[k];
+        for (int k = 0; k < AIRG_PHASE_COUNT; ++k) info->setup_seconds[k] = L.phase[k];
+        info->setup_bytes = L.setup_bytes;
         if (h_cf) {
             if (L.coarsest) std::memset(h_cf, CF_F, (size_t)L.n);
             else d2h(h_cf, L.cf.p, (size_t)L.n, H->s);

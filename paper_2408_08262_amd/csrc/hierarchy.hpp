@@ -42,6 +42,10 @@ struct Level {
     DBuf<int32_t> pcol;
     DBuf<double> pval64;
     DBuf<float> pval32;
+    // setup device time of this level by phase, and the bytes its setup steps
+    // must move (each step reading its inputs and writing its outputs once)
+    double phase[AIRG_PHASE_COUNT] = {};
+    int64_t setup_bytes = 0;
 };
 
 struct Hier {
@@ -64,6 +68,12 @@ struct Hier {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int eager[2] = {0, 0};
     hipStream_t cap = nullptr;
+    // V-cycles applied since setup: launched one kernel at a time, or as one
+    // replay of a captured graph
+    int64_t cycles_eager = 0, cycles_graph = 0;
+    // when set, vcycle records 4 events per level: around the restriction
+    // and around the work after the coarse correction (per-level profile)
+    hipEvent_t *prof = nullptr;
 
     Hier() = default;
     Hier(const Hier &) = delete;
@@ -79,19 +89,25 @@ struct Hier {
 };
 
 // Per-phase device time from events recorded around each phase on the setup
-// stream; span_on times work enqueued by another thread on another stream
-// (its phase then overlaps the others).
+// stream, tagged with the level being built (level is set by the driver
+// before each level; -1 = after the level loop); span_on times work enqueued
+// by another thread on another stream (its phase then overlaps the others).
 struct PhaseTimer {
     hipStream_t s;
     std::mutex mu;
-    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> spans;
+    struct Span {
+        int level, phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Span> spans;
     int cur = -1;
+    int level = -1;
     hipEvent_t start = nullptr;
     explicit PhaseTimer(hipStream_t st) : s(st) {}
     ~PhaseTimer() {
         for (auto &t : spans) {
-            release_event(std::get<1>(t));
-            release_event(std::get<2>(t));
+            release_event(t.a);
+            release_event(t.b);
         }
         release_event(start);
     }
@@ -106,38 +122,46 @@ struct PhaseTimer {
         hipEvent_t stop = pooled_event();
         AIRG_HIP(hipEventRecord(stop, s));
         std::lock_guard<std::mutex> lk(mu);
-        spans.emplace_back(cur, start, stop);
+        spans.push_back({level, cur, start, stop});
         start = nullptr;
         cur = -1;
     }
     template <class F>
-    void span_on(int phase, hipStream_t st, F &&f) {
+    void span_on(int phase, int lvl, hipStream_t st, F &&f) {
         hipEvent_t a = pooled_event(), b = pooled_event();
         {
             std::lock_guard<std::mutex> lk(mu);
-            spans.emplace_back(phase, a, b);
+            spans.push_back({lvl, phase, a, b});
         }
         AIRG_HIP(hipEventRecord(a, st));
         f();
         AIRG_HIP(hipEventRecord(b, st));
     }
-    void collect(double *out) {
+    // Phase totals into out[phase]; per_level(level, phase, seconds) for every
+    // span recorded inside the level loop.
+    template <class PerLevel>
+    void collect(double *out, PerLevel &&per_level) {
         end();
         AIRG_HIP(hipStreamSynchronize(s));
         for (auto &t : spans) {
-            AIRG_HIP(hipEventSynchronize(std::get<2>(t)));
+            AIRG_HIP(hipEventSynchronize(t.b));
             float ms = 0.f;
-            AIRG_HIP(hipEventElapsedTime(&ms, std::get<1>(t), std::get<2>(t)));
-            out[std::get<0>(t)] += ms * 1e-3;
+            AIRG_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+            out[t.phase] += ms * 1e-3;
+            if (t.level >= 0) per_level(t.level, t.phase, ms * 1e-3);
         }
+    }
+    void collect(double *out) {
+        collect(out, [](int, int, double) {});
     }
 };
 
 struct NullTimer {
+    int level = -1;
     void begin(int) {}
     void end() {}
     template <class F>
-    void span_on(int, hipStream_t, F &&f) {
+    void span_on(int, int, hipStream_t, F &&f) {
         f();
     }
 };
@@ -216,10 +240,18 @@ struct SolveResult {
 SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, int maxit);
 // One V-cycle e = V(g) in natural order (precision 64 or 32).
 void apply_vcycle(Hier &H, const double *g, double *e, int precision);
+// Device time of each level's own work in one eager V-cycle (the restriction
+// to the next level plus everything after the coarse correction; the whole
+// coarse solve on the coarsest level), averaged over reps cycles on a zero
+// input: out[l] for l < H.nlev().
+void profile_vcycle(Hier &H, int precision, int reps, double *out);
 SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit);
 
 // Algorithmic bytes of one V-cycle with vbytes-byte values.
 int64_t vcycle_bytes(const Hier &H, int vbytes);
+// Stored entries of every matrix one V-cycle applies (its work in units of
+// multiply-adds; divided by nnz(A_0), the cycle's work units).
+int64_t vcycle_nnz(const Hier &H);
 void complexities(const Hier &H, double *grid, double *op, double *storage);
 int64_t spmv_bytes(int64_t rows, int64_t cols, int64_t nnz, int vbytes, bool reads_y);
 

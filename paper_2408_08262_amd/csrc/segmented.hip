@@ -156,6 +156,7 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         SegLevel &L = *H->lv[l];
         const int32_t n = L.n;
         const int na = (int)L.seg.size();
+        tm.level = l;
         std::vector<int32_t> off(na + 1);
         std::vector<uint64_t> sd(na);
         std::vector<int8_t> term(na);
@@ -284,9 +285,11 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         }
         H->lv.push_back(std::move(next));
     }
+    tm.level = -1;
     tm.begin(AIRG_PHASE_FINALIZE);
     finalize_seg(*H, s);
-    tm.collect(H->phase);
+    SegHier &HH = *H;
+    tm.collect(H->phase, [&HH](int l, int ph, double sec) { HH.lv[l]->phase[ph] += sec; });
     H->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return H;
 }
@@ -327,12 +330,15 @@ void segmented_stats(const SegHier &H, airg_stats *st) {
     const SegLevel &T = *H.lv[0];
     const double n0 = T.n, z0 = (double)T.A.nnz;
     double g = 0, o = 0, sc = 0;
-    int64_t b64 = 0, b32 = 0;
+    int64_t b64 = 0, b32 = 0, znz = 0;
     const int vc = H.opt.coarse_iters;
     for (auto &lp : H.lv) {
         const SegLevel &L = *lp;
         g += L.n;
         o += (double)L.A.nnz;
+        if (L.nF + L.nC > 0)
+            znz += L.Rp.nnz + L.Pp.nnz + (int64_t)H.opt.up_smooths * (L.AF.nnz + L.Ainv.nnz);
+        if (L.nT > 0) znz += L.AinvT.nnz + (int64_t)(vc - 1) * (L.AT.nnz + L.AinvT.nnz);
         if (L.nF + L.nC > 0) {
             sc += (double)L.Ainv.nnz + (double)L.Aff.nnz + (double)L.Afc.nnz + (double)(L.Z.nnz + L.nC) +
                   (double)(L.W.nnz + L.nC);
@@ -362,6 +368,8 @@ void segmented_stats(const SegHier &H, airg_stats *st) {
     st->vcycle_bytes_fp64 = b64;
     st->vcycle_bytes_fp32 = b32;
     st->top_spmv_bytes_fp64 = spmv_bytes(T.n, T.n, T.A.nnz, 8, false);
+    st->vcycle_nnz = znz;
+    st->top_nnz = T.A.nnz;
 }
 
 void segmented_level_info(const SegHier &H, int32_t segment, int32_t level, airg_level_info *info, int8_t *h_cf,
@@ -387,6 +395,7 @@ void segmented_level_info(const SegHier &H, int32_t segment, int32_t level, airg
     info->poly_terms = e.poly.used;
     info->poly_requested = e.poly.m;
     for (int k = 0; k < e.poly.m && k < 16; ++k) info->alpha[k] = e.poly.alpha[k];
+    for (int k = 0; k < AIRG_PHASE_COUNT; ++k) info->setup_seconds[k] = L.phase[k];
     if (h_cf) {
         if (e.terminal) std::memset(h_cf, CF_F, (size_t)e.n);
         else d2h(h_cf, L.cf.p + e.off, (size_t)e.n, s);

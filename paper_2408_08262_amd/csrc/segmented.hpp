@@ -34,6 +34,7 @@ struct SegLevel {
     std::vector<SegEntry> seg;
     DBuf<int32_t> perm, iperm;           // natural <-> level order [F | C | T]
     Csr AF, Rp, Pp;                      // solve operators of the active part (level order)
+    double phase[AIRG_PHASE_COUNT] = {};  // setup device time of the level (all segments) by phase
 };
 
 struct SegHier {

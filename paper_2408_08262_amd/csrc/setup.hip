@@ -208,6 +208,22 @@ Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, int order, hipS
 
 namespace {
 
+// FP64 CSR bytes of a matrix (row pointers, columns, values).
+int64_t csr_bytes(const CsrView &M) { return M.nnz * 12 + ((int64_t)M.nr + 1) * 4; }
+// The polynomial's coefficients on an n_F-row block: m products with A_ff
+// (each reading A_ff and x, writing y) and one TSQR pass over the m + 1
+// basis columns.
+int64_t poly_bytes(const CsrView &Aff, int m) {
+    return (int64_t)m * (csr_bytes(Aff) + 16 * (int64_t)Aff.nr) + (int64_t)Aff.nr * (m + 1) * 8;
+}
+// The splitting of an n-row level: strength (A in, one flag per entry out),
+// PMISR (the strong pattern in, states out), DDC (A and states in, states
+// out) and the rank scans.
+int64_t split_bytes(const CsrView &A) {
+    const int64_t n = A.nr;
+    return csr_bytes(A) + A.nnz + (A.nnz * 5 + (n + 1) * 4 + n) + (csr_bytes(A) + 2 * n) + 5 * n;
+}
+
 // Steps 2 and 7-11 of the recipe once the splitting is known.  The
 // prolongator and A P depend on the splitting only: with a Branch they are
 // built by its thread on its stream while this thread builds the F-block
@@ -218,12 +234,13 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
                     DBuf<int32_t> &cidx, Csr &Aff, Csr *Afc, PolyInfo &poly, Csr &Ainv, Csr &Z, Csr &W, Csr &Ac,
                     Timer &tm, hipStream_t s, Branch *br = nullptr,
                     const std::function<void(hipStream_t)> &pre = nullptr, ExtractPlan *xp = nullptr,
-                    const int32_t *xtot = nullptr) {
+                    const int32_t *xtot = nullptr, int64_t *cbytes = nullptr) {
     int32_t n = A.nr;
     int m = o.poly_order + 1;
     Csr P, AP;
+    int64_t nb = 0;   // the level's setup bytes: every step reads its inputs and writes its outputs once
     auto prolong = [&](hipStream_t st) {
-        tm.span_on(AIRG_PHASE_PROLONG, st, [&] {
+        tm.span_on(AIRG_PHASE_PROLONG, lvl, st, [&] {
             onepoint_prolongator(A, cf, rank, nF, nC, o.onepoint_weight, &P, &W, st);
             AP = spgemm(A, view(P), st);
         });
@@ -248,6 +265,7 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
         cf_index_lists(cf, rank, n, fidx.p, cidx.p, s);
         extract_fc_blocks(A, cf, rank, nF, nC, Aff, fc, Acf, s);
     }
+    nb += csr_bytes(A) + 5 * (int64_t)n + csr_bytes(view(Aff)) + csr_bytes(view(fc)) + csr_bytes(view(Acf));
     if (Afc) *Afc = std::move(fc);
     tm.begin(AIRG_PHASE_POLY);
     // With the first-order pattern, the row bins of the fixed-sparsity
@@ -293,6 +311,11 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
                            : spgemm(view(Acf), view(Ainv), s);
         // Z = -A_cf Ainv, dropped; its entry count is read with R A P's plan
         Z = drop_rows_bound(view(prod), o.drop_R, false, true, s);
+        // power basis (m products with A_ff), TSQR of the basis, assembly of
+        // Ainv; Z's product and its drop (Z's size is bounded by the product's
+        // until read below)
+        nb += poly_bytes(view(Aff), m) + csr_bytes(view(Aff)) + csr_bytes(view(Ainv));
+        nb += csr_bytes(view(Acf)) + csr_bytes(view(Ainv)) + 2 * csr_bytes(view(prod));
     }
     if (br) {
         tm.end();
@@ -315,8 +338,15 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
         Csr RAP = spgemm_finish(view(R), view(AP), plan, h.data() + 1, s);
         // with a Branch the entry count is read by the next level's splitting
         Ac = br ? drop_rows_bound(view(RAP), o.drop_A, true, false, s) : drop_rows(view(RAP), o.drop_A, true, false, s);
+        // W and P from A; A P; R from Z; R (A P); the drop of R A P (A_c's
+        // dropped count is counted as the product's, an upper bound)
+        nb += csr_bytes(A) + 5 * (int64_t)n + csr_bytes(view(W)) + csr_bytes(view(P));
+        nb += csr_bytes(A) + csr_bytes(view(P)) + csr_bytes(view(AP));
+        nb += csr_bytes(view(Z)) + csr_bytes(view(R));
+        nb += csr_bytes(view(R)) + csr_bytes(view(AP)) + 3 * csr_bytes(view(RAP));
     }
     tm.end();
+    if (cbytes) *cbytes += nb;
 }
 
 }  // namespace
@@ -647,6 +677,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
     for (int l = 0;; ++l) {
         Level &L = H->L(l);
         int32_t n = L.n;
+        tm.level = l;
         bool coarsest = (o.truncate_n > 0 && n <= o.truncate_n) || l == maxl - 1;
         // below the top, A's entry count is an upper bound until read: with
         // the splitting's counts, or on its own for a coarsest level
@@ -660,6 +691,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             if (bound) L.A.nnz = nz;
             L.nF = nF;
             L.nC = nC;
+            L.setup_bytes += split_bytes(view(L.A));
             tm.end();
             if (nF == 0 || nC < o.poly_order) coarsest = true;
         } else if (bound) {
@@ -676,7 +708,11 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             L.nC = 0;
             int m = o.coarse_poly_order + 1;
             L.poly = gmres_poly(view(L.A), seed, l, m, s);
-            if (!o.coarse_matrix_free) L.Ainv = assemble_inverse(view(L.A), L.poly, m, o.poly_sparsity_order, s);
+            L.setup_bytes += poly_bytes(view(L.A), m);
+            if (!o.coarse_matrix_free) {
+                L.Ainv = assemble_inverse(view(L.A), L.poly, m, o.poly_sparsity_order, s);
+                L.setup_bytes += csr_bytes(view(L.A)) + csr_bytes(view(L.Ainv));
+            }
             tm.end();
             break;
         }
@@ -689,13 +725,15 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             if (l > 0) solve_ops(HH, l - 1, st);
         };
         complete_level(view(L.A), o, seed, l, nullptr, L.cf.p, L.rank.p, L.nF, L.nC, L.fidx, L.cidx, L.Aff, &L.Afc,
-                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br, pre, &xplan, xtot);
+                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br, pre, &xplan, xtot, &L.setup_bytes);
         next->n = next->A.nr;
         H->lv.push_back(std::move(next));
     }
+    tm.level = -1;
     tm.begin(AIRG_PHASE_FINALIZE);
     finalize(*H, std::max(0, H->nlev() - 2));
-    tm.collect(H->phase);
+    Hier &HH = *H;
+    tm.collect(H->phase, [&HH](int l, int ph, double sec) { HH.L(l).phase[ph] += sec; });
     H->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return H;
 }
@@ -781,6 +819,23 @@ int64_t vcycle_bytes(const Hier &H, int vb) {
              (spmv_bytes(L.AF.nr, L.AF.nc, L.AF.nnz, vb, true) + spmv_bytes(L.Ainv.nr, L.Ainv.nc, L.Ainv.nnz, vb, true));
     }
     return b;
+}
+
+int64_t vcycle_nnz(const Hier &H) {
+    int64_t z = 0;
+    for (int l = 0; l < (int)H.lv.size(); ++l) {
+        const Level &L = *H.lv[l];
+        if (L.coarsest) {
+            int vc = H.opt.coarse_iters;
+            if (H.opt.coarse_matrix_free)
+                z += (int64_t)vc * (L.poly.m - 1) * L.A.nnz + (int64_t)(vc - 1) * L.A.nnz;
+            else
+                z += L.Ainv.nnz + (int64_t)(vc - 1) * (L.A.nnz + L.Ainv.nnz);
+            continue;
+        }
+        z += L.Rp.nnz + L.Pp.nnz + (int64_t)H.opt.up_smooths * (L.AF.nnz + L.Ainv.nnz);
+    }
+    return z;
 }
 
 void complexities(const Hier &H, double *grid, double *op, double *storage) {

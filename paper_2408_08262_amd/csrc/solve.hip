@@ -133,19 +133,29 @@ template <class T>
 void Hier::vcycle(int l, const T *g, T *e) {
     Level &Lv = L(l);
     T *t = Bufs<T>::t(Lv);
+    auto mark = [&](int k) {
+        if (prof) AIRG_HIP(hipEventRecord(prof[4 * l + k], s));
+    };
     if (Lv.coarsest) {
+        mark(0);
         coarse_apply<T>(*this, Lv, g, e, SPMV_SET);
         for (int it = 1; it < opt.coarse_iters; ++it) {
             spmvT(Lv.A, e, t, g, SPMV_ZMINUS, s);
             coarse_apply<T>(*this, Lv, t, e, SPMV_ADD);
         }
+        mark(1);
+        mark(2);
+        mark(3);
         return;
     }
     Level &N = L(l + 1);
     T *gc = Bufs<T>::g(N);
     T *ec = Bufs<T>::e(N);
+    mark(0);
     spmvT(Lv.Rp, g, gc, (const T *)nullptr, SPMV_SET, s);
+    mark(1);
     vcycle<T>(l + 1, gc, ec);
+    mark(2);
     int k0 = 0;
     if (Lv.pcol.p && opt.up_smooths > 0) {
         prolong_resid<T>(Lv, ec, g, e, t, s);
@@ -158,6 +168,7 @@ void Hier::vcycle(int l, const T *g, T *e) {
         spmvT(Lv.AF, e, t, g, SPMV_ZMINUS, s);
         spmvT(Lv.Ainv, t, e, (const T *)nullptr, SPMV_ADD, s);
     }
+    mark(3);
 }
 
 template void Hier::vcycle<double>(int, const double *, double *);
@@ -187,6 +198,7 @@ void run_captured(Hier &H, int k, F &&f) {
     if (!H.gexec[k]) {
         if (H.eager[k] < Hier::kEagerCycles) {
             ++H.eager[k];
+            ++H.cycles_eager;
             f();
             return;
         }
@@ -207,6 +219,7 @@ void run_captured(Hier &H, int k, F &&f) {
         AIRG_HIP(hipStreamEndCapture(H.cap, &H.graph[k]));
         AIRG_HIP(hipGraphInstantiate(&H.gexec[k], H.graph[k], nullptr, nullptr, 0));
     }
+    ++H.cycles_graph;
     AIRG_HIP(hipGraphLaunch(H.gexec[k], H.s));
 }
 }  // namespace
@@ -224,16 +237,24 @@ void Hier::precondition(const double *rv, double *ev, int precision) {
     if (precision == 32) {
         if (ip) gather_d2f(rv, ip, r32.p, n0, s);
         else cast_d2f(rv, r32.p, n0, s);
-        if (graphed) run_captured(*this, 1, [&] { vcycle<float>(0, r32.p, e32.p); });
-        else vcycle<float>(0, r32.p, e32.p);
+        if (graphed) {
+            run_captured(*this, 1, [&] { vcycle<float>(0, r32.p, e32.p); });
+        } else {
+            ++cycles_eager;
+            vcycle<float>(0, r32.p, e32.p);
+        }
         if (ip) scatter_f2d(e32.p, ip, ev, n0, s);
         else cast_f2d(e32.p, ev, n0, s);
         return;
     }
     if (ip) gather(rv, ip, T.g64.p, n0, s);
     else d2d(T.g64.p, rv, (size_t)n0, s);
-    if (graphed) run_captured(*this, 0, [&] { vcycle<double>(0, T.g64.p, T.e64.p); });
-    else vcycle<double>(0, T.g64.p, T.e64.p);
+    if (graphed) {
+        run_captured(*this, 0, [&] { vcycle<double>(0, T.g64.p, T.e64.p); });
+    } else {
+        ++cycles_eager;
+        vcycle<double>(0, T.g64.p, T.e64.p);
+    }
     if (ip) scatter(T.e64.p, ip, ev, n0, s);
     else d2d(ev, T.e64.p, (size_t)n0, s);
 }
@@ -244,6 +265,36 @@ void copy_vec(Hier &H, const double *src, double *dst) { d2d(dst, src, (size_t)H
 }  // namespace
 
 void apply_vcycle(Hier &H, const double *g, double *e, int precision) { H.precondition(g, e, precision); }
+
+void profile_vcycle(Hier &H, int precision, int reps, double *out) {
+    const int nl = H.nlev();
+    for (int l = 0; l < nl; ++l) out[l] = 0.0;
+    Level &T = H.L(0);
+    if (precision == 32) fill_zero(T.g32.p, (size_t)T.n * 4, H.s);
+    else fill_zero(T.g64.p, (size_t)T.n * 8, H.s);
+    std::vector<hipEvent_t> ev((size_t)4 * nl);
+    for (auto &e : ev) e = pooled_event();
+    try {
+        for (int r = 0; r < reps; ++r) {
+            H.prof = ev.data();
+            if (precision == 32) H.vcycle<float>(0, T.g32.p, T.e32.p);
+            else H.vcycle<double>(0, T.g64.p, T.e64.p);
+            H.prof = nullptr;
+            AIRG_HIP(hipStreamSynchronize(H.s));
+            for (int l = 0; l < nl; ++l) {
+                float a = 0.f, b = 0.f;
+                AIRG_HIP(hipEventElapsedTime(&a, ev[4 * l], ev[4 * l + 1]));
+                AIRG_HIP(hipEventElapsedTime(&b, ev[4 * l + 2], ev[4 * l + 3]));
+                out[l] += (a + b) * 1e-3 / reps;
+            }
+        }
+    } catch (...) {
+        H.prof = nullptr;
+        for (auto &e : ev) release_event(e);
+        throw;
+    }
+    for (auto &e : ev) release_event(e);
+}
 
 // Undamped Richardson from a zero guess: x += V(b - A x) until
 // ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual every iteration).
