@@ -66,6 +66,9 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison forms")
     p.add_argument("--levels", action="store_true",
                    help="only print per-level setup (by phase) and V-cycle times of the workload")
+    p.add_argument("--ladder", action="store_true",
+                   help="only run the work-growth ladder: dg_square at 64^2..512^2 and p0_cube at 32^3..128^3, "
+                        "untruncated, both timed forms")
     p.add_argument("--sweep-poly", action="store_true",
                    help="only sweep polynomial order x sparsity order (setup + FP32-FGMRES solve per pair)")
     p.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
@@ -283,14 +286,14 @@ def forms(airg):
     }
 
 
-def time_form(airg, torch, A, b, opts, steps, warmup, rtol, workload=None, seg=None):
+def time_form(airg, torch, A, b, opts, steps, warmup, rtol, workload=None, seg=None, allow_not_converged=False):
     """warmup untimed and `steps` timed passes of setup + solve on fresh handles; the
     finest-operator product is event-timed over the timed passes when workload is given."""
     segkw = {} if seg is None else {"seg_offsets": seg[0], "seg_seeds": seg[1]}
 
     def step():
         h = airg.airg_setup(*A, opts, **segkw)
-        x, info = airg.airg_solve(h, b, rtol=rtol, max_it=300)
+        x, info = airg.airg_solve(h, b, rtol=rtol, max_it=300, allow_not_converged=allow_not_converged)
         st = airg.airg_get_stats(h)
         del h
         return x, info, st
@@ -567,8 +570,48 @@ def batched_subrecord(a, airg, torch):
     return out
 
 
+def levels_report_batch(a, airg, torch):
+    """Per-level setup time by phase (all segments together) and per-level batched FP32 cycle time."""
+    from workloads import batch as batch_problems, concat
+    probs = batch_problems()
+    rp, ci, val, bb, offs, seeds = concat(probs)
+    A = airg.to_device(rp, ci, val)
+    B = torch.as_tensor(bb, device="cuda")
+    opts = airg.default_opts(outer=airg.OUTER_FGMRES, precond_precision=32, use_graph=1, autotune=1)
+    for _ in range(2):
+        h = airg.airg_setup(*A, opts, seg_offsets=offs, seg_seeds=seeds)
+        del h
+    h = airg.airg_setup(*A, opts, seg_offsets=offs, seg_seeds=seeds)
+    airg.airg_solve(h, B, rtol=a.rtol, max_it=300)
+    st = airg.airg_get_stats(h)
+    t32 = airg.airg_batch_vcycle_profile(h, nrhs=bb.shape[1], reps=20)
+    rows = []
+    for l in range(st["levels"]):
+        lv, n, nnz, segs = None, 0, 0, 0
+        for p in range(len(probs)):
+            try:
+                x = airg.airg_get_level(h, l, segment=p, with_cf=False)
+            except airg.AirgError:
+                continue
+            lv = x
+            n += x["n"]
+            nnz += x["nnz_a"]
+            segs += 1
+        rows.append({"level": l, "n": n, "nnz_a": nnz, "segments": segs, "coarsest": False,
+                     "setup_ms": {k: round(v * 1e3, 4) for k, v in lv["setup_seconds"].items()},
+                     "setup_bytes": lv["setup_bytes"], "vcycle_us_fp32": round(t32[l] * 1e6, 2),
+                     "vcycle_us_fp64": 0.0})
+    print(json.dumps({"levels_report": "batch48: 48 DG-P1 upwind problems x 4 rhs, batched FP32 cycle, "
+                                       "n=%d, nnz=%d" % (int(offs[-1]), int(rp[-1])),
+                      "setup_s": st["setup_seconds"], "phase_seconds": st["phase_seconds"], "rows": rows}),
+          flush=True)
+    return 0
+
+
 def levels_report(a, airg, torch):
     """Per-level setup time by phase and per-level V-cycle time (FP32 and FP64) of one workload."""
+    if a.workload == "batch48":
+        return levels_report_batch(a, airg, torch)
     P, desc, bs = make_problem(a.workload, a.size)
     trunc, citers = truncation(a)
     A = airg.to_device(P.rowptr, P.col, P.val)
@@ -591,6 +634,32 @@ def levels_report(a, airg, torch):
     print(json.dumps({"levels_report": desc + ", truncate_n=%d, coarse_iters=%d" % (trunc, citers),
                       "setup_s": st["setup_seconds"], "phase_seconds": st["phase_seconds"], "rows": rows}),
           flush=True)
+    return 0
+
+
+def ladder(a, airg, torch):
+    """Iterations, work units and grind time of both timed forms as the problem grows (flat
+    iterations and WUs = work linear in n), untruncated hierarchies with the default options."""
+    F = forms(airg)
+    for name, sizes in (("dg_square_512", (64, 128, 256, 512)), ("p0_cube_128", (32, 64, 128))):
+        for N in sizes:
+            P, desc, bs = make_problem(name, N)
+            A = airg.to_device(P.rowptr, P.col, P.val)
+            b = torch.as_tensor(P.b, device="cuda")
+            row = {"ladder": desc, "n": P.n, "nnz": P.nnz}
+            for k in ("fp32_fgmres", "fp64_richardson"):
+                # undamped Richardson may diverge (a level polynomial with an outlier eigenvalue): recorded
+                r = time_form(airg, torch, A, b, airg.default_opts(seed=P.seed, use_graph=1, **F[k][0]),
+                              a.sub_steps, 1, a.rtol, allow_not_converged=True)
+                rec = form_record(k, F[k][1], r, P.n)
+                row[k] = {kk: rec[kk] for kk in ("seconds_per_step", "setup_s", "solve_s", "iterations", "levels",
+                                                 "wu_per_cycle", "wus", "grind_ns_per_unknown_per_cycle")}
+                row[k]["converged"] = bool(r["info"]["converged"])
+                row[k]["complexity"] = [round(r["st"]["grid_complexity"], 3), round(r["st"]["operator_complexity"], 3)]
+                del r
+            print(json.dumps(row), flush=True)
+            del A, b, P
+            torch.cuda.empty_cache()
     return 0
 
 
@@ -679,6 +748,8 @@ def main():
         return sweep_poly(a, airg, torch)
     if a.levels:
         return levels_report(a, airg, torch)
+    if a.ladder:
+        return ladder(a, airg, torch)
     sub = {}
     if a.workload == "batch48":
         rec = batched_subrecord(a, airg, torch)

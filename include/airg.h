@@ -231,6 +231,12 @@ airg_status airg_batch_vcycle(airg_handle *h, int32_t nrhs, const double *d_g, d
  * hip_stream. */
 airg_status airg_vcycle_profile(const airg_handle *h, int32_t segment, int32_t precision, int32_t reps,
                                 double *h_level_seconds, int32_t max_levels, void *hip_stream);
+/* The same for the batched FP32 cycle of a batched-form handle with nrhs
+ * right-hand sides (1, 2, 4 or 8): level l's own stages over every segment
+ * (restriction, prolongation, smoothing and the coarse solves of segments
+ * whose hierarchy ends on that level), eager, mean of reps cycles. */
+airg_status airg_batch_vcycle_profile(airg_handle *h, int32_t nrhs, int32_t reps, double *h_level_seconds,
+                                      int32_t max_levels, void *hip_stream);
 
 /* Describes one level of one segment; h_cf (nullable, n entries) receives
  * the CF markers (1 = F, 2 = C; all 1 on the coarsest level).  segment >= 0

@@ -75,6 +75,7 @@ _SIGS = {
     "airg_vcycle": [_VP, _I32, _VP, _VP, _I32, _VP],
     "airg_batch_vcycle": [_VP, _I32, _VP, _VP, _VP],
     "airg_vcycle_profile": [_VP, _I32, _I32, _I32, _VP, _I32, _VP],
+    "airg_batch_vcycle_profile": [_VP, _I32, _I32, _VP, _I32, _VP],
     "airg_get_level": [_VP, _I32, _I32, C.POINTER(LevelInfo), _VP],
     "airg_get_level_matrix": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
     "airg_csr_info": [_VP, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)],
@@ -286,6 +287,14 @@ def airg_vcycle_profile(h, precision=32, reps=10, segment=0, stream=None):
     nl = airg_get_stats(h)["levels"]
     out = (C.c_double * max(nl, 1))()
     _check(lib().airg_vcycle_profile(h.ptr, segment, precision, reps, out, nl, _stream(stream)))
+    return list(out)[:nl]
+
+
+def airg_batch_vcycle_profile(h, nrhs=4, reps=10, stream=None):
+    """Mean device seconds per batched FP32 cycle of each level's own stages."""
+    nl = airg_get_stats(h)["levels"]
+    out = (C.c_double * max(nl, 1))()
+    _check(lib().airg_batch_vcycle_profile(h.ptr, nrhs, reps, out, nl, _stream(stream)))
     return list(out)[:nl]
 
 

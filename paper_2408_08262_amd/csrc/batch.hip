@@ -348,10 +348,16 @@ void finish_batch(Batch &Bt, bool tune, hipStream_t s) {
 void Batch::vcycle(int l, const float *g, float *e, hipStream_t s) {
     BatchLevel &BL = *lv[l];
     float *t = BL.t.p;
+    auto mark = [&](int q) {
+        if (prof) AIRG_HIP(hipEventRecord(prof[4 * l + q], s));
+    };
+    mark(0);
     if (BL.nF + BL.nC > 0) {
         BatchLevel &NX = *lv[l + 1];
         spmm32(view(BL.Rp), k, g, NX.g.p, nullptr, SPMV_SET, s, BL.lRp);
+        mark(1);
         vcycle(l + 1, NX.g.p, NX.e.p, s);
+        mark(2);
         spmm32(view(BL.Pp), k, NX.e.p, e, nullptr, SPMV_SET, s, BL.lPp);
         for (int q = 0; q < up_smooths; ++q) {
             spmm32(view(BL.AF), k, e, t, g, SPMV_ZMINUS, s, BL.lAF);
@@ -366,6 +372,38 @@ void Batch::vcycle(int l, const float *g, float *e, hipStream_t s) {
             spmm32(view(BL.AinvT), k, t + o, e + o, nullptr, SPMV_ADD, s, BL.lAinvT);
         }
     }
+    if (BL.nF + BL.nC == 0) {
+        mark(1);
+        mark(2);
+    }
+    mark(3);
+}
+
+void batch_profile(Batch &B, int reps, double *out, hipStream_t s) {
+    const int nl = (int)B.lv.size();
+    for (int l = 0; l < nl; ++l) out[l] = 0.0;
+    std::vector<hipEvent_t> ev((size_t)4 * nl);
+    for (auto &e : ev) e = pooled_event();
+    try {
+        fill_zero(B.g0.p, B.g0.bytes(), s);
+        for (int r = 0; r < reps; ++r) {
+            B.prof = ev.data();
+            B.vcycle(0, B.g0.p, B.e0.p, s);
+            B.prof = nullptr;
+            AIRG_HIP(hipStreamSynchronize(s));
+            for (int l = 0; l < nl; ++l) {
+                float a = 0.f, b = 0.f;
+                AIRG_HIP(hipEventElapsedTime(&a, ev[4 * l], ev[4 * l + 1]));
+                AIRG_HIP(hipEventElapsedTime(&b, ev[4 * l + 2], ev[4 * l + 3]));
+                out[l] += (a + b) * 1e-3 / reps;
+            }
+        }
+    } catch (...) {
+        B.prof = nullptr;
+        for (auto &e : ev) release_event(e);
+        throw;
+    }
+    for (auto &e : ev) release_event(e);
 }
 
 // The graph is captured once on a private non-blocking stream (the legacy

@@ -34,6 +34,7 @@ struct Batch {
     hipStream_t cap = nullptr;         // private stream the graph is captured on
     std::map<std::string, int> tuned;  // autotuner record: "rows:nnz:k" -> kernel choice
     int64_t cycles_eager = 0, cycles_graph = 0;   // cycles run kernel by kernel / as graph replays
+    hipEvent_t *prof = nullptr;                   // per-level profile events (4 per level) when set
     ~Batch();
     void vcycle(int l, const float *g, float *e, hipStream_t s);
     void run(hipStream_t s, bool use_graph);   // e0 = V(g0)
@@ -60,5 +61,10 @@ BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg,
 // One batched FP32 V-cycle on FP64 vectors in natural row order (n x k
 // row-major): e = V(g), the cast into and out of the cycle included.
 void batch_apply(Batch &B, const double *g, double *e, bool use_graph, hipStream_t s);
+
+// Mean device seconds per eager batched cycle of each level's own work (the
+// restriction, then the prolongation, smoothing and terminal coarse solves),
+// over reps cycles on a zero input: out[l] for l < B.lv.size().
+void batch_profile(Batch &B, int reps, double *out, hipStream_t s);
 
 }  // namespace airg

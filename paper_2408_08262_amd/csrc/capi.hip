@@ -502,6 +502,20 @@ airg_status airg_vcycle_profile(const airg_handle *h, int32_t segment, int32_t p
     });
 }
 
+airg_status airg_batch_vcycle_profile(airg_handle *h, int32_t nrhs, int32_t reps, double *h_level_seconds,
+                                      int32_t max_levels, void *hip_stream) {
+    return guarded([&] {
+        AIRG_REQUIRE(h && h_level_seconds && reps > 0 && max_levels > 0, ST_INVALID_ARG, "bad argument");
+        AIRG_REQUIRE(batched_form(h), ST_INVALID_ARG, "the handle is not in the batched form");
+        hipStream_t s = (hipStream_t)hip_stream;
+        ensure_batch(h, nrhs, s);
+        Batch &B = *h->batch;
+        std::vector<double> t(B.lv.size());
+        batch_profile(B, reps, t.data(), s);
+        for (size_t l = 0; l < t.size() && (int)l < max_levels; ++l) h_level_seconds[l] = t[l];
+    });
+}
+
 airg_status airg_batch_vcycle(airg_handle *h, int32_t nrhs, const double *d_g, double *d_e, void *hip_stream) {
     return guarded([&] {
         AIRG_REQUIRE(h && d_g && d_e, ST_INVALID_ARG, "null argument");

@@ -791,6 +791,18 @@ void extract_finish(const CsrView &A, const int8_t *cf, const int32_t *rank, int
     AIRG_LAUNCH_CHECK();
 }
 
+void extract_refill(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC,
+                    const ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s) {
+    AIRG_REQUIRE(P.n == A.nr && Aff.nr == nF && Acf.nr == nC, ST_INVALID_ARG, "extraction plan does not match");
+    if (A.nr == 0) return;
+    dispatch_group(lanes_for(A.nnz, A.nr), [&]<int G>() {
+        k_extract3_fill<G><<<grid_for((int64_t)A.nr * G, 256), 256, 0, s>>>(
+            A.nr, A.rp, A.ci, A.v, cf, rank, P.off.p, nF, nC, Aff.rp.p, Aff.ci.p, Aff.v.p, Afc.rp.p, Afc.ci.p,
+            Afc.v.p, Acf.rp.p, Acf.ci.p, Acf.v.p, nullptr, nullptr);
+    });
+    AIRG_LAUNCH_CHECK();
+}
+
 void extract_fc_blocks(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC, Csr &Aff,
                        Csr &Afc, Csr &Acf, hipStream_t s) {
     ExtractPlan P = extract_begin(A, cf, s);

@@ -77,6 +77,10 @@ ExtractPlan extract_begin(const CsrView &A, const int8_t *cf, hipStream_t s);
 void extract_finish(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC,
                     const int32_t *tot, ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s,
                     int32_t *fidx = nullptr, int32_t *cidx = nullptr);
+// The values of the three blocks again, into blocks extracted earlier with
+// the same plan and splitting (A's values changed, its pattern did not).
+void extract_refill(const CsrView &A, const int8_t *cf, const int32_t *rank, int32_t nF, int32_t nC,
+                    const ExtractPlan &P, Csr &Aff, Csr &Afc, Csr &Acf, hipStream_t s);
 
 // Keep entries with |x| >= tau * max_j |x_rj| (and the diagonal when
 // keep_diag); negate scales every kept value by -1 when set.

@@ -12,6 +12,7 @@
 
 #include "airg.h"
 #include "common.hpp"
+#include "csr.hpp"
 #include "poly.hpp"
 
 namespace airg {
@@ -46,6 +47,13 @@ struct Level {
     // must move (each step reading its inputs and writing its outputs once)
     double phase[AIRG_PHASE_COUNT] = {};
     int64_t setup_bytes = 0;
+    // kept from setup for numeric re-setup: the extraction plan, A_cf, the
+    // prolongator [W; I] (natural order) and the pattern of A P; the row bins
+    // of the re-setup's assembly and products, made by the first re-setup
+    ExtractPlan xplan;
+    Csr Acf, P, APp;
+    bool rbins = false;
+    Bins rb_ainv, rb_z, rb_ap, rb_rap;
 };
 
 struct Hier {

@@ -473,8 +473,18 @@ std::vector<PolyInfo> gmres_poly_seg(const CsrView &A, const std::vector<int32_t
 
 // --------------------------------------------- fixed-sparsity assembly ----
 // One G-lane group per row (L = row length <= G).  M_i = A(J_i, J_i) is built
-// in LDS by merging each gathered row with J_i; then v_k = v_{k-1} M_i with
-// lane a owning column a, the sum over p ascending (v_{k-1} read from LDS).
+// in LDS: the positions of J_i go into a small LDS hash (column -> position),
+// and each lane looks up the columns of its gathered row there (independent
+// lookups, four loads in flight); then v_k = v_{k-1} M_i with lane a owning
+// column a, the sum over p ascending.  The terms of that sum are broadcast
+// from the lanes that own them (a lane read for a whole-wavefront group,
+// through LDS otherwise) and their loads are issued eight at a time ahead of
+// the additions, which stay in ascending p.
+template <int G>
+__device__ inline uint32_t poly_hash(int32_t c) {
+    return ((uint32_t)c * 2654435761u) & (2 * G - 1);
+}
+
 template <int G, int TPB>
 __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ list, int64_t count,
                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -486,7 +496,8 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     constexpr int NG = TPB / G;
     __shared__ double Ms[NG][G * G];
     __shared__ double Xs[NG][G];
-    __shared__ int32_t Js[NG][G];
+    __shared__ int32_t Hk[NG][2 * G];
+    __shared__ int32_t Hp[NG][2 * G];
     int gid = threadIdx.x / G;
     int lane = group_lane<G>();
     int64_t idx = (int64_t)blockIdx.x * NG + gid;
@@ -496,45 +507,86 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     int32_t L = prp[row + 1] - b;
     double *M = Ms[gid];
     double *X = Xs[gid];
-    int32_t *J = Js[gid];
-    if (lane < L) J[lane] = pci[b + lane];
+    int32_t *hk = Hk[gid];
+    int32_t *hp = Hp[gid];
+    const int32_t myc = lane < L ? pci[b + lane] : -1;
+    for (int t = lane; t < 2 * G; t += G) hk[t] = -1;
     for (int t = lane; t < G * G; t += G) M[t] = 0.0;
     wave_sync();
+    if (lane < L) {   // columns are distinct: each claims its own slot
+        uint32_t h = poly_hash<G>(myc);
+        while (atomicCAS(&hk[h], -1, myc) != -1) h = (h + 1) & (2 * G - 1);
+        hp[h] = lane;
+    }
+    wave_sync();
     if (lane < L) {
-        // row J[lane] of A merged with J, its entries loaded four at a time
-        // (the loads of a batch in flight together); past the row end the
-        // column INT_MAX moves q to L
-        const int32_t r = J[lane];
+        // row J[lane] of A against J_i, its entries loaded four at a time
+        const int32_t r = myc;
         const int32_t ke = rp[r + 1];
-        int q = 0;
-        for (int32_t kk = rp[r]; kk < ke && q < L; kk += 4) {
+        for (int32_t kk = rp[r]; kk < ke; kk += 4) {
             int32_t c4[4];
             double v4[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const bool ok = kk + u < ke;
-                c4[u] = ok ? ci[kk + u] : 0x7fffffff;
+                c4[u] = ok ? ci[kk + u] : -1;
                 v4[u] = ok ? v[kk + u] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                while (q < L && J[q] < c4[u]) ++q;
-                if (q < L && J[q] == c4[u]) M[lane * G + q] = v4[u];
+                if (c4[u] < 0) continue;
+                uint32_t h = poly_hash<G>(c4[u]);
+                int32_t key;
+                while ((key = hk[h]) != -1 && key != c4[u]) h = (h + 1) & (2 * G - 1);
+                if (key == c4[u]) M[lane * G + hp[h]] = v4[u];
             }
         }
     }
     wave_sync();
     const double *al = alt + (nseg > 1 ? seg_of(soff, nseg, row) : 0) * kMaxPolyCols;
-    double x = (lane < L && J[lane] == row) ? 1.0 : 0.0;
+    double x = (lane < L && myc == row) ? 1.0 : 0.0;
     double acc = al[0] * x;
+    const int Lu = __builtin_amdgcn_readfirstlane(L);   // one group per wavefront when G == 64
     for (int k = 1; k < nalpha; ++k) {
-        // x goes through LDS, so that the L broadcast reads are independent
-        // loads rather than a chain of shuffles
-        X[lane] = x;
-        wave_sync();
         double xn = 0.0;
-        for (int p = 0; p < L; ++p) xn += X[p] * M[p * G + lane];
-        wave_sync();
+        if constexpr (G == 64) {
+            int p = 0;
+            for (; p + 8 <= Lu; p += 8) {
+                double m8[8], x8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    m8[u] = M[(p + u) * G + lane];
+                    const int64_t xb = __double_as_longlong(x);
+                    const int32_t lo = __builtin_amdgcn_readlane((int32_t)xb, p + u);
+                    const int32_t hi = __builtin_amdgcn_readlane((int32_t)(xb >> 32), p + u);
+                    x8[u] = __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xn += x8[u] * m8[u];
+            }
+            for (; p < Lu; ++p) {
+                const int64_t xb = __double_as_longlong(x);
+                const int32_t lo = __builtin_amdgcn_readlane((int32_t)xb, p);
+                const int32_t hi = __builtin_amdgcn_readlane((int32_t)(xb >> 32), p);
+                xn += __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo) * M[p * G + lane];
+            }
+        } else {
+            X[lane] = x;
+            wave_sync();
+            int p = 0;
+            for (; p + 8 <= L; p += 8) {
+                double m8[8], x8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    m8[u] = M[(p + u) * G + lane];
+                    x8[u] = X[p + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xn += x8[u] * m8[u];
+            }
+            for (; p < L; ++p) xn += X[p] * M[p * G + lane];
+            wave_sync();
+        }
         x = xn;
         acc += al[k] * x;
     }
@@ -603,12 +655,28 @@ FixedPlan fixed_sparsity_begin(const CsrView &Pt, hipStream_t s) {
     return F;
 }
 
-// Coefficient table (kMaxPolyCols per segment) and segment offsets on the
-// device; nseg = 1 needs no offsets.  h_tot: the plan's bin totals.
-static void fixed_sparsity_run(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff, int nseg,
-                               int nalpha, double *out_v, FixedPlan &F, const int32_t *h_tot, hipStream_t s) {
-    int32_t n = A.nr;
+// Rows of the pattern by length (bins of fixed_sparsity_begin), and the
+// longest of the long ones checked against the LDS capacity of k_poly_long.
+static Bins fixed_bins(const CsrView &Pt, FixedPlan &F, const int32_t *h_tot, hipStream_t s) {
     Bins B = bin_rows_end(F.bins, h_tot, s);
+    if (B.count(5)) {
+        int32_t maxlen = 0;
+        {
+            std::vector<int32_t> lr((size_t)B.count(5)), rpl((size_t)Pt.nr + 1);
+            d2h(lr.data(), B.list(5), lr.size(), s);
+            d2h(rpl.data(), Pt.rp, rpl.size(), s);
+            for (int32_t r : lr) maxlen = std::max(maxlen, rpl[r + 1] - rpl[r]);
+        }
+        AIRG_REQUIRE(maxlen <= kLongRowMax, ST_LIMIT,
+                     "row of " + std::to_string(maxlen) + " entries exceeds the fixed-sparsity row limit");
+    }
+    return B;
+}
+
+// Coefficient table (kMaxPolyCols per segment) and segment offsets on the
+// device; nseg = 1 needs no offsets.
+static void fixed_sparsity_binned(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff,
+                                  int nseg, int nalpha, double *out_v, const Bins &B, hipStream_t s) {
     auto rows = [&](auto kern, int b, int per_block, unsigned tpb) {
         if (B.count(b))
             kern<<<grid_for(B.count(b), per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Pt.rp,
@@ -621,22 +689,17 @@ static void fixed_sparsity_run(const CsrView &A, const CsrView &Pt, const double
     rows(k_poly_rows<64, 64>, 4, 1, 64);
     AIRG_LAUNCH_CHECK();
     if (B.count(5)) {
-        int32_t maxlen = 0;
-        {
-            // longest row among the long ones, checked against the LDS capacity
-            std::vector<int32_t> lr((size_t)B.count(5)), rpl((size_t)n + 1);
-            d2h(lr.data(), B.list(5), lr.size(), s);
-            d2h(rpl.data(), Pt.rp, rpl.size(), s);
-            for (int32_t r : lr) maxlen = std::max(maxlen, rpl[r + 1] - rpl[r]);
-        }
-        AIRG_REQUIRE(maxlen <= kLongRowMax, ST_LIMIT,
-                     "row of " + std::to_string(maxlen) + " entries exceeds the fixed-sparsity row limit");
         k_poly_long<<<(unsigned)B.count(5), 256, 0, s>>>(B.list(5), B.count(5), A.rp, A.ci, A.v, Pt.rp, Pt.ci, alt,
                                                          soff, nseg, nalpha, out_v);
         AIRG_LAUNCH_CHECK();
     }
 }
 
+static void fixed_sparsity_run(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff, int nseg,
+                               int nalpha, double *out_v, FixedPlan &F, const int32_t *h_tot, hipStream_t s) {
+    Bins B = fixed_bins(Pt, F, h_tot, s);
+    fixed_sparsity_binned(A, Pt, alt, soff, nseg, nalpha, out_v, B, s);
+}
 
 static void fixed_sparsity_tab(const CsrView &A, const CsrView &Pt, const double *alt, const int32_t *soff,
                                int nseg, int nalpha, double *out_v, hipStream_t s) {
@@ -656,6 +719,26 @@ __global__ void k_set_coefs(CoefArgs c, double *__restrict__ out) {
 #pragma unroll
         for (int k = 0; k < kMaxPolyCols; ++k) out[k] = c.a[k];
     }
+}
+
+Bins poly_pattern_bins(const CsrView &Pt, hipStream_t s) {
+    FixedPlan F = fixed_sparsity_begin(Pt, s);
+    int32_t h[kFixedBins + 1];
+    d2h(h, F.bins.tot.p, (size_t)kFixedBins + 1, s);
+    return fixed_bins(Pt, F, h, s);
+}
+
+void poly_fixed_sparsity_binned(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha, double *out_v,
+                                const Bins &B, hipStream_t s) {
+    AIRG_REQUIRE(nalpha >= 1 && nalpha <= kMaxPolyCols, ST_INVALID_ARG, "bad number of coefficients");
+    AIRG_REQUIRE(Pt.nr == A.nr, ST_INVALID_ARG, "pattern and matrix differ in rows");
+    if (A.nr == 0) return;
+    CoefArgs c{};
+    for (int k = 0; k < nalpha; ++k) c.a[k] = alpha[k];
+    DBuf<double> alt(kMaxPolyCols, s);
+    k_set_coefs<<<1, 64, 0, s>>>(c, alt.p);
+    AIRG_LAUNCH_CHECK();
+    fixed_sparsity_binned(A, Pt, alt.p, nullptr, 1, nalpha, out_v, B, s);
 }
 
 void poly_fixed_sparsity_planned(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha,

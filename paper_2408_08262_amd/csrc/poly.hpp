@@ -72,6 +72,11 @@ struct FixedPlan {
 FixedPlan fixed_sparsity_begin(const CsrView &Pt, hipStream_t s);
 void poly_fixed_sparsity_planned(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha,
                                  double *out_v, FixedPlan &plan, const int32_t *h_tot, hipStream_t s);
+// The assembly's row bins of a pattern (one host synchronisation), and the
+// assembly on them, for repeated assemblies on one pattern.
+Bins poly_pattern_bins(const CsrView &Pt, hipStream_t s);
+void poly_fixed_sparsity_binned(const CsrView &A, const CsrView &Pt, const double *alpha, int nalpha, double *out_v,
+                                const Bins &bins, hipStream_t s);
 // Batch form: the rows of segment p (host offsets off) use P[p]'s
 // coefficients; patterns from Pt.
 void poly_fixed_sparsity_seg(const CsrView &A, const CsrView &Pt, const std::vector<int32_t> &off,

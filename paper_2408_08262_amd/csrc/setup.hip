@@ -234,7 +234,8 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
                     DBuf<int32_t> &cidx, Csr &Aff, Csr *Afc, PolyInfo &poly, Csr &Ainv, Csr &Z, Csr &W, Csr &Ac,
                     Timer &tm, hipStream_t s, Branch *br = nullptr,
                     const std::function<void(hipStream_t)> &pre = nullptr, ExtractPlan *xp = nullptr,
-                    const int32_t *xtot = nullptr, int64_t *cbytes = nullptr) {
+                    const int32_t *xtot = nullptr, int64_t *cbytes = nullptr, Csr *acf_keep = nullptr,
+                    Csr *p_keep = nullptr, Csr *ap_keep = nullptr) {
     int32_t n = A.nr;
     int m = o.poly_order + 1;
     Csr P, AP;
@@ -317,6 +318,7 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
         nb += poly_bytes(view(Aff), m) + csr_bytes(view(Aff)) + csr_bytes(view(Ainv));
         nb += csr_bytes(view(Acf)) + csr_bytes(view(Ainv)) + 2 * csr_bytes(view(prod));
     }
+    if (acf_keep) *acf_keep = std::move(Acf);
     if (br) {
         tm.end();
         guard.b = nullptr;
@@ -347,6 +349,12 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     }
     tm.end();
     if (cbytes) *cbytes += nb;
+    if (p_keep) *p_keep = std::move(P);
+    if (ap_keep) {
+        AP.v.reset();
+        AP.vf.reset();
+        *ap_keep = std::move(AP);
+    }
 }
 
 }  // namespace
@@ -658,6 +666,22 @@ void finalize(Hier &H, int built = 0) {
     H.e32.alloc((size_t)n0, s);
 }
 
+// After a numeric re-setup: the values of every solve operator and FP32
+// copy again, into the operators of the same patterns (no size readback).
+void refresh_solve_values(Hier &H) {
+    hipStream_t s = H.s;
+    H.drop_graphs();
+    for (int l = 0; l < H.nlev(); ++l) {
+        Level &L = H.L(l);
+        if (L.coarsest) {
+            make_f32(L.A, s);
+            if (L.Ainv.rp.p) make_f32(L.Ainv, s);
+            continue;
+        }
+        solve_ops_fill(H, l, s);
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ build --
@@ -725,7 +749,9 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             if (l > 0) solve_ops(HH, l - 1, st);
         };
         complete_level(view(L.A), o, seed, l, nullptr, L.cf.p, L.rank.p, L.nF, L.nC, L.fidx, L.cidx, L.Aff, &L.Afc,
-                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br, pre, &xplan, xtot, &L.setup_bytes);
+                       L.poly, L.Ainv, L.Z, L.W, next->A, tm, s, &br, pre, &xplan, xtot, &L.setup_bytes, &L.Acf,
+                       &L.P, &L.APp);
+        L.xplan = std::move(xplan);
         next->n = next->A.nr;
         H->lv.push_back(std::move(next));
     }
@@ -739,11 +765,14 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
 }
 
 // ----------------------------------------------------- numeric re-setup --
-// The CF splittings, the pattern of every level operator (after its drop)
-// and the patterns of Z and W are kept; the values are recomputed level by
-// level from the new top-level values: extraction, coefficients and Ainv,
-// Z = -A_cf Ainv and A_c = R (A P) on the kept patterns (no drops), then the
-// solve operators.
+// The CF splittings, the pattern of every level operator (after its drop),
+// the patterns of Z and W, the extraction plan and the pattern of A P are
+// kept; the values are recomputed level by level from the new top-level
+// values: the blocks, coefficients and Ainv, Z = -A_cf Ainv, A P and
+// A_c = R (A P) on the kept patterns (no drops), then the values of the solve
+// operators.  The first re-setup bins the rows of the kept patterns for the
+// assembly and the products (one host synchronisation each); later ones only
+// synchronise for the polynomial's R factor.
 void resetup_hierarchy(Hier &H, const double *vals, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     H.s = s;
@@ -755,23 +784,41 @@ void resetup_hierarchy(Hier &H, const double *vals, hipStream_t s) {
         Level &L = H.L(l);
         if (L.coarsest) {
             L.poly = gmres_poly(view(L.A), H.seed, l, mc, s);
-            if (!o.coarse_matrix_free)
-                poly_fixed_sparsity_pattern(view(L.A), view(L.Ainv), L.poly.alpha, mc, L.Ainv.v.p, s);
+            if (!o.coarse_matrix_free) {
+                if (!L.rbins) {
+                    L.rb_ainv = poly_pattern_bins(view(L.Ainv), s);
+                    L.rbins = true;
+                }
+                poly_fixed_sparsity_binned(view(L.A), view(L.Ainv), L.poly.alpha, mc, L.Ainv.v.p, L.rb_ainv, s);
+            }
             break;
         }
         Level &N = H.L(l + 1);
-        Csr Acf;
-        extract_fc_blocks(view(L.A), L.cf.p, L.rank.p, L.nF, L.nC, L.Aff, L.Afc, Acf, s);
+        AIRG_REQUIRE(L.xplan.n == L.n && L.P.rp.p && L.APp.rp.p && L.Acf.rp.p, ST_INVALID_ARG,
+                     "hierarchy has no kept patterns for a numeric re-setup");
+        if (!L.rbins) {
+            L.rb_ainv = poly_pattern_bins(view(L.Ainv), s);
+            L.rb_z = pattern_bins(L.Z, s);
+            L.rb_ap = pattern_bins(L.APp, s);
+            L.rb_rap = pattern_bins(N.A, s);
+            L.rbins = true;
+        }
+        extract_refill(view(L.A), L.cf.p, L.rank.p, L.nF, L.nC, L.xplan, L.Aff, L.Afc, L.Acf, s);
         L.poly = gmres_poly(view(L.Aff), H.seed, l, m, s);
-        poly_fixed_sparsity_pattern(view(L.Aff), view(L.Ainv), L.poly.alpha, m, L.Ainv.v.p, s);
-        spgemm_on_pattern(view(Acf), view(L.Ainv), L.Z, -1.0, L.Z.v.p, s);
-        if (o.onepoint_weight == 1) onepoint_values(view(L.A), L.fidx.p, L.cidx.p, L.W, s);
-        Csr P = prolongator_from_w(L.W, L.cf.p, L.rank.p, L.n, L.nC, s);
+        poly_fixed_sparsity_binned(view(L.Aff), view(L.Ainv), L.poly.alpha, m, L.Ainv.v.p, L.rb_ainv, s);
+        spgemm_on_pattern_binned(view(L.Acf), view(L.Ainv), view(L.Z), L.rb_z, -1.0, L.Z.v.p, s);
+        if (o.onepoint_weight == 1) {
+            onepoint_values(view(L.A), L.fidx.p, L.cidx.p, L.W, s);
+            L.P = prolongator_from_w(L.W, L.cf.p, L.rank.p, L.n, L.nC, s);
+        }
         Csr R = restriction_full(view(L.Z), L.fidx.p, L.cidx.p, L.n, s);
-        Csr AP = spgemm(view(L.A), view(P), s);
-        spgemm_on_pattern(view(R), view(AP), N.A, 1.0, N.A.v.p, s);
+        DBuf<double> apv((size_t)L.APp.nnz, s);
+        CsrView AP = view(L.APp);
+        AP.v = apv.p;
+        spgemm_on_pattern_binned(view(L.A), view(L.P), AP, L.rb_ap, 1.0, apv.p, s);
+        spgemm_on_pattern_binned(view(R), AP, view(N.A), L.rb_rap, 1.0, N.A.v.p, s);
     }
-    finalize(H);
+    refresh_solve_values(H);
     AIRG_HIP(hipStreamSynchronize(s));
     H.resetup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }

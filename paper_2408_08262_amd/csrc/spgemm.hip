@@ -115,7 +115,7 @@ __device__ inline void for_products(int32_t row, const int32_t *__restrict__ arp
 // entry, with a wave barrier between entries, when ORDERED.  An A entry whose
 // B row alone exceeds the stage is visited straight from global memory.  The
 // products and their order per table slot are those of for_products.
-constexpr int kStage = 1024;
+constexpr int kStage = 256;
 template <bool VALUES>
 struct ProdStage {
     int32_t c[kStage];
@@ -797,20 +797,26 @@ __global__ void k_pattern_bin(int32_t m, const int32_t *__restrict__ prp, int8_t
     bin[i] = L == 0 ? 0 : L <= 16 ? 1 : L <= 64 ? 2 : L <= 256 ? 3 : L <= 1024 ? 4 : L <= 4096 ? 5 : 6;
 }
 
-void spgemm_on_pattern(const CsrView &A, const CsrView &Bm, const Csr &Pt, double sign, double *out_v,
-                       hipStream_t s) {
-    AIRG_REQUIRE(A.nc == Bm.nr && Pt.nr == A.nr, ST_INVALID_ARG, "pattern product dimensions differ");
-    int32_t m = A.nr;
-    if (m == 0 || Pt.nnz == 0) return;
-    DBuf<int8_t> bin((size_t)m, s);
-    k_pattern_bin<<<grid_for(m, 256), 256, 0, s>>>(m, Pt.rp.p, bin.p);
-    AIRG_LAUNCH_CHECK();
+Bins pattern_bins(const Csr &Pt, hipStream_t s) {
+    const int32_t m = Pt.nr;
+    DBuf<int8_t> bin((size_t)std::max<int32_t>(m, 1), s);
+    if (m > 0) {
+        k_pattern_bin<<<grid_for(m, 256), 256, 0, s>>>(m, Pt.rp.p, bin.p);
+        AIRG_LAUNCH_CHECK();
+    }
     Bins B = bin_rows(bin.p, m, 8, s);
     AIRG_REQUIRE(B.count(6) == 0, ST_LIMIT, "pattern row longer than 4096 entries");
+    return B;
+}
+
+void spgemm_on_pattern_binned(const CsrView &A, const CsrView &Bm, const CsrView &Pt, const Bins &B, double sign,
+                              double *out_v, hipStream_t s) {
+    AIRG_REQUIRE(A.nc == Bm.nr && Pt.nr == A.nr, ST_INVALID_ARG, "pattern product dimensions differ");
+    if (A.nr == 0 || Pt.nnz == 0) return;
     auto grp = [&](auto kern, int b, int rows_per_block, unsigned tpb) {
         if (B.count(b))
             kern<<<grid_for(B.count(b), rows_per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Bm.rp,
-                                                                      Bm.ci, Bm.v, Pt.rp.p, Pt.ci.p, sign, out_v);
+                                                                      Bm.ci, Bm.v, Pt.rp, Pt.ci, sign, out_v);
     };
     grp(k_spgemm_on_pattern<4, 16, 256>, 1, 64, 256);
     grp(k_spgemm_on_pattern<8, 64, 256>, 2, 32, 256);
@@ -818,6 +824,14 @@ void spgemm_on_pattern(const CsrView &A, const CsrView &Bm, const Csr &Pt, doubl
     grp(k_spgemm_on_pattern<64, 1024, 64>, 4, 1, 64);
     grp(k_spgemm_on_pattern<64, 4096, 64>, 5, 1, 64);
     AIRG_LAUNCH_CHECK();
+}
+
+void spgemm_on_pattern(const CsrView &A, const CsrView &Bm, const Csr &Pt, double sign, double *out_v,
+                       hipStream_t s) {
+    AIRG_REQUIRE(A.nc == Bm.nr && Pt.nr == A.nr, ST_INVALID_ARG, "pattern product dimensions differ");
+    if (A.nr == 0 || Pt.nnz == 0) return;
+    Bins B = pattern_bins(Pt, s);
+    spgemm_on_pattern_binned(A, Bm, view(Pt), B, sign, out_v, s);
 }
 
 static void run_global(bool numeric, const Bins &B, int b, const std::vector<int32_t> &per_row, const CsrView &A,

@@ -32,5 +32,11 @@ Csr spgemm_finish(const CsrView &A, const CsrView &B, SpgemmPlan &P, const int32
 // of the product off the pattern are not formed.  Same accumulation as spgemm.
 void spgemm_on_pattern(const CsrView &A, const CsrView &B, const Csr &Pt, double sign, double *out_v,
                        hipStream_t s);
+// The same in two halves: the rows of Pt binned by length once (one host
+// synchronisation), then products on those bins as often as the values of A
+// and B change.
+Bins pattern_bins(const Csr &Pt, hipStream_t s);
+void spgemm_on_pattern_binned(const CsrView &A, const CsrView &B, const CsrView &Pt, const Bins &bins, double sign,
+                              double *out_v, hipStream_t s);
 
 }  // namespace airg

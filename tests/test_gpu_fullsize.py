@@ -46,11 +46,17 @@ def residual_ok(P, x, b):
 def test_dg_square_512_fp32_fgmres():
     P = full_problem("dg_square_512")
     A = airg.to_device(P.rowptr, P.col, P.val)
+    kw = {"truncate_n": 65536, "coarse_iters": 6}      # as the benchmark times it
+    h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, **kw))
+    x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
+    assert info["converged"]
+    assert residual_ok(P, x.cpu().numpy(), P.b) <= 1.0001e-10
+    check_split_and_first_level(h, P, kw)
+    # and untruncated
     h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32))
     x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
     assert info["converged"]
     assert residual_ok(P, x.cpu().numpy(), P.b) <= 1.0001e-10
-    check_split_and_first_level(h, P, {})
 
 
 @pytest.mark.timeout(400)

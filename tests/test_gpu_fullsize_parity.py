@@ -34,6 +34,8 @@ airg = pytest.importorskip("paper_2408_08262_amd.airg")
 
 FP64_CYCLE_RTOL = 1e-12
 FP32_CYCLE_RTOL = 1e-5
+# the hierarchy options the benchmark times on dg_square_512
+DG_BENCH = {"truncate_n": 65536, "coarse_iters": 6}
 
 
 def say(*a):
@@ -71,7 +73,7 @@ def bench_opts(P, **kw):
 @pytest.mark.parametrize("name", ["dg_square_512", "p0_cube_128"])
 def test_whole_hierarchy_replay_complexities_and_vcycle(name):
     if name == "dg_square_512":
-        P, kw = full_problem("dg_square_512"), {}
+        P, kw = full_problem("dg_square_512"), dict(DG_BENCH)
     else:
         P, kw = full_problem("p0_cube_128"), {"truncate_n": 65536}
     say("%s: n=%d nnz=%d" % (name, P.n, P.nnz))
@@ -102,21 +104,22 @@ def test_whole_hierarchy_replay_complexities_and_vcycle(name):
 
 @pytest.mark.timeout(600)
 def test_dg_square_512_fp64_richardson_against_oracle_and_sweep():
-    """The benchmark's comparison form at full size: FP64 V-cycle inside
-    undamped Richardson (Results), residual recomputed by the oracle, error
+    """The benchmark's comparison form at full size (truncated as timed): FP64
+    V-cycle inside undamped Richardson (Results), residual recomputed by the oracle, error
     against the exact sweep and against the oracle's own Richardson solution
     on the replayed hierarchy."""
     P = full_problem("dg_square_512")
     A = airg.to_device(P.rowptr, P.col, P.val)
     h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_RICHARDSON, precond_precision=64,
-                                              use_graph=1))
+                                              use_graph=1, **DG_BENCH))
     x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
     x = x.cpu().numpy()
     r = np.linalg.norm(P.b - O.spmv((P.rowptr, P.col, P.val), x)) / np.linalg.norm(P.b)
     say("device Richardson: %d its, residual %.3e" % (info["iterations"], r))
     assert info["converged"] and r <= 1.0001e-10
     st = airg.airg_get_stats(h)
-    H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed), alphas=device_alphas(h, st["levels"]))
+    H = O.Hierarchy((P.rowptr, P.col, P.val), O.default_params(seed=P.seed, **DG_BENCH),
+                    alphas=device_alphas(h, st["levels"]))
     xo, its, rr = H.richardson(P.b, 1e-10, 100)
     say("oracle Richardson: %d its, residual %.3e" % (its, rr))
     assert its == info["iterations"]
