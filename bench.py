@@ -316,6 +316,16 @@ def time_form(airg, torch, A, b, opts, steps, warmup, rtol, workload=None, seg=N
     return {"sec": (t1 - t0) / steps, "x": x, "info": info, "st": st, "roof": roof}
 
 
+def cycle_bytes(st, vb, k=1):
+    """Algorithmic bytes of one V-cycle with vb-byte values and k right-hand sides."""
+    return st["vcycle_index_bytes"] + vb * st["vcycle_nnz"] + vb * k * st["vcycle_vec_entries"]
+
+
+def top_bytes(st, n, k=1):
+    """Algorithmic bytes of one FP64 product with the top operator(s) on k right-hand sides."""
+    return st["top_nnz"] * 12 + 4 * (n + 1) + 8 * k * 2 * n
+
+
 def outer_bytes(form, its, n, restart=30):
     """Vector traffic of the outer iterations around the cycles and top products: the casts and
     permutations into and out of the cycle, FGMRES's classical Gram-Schmidt twice (read the basis
@@ -330,13 +340,14 @@ def outer_bytes(form, its, n, restart=30):
     return tot
 
 
-def form_record(form, label, r, n, top_us=None):
+def form_record(form, label, r, n, top_us=None, k=1):
+    """k: right-hand sides solved together (the batched form's vectors are n x k)."""
     info, st = r["info"], r["st"]
     its = max(1, info["iterations"])
     wu_cycle = st["vcycle_nnz"] / st["top_nnz"]
     wus = info["iterations"] * (wu_cycle + 1.0)
-    vb = st["vcycle_bytes_fp32"] if form == "fp32_fgmres" else st["vcycle_bytes_fp64"]
-    solve_bytes = info["iterations"] * (vb + st["top_spmv_bytes_fp64"]) + outer_bytes(form, info["iterations"], n)
+    vb = cycle_bytes(st, 4 if form == "fp32_fgmres" else 8, k)
+    solve_bytes = info["iterations"] * (vb + top_bytes(st, n, k)) + outer_bytes(form, info["iterations"], n * k)
     solve_gbs = solve_bytes / info["seconds"] / 1e9 if info["seconds"] > 0 else 0.0
     setup_gbs = st["setup_bytes"] / st["setup_seconds"] / 1e9 if st["setup_seconds"] > 0 else 0.0
     rec = {"form": label, "seconds_per_step": round(r["sec"], 4), "setup_s": round(st["setup_seconds"], 4),
@@ -535,12 +546,15 @@ def batched_subrecord(a, airg, torch):
     out["roofline"] = rb["roof"]
     recb = form_record("fp32_fgmres", "batched FGMRES(30) FP64 per (segment, rhs) + batched FP32 V-cycle, one "
                                       "SpMM launch per stage, HIP graph, autotuned kernels", rb, n,
-                       rb["roof"]["avg_launch_us"] if rb["roof"] else None)
+                       rb["roof"]["avg_launch_us"] if rb["roof"] else None, k=bb.shape[1])
     log("timing batch48: sequential FP64")
     r64 = time_form(airg, torch, A, B, airg.default_opts(outer=airg.OUTER_RICHARDSON, precond_precision=64),
                     1, 1, a.rtol, seg=(offs, seeds))
     rec64 = form_record("fp64_richardson", "48 segments solved one after another, 4 rhs one after another, "
                                            "plain FP64 AIRG (Richardson)", r64, n)
+    # each (segment, rhs) pair iterates to its own count, of which only the largest is reported:
+    # no byte count for this form's solve
+    rec64["solve_roofline"] = None
     if not a.quick:
         import oracle as O
         from oracle.sweep import sweep_solve

@@ -145,6 +145,10 @@ typedef struct airg_stats {
     int64_t cycles_eager;         /* V-cycles applied since setup kernel by kernel      */
     int64_t cycles_graph;         /* ... and as replays of a captured HIP graph         */
     int64_t setup_bytes;          /* sum of the levels' setup_bytes                     */
+    int64_t vcycle_index_bytes;   /* column and row-pointer bytes one V-cycle reads;    */
+    int64_t vcycle_vec_entries;   /* vector entries it reads or writes per rhs: with  */
+                                  /* v-byte values and k rhs a cycle moves             */
+                                  /* index_bytes + v vcycle_nnz + v k vec_entries      */
 } airg_stats;
 
 /* Fills *opts with the defaults above.  Returns AIRG_ERR_INVALID_ARG if

@@ -61,7 +61,8 @@ class Stats(C.Structure):
                 ("vcycle_bytes_fp64", C.c_int64), ("vcycle_bytes_fp32", C.c_int64),
                 ("top_spmv_bytes_fp64", C.c_int64), ("device_bytes", C.c_int64),
                 ("resetup_seconds", C.c_double), ("vcycle_nnz", C.c_int64), ("top_nnz", C.c_int64),
-                ("cycles_eager", C.c_int64), ("cycles_graph", C.c_int64), ("setup_bytes", C.c_int64)]
+                ("cycles_eager", C.c_int64), ("cycles_graph", C.c_int64), ("setup_bytes", C.c_int64),
+                ("vcycle_index_bytes", C.c_int64), ("vcycle_vec_entries", C.c_int64)]
 
 
 _VP, _I32, _I64, _U64, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double

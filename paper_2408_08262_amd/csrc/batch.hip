@@ -12,6 +12,7 @@
 
 #include "batch.hpp"
 #include "csr.hpp"
+#include "trace.hpp"
 
 namespace airg {
 
@@ -410,6 +411,7 @@ void batch_profile(Batch &B, int reps, double *out, hipStream_t s) {
 // default stream cannot be captured) and then launched on the caller's
 // stream; it holds only kernel nodes over the batch's own buffers.
 void Batch::run(hipStream_t s, bool use_graph) {
+    TraceRange trace("batched V-cycle fp32");
     if (!use_graph) {
         ++cycles_eager;
         vcycle(0, g0.p, e0.p, s);
@@ -669,6 +671,7 @@ struct SegDots {
 
 BatchResult solve_batch(Batch &B, const Csr &A, const std::vector<int64_t> &seg, const double *b, double *x,
                         double rtol, int maxit, int restart, bool use_graph, hipStream_t s) {
+    TraceRange trace("airg batched solve: FGMRES");
     const int k = B.k, nseg = B.nseg;
     const int64_t n = B.n;
     const int np = nseg * k;   // (segment, rhs) pairs

@@ -422,7 +422,10 @@ airg_status airg_get_stats(const airg_handle *h, airg_stats *st) {
             st->vcycle_bytes_fp32 += vcycle_bytes(H, 4);
             const Level &T = *H.lv[0];
             st->top_spmv_bytes_fp64 += spmv_bytes(T.n, T.n, T.A.nnz, 8, false);
-            st->vcycle_nnz += vcycle_nnz(H);
+            const CycleCost cc = vcycle_cost(H);
+            st->vcycle_nnz += cc.nnz;
+            st->vcycle_index_bytes += cc.index_bytes;
+            st->vcycle_vec_entries += cc.vec_entries;
             st->top_nnz += T.A.nnz;
             st->cycles_eager += H.cycles_eager;
             st->cycles_graph += H.cycles_graph;

@@ -160,4 +160,13 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Keeps the compiler from moving memory accesses across this point without
+// waiting for outstanding ones: a wavefront's LDS operations are carried out
+// in the order they are issued, so issue order is all that the per-slot
+// order of LDS accumulations needs.
+__device__ inline void lds_issue_order() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+}
+
 }  // namespace airg

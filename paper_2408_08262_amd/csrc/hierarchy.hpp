@@ -14,6 +14,7 @@
 #include "common.hpp"
 #include "csr.hpp"
 #include "poly.hpp"
+#include "trace.hpp"
 
 namespace airg {
 
@@ -100,6 +101,12 @@ struct Hier {
 // stream, tagged with the level being built (level is set by the driver
 // before each level; -1 = after the level loop); span_on times work enqueued
 // by another thread on another stream (its phase then overlaps the others).
+inline const char *phase_name(int phase) {
+    static const char *const names[AIRG_PHASE_COUNT] = {"cf", "extract", "poly", "restrictor",
+                                                        "prolongator", "coarse", "finalize"};
+    return phase >= 0 && phase < AIRG_PHASE_COUNT ? names[phase] : "phase";
+}
+
 struct PhaseTimer {
     hipStream_t s;
     std::mutex mu;
@@ -124,9 +131,11 @@ struct PhaseTimer {
         start = pooled_event();
         AIRG_HIP(hipEventRecord(start, s));
         cur = phase;
+        trace_push(phase_name(phase));
     }
     void end() {
         if (cur < 0) return;
+        trace_pop();
         hipEvent_t stop = pooled_event();
         AIRG_HIP(hipEventRecord(stop, s));
         std::lock_guard<std::mutex> lk(mu);
@@ -136,6 +145,7 @@ struct PhaseTimer {
     }
     template <class F>
     void span_on(int phase, int lvl, hipStream_t st, F &&f) {
+        TraceRange tr(phase_name(phase));
         hipEvent_t a = pooled_event(), b = pooled_event();
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -255,6 +265,15 @@ void apply_vcycle(Hier &H, const double *g, double *e, int precision);
 void profile_vcycle(Hier &H, int precision, int reps, double *out);
 SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit);
 
+// One V-cycle's products: stored entries, index bytes (columns, row
+// pointers) and vector entries read or written per right-hand side; its
+// algorithmic bytes with v-byte values and k right-hand sides follow.
+struct CycleCost {
+    int64_t nnz = 0, index_bytes = 0, vec_entries = 0;
+    void add(int64_t rows, int64_t cols, int64_t nz, bool reads_y, int64_t times);
+    int64_t bytes(int vb, int k) const { return index_bytes + vb * nnz + (int64_t)vb * k * vec_entries; }
+};
+CycleCost vcycle_cost(const Hier &H);
 // Algorithmic bytes of one V-cycle with vbytes-byte values.
 int64_t vcycle_bytes(const Hier &H, int vbytes);
 // Stored entries of every matrix one V-cycle applies (its work in units of

@@ -130,6 +130,7 @@ void check_segments(const Csr &A, const std::vector<int64_t> &seg, hipStream_t s
 
 std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &seg,
                                          const std::vector<uint64_t> &seeds, const airg_opts &o, hipStream_t s) {
+    TraceRange trace("airg batch setup");
     auto t0 = std::chrono::steady_clock::now();
     auto H = std::make_unique<SegHier>();
     H->opt = o;
@@ -156,6 +157,7 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         SegLevel &L = *H->lv[l];
         const int32_t n = L.n;
         const int na = (int)L.seg.size();
+        TraceRange trace_level("batch setup level %d", l);
         tm.level = l;
         std::vector<int32_t> off(na + 1);
         std::vector<uint64_t> sd(na);
@@ -330,34 +332,25 @@ void segmented_stats(const SegHier &H, airg_stats *st) {
     const SegLevel &T = *H.lv[0];
     const double n0 = T.n, z0 = (double)T.A.nnz;
     double g = 0, o = 0, sc = 0;
-    int64_t b64 = 0, b32 = 0, znz = 0;
+    CycleCost c;
     const int vc = H.opt.coarse_iters;
     for (auto &lp : H.lv) {
         const SegLevel &L = *lp;
         g += L.n;
         o += (double)L.A.nnz;
-        if (L.nF + L.nC > 0)
-            znz += L.Rp.nnz + L.Pp.nnz + (int64_t)H.opt.up_smooths * (L.AF.nnz + L.Ainv.nnz);
-        if (L.nT > 0) znz += L.AinvT.nnz + (int64_t)(vc - 1) * (L.AT.nnz + L.AinvT.nnz);
         if (L.nF + L.nC > 0) {
             sc += (double)L.Ainv.nnz + (double)L.Aff.nnz + (double)L.Afc.nnz + (double)(L.Z.nnz + L.nC) +
                   (double)(L.W.nnz + L.nC);
-            for (int vb : {8, 4}) {
-                int64_t b = spmv_bytes(L.Rp.nr, L.Rp.nc, L.Rp.nnz, vb, false) +
-                            spmv_bytes(L.Pp.nr, L.Pp.nc, L.Pp.nnz, vb, false) +
-                            H.opt.up_smooths * (spmv_bytes(L.AF.nr, L.AF.nc, L.AF.nnz, vb, true) +
-                                                spmv_bytes(L.Ainv.nr, L.Ainv.nc, L.Ainv.nnz, vb, true));
-                (vb == 8 ? b64 : b32) += b;
-            }
+            c.add(L.Rp.nr, L.Rp.nc, L.Rp.nnz, false, 1);
+            c.add(L.Pp.nr, L.Pp.nc, L.Pp.nnz, false, 1);
+            c.add(L.AF.nr, L.AF.nc, L.AF.nnz, true, H.opt.up_smooths);
+            c.add(L.Ainv.nr, L.Ainv.nc, L.Ainv.nnz, true, H.opt.up_smooths);
         }
         if (L.nT > 0) {
             sc += (double)L.AinvT.nnz + (vc > 1 ? (double)L.AT.nnz : 0.0);
-            for (int vb : {8, 4}) {
-                int64_t b = spmv_bytes(L.nT, L.nT, L.AinvT.nnz, vb, false) +
-                            (int64_t)(vc - 1) * (spmv_bytes(L.nT, L.nT, L.AT.nnz, vb, true) +
-                                                 spmv_bytes(L.nT, L.nT, L.AinvT.nnz, vb, true));
-                (vb == 8 ? b64 : b32) += b;
-            }
+            c.add(L.nT, L.nT, L.AinvT.nnz, false, 1);
+            c.add(L.nT, L.nT, L.AT.nnz, true, vc - 1);
+            c.add(L.nT, L.nT, L.AinvT.nnz, true, vc - 1);
         }
     }
     st->levels = (int32_t)H.lv.size();
@@ -365,10 +358,12 @@ void segmented_stats(const SegHier &H, airg_stats *st) {
     st->operator_complexity = o / z0;
     st->storage_complexity = sc / z0;
     for (int k = 0; k < AIRG_PHASE_COUNT; ++k) st->phase_seconds[k] = H.phase[k];
-    st->vcycle_bytes_fp64 = b64;
-    st->vcycle_bytes_fp32 = b32;
+    st->vcycle_bytes_fp64 = c.bytes(8, 1);
+    st->vcycle_bytes_fp32 = c.bytes(4, 1);
     st->top_spmv_bytes_fp64 = spmv_bytes(T.n, T.n, T.A.nnz, 8, false);
-    st->vcycle_nnz = znz;
+    st->vcycle_nnz = c.nnz;
+    st->vcycle_index_bytes = c.index_bytes;
+    st->vcycle_vec_entries = c.vec_entries;
     st->top_nnz = T.A.nnz;
 }
 

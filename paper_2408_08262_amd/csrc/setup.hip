@@ -686,6 +686,7 @@ void refresh_solve_values(Hier &H) {
 
 // ------------------------------------------------------------------ build --
 std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t seed, hipStream_t s) {
+    TraceRange trace("airg setup");
     auto t0 = std::chrono::steady_clock::now();
     auto H = std::make_unique<Hier>();
     H->opt = o;
@@ -699,6 +700,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
     int maxl = o.max_levels > 0 ? o.max_levels : 64;
     Branch br(s);
     for (int l = 0;; ++l) {
+        TraceRange trace_level("setup level %d", l);
         Level &L = H->L(l);
         int32_t n = L.n;
         tm.level = l;
@@ -774,6 +776,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
 // assembly and the products (one host synchronisation each); later ones only
 // synchronise for the polynomial's R factor.
 void resetup_hierarchy(Hier &H, const double *vals, hipStream_t s) {
+    TraceRange trace("airg re-setup");
     auto t0 = std::chrono::steady_clock::now();
     H.s = s;
     const airg_opts &o = H.opt;
@@ -843,47 +846,43 @@ int64_t spmv_bytes(int64_t rows, int64_t cols, int64_t nnz, int vbytes, bool rea
     return nnz * (vbytes + 4) + 4 * (rows + 1) + (int64_t)vbytes * (cols + rows + (reads_y ? rows : 0));
 }
 
-int64_t vcycle_bytes(const Hier &H, int vb) {
-    int64_t b = 0;
+// One V-cycle's products: stored entries, index bytes (columns and row
+// pointers) and vector entries read or written per right-hand side.
+void CycleCost::add(int64_t rows, int64_t cols, int64_t nz, bool reads_y, int64_t times) {
+    nnz += times * nz;
+    index_bytes += times * (4 * nz + 4 * (rows + 1));
+    vec_entries += times * (cols + rows + (reads_y ? rows : 0));
+}
+
+CycleCost vcycle_cost(const Hier &H) {
+    CycleCost c;
     for (int l = 0; l < (int)H.lv.size(); ++l) {
         const Level &L = *H.lv[l];
         if (L.coarsest) {
-            int vc = H.opt.coarse_iters;
+            const int vc = H.opt.coarse_iters;
             if (H.opt.coarse_matrix_free) {
                 // vc applications of q(A): m - 1 products each; vc - 1 residuals
-                int64_t per = (int64_t)(L.poly.m - 1) * spmv_bytes(L.n, L.n, L.A.nnz, vb, false);
-                b += (int64_t)vc * per + (int64_t)(vc - 1) * spmv_bytes(L.n, L.n, L.A.nnz, vb, true);
+                c.add(L.n, L.n, L.A.nnz, false, (int64_t)vc * (L.poly.m - 1));
+                c.add(L.n, L.n, L.A.nnz, true, vc - 1);
                 continue;
             }
             // e = Ainv g, then (vc - 1) times: t = g - A e; e += Ainv t
-            b += spmv_bytes(L.n, L.n, L.Ainv.nnz, vb, false);
-            b += (int64_t)(vc - 1) * (spmv_bytes(L.n, L.n, L.A.nnz, vb, true) + spmv_bytes(L.n, L.n, L.Ainv.nnz, vb, true));
+            c.add(L.n, L.n, L.Ainv.nnz, false, 1);
+            c.add(L.n, L.n, L.A.nnz, true, vc - 1);
+            c.add(L.n, L.n, L.Ainv.nnz, true, vc - 1);
             continue;
         }
-        b += spmv_bytes(L.Rp.nr, L.Rp.nc, L.Rp.nnz, vb, false);
-        b += spmv_bytes(L.Pp.nr, L.Pp.nc, L.Pp.nnz, vb, false);
-        b += H.opt.up_smooths *
-             (spmv_bytes(L.AF.nr, L.AF.nc, L.AF.nnz, vb, true) + spmv_bytes(L.Ainv.nr, L.Ainv.nc, L.Ainv.nnz, vb, true));
+        c.add(L.Rp.nr, L.Rp.nc, L.Rp.nnz, false, 1);
+        c.add(L.Pp.nr, L.Pp.nc, L.Pp.nnz, false, 1);
+        c.add(L.AF.nr, L.AF.nc, L.AF.nnz, true, H.opt.up_smooths);
+        c.add(L.Ainv.nr, L.Ainv.nc, L.Ainv.nnz, true, H.opt.up_smooths);
     }
-    return b;
+    return c;
 }
 
-int64_t vcycle_nnz(const Hier &H) {
-    int64_t z = 0;
-    for (int l = 0; l < (int)H.lv.size(); ++l) {
-        const Level &L = *H.lv[l];
-        if (L.coarsest) {
-            int vc = H.opt.coarse_iters;
-            if (H.opt.coarse_matrix_free)
-                z += (int64_t)vc * (L.poly.m - 1) * L.A.nnz + (int64_t)(vc - 1) * L.A.nnz;
-            else
-                z += L.Ainv.nnz + (int64_t)(vc - 1) * (L.A.nnz + L.Ainv.nnz);
-            continue;
-        }
-        z += L.Rp.nnz + L.Pp.nnz + (int64_t)H.opt.up_smooths * (L.AF.nnz + L.Ainv.nnz);
-    }
-    return z;
-}
+int64_t vcycle_bytes(const Hier &H, int vb) { return vcycle_cost(H).bytes(vb, 1); }
+
+int64_t vcycle_nnz(const Hier &H) { return vcycle_cost(H).nnz; }
 
 void complexities(const Hier &H, double *grid, double *op, double *storage) {
     const Level &T = *H.lv[0];

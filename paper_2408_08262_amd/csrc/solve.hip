@@ -230,6 +230,7 @@ void run_captured(Hier &H, int k, F &&f) {
 // the casts in and out permute.  With use_graph one captured graph per
 // precision serves every call after the first Hier::kEagerCycles.
 void Hier::precondition(const double *rv, double *ev, int precision) {
+    TraceRange trace(precision == 32 ? "V-cycle fp32" : "V-cycle fp64");
     Level &T = L(0);
     const int64_t n0 = T.n;
     const int32_t *ip = T.coarsest ? nullptr : T.iperm.p;   // level position -> natural index
@@ -299,6 +300,7 @@ void profile_vcycle(Hier &H, int precision, int reps, double *out) {
 // Undamped Richardson from a zero guess: x += V(b - A x) until
 // ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual every iteration).
 SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, int maxit) {
+    TraceRange trace("airg solve: Richardson");
     hipStream_t s = H.s;
     int64_t n = H.L(0).n;
     SolveResult res;
@@ -334,6 +336,7 @@ SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, i
 // Gram-Schmidt coefficients and the new vector's norm stay on the device
 // until one readback per Arnoldi step brings all of them to the host.
 SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit) {
+    TraceRange trace("airg solve: FGMRES");
     hipStream_t s = H.s;
     int64_t n = H.L(0).n;
     int m = H.opt.fgmres_restart > 0 ? H.opt.fgmres_restart : 30;

@@ -103,7 +103,7 @@ __device__ inline void for_products(int32_t row, const int32_t *__restrict__ arp
                             if (c2[t] >= 0) f(c2[t], VALUES ? a[j] * v2[t] : 0.0);
                     }
                 }
-                if (ORDERED) wave_sync();
+                if (ORDERED) lds_issue_order();
             }
         }
     }
@@ -209,8 +209,9 @@ __device__ inline void for_products_staged(int32_t row, const int32_t *__restric
             for (int j = 0; j < nq; ++j) {
                 const int32_t o1 = S.off[j + 1];
                 for (int32_t p = S.off[j] + lane; p < o1; p += 64) f(S.c[p], VALUES ? S.v[p] : 0.0);
-                wave_sync();
+                lds_issue_order();
             }
+            wave_sync();
         } else {
             for (int32_t p = lane; p < tot; p += 64) f(S.c[p], VALUES ? S.v[p] : 0.0);
             wave_sync();
@@ -676,8 +677,9 @@ __global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *
                     mark[c] = 1;
                     unsafeAtomicAdd(&acc[c], sv[p]);
                 }
-                wave_sync();
+                lds_issue_order();
             }
+            wave_sync();
         } else {
             for (int32_t p = lane; p < tot; p += 64)
                 if ((uint32_t)sc[p] < (uint32_t)NC) mark[sc[p]] = 1;

@@ -57,6 +57,9 @@ def test_vcycle_work_units_match_oracle_replay(name, kw):
         want += ups * (f_rows_nnz(Al, cf) + int(H.matrix(l, "Ainv")[0][-1]))
     assert st["vcycle_nnz"] == want
     assert st["top_nnz"] == P.nnz
+    # the byte count splits into index bytes, values and vector entries
+    for vb, key in ((8, "vcycle_bytes_fp64"), (4, "vcycle_bytes_fp32")):
+        assert st["vcycle_index_bytes"] + vb * st["vcycle_nnz"] + vb * st["vcycle_vec_entries"] == st[key]
 
 
 def test_per_level_setup_times_add_up_and_profile_covers_levels():

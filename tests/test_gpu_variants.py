@@ -97,9 +97,16 @@ def test_vcycle_matches_oracle(kw):
     g = np.random.default_rng(3).standard_normal(P.n)
     want = H.vcycle(g)
     got = airg.airg_vcycle(h, torch.as_tensor(g, device="cuda")).cpu().numpy()
-    assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(want)
     got32 = airg.airg_vcycle(h, torch.as_tensor(g, device="cuda"), precision=32).cpu().numpy()
-    assert np.linalg.norm(got32 - want) <= 1e-4 * np.linalg.norm(want)
+    r64 = np.linalg.norm(got - want) / np.linalg.norm(want)
+    r32 = np.linalg.norm(got32 - want) / np.linalg.norm(want)
+    print("V-cycle against the oracle's: fp64 %.3e fp32 %.3e" % (r64, r32))
+    # the hierarchies' coefficients differ at the TSQR's rounding (about 1e-9 here); the FP32 cycle adds
+    # single-precision rounding, a few units of 6e-8 per level (measured 1.6e-7).  The matrix-free
+    # coarse polynomial sums alpha_k A^k x over thirteen powers whose coefficients are large and of
+    # alternating sign, which magnifies FP32 rounding (measured 6.0e-5)
+    assert r64 <= 1e-9
+    assert r32 <= (1e-4 if kw.get("coarse_matrix_free") else 1e-5)
 
 
 @pytest.mark.parametrize("kw", [{"poly_sparsity_order": 2}, {"poly_sparsity_order": 3},
