@@ -46,7 +46,7 @@ def residual_ok(P, x, b):
 def test_dg_square_512_fp32_fgmres():
     P = full_problem("dg_square_512")
     A = airg.to_device(P.rowptr, P.col, P.val)
-    kw = {"truncate_n": 65536, "coarse_iters": 6}      # as the benchmark times it
+    kw = {"truncate_n": 98304, "coarse_iters": 6}      # as the benchmark times it
     h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, outer=airg.OUTER_FGMRES, precond_precision=32, **kw))
     x, info = airg.airg_solve(h, torch.as_tensor(P.b, device="cuda"), rtol=1e-10, max_it=100)
     assert info["converged"]

@@ -35,7 +35,7 @@ airg = pytest.importorskip("paper_2408_08262_amd.airg")
 FP64_CYCLE_RTOL = 1e-12
 FP32_CYCLE_RTOL = 1e-5
 # the hierarchy options the benchmark times on dg_square_512
-DG_BENCH = {"truncate_n": 65536, "coarse_iters": 6}
+DG_BENCH = {"truncate_n": 98304, "coarse_iters": 6}
 
 
 def say(*a):
