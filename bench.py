@@ -588,6 +588,25 @@ def batched_subrecord(a, airg, torch):
     return out
 
 
+def level_cycle_bytes(lv, ups, citers, k):
+    """Algorithmic bytes (FP32, FP64) of a level's own work in one cycle on k right-hand sides: the
+    restriction [Z I], the prolongation [W; I] and ups x ([A_ff A_fc] residual + Ainv update); on the
+    coarsest level Ainv once and (A residual + Ainv update) citers - 1 times."""
+    def spmv(rows, cols, nz, reads_y, vb):
+        return nz * (vb + 4) + 4 * (rows + 1) + vb * k * (cols + rows + (rows if reads_y else 0))
+    out = []
+    for vb in (4, 8):
+        n, nf, nc = lv["n"], lv["n_f"], lv["n_c"]
+        if lv["coarsest"]:
+            b = spmv(n, n, lv["nnz_ainv"], False, vb) + (citers - 1) * (spmv(n, n, lv["nnz_a"], True, vb) +
+                                                                         spmv(n, n, lv["nnz_ainv"], True, vb))
+        else:
+            b = spmv(nc, n, lv["nnz_z"] + nc, False, vb) + spmv(n, nc, lv["nnz_w"] + nc, False, vb)
+            b += ups * (spmv(nf, n, lv["nnz_aff"] + lv["nnz_afc"], True, vb) + spmv(nf, nf, lv["nnz_ainv"], True, vb))
+        out.append(int(b))
+    return out
+
+
 def levels_report_batch(a, airg, torch):
     """Per-level setup time by phase (all segments together) and per-level batched FP32 cycle time."""
     from workloads import batch as batch_problems, concat
@@ -605,7 +624,7 @@ def levels_report_batch(a, airg, torch):
     t32 = airg.airg_batch_vcycle_profile(h, nrhs=bb.shape[1], reps=20)
     rows = []
     for l in range(st["levels"]):
-        lv, n, nnz, segs = None, 0, 0, 0
+        lv, n, nnz, segs, b32 = None, 0, 0, 0, 0
         for p in range(len(probs)):
             try:
                 x = airg.airg_get_level(h, l, segment=p, with_cf=False)
@@ -615,10 +634,11 @@ def levels_report_batch(a, airg, torch):
             n += x["n"]
             nnz += x["nnz_a"]
             segs += 1
+            b32 += level_cycle_bytes(x, opts.up_smooths, opts.coarse_iters, bb.shape[1])[0]
         rows.append({"level": l, "n": n, "nnz_a": nnz, "segments": segs, "coarsest": False,
                      "setup_ms": {k: round(v * 1e3, 4) for k, v in lv["setup_seconds"].items()},
                      "setup_bytes": lv["setup_bytes"], "vcycle_us_fp32": round(t32[l] * 1e6, 2),
-                     "vcycle_us_fp64": 0.0})
+                     "vcycle_us_fp64": 0.0, "vcycle_bytes_fp32": b32, "vcycle_bytes_fp64": 0})
     print(json.dumps({"levels_report": "batch48: 48 DG-P1 upwind problems x 4 rhs, batched FP32 cycle, "
                                        "n=%d, nnz=%d" % (int(offs[-1]), int(rp[-1])),
                       "setup_s": st["setup_seconds"], "phase_seconds": st["phase_seconds"], "rows": rows}),
@@ -645,10 +665,14 @@ def levels_report(a, airg, torch):
     rows = []
     for l in range(st["levels"]):
         lv = airg.airg_get_level(h, l, with_cf=False)
+        b32, b64 = level_cycle_bytes(lv, opts.up_smooths, citers, 1)
         rows.append({"level": l, "n": lv["n"], "nnz_a": lv["nnz_a"], "coarsest": lv["coarsest"],
                      "setup_ms": {k: round(v * 1e3, 4) for k, v in lv["setup_seconds"].items()},
                      "setup_bytes": lv["setup_bytes"],
-                     "vcycle_us_fp32": round(t32[l] * 1e6, 2), "vcycle_us_fp64": round(t64[l] * 1e6, 2)})
+                     "vcycle_us_fp32": round(t32[l] * 1e6, 2), "vcycle_us_fp64": round(t64[l] * 1e6, 2),
+                     "vcycle_bytes_fp32": b32, "vcycle_bytes_fp64": b64})
+    # the levels' cycle bytes add up to the hierarchy's
+    assert sum(r["vcycle_bytes_fp64"] for r in rows) == st["vcycle_bytes_fp64"]
     print(json.dumps({"levels_report": desc + ", truncate_n=%d, coarse_iters=%d" % (trunc, citers),
                       "setup_s": st["setup_seconds"], "phase_seconds": st["phase_seconds"], "rows": rows}),
           flush=True)

@@ -485,7 +485,9 @@ __device__ inline uint32_t poly_hash(int32_t c) {
     return ((uint32_t)c * 2654435761u) & (2 * G - 1);
 }
 
-template <int G, int TPB>
+// MS (<= G): the rows of the launch have at most MS entries, and M_i is
+// stored MS x MS, so that a bin of shorter rows holds more of them in LDS.
+template <int G, int TPB, int MS>
 __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ list, int64_t count,
                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                    const double *__restrict__ v, const int32_t *__restrict__ prp,
@@ -493,8 +495,9 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
                                                    const int32_t *__restrict__ soff, int nseg, int nalpha,
                                                    double *__restrict__ out) {
 #pragma clang fp contract(off)
+    static_assert(MS <= G, "row capacity above the group width");
     constexpr int NG = TPB / G;
-    __shared__ double Ms[NG][G * G];
+    __shared__ double Ms[NG][MS * MS];
     __shared__ double Xs[NG][G];
     __shared__ int32_t Hk[NG][2 * G];
     __shared__ int32_t Hp[NG][2 * G];
@@ -511,7 +514,7 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     int32_t *hp = Hp[gid];
     const int32_t myc = lane < L ? pci[b + lane] : -1;
     for (int t = lane; t < 2 * G; t += G) hk[t] = -1;
-    for (int t = lane; t < G * G; t += G) M[t] = 0.0;
+    for (int t = lane; t < MS * MS; t += G) M[t] = 0.0;
     wave_sync();
     if (lane < L) {   // columns are distinct: each claims its own slot
         uint32_t h = poly_hash<G>(myc);
@@ -538,7 +541,7 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
                 uint32_t h = poly_hash<G>(c4[u]);
                 int32_t key;
                 while ((key = hk[h]) != -1 && key != c4[u]) h = (h + 1) & (2 * G - 1);
-                if (key == c4[u]) M[lane * G + hp[h]] = v4[u];
+                if (key == c4[u]) M[lane * MS + hp[h]] = v4[u];
             }
         }
     }
@@ -555,7 +558,7 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
                 double m8[8], x8[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    m8[u] = M[(p + u) * G + lane];
+                    m8[u] = lane < MS ? M[(p + u) * MS + lane] : 0.0;
                     const int64_t xb = __double_as_longlong(x);
                     const int32_t lo = __builtin_amdgcn_readlane((int32_t)xb, p + u);
                     const int32_t hi = __builtin_amdgcn_readlane((int32_t)(xb >> 32), p + u);
@@ -568,7 +571,7 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
                 const int64_t xb = __double_as_longlong(x);
                 const int32_t lo = __builtin_amdgcn_readlane((int32_t)xb, p);
                 const int32_t hi = __builtin_amdgcn_readlane((int32_t)(xb >> 32), p);
-                xn += __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo) * M[p * G + lane];
+                xn += __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo) * (lane < MS ? M[p * MS + lane] : 0.0);
             }
         } else {
             X[lane] = x;
@@ -578,13 +581,13 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
                 double m8[8], x8[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    m8[u] = M[(p + u) * G + lane];
+                    m8[u] = lane < MS ? M[(p + u) * MS + lane] : 0.0;
                     x8[u] = X[p + u];
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) xn += x8[u] * m8[u];
             }
-            for (; p < L; ++p) xn += X[p] * M[p * G + lane];
+            for (; p < L; ++p) xn += X[p] * (lane < MS ? M[p * MS + lane] : 0.0);
             wave_sync();
         }
         x = xn;
@@ -649,8 +652,8 @@ FixedPlan fixed_sparsity_begin(const CsrView &Pt, hipStream_t s) {
     FixedPlan F;
     const int32_t n = Pt.nr;
     F.bin.alloc((size_t)n + 1, s);
-    // bins by row length: <= 4, 8, 16, 32, 64, longer
-    const BinRule rule{{4, 8, 16, 32, 64}, 5};
+    // bins by row length: <= 4, 8, 16, 24, 32, 48, 64, longer
+    const BinRule rule{{4, 8, 16, 24, 32, 48, 64}, 7};
     F.bins = bin_rows_begin_rule(Pt.rp, true, rule, F.bin.p, n, kFixedBins, s);
     return F;
 }
@@ -659,11 +662,11 @@ FixedPlan fixed_sparsity_begin(const CsrView &Pt, hipStream_t s) {
 // longest of the long ones checked against the LDS capacity of k_poly_long.
 static Bins fixed_bins(const CsrView &Pt, FixedPlan &F, const int32_t *h_tot, hipStream_t s) {
     Bins B = bin_rows_end(F.bins, h_tot, s);
-    if (B.count(5)) {
+    if (B.count(kFixedLongBin)) {
         int32_t maxlen = 0;
         {
-            std::vector<int32_t> lr((size_t)B.count(5)), rpl((size_t)Pt.nr + 1);
-            d2h(lr.data(), B.list(5), lr.size(), s);
+            std::vector<int32_t> lr((size_t)B.count(kFixedLongBin)), rpl((size_t)Pt.nr + 1);
+            d2h(lr.data(), B.list(kFixedLongBin), lr.size(), s);
             d2h(rpl.data(), Pt.rp, rpl.size(), s);
             for (int32_t r : lr) maxlen = std::max(maxlen, rpl[r + 1] - rpl[r]);
         }
@@ -682,15 +685,18 @@ static void fixed_sparsity_binned(const CsrView &A, const CsrView &Pt, const dou
             kern<<<grid_for(B.count(b), per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v, Pt.rp,
                                                                 Pt.ci, alt, soff, nseg, nalpha, out_v);
     };
-    rows(k_poly_rows<4, 256>, 0, 64, 256);
-    rows(k_poly_rows<8, 256>, 1, 32, 256);
-    rows(k_poly_rows<16, 256>, 2, 16, 256);
-    rows(k_poly_rows<32, 128>, 3, 4, 128);
-    rows(k_poly_rows<64, 64>, 4, 1, 64);
+    rows(k_poly_rows<4, 256, 4>, 0, 64, 256);
+    rows(k_poly_rows<8, 256, 8>, 1, 32, 256);
+    rows(k_poly_rows<16, 256, 16>, 2, 16, 256);
+    rows(k_poly_rows<32, 128, 24>, 3, 4, 128);
+    rows(k_poly_rows<32, 128, 32>, 4, 4, 128);
+    rows(k_poly_rows<64, 64, 48>, 5, 1, 64);
+    rows(k_poly_rows<64, 64, 64>, 6, 1, 64);
     AIRG_LAUNCH_CHECK();
-    if (B.count(5)) {
-        k_poly_long<<<(unsigned)B.count(5), 256, 0, s>>>(B.list(5), B.count(5), A.rp, A.ci, A.v, Pt.rp, Pt.ci, alt,
-                                                         soff, nseg, nalpha, out_v);
+    if (B.count(kFixedLongBin)) {
+        k_poly_long<<<(unsigned)B.count(kFixedLongBin), 256, 0, s>>>(B.list(kFixedLongBin), B.count(kFixedLongBin),
+                                                                     A.rp, A.ci, A.v, Pt.rp, Pt.ci, alt, soff, nseg,
+                                                                     nalpha, out_v);
         AIRG_LAUNCH_CHECK();
     }
 }

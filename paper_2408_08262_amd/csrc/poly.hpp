@@ -64,7 +64,8 @@ void poly_fixed_sparsity_pattern(const CsrView &A, const CsrView &Pt, const doub
 // The same in two halves: the rows of Pt binned by length (no
 // synchronisation; kFixedBins + 1 totals at plan.bins.tot), then, with those
 // totals on the host, the assembly.
-constexpr int kFixedBins = 6;
+constexpr int kFixedBins = 8;      // rows of <= 4, 8, 16, 24, 32, 48, 64 entries, longer
+constexpr int kFixedLongBin = 7;
 struct FixedPlan {
     DBuf<int8_t> bin;
     BinPlan bins;
