@@ -120,7 +120,7 @@ typedef struct airg_level_info {
                                   /* (batched form: the level over all segments)         */
     int64_t setup_bytes;          /* bytes the level's setup steps must move, each step */
                                   /* reading its inputs and writing its outputs once    */
-                                  /* (0 in the batched form)                            */
+                                  /* (batched form: the level over all segments)        */
 } airg_level_info;
 
 

@@ -281,5 +281,11 @@ int64_t vcycle_bytes(const Hier &H, int vbytes);
 int64_t vcycle_nnz(const Hier &H);
 void complexities(const Hier &H, double *grid, double *op, double *storage);
 int64_t spmv_bytes(int64_t rows, int64_t cols, int64_t nnz, int vbytes, bool reads_y);
+// Algorithmic bytes of the setup steps (each reads its inputs and writes its
+// outputs once): an FP64 CSR matrix, the polynomial's coefficients on an
+// F-block (m products, one TSQR pass) and the CF splitting of a level.
+int64_t csr_bytes(const CsrView &M);
+int64_t poly_bytes(const CsrView &Aff, int m);
+int64_t split_bytes(const CsrView &A);
 
 }  // namespace airg

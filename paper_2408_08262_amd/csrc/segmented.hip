@@ -183,6 +183,7 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             DBuf<int8_t> cf0((size_t)n, s);
             pmisr(view(L.A), G, h.p, o.pmisr_max_rounds, cf0.p, s);
             ddc(view(L.A), o.ddc_threshold, cf0.p, L.cf.p, nullptr, s);
+            L.setup_bytes += split_bytes(view(L.A));
         }
         std::vector<int32_t> bnd((size_t)3 * (na + 1));
         auto mark_and_rank = [&]() {
@@ -240,6 +241,9 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             for (size_t j = 0; j < tidx.size(); ++j) L.seg[tidx[j]].poly = P[j];
             L.AinvT = inverse_pattern(view(L.AT), o.poly_sparsity_order, s);
             poly_fixed_sparsity_seg(view(L.AT), view(L.AinvT), toff, P, L.AinvT.v.p, s);
+            // extraction of the terminal block, its polynomial, the assembly
+            L.setup_bytes += csr_bytes(view(L.A)) + csr_bytes(view(L.AT)) + poly_bytes(view(L.AT), mc) +
+                             csr_bytes(view(L.AT)) + csr_bytes(view(L.AinvT));
             tm.end();
         }
         if (c.nF + c.nC == 0) break;
@@ -251,6 +255,8 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         cf_index_lists(L.cf.p, L.rank.p, n, L.fidx.p, L.cidx.p, s);
         Csr Acf;
         extract_fc_blocks(view(L.A), L.cf.p, L.rank.p, c.nF, c.nC, L.Aff, L.Afc, Acf, s);
+        L.setup_bytes += csr_bytes(view(L.A)) + 5 * (int64_t)n + csr_bytes(view(L.Aff)) + csr_bytes(view(L.Afc)) +
+                         csr_bytes(view(Acf));
         tm.begin(AIRG_PHASE_POLY);
         foff.push_back(c.nF);
         {
@@ -260,11 +266,13 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             for (size_t j = 0; j < aidx.size(); ++j) L.seg[aidx[j]].poly = P[j];
             L.Ainv = inverse_pattern(view(L.Aff), o.poly_sparsity_order, s);
             poly_fixed_sparsity_seg(view(L.Aff), view(L.Ainv), foff, P, L.Ainv.v.p, s);
+            L.setup_bytes += poly_bytes(view(L.Aff), m) + csr_bytes(view(L.Aff)) + csr_bytes(view(L.Ainv));
         }
         tm.begin(AIRG_PHASE_RESTRICTOR);
         {
             Csr prod = spgemm(view(Acf), view(L.Ainv), s);
             L.Z = drop_rows(view(prod), o.drop_R, false, true, s);   // Z = -A_cf Ainv, dropped
+            L.setup_bytes += csr_bytes(view(Acf)) + csr_bytes(view(L.Ainv)) + 2 * csr_bytes(view(prod));
         }
         tm.begin(AIRG_PHASE_PROLONG);
         Csr P;
@@ -275,6 +283,11 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             Csr AP = spgemm(view(L.A), view(P), s);
             Csr RAP = spgemm(view(R), view(AP), s);
             next->A = drop_rows(view(RAP), o.drop_A, true, false, s);
+            // W and P from A; A P; R from Z; R (A P); the drop of R A P
+            L.setup_bytes += csr_bytes(view(L.A)) + 5 * (int64_t)n + csr_bytes(view(L.W)) + csr_bytes(view(P));
+            L.setup_bytes += csr_bytes(view(L.A)) + csr_bytes(view(P)) + csr_bytes(view(AP));
+            L.setup_bytes += csr_bytes(view(L.Z)) + csr_bytes(view(R));
+            L.setup_bytes += csr_bytes(view(R)) + csr_bytes(view(AP)) + 3 * csr_bytes(view(RAP));
         }
         tm.end();
         next->n = next->A.nr;
@@ -338,6 +351,7 @@ void segmented_stats(const SegHier &H, airg_stats *st) {
         const SegLevel &L = *lp;
         g += L.n;
         o += (double)L.A.nnz;
+        st->setup_bytes += L.setup_bytes;
         if (L.nF + L.nC > 0) {
             sc += (double)L.Ainv.nnz + (double)L.Aff.nnz + (double)L.Afc.nnz + (double)(L.Z.nnz + L.nC) +
                   (double)(L.W.nnz + L.nC);
@@ -391,6 +405,7 @@ void segmented_level_info(const SegHier &H, int32_t segment, int32_t level, airg
     info->poly_requested = e.poly.m;
     for (int k = 0; k < e.poly.m && k < 16; ++k) info->alpha[k] = e.poly.alpha[k];
     for (int k = 0; k < AIRG_PHASE_COUNT; ++k) info->setup_seconds[k] = L.phase[k];
+    info->setup_bytes = L.setup_bytes;   // the level's, over all segments
     if (h_cf) {
         if (e.terminal) std::memset(h_cf, CF_F, (size_t)e.n);
         else d2h(h_cf, L.cf.p + e.off, (size_t)e.n, s);

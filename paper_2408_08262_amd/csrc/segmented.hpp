@@ -35,6 +35,7 @@ struct SegLevel {
     DBuf<int32_t> perm, iperm;           // natural <-> level order [F | C | T]
     Csr AF, Rp, Pp;                      // solve operators of the active part (level order)
     double phase[AIRG_PHASE_COUNT] = {};  // setup device time of the level (all segments) by phase
+    int64_t setup_bytes = 0;             // algorithmic bytes of the level's setup steps (all segments)
 };
 
 struct SegHier {

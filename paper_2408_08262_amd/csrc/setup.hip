@@ -206,8 +206,6 @@ Csr assemble_inverse(const CsrView &A, const PolyInfo &P, int m, int order, hipS
     return X;
 }
 
-namespace {
-
 // FP64 CSR bytes of a matrix (row pointers, columns, values).
 int64_t csr_bytes(const CsrView &M) { return M.nnz * 12 + ((int64_t)M.nr + 1) * 4; }
 // The polynomial's coefficients on an n_F-row block: m products with A_ff
@@ -223,6 +221,8 @@ int64_t split_bytes(const CsrView &A) {
     const int64_t n = A.nr;
     return csr_bytes(A) + A.nnz + (A.nnz * 5 + (n + 1) * 4 + n) + (csr_bytes(A) + 2 * n) + 5 * n;
 }
+
+namespace {
 
 // Steps 2 and 7-11 of the recipe once the splitting is known.  The
 // prolongator and A P depend on the splitting only: with a Branch they are

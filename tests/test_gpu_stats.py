@@ -5,7 +5,8 @@ airg_vcycle_profile, through the C ABI:
   [Z I] and [W; I] once, [A_ff A_fc] and Ainv once per up smooth; on the
   coarsest level Ainv once and (A, Ainv) once per further coarse iteration)
   counted independently from the oracle's replay of the same hierarchy;
-* per-level setup times add up to the phase totals;
+* per-level setup times and setup bytes add up to the totals (single and
+  batched forms);
 * the cycle counters tell eager cycles from graph replays;
 * the per-level V-cycle profile covers every level."""
 import numpy as np
@@ -13,7 +14,7 @@ import pytest
 import torch
 
 import oracle as O
-from workloads import dg_square, p0_cube
+from workloads import batch as batch_problems, concat, dg_square, p0_cube
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +86,30 @@ def test_per_level_setup_times_add_up_and_profile_covers_levels():
     for prec in (32, 64):
         t = airg.airg_vcycle_profile(h, precision=prec, reps=3)
         assert len(t) == st["levels"] and all(x > 0.0 for x in t)
+
+
+def test_batched_setup_bytes_add_up_over_levels():
+    probs = batch_problems(count=5, lo=12, hi=40, nrhs=2)
+    rp, ci, val, b, offs, seeds = concat(probs)
+    A = airg.to_device(rp, ci, val)
+    h = airg.airg_setup(*A, airg.default_opts(outer=airg.OUTER_FGMRES, precond_precision=32),
+                        seg_offsets=offs, seg_seeds=seeds)
+    st = airg.airg_get_stats(h)
+    nnz0 = int(rp[-1])
+    tot = 0
+    for l in range(st["levels"]):
+        lv = None
+        for p in range(len(probs)):        # any segment present on level l reports the level's total
+            try:
+                lv = airg.airg_get_level(h, l, segment=p, with_cf=False)
+                break
+            except airg.AirgError:
+                continue
+        assert lv is not None, l
+        assert lv["setup_bytes"] > 0, l
+        tot += lv["setup_bytes"]
+    assert tot == st["setup_bytes"]
+    assert st["setup_bytes"] > 2 * 12 * nnz0     # the splitting alone reads A_0 twice
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
