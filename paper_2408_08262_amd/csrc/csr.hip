@@ -1120,6 +1120,83 @@ __global__ void k_finish_dots(const double *__restrict__ partial, int nb, int nv
     if (threadIdx.x == 0) out[j] = s;
 }
 
+// Gram-Schmidt pass fused with the next one's products: w -= V h, then
+// out[j] = dot(V_j, w) on the updated w, or (NORM) out[0] = dot(w, w).  V is
+// read once for both; the entries are visited as in k_multi_dot (the same
+// per-thread order and block tree; k_finish_dots adds the block partials), so
+// the sums are those of a separate update and product.  NV >= nvec bounds the unrolled vector loops: each thread keeps
+// the NV entries of a row of V in registers, two rows of the stride in flight.
+template <int NV, bool NORM>
+__global__ void __launch_bounds__(kRedThreads) k_gemv_fused(const double *__restrict__ V, int64_t ldv, int nvec,
+                                                            const double *__restrict__ h, double *__restrict__ w,
+                                                            int64_t n, double *__restrict__ partial) {
+    constexpr int NA = NORM ? 1 : NV;
+    const int nb = gridDim.x;
+    const int64_t step = (int64_t)nb * kRedThreads;
+    double hh[NV], acc[NA];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) hh[j] = j < nvec ? h[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+    auto row = [&](int64_t i, const double (&v)[NV]) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (j < nvec) s += v[j] * hh[j];
+        const double wi = w[i] + -1.0 * s;
+        w[i] = wi;
+        if constexpr (NORM) {
+            acc[0] += wi * wi;
+        } else {
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+                if (j < nvec) acc[j] += v[j] * wi;
+        }
+    };
+    int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+    for (; i + step < n; i += 2 * step) {
+        double a[NV], b[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            a[j] = j < nvec ? V[(int64_t)j * ldv + i] : 0.0;
+            b[j] = j < nvec ? V[(int64_t)j * ldv + i + step] : 0.0;
+        }
+        row(i, a);
+        row(i + step, b);
+    }
+    if (i < n) {
+        double a[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) a[j] = j < nvec ? V[(int64_t)j * ldv + i] : 0.0;
+        row(i, a);
+    }
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        if (j < (NORM ? 1 : nvec)) {
+            const double t = block_sum(acc[j]);
+            if (threadIdx.x == 0) partial[(int64_t)j * nb + blockIdx.x] = t;
+        }
+    }
+}
+
+constexpr int kMaxGsVectors = 32;
+template <bool NORM>
+static void gemv_fused(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n,
+                       double *d_out, hipStream_t s) {
+    AIRG_REQUIRE(nvec >= 1 && nvec <= kMaxGsVectors, ST_INVALID_ARG, "too many basis vectors");
+    const int nb = red_blocks(n);
+    const int nd = NORM ? 1 : nvec;
+    DBuf<double> part((size_t)nb * nd, s);
+    auto go = [&](auto kern) { kern<<<nb, kRedThreads, 0, s>>>(V, ldv, nvec, h_dev, w, n, part.p); };
+    if (nvec <= 4) go(k_gemv_fused<4, NORM>);
+    else if (nvec <= 8) go(k_gemv_fused<8, NORM>);
+    else if (nvec <= 16) go(k_gemv_fused<16, NORM>);
+    else go(k_gemv_fused<32, NORM>);
+    AIRG_LAUNCH_CHECK();
+    k_finish_dots<<<nd, kRedThreads, 0, s>>>(part.p, nb, nd, d_out);
+    AIRG_LAUNCH_CHECK();
+}
+
 void multi_dot_dev(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *d_out,
                    hipStream_t s) {
     int nb = red_blocks(n);
@@ -1128,6 +1205,16 @@ void multi_dot_dev(const double *V, int64_t ldv, int nvec, const double *w, int6
     AIRG_LAUNCH_CHECK();
     k_finish_dots<<<nvec, kRedThreads, 0, s>>>(part.p, nb, nvec, d_out);
     AIRG_LAUNCH_CHECK();
+}
+
+void gemv_sub_dots(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, double *d_out,
+                   hipStream_t s) {
+    gemv_fused<false>(V, ldv, nvec, h_dev, w, n, d_out, s);
+}
+
+void gemv_sub_norm(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, double *d_nn,
+                   hipStream_t s) {
+    gemv_fused<true>(V, ldv, nvec, h_dev, w, n, d_nn, s);
 }
 
 void multi_dot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *h_out, hipStream_t s) {

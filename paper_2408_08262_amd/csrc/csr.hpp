@@ -110,6 +110,14 @@ double nrm2(const double *x, int64_t n, hipStream_t s);
 void axpy(double a, const double *x, double *y, int64_t n, hipStream_t s);            // y += a x
 void scal_copy(double a, const double *x, double *y, int64_t n, hipStream_t s);       // y = a x
 void gemv_sub(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, hipStream_t s);
+// w -= V h, then d_out[j] = dot(V_j, w) for j < nvec (<= 32) on the updated w:
+// one pass over V, the sums equal to gemv_sub followed by multi_dot_dev.
+void gemv_sub_dots(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, double *d_out,
+                   hipStream_t s);
+// w -= V h, then d_nn[0] = dot(w, w): equal to gemv_sub followed by
+// multi_dot_dev(w, ., 1, w, ...); nvec <= 32.
+void gemv_sub_norm(const double *V, int64_t ldv, int nvec, const double *h_dev, double *w, int64_t n, double *d_nn,
+                   hipStream_t s);
 void gemv_add(const double *V, int64_t ldv, int nvec, const double *h_dev, double *x, int64_t n, hipStream_t s);
 void cast_d2f(const double *x, float *y, int64_t n, hipStream_t s);
 void cast_f2d(const float *x, double *y, int64_t n, hipStream_t s);

@@ -335,6 +335,8 @@ SolveResult solve_richardson(Hier &H, const double *b, double *x, double rtol, i
 // rotations on the host, true FP64 residual at every restart.  The
 // Gram-Schmidt coefficients and the new vector's norm stay on the device
 // until one readback per Arnoldi step brings all of them to the host.
+constexpr int kMaxFusedBasis = 32;   // basis vectors gemv_sub_dots takes
+
 SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int maxit) {
     TraceRange trace("airg solve: FGMRES");
     hipStream_t s = H.s;
@@ -368,11 +370,16 @@ SolveResult solve_fgmres(Hier &H, const double *b, double *x, double rtol, int m
             res.iterations++;
             spmv_top(A, zj, w, nullptr, SPMV_SET, s);
             double *d1 = hdev.p, *d2 = hdev.p + (m + 1), *dn = hdev.p + 2 * (m + 1);
-            multi_dot_dev(V.p, n, j + 1, w, n, d1, s);
-            gemv_sub(V.p, n, j + 1, d1, w, n, s);
-            multi_dot_dev(V.p, n, j + 1, w, n, d2, s);
-            gemv_sub(V.p, n, j + 1, d2, w, n, s);
-            multi_dot_dev(w, n, 1, w, n, dn, s);
+            multi_dot_dev(V.p, n, j + 1, w, n, d1, s);            // h1 = V^T w
+            if (j + 1 <= kMaxFusedBasis) {
+                gemv_sub_dots(V.p, n, j + 1, d1, w, n, d2, s);    // w -= V h1; h2 = V^T w
+                gemv_sub_norm(V.p, n, j + 1, d2, w, n, dn, s);    // w -= V h2; ||w||^2
+            } else {
+                gemv_sub(V.p, n, j + 1, d1, w, n, s);
+                multi_dot_dev(V.p, n, j + 1, w, n, d2, s);
+                gemv_sub(V.p, n, j + 1, d2, w, n, s);
+                multi_dot_dev(w, n, 1, w, n, dn, s);
+            }
             normalize_dev(w, dn, n, s);
             read_ints({reinterpret_cast<const int32_t *>(d1), reinterpret_cast<const int32_t *>(d2),
                        reinterpret_cast<const int32_t *>(dn)},

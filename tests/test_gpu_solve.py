@@ -206,3 +206,26 @@ def test_setup_under_memory_caps_fails_cleanly():
     h, _ = setup(P)
     x, info = airg.airg_solve(h, b, rtol=1e-10, max_it=100)
     assert info["converged"]
+
+
+def test_fgmres_long_restart_cycle_matches_oracle():
+    """FGMRES with a restart cycle longer than the 32 basis vectors the fused
+    Gram-Schmidt pass takes (the later Arnoldi steps of a cycle take the
+    separate update and products).  The whole operator is the coarsest level
+    (truncate_n above n) with a degree-6 polynomial iterated twice, a weak
+    preconditioner for transport: the solve takes about 95 iterations, two
+    restart cycles of up to 48 steps.  The oracle's FGMRES on the replayed
+    hierarchy (same coefficients) takes the same number of iterations within 2."""
+    P = dg_square(48)
+    kw = dict(truncate_n=P.n + 1, coarse_poly_order=6, coarse_iters=2)
+    h, opts = setup(P, outer=airg.OUTER_FGMRES, precond_precision=64, fgmres_restart=48, **kw)
+    b = torch.as_tensor(P.b, device="cuda")
+    x, info = airg.airg_solve(h, b, rtol=1e-10, max_it=400)
+    x = x.cpu().numpy()
+    rel = np.linalg.norm(P.b - O.spmv(csr_of(P), x)) / np.linalg.norm(P.b)
+    assert info["converged"] and rel <= 1e-10 * 1.0001, rel
+    assert info["iterations"] > 33, info["iterations"]
+    alphas = [airg.airg_get_level(h, 0, with_cf=False)["alpha"]]
+    H = O.Hierarchy(csr_of(P), O.default_params(seed=P.seed, **kw), alphas=alphas)
+    _, its, _ = H.fgmres(P.b, 1e-10, 400, restart=48)
+    assert abs(info["iterations"] - its) <= 2, (info["iterations"], its)
