@@ -328,15 +328,18 @@ def top_bytes(st, n, k=1):
 
 def outer_bytes(form, its, n, restart=30):
     """Vector traffic of the outer iterations around the cycles and top products: the casts and
-    permutations into and out of the cycle, FGMRES's classical Gram-Schmidt twice (read the basis
-    twice per pass, update w) and normalisation, or Richardson's update and norm."""
+    permutations into and out of the cycle, FGMRES's classical Gram-Schmidt twice in three passes
+    over the basis (the products; the first update fused with the second products; the second update
+    fused with the norm: 3 (j + 1) basis reads, w read three times and written twice) and the
+    normalisation (w read and written), or Richardson's update and norm."""
     if form == "fp64_richardson":
         return its * (24 + 8 + 40) * n
     cast = 32 if form == "fp32_fgmres" else 40
     tot = 0
     for i in range(its):
         j = i % restart
-        tot += (4 * (j + 1) + 8) * 8 * n + cast * n
+        nv = 3 * (j + 1) + 7 if j + 1 <= 32 else 4 * (j + 1) + 9
+        tot += nv * 8 * n + cast * n
     return tot
 
 
