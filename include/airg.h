@@ -96,7 +96,10 @@ typedef struct airg_opts {
     int32_t coarse_matrix_free;   /* 1: the coarse polynomial is applied as q(A) x by   */
                                   /* products with A instead of an assembled matrix     */
                                   /* (truncation subsection); not in the batched form   */
-    int32_t reserved_opts;
+    int32_t time_phases;          /* 1: time each setup phase per level on the device   */
+                                  /* (phase_seconds, airg_level_info.setup_seconds);    */
+                                  /* 0 (default): no timing events, which cost the      */
+                                  /* setup about 3%; those times then read 0            */
 } airg_opts;
 
 typedef struct airg_solve_info {

@@ -38,7 +38,7 @@ class Opts(C.Structure):
                 ("outer", C.c_int32), ("fgmres_restart", C.c_int32), ("seed", C.c_uint64),
                 ("build_adjoint", C.c_int32), ("onepoint_weight", C.c_int32), ("use_graph", C.c_int32),
                 ("autotune", C.c_int32), ("device_bytes_cap", C.c_int64),
-                ("coarse_matrix_free", C.c_int32), ("reserved_opts", C.c_int32)]
+                ("coarse_matrix_free", C.c_int32), ("time_phases", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

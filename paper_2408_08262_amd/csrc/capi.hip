@@ -69,6 +69,7 @@ void check_opts(const airg_opts &o) {
                  "poly_sparsity_order must be 1, 2 or 3");
     AIRG_REQUIRE(o.coarse_matrix_free == 0 || o.coarse_matrix_free == 1, ST_INVALID_ARG,
                  "coarse_matrix_free must be 0 or 1");
+    AIRG_REQUIRE(o.time_phases == 0 || o.time_phases == 1, ST_INVALID_ARG, "time_phases must be 0 or 1");
     AIRG_REQUIRE(o.down_smooths == 0, ST_INVALID_ARG, "only up F-point smoothing is implemented");
     AIRG_REQUIRE(o.up_smooths >= 0 && o.coarse_iters >= 1, ST_INVALID_ARG, "bad smoothing counts");
     AIRG_REQUIRE(o.precond_precision == 32 || o.precond_precision == 64, ST_INVALID_ARG,
@@ -285,6 +286,7 @@ airg_status airg_default_opts(airg_opts *o) {
     o->autotune = 0;
     o->device_bytes_cap = 0;
     o->coarse_matrix_free = 0;
+    o->time_phases = 0;
     return AIRG_OK;
 }
 

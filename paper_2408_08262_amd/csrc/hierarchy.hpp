@@ -109,6 +109,7 @@ inline const char *phase_name(int phase) {
 
 struct PhaseTimer {
     hipStream_t s;
+    bool on;   // off: phases still open and close roctx ranges, but record no events
     std::mutex mu;
     struct Span {
         int level, phase;
@@ -118,7 +119,7 @@ struct PhaseTimer {
     int cur = -1;
     int level = -1;
     hipEvent_t start = nullptr;
-    explicit PhaseTimer(hipStream_t st) : s(st) {}
+    PhaseTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
     ~PhaseTimer() {
         for (auto &t : spans) {
             release_event(t.a);
@@ -128,14 +129,20 @@ struct PhaseTimer {
     }
     void begin(int phase) {
         end();
-        start = pooled_event();
-        AIRG_HIP(hipEventRecord(start, s));
+        if (on) {
+            start = pooled_event();
+            AIRG_HIP(hipEventRecord(start, s));
+        }
         cur = phase;
         trace_push(phase_name(phase));
     }
     void end() {
         if (cur < 0) return;
         trace_pop();
+        if (!on) {
+            cur = -1;
+            return;
+        }
         hipEvent_t stop = pooled_event();
         AIRG_HIP(hipEventRecord(stop, s));
         std::lock_guard<std::mutex> lk(mu);
@@ -146,6 +153,10 @@ struct PhaseTimer {
     template <class F>
     void span_on(int phase, int lvl, hipStream_t st, F &&f) {
         TraceRange tr(phase_name(phase));
+        if (!on) {
+            f();
+            return;
+        }
         hipEvent_t a = pooled_event(), b = pooled_event();
         {
             std::lock_guard<std::mutex> lk(mu);

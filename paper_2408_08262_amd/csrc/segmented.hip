@@ -136,7 +136,7 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
     H->opt = o;
     H->s = s;
     H->nseg = (int)seg.size() - 1;
-    PhaseTimer tm(s);
+    PhaseTimer tm(s, o.time_phases != 0);
     {
         auto L0 = std::make_unique<SegLevel>();
         L0->n = A0.nr;

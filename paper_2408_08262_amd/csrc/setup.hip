@@ -692,7 +692,7 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
     H->opt = o;
     H->seed = seed;
     H->s = s;
-    PhaseTimer tm(s);
+    PhaseTimer tm(s, o.time_phases != 0);
     auto first = std::make_unique<Level>();
     first->n = A0.nr;
     first->A = std::move(A0);

@@ -6,7 +6,7 @@ airg_vcycle_profile, through the C ABI:
   coarsest level Ainv once and (A, Ainv) once per further coarse iteration)
   counted independently from the oracle's replay of the same hierarchy;
 * per-level setup times and setup bytes add up to the totals (single and
-  batched forms);
+  batched forms); the phase times are recorded only with time_phases set;
 * the cycle counters tell eager cycles from graph replays;
 * the per-level V-cycle profile covers every level."""
 import numpy as np
@@ -63,10 +63,30 @@ def test_vcycle_work_units_match_oracle_replay(name, kw):
         assert st["vcycle_index_bytes"] + vb * st["vcycle_nnz"] + vb * st["vcycle_vec_entries"] == st[key]
 
 
+def test_phase_times_are_recorded_only_when_asked():
+    P = dg_square(64)
+    A = airg.to_device(P.rowptr, P.col, P.val)
+    h = airg.airg_setup(*A, airg.default_opts(seed=P.seed))          # time_phases 0: no events
+    st = airg.airg_get_stats(h)
+    assert st["setup_seconds"] > 0.0 and all(v == 0.0 for v in st["phase_seconds"].values())
+    assert all(v == 0.0 for v in airg.airg_get_level(h, 0, with_cf=False)["setup_seconds"].values())
+    h1 = airg.airg_setup(*A, airg.default_opts(seed=P.seed, time_phases=1))
+    st1 = airg.airg_get_stats(h1)
+    assert st1["phase_seconds"]["cf"] > 0.0 and st1["phase_seconds"]["poly"] > 0.0
+    # the events change no result: the same hierarchy either way
+    for l in range(st["levels"]):
+        for key in ("A", "Ainv"):
+            m0 = airg.airg_get_level_matrix(h, l, key)
+            m1 = airg.airg_get_level_matrix(h1, l, key)
+            assert all(np.array_equal(x, y) for x, y in zip(m0[:3], m1[:3])), (l, key)
+    with pytest.raises(airg.AirgError):
+        airg.airg_setup(*A, airg.default_opts(seed=P.seed, time_phases=2))
+
+
 def test_per_level_setup_times_add_up_and_profile_covers_levels():
     P = dg_square(96)
     A = airg.to_device(P.rowptr, P.col, P.val)
-    h = airg.airg_setup(*A, airg.default_opts(seed=P.seed))
+    h = airg.airg_setup(*A, airg.default_opts(seed=P.seed, time_phases=1))
     st = airg.airg_get_stats(h)
     per = {k: 0.0 for k in st["phase_seconds"]}
     tot_bytes = 0
