@@ -74,15 +74,14 @@ __device__ inline void block_sum_vec(double (&v)[N], int cnt, double *sh /* [4][
 // -------------------------------------------------------------- TSQR leaf ---
 // Householder QR of a panel of `rows` (<= kQrRows) rows x cols (columns
 // scaled by `scale` when given) by one wavefront, the panel held in
-// registers: lane l owns rows l, l + 64, ... of every column.  After each
-// step the remaining columns move one register column to the left, so the
-// active column is always register column 0 and every register index is a
-// constant.  The reductions are DPP wave sums.  Row `col` of R is taken after
-// step col (alpha on the diagonal, or x0 when the column below is already
-// zero); R (cols x cols, upper triangular) is written column-major at out with
-// leading dimension ldo, through Rl (cols * cols doubles of LDS).  NC >= cols
-// is the compile-time register width, so that the column loops and the shift
-// cover no more than the panel's columns.
+// registers: lane l owns rows l, l + 64, ... of every column.  The column
+// loop is unrolled over the compile-time width NC >= cols, so every register
+// index is a constant and step col touches only the columns after it (a
+// triangular amount of work; no register shifts).  The reductions are DPP
+// wave sums, the independent ones of a step side by side.  Row `col` of R is
+// taken after step col (alpha on the diagonal, or x0 when the column below is
+// already zero); R (cols x cols, upper triangular) is written column-major at
+// out with leading dimension ldo, through Rl (cols * cols doubles of LDS).
 template <int NC>
 __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t ldk, int64_t r0, int rows, int cols,
                          const double *__restrict__ scale, double *__restrict__ out, int64_t ldo,
@@ -102,14 +101,15 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
     }
     for (int idx = lane; idx < cols * cols; idx += kQrLanes) Rl[idx] = 0.0;
     wave_sync();
-    for (int col = 0; col < cols; ++col) {
-        const int left = cols - col;   // active register columns 0 .. left-1
+#pragma clang loop unroll(full)
+    for (int col = 0; col < NC; ++col) {
+        if (col >= cols) continue;   // uniform
         double part = 0.0;
 #pragma unroll
         for (int j = 0; j < RPL; ++j)
-            if (lane + j * kQrLanes >= col) part += W[j][0] * W[j][0];
+            if (lane + j * kQrLanes >= col) part += W[j][col] * W[j][col];
         const double nx2 = wave_sum_f64(part);
-        const double x0 = readlane_f64(W[0][0], col);   // row col: lane col (cols <= 64)
+        const double x0 = readlane_f64(W[0][col], col);   // row col: lane col (cols <= 64)
         const double nx = sqrt(nx2);
         const double alpha = x0 >= 0.0 ? -nx : nx;
         const double vv = 2.0 * nx * (nx + fabs(x0));
@@ -119,23 +119,22 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
 #pragma unroll
             for (int j = 0; j < RPL; ++j) {
                 const int r = lane + j * kQrLanes;
-                v[j] = r == col ? x0 - alpha : (r > col ? W[j][0] : 0.0);
+                v[j] = r == col ? x0 - alpha : (r > col ? W[j][col] : 0.0);
             }
-            // the dot products of every register column, then their wave
-            // sums side by side (independent reductions overlap); columns
-            // at or past `left` are discarded
+            // the dot products of the columns after col, then their wave
+            // sums side by side (independent reductions overlap)
             double d[NC];
 #pragma unroll
-            for (int c = 1; c < NC; ++c) {
+            for (int c = col + 1; c < NC; ++c) {
                 d[c] = 0.0;
 #pragma unroll
                 for (int j = 0; j < RPL; ++j) d[c] += v[j] * W[j][c];
             }
 #pragma unroll
-            for (int c = 1; c < NC; ++c) d[c] = wave_sum_f64(d[c]);
+            for (int c = col + 1; c < NC; ++c) d[c] = wave_sum_f64(d[c]);
 #pragma unroll
-            for (int c = 1; c < NC; ++c) {
-                if (c < left) {
+            for (int c = col + 1; c < NC; ++c) {
+                if (c < cols) {
                     const double f = 2.0 * d[c] / vv;
 #pragma unroll
                     for (int j = 0; j < RPL; ++j) W[j][c] -= f * v[j];
@@ -143,20 +142,16 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
             }
             diag = alpha;
         }
-        // row col of R: lane t < left takes entry (col, col + t)
+        // row col of R: lane t < cols - col takes entry (col, col + t)
         double mine = diag;
 #pragma unroll
-        for (int c = 1; c < NC; ++c) {
-            if (c < left) {
+        for (int c = col + 1; c < NC; ++c) {
+            if (c < cols) {
                 const double t = readlane_f64(W[0][c], col);
-                if (lane == c) mine = t;
+                if (lane == c - col) mine = t;
             }
         }
-        if (lane < left) Rl[(col + lane) * cols + col] = mine;
-#pragma unroll
-        for (int c = 0; c + 1 < NC; ++c)
-#pragma unroll
-            for (int j = 0; j < RPL; ++j) W[j][c] = W[j][c + 1];
+        if (lane < cols - col) Rl[(col + lane) * cols + col] = mine;
     }
     wave_sync();
     for (int idx = lane; idx < cols * cols; idx += kQrLanes) {
@@ -164,9 +159,6 @@ __device__ __forceinline__ void qr_panel(const double *__restrict__ K, int64_t l
         out[(int64_t)c * ldo + r] = Rl[idx];
     }
 }
-
-// Leaf b takes rows b*kQrRows.. of K; its R is rows b*cols.. of the next
-// (column-major) stacked matrix.
 template <int NC>
 __global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf(const double *__restrict__ K, int64_t n, int64_t ldk,
                                                         int cols, const double *__restrict__ scale,
