@@ -790,7 +790,7 @@ def main():
     if a.record_traffic:
         return record_traffic(a.workload, a.record_traffic)
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no sharding, no collectives); "
+        print("bench.py: the library runs on one GPU only (no sharding, no collectives); "
               "--gpus %d is not supported" % a.gpus, file=sys.stderr)
         return 2
     import torch

@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kQrLanes) k_tsqr_leaf(const double *__restrict
 struct QrLeaf {
     int64_t r0;      // first row in the source
     int32_t rows;
-    int32_t seg;     // scale row (round 0), else unused
+    int32_t seg;     // scale row (first tree level), else unused
     int64_t out;     // first row in the stacked output
     int32_t fin;
     int32_t pad;
@@ -359,7 +359,7 @@ void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, doub
     AIRG_REQUIRE(cols >= 1 && cols <= kMaxPolyCols, ST_INVALID_ARG, "polynomial order too large");
     const int nseg = (int)off.size() - 1;
     const int64_t n = off[nseg];
-    // round 0 leaves: the segments' own row blocks
+    // first tree level: the segments' own row blocks
     std::vector<QrLeaf> leaves;
     std::vector<int32_t> first(nseg + 1, 0);
     std::vector<int64_t> rows0(nseg), start0(nseg);
@@ -384,7 +384,7 @@ void tsqr_r_seg(const double *K, const std::vector<int32_t> &off, int cols, doub
     double *norm = normout.p + (size_t)nseg * cols * cols;
     k_colsq_seg_finish<<<grid_for((int64_t)nseg * cols, 256), 256, 0, s>>>(part.p, dfirst.p, nseg, cols, norm, inv.p);
     AIRG_LAUNCH_CHECK();
-    // rounds: every unfinished segment's rows -> one R per leaf, stacked
+    // further tree levels: every unfinished segment's rows -> one R per leaf, stacked
     std::vector<int64_t> rows = rows0, start = start0;
     std::vector<char> done(nseg, 0);
     const double *src = K;
