@@ -334,12 +334,17 @@ __global__ void k_scan_bsums(ScanSet S) {
     if (threadIdx.x == 0) bsum[nb] = tot;
 }
 
+__device__ inline int scan_slot(int p) { return p + (p >> 5); }   // pads out LDS bank conflicts
+
 // Block b scans its tile and adds the sums of the blocks before it: with
 // SUMS_SCANNED bsum[b] already holds them (k_scan_bsums ran); otherwise the
 // block reduces bsum[0..b) itself (few, L2-resident values), which saves the
-// separate pass.  The last block writes out[n] and the total at bsum[nb].
+// separate pass.  The tile moves through LDS both ways, so that the loads and
+// stores are coalesced while each thread scans kScanItems consecutive
+// entries.  The last block writes out[n] and the total at bsum[nb].
 template <bool SUMS_SCANNED>
-__global__ void k_scan_final(ScanSet S) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_final(ScanSet S) {
+    __shared__ int32_t buf[kScanTile + kScanTile / 32];
     const int r = blockIdx.y;
     const int32_t *in = S.in[r];
     int32_t *out = S.out[r];
@@ -347,36 +352,48 @@ __global__ void k_scan_final(ScanSet S) {
     int64_t *bsum = S.bsum[r];
     const int64_t nb = scan_tiles(n);
     if ((int64_t)blockIdx.x >= nb) return;
+    const int tid = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int p = j * kScanThreads + tid;
+        buf[scan_slot(p)] = t0 + p < n ? in[t0 + p] : 0;
+    }
     int64_t before;
     if (SUMS_SCANNED) {
         before = bsum[blockIdx.x];
     } else {
         int64_t part = 0;
-        for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) part += bsum[i];
-        block_exclusive_scan(part, &before);
+        for (int64_t i = tid; i < (int64_t)blockIdx.x; i += kScanThreads) part += bsum[i];
+        block_exclusive_scan(part, &before);   // its barriers also complete the tile's LDS stores
     }
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    __syncthreads();
     int32_t v[kScanItems];
     int64_t s = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        v[k] = i < n ? in[i] : 0;
+        v[k] = buf[scan_slot(tid * kScanItems + k)];
         s += v[k];
     }
     int64_t tot;
     int64_t off = block_exclusive_scan(s, &tot) + before;
-    // next sampled position at or after base
-    const int64_t st = S.sstride[r], ns = S.nsamp[r];
-    int64_t q = ns > 0 ? (base + st - 1) / st : 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        if (i < n) {
-            out[i] = (int32_t)off;
-            if (q < ns && i == q * st) S.samp[r][q++] = (int32_t)off;
-        }
+        buf[scan_slot(tid * kScanItems + k)] = (int32_t)off;
         off += v[k];
     }
-    if ((int64_t)blockIdx.x == nb - 1 && threadIdx.x == 0) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int p = j * kScanThreads + tid;
+        if (t0 + p < n) out[t0 + p] = buf[scan_slot(p)];
+    }
+    if (S.nsamp[r] > 0) {   // sampled positions inside [t0, min(t0 + tile, n))
+        const int64_t st = S.sstride[r], hi = t0 + kScanTile < n ? t0 + kScanTile : n;
+        for (int64_t q = (t0 + st - 1) / st + tid; q < S.nsamp[r] && q * st < hi; q += kScanThreads)
+            S.samp[r][q] = buf[scan_slot((int)(q * st - t0))];
+    }
+    if ((int64_t)blockIdx.x == nb - 1 && tid == 0) {
         out[n] = (int32_t)(before + tot);
         sample_total(S, r, n, before + tot);
         if (!SUMS_SCANNED) bsum[nb] = before + tot;
@@ -391,8 +408,6 @@ constexpr int kSmallScanThreads = 1024;
 constexpr int kSmallScanItems = 8;
 constexpr int64_t kSmallScan = 16384;
 constexpr int64_t kTinyScan = 2048;   // up to this size a 256-thread workgroup
-
-__device__ inline int small_scan_slot(int p) { return p + (p >> 5); }   // pads out LDS bank conflicts
 
 template <int TH>
 __global__ void __launch_bounds__(TH) k_scan_small(ScanSet S) {
@@ -409,14 +424,14 @@ __global__ void __launch_bounds__(TH) k_scan_small(ScanSet S) {
 #pragma unroll
         for (int j = 0; j < kSmallScanItems; ++j) {
             int p = j * TH + tid;
-            buf[small_scan_slot(p)] = t0 + p < n ? in[t0 + p] : 0;
+            buf[scan_slot(p)] = t0 + p < n ? in[t0 + p] : 0;
         }
         __syncthreads();
         int32_t v[kSmallScanItems];
         int64_t s = 0;
 #pragma unroll
         for (int u = 0; u < kSmallScanItems; ++u) {
-            v[u] = buf[small_scan_slot(tid * kSmallScanItems + u)];
+            v[u] = buf[scan_slot(tid * kSmallScanItems + u)];
             s += v[u];
         }
         int64_t x = s;
@@ -433,19 +448,19 @@ __global__ void __launch_bounds__(TH) k_scan_small(ScanSet S) {
         }
 #pragma unroll
         for (int u = 0; u < kSmallScanItems; ++u) {
-            buf[small_scan_slot(tid * kSmallScanItems + u)] = (int32_t)off;
+            buf[scan_slot(tid * kSmallScanItems + u)] = (int32_t)off;
             off += v[u];
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kSmallScanItems; ++j) {
             int p = j * TH + tid;
-            if (t0 + p < n) out[t0 + p] = buf[small_scan_slot(p)];
+            if (t0 + p < n) out[t0 + p] = buf[scan_slot(p)];
         }
         if (S.nsamp[r] > 0) {   // sampled positions inside [t0, min(t0 + tile, n))
             const int64_t st = S.sstride[r], hi = t0 + kSmallScanTile < n ? t0 + kSmallScanTile : n;
             for (int64_t q = (t0 + st - 1) / st + tid; q < S.nsamp[r] && q * st < hi; q += TH)
-                S.samp[r][q] = buf[small_scan_slot((int)(q * st - t0))];
+                S.samp[r][q] = buf[scan_slot((int)(q * st - t0))];
         }
         carry += tot;
         __syncthreads();
