@@ -308,10 +308,15 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     }
     tm.begin(AIRG_PHASE_RESTRICTOR);
     {
-        Csr prod = planned ? spgemm_finish(view(Acf), view(Ainv), zplan, htot.data() + zoff, s)
+        // Z = -A_cf Ainv, dropped (in the planned form as its rows are written); its entry count is
+        // read with R A P's plan
+        DropArgs dz;
+        dz.tau = o.drop_R;
+        dz.sign = -1.0;
+        dz.keep_diag = 0;
+        Csr prod = planned ? spgemm_finish(view(Acf), view(Ainv), zplan, htot.data() + zoff, s, &dz)
                            : spgemm(view(Acf), view(Ainv), s);
-        // Z = -A_cf Ainv, dropped; its entry count is read with R A P's plan
-        Z = drop_rows_bound(view(prod), o.drop_R, false, true, s);
+        Z = planned ? drop_compact(prod, zplan.kcnt.p, true, s) : drop_rows_bound(view(prod), o.drop_R, false, true, s);
         // power basis (m products with A_ff), TSQR of the basis, assembly of
         // Ainv; Z's product and its drop (Z's size is bounded by the product's
         // until read below)
@@ -337,9 +342,13 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
         else read_ints({Z.rp.p + Z.nr}, {1}, h.data(), s);
         Z.nnz = h[0];
         R.nnz = Z.nnz + Z.nr;
-        Csr RAP = spgemm_finish(view(R), view(AP), plan, h.data() + 1, s);
+        DropArgs da;   // the drop of the coarse operator, as R A P's rows are written
+        da.tau = o.drop_A;
+        da.sign = 1.0;
+        da.keep_diag = 1;
+        Csr RAP = spgemm_finish(view(R), view(AP), plan, h.data() + 1, s, &da);
         // with a Branch the entry count is read by the next level's splitting
-        Ac = br ? drop_rows_bound(view(RAP), o.drop_A, true, false, s) : drop_rows(view(RAP), o.drop_A, true, false, s);
+        Ac = drop_compact(RAP, plan.kcnt.p, br != nullptr, s);
         // W and P from A; A P; R from Z; R (A P); the drop of R A P (A_c's
         // dropped count is counted as the product's, an upper bound)
         nb += csr_bytes(A) + 5 * (int64_t)n + csr_bytes(view(W)) + csr_bytes(view(P));

@@ -226,7 +226,8 @@ template <int G>
 __global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp,
                                                    const int32_t *__restrict__ aci,
                                                    const int32_t *__restrict__ brp, int32_t *__restrict__ ub,
-                                                   int8_t *__restrict__ bin, int32_t *__restrict__ cnt) {
+                                                   int8_t *__restrict__ bin, int32_t *__restrict__ cnt,
+                                                   int32_t *__restrict__ kcnt) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t i = (int32_t)(t / G);
     const int lane = group_lane<G>();
@@ -240,7 +241,8 @@ __global__ void __launch_bounds__(256) k_spgemm_ub(int32_t m, const int32_t *__r
     if (lane != 0) return;
     int32_t uc = u > 0x7fffffff ? 0x7fffffff : (int32_t)u;
     ub[i] = uc;
-    cnt[i] = 0;   // the symbolic pass counts into it
+    cnt[i] = 0;    // the symbolic pass counts into it
+    kcnt[i] = 0;   // a fused drop counts into it (rows with no product keep 0)
     bin[i] = uc == 0                            ? SB_EMPTY
              : uc <= 8                         ? SB_G4
              : uc <= 32                        ? SB_G8
@@ -316,7 +318,7 @@ __device__ inline void sort_in_lane(int32_t (&k)[E], double (&v)[E], int lane, i
 
 template <int G, int E>
 __device__ inline void group_sort_store(const int32_t *keys, const double *vals, int w, int32_t *__restrict__ oci,
-                                        double *__restrict__ ov) {
+                                        double *__restrict__ ov, int32_t row, const DropArgs &D) {
     const int lane = group_lane<G>();
     int32_t k[E];
     double v[E];
@@ -350,6 +352,39 @@ __device__ inline void group_sort_store(const int32_t *keys, const double *vals,
             }
         }
     }
+    if (D.kcnt) {
+        // lane l holds sorted entries l*E .. l*E+E-1: the kept ones, lane by
+        // lane, are the row's kept entries in column order
+        double mx = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (lane * E + e < w) mx = fmax(mx, fabs(v[e]));
+        const double thr = D.tau * group_max<G>(mx);
+        bool keep[E];
+        int mine = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            keep[e] = lane * E + e < w && ((D.keep_diag && k[e] == row) || fabs(v[e]) >= thr);
+            mine += keep[e];
+        }
+        int x = mine;   // inclusive scan of the kept counts over the group's lanes
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int y = __shfl_up(x, o, G);
+            if (lane >= o) x += y;
+        }
+        int pos = x - mine;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (keep[e]) {
+                oci[pos] = k[e];
+                ov[pos] = D.sign * v[e];
+                ++pos;
+            }
+        }
+        if (lane == G - 1) D.kcnt[row] = x;
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         int i = lane * E + e;
@@ -364,15 +399,16 @@ __device__ inline void group_sort_store(const int32_t *keys, const double *vals,
 // among the widths up to EMAX.
 template <int G, int EMAX>
 __device__ inline void group_sort_store_upto(const int32_t *keys, const double *vals, int w,
-                                             int32_t *__restrict__ oci, double *__restrict__ ov) {
+                                             int32_t *__restrict__ oci, double *__restrict__ ov, int32_t row,
+                                             const DropArgs &D) {
     if constexpr (EMAX > 1) {
         if (w > G * (EMAX / 2)) {
-            group_sort_store<G, EMAX>(keys, vals, w, oci, ov);
+            group_sort_store<G, EMAX>(keys, vals, w, oci, ov, row, D);
             return;
         }
-        group_sort_store_upto<G, EMAX / 2>(keys, vals, w, oci, ov);
+        group_sort_store_upto<G, EMAX / 2>(keys, vals, w, oci, ov, row, D);
     } else {
-        group_sort_store<G, 1>(keys, vals, w, oci, ov);
+        group_sort_store<G, 1>(keys, vals, w, oci, ov, row, D);
     }
 }
 
@@ -388,7 +424,7 @@ __global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__
                                                      const int32_t *__restrict__ brp,
                                                      const int32_t *__restrict__ bci,
                                                      const double *__restrict__ bv, const int32_t *__restrict__ crp,
-                                                     int32_t *__restrict__ cci, double *__restrict__ cv) {
+                                                     int32_t *__restrict__ cci, double *__restrict__ cv, DropArgs D) {
 #pragma clang fp contract(off)
     constexpr int NG = TPB / G;
     __shared__ int32_t Ks[NG][T];
@@ -434,7 +470,7 @@ __global__ void __launch_bounds__(TPB) k_spgemm_fill(const int32_t *__restrict__
     }
     int32_t base = crp[row];
     constexpr int EMAX = T / 2 / G < 1 ? 1 : T / 2 / G > 8 ? 8 : T / 2 / G;   // w <= T / 2
-    group_sort_store_upto<G, EMAX>(keys, vals, w, cci + base, cv + base);
+    group_sort_store_upto<G, EMAX>(keys, vals, w, cci + base, cv + base, row, D);
 }
 
 // ----------------------------------------------------------- block rows ---
@@ -468,7 +504,7 @@ __device__ void spgemm_block_row(int32_t row, int32_t *keys, double *vals, uint3
                                  const double *__restrict__ av, const int32_t *__restrict__ brp,
                                  const int32_t *__restrict__ bci, const double *__restrict__ bv,
                                  int32_t *__restrict__ cnt, const int32_t *__restrict__ crp,
-                                 int32_t *__restrict__ cci, double *__restrict__ cv) {
+                                 int32_t *__restrict__ cci, double *__restrict__ cv, const DropArgs &D) {
 #pragma clang fp contract(off)
     __shared__ int sh[kBlk / 64];
     for (uint32_t t = threadIdx.x; t < T; t += kBlk) {
@@ -544,6 +580,34 @@ __device__ void spgemm_block_row(int32_t row, int32_t *keys, double *vals, uint3
             __syncthreads();
         }
     }
+    if (D.kcnt) {
+        // the row's largest magnitude, then its kept entries packed in
+        // column order: thread t takes a contiguous chunk of the sorted row
+        __shared__ double shm[kBlk / 64];
+        double mx = 0.0;
+        for (int t = threadIdx.x; t < nz; t += kBlk) mx = fmax(mx, fabs(vals[t]));
+        mx = group_max<64>(mx);
+        if ((threadIdx.x & 63) == 0) shm[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        double m = 0.0;
+        for (int q = 0; q < kBlk / 64; ++q) m = fmax(m, shm[q]);
+        const double thr = D.tau * m;
+        const int per2 = (nz + kBlk - 1) / kBlk;
+        const int lo2 = (int)threadIdx.x * per2, hi2 = lo2 + per2 < nz ? lo2 + per2 : nz;
+        int mine2 = 0;
+        for (int t = lo2; t < hi2; ++t) mine2 += (D.keep_diag && keys[t] == row) || fabs(vals[t]) >= thr;
+        int kept;
+        int o2 = block_exclusive_count(mine2, &kept, sh);
+        for (int t = lo2; t < hi2; ++t) {
+            if ((D.keep_diag && keys[t] == row) || fabs(vals[t]) >= thr) {
+                cci[base + o2] = keys[t];
+                cv[base + o2] = D.sign * vals[t];
+                ++o2;
+            }
+        }
+        if (threadIdx.x == 0) D.kcnt[row] = kept;
+        return;
+    }
     for (int t = threadIdx.x; t < nz; t += kBlk) {
         cci[base + t] = keys[t];
         cv[base + t] = vals[t];
@@ -559,12 +623,12 @@ __global__ void __launch_bounds__(kBlk) k_spgemm_block_lds(const int32_t *__rest
                                                            const int32_t *__restrict__ bci,
                                                            const double *__restrict__ bv, int32_t *__restrict__ cnt,
                                                            const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
-                                                           double *__restrict__ cv) {
+                                                           double *__restrict__ cv, DropArgs D) {
     __shared__ int32_t keys[T];
     __shared__ double vals[NUMERIC ? T : 1];
     int64_t idx = blockIdx.x;
     if (idx >= count) return;
-    spgemm_block_row<NUMERIC>(list[idx], keys, vals, T, arp, aci, av, brp, bci, bv, cnt, crp, cci, cv);
+    spgemm_block_row<NUMERIC>(list[idx], keys, vals, T, arp, aci, av, brp, bci, bv, cnt, crp, cci, cv, D);
 }
 
 template <bool NUMERIC>
@@ -580,13 +644,14 @@ __global__ void __launch_bounds__(kBlk) k_spgemm_block_global(const int32_t *__r
                                                               const double *__restrict__ bv,
                                                               int32_t *__restrict__ cnt,
                                                               const int32_t *__restrict__ crp,
-                                                              int32_t *__restrict__ cci, double *__restrict__ cv) {
+                                                              int32_t *__restrict__ cci, double *__restrict__ cv,
+                                                              DropArgs D) {
     int64_t idx = blockIdx.x;
     if (idx >= count) return;
     int64_t o = toff[idx];
     uint32_t T = (uint32_t)(toff[idx + 1] - o);
     spgemm_block_row<NUMERIC>(list[idx], gkeys + o, NUMERIC ? gvals + o : nullptr, T, arp, aci, av, brp, bci, bv,
-                              cnt, crp, cci, cv);
+                              cnt, crp, cci, cv, D);
 }
 
 // -------------------------------------------------------- narrow rows ----
@@ -609,7 +674,7 @@ __global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *
                                                       const int32_t *__restrict__ bci,
                                                       const double *__restrict__ bv, int32_t *__restrict__ cnt,
                                                       const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
-                                                      double *__restrict__ cv) {
+                                                      double *__restrict__ cv, DropArgs D) {
 #pragma clang fp contract(off)
     __shared__ double acc[NUMERIC ? NC : 1];
     __shared__ uint8_t mark[NC];
@@ -688,26 +753,35 @@ __global__ void __launch_bounds__(64) k_spgemm_narrow(int32_t m, const int32_t *
         q0 += nq;
     }
     const int32_t base = NUMERIC ? crp[row] : 0;
+    double thr = 0.0;
+    if (NUMERIC && D.kcnt) {   // the row's largest magnitude, for the fused drop
+        double mx = 0.0;
+        for (int c = lane; c < NC; c += 64)
+            if (mark[c]) mx = fmax(mx, fabs(acc[c]));
+        thr = D.tau * group_max<64>(mx);
+    }
     int32_t w = 0;
     for (int c0 = 0; c0 < NC; c0 += 64) {
         const int c = c0 + lane;
-        const bool occ = mark[c] != 0;
+        bool occ = mark[c] != 0;
+        if (NUMERIC && D.kcnt) occ = occ && ((D.keep_diag && c == row) || fabs(acc[c]) >= thr);
         const uint64_t bm = __ballot(occ);
         if (NUMERIC && occ) {
             const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
             cci[base + pos] = c;
-            cv[base + pos] = acc[c];
+            cv[base + pos] = D.kcnt ? D.sign * acc[c] : acc[c];
         }
         w += __popcll(bm);
     }
     if (!NUMERIC && lane == 0) cnt[row] = w;
+    if (NUMERIC && D.kcnt && lane == 0) D.kcnt[row] = w;
 }
 
 constexpr int32_t kNarrowMaxCols = 4096;
 constexpr int64_t kNarrowMaxWork = (int64_t)1 << 24;   // rows x NC: the accumulator sweeps per product
 
 template <int NC>
-static Csr spgemm_narrow(const CsrView &A, const CsrView &Bm, hipStream_t s) {
+static Csr spgemm_narrow(const CsrView &A, const CsrView &Bm, hipStream_t s, const DropArgs &D) {
     Csr C;
     C.nr = A.nr;
     C.nc = Bm.nc;
@@ -716,7 +790,7 @@ static Csr spgemm_narrow(const CsrView &A, const CsrView &Bm, hipStream_t s) {
     DBuf<int32_t> cnt((size_t)m + 1, s);
     if (m > 0) {
         k_spgemm_narrow<NC, false><<<(unsigned)m, 64, 0, s>>>(m, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt.p,
-                                                                nullptr, nullptr, nullptr);
+                                                                nullptr, nullptr, nullptr, DropArgs{});
         AIRG_LAUNCH_CHECK();
     }
     C.nnz = exclusive_scan(cnt.p, C.rp.p, m, s);
@@ -724,8 +798,10 @@ static Csr spgemm_narrow(const CsrView &A, const CsrView &Bm, hipStream_t s) {
     C.v.alloc((size_t)C.nnz, s);
     if (C.nnz > 0) {
         k_spgemm_narrow<NC, true><<<(unsigned)m, 64, 0, s>>>(m, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, nullptr,
-                                                               C.rp.p, C.ci.p, C.v.p);
+                                                               C.rp.p, C.ci.p, C.v.p, D);
         AIRG_LAUNCH_CHECK();
+    } else if (D.kcnt && m > 0) {
+        fill_zero(D.kcnt, (size_t)m * sizeof(int32_t), s);   // no fill pass to count the kept entries
     }
     return C;
 }
@@ -837,7 +913,8 @@ void spgemm_on_pattern(const CsrView &A, const CsrView &Bm, const Csr &Pt, doubl
 }
 
 static void run_global(bool numeric, const Bins &B, int b, const std::vector<int32_t> &per_row, const CsrView &A,
-                       const CsrView &Bm, int32_t *cnt, const int32_t *crp, int32_t *cci, double *cv, hipStream_t s) {
+                       const CsrView &Bm, int32_t *cnt, const int32_t *crp, int32_t *cci, double *cv, hipStream_t s,
+                       const DropArgs &D = DropArgs{}) {
     // one table of 2 x per_row[r] slots (rounded up to a power of two) per row
     std::vector<int64_t> off(per_row.size() + 1, 0);
     for (size_t r = 0; r < per_row.size(); ++r) off[r + 1] = off[r] + pow2_at_least(2 * (int64_t)per_row[r]);
@@ -847,10 +924,11 @@ static void run_global(bool numeric, const Bins &B, int b, const std::vector<int
     DBuf<double> gv(numeric ? (size_t)off.back() : 1, s);
     if (numeric)
         k_spgemm_block_global<true><<<(unsigned)B.count(b), kBlk, 0, s>>>(
-            B.list(b), B.count(b), toff.p, gk.p, gv.p, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
+            B.list(b), B.count(b), toff.p, gk.p, gv.p, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv, D);
     else
         k_spgemm_block_global<false><<<(unsigned)B.count(b), kBlk, 0, s>>>(
-            B.list(b), B.count(b), toff.p, gk.p, gv.p, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
+            B.list(b), B.count(b), toff.p, gk.p, gv.p, A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv,
+            DropArgs{});
     AIRG_LAUNCH_CHECK();
 }
 
@@ -879,18 +957,19 @@ static void run_symbolic(const Bins &B, const CsrView &A, const CsrView &Bm, int
     grp(k_spgemm_count<64, 4096, 128>, SB_G64, 2, 128);
     if (B.count(SB_BLOCK))
         k_spgemm_block_lds<16384, false><<<(unsigned)B.count(SB_BLOCK), kBlk, 0, s>>>(
-            B.list(SB_BLOCK), B.count(SB_BLOCK), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, nullptr, nullptr, nullptr);
+            B.list(SB_BLOCK), B.count(SB_BLOCK), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, nullptr, nullptr, nullptr,
+            DropArgs{});
     AIRG_LAUNCH_CHECK();
     if (B.count(SB_GLOBAL))
         run_global(false, B, SB_GLOBAL, gather_bin(B, SB_GLOBAL, ub, m, s), A, Bm, cnt, nullptr, nullptr, nullptr, s);
 }
 
 static void run_numeric(const Bins &B, const CsrView &A, const CsrView &Bm, int32_t *cnt, const int32_t *crp,
-                        int32_t *cci, double *cv, int32_t m, hipStream_t s) {
+                        int32_t *cci, double *cv, int32_t m, hipStream_t s, const DropArgs &D) {
     auto grp = [&](auto kern, int b, int rows_per_block, unsigned tpb) {
         if (B.count(b))
             kern<<<grid_for(B.count(b), rows_per_block), tpb, 0, s>>>(B.list(b), B.count(b), A.rp, A.ci, A.v,
-                                                                      Bm.rp, Bm.ci, Bm.v, crp, cci, cv);
+                                                                      Bm.rp, Bm.ci, Bm.v, crp, cci, cv, D);
     };
     grp(k_spgemm_fill<4, 16, 256>, NB_G4, 64, 256);
     grp(k_spgemm_fill<8, 64, 256>, NB_G8, 32, 256);
@@ -900,13 +979,13 @@ static void run_numeric(const Bins &B, const CsrView &A, const CsrView &Bm, int3
     grp(k_spgemm_fill<64, 1024, 64>, NB_G64, 1, 64);
     if (B.count(NB_BLOCK4K))
         k_spgemm_block_lds<4096, true><<<(unsigned)B.count(NB_BLOCK4K), kBlk, 0, s>>>(
-            B.list(NB_BLOCK4K), B.count(NB_BLOCK4K), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
+            B.list(NB_BLOCK4K), B.count(NB_BLOCK4K), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv, D);
     if (B.count(NB_BLOCK8K))
         k_spgemm_block_lds<8192, true><<<(unsigned)B.count(NB_BLOCK8K), kBlk, 0, s>>>(
-            B.list(NB_BLOCK8K), B.count(NB_BLOCK8K), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv);
+            B.list(NB_BLOCK8K), B.count(NB_BLOCK8K), A.rp, A.ci, A.v, Bm.rp, Bm.ci, Bm.v, cnt, crp, cci, cv, D);
     AIRG_LAUNCH_CHECK();
     if (B.count(NB_GLOBAL))
-        run_global(true, B, NB_GLOBAL, gather_bin(B, NB_GLOBAL, cnt, m, s), A, Bm, cnt, crp, cci, cv, s);
+        run_global(true, B, NB_GLOBAL, gather_bin(B, NB_GLOBAL, cnt, m, s), A, Bm, cnt, crp, cci, cv, s, D);
 }
 
 static bool narrow_shape(int32_t m, int32_t bnc, int *nc) {
@@ -931,9 +1010,11 @@ SpgemmPlan spgemm_begin(const CsrView &A, const int32_t *b_rp, int32_t b_nc, hip
     P.ub.alloc((size_t)m + 1, s);
     P.sbin.alloc((size_t)m + 1, s);
     P.cnt.alloc((size_t)m + 1, s);
+    P.kcnt.alloc((size_t)m + 1, s);
     if (m > 0) {
         dispatch_group(lanes_for(A.nnz, m), [&]<int G>() {
-            k_spgemm_ub<G><<<grid_for((int64_t)m * G, 256), 256, 0, s>>>(m, A.rp, A.ci, b_rp, P.ub.p, P.sbin.p, P.cnt.p);
+            k_spgemm_ub<G><<<grid_for((int64_t)m * G, 256), 256, 0, s>>>(m, A.rp, A.ci, b_rp, P.ub.p, P.sbin.p, P.cnt.p,
+                                                                        P.kcnt.p);
         });
         AIRG_LAUNCH_CHECK();
     }
@@ -941,14 +1022,21 @@ SpgemmPlan spgemm_begin(const CsrView &A, const int32_t *b_rp, int32_t b_nc, hip
     return P;
 }
 
-Csr spgemm_finish(const CsrView &A, const CsrView &Bm, SpgemmPlan &P, const int32_t *h_tot, hipStream_t s) {
+Csr spgemm_finish(const CsrView &A, const CsrView &Bm, SpgemmPlan &P, const int32_t *h_tot, hipStream_t s,
+                  const DropArgs *drop) {
     AIRG_REQUIRE(A.nc == Bm.nr && P.m == A.nr && P.bnc == Bm.nc, ST_INVALID_ARG, "product plan does not match");
+    DropArgs D;
+    if (drop) {
+        D = *drop;
+        if (!P.kcnt.p) P.kcnt.alloc((size_t)A.nr + 1, s);   // narrow plans: every row is filled, no clearing
+        D.kcnt = P.kcnt.p;
+    }
     if (P.narrow) {
         int nc;
         narrow_shape(A.nr, Bm.nc, &nc);
-        if (nc == 1024) return spgemm_narrow<1024>(A, Bm, s);
-        if (nc == 2048) return spgemm_narrow<2048>(A, Bm, s);
-        return spgemm_narrow<4096>(A, Bm, s);
+        if (nc == 1024) return spgemm_narrow<1024>(A, Bm, s, D);
+        if (nc == 2048) return spgemm_narrow<2048>(A, Bm, s, D);
+        return spgemm_narrow<4096>(A, Bm, s, D);
     }
     Csr C;
     C.nr = A.nr;
@@ -970,8 +1058,48 @@ Csr spgemm_finish(const CsrView &A, const CsrView &Bm, SpgemmPlan &P, const int3
     C.v.alloc((size_t)C.nnz, s);
     if (C.nnz == 0) return C;
     Bins NB = bin_rows_end(NP, h.data() + 1, s);
-    run_numeric(NB, A, Bm, cnt.p, C.rp.p, C.ci.p, C.v.p, m, s);
+    run_numeric(NB, A, Bm, cnt.p, C.rp.p, C.ci.p, C.v.p, m, s, D);
     return C;
+}
+
+// Row r's first kcnt[r] entries of C moved to its place in the packed matrix.
+template <int G>
+__global__ void __launch_bounds__(256) k_drop_pack(int32_t n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                   const int32_t *__restrict__ orp, int32_t *__restrict__ oci,
+                                                   double *__restrict__ ov) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t row = (int32_t)(t / G);
+    const int lane = group_lane<G>();
+    if (row >= n) return;
+    const int32_t b = rp[row], w = orp[row], kept = orp[row + 1] - w;
+    for (int32_t k = lane; k < kept; k += G) {
+        oci[w + k] = ci[b + k];
+        ov[w + k] = v[b + k];
+    }
+}
+
+Csr drop_compact(const Csr &C, const int32_t *kcnt, bool bound, hipStream_t s) {
+    Csr B;
+    B.nr = C.nr;
+    B.nc = C.nc;
+    B.rp.alloc((size_t)C.nr + 1, s);
+    if (bound) {
+        exclusive_scan(kcnt, B.rp.p, C.nr, s, false);
+        B.nnz = C.nnz;
+    } else {
+        B.nnz = exclusive_scan(kcnt, B.rp.p, C.nr, s);
+    }
+    B.ci.alloc((size_t)B.nnz, s);
+    B.v.alloc((size_t)B.nnz, s);
+    if (C.nr > 0 && C.nnz > 0) {
+        dispatch_group(lanes_for(C.nnz, C.nr), [&]<int G>() {
+            k_drop_pack<G><<<grid_for((int64_t)C.nr * G, 256), 256, 0, s>>>(C.nr, C.rp.p, C.ci.p, C.v.p, B.rp.p,
+                                                                            B.ci.p, B.v.p);
+        });
+        AIRG_LAUNCH_CHECK();
+    }
+    return B;
 }
 
 Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
