@@ -270,9 +270,14 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         }
         tm.begin(AIRG_PHASE_RESTRICTOR);
         {
-            Csr prod = spgemm(view(Acf), view(L.Ainv), s);
-            L.Z = drop_rows(view(prod), o.drop_R, false, true, s);   // Z = -A_cf Ainv, dropped
-            L.setup_bytes += csr_bytes(view(Acf)) + csr_bytes(view(L.Ainv)) + 2 * csr_bytes(view(prod));
+            DropArgs dz;   // Z = -A_cf Ainv, dropped as its rows are written
+            dz.tau = o.drop_R;
+            dz.sign = -1.0;
+            dz.keep_diag = 0;
+            int64_t pz = 0;
+            L.Z = spgemm_drop(view(Acf), view(L.Ainv), dz, s, &pz);
+            // the product and its drop as two steps: the product written and read back whole
+            L.setup_bytes += csr_bytes(view(Acf)) + csr_bytes(view(L.Ainv)) + 2 * (pz * 12 + ((int64_t)L.Z.nr + 1) * 4);
         }
         tm.begin(AIRG_PHASE_PROLONG);
         Csr P;
@@ -281,13 +286,17 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         {
             Csr R = restriction_full(view(L.Z), L.fidx.p, L.cidx.p, n, s);
             Csr AP = spgemm(view(L.A), view(P), s);
-            Csr RAP = spgemm(view(R), view(AP), s);
-            next->A = drop_rows(view(RAP), o.drop_A, true, false, s);
+            DropArgs da;   // the coarse operator, dropped as its rows are written
+            da.tau = o.drop_A;
+            da.sign = 1.0;
+            da.keep_diag = 1;
+            int64_t pa = 0;
+            next->A = spgemm_drop(view(R), view(AP), da, s, &pa);
             // W and P from A; A P; R from Z; R (A P); the drop of R A P
             L.setup_bytes += csr_bytes(view(L.A)) + 5 * (int64_t)n + csr_bytes(view(L.W)) + csr_bytes(view(P));
             L.setup_bytes += csr_bytes(view(L.A)) + csr_bytes(view(P)) + csr_bytes(view(AP));
             L.setup_bytes += csr_bytes(view(L.Z)) + csr_bytes(view(R));
-            L.setup_bytes += csr_bytes(view(R)) + csr_bytes(view(AP)) + 3 * csr_bytes(view(RAP));
+            L.setup_bytes += csr_bytes(view(R)) + csr_bytes(view(AP)) + 3 * (pa * 12 + ((int64_t)R.nr + 1) * 4);
         }
         tm.end();
         next->n = next->A.nr;

@@ -1102,6 +1102,17 @@ Csr drop_compact(const Csr &C, const int32_t *kcnt, bool bound, hipStream_t s) {
     return B;
 }
 
+Csr spgemm_drop(const CsrView &A, const CsrView &Bm, const DropArgs &drop, hipStream_t s, int64_t *product_nnz) {
+    AIRG_REQUIRE(A.nc == Bm.nr, ST_INVALID_ARG, "inner dimensions differ");
+    SpgemmPlan P = spgemm_begin(A, Bm.rp, Bm.nc, s);
+    auto [src, cnt] = P.totals();
+    std::vector<int32_t> h((size_t)std::max(cnt, 1));
+    if (cnt > 0) d2h(h.data(), src, (size_t)cnt, s);
+    Csr C = spgemm_finish(A, Bm, P, h.data(), s, &drop);
+    if (product_nnz) *product_nnz = C.nnz;
+    return drop_compact(C, P.kcnt.p, false, s);
+}
+
 Csr spgemm(const CsrView &A, const CsrView &Bm, hipStream_t s) {
     AIRG_REQUIRE(A.nc == Bm.nr, ST_INVALID_ARG, "inner dimensions differ");
     SpgemmPlan P = spgemm_begin(A, Bm.rp, Bm.nc, s);

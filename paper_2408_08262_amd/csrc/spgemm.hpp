@@ -45,6 +45,11 @@ Csr spgemm_finish(const CsrView &A, const CsrView &B, SpgemmPlan &P, const int32
 // rows' kept counts scanned, their entries copied.  bound: no readback, the
 // result's nnz is only the product's (its row pointer holds the exact count).
 Csr drop_compact(const Csr &C, const int32_t *kcnt, bool bound, hipStream_t s);
+// The dropped product in one call: spgemm with the drop fused, then packed
+// (exact entry count); *product_nnz (nullable) receives the undropped
+// product's entry count.
+Csr spgemm_drop(const CsrView &A, const CsrView &B, const DropArgs &drop, hipStream_t s,
+                int64_t *product_nnz = nullptr);
 
 // out_v (Pt.nnz values, Pt's order) = sign * (A B) at the stored positions of
 // the pattern Pt (Pt.nr == A.nr; rows sorted, at most 4096 entries); entries
