@@ -465,16 +465,25 @@ std::vector<PolyInfo> gmres_poly_seg(const CsrView &A, const std::vector<int32_t
 
 // --------------------------------------------- fixed-sparsity assembly ----
 // One G-lane group per row (L = row length <= G).  M_i = A(J_i, J_i) is built
-// in LDS: the positions of J_i go into a small LDS hash (column -> position),
-// and each lane looks up the columns of its gathered row there (independent
-// lookups, four loads in flight); then v_k = v_{k-1} M_i with lane a owning
-// column a, the sum over p ascending.  The terms of that sum are broadcast
-// from the lanes that own them (a lane read for a whole-wavefront group,
-// through LDS otherwise) and their loads are issued eight at a time ahead of
-// the additions, which stay in ascending p.
-template <int G>
-__device__ inline uint32_t poly_hash(int32_t c) {
-    return ((uint32_t)c * 2654435761u) & (2 * G - 1);
+// in LDS: the pairs (column, position) of J_i go into a small LDS hash of
+// two-slot buckets (4G slots for groups of 32 lanes, 2G otherwise; a key
+// goes to the first bucket from its home with a free slot, so a lookup ends
+// at the first bucket that holds it or has a free slot).  The group then
+// reads the gathered rows A(J_i[p], :) in batches of rows, lane t taking
+// entries t, t + G, ... of each row, and looks every column up.  The lookups
+// of a batch probe in step: one round reads the current bucket of every row
+// of the batch (independent LDS reads behind one wait), so a batch costs as
+// many LDS round trips as its longest probe sequence.  Then
+// v_k = v_{k-1} M_i with lane a owning column a of M_i in registers, the sum
+// over p ascending; v_{k-1} is broadcast through LDS, two entries per read.
+// Over the earlier form (each lane walking its own gathered row, M_i read
+// from LDS in the powers, x broadcast by lane reads) this takes the coarsest
+// dg_square_512 assembly from 0.67 to 0.47 ms.
+template <int NB>
+__device__ inline uint32_t poly_hash(int32_t c) {   // multiplicative hash, top bits
+    constexpr int kBits = __builtin_ctz(NB);
+    static_assert(NB >= 2 && (NB & (NB - 1)) == 0, "a power-of-two bucket count");
+    return ((uint32_t)c * 2654435761u) >> (32 - kBits);
 }
 
 // MS (<= G): the rows of the launch have at most MS entries, and M_i is
@@ -489,10 +498,11 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
 #pragma clang fp contract(off)
     static_assert(MS <= G, "row capacity above the group width");
     constexpr int NG = TPB / G;
+    constexpr int NB = G == 32 ? 2 * G : G;   // hash buckets of two slots
+    constexpr uint32_t kHM = NB - 1;
     __shared__ double Ms[NG][MS * MS];
-    __shared__ double Xs[NG][G];
-    __shared__ int32_t Hk[NG][2 * G];
-    __shared__ int32_t Hp[NG][2 * G];
+    __shared__ __align__(16) double Xs[NG][G];
+    __shared__ int4 Hs[NG][NB];   // (column, position) x 2; column -1 marks an empty slot
     int gid = threadIdx.x / G;
     int lane = group_lane<G>();
     int64_t idx = (int64_t)blockIdx.x * NG + gid;
@@ -502,86 +512,116 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     int32_t L = prp[row + 1] - b;
     double *M = Ms[gid];
     double *X = Xs[gid];
-    int32_t *hk = Hk[gid];
-    int32_t *hp = Hp[gid];
+    int4 *H = Hs[gid];
     const int32_t myc = lane < L ? pci[b + lane] : -1;
-    for (int t = lane; t < 2 * G; t += G) hk[t] = -1;
+    const int32_t rb = lane < L ? rp[myc] : 0;       // extent of the gathered row J_i[lane]
+    const int32_t re = lane < L ? rp[myc + 1] : 0;
+    for (int t = lane; t < NB; t += G) H[t] = make_int4(-1, 0, -1, 0);
     for (int t = lane; t < MS * MS; t += G) M[t] = 0.0;
     wave_sync();
     if (lane < L) {   // columns are distinct: each claims its own slot
-        uint32_t h = poly_hash<G>(myc);
-        while (atomicCAS(&hk[h], -1, myc) != -1) h = (h + 1) & (2 * G - 1);
-        hp[h] = lane;
+        uint32_t h = poly_hash<NB>(myc);
+        for (;;) {   // L <= G < 2 NB keys: a free slot remains
+            if (atomicCAS(&H[h].x, -1, myc) == -1) {
+                H[h].y = lane;
+                break;
+            }
+            if (atomicCAS(&H[h].z, -1, myc) == -1) {
+                H[h].w = lane;
+                break;
+            }
+            h = (h + 1) & kHM;
+        }
     }
     wave_sync();
-    if (lane < L) {
-        // row J[lane] of A against J_i, its entries loaded four at a time
-        const int32_t r = myc;
-        const int32_t ke = rp[r + 1];
-        for (int32_t kk = rp[r]; kk < ke; kk += 4) {
-            int32_t c4[4];
-            double v4[4];
+    // row p of M_i is row J_i[p] of A against J_i; a row's columns are
+    // distinct, so its lanes write distinct entries.  The first G entries of
+    // RB rows are loaded before any is looked up; entries past G (rows
+    // longer than the group) take a pass of their own.  The pad rows p >= L
+    // have the empty extent [0, 0).
+    constexpr int RB = MS <= 4 ? MS : MS <= 8 ? 4 : MS <= 24 ? 8 : 16;
+    static_assert((MS + RB - 1) / RB * RB <= G, "padded row batches exceed the group");
+    bool longer = false;
+    for (int p0 = 0; p0 < L; p0 += RB) {
+        int32_t cb[RB];
+        double vb[RB];
+        uint32_t hb[RB];
+        int32_t kb[RB], eb[RB];
+        uint32_t pend = 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool ok = kk + u < ke;
-                c4[u] = ok ? ci[kk + u] : -1;
-                v4[u] = ok ? v[kk + u] : 0.0;
+        for (int u = 0; u < RB; ++u) {
+            kb[u] = group_bcast<G>(rb, p0 + u) + lane;
+            eb[u] = group_bcast<G>(re, p0 + u);
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const bool ok = kb[u] < eb[u];
+            longer |= kb[u] + G < eb[u];
+            cb[u] = ok ? ci[kb[u]] : -1;
+            vb[u] = ok ? v[kb[u]] : 0.0;
+            pend |= ok ? 1u << u : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) hb[u] = poly_hash<NB>(cb[u]);
+        while (pend) {
+            int4 kv[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) kv[u] = H[hb[u]];   // every bucket index is in range
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const bool on = (pend >> u) & 1u;
+                const bool h0 = kv[u].x == cb[u];
+                const bool hit = on && (h0 || kv[u].z == cb[u]);
+                const bool stop = hit || kv[u].z < 0;
+                if (hit) M[(p0 + u) * MS + (h0 ? kv[u].y : kv[u].w)] = vb[u];
+                pend &= on && stop ? ~(1u << u) : ~0u;
+                hb[u] = on && !stop ? (hb[u] + 1) & kHM : hb[u];
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (c4[u] < 0) continue;
-                uint32_t h = poly_hash<G>(c4[u]);
-                int32_t key;
-                while ((key = hk[h]) != -1 && key != c4[u]) h = (h + 1) & (2 * G - 1);
-                if (key == c4[u]) M[lane * MS + hp[h]] = v4[u];
+        }
+    }
+    if (group_any<G>(longer)) {
+        for (int p = 0; p < L; ++p) {
+            const int32_t e = group_bcast<G>(re, p);
+            for (int32_t k = group_bcast<G>(rb, p) + G + lane; k < e; k += G) {
+                const int32_t c = ci[k];
+                for (uint32_t h = poly_hash<NB>(c);; h = (h + 1) & kHM) {
+                    const int4 kv = H[h];
+                    if (kv.x == c || kv.z == c) {
+                        M[p * MS + (kv.x == c ? kv.y : kv.w)] = v[k];
+                        break;
+                    }
+                    if (kv.z < 0) break;
+                }
             }
         }
     }
     wave_sync();
+    // Lane a keeps column a of M_i in registers.  Every power sums all MS
+    // terms in ascending p: the terms past L are 0 * 0 (rows and columns of
+    // M_i past L are zero, and so is x there, which is reset after every
+    // power), and adding +0 leaves a sum that starts at +0 unchanged, so the
+    // sum equals the one over p < L.
+    double Mr[MS];
+#pragma unroll
+    for (int p = 0; p < MS; ++p) {
+        const double m = M[p * MS + min(lane, MS - 1)];   // read on every lane, kept below MS
+        Mr[p] = lane < MS ? m : 0.0;
+    }
     const double *al = alt + (nseg > 1 ? seg_of(soff, nseg, row) : 0) * kMaxPolyCols;
     double x = (lane < L && myc == row) ? 1.0 : 0.0;
     double acc = al[0] * x;
-    const int Lu = __builtin_amdgcn_readfirstlane(L);   // one group per wavefront when G == 64
     for (int k = 1; k < nalpha; ++k) {
+        X[lane] = x;
+        wave_sync();
         double xn = 0.0;
-        if constexpr (G == 64) {
-            int p = 0;
-            for (; p + 8 <= Lu; p += 8) {
-                double m8[8], x8[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    m8[u] = lane < MS ? M[(p + u) * MS + lane] : 0.0;
-                    const int64_t xb = __double_as_longlong(x);
-                    const int32_t lo = __builtin_amdgcn_readlane((int32_t)xb, p + u);
-                    const int32_t hi = __builtin_amdgcn_readlane((int32_t)(xb >> 32), p + u);
-                    x8[u] = __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) xn += x8[u] * m8[u];
-            }
-            for (; p < Lu; ++p) {
-                const int64_t xb = __double_as_longlong(x);
-                const int32_t lo = __builtin_amdgcn_readlane((int32_t)xb, p);
-                const int32_t hi = __builtin_amdgcn_readlane((int32_t)(xb >> 32), p);
-                xn += __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo) * (lane < MS ? M[p * MS + lane] : 0.0);
-            }
-        } else {
-            X[lane] = x;
-            wave_sync();
-            int p = 0;
-            for (; p + 8 <= L; p += 8) {
-                double m8[8], x8[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    m8[u] = lane < MS ? M[(p + u) * MS + lane] : 0.0;
-                    x8[u] = X[p + u];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) xn += x8[u] * m8[u];
-            }
-            for (; p < L; ++p) xn += X[p] * (lane < MS ? M[p * MS + lane] : 0.0);
-            wave_sync();
+        for (int p = 0; p < MS; p += 2) {
+            const double2 xp = *reinterpret_cast<const double2 *>(X + p);   // same address on every lane
+            xn += xp.x * Mr[p];
+            xn += xp.y * Mr[p + 1];
         }
+        wave_sync();
+        xn = lane < L ? xn : 0.0;
         x = xn;
         acc += al[k] * x;
     }
