@@ -207,13 +207,21 @@ public:
     Branch(const Branch &) = delete;
     Branch &operator=(const Branch &) = delete;
     hipStream_t stream() const { return s_; }
+    // Starts a job on the worker thread and stream (after the previous job
+    // has ended; its exception, if any, is rethrown here).
     void start(std::function<void()> job);
     void finish();        // rethrows the job's exception
     void wait_idle();     // waits for a running job, ignoring its outcome
+    // Called by the job: the work it has queued so far is what the main
+    // stream needs first.  wait_mark() makes the main stream wait for that
+    // work only (rethrowing an exception raised before the mark); the rest
+    // of the job is joined by the next start() or finish().
+    void mark();
+    void wait_mark();
     struct Worker;        // the host thread; kept per device for later setups
 private:
     hipStream_t main_, s_ = nullptr;
-    hipEvent_t fork_ = nullptr, join_ = nullptr;
+    hipEvent_t fork_ = nullptr, join_ = nullptr, mid_ = nullptr;
     int dev_ = 0;
     Worker *w_ = nullptr;
 };

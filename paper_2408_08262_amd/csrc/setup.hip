@@ -37,7 +37,7 @@ struct Branch::Worker {
     std::condition_variable cv;
     std::function<void()> job;
     std::exception_ptr err;
-    bool has = false, busy = false;
+    bool has = false, busy = false, marked = false;
 
     void loop() {
         (void)hipSetDevice(dev);
@@ -100,7 +100,10 @@ Branch::Branch(hipStream_t main) : main_(main) {
     s_ = branch_stream(dev_);
     fork_ = pooled_event();
     join_ = pooled_event();
+    mid_ = pooled_event();
     w_ = take_worker(dev_);
+    std::lock_guard<std::mutex> lk(w_->mu);   // an idle worker: drop a failure left by its last owner
+    w_->err = nullptr;
 }
 
 Branch::~Branch() {
@@ -108,10 +111,13 @@ Branch::~Branch() {
     (void)hipStreamSynchronize(s_);
     release_event(fork_);
     release_event(join_);
+    release_event(mid_);
     give_worker(w_);
 }
 
 void Branch::start(std::function<void()> job) {
+    wait_idle();
+    if (w_->err) std::rethrow_exception(w_->err);
     AIRG_HIP(hipEventRecord(fork_, main_));
     AIRG_HIP(hipStreamWaitEvent(s_, fork_, 0));
     {
@@ -120,8 +126,34 @@ void Branch::start(std::function<void()> job) {
         w_->err = nullptr;
         w_->has = true;
         w_->busy = true;
+        w_->marked = false;
     }
     w_->cv.notify_all();
+}
+
+void Branch::mark() {
+    AIRG_HIP(hipEventRecord(mid_, s_));
+    {
+        std::lock_guard<std::mutex> lk(w_->mu);
+        w_->marked = true;
+    }
+    w_->cv.notify_all();
+}
+
+void Branch::wait_mark() {
+    bool marked;
+    {
+        std::unique_lock<std::mutex> lk(w_->mu);
+        w_->cv.wait(lk, [&] { return w_->marked || !w_->busy; });
+        marked = w_->marked;
+    }
+    if (!marked) {   // the job ended before its mark
+        if (w_->err) std::rethrow_exception(w_->err);
+        AIRG_HIP(hipEventRecord(join_, s_));
+        AIRG_HIP(hipStreamWaitEvent(main_, join_, 0));
+        return;
+    }
+    AIRG_HIP(hipStreamWaitEvent(main_, mid_, 0));
 }
 
 void Branch::wait_idle() {
@@ -248,10 +280,17 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     };
     BranchGuard guard;
     if (br) {
+        // the prolongator and A P first (the coarse phase waits for them),
+        // then `pre`, which runs on while this thread goes on; it owns a copy
+        // of its callable, since it may outlive this call
         guard.b = br;
-        br->start([&] {
-            if (pre) pre(br->stream());
-            prolong(br->stream());
+        std::function<void(hipStream_t)> after = pre;
+        const hipStream_t bs = br->stream();
+        Branch *b = br;
+        br->start([&prolong, after, bs, b] {
+            prolong(bs);
+            b->mark();
+            if (after) after(bs);
         });
     } else if (pre) {
         pre(s);
@@ -327,7 +366,7 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     if (br) {
         tm.end();
         guard.b = nullptr;
-        br->finish();
+        br->wait_mark();
     } else {
         tm.end();
         prolong(s);
@@ -707,6 +746,10 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
     first->A = std::move(A0);
     H->lv.push_back(std::move(first));
     int maxl = o.max_levels > 0 ? o.max_levels : 64;
+    // the branch's jobs look levels up while this thread appends new ones:
+    // the level table must not move (past its reserve, an append first
+    // waits for the branch)
+    H->lv.reserve((size_t)std::min(maxl, 256) + 1);
     Branch br(s);
     for (int l = 0;; ++l) {
         TraceRange trace_level("setup level %d", l);
@@ -752,8 +795,9 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
             break;
         }
         auto next = std::make_unique<Level>();
-        // the branch also makes this level's permutation and the previous
-        // level's solve operators, which need it
+        // after the prolongator, the branch makes this level's permutation
+        // and the previous level's solve operators, which need it; that work
+        // overlaps this level's coarse phase and the next splitting
         Hier &HH = *H;
         auto pre = [&HH, l](hipStream_t st) {
             level_perm(HH.L(l), st);
@@ -764,8 +808,10 @@ std::unique_ptr<Hier> build_hierarchy(Csr &&A0, const airg_opts &o, uint64_t see
                        &L.P, &L.APp);
         L.xplan = std::move(xplan);
         next->n = next->A.nr;
+        if (H->lv.size() == H->lv.capacity()) br.wait_idle();
         H->lv.push_back(std::move(next));
     }
+    br.finish();
     tm.level = -1;
     tm.begin(AIRG_PHASE_FINALIZE);
     finalize(*H, std::max(0, H->nlev() - 2));
