@@ -44,8 +44,10 @@ __global__ void __launch_bounds__(256) k_strength(int32_t n, const int32_t *__re
 }
 
 // Per strong entry (i, j): write it to row i of S's own CSR, count it for
-// S^T_j, and find whether i in S_j (binary search of column i in row j) to
-// count mutual pairs.
+// S^T_j, and find whether i in S_j to count mutual pairs: a row j of up to
+// kMutualScan entries is read whole (its loads issued together, one trip to
+// memory), a longer one is searched by bisection (its columns ascend).
+constexpr int kMutualScan = 8;
 template <int G>
 __global__ void __launch_bounds__(256) k_strength_mutual(int32_t n, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
@@ -67,13 +69,24 @@ __global__ void __launch_bounds__(256) k_strength_mutual(int32_t n, const int32_
             const int32_t j = ci[k];
             sci[w + __popcll(m & ((1ull << lane) - 1ull))] = j;
             atomicAdd(&cntT[j], 1);
-            int32_t lo = rp[j], hi = rp[j + 1];
-            while (lo < hi) {
-                int32_t mid = (lo + hi) >> 1;
-                if (ci[mid] < row) lo = mid + 1;
-                else hi = mid;
+            const int32_t jb = rp[j], je = rp[j + 1];
+            int32_t pos = -1;
+            if (je - jb <= kMutualScan) {
+                int32_t c[kMutualScan];
+#pragma unroll
+                for (int u = 0; u < kMutualScan; ++u) c[u] = jb + u < je ? ci[jb + u] : -1;
+#pragma unroll
+                for (int u = 0; u < kMutualScan; ++u) pos = c[u] == row ? jb + u : pos;
+            } else {
+                int32_t lo = jb, hi = je;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi) >> 1;
+                    if (ci[mid] < row) lo = mid + 1;
+                    else hi = mid;
+                }
+                pos = lo < je && ci[lo] == row ? lo : -1;
             }
-            if (lo < rp[j + 1] && ci[lo] == row && strong[lo]) ++mu;
+            if (pos >= 0 && strong[pos]) ++mu;
         }
         w += __popcll(m);
     }
