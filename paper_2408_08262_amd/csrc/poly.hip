@@ -535,13 +535,14 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     }
     wave_sync();
     // row p of M_i is row J_i[p] of A against J_i; a row's columns are
-    // distinct, so its lanes write distinct entries.  The first G entries of
-    // RB rows are loaded before any is looked up; entries past G (rows
-    // longer than the group) take a pass of their own.  The pad rows p >= L
-    // have the empty extent [0, 0).
+    // distinct, so its lanes write distinct entries.  Pass q takes entries
+    // qG .. qG + G - 1 of every gathered row (as many passes as the group's
+    // longest gathered row needs), RB rows loaded before any is looked up.
+    // The pad rows p >= L have the empty extent [0, 0).
     constexpr int RB = MS <= 4 ? MS : MS <= 8 ? 4 : MS <= 24 ? 8 : 16;
     static_assert((MS + RB - 1) / RB * RB <= G, "padded row batches exceed the group");
-    bool longer = false;
+    const int passes = group_max<G>((re - rb + G - 1) / G);
+    for (int q = 0; q < passes; ++q)
     for (int p0 = 0; p0 < L; p0 += RB) {
         int32_t cb[RB];
         double vb[RB];
@@ -550,13 +551,12 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
         uint32_t pend = 0;
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
-            kb[u] = group_bcast<G>(rb, p0 + u) + lane;
+            kb[u] = group_bcast<G>(rb, p0 + u) + q * G + lane;
             eb[u] = group_bcast<G>(re, p0 + u);
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
             const bool ok = kb[u] < eb[u];
-            longer |= kb[u] + G < eb[u];
             cb[u] = ok ? ci[kb[u]] : -1;
             vb[u] = ok ? v[kb[u]] : 0.0;
             pend |= ok ? 1u << u : 0u;
@@ -576,22 +576,6 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
                 if (hit) M[(p0 + u) * MS + (h0 ? kv[u].y : kv[u].w)] = vb[u];
                 pend &= on && stop ? ~(1u << u) : ~0u;
                 hb[u] = on && !stop ? (hb[u] + 1) & kHM : hb[u];
-            }
-        }
-    }
-    if (group_any<G>(longer)) {
-        for (int p = 0; p < L; ++p) {
-            const int32_t e = group_bcast<G>(re, p);
-            for (int32_t k = group_bcast<G>(rb, p) + G + lane; k < e; k += G) {
-                const int32_t c = ci[k];
-                for (uint32_t h = poly_hash<NB>(c);; h = (h + 1) & kHM) {
-                    const int4 kv = H[h];
-                    if (kv.x == c || kv.z == c) {
-                        M[p * MS + (kv.x == c ? kv.y : kv.w)] = v[k];
-                        break;
-                    }
-                    if (kv.z < 0) break;
-                }
             }
         }
     }
