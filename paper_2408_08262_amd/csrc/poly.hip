@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     constexpr int NG = TPB / G;
     constexpr int NB = G == 32 ? 2 * G : G;   // hash buckets of two slots
     constexpr uint32_t kHM = NB - 1;
-    __shared__ double Ms[NG][MS * MS];
+    __shared__ __align__(16) double Ms[NG][MS * MS];
     __shared__ __align__(16) double Xs[NG][G];
     __shared__ int4 Hs[NG][NB];   // (column, position) x 2; column -1 marks an empty slot
     int gid = threadIdx.x / G;
@@ -517,7 +517,8 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
     const int32_t rb = lane < L ? rp[myc] : 0;       // extent of the gathered row J_i[lane]
     const int32_t re = lane < L ? rp[myc + 1] : 0;
     for (int t = lane; t < NB; t += G) H[t] = make_int4(-1, 0, -1, 0);
-    for (int t = lane; t < MS * MS; t += G) M[t] = 0.0;
+    static_assert(MS % 2 == 0, "M_i rows of an even length, cleared two entries at a time");
+    for (int t = lane; t < MS * MS / 2; t += G) reinterpret_cast<double2 *>(M)[t] = make_double2(0.0, 0.0);
     wave_sync();
     if (lane < L) {   // columns are distinct: each claims its own slot
         uint32_t h = poly_hash<NB>(myc);
@@ -551,8 +552,13 @@ __global__ void __launch_bounds__(TPB) k_poly_rows(const int32_t *__restrict__ l
         uint32_t pend = 0;
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
-            kb[u] = group_bcast<G>(rb, p0 + u) + q * G + lane;
-            eb[u] = group_bcast<G>(re, p0 + u);
+            if constexpr (G == 64) {   // one group per wavefront: p0 + u is uniform, a lane read
+                kb[u] = __builtin_amdgcn_readlane(rb, p0 + u) + q * G + lane;
+                eb[u] = __builtin_amdgcn_readlane(re, p0 + u);
+            } else {
+                kb[u] = group_bcast<G>(rb, p0 + u) + q * G + lane;
+                eb[u] = group_bcast<G>(re, p0 + u);
+            }
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
