@@ -218,6 +218,11 @@ public:
     // of the job is joined by the next start() or finish().
     void mark();
     void wait_mark();
+    // Orders the branch stream's later work after the main stream's work so
+    // far (called by the main thread before it returns blocks that were made
+    // on the branch stream, and that its own stream has used, to the
+    // allocator's cache for the branch stream, while a job may be running).
+    void follow_main();
     struct Worker;        // the host thread; kept per device for later setups
 private:
     hipStream_t main_, s_ = nullptr;

@@ -140,6 +140,11 @@ void Branch::mark() {
     w_->cv.notify_all();
 }
 
+void Branch::follow_main() {
+    AIRG_HIP(hipEventRecord(fork_, main_));
+    AIRG_HIP(hipStreamWaitEvent(s_, fork_, 0));
+}
+
 void Branch::wait_mark() {
     bool marked;
     {
@@ -397,6 +402,10 @@ void complete_level(const CsrView &A, const airg_opts &o, uint64_t seed, int lvl
     }
     tm.end();
     if (cbytes) *cbytes += nb;
+    // A P's values were made on the branch stream and read by the Galerkin
+    // product on this one; the branch job may still be running (and
+    // allocating): its stream first waits for this one, then they go back
+    if (br) br->follow_main();
     if (p_keep) *p_keep = std::move(P);
     if (ap_keep) {
         AP.v.reset();
