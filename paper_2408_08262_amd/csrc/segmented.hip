@@ -153,6 +153,7 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
     const int maxl = o.max_levels > 0 ? o.max_levels : 64;
     const int m = o.poly_order + 1, mc = o.coarse_poly_order + 1;
     const int32_t min_c = std::max(o.poly_order, 1);
+    Branch br(s);   // after H and tm: waits for a running job before they go
     for (int l = 0;; ++l) {
         SegLevel &L = *H->lv[l];
         const int32_t n = L.n;
@@ -249,6 +250,26 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         if (c.nF + c.nC == 0) break;
         // active segments: extraction, polynomials, Z, W and the coarse operator
         auto next = std::make_unique<SegLevel>();
+        // the one-point prolongator and A P depend on the splitting only: the
+        // branch thread builds them on its stream while this one extracts the
+        // blocks and builds the polynomials and Z; the Galerkin product joins it
+        Csr P, AP;
+        struct Join {
+            Branch *b;
+            ~Join() {
+                if (b) b->wait_idle();
+            }
+        } join{&br};
+        {
+            const hipStream_t bs = br.stream();
+            const int32_t nF = c.nF, nC = c.nC;
+            br.start([&L, &o, &tm, &P, &AP, bs, nF, nC, l] {
+                tm.span_on(AIRG_PHASE_PROLONG, l, bs, [&] {
+                    onepoint_prolongator(view(L.A), L.cf.p, L.rank.p, nF, nC, o.onepoint_weight, &P, &L.W, bs);
+                    AP = spgemm(view(L.A), view(P), bs);
+                });
+            });
+        }
         tm.begin(AIRG_PHASE_EXTRACT);
         L.fidx.alloc((size_t)c.nF + 1, s);
         L.cidx.alloc((size_t)c.nC + 1, s);
@@ -279,13 +300,12 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             // the product and its drop as two steps: the product written and read back whole
             L.setup_bytes += csr_bytes(view(Acf)) + csr_bytes(view(L.Ainv)) + 2 * (pz * 12 + ((int64_t)L.Z.nr + 1) * 4);
         }
-        tm.begin(AIRG_PHASE_PROLONG);
-        Csr P;
-        onepoint_prolongator(view(L.A), L.cf.p, L.rank.p, c.nF, c.nC, o.onepoint_weight, &P, &L.W, s);
+        tm.end();
+        join.b = nullptr;
+        br.finish();
         tm.begin(AIRG_PHASE_COARSE);
         {
             Csr R = restriction_full(view(L.Z), L.fidx.p, L.cidx.p, n, s);
-            Csr AP = spgemm(view(L.A), view(P), s);
             DropArgs da;   // the coarse operator, dropped as its rows are written
             da.tau = o.drop_A;
             da.sign = 1.0;
