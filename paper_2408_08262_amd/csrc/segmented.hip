@@ -232,27 +232,35 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
             }
         }
         // terminal segments: the coarse polynomial on each one's whole block
-        if (c.nT > 0) {
-            tm.begin(AIRG_PHASE_POLY);
+        int64_t tbytes = 0;   // their setup bytes (added once the branch has joined)
+        auto terminal = [&L, &o, &toff, &tsd, &tidx, &c, mc, l](hipStream_t st, int64_t *bytes) {
             toff.push_back(c.nT);
-            L.AT = extract_block(view(L.A), L.cf.p, L.rank.p, CF_T, CF_T, c.nT, c.nT, s);
-            DBuf<int32_t> dtoff = to_dev(toff, s);
-            DBuf<uint64_t> dtsd = to_dev(tsd, s);
-            std::vector<PolyInfo> P = gmres_poly_seg(view(L.AT), toff, dtoff.p, dtsd.p, l, mc, s);
+            L.AT = extract_block(view(L.A), L.cf.p, L.rank.p, CF_T, CF_T, c.nT, c.nT, st);
+            DBuf<int32_t> dtoff = to_dev(toff, st);
+            DBuf<uint64_t> dtsd = to_dev(tsd, st);
+            std::vector<PolyInfo> P = gmres_poly_seg(view(L.AT), toff, dtoff.p, dtsd.p, l, mc, st);
             for (size_t j = 0; j < tidx.size(); ++j) L.seg[tidx[j]].poly = P[j];
-            L.AinvT = inverse_pattern(view(L.AT), o.poly_sparsity_order, s);
-            poly_fixed_sparsity_seg(view(L.AT), view(L.AinvT), toff, P, L.AinvT.v.p, s);
+            L.AinvT = inverse_pattern(view(L.AT), o.poly_sparsity_order, st);
+            poly_fixed_sparsity_seg(view(L.AT), view(L.AinvT), toff, P, L.AinvT.v.p, st);
             // extraction of the terminal block, its polynomial, the assembly
-            L.setup_bytes += csr_bytes(view(L.A)) + csr_bytes(view(L.AT)) + poly_bytes(view(L.AT), mc) +
-                             csr_bytes(view(L.AT)) + csr_bytes(view(L.AinvT));
-            tm.end();
+            *bytes += csr_bytes(view(L.A)) + csr_bytes(view(L.AT)) + poly_bytes(view(L.AT), mc) +
+                      csr_bytes(view(L.AT)) + csr_bytes(view(L.AinvT));
+        };
+        if (c.nF + c.nC == 0) {   // only terminal segments are left: this thread takes them
+            if (c.nT > 0) {
+                tm.begin(AIRG_PHASE_POLY);
+                terminal(s, &tbytes);
+                tm.end();
+            }
+            L.setup_bytes += tbytes;
+            break;
         }
-        if (c.nF + c.nC == 0) break;
         // active segments: extraction, polynomials, Z, W and the coarse operator
         auto next = std::make_unique<SegLevel>();
-        // the one-point prolongator and A P depend on the splitting only: the
-        // branch thread builds them on its stream while this one extracts the
-        // blocks and builds the polynomials and Z; the Galerkin product joins it
+        // the terminal segments' polynomials, the one-point prolongator and A P
+        // depend on the splitting only: the branch thread builds them on its
+        // stream while this one extracts the blocks and builds the polynomials
+        // and Z; the Galerkin product joins it
         Csr P, AP;
         struct Join {
             Branch *b;
@@ -262,8 +270,9 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         } join{&br};
         {
             const hipStream_t bs = br.stream();
-            const int32_t nF = c.nF, nC = c.nC;
-            br.start([&L, &o, &tm, &P, &AP, bs, nF, nC, l] {
+            const int32_t nF = c.nF, nC = c.nC, nT = c.nT;
+            br.start([&L, &o, &tm, &P, &AP, &terminal, &tbytes, bs, nF, nC, nT, l] {
+                if (nT > 0) tm.span_on(AIRG_PHASE_POLY, l, bs, [&] { terminal(bs, &tbytes); });
                 tm.span_on(AIRG_PHASE_PROLONG, l, bs, [&] {
                     onepoint_prolongator(view(L.A), L.cf.p, L.rank.p, nF, nC, o.onepoint_weight, &P, &L.W, bs);
                     AP = spgemm(view(L.A), view(P), bs);
@@ -303,6 +312,7 @@ std::unique_ptr<SegHier> build_segmented(Csr &&A0, const std::vector<int64_t> &s
         tm.end();
         join.b = nullptr;
         br.finish();
+        L.setup_bytes += tbytes;
         tm.begin(AIRG_PHASE_COARSE);
         {
             Csr R = restriction_full(view(L.Z), L.fidx.p, L.cidx.p, n, s);
